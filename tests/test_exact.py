@@ -1,0 +1,94 @@
+"""Pins of the exact Liouvillian / steady-state solver (the reference the DDQMC
+estimators are checked against, Sec. V "solving the linear system").
+
+* The Kronecker form of Sec. III.C equals the master equation of Sec. III.A applied
+  directly to every basis operator |l><m| (dense matrix products).
+* The steady state has zero residual, unit trace, is Hermitian and positive.
+* Closed forms: Jx = Jy makes |dn..dn> an eigenstate of H with no up spin, so the
+  steady state is |dn..dn><dn..dn| (M_z = -1); J = 0 likewise.
+* At zero field the parity selection rule forces <sigma^x> = <sigma^y> = 0.
+* Trace preservation: the diagonal rows of L sum to zero.
+"""
+import numpy as np
+import pytest
+
+from oracle import exact
+
+
+@pytest.mark.parametrize("Lx,Ly", [(2, 2)])
+def test_kronecker_equals_master_equation(Lx, Ly):
+    Ld = exact.liouvillian_direct(Lx, Ly, 0.9, 1.0, 1.3, 0.7)
+    Lk = exact.liouvillian(Lx, Ly, 0.9, 1.0, 1.3, 0.7).toarray()
+    assert np.abs(Ld - Lk).max() < 1e-14
+
+
+def test_kronecker_action_on_random_rho_2x3():
+    Lx, Ly = 2, 3
+    D = 2 ** (Lx * Ly)
+    rng = np.random.default_rng(3)
+    rho = rng.normal(size=(D, D)) + 1j * rng.normal(size=(D, D))
+    H = exact.hamiltonian(Lx, Ly, 0.7, 1.0, 1.1).toarray()
+    gamma = 0.8
+    direct = -1j * (H @ rho - rho @ H)
+    for F in exact.jump_ops(Lx, Ly):
+        F = F.toarray()
+        FdF = F.conj().T @ F
+        direct += gamma * (F @ rho @ F.conj().T - 0.5 * (FdF @ rho + rho @ FdF))
+    L = exact.liouvillian(Lx, Ly, 0.7, 1.0, 1.1, gamma)
+    kron = (L @ rho.reshape(-1, order="F")).reshape((D, D), order="F")
+    assert np.abs(kron - direct).max() < 1e-12
+
+
+def test_trace_preservation_rows():
+    L = exact.liouvillian(2, 2, 0.9, 1.0, 1.0, 1.0).toarray()
+    D = 16
+    diag_rows = [l * D + l for l in range(D)]
+    assert np.abs(L[diag_rows].sum(axis=0)).max() < 1e-14
+
+
+def test_bond_counts():
+    assert len(exact.bonds(2, 2)) == 4
+    assert len(exact.bonds(3, 3)) == 18
+    assert len(exact.bonds(4, 4)) == 32
+    assert len(exact.bonds(2, 6)) == 18
+    assert len(exact.bonds(5, 5)) == 50
+
+
+@pytest.mark.parametrize("Lx,Ly,Jx", [(2, 2, 0.9), (2, 3, 0.6)])
+def test_ness_properties(Lx, Ly, Jx):
+    rho = exact.ness(Lx, Ly, Jx, 1.0, 1.0, 1.0)
+    D = rho.shape[0]
+    L = exact.liouvillian(Lx, Ly, Jx, 1.0, 1.0, 1.0)
+    res = L @ rho.reshape(-1, order="F")
+    assert np.abs(res).max() < 1e-11
+    assert abs(np.trace(rho) - 1) < 1e-12
+    assert np.abs(rho - rho.conj().T).max() < 1e-11
+    ev = np.linalg.eigvalsh(0.5 * (rho + rho.conj().T))
+    assert ev.min() > -1e-11
+    obs = exact.observables(rho, Lx, Ly)
+    assert abs(obs["mx"]) < 1e-13 and abs(obs["my"]) < 1e-13
+    assert -1.0 < obs["mz"] < 0.0
+    assert D == 2 ** (Lx * Ly)
+
+
+@pytest.mark.parametrize("Jx,Jy", [(0.8, 0.8), (0.0, 0.0)])
+def test_ness_closed_form_all_down(Jx, Jy):
+    rho = exact.ness(2, 2, Jx, Jy, 1.0, 1.0)
+    expected = np.zeros_like(rho)
+    expected[0, 0] = 1.0
+    assert np.abs(rho - expected).max() < 1e-12
+    assert exact.observables(rho, 2, 2)["mz"] == pytest.approx(-1.0, abs=1e-14)
+
+
+def test_single_spin_relaxation_closed_form():
+    """A lone decaying spin (no bonds contribute when J = 0): the coherence
+    |up><dn| decays at gamma/2 and the up population at gamma."""
+    gamma = 1.7
+    L = exact.liouvillian(2, 2, 0.0, 0.0, 0.0, gamma).toarray()
+    D = 16
+    up0 = 1  # site 0 up, others down
+    col = L[:, up0 * D + up0]
+    assert col[up0 * D + up0] == pytest.approx(-gamma)
+    assert col[0] == pytest.approx(gamma)
+    coh = L[:, 0 * D + up0]   # rho_{up0, 0}
+    assert coh[0 * D + up0] == pytest.approx(-gamma / 2)

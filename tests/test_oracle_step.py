@@ -1,0 +1,223 @@
+"""Pins of the oracle's whole step against what the paper and the mathematics fix.
+
+* Unbiasedness: the step samples the Euler map of eq. (Euler) for the shifted
+  Liouvillian, so E[rho_{n+1} | rho_n] = (1 + dt L~) rho_n exactly (initiator
+  off, shift frozen), element by element, with and without importance sampling,
+  and also in the regime where a probability exceeds 1 (integer part drawn
+  deterministically).
+* The initiator rule (Sec. IV.A) removes exactly the progeny of non-initiators on
+  unoccupied off-diagonal configurations: the expectation equals the masked map.
+* Trace: E[Tr rho_{n+1}] = (1 - dt S) Tr rho_n (trace-preserving L).
+* Hermiticity in expectation from a Hermitian start (Sec. III.C: no built-in
+  constraint, but the expectation is Hermitian).
+* Closed forms: Jx = Jy keeps the list at |dn..dn><dn..dn| bit-exactly and
+  gives M_z = -1; the parity selection rule keeps popcount(ket)+popcount(bra) even
+  and sigma^x, sigma^y numerators at exactly 0.
+* Estimator sums equal Tr(rho O) numerators computed with the Pauli matrices.
+* The whole method: the accumulated M_z (and correlators) lie within a few
+  standard errors of the exact steady state on 2x2 and 2x3 at n_a = 0.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import exact
+from tests.blocking import ratio_se
+
+
+def _one_step_samples(orc, params, keys, re, im, S, nseed):
+    N = params.Lx * params.Ly
+    D = 2 ** N
+    acc = []
+    for seed in range(nseed):
+        params.seed = 1000 + seed
+        o = orc.Oracle(params)
+        o.set_list(keys, re, im)
+        o.set_scalars(S, 0, 0, 1)
+        o.step(1)
+        k, r, i = o.get_list()
+        v = np.zeros(D * D, complex)
+        v[exact.vec_index(k, N)] = r + 1j * i
+        acc.append(v)
+        o.close()
+    return np.array(acc)
+
+
+def _z_check(samples, expected, zmax=5.5):
+    M = len(samples)
+    mean = samples.mean(axis=0)
+    for part in (np.real, np.imag):
+        sd = part(samples).std(axis=0, ddof=1)
+        diff = part(mean) - part(expected)
+        fixed = sd == 0
+        assert np.all(np.abs(diff[fixed]) < 1e-9), "deterministic element off"
+        z = diff[~fixed] / (sd[~fixed] / np.sqrt(M))
+        assert np.abs(z).max() < zmax, np.abs(z).max()
+        chi = np.mean(z ** 2)
+        assert 0.75 < chi < 1.3, chi
+
+
+CASES = [
+    # Lx, Ly, is_p, dt, S, entries, max_pop
+    (2, 2, 0.0, 0.01, 0.2, 128, 400),
+    (2, 2, 1.5, 0.05, -0.3, 80, 300),
+    (2, 3, 0.7, 0.02, 0.1, 250, 200),
+    (2, 2, 0.0, 0.6, -1.2, 60, 50),     # probabilities above 1: loud path
+]
+
+
+@pytest.mark.parametrize("Lx,Ly,is_p,dt,S,nent,pop", CASES)
+def test_one_step_expectation_is_euler_map(orc, Lx, Ly, is_p, dt, S, nent, pop):
+    keys, re, im = workloads.random_list(Lx, Ly, nent, pop, seed=nent + Lx)
+    p = orc.make_params(Lx=Lx, Ly=Ly, Jx=0.6, Jy=1.0, Jz=1.2, gamma=1.0, dt=dt, n_a=0,
+                        is_p=is_p, target_walkers=2 ** 62)
+    samples = _one_step_samples(orc, p, keys, re, im, S, nseed=600)
+    expected = exact.one_step_expectation(keys, re, im, Lx, Ly, 0.6, 1.0, 1.2, 1.0, dt, S,
+                                          is_p=is_p)
+    _z_check(samples, expected)
+    # trace: E[Tr rho'] = (1 - dt S) Tr rho
+    N = Lx * Ly
+    D = 2 ** N
+    diag = [l * D + l for l in range(D)]
+    tr = samples[:, diag].sum(axis=1)
+    tr0 = sum(complex(r, i) for k, r, i in zip(keys, re, im)
+              if (int(k) >> N) == (int(k) & (D - 1)))
+    exp_tr = (1 - dt * S) * tr0
+    assert abs(tr.real.mean() - exp_tr.real) < 5.5 * tr.real.std() / np.sqrt(len(tr)) + 1e-9
+    assert abs(tr.imag.mean() - exp_tr.imag) < 5.5 * tr.imag.std() / np.sqrt(len(tr)) + 1e-9
+
+
+def test_initiator_filter_expectation(orc):
+    Lx, Ly = 2, 2
+    keys, re, im = workloads.random_list(Lx, Ly, 40, 30, seed=5)
+    n_a = 20
+    p = orc.make_params(Lx=Lx, Ly=Ly, Jx=0.6, Jy=1.0, Jz=1.2, gamma=1.0, dt=0.05, n_a=n_a,
+                        target_walkers=2 ** 62)
+    N = Lx * Ly
+    D = 2 ** N
+    l = keys >> np.uint64(N)
+    m = keys & np.uint64(D - 1)
+    non_init = (l != m) & ((np.abs(re.astype(np.int64)) + np.abs(im.astype(np.int64))) <= n_a)
+    assert 5 < non_init.sum() < len(keys) - 5
+    samples = _one_step_samples(orc, p, keys, re, im, 0.1, nseed=600)
+    expected = exact.one_step_expectation(keys, re, im, Lx, Ly, 0.6, 1.0, 1.2, 1.0, 0.05, 0.1,
+                                          non_initiator=non_init)
+    _z_check(samples, expected)
+    # and the unfiltered map is measurably different
+    full = exact.one_step_expectation(keys, re, im, Lx, Ly, 0.6, 1.0, 1.2, 1.0, 0.05, 0.1)
+    assert np.abs(full - expected).max() > 0.1
+
+
+def test_hermitian_in_expectation(orc):
+    Lx, Ly = 2, 2
+    D = 16
+    keys, re, im = workloads.random_list(Lx, Ly, 90, 300, seed=9, hermitian=True)
+    p = orc.make_params(Lx=Lx, Ly=Ly, dt=0.03, n_a=0, target_walkers=2 ** 62)
+    s = _one_step_samples(orc, p, keys, re, im, 0.0, nseed=500)
+    mean = s.mean(axis=0).reshape((D, D), order="F")
+    sd = s.std(axis=0).reshape((D, D), order="F") / np.sqrt(len(s))
+    diff = mean - mean.conj().T
+    tol = 6 * np.sqrt(sd ** 2 + sd.T ** 2) + 1e-9
+    assert np.all(np.abs(diff.real) <= tol) and np.all(np.abs(diff.imag) <= tol)
+
+
+def test_xxz_stays_all_down(orc):
+    o = orc.Oracle(Lx=3, Ly=3, Jx=0.8, Jy=0.8, dt=0.005, target_walkers=300,
+                   initial_walkers=100)
+    for _ in range(30):
+        o.step(20)
+        k, r, i = o.get_list()
+        assert k.tolist() == [0] and i.tolist() == [0]
+        last = o.last()
+        assert last["z"] == -9 * last["t_re"]
+    assert o.scalars()["mode"] == 1
+
+
+def test_parity_rule_and_zero_transverse_numerators(orc):
+    o = orc.Oracle(**workloads.D1)
+    o.step(3000)
+    k, r, i = o.get_list()
+    N = 4
+    pc = [bin(int(x) >> N).count("1") + bin(int(x) & 15).count("1") for x in k]
+    assert all(c % 2 == 0 for c in pc)
+    rows = o.series()
+    x_col = 3 + orc.SUM_NAMES.index("x")
+    y_col = 3 + orc.SUM_NAMES.index("y")
+    assert np.all(rows[:, x_col] == 0) and np.all(rows[:, y_col] == 0)
+
+
+def test_determinism_and_seed_dependence(orc):
+    a = orc.Oracle(**dict(workloads.D1, seed=4))
+    b = orc.Oracle(**dict(workloads.D1, seed=4))
+    c = orc.Oracle(**dict(workloads.D1, seed=5))
+    for o in (a, b, c):
+        o.step(800)
+    ka, ra, ia = a.get_list()
+    kb, rb, ib = b.get_list()
+    kc, rc, ic = c.get_list()
+    assert np.array_equal(ka, kb) and np.array_equal(ra, rb) and np.array_equal(ia, ib)
+    assert not (len(ka) == len(kc) and np.array_equal(ka, kc) and np.array_equal(ra, rc))
+
+
+def test_initiator_threshold_zero_is_no_initiator(orc):
+    a = orc.Oracle(**dict(workloads.D1, n_a=0))
+    b = orc.Oracle(**dict(workloads.D1, n_a=5, flags=orc.NO_INITIATOR))
+    a.step(1500)
+    b.step(1500)
+    for x, y in zip(a.get_list(), b.get_list()):
+        assert np.array_equal(x, y)
+
+
+def test_estimator_sums_are_trace_numerators(orc):
+    Lx, Ly = 2, 3
+    N = 6
+    D = 64
+    keys, re, im = workloads.random_list(Lx, Ly, 400, 50, seed=8)
+    o = orc.Oracle(Lx=Lx, Ly=Ly, dt=1e-9, n_a=0, target_walkers=2 ** 62)
+    o.set_list(keys, re, im)
+    o.set_scalars(0.0, 0, 0, 1)
+    o.step(1)                          # dt ~ 0: nothing moves
+    k, r, i = o.get_list()
+    assert np.array_equal(k, keys) and np.array_equal(r, re) and np.array_equal(i, im)
+    s = o.last()
+    rho = np.zeros((D, D), complex)
+    for kk, rr, ii in zip(k, r, i):
+        rho[int(kk) >> N, int(kk) & (D - 1)] = complex(rr, ii)
+    tr_num = {}
+    for name, op in (("x", exact.SX), ("y", exact.SY), ("z", exact.SZ)):
+        tr_num[name] = sum((exact.site_op(op, q, N).multiply(rho.T)).sum().real for q in range(N))
+    for name, op in (("cxx", exact.SX), ("cyy", exact.SY), ("czz", exact.SZ)):
+        tr_num[name] = sum(((exact.site_op(op, a, N) @ exact.site_op(op, b, N)).multiply(rho.T))
+                           .sum().real for a, b in exact.bonds(Lx, Ly))
+    for name, v in tr_num.items():
+        assert s[name] == round(v), name
+    assert s["t_re"] == round(np.trace(rho).real) and s["t_im"] == round(np.trace(rho).imag)
+    assert s["n_w"] == int(np.abs(np.diag(rho).real).sum())
+    assert s["w_tot"] == int(np.abs(re.astype(np.int64)).sum() + np.abs(im.astype(np.int64)).sum())
+    assert s["n_entries"] == len(keys)
+
+
+@pytest.mark.parametrize("Lx,Ly,steps,target,seed", [(2, 2, 60000, 3000, 1), (2, 3, 20000, 4000, 2)])
+def test_ness_within_three_standard_errors(orc, Lx, Ly, steps, target, seed):
+    equil = 3000
+    o = orc.Oracle(Lx=Lx, Ly=Ly, Jx=0.6, dt=0.01, n_a=0, target_walkers=target,
+                   initial_walkers=100, seed=seed, n_equil=equil)
+    o.step(steps)
+    rows = o.series()
+    rows = rows[rows[:, 0] > equil]
+    col = {n: 3 + i for i, n in enumerate(orc.SUM_NAMES)}
+    rho = exact.ness(Lx, Ly, 0.6, 1.0, 1.0, 1.0)
+    ex = exact.observables(rho, Lx, Ly)
+    N = Lx * Ly
+    nb = len(exact.bonds(Lx, Ly))
+    den = rows[:, col["t_re"]]
+    mz, se, _ = ratio_se(rows[:, col["z"]] / N, den)
+    assert se > 0
+    assert abs(mz - ex["mz"]) < 3 * se, (mz, ex["mz"], se)
+    for name in ("czz", "cxx", "cyy"):
+        v, s2, _ = ratio_se(rows[:, col[name]] / nb, den)
+        assert abs(v - ex[name]) < 4 * s2, (name, v, ex[name], s2)
+    # the shift fluctuates around the steady-state eigenvalue 0 (Sec. III.A)
+    S = rows[:, 1].view(np.float64)
+    s_mean, s_se, _ = ratio_se(S, np.ones_like(S))
+    assert abs(s_mean) < 4 * s_se + 1e-3
