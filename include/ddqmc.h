@@ -1,0 +1,193 @@
+/*
+ * ddqmc.h -- C ABI of the MI355X (gfx950) library for the driven-dissipative
+ * quantum Monte Carlo propagation step of Nagy & Savona, arXiv:1802.05931.
+ *
+ * One step advances a complex integer walker population over density-matrix
+ * configurations |ket><bra| by the rules of Sec. III.C (spawning along the
+ * off-diagonal Liouvillian elements by the multinomial formalism of Sec. III.B,
+ * clone/death on the diagonal element, annihilation), with the initiator rule of
+ * Sec. IV.A, the importance-sampling weights of Sec. IV.B, the shift update of
+ * Sec. III.C and the estimators of Sec. III.A / V.A, for the dissipative 2D XYZ
+ * model of Sec. V.  Every stage runs in hand-written HIP kernels on the device.
+ *
+ * Conventions
+ *   site s = x + Lx*y; bit s of a bitstring = 1 <=> spin up;
+ *   configuration key = (ket << N) | bra, N = Lx*Ly <= 32 (a 64-bit value);
+ *   H = sum over unique nearest-neighbour bonds of the periodic Lx x Ly lattice of
+ *       Jx SxSx + Jy SySy + Jz SzSz with S = sigma/2; jump S^- per site, rate gamma;
+ *   walkers are int32 (re, im) per configuration; all estimator sums are int64.
+ *
+ * Return codes: 0 on success, a negative DDQMC_E* code otherwise (see
+ * ddqmc_strerror).  On any error a handle is left at its last completed step.
+ * Calls on one handle are not thread-safe; distinct handles are independent.
+ * Host pointers are borrowed for the duration of a call only.
+ */
+#ifndef DDQMC_H
+#define DDQMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DDQMC_OK 0
+#define DDQMC_EINVAL (-1)     /* bad argument or parameter                          */
+#define DDQMC_ENOMEM (-2)     /* host or device allocation failed                   */
+#define DDQMC_ECAPACITY (-3)  /* list exceeds the allowed capacity after regrowing  */
+#define DDQMC_EOVERFLOW (-4)  /* a configuration's walker count left int32 range    */
+#define DDQMC_EEXTINCT (-5)   /* no walkers left / diagonal weight N_w reached zero  */
+#define DDQMC_EHIP (-6)       /* HIP runtime error                                  */
+#define DDQMC_ESTATE (-7)     /* call not valid in the handle's current state       */
+#define DDQMC_ERNG (-8)       /* a random stream ran out of counter blocks          */
+
+/* flags */
+#define DDQMC_NO_INITIATOR 1u /* every parent counts as an initiator                */
+
+/* Parameters of one steady-state solve (Sec. V model; Sec. III.C shift;
+ * Sec. IV.A initiator threshold; Sec. IV.B importance-sampling parameter). */
+typedef struct {
+  uint32_t struct_size;     /* = sizeof(ddqmc_params)                              */
+  int32_t Lx, Ly;           /* 2 <= Lx, Ly and Lx*Ly <= 32, periodic               */
+  double Jx, Jy, Jz;        /* couplings                                           */
+  double gamma;             /* > 0, rate of the S^- jump on every site             */
+  double dt;                /* > 0, Euler time step                                */
+  int32_t n_a;              /* >= 0, initiator threshold I_limit on |re|+|im|      */
+  int64_t target_walkers;   /* N_w (diagonal real weight) that ends the growth phase */
+  int64_t initial_walkers;  /* 1 .. 2^31-1 real walkers on |dn..dn><dn..dn|         */
+  double is_p;              /* >= 0, weight e^{-p} on off-diagonal configurations  */
+  double shift_damping;     /* delta of the shift update                           */
+  double shift_init;        /* shift held while N_w < target_walkers               */
+  uint64_t seed;            /* Philox key (with solve_id)                          */
+  uint32_t solve_id;        /* < 65536; distinct solves draw distinct streams       */
+  int64_t n_equil;          /* steps before estimator accumulation starts          */
+  int64_t capacity_hint;    /* initial list capacity in entries; 0 = automatic     */
+  uint32_t flags;           /* DDQMC_NO_INITIATOR                                  */
+} ddqmc_params;
+
+/* Sums over the walker list after a step (Sec. III.A numerators/denominators):
+ * t_re/t_im = Re/Im Tr rho; n_w = sum |Re rho_ii|; z = sum_i Re rho_ii (2 n_up(i) - N);
+ * x, y = sum over single-flip configurations of the sigma^x / sigma^y element
+ * (real part); cxx, cyy, czz = the same for nearest-neighbour pairs (czz on the
+ * diagonal); w_tot = sum |re| + |im|; n_entries = occupied configurations. */
+enum {
+  DDQMC_T_RE = 0, DDQMC_T_IM, DDQMC_NW, DDQMC_Z, DDQMC_X, DDQMC_Y, DDQMC_CXX, DDQMC_CYY,
+  DDQMC_CZZ, DDQMC_WTOT, DDQMC_NENT, DDQMC_NSUM
+};
+
+typedef struct {
+  int64_t step;             /* steps done by this solve                            */
+  double shift;             /* current shift S                                     */
+  int32_t mode;             /* 0 growth (S held), 1 shift varies                   */
+  int32_t status;           /* 1 running, 0 slot empty                             */
+  int64_t last[DDQMC_NSUM]; /* sums after the last step                            */
+  int64_t n_accum;          /* steps accumulated (those with step > n_equil)       */
+  int64_t acc[DDQMC_NSUM];  /* sums over the accumulated steps                     */
+  /* ratios of the accumulated sums: M_alpha = num / (N acc[T_RE]),
+   * C_alpha = num / (n_bonds acc[T_RE]); off-diagonal numerators times e^{p}    */
+  double mx, my, mz, cxx, cyy, czz;
+  /* standard errors: blocking of the per-step series + delta method            */
+  double se_mx, se_my, se_mz, se_cxx, se_cyy, se_czz;
+} ddqmc_obs;
+
+typedef struct ddqmc_t ddqmc_t;
+
+/* ---- one solve -------------------------------------------------------------
+ * ddqmc_create: validates *p, allocates device buffers (hipMalloc), places
+ *   initial_walkers real walkers on key 0 and sets S = shift_init.  stream may be
+ *   NULL (the handle creates its own) or a hipStream_t owned by the caller, which
+ *   must outlive the handle.  EINVAL on bad parameters, ENOMEM, EHIP.
+ * ddqmc_step: advances n_steps steps on the stream; returns after they finished.
+ *   Lists that outgrow their buffers are regrown and the step is redone (the
+ *   random streams are counter based, so the result is unchanged).  EOVERFLOW,
+ *   EEXTINCT, ECAPACITY, ERNG or EHIP leave the handle at its last good step.
+ * ddqmc_observables: sums, ratios and standard errors of solve 0.
+ * ddqmc_destroy: frees everything; NULL is accepted.                          */
+int ddqmc_create(const ddqmc_params *p, void *hip_stream, ddqmc_t **out);
+int ddqmc_step(ddqmc_t *h, int64_t n_steps);
+int ddqmc_observables(ddqmc_t *h, ddqmc_obs *out);
+int ddqmc_destroy(ddqmc_t *h);
+
+/* ---- many independent solves in one launch per stage (batched) --------------
+ * The solves share one sorted list whose keys carry the slot number above the
+ * configuration bits; each solve keeps its own parameters, shift and step count
+ * and draws exactly the random numbers it would draw alone.
+ * ddqmc_batch_create: count solves, parameters p[0..count-1], all started.
+ * ddqmc_batch_step == ddqmc_step.  ddqmc_batch_observables: solve idx.        */
+int ddqmc_batch_create(const ddqmc_params *p, int32_t count, void *hip_stream, ddqmc_t **out);
+int ddqmc_batch_step(ddqmc_t *h, int64_t n_steps);
+int ddqmc_batch_observables(ddqmc_t *h, int32_t idx, ddqmc_obs *out);
+
+/* ---- continuous batching (serving) ------------------------------------------
+ * ddqmc_pool_create: an empty handle with `slots` slots for lattices of up to
+ *   max_sites sites (<= 32; with the slot bits the key must fit 64 bits).
+ * ddqmc_slot_admit: puts a new solve in a free slot; its initial walkers enter the
+ *   list during the next step, after which it steps like a fresh ddqmc_create
+ *   handle.  Writes the slot index; ESTATE if no slot is free.
+ * ddqmc_slot_retire: the slot's walkers leave the list during the next step.
+ * ddqmc_slot_observables: as ddqmc_observables for one slot.
+ * ddqmc_list_size: occupied configurations over all slots (last synchronised). */
+int ddqmc_pool_create(int32_t slots, int32_t max_sites, int64_t capacity_hint, void *hip_stream,
+                      ddqmc_t **out);
+int ddqmc_slot_admit(ddqmc_t *h, const ddqmc_params *p, int32_t *slot);
+int ddqmc_slot_retire(ddqmc_t *h, int32_t slot);
+int ddqmc_slot_observables(ddqmc_t *h, int32_t slot, ddqmc_obs *out);
+int ddqmc_list_size(ddqmc_t *h, int64_t *n);
+
+/* ---- state access (tests, checkpoints) ---------------------------------------
+ * Keys cross the ABI as uint64 (ket << N) | bra without slot bits, ascending.
+ * ddqmc_get_walkers: copies slot's list; cap in entries; *n = its length
+ *   (EINVAL, with *n set, if cap is too small).
+ * ddqmc_set_walkers: replaces slot's list (keys strictly ascending, no (0,0),
+ *   |values| < 2^31); only on a handle with one slot.
+ * ddqmc_get_scalars / ddqmc_set_scalars: shift, mode, step, N_w of the previous
+ *   step of one slot.
+ * ddqmc_get_state / ddqmc_set_state: checkpoint of a one-slot handle as an opaque
+ *   byte string (list, scalars, accumulators); set_state requires the same
+ *   parameters.  get_state with buf == NULL reports the size in *n.           */
+int ddqmc_get_walkers(ddqmc_t *h, int32_t slot, uint64_t *keys, int32_t *re, int32_t *im,
+                      int64_t cap, int64_t *n);
+int ddqmc_set_walkers(ddqmc_t *h, const uint64_t *keys, const int32_t *re, const int32_t *im,
+                      int64_t n);
+int ddqmc_get_scalars(ddqmc_t *h, int32_t slot, double *shift, int32_t *mode, int64_t *step,
+                      int64_t *nw_prev);
+int ddqmc_set_scalars(ddqmc_t *h, int32_t slot, double shift, int32_t mode, int64_t step,
+                      int64_t nw_prev);
+int ddqmc_get_state(ddqmc_t *h, void *buf, size_t cap, size_t *n);
+int ddqmc_set_state(ddqmc_t *h, const void *buf, size_t n);
+
+/* Per-step series of one slot since creation: rows of (step, shift bit pattern,
+ * mode, the DDQMC_NSUM sums), int64.  *n = rows available; copies min(cap, n). */
+int ddqmc_get_series(ddqmc_t *h, int32_t slot, int64_t *rows, int64_t cap, int64_t *n);
+
+/* Device bytes a one-slot handle with the given capacity would allocate
+ * (serving admission). */
+int ddqmc_workspace_query(const ddqmc_params *p, int64_t capacity, size_t *bytes);
+
+/* Wall time of the kernels of the last ddqmc_step call, per stage, from HIP
+ * events when profiling is on (ddqmc_set_profiling); ms[5] = spawn, histogram,
+ * sort, merge, finalize summed over the call's steps. */
+int ddqmc_set_profiling(ddqmc_t *h, int32_t on);
+int ddqmc_stage_times(ddqmc_t *h, double ms[5], int64_t *steps);
+
+/* ---- device self-checks of the sampling primitives --------------------------
+ * Same streams as the step (Philox4x32-10, key (seed_lo, seed_hi ^ solve),
+ * counter (cfg_lo, cfg_hi, step, draw << 16 | block), 53-bit uniforms).
+ * ddqmc_dev_uniforms: count uniforms of one stream, computed on the device.
+ * ddqmc_dev_binom: sample i uses stream (seed, 0, cfg = i, 0, draw 1);
+ *   mode 0 Bin(n,p), 1 Bin(n,p | >= 1), 2 integer part + Bin(n, fraction).
+ * ddqmc_dev_math: out[4i..4i+3] = det_log(x_i), det_exp(x_i), sqrt(x_i), 1/x_i.
+ * All pointers are host memory.                                               */
+int ddqmc_dev_uniforms(uint64_t seed, uint32_t solve_id, uint64_t cfg, uint32_t step,
+                       uint32_t draw, int64_t count, double *out);
+int ddqmc_dev_binom(int64_t n, double p, int32_t mode, uint64_t seed, int64_t count,
+                    int64_t *out);
+int ddqmc_dev_math(const double *x, int64_t count, double *out);
+
+const char *ddqmc_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

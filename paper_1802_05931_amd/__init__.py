@@ -1,0 +1,207 @@
+"""MI355X (gfx950) DDQMC propagation step -- Python side of the C ABI.
+
+``Solve``, ``Batch`` and ``Pool`` wrap the handles of include/ddqmc.h
+(ddqmc_create / ddqmc_step / ddqmc_observables / ddqmc_destroy and the batched
+and serving calls).  The walker step itself runs in the library's HIP kernels;
+this module only marshals arguments.  PyTorch is optional: a ``torch.cuda``
+stream can be handed over with ``stream=torch.cuda.current_stream()``.
+"""
+import ctypes
+
+import numpy as np
+
+from ._lib import (DDQMCError, NO_INITIATOR, NSUM, Obs, Params, SERIES_W, SUM_NAMES, check, lib,
+                   make_params, ptr)
+
+__all__ = ["Solve", "Batch", "Pool", "make_params", "DDQMCError", "NO_INITIATOR", "SUM_NAMES",
+           "dev_uniforms", "dev_binom", "dev_math", "workspace_query"]
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    s = getattr(stream, "cuda_stream", stream)
+    return ctypes.c_void_p(int(s))
+
+
+def _obs_dict(o):
+    d = {f: getattr(o, f) for f, _ in Obs._fields_ if f not in ("last", "acc")}
+    d["last"] = dict(zip(SUM_NAMES, list(o.last)))
+    d["acc"] = dict(zip(SUM_NAMES, list(o.acc)))
+    return d
+
+
+class _Handle:
+    _h = None
+
+    def _step(self, n):
+        check(lib().ddqmc_step(self._h, int(n)), "ddqmc_step")
+
+    def close(self):
+        if self._h:
+            lib().ddqmc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def observables(self, slot=0):
+        o = Obs()
+        check(lib().ddqmc_slot_observables(self._h, int(slot), ctypes.byref(o)),
+              "ddqmc_observables")
+        return _obs_dict(o)
+
+    def walkers(self, slot=0):
+        n = ctypes.c_int64()
+        lib().ddqmc_get_walkers(self._h, int(slot), None, None, None, 0, ctypes.byref(n))
+        cap = max(n.value, 1)
+        k = np.empty(cap, np.uint64)
+        r = np.empty(cap, np.int32)
+        i = np.empty(cap, np.int32)
+        check(lib().ddqmc_get_walkers(self._h, int(slot), ptr(k, ctypes.c_uint64),
+                                      ptr(r, ctypes.c_int32), ptr(i, ctypes.c_int32), cap,
+                                      ctypes.byref(n)), "ddqmc_get_walkers")
+        return k[:n.value], r[:n.value], i[:n.value]
+
+    def scalars(self, slot=0):
+        S = ctypes.c_double()
+        mode = ctypes.c_int32()
+        step = ctypes.c_int64()
+        nwp = ctypes.c_int64()
+        check(lib().ddqmc_get_scalars(self._h, int(slot), ctypes.byref(S), ctypes.byref(mode),
+                                      ctypes.byref(step), ctypes.byref(nwp)), "get_scalars")
+        return dict(S=S.value, mode=mode.value, step=step.value, nw_prev=nwp.value)
+
+    def set_scalars(self, S, mode, step, nw_prev, slot=0):
+        check(lib().ddqmc_set_scalars(self._h, int(slot), float(S), int(mode), int(step),
+                                      int(nw_prev)), "set_scalars")
+
+    def series(self, slot=0):
+        n = ctypes.c_int64()
+        check(lib().ddqmc_get_series(self._h, int(slot), None, 0, ctypes.byref(n)), "series")
+        rows = np.zeros((n.value, SERIES_W), np.int64)
+        check(lib().ddqmc_get_series(self._h, int(slot), ptr(rows, ctypes.c_int64), n.value,
+                                     ctypes.byref(n)), "series")
+        return rows
+
+    def list_size(self):
+        n = ctypes.c_int64()
+        check(lib().ddqmc_list_size(self._h, ctypes.byref(n)), "list_size")
+        return n.value
+
+    def set_profiling(self, on=True):
+        check(lib().ddqmc_set_profiling(self._h, 1 if on else 0), "set_profiling")
+
+    def stage_times(self):
+        ms = (ctypes.c_double * 5)()
+        steps = ctypes.c_int64()
+        check(lib().ddqmc_stage_times(self._h, ms, ctypes.byref(steps)), "stage_times")
+        return dict(zip(("spawn", "histogram", "sort", "merge", "finalize"), list(ms))), \
+            steps.value
+
+
+class Solve(_Handle):
+    """One steady-state solve (ddqmc_create)."""
+
+    def __init__(self, params=None, stream=None, **kw):
+        self.params = params if params is not None else make_params(**kw)
+        h = ctypes.c_void_p()
+        check(lib().ddqmc_create(ctypes.byref(self.params), _stream_ptr(stream), ctypes.byref(h)),
+              "ddqmc_create")
+        self._h = h
+
+    def step(self, n=1):
+        self._step(n)
+
+    def set_walkers(self, keys, re, im):
+        k = np.ascontiguousarray(keys, np.uint64)
+        r = np.ascontiguousarray(re, np.int32)
+        i = np.ascontiguousarray(im, np.int32)
+        check(lib().ddqmc_set_walkers(self._h, ptr(k, ctypes.c_uint64), ptr(r, ctypes.c_int32),
+                                      ptr(i, ctypes.c_int32), len(k)), "ddqmc_set_walkers")
+
+    def get_state(self):
+        n = ctypes.c_size_t()
+        check(lib().ddqmc_get_state(self._h, None, 0, ctypes.byref(n)), "get_state")
+        buf = ctypes.create_string_buffer(n.value)
+        check(lib().ddqmc_get_state(self._h, buf, n.value, ctypes.byref(n)), "get_state")
+        return buf.raw
+
+    def set_state(self, blob):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        check(lib().ddqmc_set_state(self._h, buf, len(blob)), "set_state")
+
+
+class Batch(_Handle):
+    """Independent solves advanced together (ddqmc_batch_create)."""
+
+    def __init__(self, params_list, stream=None):
+        arr = (Params * len(params_list))(*params_list)
+        h = ctypes.c_void_p()
+        check(lib().ddqmc_batch_create(arr, len(params_list), _stream_ptr(stream),
+                                       ctypes.byref(h)), "ddqmc_batch_create")
+        self._h = h
+        self.count = len(params_list)
+
+    def step(self, n=1):
+        check(lib().ddqmc_batch_step(self._h, int(n)), "ddqmc_batch_step")
+
+
+class Pool(_Handle):
+    """Continuous batching: solves enter and leave slots between steps."""
+
+    def __init__(self, slots, max_sites, capacity_hint=0, stream=None):
+        h = ctypes.c_void_p()
+        check(lib().ddqmc_pool_create(int(slots), int(max_sites), int(capacity_hint),
+                                      _stream_ptr(stream), ctypes.byref(h)), "ddqmc_pool_create")
+        self._h = h
+        self.slots = slots
+
+    def admit(self, params):
+        s = ctypes.c_int32()
+        check(lib().ddqmc_slot_admit(self._h, ctypes.byref(params), ctypes.byref(s)), "admit")
+        return s.value
+
+    def retire(self, slot):
+        check(lib().ddqmc_slot_retire(self._h, int(slot)), "retire")
+
+    def step(self, n=1):
+        self._step(n)
+
+
+def workspace_query(params, capacity=0):
+    n = ctypes.c_size_t()
+    check(lib().ddqmc_workspace_query(ctypes.byref(params), int(capacity), ctypes.byref(n)),
+          "workspace_query")
+    return n.value
+
+
+def dev_uniforms(seed, solve_id, cfg, step, draw, count):
+    out = np.zeros(count, np.float64)
+    check(lib().ddqmc_dev_uniforms(seed, solve_id, cfg, step, draw, count,
+                                   ptr(out, ctypes.c_double)), "dev_uniforms")
+    return out
+
+
+def dev_binom(n, p, mode, seed, count):
+    out = np.zeros(count, np.int64)
+    check(lib().ddqmc_dev_binom(int(n), float(p), int(mode), int(seed), int(count),
+                                ptr(out, ctypes.c_int64)), "dev_binom")
+    return out
+
+
+def dev_math(x):
+    x = np.ascontiguousarray(x, np.float64)
+    out = np.zeros(4 * len(x), np.float64)
+    check(lib().ddqmc_dev_math(ptr(x, ctypes.c_double), len(x), ptr(out, ctypes.c_double)),
+          "dev_math")
+    return out.reshape(-1, 4)

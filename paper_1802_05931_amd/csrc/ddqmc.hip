@@ -1,0 +1,947 @@
+// C ABI of the DDQMC step library (declared in include/ddqmc.h).
+//
+// A handle owns a sorted walker list (two ping-pong buffers), the spawn-record
+// buffers of the radix sort, the look-back words, per-tile estimator partials
+// and the per-solve parameter/state tables.  One step is a fixed sequence of
+// launches on the handle's stream (kernels.hpp); the host synchronises only at
+// the end of a chunk of steps, reads the control block and, if a buffer was too
+// small, grows it and redoes the failed step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ddqmc.h"
+#include "kernels.hpp"
+
+using namespace ddqmc;
+
+namespace {
+
+constexpr uint32_t SERIES_CAP = 1024;  // steps per chunk between host synchronisations
+constexpr uint64_t MAX_CAP = 0xF0000000ull;
+constexpr int NSTAGE = 5;
+
+struct StageEvents {
+  hipEvent_t e[NSTAGE + 1];
+};
+
+}  // namespace
+
+struct ddqmc_t {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  int nslots = 1;
+  int Nmax = 0;
+  int SB = 0;       // bit position of the slot field
+  int key_bits = 0;
+  int passes = 1;
+  bool k64 = false;
+  bool pool = false;
+  uint64_t cap_main = 0, cap_sp = 0;
+  int cur = 0;
+  uint32_t n_main_known = 0, n_spawn_known = 0;
+
+  void *mk[2] = {nullptr, nullptr};
+  int2 *mv[2] = {nullptr, nullptr};
+  void *sk[2] = {nullptr, nullptr};
+  int2 *sv[2] = {nullptr, nullptr};
+  uint64_t *sort_status = nullptr;
+  uint64_t *merge_status = nullptr;
+  Partial *partials = nullptr;
+  uint32_t *hist = nullptr;
+  Ctrl *ctrl = nullptr;
+  SlotParams *dsp = nullptr;
+  SlotState *dss = nullptr;
+  unsigned long long *spill = nullptr;
+  int64_t *series = nullptr;
+  void *inj_k = nullptr;
+  int2 *inj_v = nullptr;
+  uint32_t n_inject_host = 0;
+
+  std::vector<SlotParams> hp;
+  std::vector<ddqmc_params> up;
+  std::vector<int> slot_state;  // host view: 0 free, 1 running, 2 entering, 3 leaving
+  std::vector<std::vector<int64_t>> hseries;
+
+  bool profiling = false;
+  std::vector<StageEvents> ev;
+  double stage_ms[NSTAGE] = {0, 0, 0, 0, 0};
+  int64_t stage_steps = 0;
+};
+
+namespace {
+
+int hip_err(hipError_t e) {
+  if (e == hipSuccess) return DDQMC_OK;
+  if (e == hipErrorOutOfMemory) return DDQMC_ENOMEM;
+  std::fprintf(stderr, "ddqmc: HIP error %s\n", hipGetErrorString(e));
+  return DDQMC_EHIP;
+}
+
+#define HIPC(x)                           \
+  do {                                    \
+    const hipError_t e_ = (x);            \
+    if (e_ != hipSuccess) return hip_err(e_); \
+  } while (0)
+
+size_t key_size(const ddqmc_t *h) { return h->k64 ? 8 : 4; }
+
+uint64_t sort_tiles(uint64_t cap) { return (cap + SORT_TILE - 1) / SORT_TILE; }
+uint64_t merge_tiles(uint64_t a, uint64_t b) { return (a + b + MERGE_TILE - 1) / MERGE_TILE; }
+
+size_t list_bytes(size_t ks, uint64_t cap) { return 2 * cap * (ks + sizeof(int2)); }
+size_t spawn_bytes(size_t ks, uint64_t cap) {
+  return 2 * cap * (ks + sizeof(int2)) + sort_tiles(cap) * 256 * sizeof(uint64_t);
+}
+size_t merge_bytes(uint64_t cm, uint64_t cs) {
+  return merge_tiles(cm, cs) * (sizeof(uint64_t) + sizeof(Partial));
+}
+
+int validate(const ddqmc_params *p) {
+  if (!p || p->struct_size != sizeof(ddqmc_params)) return DDQMC_EINVAL;
+  if (p->Lx < 2 || p->Ly < 2 || p->Lx * p->Ly > 32) return DDQMC_EINVAL;
+  if (!(p->gamma > 0.0) || !(p->dt > 0.0) || p->n_a < 0 || !(p->is_p >= 0.0)) return DDQMC_EINVAL;
+  if (!std::isfinite(p->Jx) || !std::isfinite(p->Jy) || !std::isfinite(p->Jz)) return DDQMC_EINVAL;
+  if (p->initial_walkers <= 0 || p->initial_walkers > 2147483647LL) return DDQMC_EINVAL;
+  if (p->solve_id >= 65536u || p->capacity_hint < 0 || p->n_equil < 0) return DDQMC_EINVAL;
+  if (!std::isfinite(p->shift_damping) || !std::isfinite(p->shift_init)) return DDQMC_EINVAL;
+  return DDQMC_OK;
+}
+
+// Lattice tables and constants of one solve.
+SlotParams make_slot(const ddqmc_params &p) {
+  SlotParams s;
+  std::memset(&s, 0, sizeof(s));
+  const uint32_t Lx = (uint32_t)p.Lx, Ly = (uint32_t)p.Ly, N = Lx * Ly;
+  s.N = N;
+  s.Lx = Lx;
+  s.Ly = Ly;
+  for (uint32_t site = 0; site < N; ++site) {
+    const uint32_t x = site % Lx, y = site / Lx;
+    if (Lx > 2 || x == 0) s.rmask |= 1u << site;
+    if (Ly > 2 || y == 0) s.umask |= 1u << site;
+    if (x == Lx - 1) s.col_last |= 1u << site;
+    if (y == Ly - 1) s.row_last |= 1u << site;
+  }
+  s.nb = (uint32_t)(__builtin_popcount(s.rmask) + __builtin_popcount(s.umask));
+  s.flags = p.flags;
+  s.solve = p.solve_id;
+  s.n_a = p.n_a;
+  s.target = p.target_walkers;
+  s.n_equil = p.n_equil;
+  s.seed = p.seed;
+  s.dt = p.dt;
+  s.gamma = p.gamma;
+  s.half_gamma = 0.5 * p.gamma;
+  s.half_jz = 0.5 * p.Jz;
+  s.h_al = (p.Jx - p.Jy) * 0.25;
+  s.h_an = (p.Jx + p.Jy) * 0.25;
+  s.a_al = std::fabs(s.h_al);
+  s.a_an = std::fabs(s.h_an);
+  s.w_dn = dexp(-p.is_p);
+  s.w_up = dexp(p.is_p);
+  s.delta_over_dt = p.shift_damping / p.dt;
+  s.shift_init = p.shift_init;
+  return s;
+}
+
+SlotState fresh_state(const ddqmc_params &p, int status) {
+  SlotState st;
+  std::memset(&st, 0, sizeof(st));
+  st.S = p.shift_init;
+  st.mode = 0;
+  st.status = status;
+  st.step = 0;
+  st.nw_prev = p.initial_walkers;
+  return st;
+}
+
+void free_all(ddqmc_t *h) {
+  void *ptrs[] = {h->mk[0], h->mk[1], h->mv[0], h->mv[1], h->sk[0], h->sk[1], h->sv[0],
+                  h->sv[1], h->sort_status, h->merge_status, h->partials, h->hist, h->ctrl,
+                  h->dsp, h->dss, h->spill, h->series, h->inj_k, h->inj_v};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  for (auto &e : h->ev)
+    for (int i = 0; i <= NSTAGE; ++i) (void)hipEventDestroy(e.e[i]);
+  h->ev.clear();
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+}
+
+int alloc_list(ddqmc_t *h, uint64_t cap) {
+  const size_t ks = key_size(h);
+  for (int b = 0; b < 2; ++b) {
+    HIPC(hipMalloc(&h->mk[b], cap * ks));
+    HIPC(hipMalloc((void **)&h->mv[b], cap * sizeof(int2)));
+  }
+  h->cap_main = cap;
+  return DDQMC_OK;
+}
+
+int alloc_spawn(ddqmc_t *h, uint64_t cap) {
+  const size_t ks = key_size(h);
+  for (int b = 0; b < 2; ++b) {
+    HIPC(hipMalloc(&h->sk[b], cap * ks));
+    HIPC(hipMalloc((void **)&h->sv[b], cap * sizeof(int2)));
+  }
+  const uint64_t st = sort_tiles(cap) * 256;
+  HIPC(hipMalloc((void **)&h->sort_status, st * sizeof(uint64_t)));
+  HIPC(hipMemsetAsync(h->sort_status, 0, st * sizeof(uint64_t), h->stream));
+  h->cap_sp = cap;
+  return DDQMC_OK;
+}
+
+int alloc_merge(ddqmc_t *h) {
+  const uint64_t t = merge_tiles(h->cap_main, h->cap_sp);
+  HIPC(hipMalloc((void **)&h->merge_status, t * sizeof(uint64_t)));
+  HIPC(hipMemsetAsync(h->merge_status, 0, t * sizeof(uint64_t), h->stream));
+  HIPC(hipMalloc((void **)&h->partials, t * sizeof(Partial)));
+  return DDQMC_OK;
+}
+
+// Common construction: slots, key layout, buffers.
+int build(ddqmc_t *h, int nslots, int Nmax, uint64_t cap, void *stream) {
+  if (nslots < 1 || nslots > MAX_SLOTS || Nmax < 4 || Nmax > 32) return DDQMC_EINVAL;
+  HIPC(hipGetDevice(&h->device));
+  if (stream) {
+    h->stream = (hipStream_t)stream;
+  } else {
+    HIPC(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+    h->own_stream = true;
+  }
+  h->nslots = nslots;
+  h->Nmax = Nmax;
+  h->SB = 2 * Nmax;
+  int slot_bits = 0;
+  while ((1 << slot_bits) < nslots) ++slot_bits;
+  h->key_bits = h->SB + slot_bits;
+  if (h->key_bits > 64) return DDQMC_EINVAL;
+  h->k64 = h->key_bits > 32;
+  h->passes = (h->key_bits + 7) / 8;
+  cap = std::max<uint64_t>(cap, 4096);
+  cap = std::min<uint64_t>(cap, MAX_CAP);
+  int rc;
+  if ((rc = alloc_list(h, cap)) != DDQMC_OK) return rc;
+  if ((rc = alloc_spawn(h, std::max<uint64_t>(4096, cap / 4))) != DDQMC_OK) return rc;
+  if ((rc = alloc_merge(h)) != DDQMC_OK) return rc;
+  HIPC(hipMalloc((void **)&h->hist, MAX_PASSES * 256 * sizeof(uint32_t)));
+  HIPC(hipMemsetAsync(h->hist, 0, MAX_PASSES * 256 * sizeof(uint32_t), h->stream));
+  HIPC(hipMalloc((void **)&h->ctrl, sizeof(Ctrl)));
+  HIPC(hipMemsetAsync(h->ctrl, 0, sizeof(Ctrl), h->stream));
+  HIPC(hipMalloc((void **)&h->dsp, nslots * sizeof(SlotParams)));
+  HIPC(hipMemsetAsync(h->dsp, 0, nslots * sizeof(SlotParams), h->stream));
+  HIPC(hipMalloc((void **)&h->dss, nslots * sizeof(SlotState)));
+  HIPC(hipMemsetAsync(h->dss, 0, nslots * sizeof(SlotState), h->stream));
+  HIPC(hipMalloc((void **)&h->spill, nslots * S_NSUM * sizeof(unsigned long long)));
+  HIPC(hipMemsetAsync(h->spill, 0, nslots * S_NSUM * sizeof(unsigned long long), h->stream));
+  HIPC(hipMalloc((void **)&h->series, (size_t)SERIES_CAP * nslots * SERIES_W * sizeof(int64_t)));
+  HIPC(hipMalloc(&h->inj_k, nslots * key_size(h)));
+  HIPC(hipMalloc((void **)&h->inj_v, nslots * sizeof(int2)));
+  h->hp.assign(nslots, SlotParams{});
+  h->up.assign(nslots, ddqmc_params{});
+  h->slot_state.assign(nslots, 0);
+  h->hseries.assign(nslots, {});
+  return DDQMC_OK;
+}
+
+// Upload a sorted list (keys with slot bits) into the current buffer.
+int upload_list(ddqmc_t *h, const std::vector<uint64_t> &keys, const std::vector<int2> &vals) {
+  const size_t n = keys.size();
+  if (n > h->cap_main) return DDQMC_ECAPACITY;
+  if (n) {
+    if (h->k64) {
+      HIPC(hipMemcpyAsync(h->mk[h->cur], keys.data(), n * 8, hipMemcpyHostToDevice, h->stream));
+    } else {
+      std::vector<uint32_t> k32(keys.begin(), keys.end());
+      HIPC(hipMemcpyAsync(h->mk[h->cur], k32.data(), n * 4, hipMemcpyHostToDevice, h->stream));
+      HIPC(hipStreamSynchronize(h->stream));
+    }
+    HIPC(hipMemcpyAsync(h->mv[h->cur], vals.data(), n * sizeof(int2), hipMemcpyHostToDevice,
+                        h->stream));
+  }
+  const uint32_t n32 = (uint32_t)n;
+  HIPC(hipMemcpyAsync(&h->ctrl->n_main, &n32, sizeof(uint32_t), hipMemcpyHostToDevice, h->stream));
+  HIPC(hipStreamSynchronize(h->stream));
+  h->n_main_known = n32;
+  return DDQMC_OK;
+}
+
+int download_list(ddqmc_t *h, std::vector<uint64_t> &keys, std::vector<int2> &vals) {
+  HIPC(hipStreamSynchronize(h->stream));
+  uint32_t n = 0;
+  HIPC(hipMemcpy(&n, &h->ctrl->n_main, sizeof(uint32_t), hipMemcpyDeviceToHost));
+  keys.resize(n);
+  vals.resize(n);
+  if (n) {
+    if (h->k64) {
+      HIPC(hipMemcpy(keys.data(), h->mk[h->cur], n * 8, hipMemcpyDeviceToHost));
+    } else {
+      std::vector<uint32_t> k32(n);
+      HIPC(hipMemcpy(k32.data(), h->mk[h->cur], n * 4, hipMemcpyDeviceToHost));
+      for (uint32_t i = 0; i < n; ++i) keys[i] = k32[i];
+    }
+    HIPC(hipMemcpy(vals.data(), h->mv[h->cur], n * sizeof(int2), hipMemcpyDeviceToHost));
+  }
+  h->n_main_known = n;
+  return DDQMC_OK;
+}
+
+uint32_t clampu(uint64_t v, uint32_t lo, uint32_t hi) {
+  return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(v, lo), hi);
+}
+
+template <typename K>
+int launch_step(ddqmc_t *h, int par, StageEvents *ev) {
+  hipStream_t s = h->stream;
+  const K *ak = (const K *)h->mk[par];
+  const int2 *av = h->mv[par];
+  K *ck = (K *)h->mk[par ^ 1];
+  int2 *cv = h->mv[par ^ 1];
+  const uint32_t capS = (uint32_t)h->cap_sp, capC = (uint32_t)h->cap_main;
+  const uint64_t est_main = (uint64_t)h->n_main_known + h->n_main_known / 4 + 1;
+  const uint64_t est_sp = 2ull * h->n_spawn_known + 4096;
+  const uint32_t g_sp = clampu((est_main + NT - 1) / NT, 1, 8192);
+  const uint32_t g_h = clampu((est_sp + NT * 8 - 1) / (NT * 8), 1, 1024);
+  const uint32_t g_s = clampu(sort_tiles(est_sp), 1, (uint32_t)sort_tiles(h->cap_sp));
+  const uint32_t g_m =
+      clampu(merge_tiles(est_main, est_sp), 1, (uint32_t)merge_tiles(h->cap_main, h->cap_sp));
+  if (ev) HIPC(hipEventRecord(ev->e[0], s));
+  k_spawn<K><<<g_sp, NT, 0, s>>>(ak, av, h->ctrl, h->dsp, h->dss, (K *)h->sk[0], h->sv[0], capS,
+                                 h->SB);
+  if (h->pool)
+    k_inject<K><<<1, NT, 0, s>>>((const K *)h->inj_k, h->inj_v, h->ctrl, (K *)h->sk[0], h->sv[0],
+                                 capS);
+  if (ev) HIPC(hipEventRecord(ev->e[1], s));
+  k_hist<K><<<g_h, NT, 0, s>>>((const K *)h->sk[0], h->ctrl, h->hist, h->passes, capS);
+  if (ev) HIPC(hipEventRecord(ev->e[2], s));
+  for (int p = 0; p < h->passes; ++p)
+    k_sort_pass<K><<<g_s, NT, 0, s>>>((const K *)h->sk[p & 1], h->sv[p & 1],
+                                      (K *)h->sk[(p + 1) & 1], h->sv[(p + 1) & 1], h->ctrl,
+                                      h->hist, h->sort_status, p, capS);
+  if (ev) HIPC(hipEventRecord(ev->e[3], s));
+  const int sp = h->passes & 1;
+  k_merge<K><<<g_m, NT, 0, s>>>(ak, av, (const K *)h->sk[sp], h->sv[sp], ck, cv, capC, capS,
+                                h->ctrl, h->dsp, h->dss, h->partials, h->spill, h->merge_status,
+                                h->SB);
+  if (ev) HIPC(hipEventRecord(ev->e[4], s));
+  k_finalize<<<1, 1024, 0, s>>>(h->ctrl, h->dsp, h->dss, h->partials, h->spill, h->nslots,
+                                h->hist, h->passes, capC, capS, h->series, SERIES_CAP);
+  if (ev) HIPC(hipEventRecord(ev->e[5], s));
+  HIPC(hipGetLastError());
+  return DDQMC_OK;
+}
+
+// Grow the list (keeping the current entries) or the spawn buffers.
+int regrow(ddqmc_t *h, uint64_t need_main, uint64_t need_sp) {
+  HIPC(hipStreamSynchronize(h->stream));
+  const size_t ks = key_size(h);
+  if (need_main > h->cap_main) {
+    const uint64_t cap = std::min<uint64_t>(MAX_CAP, need_main + need_main / 2 + 4096);
+    if (cap < need_main) return DDQMC_ECAPACITY;
+    void *nk[2];
+    int2 *nv[2];
+    for (int b = 0; b < 2; ++b) {
+      HIPC(hipMalloc(&nk[b], cap * ks));
+      HIPC(hipMalloc((void **)&nv[b], cap * sizeof(int2)));
+    }
+    const uint32_t n = h->n_main_known;
+    HIPC(hipMemcpyAsync(nk[0], h->mk[h->cur], (size_t)n * ks, hipMemcpyDeviceToDevice, h->stream));
+    HIPC(hipMemcpyAsync(nv[0], h->mv[h->cur], (size_t)n * sizeof(int2), hipMemcpyDeviceToDevice,
+                        h->stream));
+    HIPC(hipStreamSynchronize(h->stream));
+    for (int b = 0; b < 2; ++b) {
+      HIPC(hipFree(h->mk[b]));
+      HIPC(hipFree(h->mv[b]));
+      h->mk[b] = nk[b];
+      h->mv[b] = nv[b];
+    }
+    h->cur = 0;
+    h->cap_main = cap;
+  }
+  if (need_sp > h->cap_sp) {
+    const uint64_t cap = std::min<uint64_t>(MAX_CAP, need_sp + need_sp / 2 + 4096);
+    if (cap < need_sp) return DDQMC_ECAPACITY;
+    for (int b = 0; b < 2; ++b) {
+      HIPC(hipFree(h->sk[b]));
+      HIPC(hipFree(h->sv[b]));
+      h->sk[b] = nullptr;
+      h->sv[b] = nullptr;
+    }
+    HIPC(hipFree(h->sort_status));
+    h->sort_status = nullptr;
+    int rc = alloc_spawn(h, cap);
+    if (rc != DDQMC_OK) return rc;
+  }
+  HIPC(hipFree(h->merge_status));
+  HIPC(hipFree(h->partials));
+  h->merge_status = nullptr;
+  h->partials = nullptr;
+  int rc = alloc_merge(h);
+  if (rc != DDQMC_OK) return rc;
+  HIPC(hipStreamSynchronize(h->stream));
+  return DDQMC_OK;
+}
+
+int run_steps(ddqmc_t *h, int64_t n) {
+  if (!h || n < 0) return DDQMC_EINVAL;
+  if (h->profiling && h->ev.size() < SERIES_CAP) {
+    const size_t old = h->ev.size();
+    h->ev.resize(SERIES_CAP);
+    for (size_t i = old; i < h->ev.size(); ++i)
+      for (int j = 0; j <= NSTAGE; ++j) HIPC(hipEventCreate(&h->ev[i].e[j]));
+  }
+  for (int i = 0; i < NSTAGE; ++i) h->stage_ms[i] = 0.0;
+  h->stage_steps = 0;
+  int64_t left = n;
+  while (left > 0) {
+    const uint32_t chunk = (uint32_t)std::min<int64_t>(left, SERIES_CAP);
+    k_chunk_begin<<<1, 1, 0, h->stream>>>(h->ctrl);
+    for (uint32_t j = 0; j < chunk; ++j) {
+      const int par = (h->cur + (int)j) & 1;
+      StageEvents *ev = h->profiling ? &h->ev[j] : nullptr;
+      const int rc = h->k64 ? launch_step<uint64_t>(h, par, ev) : launch_step<uint32_t>(h, par, ev);
+      if (rc != DDQMC_OK) return rc;
+    }
+    Ctrl c;
+    HIPC(hipMemcpyAsync(&c, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
+    HIPC(hipStreamSynchronize(h->stream));
+    const uint32_t done = c.committed;
+    if (done) {
+      std::vector<int64_t> rows((size_t)done * h->nslots * SERIES_W);
+      HIPC(hipMemcpy(rows.data(), h->series, rows.size() * sizeof(int64_t),
+                     hipMemcpyDeviceToHost));
+      for (uint32_t r = 0; r < done; ++r)
+        for (int s = 0; s < h->nslots; ++s) {
+          const int64_t *row = &rows[((size_t)r * h->nslots + s) * SERIES_W];
+          if (row[0] >= 1) h->hseries[s].insert(h->hseries[s].end(), row, row + SERIES_W);
+        }
+    }
+    if (h->profiling) {
+      for (uint32_t j = 0; j < done; ++j)
+        for (int st = 0; st < NSTAGE; ++st) {
+          float ms = 0.f;
+          HIPC(hipEventElapsedTime(&ms, h->ev[j].e[st], h->ev[j].e[st + 1]));
+          h->stage_ms[st] += ms;
+        }
+      h->stage_steps += done;
+    }
+    h->cur = (h->cur + (int)done) & 1;
+    h->n_main_known = c.n_main;
+    h->n_spawn_known = c.last_spawn;
+    left -= done;
+    // slots that entered or left are settled after a completed step
+    if (done) {
+      std::vector<SlotState> st(h->nslots);
+      HIPC(hipMemcpy(st.data(), h->dss, h->nslots * sizeof(SlotState), hipMemcpyDeviceToHost));
+      for (int s = 0; s < h->nslots; ++s) h->slot_state[s] = st[s].status;
+    }
+    if (c.abort) {
+      const uint32_t f = c.fail_flags;
+      const uint32_t need_sp = c.n_spawn, need_main = c.n_new;
+      k_rearm<<<1, 256, 0, h->stream>>>(h->ctrl, h->hist, MAX_PASSES, h->spill,
+                                         h->nslots * S_NSUM);
+      HIPC(hipGetLastError());
+      HIPC(hipStreamSynchronize(h->stream));
+      if (f & F_INT_OVF) return DDQMC_EOVERFLOW;
+      if (f & F_RNG) return DDQMC_ERNG;
+      if (f & F_EXTINCT) return DDQMC_EEXTINCT;
+      if (f & (F_SPAWN_CAP | F_MAIN_CAP)) {
+        const int rc = regrow(h, (f & F_MAIN_CAP) ? need_main : 0, (f & F_SPAWN_CAP) ? need_sp : 0);
+        if (rc != DDQMC_OK) return rc;
+        continue;
+      }
+      return DDQMC_EHIP;
+    }
+  }
+  return DDQMC_OK;
+}
+
+// Flyvbjerg-Petersen blocking of (num, den) per-step series; the error of the
+// ratio of means by the delta method, maximised over blocking levels.
+double ratio_se(const std::vector<double> &num, const std::vector<double> &den) {
+  std::vector<double> a = num, b = den;
+  double best = 0.0;
+  while (a.size() >= 16) {
+    const size_t n = a.size();
+    double ma = 0, mb = 0;
+    for (size_t i = 0; i < n; ++i) {
+      ma += a[i];
+      mb += b[i];
+    }
+    ma /= (double)n;
+    mb /= (double)n;
+    const double r = ma / mb;
+    double var = 0, mg = 0;
+    std::vector<double> g(n);
+    for (size_t i = 0; i < n; ++i) {
+      g[i] = (a[i] - r * b[i]) / mb;
+      mg += g[i];
+    }
+    mg /= (double)n;
+    for (size_t i = 0; i < n; ++i) var += (g[i] - mg) * (g[i] - mg);
+    var /= (double)(n - 1);
+    best = std::max(best, std::sqrt(var / (double)n));
+    std::vector<double> a2(n / 2), b2(n / 2);
+    for (size_t i = 0; i < n / 2; ++i) {
+      a2[i] = 0.5 * (a[2 * i] + a[2 * i + 1]);
+      b2[i] = 0.5 * (b[2 * i] + b[2 * i + 1]);
+    }
+    a.swap(a2);
+    b.swap(b2);
+  }
+  return best;
+}
+
+int fill_obs(ddqmc_t *h, int slot, ddqmc_obs *o) {
+  if (!h || !o || slot < 0 || slot >= h->nslots) return DDQMC_EINVAL;
+  HIPC(hipStreamSynchronize(h->stream));
+  SlotState st;
+  HIPC(hipMemcpy(&st, &h->dss[slot], sizeof(SlotState), hipMemcpyDeviceToHost));
+  std::memset(o, 0, sizeof(*o));
+  o->step = st.step;
+  o->shift = st.S;
+  o->mode = st.mode;
+  o->status = st.status == 0 ? 0 : 1;
+  for (int i = 0; i < S_NSUM; ++i) {
+    o->last[i] = st.last[i];
+    o->acc[i] = st.acc[i];
+  }
+  o->n_accum = st.n_accum;
+  const SlotParams &P = h->hp[slot];
+  const double wup = P.w_up;
+  const double N = (double)P.N, nb = (double)P.nb;
+  const double den = (double)st.acc[S_T_RE];
+  if (st.n_accum > 0 && den != 0.0) {
+    o->mz = (double)st.acc[S_Z] / (N * den);
+    o->mx = ((double)st.acc[S_X] * wup) / (N * den);
+    o->my = ((double)st.acc[S_Y] * wup) / (N * den);
+    o->cxx = ((double)st.acc[S_CXX] * wup) / (nb * den);
+    o->cyy = ((double)st.acc[S_CYY] * wup) / (nb * den);
+    o->czz = (double)st.acc[S_CZZ] / (nb * den);
+  }
+  // errors from the per-step series after n_equil
+  const std::vector<int64_t> &rows = h->hseries[slot];
+  std::vector<double> d, nz, nx, ny, cx, cy, cz;
+  for (size_t r = 0; r + SERIES_W <= rows.size(); r += SERIES_W) {
+    if (rows[r] <= P.n_equil) continue;
+    const int64_t *v = &rows[r + 3];
+    d.push_back((double)v[S_T_RE]);
+    nz.push_back((double)v[S_Z] / N);
+    nx.push_back((double)v[S_X] * wup / N);
+    ny.push_back((double)v[S_Y] * wup / N);
+    cx.push_back((double)v[S_CXX] * wup / nb);
+    cy.push_back((double)v[S_CYY] * wup / nb);
+    cz.push_back((double)v[S_CZZ] / nb);
+  }
+  if (d.size() >= 16) {
+    o->se_mz = ratio_se(nz, d);
+    o->se_mx = ratio_se(nx, d);
+    o->se_my = ratio_se(ny, d);
+    o->se_cxx = ratio_se(cx, d);
+    o->se_cyy = ratio_se(cy, d);
+    o->se_czz = ratio_se(cz, d);
+  }
+  return DDQMC_OK;
+}
+
+uint64_t auto_capacity(const ddqmc_params &p) {
+  if (p.capacity_hint > 0) return (uint64_t)p.capacity_hint;
+  const uint64_t t = (uint64_t)std::max<int64_t>(p.target_walkers, p.initial_walkers);
+  return std::min<uint64_t>(std::max<uint64_t>(t / 2, 16384), 1ull << 26);
+}
+
+struct StateHeader {
+  uint64_t magic;
+  uint32_t version, key_bytes;
+  ddqmc_params params;
+  SlotState state;
+  uint64_t n;
+};
+
+}  // namespace
+
+extern "C" {
+
+const char *ddqmc_strerror(int code) {
+  switch (code) {
+    case DDQMC_OK: return "ok";
+    case DDQMC_EINVAL: return "invalid argument";
+    case DDQMC_ENOMEM: return "out of memory";
+    case DDQMC_ECAPACITY: return "walker list exceeds the largest buffer";
+    case DDQMC_EOVERFLOW: return "walker count left the int32 range";
+    case DDQMC_EEXTINCT: return "walker population died out";
+    case DDQMC_EHIP: return "HIP runtime error";
+    case DDQMC_ESTATE: return "call not valid in this state";
+    case DDQMC_ERNG: return "random stream exhausted";
+    default: return "unknown error";
+  }
+}
+
+int ddqmc_batch_create(const ddqmc_params *p, int32_t count, void *hip_stream, ddqmc_t **out) {
+  if (!p || !out || count < 1 || count > MAX_SLOTS) return DDQMC_EINVAL;
+  *out = nullptr;
+  int Nmax = 0;
+  uint64_t cap = 0;
+  for (int i = 0; i < count; ++i) {
+    const int rc = validate(&p[i]);
+    if (rc != DDQMC_OK) return rc;
+    Nmax = std::max(Nmax, p[i].Lx * p[i].Ly);
+    cap += auto_capacity(p[i]);
+  }
+  ddqmc_t *h = new (std::nothrow) ddqmc_t();
+  if (!h) return DDQMC_ENOMEM;
+  int rc = build(h, count, Nmax, cap, hip_stream);
+  if (rc != DDQMC_OK) {
+    free_all(h);
+    delete h;
+    return rc;
+  }
+  std::vector<SlotState> st(count);
+  std::vector<uint64_t> keys(count);
+  std::vector<int2> vals(count);
+  for (int i = 0; i < count; ++i) {
+    h->hp[i] = make_slot(p[i]);
+    h->up[i] = p[i];
+    st[i] = fresh_state(p[i], 1);
+    h->slot_state[i] = 1;
+    keys[i] = (count > 1) ? ((uint64_t)i << h->SB) : 0ull;
+    vals[i] = make_int2((int)p[i].initial_walkers, 0);
+  }
+  rc = hip_err(hipMemcpyAsync(h->dsp, h->hp.data(), count * sizeof(SlotParams),
+                              hipMemcpyHostToDevice, h->stream));
+  if (rc == DDQMC_OK)
+    rc = hip_err(hipMemcpyAsync(h->dss, st.data(), count * sizeof(SlotState),
+                                hipMemcpyHostToDevice, h->stream));
+  if (rc == DDQMC_OK) rc = upload_list(h, keys, vals);
+  if (rc != DDQMC_OK) {
+    free_all(h);
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return DDQMC_OK;
+}
+
+int ddqmc_create(const ddqmc_params *p, void *hip_stream, ddqmc_t **out) {
+  return ddqmc_batch_create(p, 1, hip_stream, out);
+}
+
+int ddqmc_step(ddqmc_t *h, int64_t n_steps) { return run_steps(h, n_steps); }
+int ddqmc_batch_step(ddqmc_t *h, int64_t n_steps) { return run_steps(h, n_steps); }
+
+int ddqmc_observables(ddqmc_t *h, ddqmc_obs *out) { return fill_obs(h, 0, out); }
+int ddqmc_batch_observables(ddqmc_t *h, int32_t idx, ddqmc_obs *out) {
+  return fill_obs(h, idx, out);
+}
+int ddqmc_slot_observables(ddqmc_t *h, int32_t slot, ddqmc_obs *out) {
+  return fill_obs(h, slot, out);
+}
+
+int ddqmc_destroy(ddqmc_t *h) {
+  if (!h) return DDQMC_OK;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  free_all(h);
+  delete h;
+  return DDQMC_OK;
+}
+
+int ddqmc_pool_create(int32_t slots, int32_t max_sites, int64_t capacity_hint, void *hip_stream,
+                      ddqmc_t **out) {
+  if (!out || slots < 1 || slots > MAX_SLOTS || max_sites < 4 || max_sites > 32 ||
+      capacity_hint < 0)
+    return DDQMC_EINVAL;
+  *out = nullptr;
+  ddqmc_t *h = new (std::nothrow) ddqmc_t();
+  if (!h) return DDQMC_ENOMEM;
+  int rc = build(h, slots, max_sites, capacity_hint ? (uint64_t)capacity_hint : 1ull << 20,
+                 hip_stream);
+  if (rc == DDQMC_OK) {
+    h->pool = true;
+    rc = upload_list(h, {}, {});
+  }
+  if (rc != DDQMC_OK) {
+    free_all(h);
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return DDQMC_OK;
+}
+
+int ddqmc_slot_admit(ddqmc_t *h, const ddqmc_params *p, int32_t *slot) {
+  if (!h || !slot || !h->pool) return DDQMC_EINVAL;
+  int rc = validate(p);
+  if (rc != DDQMC_OK) return rc;
+  if (p->Lx * p->Ly > h->Nmax) return DDQMC_EINVAL;
+  int s = -1;
+  for (int i = 0; i < h->nslots; ++i)
+    if (h->slot_state[i] == 0) {
+      s = i;
+      break;
+    }
+  if (s < 0) return DDQMC_ESTATE;
+  h->hp[s] = make_slot(*p);
+  h->up[s] = *p;
+  h->hseries[s].clear();
+  const SlotState st = fresh_state(*p, 2);
+  HIPC(hipStreamSynchronize(h->stream));
+  uint32_t ninj = 0;
+  HIPC(hipMemcpy(&ninj, &h->ctrl->n_inject, 4, hipMemcpyDeviceToHost));
+  const uint64_t key = (uint64_t)s << h->SB;
+  const int2 val = make_int2((int)p->initial_walkers, 0);
+  if (h->k64) {
+    HIPC(hipMemcpy((uint64_t *)h->inj_k + ninj, &key, 8, hipMemcpyHostToDevice));
+  } else {
+    const uint32_t k32 = (uint32_t)key;
+    HIPC(hipMemcpy((uint32_t *)h->inj_k + ninj, &k32, 4, hipMemcpyHostToDevice));
+  }
+  HIPC(hipMemcpy(h->inj_v + ninj, &val, sizeof(int2), hipMemcpyHostToDevice));
+  ninj += 1;
+  HIPC(hipMemcpy(&h->ctrl->n_inject, &ninj, 4, hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(&h->dsp[s], &h->hp[s], sizeof(SlotParams), hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(&h->dss[s], &st, sizeof(SlotState), hipMemcpyHostToDevice));
+  h->slot_state[s] = 2;
+  *slot = s;
+  return DDQMC_OK;
+}
+
+int ddqmc_slot_retire(ddqmc_t *h, int32_t slot) {
+  if (!h || slot < 0 || slot >= h->nslots) return DDQMC_EINVAL;
+  if (h->slot_state[slot] != 1) return DDQMC_ESTATE;
+  HIPC(hipStreamSynchronize(h->stream));
+  const int32_t three = 3;
+  HIPC(hipMemcpy(&h->dss[slot].status, &three, 4, hipMemcpyHostToDevice));
+  h->slot_state[slot] = 3;
+  return DDQMC_OK;
+}
+
+int ddqmc_list_size(ddqmc_t *h, int64_t *n) {
+  if (!h || !n) return DDQMC_EINVAL;
+  HIPC(hipStreamSynchronize(h->stream));
+  uint32_t v = 0;
+  HIPC(hipMemcpy(&v, &h->ctrl->n_main, 4, hipMemcpyDeviceToHost));
+  *n = v;
+  return DDQMC_OK;
+}
+
+int ddqmc_get_walkers(ddqmc_t *h, int32_t slot, uint64_t *keys, int32_t *re, int32_t *im,
+                      int64_t cap, int64_t *n) {
+  if (!h || !n || slot < 0 || slot >= h->nslots) return DDQMC_EINVAL;
+  std::vector<uint64_t> k;
+  std::vector<int2> v;
+  int rc = download_list(h, k, v);
+  if (rc != DDQMC_OK) return rc;
+  const uint64_t lowm = (h->SB >= 64) ? ~0ull : ((1ull << h->SB) - 1);
+  int64_t cnt = 0;
+  for (size_t i = 0; i < k.size(); ++i) {
+    const uint64_t s = (h->SB >= 64) ? 0 : (k[i] >> h->SB);
+    if ((int)s != slot) continue;
+    if (cnt < cap && keys && re && im) {
+      keys[cnt] = k[i] & lowm;
+      re[cnt] = v[i].x;
+      im[cnt] = v[i].y;
+    }
+    ++cnt;
+  }
+  *n = cnt;
+  return cnt > cap ? DDQMC_EINVAL : DDQMC_OK;
+}
+
+int ddqmc_set_walkers(ddqmc_t *h, const uint64_t *keys, const int32_t *re, const int32_t *im,
+                      int64_t n) {
+  if (!h || h->nslots != 1 || n < 0 || (n > 0 && (!keys || !re || !im))) return DDQMC_EINVAL;
+  const uint64_t lim = (h->SB >= 64) ? ~0ull : ((1ull << h->SB) - 1);
+  std::vector<uint64_t> k(n);
+  std::vector<int2> v(n);
+  for (int64_t i = 0; i < n; ++i) {
+    if (keys[i] > lim || (i > 0 && keys[i] <= keys[i - 1])) return DDQMC_EINVAL;
+    if ((re[i] == 0 && im[i] == 0) || re[i] == INT32_MIN || im[i] == INT32_MIN)
+      return DDQMC_EINVAL;
+    k[i] = keys[i];
+    v[i] = make_int2(re[i], im[i]);
+  }
+  if ((uint64_t)n > h->cap_main) {
+    int rc = regrow(h, (uint64_t)n, 0);
+    if (rc != DDQMC_OK) return rc;
+  }
+  return upload_list(h, k, v);
+}
+
+int ddqmc_get_scalars(ddqmc_t *h, int32_t slot, double *shift, int32_t *mode, int64_t *step,
+                      int64_t *nw_prev) {
+  if (!h || slot < 0 || slot >= h->nslots) return DDQMC_EINVAL;
+  HIPC(hipStreamSynchronize(h->stream));
+  SlotState st;
+  HIPC(hipMemcpy(&st, &h->dss[slot], sizeof(SlotState), hipMemcpyDeviceToHost));
+  if (shift) *shift = st.S;
+  if (mode) *mode = st.mode;
+  if (step) *step = st.step;
+  if (nw_prev) *nw_prev = st.nw_prev;
+  return DDQMC_OK;
+}
+
+int ddqmc_set_scalars(ddqmc_t *h, int32_t slot, double shift, int32_t mode, int64_t step,
+                      int64_t nw_prev) {
+  if (!h || slot < 0 || slot >= h->nslots || (mode != 0 && mode != 1) || step < 0 ||
+      step > 0xffffffffLL)
+    return DDQMC_EINVAL;
+  HIPC(hipStreamSynchronize(h->stream));
+  SlotState st;
+  HIPC(hipMemcpy(&st, &h->dss[slot], sizeof(SlotState), hipMemcpyDeviceToHost));
+  st.S = shift;
+  st.mode = mode;
+  st.step = step;
+  st.nw_prev = nw_prev;
+  HIPC(hipMemcpy(&h->dss[slot], &st, sizeof(SlotState), hipMemcpyHostToDevice));
+  return DDQMC_OK;
+}
+
+int ddqmc_get_state(ddqmc_t *h, void *buf, size_t cap, size_t *n) {
+  if (!h || !n || h->nslots != 1) return DDQMC_EINVAL;
+  std::vector<uint64_t> k;
+  std::vector<int2> v;
+  int rc = download_list(h, k, v);
+  if (rc != DDQMC_OK) return rc;
+  const size_t bytes = sizeof(StateHeader) + k.size() * (8 + sizeof(int2));
+  *n = bytes;
+  if (!buf) return DDQMC_OK;
+  if (cap < bytes) return DDQMC_EINVAL;
+  StateHeader hd;
+  std::memset(&hd, 0, sizeof(hd));
+  hd.magic = 0x43514d5144445144ull;
+  hd.version = 1;
+  hd.key_bytes = 8;
+  hd.params = h->up[0];
+  HIPC(hipMemcpy(&hd.state, &h->dss[0], sizeof(SlotState), hipMemcpyDeviceToHost));
+  hd.n = k.size();
+  char *b = (char *)buf;
+  std::memcpy(b, &hd, sizeof(hd));
+  std::memcpy(b + sizeof(hd), k.data(), k.size() * 8);
+  std::memcpy(b + sizeof(hd) + k.size() * 8, v.data(), v.size() * sizeof(int2));
+  return DDQMC_OK;
+}
+
+int ddqmc_set_state(ddqmc_t *h, const void *buf, size_t n) {
+  if (!h || !buf || h->nslots != 1 || n < sizeof(StateHeader)) return DDQMC_EINVAL;
+  StateHeader hd;
+  std::memcpy(&hd, buf, sizeof(hd));
+  if (hd.magic != 0x43514d5144445144ull || hd.version != 1 || hd.key_bytes != 8)
+    return DDQMC_EINVAL;
+  if (n != sizeof(hd) + hd.n * (8 + sizeof(int2))) return DDQMC_EINVAL;
+  ddqmc_params a = hd.params, b = h->up[0];
+  a.capacity_hint = b.capacity_hint = 0;
+  if (std::memcmp(&a, &b, sizeof(a)) != 0) return DDQMC_EINVAL;
+  const char *c = (const char *)buf;
+  std::vector<uint64_t> k(hd.n);
+  std::vector<int2> v(hd.n);
+  std::memcpy(k.data(), c + sizeof(hd), hd.n * 8);
+  std::memcpy(v.data(), c + sizeof(hd) + hd.n * 8, hd.n * sizeof(int2));
+  if (hd.n > h->cap_main) {
+    int rc = regrow(h, hd.n, 0);
+    if (rc != DDQMC_OK) return rc;
+  }
+  int rc = upload_list(h, k, v);
+  if (rc != DDQMC_OK) return rc;
+  HIPC(hipMemcpy(&h->dss[0], &hd.state, sizeof(SlotState), hipMemcpyHostToDevice));
+  h->hseries[0].clear();
+  return DDQMC_OK;
+}
+
+int ddqmc_get_series(ddqmc_t *h, int32_t slot, int64_t *rows, int64_t cap, int64_t *n) {
+  if (!h || !n || slot < 0 || slot >= h->nslots) return DDQMC_EINVAL;
+  const std::vector<int64_t> &s = h->hseries[slot];
+  const int64_t nr = (int64_t)(s.size() / SERIES_W);
+  *n = nr;
+  if (rows && cap > 0)
+    std::memcpy(rows, s.data(), (size_t)std::min(cap, nr) * SERIES_W * sizeof(int64_t));
+  return DDQMC_OK;
+}
+
+int ddqmc_workspace_query(const ddqmc_params *p, int64_t capacity, size_t *bytes) {
+  if (!bytes) return DDQMC_EINVAL;
+  int rc = validate(p);
+  if (rc != DDQMC_OK) return rc;
+  const int N = p->Lx * p->Ly;
+  const size_t ks = (2 * N > 32) ? 8 : 4;
+  const uint64_t cm = capacity > 0 ? (uint64_t)capacity : auto_capacity(*p);
+  const uint64_t cs = std::max<uint64_t>(4096, cm / 4);
+  *bytes = list_bytes(ks, cm) + spawn_bytes(ks, cs) + merge_bytes(cm, cs) +
+           MAX_PASSES * 256 * 4 + sizeof(Ctrl) + sizeof(SlotParams) + sizeof(SlotState) +
+           SERIES_CAP * SERIES_W * 8;
+  return DDQMC_OK;
+}
+
+int ddqmc_set_profiling(ddqmc_t *h, int32_t on) {
+  if (!h) return DDQMC_EINVAL;
+  h->profiling = on != 0;
+  return DDQMC_OK;
+}
+
+int ddqmc_stage_times(ddqmc_t *h, double ms[5], int64_t *steps) {
+  if (!h || !ms) return DDQMC_EINVAL;
+  for (int i = 0; i < NSTAGE; ++i) ms[i] = h->stage_ms[i];
+  if (steps) *steps = h->stage_steps;
+  return DDQMC_OK;
+}
+
+int ddqmc_dev_uniforms(uint64_t seed, uint32_t solve_id, uint64_t cfg, uint32_t step,
+                       uint32_t draw, int64_t count, double *out) {
+  if (!out || count < 0) return DDQMC_EINVAL;
+  if (count == 0) return DDQMC_OK;
+  double *d = nullptr;
+  HIPC(hipMalloc((void **)&d, count * sizeof(double)));
+  k_dev_uniforms<<<1, 64>>>(seed, solve_id, cfg, step, draw, count, d);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpy(out, d, count * sizeof(double), hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  return hip_err(e);
+}
+
+int ddqmc_dev_binom(int64_t n, double p, int32_t mode, uint64_t seed, int64_t count,
+                    int64_t *out) {
+  if (!out || count < 0 || mode < 0 || mode > 2 || n < 0 || !(p >= 0.0)) return DDQMC_EINVAL;
+  if ((mode == 0 || mode == 1) && p > 1.0) return DDQMC_EINVAL;
+  if (mode == 1 && (n < 1 || p <= 0.0 || p >= 1.0)) return DDQMC_EINVAL;
+  if (count == 0) return DDQMC_OK;
+  int64_t *d = nullptr;
+  int *err = nullptr;
+  HIPC(hipMalloc((void **)&d, count * sizeof(int64_t)));
+  HIPC(hipMalloc((void **)&err, sizeof(int)));
+  HIPC(hipMemset(err, 0, sizeof(int)));
+  const int64_t blocks = (count + 255) / 256;
+  k_dev_binom<<<(uint32_t)blocks, 256>>>(n, p, mode, seed, count, d, err);
+  hipError_t e = hipGetLastError();
+  int he = 0;
+  if (e == hipSuccess) e = hipMemcpy(out, d, count * sizeof(int64_t), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(&he, err, sizeof(int), hipMemcpyDeviceToHost);
+  (void)hipFree(d);
+  (void)hipFree(err);
+  if (e != hipSuccess) return hip_err(e);
+  return he ? DDQMC_ERNG : DDQMC_OK;
+}
+
+int ddqmc_dev_math(const double *x, int64_t count, double *out) {
+  if (!x || !out || count < 0) return DDQMC_EINVAL;
+  if (count == 0) return DDQMC_OK;
+  double *dx = nullptr, *dout = nullptr;
+  HIPC(hipMalloc((void **)&dx, count * sizeof(double)));
+  HIPC(hipMalloc((void **)&dout, 4 * count * sizeof(double)));
+  hipError_t e = hipMemcpy(dx, x, count * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    k_dev_math<<<(uint32_t)((count + 255) / 256), 256>>>(dx, count, dout);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpy(out, dout, 4 * count * sizeof(double), hipMemcpyDeviceToHost);
+  (void)hipFree(dx);
+  (void)hipFree(dout);
+  return hip_err(e);
+}
+
+}  // extern "C"

@@ -1,0 +1,778 @@
+// HIP kernels of one DDQMC step on gfx950 (wave64).
+//
+//   spawn     one thread per occupied configuration: clone/death and spawning
+//             counts (model.hpp), initiator rule at the source, records staged
+//             in LDS and written with one global atomic per block iteration
+//   histogram digit counts of the records for every radix pass at once
+//   sort      LSD radix sort of the records by key, one launch per 8-bit digit,
+//             tiles ranked in LDS with wave ballots and placed by a decoupled
+//             look-back over the tiles (one pass reads and writes each record once)
+//   merge     merge-path join of the sorted list with the sorted records: sums
+//             every run of equal keys (annihilation), drops empty entries,
+//             compacts by a decoupled look-back and emits estimator sums
+//   finalize  one block: reduces the estimator sums per solve, updates the shift
+//             and the accumulators, and arms the next step
+//
+// Counts live in device memory (Ctrl) so the host never waits between steps; a
+// step that overflows a buffer sets a flag and every later kernel returns at
+// once, leaving the list of the last completed step untouched.
+#pragma once
+
+#include "model.hpp"
+
+namespace ddqmc {
+
+constexpr int NT = 256;              // threads per block
+constexpr int SORT_IT = 8;           // records per thread in a sort tile
+constexpr int SORT_TILE = NT * SORT_IT;
+constexpr int MERGE_IT = 8;          // merged positions per thread
+constexpr int MERGE_TILE = NT * MERGE_IT;
+constexpr int STAGE = 2048;          // spawn records staged in LDS per block iteration
+constexpr int MAX_PASSES = 8;
+constexpr int MAX_SLOTS = 512;
+constexpr int TICKET_MERGE = MAX_PASSES;
+constexpr int SERIES_W = 3 + S_NSUM;
+
+enum : uint32_t {
+  F_SPAWN_CAP = 1u,  // spawn records exceed their buffer
+  F_MAIN_CAP = 2u,   // the new list exceeds its buffer
+  F_INT_OVF = 4u,    // a walker count left int32
+  F_EXTINCT = 8u,    // a solve lost all walkers / its diagonal weight
+  F_RNG = 16u,       // a random stream ran dry
+};
+
+struct Ctrl {
+  uint32_t n_main;      // entries of the current list
+  uint32_t n_new;       // entries of the list being built
+  uint32_t n_spawn;     // records requested this step (may exceed the buffer)
+  uint32_t abort;       // set by finalize when a step fails
+  uint32_t flags;       // F_* of the current step
+  uint32_t fail_flags;  // flags of the failed step
+  uint32_t committed;   // steps completed since the host last looked
+  uint32_t series_pos;  // rows in the series buffer
+  uint32_t epoch;       // bumped every step; tags look-back words
+  uint32_t n_inject;    // records waiting to enter the list
+  uint32_t tickets[MAX_PASSES + 1];
+  uint32_t extinct_slot;
+  uint32_t last_spawn;  // records of the last completed step
+};
+
+struct Partial {
+  int32_t slot;
+  int32_t pad;
+  int64_t s[S_NSUM];
+};
+
+// ---- small helpers --------------------------------------------------------
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// exclusive scan over the block (NT threads); *total = sum
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *lds4, uint32_t *total) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t inc = wave_incl_scan(v);
+  if (lane == 63) lds4[w] = inc;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) {
+    const uint32_t x = lds4[i];
+    before += (i < w) ? x : 0u;
+    all += x;
+  }
+  *total = all;
+  __syncthreads();
+  return before + inc - v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// look-back words: epoch (30 bits) | flag (2 bits: 1 aggregate, 2 prefix) | count
+__device__ __forceinline__ uint64_t lb_pack(uint32_t epoch, uint32_t flag, uint32_t v) {
+  return ((uint64_t)(epoch & 0x3fffffffu) << 34) | ((uint64_t)flag << 32) | v;
+}
+__device__ __forceinline__ void lb_store(uint64_t *p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t lb_load(uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive prefix of tile t from tiles t-1, t-2, ... (word i of tile j at
+// base[j * stride]).  Waits only on tiles taken earlier from the ticket counter,
+// which are running or done, so the wait ends.
+__device__ uint32_t look_back(uint64_t *base, size_t stride, uint32_t t, uint32_t epoch) {
+  uint32_t excl = 0;
+  int64_t j = (int64_t)t - 1;
+  const uint64_t ep = (uint64_t)(epoch & 0x3fffffffu);
+  while (j >= 0) {
+    const uint64_t w = lb_load(base + (size_t)j * stride);
+    const uint32_t flag = (uint32_t)(w >> 32) & 3u;
+    if ((w >> 34) != ep || flag == 0) {
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    excl += (uint32_t)w;
+    if (flag == 2) break;
+    --j;
+  }
+  return excl;
+}
+
+template <typename K>
+__device__ __forceinline__ uint32_t lower_bound(const K *a, uint32_t n, K key) {
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (a[mid] < key)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// number of A elements among the first `diag` merged (ties: A first)
+template <typename K>
+__device__ __forceinline__ uint32_t merge_path(const K *A, uint32_t na, const K *B, uint32_t nb,
+                                               uint32_t diag) {
+  uint32_t lo = diag > nb ? diag - nb : 0;
+  uint32_t hi = diag < na ? diag : na;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (A[mid] <= B[diag - 1 - mid])
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+template <typename K>
+__device__ __forceinline__ uint32_t slot_of(K key, int SB) {
+  return (SB >= (int)(8 * sizeof(K))) ? 0u : (uint32_t)(key >> SB);
+}
+template <typename K>
+__device__ __forceinline__ K low_mask(int SB) {
+  return (SB >= (int)(8 * sizeof(K))) ? ~(K)0 : (((K)1 << SB) - 1);
+}
+
+// ---- spawn ----------------------------------------------------------------
+template <typename K>
+__global__ __launch_bounds__(NT) void k_spawn(const K *__restrict__ keys,
+                                              const int2 *__restrict__ vals, Ctrl *ctrl,
+                                              const SlotParams *__restrict__ sp,
+                                              const SlotState *__restrict__ ss,
+                                              K *__restrict__ ok, int2 *__restrict__ ov,
+                                              uint32_t cap, int SB) {
+  if (ctrl->abort) return;
+  __shared__ K sk[STAGE];
+  __shared__ int2 sv[STAGE];
+  __shared__ uint32_t scount, sbase;
+  const uint32_t n = ctrl->n_main;
+  const K lowm = low_mask<K>(SB);
+  int rng_err = 0;
+  bool int_ovf = false;
+  for (uint32_t base = blockIdx.x * NT; base < n; base += gridDim.x * NT) {
+    if (threadIdx.x == 0) scount = 0;
+    __syncthreads();
+    const uint32_t i = base + threadIdx.x;
+    if (i < n) {
+      const K key = keys[i];
+      const int2 v = vals[i];
+      const uint32_t slot = slot_of<K>(key, SB);
+      if (ss[slot].status == 1) {
+        const SlotParams &P = sp[slot];
+        const K hibits = key & ~lowm;
+        const uint64_t cfg = (uint64_t)(key & lowm);
+        const uint32_t N = P.N;
+        const uint32_t l = (uint32_t)(cfg >> N);
+        const uint32_t m = (uint32_t)(cfg & ((N == 32) ? 0xffffffffull : ((1ull << N) - 1)));
+        entry_events(P, ss[slot].S, (uint32_t)ss[slot].step, l, m, v.x, v.y, &rng_err,
+                     [&](uint32_t cl, uint32_t cm, int64_t dr, int64_t di, bool keep) {
+                       const K ck = hibits | (K)(((uint64_t)cl << N) | cm);
+                       if (!keep) {
+                         const uint32_t p = lower_bound(keys, n, ck);
+                         if (p >= n || keys[p] != ck) return;
+                       }
+                       if (dr > 2147483647LL || dr < -2147483647LL || di > 2147483647LL ||
+                           di < -2147483647LL)
+                         int_ovf = true;
+                       const int2 rv = make_int2((int)dr, (int)di);
+                       const uint32_t q = atomicAdd(&scount, 1u);
+                       if (q < (uint32_t)STAGE) {
+                         sk[q] = ck;
+                         sv[q] = rv;
+                       } else {
+                         const uint32_t g = atomicAdd(&ctrl->n_spawn, 1u);
+                         if (g < cap) {
+                           ok[g] = ck;
+                           ov[g] = rv;
+                         }
+                       }
+                     });
+      }
+    }
+    __syncthreads();
+    const uint32_t c = scount < (uint32_t)STAGE ? scount : (uint32_t)STAGE;
+    if (threadIdx.x == 0) sbase = c ? atomicAdd(&ctrl->n_spawn, c) : 0u;
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < c; q += NT) {
+      const uint32_t g = sbase + q;
+      if (g < cap) {
+        ok[g] = sk[q];
+        ov[g] = sv[q];
+      }
+    }
+    __syncthreads();
+  }
+  if (rng_err) atomicOr(&ctrl->flags, F_RNG);
+  if (int_ovf) atomicOr(&ctrl->flags, F_INT_OVF);
+}
+
+// Records of solves entering the list this step (serving admissions).
+template <typename K>
+__global__ void k_inject(const K *__restrict__ ik, const int2 *__restrict__ iv, Ctrl *ctrl,
+                         K *__restrict__ ok, int2 *__restrict__ ov, uint32_t cap) {
+  if (ctrl->abort) return;
+  __shared__ uint32_t cnt, base;
+  if (threadIdx.x == 0) {
+    cnt = ctrl->n_inject;
+    base = cnt ? atomicAdd(&ctrl->n_spawn, cnt) : 0u;
+  }
+  __syncthreads();
+  for (uint32_t q = threadIdx.x; q < cnt; q += blockDim.x) {
+    if (base + q < cap) {
+      ok[base + q] = ik[q];
+      ov[base + q] = iv[q];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) ctrl->n_inject = 0;
+}
+
+// ---- radix sort -------------------------------------------------------------
+template <typename K>
+__global__ __launch_bounds__(NT) void k_hist(const K *__restrict__ sk, Ctrl *ctrl,
+                                             uint32_t *__restrict__ hist, int passes,
+                                             uint32_t cap) {
+  if (ctrl->abort) return;
+  const uint32_t n = ctrl->n_spawn;
+  if (n > cap) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&ctrl->flags, F_SPAWN_CAP);
+    return;
+  }
+  __shared__ uint32_t h[MAX_PASSES * 256];
+  for (int i = threadIdx.x; i < passes * 256; i += NT) h[i] = 0;
+  __syncthreads();
+  for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
+    const K k = sk[i];
+    for (int p = 0; p < passes; ++p) atomicAdd(&h[p * 256 + (uint32_t)((k >> (8 * p)) & 255u)], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < passes * 256; i += NT)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+template <typename K>
+__global__ __launch_bounds__(NT) void k_sort_pass(const K *__restrict__ ik,
+                                                  const int2 *__restrict__ iv,
+                                                  K *__restrict__ okk, int2 *__restrict__ ov,
+                                                  Ctrl *ctrl, const uint32_t *__restrict__ hist,
+                                                  uint64_t *status, int pass, uint32_t cap) {
+  if (ctrl->abort) return;
+  const uint32_t n = ctrl->n_spawn;
+  if (n > cap || n == 0) return;
+  const uint32_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
+  const int shift = 8 * pass;
+  const uint32_t epoch = ctrl->epoch * 8u + (uint32_t)pass;
+
+  __shared__ K tk[SORT_TILE];
+  __shared__ int2 tv[SORT_TILE];
+  __shared__ uint32_t wcnt[NT / 64][256];
+  __shared__ uint32_t gstart[256], lstart[256], goff[256];
+  __shared__ uint32_t scan4[NT / 64];
+  __shared__ uint32_t s_tile;
+
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  {
+    uint32_t tot;
+    const uint32_t h = hist[pass * 256 + threadIdx.x];
+    gstart[threadIdx.x] = block_excl_scan(h, scan4, &tot);
+  }
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_tile = atomicAdd(&ctrl->tickets[pass], 1u);
+    for (int i = threadIdx.x; i < (NT / 64) * 256; i += NT) (&wcnt[0][0])[i] = 0;
+    __syncthreads();
+    const uint32_t t = s_tile;
+    if (t >= ntiles) break;
+    const uint32_t tbase = t * SORT_TILE;
+    const uint32_t wbase = tbase + (uint32_t)w * 64u * SORT_IT;
+    K key[SORT_IT];
+    int2 val[SORT_IT];
+    uint32_t rank[SORT_IT];
+#pragma unroll
+    for (int k = 0; k < SORT_IT; ++k) {
+      const uint32_t pos = wbase + (uint32_t)k * 64u + (uint32_t)lane;
+      const bool valid = pos < n;
+      if (valid) {
+        key[k] = ik[pos];
+        val[k] = iv[pos];
+      }
+      const uint32_t d = valid ? (uint32_t)((key[k] >> shift) & 255u) : 0u;
+      uint64_t peers = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const uint64_t bb = __ballot((d >> b) & 1u);
+        peers &= ((d >> b) & 1u) ? bb : ~bb;
+      }
+      if (valid) {
+        const uint32_t below = (uint32_t)__popcll(peers & lt);
+        const uint32_t old = wcnt[w][d];
+        rank[k] = old + below;
+        __builtin_amdgcn_wave_barrier();
+        if (below == 0) wcnt[w][d] = old + (uint32_t)__popcll(peers);
+      } else {
+        __builtin_amdgcn_wave_barrier();
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // per digit: wave prefixes, tile count, tile-local start
+    const int d = threadIdx.x;
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int ww = 0; ww < NT / 64; ++ww) {
+      const uint32_t c = wcnt[ww][d];
+      wcnt[ww][d] = cnt;
+      cnt += c;
+    }
+    uint32_t tot;
+    const uint32_t ls = block_excl_scan(cnt, scan4, &tot);
+    lstart[d] = ls;
+    uint64_t *st = status + (size_t)t * 256 + d;
+    if (t == 0) {
+      lb_store(st, lb_pack(epoch, 2u, cnt));
+      goff[d] = gstart[d];
+    } else {
+      lb_store(st, lb_pack(epoch, 1u, cnt));
+      const uint32_t excl = look_back(status + d, 256, t, epoch);
+      lb_store(st, lb_pack(epoch, 2u, excl + cnt));
+      goff[d] = gstart[d] + excl;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < SORT_IT; ++k) {
+      const uint32_t pos = wbase + (uint32_t)k * 64u + (uint32_t)lane;
+      if (pos < n) {
+        const uint32_t dd = (uint32_t)((key[k] >> shift) & 255u);
+        const uint32_t lp = lstart[dd] + wcnt[w][dd] + rank[k];
+        tk[lp] = key[k];
+        tv[lp] = val[k];
+      }
+    }
+    __syncthreads();
+    const uint32_t tn = (n - tbase) < (uint32_t)SORT_TILE ? (n - tbase) : (uint32_t)SORT_TILE;
+    for (uint32_t q = threadIdx.x; q < tn; q += NT) {
+      const K kq = tk[q];
+      const uint32_t dd = (uint32_t)((kq >> shift) & 255u);
+      const uint32_t g = goff[dd] + (q - lstart[dd]);
+      okk[g] = kq;
+      ov[g] = tv[q];
+    }
+  }
+}
+
+// ---- merge ----------------------------------------------------------------
+template <typename K>
+__global__ __launch_bounds__(NT) void k_merge(
+    const K *__restrict__ Ak, const int2 *__restrict__ Av, const K *__restrict__ Bk,
+    const int2 *__restrict__ Bv, K *__restrict__ Ck, int2 *__restrict__ Cv, uint32_t capC,
+    uint32_t capB, Ctrl *ctrl, const SlotParams *__restrict__ sp,
+    const SlotState *__restrict__ ss, Partial *__restrict__ partials,
+    unsigned long long *__restrict__ spill, uint64_t *status, int SB) {
+  if (ctrl->abort) return;
+  const uint32_t na = ctrl->n_main;
+  const uint32_t nb = ctrl->n_spawn;
+  if (nb > capB) return;
+  const uint32_t total = na + nb;
+  const uint32_t ntiles = (total + MERGE_TILE - 1) / MERGE_TILE;
+  const uint32_t epoch = ctrl->epoch;
+  const K lowm = low_mask<K>(SB);
+
+  __shared__ K sAk[MERGE_TILE], sBk[MERGE_TILE];
+  __shared__ int2 sAv[MERGE_TILE];
+  __shared__ uint32_t s_tile, s_i0, s_i1, s_excl;
+  __shared__ uint32_t scan4[NT / 64];
+  __shared__ int64_t red[NT / 64][S_NSUM];
+  bool int_ovf = false;
+
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_tile = atomicAdd(&ctrl->tickets[TICKET_MERGE], 1u);
+    __syncthreads();
+    const uint32_t t = s_tile;
+    if (t >= ntiles) break;
+    const uint32_t d0 = t * MERGE_TILE;
+    const uint32_t d1 = (d0 + MERGE_TILE < total) ? d0 + MERGE_TILE : total;
+    if (threadIdx.x == 0) s_i0 = merge_path(Ak, na, Bk, nb, d0);
+    if (threadIdx.x == 64) s_i1 = merge_path(Ak, na, Bk, nb, d1);
+    __syncthreads();
+    const uint32_t i0 = s_i0, i1 = s_i1, j0 = d0 - i0, j1 = d1 - i1;
+    const uint32_t nA = i1 - i0, nB = j1 - j0;
+    for (uint32_t q = threadIdx.x; q < nA; q += NT) {
+      sAk[q] = Ak[i0 + q];
+      sAv[q] = Av[i0 + q];
+    }
+    for (uint32_t q = threadIdx.x; q < nB; q += NT) sBk[q] = Bk[j0 + q];
+    __syncthreads();
+    auto bkey = [&](uint32_t j) -> K { return (j >= j0 && j < j1) ? sBk[j - j0] : Bk[j]; };
+    auto akey = [&](uint32_t i) -> K { return (i >= i0 && i < i1) ? sAk[i - i0] : Ak[i]; };
+
+    // this thread's merged positions [dd, dd + MERGE_IT)
+    const uint32_t len = nA + nB;
+    const uint32_t dd = (uint32_t)threadIdx.x * MERGE_IT < len ? (uint32_t)threadIdx.x * MERGE_IT
+                                                               : len;
+    uint32_t a, b;
+    {
+      uint32_t lo = dd > nB ? dd - nB : 0, hi = dd < nA ? dd : nA;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (sAk[mid] <= sBk[dd - 1 - mid])
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      a = lo;
+      b = dd - lo;
+    }
+    K ck[MERGE_IT];
+    int2 cv[MERGE_IT];
+    uint32_t nsurv = 0;
+    const uint32_t s0 = slot_of<K>(d0 < na + nb ? ((i0 < na && (j0 >= nb || Ak[i0] <= Bk[j0]))
+                                                       ? Ak[i0]
+                                                       : Bk[j0])
+                                                : (K)0,
+                                   SB);
+    int64_t acc[S_NSUM];
+#pragma unroll
+    for (int s = 0; s < S_NSUM; ++s) acc[s] = 0;
+
+#pragma unroll
+    for (int it = 0; it < MERGE_IT; ++it) {
+      if (dd + (uint32_t)it >= len) break;
+      K k;
+      int64_t R = 0, I = 0;
+      bool emit = false;
+      if (a < nA && (b >= nB || sAk[a] <= sBk[b])) {
+        k = sAk[a];
+        R = sAv[a].x;
+        I = sAv[a].y;
+        uint32_t gj = j0 + b;
+        while (gj < nb && bkey(gj) == k) {
+          const int2 v = Bv[gj];
+          R += v.x;
+          I += v.y;
+          ++gj;
+        }
+        emit = true;
+        ++a;
+      } else {
+        k = sBk[b];
+        uint32_t gj = j0 + b;
+        const uint32_t gi = i0 + a;
+        const bool head = (gj == 0) || bkey(gj - 1) != k;
+        const bool matched = (gi > 0) && akey(gi - 1) == k;
+        if (head && !matched) {
+          while (gj < nb && bkey(gj) == k) {
+            const int2 v = Bv[gj];
+            R += v.x;
+            I += v.y;
+            ++gj;
+          }
+          emit = true;
+        }
+        ++b;
+      }
+      if (!emit || (R == 0 && I == 0)) continue;
+      const uint32_t slot = slot_of<K>(k, SB);
+      if (ss[slot].status == 3) continue;  // solve leaving the list
+      if (R > 2147483647LL || R < -2147483647LL || I > 2147483647LL || I < -2147483647LL)
+        int_ovf = true;
+      ck[nsurv] = k;
+      cv[nsurv] = make_int2((int)R, (int)I);
+      ++nsurv;
+      const SlotParams &P = sp[slot];
+      const uint64_t cfg = (uint64_t)(k & lowm);
+      const uint32_t l = (uint32_t)(cfg >> P.N);
+      const uint32_t m = (uint32_t)(cfg & ((P.N == 32) ? 0xffffffffull : ((1ull << P.N) - 1)));
+      if (slot == s0) {
+        entry_sums(P, l, m, R, I, acc);
+      } else {
+        int64_t one[S_NSUM];
+#pragma unroll
+        for (int s = 0; s < S_NSUM; ++s) one[s] = 0;
+        entry_sums(P, l, m, R, I, one);
+#pragma unroll
+        for (int s = 0; s < S_NSUM; ++s)
+          if (one[s]) atomicAdd(&spill[(size_t)slot * S_NSUM + s], (unsigned long long)one[s]);
+      }
+    }
+    // compaction: position of this thread's survivors
+    uint32_t ttot;
+    const uint32_t lpos = block_excl_scan(nsurv, scan4, &ttot);
+    if (threadIdx.x == 0) {
+      uint64_t *st = status + t;
+      uint32_t excl = 0;
+      if (t == 0) {
+        lb_store(st, lb_pack(epoch, 2u, ttot));
+      } else {
+        lb_store(st, lb_pack(epoch, 1u, ttot));
+        excl = look_back(status, 1, t, epoch);
+        lb_store(st, lb_pack(epoch, 2u, excl + ttot));
+      }
+      s_excl = excl;
+      if (t == ntiles - 1) ctrl->n_new = excl + ttot;
+    }
+    // stage survivors in LDS (reuse the A arrays), then write them coalesced
+    __syncthreads();
+    for (uint32_t q = 0; q < nsurv; ++q) {
+      sAk[lpos + q] = ck[q];
+      sAv[lpos + q] = cv[q];
+    }
+    __syncthreads();
+    const uint32_t gbase = s_excl;
+    for (uint32_t q = threadIdx.x; q < ttot; q += NT) {
+      const uint32_t g = gbase + q;
+      if (g < capC) {
+        Ck[g] = sAk[q];
+        Cv[g] = sAv[q];
+      }
+    }
+    // estimator sums of the tile's first solve
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int s = 0; s < S_NSUM; ++s) {
+      const int64_t v = wave_sum(acc[s]);
+      if (lane == 0) red[w][s] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < S_NSUM) {
+      int64_t v = 0;
+#pragma unroll
+      for (int ww = 0; ww < NT / 64; ++ww) v += red[ww][threadIdx.x];
+      partials[t].s[threadIdx.x] = v;
+      if (threadIdx.x == 0) partials[t].slot = (int32_t)s0;
+    }
+  }
+  if (int_ovf) atomicOr(&ctrl->flags, F_INT_OVF);
+}
+
+// ---- finalize (one block) ---------------------------------------------------
+__global__ __launch_bounds__(1024) void k_finalize(Ctrl *ctrl, const SlotParams *__restrict__ sp,
+                                                   SlotState *ss, const Partial *partials,
+                                                   unsigned long long *spill, int nslots,
+                                                   uint32_t *hist, int passes, uint32_t capC,
+                                                   uint32_t capS, int64_t *series,
+                                                   uint32_t series_cap) {
+  if (ctrl->abort) return;
+  __shared__ unsigned long long sums[MAX_SLOTS * S_NSUM];
+  __shared__ uint32_t s_bad;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  // a spawn overflow means the merge did not run: its partials are not valid
+  if ((ctrl->flags & F_SPAWN_CAP) || ctrl->n_spawn > capS) {
+    if (tid == 0) {
+      ctrl->fail_flags = ctrl->flags | F_SPAWN_CAP;
+      ctrl->abort = 1;
+    }
+    return;
+  }
+  for (int i = tid; i < nslots * S_NSUM; i += nt) {
+    sums[i] = spill[i];
+    spill[i] = 0;
+  }
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  const uint32_t total = ctrl->n_main + ctrl->n_spawn;
+  const uint32_t ntiles = (total + MERGE_TILE - 1) / MERGE_TILE;
+  {
+    // contiguous chunk of tiles per thread; tiles are ordered by solve
+    const uint32_t per = (ntiles + nt - 1) / nt;
+    const uint32_t c0 = per * tid, c1 = (c0 + per < ntiles) ? c0 + per : ntiles;
+    int cur = -1;
+    int64_t a[S_NSUM];
+    for (int s = 0; s < S_NSUM; ++s) a[s] = 0;
+    for (uint32_t t = c0; t < c1; ++t) {
+      const int sl = partials[t].slot;
+      if (sl != cur) {
+        if (cur >= 0)
+          for (int s = 0; s < S_NSUM; ++s)
+            if (a[s]) atomicAdd(&sums[cur * S_NSUM + s], (unsigned long long)a[s]);
+        cur = sl;
+        for (int s = 0; s < S_NSUM; ++s) a[s] = 0;
+      }
+      for (int s = 0; s < S_NSUM; ++s) a[s] += partials[t].s[s];
+    }
+    if (cur >= 0)
+      for (int s = 0; s < S_NSUM; ++s)
+        if (a[s]) atomicAdd(&sums[cur * S_NSUM + s], (unsigned long long)a[s]);
+  }
+  __syncthreads();
+  uint32_t flags = ctrl->flags;
+  const uint32_t n_new = ntiles ? ctrl->n_new : 0u;
+  if (n_new > capC) flags |= F_MAIN_CAP;
+  // extinction check before anything is committed
+  for (int s = tid; s < nslots; s += nt) {
+    const SlotState &st = ss[s];
+    if (st.status != 1) continue;
+    const int64_t nw = (int64_t)sums[s * S_NSUM + S_NW];
+    const int64_t ne = (int64_t)sums[s * S_NSUM + S_NENT];
+    bool bad = (ne == 0);
+    if (st.mode == 1 && (nw == 0 || st.nw_prev == 0)) bad = true;
+    if (bad) {
+      atomicOr(&s_bad, 1u);
+      ctrl->extinct_slot = (uint32_t)s;
+    }
+  }
+  __syncthreads();
+  if (s_bad) flags |= F_EXTINCT;
+  if (flags) {
+    if (tid == 0) {
+      ctrl->fail_flags = flags;
+      ctrl->abort = 1;
+    }
+    return;
+  }
+  const uint32_t row = ctrl->series_pos;
+  for (int s = tid; s < nslots; s += nt) {
+    SlotState st = ss[s];
+    const SlotParams &P = sp[s];
+    int64_t v[S_NSUM];
+    for (int i = 0; i < S_NSUM; ++i) v[i] = (int64_t)sums[s * S_NSUM + i];
+    if (row < series_cap && st.status != 1) series[((size_t)row * nslots + s) * SERIES_W] = -1;
+    if (st.status == 0) continue;
+    if (st.status == 3) {
+      st.status = 0;
+      ss[s] = st;
+      continue;
+    }
+    if (st.status == 2) {  // entered this step: its step 0
+      st.status = 1;
+      st.step = 0;
+      st.S = P.shift_init;
+      st.mode = 0;
+      st.nw_prev = v[S_NW];
+      st.n_accum = 0;
+      for (int i = 0; i < S_NSUM; ++i) {
+        st.last[i] = v[i];
+        st.acc[i] = 0;
+      }
+      ss[s] = st;
+      continue;
+    }
+    const int64_t nw = v[S_NW];
+    if (st.mode == 0) {
+      if (nw >= P.target) st.mode = 1;
+    } else {
+      st.S = st.S + P.delta_over_dt * dlog((double)nw / (double)st.nw_prev);
+    }
+    st.nw_prev = nw;
+    st.step += 1;
+    for (int i = 0; i < S_NSUM; ++i) st.last[i] = v[i];
+    if (st.step > P.n_equil) {
+      for (int i = 0; i < S_NSUM; ++i) st.acc[i] += v[i];
+      st.n_accum += 1;
+    }
+    ss[s] = st;
+    if (row < series_cap) {
+      int64_t *r = series + ((size_t)row * nslots + s) * SERIES_W;
+      r[0] = st.step;
+      r[1] = __builtin_bit_cast(int64_t, st.S);
+      r[2] = st.mode;
+      for (int i = 0; i < S_NSUM; ++i) r[3 + i] = v[i];
+    }
+  }
+  for (int i = tid; i < passes * 256; i += nt) hist[i] = 0;
+  if (tid == 0) {
+    ctrl->n_main = n_new;
+    ctrl->last_spawn = ctrl->n_spawn;
+    ctrl->n_spawn = 0;
+    for (int p = 0; p <= MAX_PASSES; ++p) ctrl->tickets[p] = 0;
+    ctrl->epoch += 1;
+    ctrl->committed += 1;
+    ctrl->series_pos = row + 1;
+  }
+}
+
+// After a failed step: re-arm the counters (the list is untouched).
+__global__ void k_rearm(Ctrl *ctrl, uint32_t *hist, int passes, unsigned long long *spill,
+                        int nspill) {
+  for (int i = threadIdx.x; i < passes * 256; i += blockDim.x) hist[i] = 0;
+  for (int i = threadIdx.x; i < nspill; i += blockDim.x) spill[i] = 0;
+  if (threadIdx.x == 0) {
+    ctrl->n_spawn = 0;
+    ctrl->n_new = 0;
+    ctrl->flags = 0;
+    ctrl->abort = 0;
+    for (int p = 0; p <= MAX_PASSES; ++p) ctrl->tickets[p] = 0;
+    ctrl->epoch += 1;
+  }
+}
+
+// Start of a chunk of steps: the host reads these two counters at its end.
+__global__ void k_chunk_begin(Ctrl *ctrl) {
+  ctrl->committed = 0;
+  ctrl->series_pos = 0;
+}
+
+// ---- self-check kernels ---------------------------------------------------
+__global__ void k_dev_uniforms(uint64_t seed, uint32_t solve, uint64_t cfg, uint32_t step,
+                               uint32_t draw, int64_t count, double *out) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    Stream st(seed, solve, cfg, step, draw, nullptr);
+    for (int64_t i = 0; i < count; ++i) out[i] = st.next();
+  }
+}
+
+__global__ void k_dev_binom(int64_t n, double p, int mode, uint64_t seed, int64_t count,
+                            int64_t *out, int *err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  int e = 0;
+  Stream st(seed, 0, (uint64_t)i, 0, 1, &e);
+  int64_t x;
+  if (mode == 0)
+    x = binomial(n, p, st);
+  else if (mode == 1)
+    x = binomial_positive(n, p, st);
+  else
+    x = binomial_split(n, p, st);
+  out[i] = x;
+  if (e) atomicOr(err, 1);
+}
+
+__global__ void k_dev_math(const double *x, int64_t count, double *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const double v = x[i];
+  out[4 * i + 0] = dlog(v);
+  out[4 * i + 1] = dexp(v);
+  out[4 * i + 2] = __builtin_sqrt(v);
+  out[4 * i + 3] = 1.0 / v;
+}
+
+}  // namespace ddqmc

@@ -1,0 +1,297 @@
+// Dissipative XYZ lattice (arXiv:1802.05931, Sec. V) and the Liouvillian
+// elements seen from one occupied configuration |l><m| (Sec. III.C, Kronecker
+// form, element form eq. (eq:elmeq); Sec. IV.B weights), evaluated with bit
+// arithmetic on the two bitstrings.
+//
+// Bonds are the unique nearest-neighbour pairs of the periodic Lx x Ly lattice.
+// A bond is named by its origin site and direction: "right" bonds (s, s+x) and
+// "up" bonds (s, s+y).  Bond order is: right bonds by origin, then up bonds by
+// origin.  Masks of origins (rmask, umask) drop the duplicate wrap-around pair
+// on a length-2 dimension.
+#pragma once
+
+#include "sampling.hpp"
+
+namespace ddqmc {
+
+enum { S_T_RE = 0, S_T_IM, S_NW, S_Z, S_X, S_Y, S_CXX, S_CYY, S_CZZ, S_WTOT, S_NENT, S_NSUM };
+
+enum : uint32_t { FLAG_NO_INITIATOR = 1u };
+
+// Per-solve constants (device, read-only during a step).
+struct SlotParams {
+  uint32_t N, nb, Lx, Ly;
+  uint32_t rmask, umask;       // origins of right / up bonds
+  uint32_t col_last, row_last; // sites with x == Lx-1 / y == Ly-1
+  uint32_t flags, solve;
+  int64_t n_a, target, n_equil;
+  uint64_t seed;
+  double dt, gamma, half_gamma, half_jz;
+  double h_al, h_an, a_al, a_an;  // signed / absolute hop amplitude, aligned / anti
+  double w_dn, w_up;              // e^{-p}, e^{+p}
+  double delta_over_dt, shift_init;
+};
+
+// Per-solve evolving state (device, written by the step's last kernel).
+struct SlotState {
+  double S;
+  int32_t mode;    // 0 growth (S held), 1 shift varies
+  int32_t status;  // 0 empty, 1 running, 2 entering this step, 3 leaving this step
+  int64_t step, nw_prev;
+  int64_t n_accum;
+  int64_t last[S_NSUM];
+  int64_t acc[S_NSUM];
+};
+
+DQ_HD int popc(uint32_t x) { return __builtin_popcount(x); }
+
+// bit s of the result = bit of x at the right (resp. up) neighbour of s
+DQ_HD uint32_t right_of(const SlotParams &P, uint32_t x) {
+  return ((x >> 1) & ~P.col_last) | ((uint32_t)((uint64_t)x << (P.Lx - 1)) & P.col_last);
+}
+DQ_HD uint32_t up_of(const SlotParams &P, uint32_t x) {
+  return ((x >> P.Lx) & ~P.row_last) |
+         ((uint32_t)((uint64_t)x << (P.Lx * (P.Ly - 1))) & P.row_last);
+}
+DQ_HD uint32_t right_site(const SlotParams &P, uint32_t s) {
+  return ((P.col_last >> s) & 1u) ? s - (P.Lx - 1) : s + 1;
+}
+DQ_HD uint32_t up_site(const SlotParams &P, uint32_t s) {
+  return ((P.row_last >> s) & 1u) ? s - P.Lx * (P.Ly - 1) : s + P.Lx;
+}
+
+// position of the j-th set bit of x (j < popcount(x))
+DQ_HD uint32_t nth_bit(uint32_t x, int j) {
+  for (int i = 0; i < j; ++i) x &= x - 1;
+  return (uint32_t)__builtin_ctz(x);
+}
+
+struct Geometry {
+  uint32_t al_r[2], al_u[2];  // aligned right / up bonds (by origin) of l and m
+  int al[2];                  // their counts
+  uint32_t Tr, Tu;            // the bond b with l ^ m == mask_b, if any
+  bool T_aligned;             // its alignment (same in l and m)
+};
+
+DQ_HD Geometry geometry(const SlotParams &P, uint32_t l, uint32_t m) {
+  Geometry g;
+  const uint32_t x[2] = {l, m};
+  for (int s = 0; s < 2; ++s) {
+    g.al_r[s] = ~(x[s] ^ right_of(P, x[s])) & P.rmask;
+    g.al_u[s] = ~(x[s] ^ up_of(P, x[s])) & P.umask;
+    g.al[s] = popc(g.al_r[s]) + popc(g.al_u[s]);
+  }
+  const uint32_t d = l ^ m;
+  g.Tr = 0;
+  g.Tu = 0;
+  if (popc(d) == 2) {
+    g.Tr = d & right_of(P, d) & P.rmask;
+    g.Tu = d & up_of(P, d) & P.umask;
+  }
+  g.T_aligned = ((g.Tr | g.Tu) == 0) || ((g.al_r[0] & g.Tr) | (g.al_u[0] & g.Tu)) != 0;
+  return g;
+}
+
+// Hop classes seen from (l, m): 0 ket-aligned, 1 ket-anti, 2 ket to-diagonal,
+// 3 bra-aligned, 4 bra-anti, 5 bra to-diagonal.  Each is a set of bonds given by
+// origin masks; members are ordered right bonds then up bonds, by origin.
+struct HopClasses {
+  uint32_t r[6], u[6];
+  int n[6];
+  double W[6];  // n_c |element| w_child / w_parent
+  int sgn[6];   // sign of Im of the element
+};
+
+DQ_HD HopClasses hop_classes(const SlotParams &P, const Geometry &g, uint32_t l, uint32_t m) {
+  HopClasses hc;
+  const bool diag = (l == m);
+  for (int side = 0; side < 2; ++side) {
+    const int c0 = 3 * side;
+    hc.r[c0] = g.al_r[side] & ~g.Tr;
+    hc.u[c0] = g.al_u[side] & ~g.Tu;
+    hc.r[c0 + 1] = ~g.al_r[side] & P.rmask & ~g.Tr;
+    hc.u[c0 + 1] = ~g.al_u[side] & P.umask & ~g.Tu;
+    hc.r[c0 + 2] = g.Tr;
+    hc.u[c0 + 2] = g.Tu;
+  }
+  for (int c = 0; c < 6; ++c) {
+    const int kind = c % 3;
+    const bool al = (kind == 2) ? g.T_aligned : (kind == 0);
+    const double amp = al ? P.a_al : P.a_an;
+    const double h = al ? P.h_al : P.h_an;
+    const double w = diag ? P.w_dn : (kind == 2 ? P.w_up : 1.0);
+    const int sh = (h > 0.0) - (h < 0.0);
+    hc.sgn[c] = c < 3 ? -sh : sh;  // ket: -i h, bra: +i h
+    hc.n[c] = popc(hc.r[c]) + popc(hc.u[c]);
+    hc.W[c] = ((double)hc.n[c] * amp) * w;
+  }
+  return hc;
+}
+
+// Multinomial split of M walkers over the n members of one class (equal
+// weights) by a balanced binary tree of binomials; node h of the heap draws the
+// left share Bin(M, |left| / |node|).  emit(member, count) for nonzero leaves.
+template <typename F>
+DQ_HD void tree_split(int n, int64_t M, const EntryRng &rng, uint32_t draw_base, F &&emit) {
+  struct Node {
+    int lo, hi, h;
+    int64_t M;
+  };
+  Node stack[8];
+  int sp = 0;
+  stack[sp++] = Node{0, n, 1, M};
+  while (sp > 0) {
+    const Node nd = stack[--sp];
+    if (nd.M == 0) continue;
+    if (nd.hi - nd.lo == 1) {
+      emit(nd.lo, nd.M);
+      continue;
+    }
+    const int mid = nd.lo + (nd.hi - nd.lo) / 2;
+    Stream st = rng.at(draw_base + (uint32_t)nd.h);
+    const int64_t ML = binomial(nd.M, (double)(mid - nd.lo) / (double)(nd.hi - nd.lo), st);
+    stack[sp++] = Node{mid, nd.hi, 2 * nd.h + 1, nd.M - ML};
+    stack[sp++] = Node{nd.lo, mid, 2 * nd.h, ML};
+  }
+}
+
+DQ_HD int64_t sgn64(int64_t x) { return (x > 0) - (x < 0); }
+DQ_HD int64_t sgnd(double x) { return (x > 0.0) - (x < 0.0); }
+
+// One occupied configuration |l><m| with walkers R + iI: draw its clone/death
+// and spawning counts and hand every nonzero contribution to
+// emit(child_l, child_m, d_re, d_im, survives_filter_unconditionally).
+// The caller applies the initiator rule (Sec. IV.A) to contributions flagged
+// false: they survive only on configurations occupied at the start of the step.
+template <typename Emit>
+DQ_HD void entry_events(const SlotParams &P, double S, uint32_t step, uint32_t l, uint32_t m,
+                        int32_t R, int32_t I, int *err, Emit &&emit) {
+  const bool diag = (l == m);
+  const int64_t nR = R < 0 ? -(int64_t)R : (int64_t)R;
+  const int64_t nI = I < 0 ? -(int64_t)I : (int64_t)I;
+  const int64_t sR = sgn64(R), sI = sgn64(I);
+  const bool init = diag || (nR + nI > P.n_a) || (P.flags & FLAG_NO_INITIATOR);
+
+  const Geometry g = geometry(P, l, m);
+  // diagonal element: Re = -(gamma/2)(n_up(l) + n_up(m)) - S, Im = -(E_l - E_m)
+  const double d_r = -(P.half_gamma * (double)(popc(l) + popc(m))) - S;
+  const double d_i = P.half_jz * (double)(g.al[1] - g.al[0]);
+  const double p_r = P.dt * __builtin_fabs(d_r);
+  const double p_i = P.dt * __builtin_fabs(d_i);
+
+  const HopClasses hc = hop_classes(P, g, l, m);
+  double Sc[6];
+  Sc[5] = hc.W[5];
+  for (int c = 4; c >= 0; --c) Sc[c] = hc.W[c] + Sc[c + 1];
+  const double P_im = P.dt * Sc[0];
+  const uint32_t jm = l & m;  // jump sites: up in both ket and bra
+  const int nJ = popc(jm);
+  const double P_re = P.dt * ((double)nJ * P.gamma);
+
+  const double p8[8] = {p_r, p_i, P_re, P_im, p_r, p_i, P_re, P_im};
+  const int64_t n8[8] = {nR, nR, nR, nR, nI, nI, nI, nI};
+  const EntryRng rng{P.seed, ((uint64_t)l << P.N) | m, P.solve, step, err};
+  int64_t X[8];
+  channel_counts(p8, n8, rng, X);
+
+  // clone/death: dt (R + iI)(d_r + i d_i)
+  const int64_t dR = sR * sgnd(d_r) * X[0] - sI * sgnd(d_i) * X[5];
+  const int64_t dI = sI * sgnd(d_r) * X[4] + sR * sgnd(d_i) * X[1];
+  if (dR != 0 || dI != 0) emit(l, m, dR, dI, true);
+
+  // spawning along the real elements: the jump gamma S^-_k rho S^+_k
+  for (int part = 0; part < 2; ++part) {
+    const int ch = part ? 7 : 3;
+    const int64_t cnt = X[ch - 1];
+    if (cnt == 0) continue;
+    const int64_t sg = part ? sI : sR;
+    tree_split(nJ, cnt, rng, draw_channel(ch) + 64u, [&](int j, int64_t M) {
+      const uint32_t bit = 1u << nth_bit(jm, j);
+      if (part == 0)
+        emit(l & ~bit, m & ~bit, sg * M, 0, init);
+      else
+        emit(l & ~bit, m & ~bit, 0, sg * M, init);
+    });
+  }
+
+  // spawning along the imaginary elements: -iH on the ket, +iH on the bra;
+  // classes by sequential conditional binomials, members by the tree
+  for (int part = 0; part < 2; ++part) {
+    const int ch = part ? 8 : 4;
+    int64_t rem = X[ch - 1];
+    if (rem == 0) continue;
+    const int64_t sg = part ? sI : sR;
+    int last = -1;
+    for (int c = 0; c < 6; ++c)
+      if (hc.W[c] > 0.0) last = c;
+    for (int c = 0; c < 6 && rem > 0; ++c) {
+      if (hc.W[c] == 0.0) continue;
+      int64_t Mc;
+      if (c == last) {
+        Mc = rem;
+      } else {
+        Stream st = rng.at(draw_channel(ch) + 1u + (uint32_t)c);
+        Mc = binomial(rem, hc.W[c] / Sc[c], st);
+      }
+      rem -= Mc;
+      if (Mc == 0) continue;
+      const uint32_t cr = hc.r[c], cu = hc.u[c];
+      const int nr = popc(cr);
+      const int64_t sv = sg * (int64_t)hc.sgn[c];
+      tree_split(hc.n[c], Mc, rng, draw_channel(ch) + 64u + 64u * (uint32_t)c,
+                 [&](int j, int64_t M) {
+                   uint32_t bm;
+                   if (j < nr) {
+                     const uint32_t s = nth_bit(cr, j);
+                     bm = (1u << s) | (1u << right_site(P, s));
+                   } else {
+                     const uint32_t s = nth_bit(cu, j - nr);
+                     bm = (1u << s) | (1u << up_site(P, s));
+                   }
+                   const uint32_t cl = c < 3 ? (l ^ bm) : l;
+                   const uint32_t cm = c < 3 ? m : (m ^ bm);
+                   const int64_t v = sv * M;
+                   // real parent x Im element -> imaginary child; imaginary parent
+                   // x Im element -> real child, negative (Sec. III.C rule (i))
+                   if (part == 0)
+                     emit(cl, cm, 0, v, init || cl == cm);
+                   else
+                     emit(cl, cm, -v, 0, init || cl == cm);
+                 });
+    }
+  }
+}
+
+// Estimator contributions of one entry of the new list (Sec. III.A, V.A).
+DQ_HD void entry_sums(const SlotParams &P, uint32_t l, uint32_t m, int64_t R, int64_t I,
+                      int64_t s[S_NSUM]) {
+  const int64_t aR = R < 0 ? -R : R, aI = I < 0 ? -I : I;
+  s[S_WTOT] += aR + aI;
+  s[S_NENT] += 1;
+  if (l == m) {
+    const uint32_t alr = ~(l ^ right_of(P, l)) & P.rmask;
+    const uint32_t alu = ~(l ^ up_of(P, l)) & P.umask;
+    s[S_T_RE] += R;
+    s[S_T_IM] += I;
+    s[S_NW] += aR;
+    s[S_Z] += R * (int64_t)(2 * popc(l) - (int)P.N);
+    s[S_CZZ] += R * (int64_t)(2 * (popc(alr) + popc(alu)) - (int)P.nb);
+    return;
+  }
+  const uint32_t d = l ^ m;
+  const int pd = popc(d);
+  if (pd == 1) {
+    s[S_X] += R;
+    s[S_Y] += (l & d) ? -I : I;
+  } else if (pd == 2) {
+    const uint32_t tr = d & right_of(P, d) & P.rmask;
+    const uint32_t tu = d & up_of(P, d) & P.umask;
+    if (tr | tu) {
+      const bool al = ((~(l ^ right_of(P, l)) & tr) | (~(l ^ up_of(P, l)) & tu)) != 0;
+      s[S_CXX] += R;
+      s[S_CYY] += al ? -R : R;
+    }
+  }
+}
+
+}  // namespace ddqmc

@@ -1,0 +1,250 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Walker lists, shifts and integer estimator sums must be bit-identical to the
+oracle on the same Philox streams (integer work: bit-exact; the fp64 sampling
+arithmetic has a fixed operation order on both sides, so it is bit-exact too).
+Cases span several sort and merge tiles with ragged tails, u32 and u64 keys,
+importance sampling, the initiator filter, buffer regrowth, batched and served
+solves, the error paths, and a window of the full-size 4x4 workload.
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dq():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1802_05931_amd as m
+    return m
+
+
+def _same_list(a, b):
+    return (len(a[0]) == len(b[0]) and np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+            and np.array_equal(a[2], b[2]))
+
+
+def _compare_run(dq, orc, cfg, chunks, per, check_series=True):
+    g = dq.Solve(dq.make_params(**cfg))
+    o = orc.Oracle(**{k: v for k, v in cfg.items() if k != "capacity_hint"})
+    for c in range(chunks):
+        g.step(per)
+        o.step(per)
+        gl = g.walkers()
+        ol = o.get_list()
+        assert _same_list(gl, ol), f"list differs after {(c + 1) * per} steps"
+        print(f"  {cfg['Lx']}x{cfg['Ly']}: {(c + 1) * per} steps, {len(gl[0])} entries ok",
+              flush=True)
+        gs, os_ = g.scalars(), o.scalars()
+        assert gs == os_, (gs, os_)
+    if check_series:
+        assert np.array_equal(g.series(), o.series())
+    go = g.observables()
+    oacc, n_acc = o.acc()
+    assert go["n_accum"] == n_acc
+    assert list(go["acc"].values()) == oacc.tolist()
+    ratios = orc.ratios(oacc, o.N, len(orc.bonds(cfg["Lx"], cfg["Ly"])), cfg.get("is_p", 0.0))
+    for k, v in ratios.items():
+        assert go[k] == v or (np.isnan(go[k]) and np.isnan(v)), k
+    n = len(gl[0])
+    g.close()
+    return n
+
+
+def test_device_math_bit_exact(dq, orc):
+    rng = np.random.default_rng(4)
+    x = np.concatenate([rng.uniform(0, 1, 4000), np.exp(rng.uniform(-700, 700, 4000)),
+                        rng.uniform(0.5, 2, 2000), [1.0, 2.0, 5e-324, 1e-310, 0.75]])
+    out = dq.dev_math(x)
+    assert np.array_equal(out[:, 0], np.array([orc.det_log(v) for v in x]))
+    xe = rng.uniform(-700, 700, 3000)
+    oute = dq.dev_math(xe)
+    assert np.array_equal(oute[:, 1], np.array([orc.det_exp(v) for v in xe]))
+    assert np.array_equal(out[:, 2], np.sqrt(x)), "device sqrt is not correctly rounded"
+    assert np.array_equal(out[:, 3], 1.0 / x), "device division is not correctly rounded"
+
+
+def test_device_uniforms_bit_exact(dq, orc):
+    for args in [(0, 0, 0, 0, 0), (0x123456789ABCDEF0, 17, 0xDEADBEEF12, 44, 3077),
+                 (2 ** 64 - 1, 65535, 2 ** 64 - 1, 2 ** 32 - 1, 0xFFFF)]:
+        assert np.array_equal(dq.dev_uniforms(*args, 5000), orc.uniforms(*args, 5000))
+
+
+@pytest.mark.parametrize("n,p,mode", [(1, 0.3, 0), (7, 0.2, 0), (200, 0.049, 0), (1000, 0.3, 0),
+                                      (100000, 0.02, 0), (2 ** 31 - 1, 1e-6, 0), (300, 0.9, 0),
+                                      (30, 0.34, 0), (5, 0.01, 1), (400, 0.1, 1), (5, 0.8, 1),
+                                      (20000, 0.001, 1), (3, 2.4, 2), (1000, 3.05, 2)])
+def test_device_binomials_bit_exact(dq, orc, n, p, mode):
+    assert np.array_equal(dq.dev_binom(n, p, mode, 11, 20000), orc.binom_many(n, p, mode, 11, 20000))
+
+
+def test_plain_2x2_d1(dq, orc):
+    cfg = dict(workloads.D1)
+    n = _compare_run(dq, orc, cfg, chunks=10, per=300)
+    assert n > 5
+
+
+def test_plain_3x3_jx06(dq, orc):
+    cfg = dict(workloads.d2(0.6), target_walkers=20000, n_equil=200)
+    n = _compare_run(dq, orc, cfg, chunks=4, per=250)
+    assert n > 2 * 2048, "should span several tiles"
+
+
+def test_plain_2x6_initiator_off(dq, orc):
+    cfg = dict(Lx=2, Ly=6, Jx=0.5, Jy=1.0, Jz=0.8, gamma=0.7, dt=0.005, n_a=0,
+               target_walkers=3000, initial_walkers=3000, shift_init=0.0, n_equil=50, seed=9)
+    _compare_run(dq, orc, cfg, chunks=3, per=60)
+
+
+def test_5x5_u64_keys(dq, orc):
+    cfg = dict(Lx=5, Ly=5, Jx=0.7, Jy=1.0, Jz=1.0, gamma=1.0, dt=0.002, n_a=3,
+               target_walkers=20000, initial_walkers=20000, shift_init=0.0, n_equil=10, seed=3)
+    _compare_run(dq, orc, cfg, chunks=3, per=40)
+
+
+@pytest.mark.parametrize("Lx,Ly,is_p,dt,S,nent,pop,n_a", [
+    (2, 2, 0.0, 0.6, -1.2, 100, 50, 0),        # probabilities above 1
+    (3, 3, 1.5, 0.02, 0.1, 5000, 300, 3),     # IS + filter, many tiles
+    (4, 4, 1.5, 0.002, 0.0, 20000, 40, 3),    # the 4x4 workload's parameters
+    (2, 6, 0.7, 0.01, 0.3, 9000, 1000, 50),
+])
+def test_one_step_from_random_lists(dq, orc, Lx, Ly, is_p, dt, S, nent, pop, n_a):
+    keys, re, im = workloads.random_list(Lx, Ly, nent, pop, seed=nent)
+    cfg = dict(Lx=Lx, Ly=Ly, Jx=0.6, Jy=1.0, Jz=1.2, gamma=1.0, dt=dt, n_a=n_a, is_p=is_p,
+               target_walkers=2 ** 62, seed=77)
+    g = dq.Solve(dq.make_params(**cfg))
+    o = orc.Oracle(**cfg)
+    for step in (0, 1, 12345):
+        g.set_walkers(keys, re, im)
+        g.set_scalars(S, 1, step, 10 ** 6)
+        o.set_list(keys, re, im)
+        o.set_scalars(S, 1, step, 10 ** 6)
+        g.step(1)
+        o.step(1)
+        assert _same_list(g.walkers(), o.get_list())
+        assert g.scalars() == o.scalars()
+    g.close()
+
+
+def test_regrow_tiny_capacity(dq, orc):
+    cfg = dict(workloads.d2(0.6), target_walkers=20000, capacity_hint=16, n_equil=100)
+    _compare_run(dq, orc, cfg, chunks=2, per=300)
+
+
+def test_batch_equals_alone(dq, orc):
+    cfgs = [dict(workloads.D1, solve_id=0, n_equil=100),
+            dict(workloads.d2(0.9), solve_id=1, target_walkers=3000, n_equil=100),
+            dict(Lx=2, Ly=6, Jx=0.5, Jz=0.9, gamma=1.3, dt=0.005, n_a=3, target_walkers=2000,
+                 initial_walkers=2000, shift_init=0.0, solve_id=2, seed=5, n_equil=50),
+            dict(workloads.D1, solve_id=3, seed=8, n_equil=100)]
+    b = dq.Batch([dq.make_params(**c) for c in cfgs])
+    orcs = [orc.Oracle(**c) for c in cfgs]
+    for _ in range(3):
+        b.step(200)
+        for i, o in enumerate(orcs):
+            o.step(200)
+            assert _same_list(b.walkers(i), o.get_list()), i
+            assert b.scalars(i) == o.scalars(), i
+    for i, o in enumerate(orcs):
+        assert np.array_equal(b.series(i), o.series())
+    b.close()
+
+
+def test_pool_admit_retire_equals_alone(dq, orc):
+    pool = dq.Pool(slots=4, max_sites=16)
+    c1 = dict(workloads.d2(1.1), solve_id=11, target_walkers=4000, n_equil=50)
+    c2 = dict(Lx=4, Ly=4, Jx=0.8, Jy=1.0, Jz=1.0, gamma=1.5, dt=0.005, n_a=3, is_p=0.0,
+              target_walkers=5000, initial_walkers=5000, shift_init=0.0, solve_id=12, n_equil=50)
+    c3 = dict(workloads.D1, solve_id=13, n_equil=50)
+    s1 = pool.admit(dq.make_params(**c1))
+    pool.step(1)                 # s1 enters the list
+    o1 = orc.Oracle(**c1)
+    pool.step(150)
+    o1.step(150)
+    s2 = pool.admit(dq.make_params(**c2))
+    pool.step(1)
+    o1.step(1)
+    o2 = orc.Oracle(**c2)
+    pool.step(100)
+    o1.step(100)
+    o2.step(100)
+    assert _same_list(pool.walkers(s1), o1.get_list())
+    assert _same_list(pool.walkers(s2), o2.get_list())
+    pool.retire(s1)
+    s3 = pool.admit(dq.make_params(**c3))
+    assert s3 != s1
+    pool.step(1)
+    o2.step(1)
+    o3 = orc.Oracle(**c3)
+    assert len(pool.walkers(s1)[0]) == 0
+    pool.step(120)
+    o2.step(120)
+    o3.step(120)
+    assert _same_list(pool.walkers(s2), o2.get_list())
+    assert _same_list(pool.walkers(s3), o3.get_list())
+    assert np.array_equal(pool.series(s3), o3.series())
+    assert pool.scalars(s2) == o2.scalars()
+    pool.close()
+
+
+def test_int32_overflow_reports_and_keeps_state(dq):
+    from paper_1802_05931_amd import DDQMCError
+    g = dq.Solve(dq.make_params(Lx=2, Ly=2, dt=0.5, shift_init=-3.0, target_walkers=2 ** 62,
+                                initial_walkers=2 ** 31 - 10))
+    before = g.walkers()
+    with pytest.raises(DDQMCError) as e:
+        g.step(5)
+    assert e.value.code == -4
+    after = g.walkers()
+    assert g.scalars()["step"] == 0 and _same_list(before, after)
+    g.close()
+
+
+def test_invalid_parameters(dq):
+    from paper_1802_05931_amd import DDQMCError
+    for bad in [dict(Lx=1), dict(Lx=8, Ly=8), dict(dt=0.0), dict(gamma=-1.0), dict(n_a=-1),
+                dict(initial_walkers=0), dict(initial_walkers=2 ** 31), dict(is_p=-1.0)]:
+        with pytest.raises(DDQMCError) as e:
+            dq.Solve(dq.make_params(**bad))
+        assert e.value.code == -1
+
+
+def test_checkpoint_resume_bit_exact(dq):
+    cfg = dict(workloads.d2(0.6), target_walkers=5000)
+    a = dq.Solve(dq.make_params(**cfg))
+    a.step(300)
+    blob = a.get_state()
+    a.step(200)
+    b = dq.Solve(dq.make_params(**cfg))
+    b.set_state(blob)
+    b.step(200)
+    assert _same_list(a.walkers(), b.walkers())
+    assert a.scalars() == b.scalars()
+
+
+def test_full_size_4x4_window(dq, orc):
+    """The 4x4 workload at its full population (1e7 walkers, IS p = 1.5): the GPU
+    runs its warm-up, then a window of steps from that state is checked against
+    the oracle started from the same snapshot."""
+    cfg = dict(workloads.D3)
+    g = dq.Solve(dq.make_params(**cfg))
+    g.step(300)
+    keys, re, im = g.walkers()
+    sc = g.scalars()
+    assert len(keys) > 10 * 2048
+    o = orc.Oracle(**cfg)
+    o.set_list(keys, re, im)
+    o.set_scalars(sc["S"], sc["mode"], sc["step"], sc["nw_prev"])
+    print(f"  4x4 snapshot at step {sc['step']}: {len(keys)} entries", flush=True)
+    for i in range(2):
+        g.step(1)
+        o.step(1)
+        assert _same_list(g.walkers(), o.get_list())
+        assert g.scalars() == o.scalars()
+        print(f"  4x4 window step {i + 1} bit-identical", flush=True)
+    g.close()
