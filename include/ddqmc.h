@@ -161,15 +161,21 @@ int ddqmc_set_state(ddqmc_t *h, const void *buf, size_t n);
  * mode, the DDQMC_NSUM sums), int64.  *n = rows available; copies min(cap, n). */
 int ddqmc_get_series(ddqmc_t *h, int32_t slot, int64_t *rows, int64_t cap, int64_t *n);
 
+/* Per step since creation, over all slots: rows of (entries at the start of the
+ * step, spawn records produced, entries after the step), int64.  These size the
+ * memory traffic of each kernel launch (bytes per launch for a roofline). */
+int ddqmc_get_step_counts(ddqmc_t *h, int64_t *rows, int64_t cap, int64_t *n);
+
 /* Device bytes a one-slot handle with the given capacity would allocate
  * (serving admission). */
 int ddqmc_workspace_query(const ddqmc_params *p, int64_t capacity, size_t *bytes);
 
 /* Wall time of the kernels of the last ddqmc_step call, per stage, from HIP
- * events when profiling is on (ddqmc_set_profiling); ms[5] = spawn, histogram,
- * sort, merge, finalize summed over the call's steps. */
+ * events on the handle's stream when profiling is on (ddqmc_set_profiling);
+ * ms[7] = quiet scan, loud spawn, record seal, histogram, sort, merge, finalize,
+ * summed over the call's steps. */
 int ddqmc_set_profiling(ddqmc_t *h, int32_t on);
-int ddqmc_stage_times(ddqmc_t *h, double ms[5], int64_t *steps);
+int ddqmc_stage_times(ddqmc_t *h, double ms[7], int64_t *steps);
 
 /* ---- device self-checks of the sampling primitives --------------------------
  * Same streams as the step (Philox4x32-10, key (seed_lo, seed_hi ^ solve),

@@ -13,6 +13,8 @@ import numpy as np
 from ._lib import (DDQMCError, NO_INITIATOR, NSUM, Obs, Params, SERIES_W, SUM_NAMES, check, lib,
                    make_params, ptr)
 
+STAGES = ("scan", "loud", "seal", "histogram", "sort", "merge", "finalize")
+
 __all__ = ["Solve", "Batch", "Pool", "make_params", "DDQMCError", "NO_INITIATOR", "SUM_NAMES",
            "dev_uniforms", "dev_binom", "dev_math", "workspace_query"]
 
@@ -93,6 +95,15 @@ class _Handle:
                                      ctypes.byref(n)), "series")
         return rows
 
+    def step_counts(self):
+        """(entries in, spawn records, entries out) for every step so far."""
+        n = ctypes.c_int64()
+        check(lib().ddqmc_get_step_counts(self._h, None, 0, ctypes.byref(n)), "step_counts")
+        rows = np.zeros((n.value, 3), np.int64)
+        check(lib().ddqmc_get_step_counts(self._h, ptr(rows, ctypes.c_int64), n.value,
+                                          ctypes.byref(n)), "step_counts")
+        return rows
+
     def list_size(self):
         n = ctypes.c_int64()
         check(lib().ddqmc_list_size(self._h, ctypes.byref(n)), "list_size")
@@ -102,11 +113,10 @@ class _Handle:
         check(lib().ddqmc_set_profiling(self._h, 1 if on else 0), "set_profiling")
 
     def stage_times(self):
-        ms = (ctypes.c_double * 5)()
+        ms = (ctypes.c_double * 7)()
         steps = ctypes.c_int64()
         check(lib().ddqmc_stage_times(self._h, ms, ctypes.byref(steps)), "stage_times")
-        return dict(zip(("spawn", "histogram", "sort", "merge", "finalize"), list(ms))), \
-            steps.value
+        return dict(zip(STAGES, list(ms))), steps.value
 
 
 class Solve(_Handle):

@@ -95,6 +95,8 @@ SIGNATURES = {
     "ddqmc_set_state": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
     "ddqmc_get_series": (ctypes.c_int, [_vp, ctypes.c_int32, _P(ctypes.c_int64), ctypes.c_int64,
                                         _P(ctypes.c_int64)]),
+    "ddqmc_get_step_counts": (ctypes.c_int, [_vp, _P(ctypes.c_int64), ctypes.c_int64,
+                                             _P(ctypes.c_int64)]),
     "ddqmc_workspace_query": (ctypes.c_int, [_P(Params), ctypes.c_int64, _P(ctypes.c_size_t)]),
     "ddqmc_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "ddqmc_stage_times": (ctypes.c_int, [_vp, _P(ctypes.c_double), _P(ctypes.c_int64)]),

@@ -25,7 +25,7 @@ namespace {
 
 constexpr uint32_t SERIES_CAP = 1024;  // steps per chunk between host synchronisations
 constexpr uint64_t MAX_CAP = 0xF0000000ull;
-constexpr int NSTAGE = 5;
+constexpr int NSTAGE = 7;  // scan, loud, seal, histogram, sort, merge, finalize
 
 struct StageEvents {
   hipEvent_t e[NSTAGE + 1];
@@ -61,6 +61,13 @@ struct ddqmc_t {
   SlotState *dss = nullptr;
   unsigned long long *spill = nullptr;
   int64_t *series = nullptr;
+  uint32_t *counts = nullptr;  // per step: entries in, records, entries out
+  uint32_t *loud = nullptr;    // indices of the entries where some event happens
+  uint32_t *loud_cnt = nullptr;  // loud entries per scan block
+  uint32_t *loud_off = nullptr;  // their offsets (nscan + 1)
+  uint32_t *segcnt = nullptr;  // record counters of the spawn segments
+  uint32_t nscan = 1;          // blocks of the scan kernel (fixed per list capacity)
+  uint32_t coop_sort = 1, coop_merge = 1;  // co-resident block limits
   void *inj_k = nullptr;
   int2 *inj_v = nullptr;
   uint32_t n_inject_host = 0;
@@ -69,10 +76,11 @@ struct ddqmc_t {
   std::vector<ddqmc_params> up;
   std::vector<int> slot_state;  // host view: 0 free, 1 running, 2 entering, 3 leaving
   std::vector<std::vector<int64_t>> hseries;
+  std::vector<int64_t> hcounts;
 
   bool profiling = false;
   std::vector<StageEvents> ev;
-  double stage_ms[NSTAGE] = {0, 0, 0, 0, 0};
+  double stage_ms[NSTAGE] = {0, 0, 0, 0, 0, 0, 0};
   int64_t stage_steps = 0;
 };
 
@@ -166,13 +174,35 @@ SlotState fresh_state(const ddqmc_params &p, int status) {
 void free_all(ddqmc_t *h) {
   void *ptrs[] = {h->mk[0], h->mk[1], h->mv[0], h->mv[1], h->sk[0], h->sk[1], h->sv[0],
                   h->sv[1], h->sort_status, h->merge_status, h->partials, h->hist, h->ctrl,
-                  h->dsp, h->dss, h->spill, h->series, h->inj_k, h->inj_v};
+                  h->dsp, h->dss, h->spill, h->series, h->counts, h->loud, h->loud_cnt, h->loud_off, h->segcnt, h->inj_k,
+                  h->inj_v};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   for (auto &e : h->ev)
     for (int i = 0; i <= NSTAGE; ++i) (void)hipEventDestroy(e.e[i]);
   h->ev.clear();
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+}
+
+uint32_t clampu(uint64_t v, uint32_t lo, uint32_t hi) {
+  return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(v, lo), hi);
+}
+
+// The loud queue: scan block b owns loud[b * chunk, (b + 1) * chunk).
+int alloc_loud(ddqmc_t *h) {
+  if (h->loud) HIPC(hipFree(h->loud));
+  if (h->loud_cnt) HIPC(hipFree(h->loud_cnt));
+  if (h->loud_off) HIPC(hipFree(h->loud_off));
+  h->loud = nullptr;
+  h->loud_cnt = nullptr;
+  h->loud_off = nullptr;
+  h->nscan = clampu((h->cap_main + NT - 1) / NT, 1, 4096);
+  const uint64_t per = (h->cap_main + h->nscan - 1) / h->nscan;
+  const uint64_t chunk = (per + NT - 1) / NT * NT;
+  HIPC(hipMalloc((void **)&h->loud, (size_t)chunk * h->nscan * sizeof(uint32_t)));
+  HIPC(hipMalloc((void **)&h->loud_cnt, (size_t)h->nscan * sizeof(uint32_t)));
+  HIPC(hipMalloc((void **)&h->loud_off, (size_t)(h->nscan + 1) * sizeof(uint32_t)));
+  return DDQMC_OK;
 }
 
 int alloc_list(ddqmc_t *h, uint64_t cap) {
@@ -182,11 +212,12 @@ int alloc_list(ddqmc_t *h, uint64_t cap) {
     HIPC(hipMalloc((void **)&h->mv[b], cap * sizeof(int2)));
   }
   h->cap_main = cap;
-  return DDQMC_OK;
+  return alloc_loud(h);
 }
 
 int alloc_spawn(ddqmc_t *h, uint64_t cap) {
   const size_t ks = key_size(h);
+  cap = (cap + NSEG - 1) / NSEG * NSEG;
   for (int b = 0; b < 2; ++b) {
     HIPC(hipMalloc(&h->sk[b], cap * ks));
     HIPC(hipMalloc((void **)&h->sv[b], cap * sizeof(int2)));
@@ -231,6 +262,26 @@ int build(ddqmc_t *h, int nslots, int Nmax, uint64_t cap, void *stream) {
   if ((rc = alloc_list(h, cap)) != DDQMC_OK) return rc;
   if ((rc = alloc_spawn(h, std::max<uint64_t>(4096, cap / 4))) != DDQMC_OK) return rc;
   if ((rc = alloc_merge(h)) != DDQMC_OK) return rc;
+  HIPC(hipMalloc((void **)&h->segcnt, NSEG * SEG_STRIDE * sizeof(uint32_t)));
+  HIPC(hipMemsetAsync(h->segcnt, 0, NSEG * SEG_STRIDE * sizeof(uint32_t), h->stream));
+  {
+    int cus = 0, nb_sort = 0, nb_merge = 0;
+    HIPC(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
+    if (h->k64) {
+      HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nb_sort, (const void *)k_sort_pass<uint64_t>, NT, 0));
+      HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nb_merge, (const void *)k_merge<uint64_t>, NT, 0));
+    } else {
+      HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nb_sort, (const void *)k_sort_pass<uint32_t>, NT, 0));
+      HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nb_merge, (const void *)k_merge<uint32_t>, NT, 0));
+    }
+    if (cus < 1 || nb_sort < 1 || nb_merge < 1) return DDQMC_EHIP;
+    h->coop_sort = (uint32_t)(nb_sort * cus);
+    h->coop_merge = (uint32_t)(nb_merge * cus);
+  }
   HIPC(hipMalloc((void **)&h->hist, MAX_PASSES * 256 * sizeof(uint32_t)));
   HIPC(hipMemsetAsync(h->hist, 0, MAX_PASSES * 256 * sizeof(uint32_t), h->stream));
   HIPC(hipMalloc((void **)&h->ctrl, sizeof(Ctrl)));
@@ -242,6 +293,7 @@ int build(ddqmc_t *h, int nslots, int Nmax, uint64_t cap, void *stream) {
   HIPC(hipMalloc((void **)&h->spill, nslots * S_NSUM * sizeof(unsigned long long)));
   HIPC(hipMemsetAsync(h->spill, 0, nslots * S_NSUM * sizeof(unsigned long long), h->stream));
   HIPC(hipMalloc((void **)&h->series, (size_t)SERIES_CAP * nslots * SERIES_W * sizeof(int64_t)));
+  HIPC(hipMalloc((void **)&h->counts, (size_t)SERIES_CAP * 3 * sizeof(uint32_t)));
   HIPC(hipMalloc(&h->inj_k, nslots * key_size(h)));
   HIPC(hipMalloc((void **)&h->inj_v, nslots * sizeof(int2)));
   h->hp.assign(nslots, SlotParams{});
@@ -293,9 +345,6 @@ int download_list(ddqmc_t *h, std::vector<uint64_t> &keys, std::vector<int2> &va
   return DDQMC_OK;
 }
 
-uint32_t clampu(uint64_t v, uint32_t lo, uint32_t hi) {
-  return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(v, lo), hi);
-}
 
 template <typename K>
 int launch_step(ddqmc_t *h, int par, StageEvents *ev) {
@@ -304,36 +353,63 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev) {
   const int2 *av = h->mv[par];
   K *ck = (K *)h->mk[par ^ 1];
   int2 *cv = h->mv[par ^ 1];
-  const uint32_t capS = (uint32_t)h->cap_sp, capC = (uint32_t)h->cap_main;
-  const uint64_t est_main = (uint64_t)h->n_main_known + h->n_main_known / 4 + 1;
-  const uint64_t est_sp = 2ull * h->n_spawn_known + 4096;
-  const uint32_t g_sp = clampu((est_main + NT - 1) / NT, 1, 8192);
-  const uint32_t g_h = clampu((est_sp + NT * 8 - 1) / (NT * 8), 1, 1024);
-  const uint32_t g_s = clampu(sort_tiles(est_sp), 1, (uint32_t)sort_tiles(h->cap_sp));
-  const uint32_t g_m =
-      clampu(merge_tiles(est_main, est_sp), 1, (uint32_t)merge_tiles(h->cap_main, h->cap_sp));
+  const uint32_t capC = (uint32_t)h->cap_main;
+  const uint32_t segcap = (uint32_t)(h->cap_sp / NSEG);
+  // grids from the capacities: every kernel loops over the device-side counts
+  const uint32_t g_loud = clampu(h->nscan, 1, 1024);
+  const uint32_t g_h = clampu((h->cap_sp + NT * 64 - 1) / (NT * 64), 1, 128);
+  const uint32_t g_s = clampu(sort_tiles(h->cap_sp), 1, h->coop_sort);
+  const uint32_t g_m = clampu(merge_tiles(h->cap_main, h->cap_sp), 1, h->coop_merge);
   if (ev) HIPC(hipEventRecord(ev->e[0], s));
-  k_spawn<K><<<g_sp, NT, 0, s>>>(ak, av, h->ctrl, h->dsp, h->dss, (K *)h->sk[0], h->sv[0], capS,
-                                 h->SB);
+  k_spawn_scan<K><<<h->nscan, NT, 0, s>>>(ak, av, h->ctrl, h->dsp, h->dss, h->loud, h->loud_cnt,
+                                         h->SB);
+  if (ev) HIPC(hipEventRecord(ev->e[1], s));
+  k_loud_offsets<<<1, 1024, 0, s>>>(h->ctrl, h->loud_cnt, h->loud_off, h->nscan);
+  k_spawn_loud<K><<<g_loud, NT, 0, s>>>(ak, av, h->ctrl, h->dsp, h->dss, h->loud, h->loud_off,
+                                        h->nscan, (K *)h->sk[0], h->sv[0], h->segcnt, segcap,
+                                        h->SB);
+  if (ev) HIPC(hipEventRecord(ev->e[2], s));
   if (h->pool)
     k_inject<K><<<1, NT, 0, s>>>((const K *)h->inj_k, h->inj_v, h->ctrl, (K *)h->sk[0], h->sv[0],
-                                 capS);
-  if (ev) HIPC(hipEventRecord(ev->e[1], s));
-  k_hist<K><<<g_h, NT, 0, s>>>((const K *)h->sk[0], h->ctrl, h->hist, h->passes, capS);
-  if (ev) HIPC(hipEventRecord(ev->e[2], s));
-  for (int p = 0; p < h->passes; ++p)
-    k_sort_pass<K><<<g_s, NT, 0, s>>>((const K *)h->sk[p & 1], h->sv[p & 1],
-                                      (K *)h->sk[(p + 1) & 1], h->sv[(p + 1) & 1], h->ctrl,
-                                      h->hist, h->sort_status, p, capS);
+                                 h->segcnt, segcap);
+  k_seal<<<1, NSEG, 0, s>>>(h->ctrl, h->segcnt, segcap);
   if (ev) HIPC(hipEventRecord(ev->e[3], s));
-  const int sp = h->passes & 1;
-  k_merge<K><<<g_m, NT, 0, s>>>(ak, av, (const K *)h->sk[sp], h->sv[sp], ck, cv, capC, capS,
-                                h->ctrl, h->dsp, h->dss, h->partials, h->spill, h->merge_status,
-                                h->SB);
+  k_hist<K><<<g_h, NT, 0, s>>>((const K *)h->sk[0], h->ctrl, h->hist, h->passes, segcap);
   if (ev) HIPC(hipEventRecord(ev->e[4], s));
-  k_finalize<<<1, 1024, 0, s>>>(h->ctrl, h->dsp, h->dss, h->partials, h->spill, h->nslots,
-                                h->hist, h->passes, capC, capS, h->series, SERIES_CAP);
+  for (int p = 0; p < h->passes; ++p) {
+    const K *ik = (const K *)h->sk[p & 1];
+    const int2 *iv = h->sv[p & 1];
+    K *ok = (K *)h->sk[(p + 1) & 1];
+    int2 *ov = h->sv[(p + 1) & 1];
+    Ctrl *ctrl = h->ctrl;
+    const uint32_t *hist = h->hist;
+    uint64_t *status = h->sort_status;
+    int pass = p;
+    uint32_t sc = p == 0 ? segcap : 0u;
+    void *args[] = {&ik, &iv, &ok, &ov, &ctrl, &hist, &status, &pass, &sc};
+    HIPC(hipLaunchCooperativeKernel((const void *)k_sort_pass<K>, dim3(g_s), dim3(NT), args, 0, s));
+  }
   if (ev) HIPC(hipEventRecord(ev->e[5], s));
+  {
+    const int sp = h->passes & 1;
+    const K *bk = (const K *)h->sk[sp];
+    const int2 *bv = h->sv[sp];
+    Ctrl *ctrl = h->ctrl;
+    const SlotParams *dsp = h->dsp;
+    const SlotState *dss = h->dss;
+    Partial *partials = h->partials;
+    unsigned long long *spill = h->spill;
+    uint64_t *status = h->merge_status;
+    int SB = h->SB;
+    void *args[] = {&ak, &av, &bk, &bv, &ck, &cv, (void *)&capC, &ctrl, &dsp, &dss, &partials,
+                    &spill, &status, &SB};
+    HIPC(hipLaunchCooperativeKernel((const void *)k_merge<K>, dim3(g_m), dim3(NT), args, 0, s));
+  }
+  if (ev) HIPC(hipEventRecord(ev->e[6], s));
+  k_finalize<<<1, 1024, 0, s>>>(h->ctrl, h->dsp, h->dss, h->partials, h->spill, h->nslots,
+                                h->hist, h->passes, capC, h->segcnt, h->series, h->counts,
+                                SERIES_CAP);
+  if (ev) HIPC(hipEventRecord(ev->e[7], s));
   HIPC(hipGetLastError());
   return DDQMC_OK;
 }
@@ -364,6 +440,8 @@ int regrow(ddqmc_t *h, uint64_t need_main, uint64_t need_sp) {
     }
     h->cur = 0;
     h->cap_main = cap;
+    const int rc = alloc_loud(h);
+    if (rc != DDQMC_OK) return rc;
   }
   if (need_sp > h->cap_sp) {
     const uint64_t cap = std::min<uint64_t>(MAX_CAP, need_sp + need_sp / 2 + 4096);
@@ -422,6 +500,9 @@ int run_steps(ddqmc_t *h, int64_t n) {
           const int64_t *row = &rows[((size_t)r * h->nslots + s) * SERIES_W];
           if (row[0] >= 1) h->hseries[s].insert(h->hseries[s].end(), row, row + SERIES_W);
         }
+      std::vector<uint32_t> cnt((size_t)done * 3);
+      HIPC(hipMemcpy(cnt.data(), h->counts, cnt.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
+      h->hcounts.insert(h->hcounts.end(), cnt.begin(), cnt.end());
     }
     if (h->profiling) {
       for (uint32_t j = 0; j < done; ++j)
@@ -444,9 +525,9 @@ int run_steps(ddqmc_t *h, int64_t n) {
     }
     if (c.abort) {
       const uint32_t f = c.fail_flags;
-      const uint32_t need_sp = c.n_spawn, need_main = c.n_new;
+      const uint32_t need_sp = c.seg_need * (uint32_t)NSEG, need_main = c.n_new;
       k_rearm<<<1, 256, 0, h->stream>>>(h->ctrl, h->hist, MAX_PASSES, h->spill,
-                                         h->nslots * S_NSUM);
+                                         h->nslots * S_NSUM, h->segcnt);
       HIPC(hipGetLastError());
       HIPC(hipStreamSynchronize(h->stream));
       if (f & F_INT_OVF) return DDQMC_EOVERFLOW;
@@ -864,6 +945,15 @@ int ddqmc_get_series(ddqmc_t *h, int32_t slot, int64_t *rows, int64_t cap, int64
   return DDQMC_OK;
 }
 
+int ddqmc_get_step_counts(ddqmc_t *h, int64_t *rows, int64_t cap, int64_t *n) {
+  if (!h || !n) return DDQMC_EINVAL;
+  const int64_t nr = (int64_t)(h->hcounts.size() / 3);
+  *n = nr;
+  if (rows && cap > 0)
+    std::memcpy(rows, h->hcounts.data(), (size_t)std::min(cap, nr) * 3 * sizeof(int64_t));
+  return DDQMC_OK;
+}
+
 int ddqmc_workspace_query(const ddqmc_params *p, int64_t capacity, size_t *bytes) {
   if (!bytes) return DDQMC_EINVAL;
   int rc = validate(p);
@@ -884,7 +974,7 @@ int ddqmc_set_profiling(ddqmc_t *h, int32_t on) {
   return DDQMC_OK;
 }
 
-int ddqmc_stage_times(ddqmc_t *h, double ms[5], int64_t *steps) {
+int ddqmc_stage_times(ddqmc_t *h, double ms[7], int64_t *steps) {
   if (!h || !ms) return DDQMC_EINVAL;
   for (int i = 0; i < NSTAGE; ++i) ms[i] = h->stage_ms[i];
   if (steps) *steps = h->stage_steps;

@@ -1,15 +1,25 @@
 // HIP kernels of one DDQMC step on gfx950 (wave64).
 //
-//   spawn     one thread per occupied configuration: clone/death and spawning
-//             counts (model.hpp), initiator rule at the source, records staged
-//             in LDS and written with one global atomic per block iteration
+//   scan      one thread per occupied configuration: the cheap test whether any
+//             clone/death or spawning event happens (most entries: none); the
+//             others are compacted into a per-block queue
+//   loud      the entries with events, densely: counts, multinomial splits and
+//             records (model.hpp), staged in LDS and flushed into 64 segments
+//             that each have their own counter
 //   histogram digit counts of the records for every radix pass at once
 //   sort      LSD radix sort of the records by key, one launch per 8-bit digit,
 //             tiles ranked in LDS with wave ballots and placed by a decoupled
 //             look-back over the tiles (one pass reads and writes each record once)
 //   merge     merge-path join of the sorted list with the sorted records: sums
-//             every run of equal keys (annihilation), drops empty entries,
-//             compacts by a decoupled look-back and emits estimator sums
+//             every run of equal keys (annihilation) applying the initiator rule,
+//             drops empty entries, compacts by a decoupled look-back and emits
+//             estimator sums
+//
+// Same-address device atomics serialise (about 11 ns each on MI355X), so no
+// kernel here issues more than a few per segment: compaction inside a block
+// uses LDS, record output is spread over 64 counters, and the sort passes and
+// the merge take their tiles in a fixed round-robin order on a cooperative
+// (co-resident) grid instead of drawing tickets.
 //   finalize  one block: reduces the estimator sums per solve, updates the shift
 //             and the accumulators, and arms the next step
 //
@@ -29,8 +39,10 @@ constexpr int MERGE_IT = 8;          // merged positions per thread
 constexpr int MERGE_TILE = NT * MERGE_IT;
 constexpr int STAGE = 2048;          // spawn records staged in LDS per block iteration
 constexpr int MAX_PASSES = 8;
+constexpr int NSEG = 64;             // spawn-record segments
+constexpr int SEG_STRIDE = 32;       // their counters sit 128 bytes apart
+constexpr int32_t NON_INIT = INT32_MIN;  // marks the unused part of a non-initiator record
 constexpr int MAX_SLOTS = 512;
-constexpr int TICKET_MERGE = MAX_PASSES;
 constexpr int SERIES_W = 3 + S_NSUM;
 
 enum : uint32_t {
@@ -52,9 +64,10 @@ struct Ctrl {
   uint32_t series_pos;  // rows in the series buffer
   uint32_t epoch;       // bumped every step; tags look-back words
   uint32_t n_inject;    // records waiting to enter the list
-  uint32_t tickets[MAX_PASSES + 1];
   uint32_t extinct_slot;
   uint32_t last_spawn;  // records of the last completed step
+  uint32_t seg_need;    // largest segment fill of a failed step
+  uint32_t seg_prefix[NSEG + 1];  // record offsets of the segments
 };
 
 struct Partial {
@@ -160,6 +173,25 @@ __device__ __forceinline__ uint32_t merge_path(const K *A, uint32_t na, const K 
   return lo;
 }
 
+// Position pos of the concatenated segments -> index in the segmented buffer.
+__device__ __forceinline__ size_t seg_addr(const uint32_t *pre, uint32_t pos, uint32_t segcap) {
+  int lo = 0, hi = NSEG;  // pre[lo] <= pos < pre[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= pos)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return (size_t)lo * segcap + (pos - pre[lo]);
+}
+
+// contiguous range of entries of scan block b
+__device__ __forceinline__ uint32_t scan_chunk(uint32_t n, uint32_t nblocks) {
+  const uint32_t per = (n + nblocks - 1) / nblocks;
+  return (per + NT - 1) / NT * NT;
+}
+
 template <typename K>
 __device__ __forceinline__ uint32_t slot_of(K key, int SB) {
   return (SB >= (int)(8 * sizeof(K))) ? 0u : (uint32_t)(key >> SB);
@@ -170,73 +202,171 @@ __device__ __forceinline__ K low_mask(int SB) {
 }
 
 // ---- spawn ----------------------------------------------------------------
+// Pass 1: the quiet test of every entry (one Philox block).  Block b owns the
+// entries [b*chunk, (b+1)*chunk); the loud ones go to loud[b*chunk + ...] in any
+// order, their number to loud_cnt[b].
 template <typename K>
-__global__ __launch_bounds__(NT) void k_spawn(const K *__restrict__ keys,
-                                              const int2 *__restrict__ vals, Ctrl *ctrl,
-                                              const SlotParams *__restrict__ sp,
-                                              const SlotState *__restrict__ ss,
-                                              K *__restrict__ ok, int2 *__restrict__ ov,
-                                              uint32_t cap, int SB) {
+__global__ __launch_bounds__(NT) void k_spawn_scan(const K *__restrict__ keys,
+                                                   const int2 *__restrict__ vals, Ctrl *ctrl,
+                                                   const SlotParams *__restrict__ sp,
+                                                   const SlotState *__restrict__ ss,
+                                                   uint32_t *__restrict__ loud,
+                                                   uint32_t *__restrict__ loud_cnt, int SB) {
+  if (ctrl->abort) return;
+  __shared__ uint32_t lcount;
+  const uint32_t n = ctrl->n_main;
+  const uint32_t chunk = scan_chunk(n, gridDim.x);
+  const uint32_t b0 = blockIdx.x * chunk;
+  const uint32_t b1 = (b0 + chunk < n) ? b0 + chunk : n;
+  const K lowm = low_mask<K>(SB);
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  if (threadIdx.x == 0) lcount = 0;
+  __syncthreads();
+  // the loop bound is wave-uniform so every lane reaches the ballot
+  for (uint32_t base = b0 + (threadIdx.x & ~63u); base < b1; base += NT) {
+    const uint32_t i = base + (uint32_t)lane;
+    bool is_loud = false;
+    if (i < b1) {
+      const K key = keys[i];
+      const uint32_t slot = slot_of<K>(key, SB);
+      if (ss[slot].status == 1) {
+        const int2 v = vals[i];
+        const SlotParams &P = sp[slot];
+        const uint64_t cfg = (uint64_t)(key & lowm);
+        const uint32_t N = P.N;
+        const uint32_t l = (uint32_t)(cfg >> N);
+        const uint32_t m = (uint32_t)(cfg & ((N == 32) ? 0xffffffffull : ((1ull << N) - 1)));
+        is_loud = !entry_quiet(P, ss[slot].S, (uint32_t)ss[slot].step, l, m, v.x, v.y);
+      }
+    }
+    const uint64_t mask = __ballot(is_loud);
+    if (mask) {
+      const int leader = __builtin_ctzll(mask);
+      uint32_t qbase = 0;
+      if (lane == leader) qbase = atomicAdd(&lcount, (uint32_t)__popcll(mask));
+      qbase = __shfl(qbase, leader, 64);
+      if (is_loud) loud[b0 + qbase + (uint32_t)__popcll(mask & lt)] = i;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) loud_cnt[blockIdx.x] = lcount;
+}
+
+// Append records to segment seg (its counter is segcnt[seg * SEG_STRIDE]).
+template <typename K>
+__device__ __forceinline__ void seg_flush(const K *sk, const int2 *sv, uint32_t c, int seg,
+                                          uint32_t *segcnt, K *ok, int2 *ov, uint32_t segcap,
+                                          uint32_t *sbase) {
+  if (threadIdx.x == 0) *sbase = c ? atomicAdd(&segcnt[seg * SEG_STRIDE], c) : 0u;
+  __syncthreads();
+  const uint32_t b = *sbase;
+  const size_t off = (size_t)seg * segcap;
+  for (uint32_t q = threadIdx.x; q < c; q += NT)
+    if (b + q < segcap) {
+      ok[off + b + q] = sk[q];
+      ov[off + b + q] = sv[q];
+    }
+  __syncthreads();
+}
+
+// Offsets of the scan blocks' loud queues: loud_off[b] = sum of loud_cnt[< b],
+// loud_off[nscan] = all loud entries.  One block of 1024 threads.
+__global__ __launch_bounds__(1024) void k_loud_offsets(Ctrl *ctrl, const uint32_t *loud_cnt,
+                                                       uint32_t *loud_off, uint32_t nscan) {
+  if (ctrl->abort) return;
+  __shared__ uint32_t wsum[16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint32_t per = (nscan + 1023) / 1024;
+  const uint32_t b0 = tid * per, b1 = (b0 + per < nscan) ? b0 + per : nscan;
+  uint32_t local = 0;
+  for (uint32_t b = b0; b < b1; ++b) local += loud_cnt[b];
+  const uint32_t inc = wave_incl_scan(local);
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  uint32_t before = 0;
+  for (int i = 0; i < w; ++i) before += wsum[i];
+  uint32_t run = before + inc - local;
+  for (uint32_t b = b0; b < b1; ++b) {
+    loud_off[b] = run;
+    run += loud_cnt[b];
+  }
+  if (tid == 1023) loud_off[nscan] = before + inc;
+}
+
+// Pass 2: the loud entries, densely (flat index over all scan blocks): clone/
+// death and spawning counts and their records.  The initiator rule is applied
+// in the merge: a record from a non-initiator parent carries NON_INIT in its
+// unused (re or im) part.
+template <typename K>
+__global__ __launch_bounds__(NT) void k_spawn_loud(
+    const K *__restrict__ keys, const int2 *__restrict__ vals, Ctrl *ctrl,
+    const SlotParams *__restrict__ sp, const SlotState *__restrict__ ss,
+    const uint32_t *__restrict__ loud, const uint32_t *__restrict__ loud_off, uint32_t nscan,
+    K *__restrict__ ok, int2 *__restrict__ ov, uint32_t *segcnt, uint32_t segcap, int SB) {
   if (ctrl->abort) return;
   __shared__ K sk[STAGE];
   __shared__ int2 sv[STAGE];
   __shared__ uint32_t scount, sbase;
   const uint32_t n = ctrl->n_main;
+  const uint32_t chunk = scan_chunk(n, nscan);
+  const uint32_t nl = loud_off[nscan];
+  const int seg = blockIdx.x % NSEG;
   const K lowm = low_mask<K>(SB);
   int rng_err = 0;
   bool int_ovf = false;
-  for (uint32_t base = blockIdx.x * NT; base < n; base += gridDim.x * NT) {
+  for (uint32_t base = blockIdx.x * NT; base < nl; base += gridDim.x * NT) {
     if (threadIdx.x == 0) scount = 0;
     __syncthreads();
-    const uint32_t i = base + threadIdx.x;
-    if (i < n) {
+    const uint32_t q = base + threadIdx.x;
+    if (q < nl) {
+      uint32_t lo = 0, hi = nscan;  // loud_off[lo] <= q < loud_off[hi]
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (loud_off[mid] <= q)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      const uint32_t i = loud[lo * chunk + (q - loud_off[lo])];
       const K key = keys[i];
       const int2 v = vals[i];
       const uint32_t slot = slot_of<K>(key, SB);
-      if (ss[slot].status == 1) {
-        const SlotParams &P = sp[slot];
-        const K hibits = key & ~lowm;
-        const uint64_t cfg = (uint64_t)(key & lowm);
-        const uint32_t N = P.N;
-        const uint32_t l = (uint32_t)(cfg >> N);
-        const uint32_t m = (uint32_t)(cfg & ((N == 32) ? 0xffffffffull : ((1ull << N) - 1)));
-        entry_events(P, ss[slot].S, (uint32_t)ss[slot].step, l, m, v.x, v.y, &rng_err,
-                     [&](uint32_t cl, uint32_t cm, int64_t dr, int64_t di, bool keep) {
-                       const K ck = hibits | (K)(((uint64_t)cl << N) | cm);
-                       if (!keep) {
-                         const uint32_t p = lower_bound(keys, n, ck);
-                         if (p >= n || keys[p] != ck) return;
+      const SlotParams &P = sp[slot];
+      const K hibits = key & ~lowm;
+      const uint64_t cfg = (uint64_t)(key & lowm);
+      const uint32_t N = P.N;
+      const uint32_t l = (uint32_t)(cfg >> N);
+      const uint32_t m = (uint32_t)(cfg & ((N == 32) ? 0xffffffffull : ((1ull << N) - 1)));
+      entry_events(P, ss[slot].S, (uint32_t)ss[slot].step, l, m, v.x, v.y, &rng_err,
+                   [&](uint32_t cl, uint32_t cm, int64_t dr, int64_t di, bool keep) {
+                     const K ck = hibits | (K)(((uint64_t)cl << N) | cm);
+                     if (dr > 2147483647LL || dr < -2147483647LL || di > 2147483647LL ||
+                         di < -2147483647LL)
+                       int_ovf = true;
+                     int2 rv = make_int2((int)dr, (int)di);
+                     if (!keep) {
+                       if (dr != 0)
+                         rv.y = NON_INIT;
+                       else
+                         rv.x = NON_INIT;
+                     }
+                     const uint32_t s = atomicAdd(&scount, 1u);
+                     if (s < (uint32_t)STAGE) {
+                       sk[s] = ck;
+                       sv[s] = rv;
+                     } else {  // staging full: straight to the segment
+                       const uint32_t g = atomicAdd(&segcnt[seg * SEG_STRIDE], 1u);
+                       if (g < segcap) {
+                         ok[(size_t)seg * segcap + g] = ck;
+                         ov[(size_t)seg * segcap + g] = rv;
                        }
-                       if (dr > 2147483647LL || dr < -2147483647LL || di > 2147483647LL ||
-                           di < -2147483647LL)
-                         int_ovf = true;
-                       const int2 rv = make_int2((int)dr, (int)di);
-                       const uint32_t q = atomicAdd(&scount, 1u);
-                       if (q < (uint32_t)STAGE) {
-                         sk[q] = ck;
-                         sv[q] = rv;
-                       } else {
-                         const uint32_t g = atomicAdd(&ctrl->n_spawn, 1u);
-                         if (g < cap) {
-                           ok[g] = ck;
-                           ov[g] = rv;
-                         }
-                       }
-                     });
-      }
+                     }
+                   });
     }
     __syncthreads();
-    const uint32_t c = scount < (uint32_t)STAGE ? scount : (uint32_t)STAGE;
-    if (threadIdx.x == 0) sbase = c ? atomicAdd(&ctrl->n_spawn, c) : 0u;
-    __syncthreads();
-    for (uint32_t q = threadIdx.x; q < c; q += NT) {
-      const uint32_t g = sbase + q;
-      if (g < cap) {
-        ok[g] = sk[q];
-        ov[g] = sv[q];
-      }
-    }
-    __syncthreads();
+    seg_flush(sk, sv, scount < (uint32_t)STAGE ? scount : (uint32_t)STAGE, seg, segcnt, ok, ov,
+              segcap, &sbase);
   }
   if (rng_err) atomicOr(&ctrl->flags, F_RNG);
   if (int_ovf) atomicOr(&ctrl->flags, F_INT_OVF);
@@ -245,16 +375,17 @@ __global__ __launch_bounds__(NT) void k_spawn(const K *__restrict__ keys,
 // Records of solves entering the list this step (serving admissions).
 template <typename K>
 __global__ void k_inject(const K *__restrict__ ik, const int2 *__restrict__ iv, Ctrl *ctrl,
-                         K *__restrict__ ok, int2 *__restrict__ ov, uint32_t cap) {
+                         K *__restrict__ ok, int2 *__restrict__ ov, uint32_t *segcnt,
+                         uint32_t segcap) {
   if (ctrl->abort) return;
   __shared__ uint32_t cnt, base;
   if (threadIdx.x == 0) {
     cnt = ctrl->n_inject;
-    base = cnt ? atomicAdd(&ctrl->n_spawn, cnt) : 0u;
+    base = cnt ? atomicAdd(&segcnt[0], cnt) : 0u;
   }
   __syncthreads();
   for (uint32_t q = threadIdx.x; q < cnt; q += blockDim.x) {
-    if (base + q < cap) {
+    if (base + q < segcap) {
       ok[base + q] = ik[q];
       ov[base + q] = iv[q];
     }
@@ -263,38 +394,66 @@ __global__ void k_inject(const K *__restrict__ ik, const int2 *__restrict__ iv, 
   if (threadIdx.x == 0) ctrl->n_inject = 0;
 }
 
+// Segment offsets and the record count (one wave).
+__global__ void k_seal(Ctrl *ctrl, const uint32_t *segcnt, uint32_t segcap) {
+  if (ctrl->abort) return;
+  const int s = threadIdx.x;  // 64 threads
+  const uint32_t c = segcnt[s * SEG_STRIDE];
+  const uint32_t inc = wave_incl_scan(c);
+  ctrl->seg_prefix[s] = inc - c;
+  if (s == NSEG - 1) {
+    ctrl->seg_prefix[NSEG] = inc;
+    ctrl->n_spawn = inc;
+  }
+  uint32_t mx = c;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const uint32_t t = __shfl_xor(mx, o, 64);
+    mx = t > mx ? t : mx;
+  }
+  if (s == 0 && mx > segcap) {
+    ctrl->seg_need = mx;
+    atomicOr(&ctrl->flags, F_SPAWN_CAP);
+  }
+}
+
 // ---- radix sort -------------------------------------------------------------
+// Digit counts of all passes; the records are read through the segment map.
 template <typename K>
 __global__ __launch_bounds__(NT) void k_hist(const K *__restrict__ sk, Ctrl *ctrl,
                                              uint32_t *__restrict__ hist, int passes,
-                                             uint32_t cap) {
-  if (ctrl->abort) return;
-  const uint32_t n = ctrl->n_spawn;
-  if (n > cap) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&ctrl->flags, F_SPAWN_CAP);
-    return;
-  }
+                                             uint32_t segcap) {
+  if (ctrl->abort || (ctrl->flags & F_SPAWN_CAP)) return;
   __shared__ uint32_t h[MAX_PASSES * 256];
+  __shared__ uint32_t pre[NSEG + 1];
+  const uint32_t n = ctrl->n_spawn;
   for (int i = threadIdx.x; i < passes * 256; i += NT) h[i] = 0;
+  for (int i = threadIdx.x; i <= NSEG; i += NT) pre[i] = ctrl->seg_prefix[i];
   __syncthreads();
   for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
-    const K k = sk[i];
-    for (int p = 0; p < passes; ++p) atomicAdd(&h[p * 256 + (uint32_t)((k >> (8 * p)) & 255u)], 1u);
+    const K kk = sk[seg_addr(pre, i, segcap)];
+    for (int q = 0; q < passes; ++q)
+      atomicAdd(&h[q * 256 + (uint32_t)((kk >> (8 * q)) & 255u)], 1u);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < passes * 256; i += NT)
     if (h[i]) atomicAdd(&hist[i], h[i]);
 }
 
+// One LSD pass over an 8-bit digit.  Launched cooperatively: every block is
+// resident, block b takes tiles b, b + G, b + 2G, ... in order, so the tile a
+// look-back waits on is held by a running block and has no later dependency.
+// Pass 0 reads the segmented spawn buffer (segcap > 0), later passes read a
+// contiguous array (segcap == 0).
 template <typename K>
 __global__ __launch_bounds__(NT) void k_sort_pass(const K *__restrict__ ik,
                                                   const int2 *__restrict__ iv,
                                                   K *__restrict__ okk, int2 *__restrict__ ov,
                                                   Ctrl *ctrl, const uint32_t *__restrict__ hist,
-                                                  uint64_t *status, int pass, uint32_t cap) {
-  if (ctrl->abort) return;
+                                                  uint64_t *status, int pass, uint32_t segcap) {
+  if (ctrl->abort || (ctrl->flags & F_SPAWN_CAP)) return;
   const uint32_t n = ctrl->n_spawn;
-  if (n > cap || n == 0) return;
+  if (n == 0) return;
   const uint32_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
   const int shift = 8 * pass;
   const uint32_t epoch = ctrl->epoch * 8u + (uint32_t)pass;
@@ -304,22 +463,20 @@ __global__ __launch_bounds__(NT) void k_sort_pass(const K *__restrict__ ik,
   __shared__ uint32_t wcnt[NT / 64][256];
   __shared__ uint32_t gstart[256], lstart[256], goff[256];
   __shared__ uint32_t scan4[NT / 64];
-  __shared__ uint32_t s_tile;
+  __shared__ uint32_t pre[NSEG + 1];
 
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint64_t lt = (1ull << lane) - 1ull;
+  if (threadIdx.x <= NSEG) pre[threadIdx.x] = ctrl->seg_prefix[threadIdx.x];
   {
     uint32_t tot;
     const uint32_t h = hist[pass * 256 + threadIdx.x];
     gstart[threadIdx.x] = block_excl_scan(h, scan4, &tot);
   }
-  for (;;) {
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     __syncthreads();
-    if (threadIdx.x == 0) s_tile = atomicAdd(&ctrl->tickets[pass], 1u);
     for (int i = threadIdx.x; i < (NT / 64) * 256; i += NT) (&wcnt[0][0])[i] = 0;
     __syncthreads();
-    const uint32_t t = s_tile;
-    if (t >= ntiles) break;
     const uint32_t tbase = t * SORT_TILE;
     const uint32_t wbase = tbase + (uint32_t)w * 64u * SORT_IT;
     K key[SORT_IT];
@@ -330,8 +487,9 @@ __global__ __launch_bounds__(NT) void k_sort_pass(const K *__restrict__ ik,
       const uint32_t pos = wbase + (uint32_t)k * 64u + (uint32_t)lane;
       const bool valid = pos < n;
       if (valid) {
-        key[k] = ik[pos];
-        val[k] = iv[pos];
+        const size_t a = segcap ? seg_addr(pre, pos, segcap) : (size_t)pos;
+        key[k] = ik[a];
+        val[k] = iv[a];
       }
       const uint32_t d = valid ? (uint32_t)((key[k] >> shift) & 255u) : 0u;
       uint64_t peers = __ballot(valid);
@@ -398,17 +556,39 @@ __global__ __launch_bounds__(NT) void k_sort_pass(const K *__restrict__ ik,
 }
 
 // ---- merge ----------------------------------------------------------------
+// Sum of a run of records: all of them, and those from initiator parents.
+struct RunSum {
+  int64_t aR, aI, iR, iI;
+};
+__device__ __forceinline__ void run_add(RunSum &s, int2 v) {
+  if (v.x == NON_INIT) {
+    s.aI += v.y;
+  } else if (v.y == NON_INIT) {
+    s.aR += v.x;
+  } else {
+    s.aR += v.x;
+    s.aI += v.y;
+    s.iR += v.x;
+    s.iI += v.y;
+  }
+}
+
+// Merge of the step-start list A (unique keys) with the sorted records B (runs
+// of equal keys).  Every key of A gets its post-step value A + (sum of its run);
+// a run without a key in A becomes a new entry with the sum of all its records
+// if the configuration is diagonal, else of its initiator records only
+// (Sec. IV.A).  Empty entries are dropped, the rest compacted in order.
+// Launched cooperatively; block b takes tiles b, b + G, ... (see k_sort_pass).
 template <typename K>
 __global__ __launch_bounds__(NT) void k_merge(
     const K *__restrict__ Ak, const int2 *__restrict__ Av, const K *__restrict__ Bk,
     const int2 *__restrict__ Bv, K *__restrict__ Ck, int2 *__restrict__ Cv, uint32_t capC,
-    uint32_t capB, Ctrl *ctrl, const SlotParams *__restrict__ sp,
-    const SlotState *__restrict__ ss, Partial *__restrict__ partials,
-    unsigned long long *__restrict__ spill, uint64_t *status, int SB) {
-  if (ctrl->abort) return;
+    Ctrl *ctrl, const SlotParams *__restrict__ sp, const SlotState *__restrict__ ss,
+    Partial *__restrict__ partials, unsigned long long *__restrict__ spill, uint64_t *status,
+    int SB) {
+  if (ctrl->abort || (ctrl->flags & F_SPAWN_CAP)) return;
   const uint32_t na = ctrl->n_main;
   const uint32_t nb = ctrl->n_spawn;
-  if (nb > capB) return;
   const uint32_t total = na + nb;
   const uint32_t ntiles = (total + MERGE_TILE - 1) / MERGE_TILE;
   const uint32_t epoch = ctrl->epoch;
@@ -416,17 +596,13 @@ __global__ __launch_bounds__(NT) void k_merge(
 
   __shared__ K sAk[MERGE_TILE], sBk[MERGE_TILE];
   __shared__ int2 sAv[MERGE_TILE];
-  __shared__ uint32_t s_tile, s_i0, s_i1, s_excl;
+  __shared__ uint32_t s_i0, s_i1, s_excl;
   __shared__ uint32_t scan4[NT / 64];
   __shared__ int64_t red[NT / 64][S_NSUM];
   bool int_ovf = false;
 
-  for (;;) {
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     __syncthreads();
-    if (threadIdx.x == 0) s_tile = atomicAdd(&ctrl->tickets[TICKET_MERGE], 1u);
-    __syncthreads();
-    const uint32_t t = s_tile;
-    if (t >= ntiles) break;
     const uint32_t d0 = t * MERGE_TILE;
     const uint32_t d1 = (d0 + MERGE_TILE < total) ? d0 + MERGE_TILE : total;
     if (threadIdx.x == 0) s_i0 = merge_path(Ak, na, Bk, nb, d0);
@@ -442,6 +618,15 @@ __global__ __launch_bounds__(NT) void k_merge(
     __syncthreads();
     auto bkey = [&](uint32_t j) -> K { return (j >= j0 && j < j1) ? sBk[j - j0] : Bk[j]; };
     auto akey = [&](uint32_t i) -> K { return (i >= i0 && i < i1) ? sAk[i - i0] : Ak[i]; };
+    // the run of records with key k starting at global index j
+    auto run_from = [&](uint32_t j, K k) -> RunSum {
+      RunSum s{0, 0, 0, 0};
+      while (j < nb && bkey(j) == k) {
+        run_add(s, Bv[j]);
+        ++j;
+      }
+      return s;
+    };
 
     // this thread's merged positions [dd, dd + MERGE_IT)
     const uint32_t len = nA + nB;
@@ -462,48 +647,40 @@ __global__ __launch_bounds__(NT) void k_merge(
     }
     K ck[MERGE_IT];
     int2 cv[MERGE_IT];
+    bool ok_it[MERGE_IT];
     uint32_t nsurv = 0;
-    const uint32_t s0 = slot_of<K>(d0 < na + nb ? ((i0 < na && (j0 >= nb || Ak[i0] <= Bk[j0]))
-                                                       ? Ak[i0]
-                                                       : Bk[j0])
-                                                : (K)0,
-                                   SB);
+    const uint32_t s0 = slot_of<K>((nA > 0 && (nB == 0 || sAk[0] <= sBk[0])) ? sAk[0] : sBk[0], SB);
     int64_t acc[S_NSUM];
 #pragma unroll
     for (int s = 0; s < S_NSUM; ++s) acc[s] = 0;
 
 #pragma unroll
     for (int it = 0; it < MERGE_IT; ++it) {
-      if (dd + (uint32_t)it >= len) break;
+      ok_it[it] = false;
+      if (dd + (uint32_t)it >= len) continue;
       K k;
       int64_t R = 0, I = 0;
       bool emit = false;
       if (a < nA && (b >= nB || sAk[a] <= sBk[b])) {
         k = sAk[a];
-        R = sAv[a].x;
-        I = sAv[a].y;
-        uint32_t gj = j0 + b;
-        while (gj < nb && bkey(gj) == k) {
-          const int2 v = Bv[gj];
-          R += v.x;
-          I += v.y;
-          ++gj;
-        }
+        const RunSum s = run_from(j0 + b, k);
+        R = (int64_t)sAv[a].x + s.aR;
+        I = (int64_t)sAv[a].y + s.aI;
         emit = true;
         ++a;
       } else {
         k = sBk[b];
-        uint32_t gj = j0 + b;
-        const uint32_t gi = i0 + a;
+        const uint32_t gj = j0 + b, gi = i0 + a;
         const bool head = (gj == 0) || bkey(gj - 1) != k;
         const bool matched = (gi > 0) && akey(gi - 1) == k;
         if (head && !matched) {
-          while (gj < nb && bkey(gj) == k) {
-            const int2 v = Bv[gj];
-            R += v.x;
-            I += v.y;
-            ++gj;
-          }
+          const RunSum s = run_from(gj, k);
+          const SlotParams &P = sp[slot_of<K>(k, SB)];
+          const uint64_t cfg = (uint64_t)(k & lowm);
+          const uint64_t lm = (P.N == 32) ? 0xffffffffull : ((1ull << P.N) - 1);
+          const bool diag = (cfg >> P.N) == (cfg & lm);
+          R = diag ? s.aR : s.iR;
+          I = diag ? s.aI : s.iI;
           emit = true;
         }
         ++b;
@@ -513,8 +690,9 @@ __global__ __launch_bounds__(NT) void k_merge(
       if (ss[slot].status == 3) continue;  // solve leaving the list
       if (R > 2147483647LL || R < -2147483647LL || I > 2147483647LL || I < -2147483647LL)
         int_ovf = true;
-      ck[nsurv] = k;
-      cv[nsurv] = make_int2((int)R, (int)I);
+      ck[it] = k;
+      cv[it] = make_int2((int)R, (int)I);
+      ok_it[it] = true;
       ++nsurv;
       const SlotParams &P = sp[slot];
       const uint64_t cfg = (uint64_t)(k & lowm);
@@ -550,9 +728,15 @@ __global__ __launch_bounds__(NT) void k_merge(
     }
     // stage survivors in LDS (reuse the A arrays), then write them coalesced
     __syncthreads();
-    for (uint32_t q = 0; q < nsurv; ++q) {
-      sAk[lpos + q] = ck[q];
-      sAv[lpos + q] = cv[q];
+    {
+      uint32_t q = lpos;
+#pragma unroll
+      for (int it = 0; it < MERGE_IT; ++it)
+        if (ok_it[it]) {
+          sAk[q] = ck[it];
+          sAv[q] = cv[it];
+          ++q;
+        }
     }
     __syncthreads();
     const uint32_t gbase = s_excl;
@@ -587,14 +771,14 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctrl *ctrl, const SlotParams 
                                                    SlotState *ss, const Partial *partials,
                                                    unsigned long long *spill, int nslots,
                                                    uint32_t *hist, int passes, uint32_t capC,
-                                                   uint32_t capS, int64_t *series,
-                                                   uint32_t series_cap) {
+                                                   uint32_t *segcnt, int64_t *series,
+                                                   uint32_t *counts, uint32_t series_cap) {
   if (ctrl->abort) return;
   __shared__ unsigned long long sums[MAX_SLOTS * S_NSUM];
   __shared__ uint32_t s_bad;
   const int tid = threadIdx.x, nt = blockDim.x;
   // a spawn overflow means the merge did not run: its partials are not valid
-  if ((ctrl->flags & F_SPAWN_CAP) || ctrl->n_spawn > capS) {
+  if (ctrl->flags & F_SPAWN_CAP) {
     if (tid == 0) {
       ctrl->fail_flags = ctrl->flags | F_SPAWN_CAP;
       ctrl->abort = 1;
@@ -707,11 +891,16 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctrl *ctrl, const SlotParams 
     }
   }
   for (int i = tid; i < passes * 256; i += nt) hist[i] = 0;
+  for (int i = tid; i < NSEG; i += nt) segcnt[i * SEG_STRIDE] = 0;
   if (tid == 0) {
+    if (row < series_cap) {
+      counts[3 * row + 0] = ctrl->n_main;
+      counts[3 * row + 1] = ctrl->n_spawn;
+      counts[3 * row + 2] = n_new;
+    }
     ctrl->n_main = n_new;
     ctrl->last_spawn = ctrl->n_spawn;
     ctrl->n_spawn = 0;
-    for (int p = 0; p <= MAX_PASSES; ++p) ctrl->tickets[p] = 0;
     ctrl->epoch += 1;
     ctrl->committed += 1;
     ctrl->series_pos = row + 1;
@@ -720,15 +909,15 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctrl *ctrl, const SlotParams 
 
 // After a failed step: re-arm the counters (the list is untouched).
 __global__ void k_rearm(Ctrl *ctrl, uint32_t *hist, int passes, unsigned long long *spill,
-                        int nspill) {
+                        int nspill, uint32_t *segcnt) {
   for (int i = threadIdx.x; i < passes * 256; i += blockDim.x) hist[i] = 0;
   for (int i = threadIdx.x; i < nspill; i += blockDim.x) spill[i] = 0;
+  for (int i = threadIdx.x; i < NSEG; i += blockDim.x) segcnt[i * SEG_STRIDE] = 0;
   if (threadIdx.x == 0) {
     ctrl->n_spawn = 0;
     ctrl->n_new = 0;
     ctrl->flags = 0;
     ctrl->abort = 0;
-    for (int p = 0; p <= MAX_PASSES; ++p) ctrl->tickets[p] = 0;
     ctrl->epoch += 1;
   }
 }

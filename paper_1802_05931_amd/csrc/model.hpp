@@ -132,7 +132,7 @@ DQ_HD HopClasses hop_classes(const SlotParams &P, const Geometry &g, uint32_t l,
 // weights) by a balanced binary tree of binomials; node h of the heap draws the
 // left share Bin(M, |left| / |node|).  emit(member, count) for nonzero leaves.
 template <typename F>
-DQ_HD void tree_split(int n, int64_t M, const EntryRng &rng, uint32_t draw_base, F &&emit) {
+DQ_HD void tree_split(int n, int64_t M, EntryCounter &cnt, uint32_t draw_base, F &&emit) {
   struct Node {
     int lo, hi, h;
     int64_t M;
@@ -148,8 +148,8 @@ DQ_HD void tree_split(int n, int64_t M, const EntryRng &rng, uint32_t draw_base,
       continue;
     }
     const int mid = nd.lo + (nd.hi - nd.lo) / 2;
-    Stream st = rng.at(draw_base + (uint32_t)nd.h);
-    const int64_t ML = binomial(nd.M, (double)(mid - nd.lo) / (double)(nd.hi - nd.lo), st);
+    const int64_t ML = cnt(draw_base + (uint32_t)nd.h, nd.M,
+                           (double)(mid - nd.lo) / (double)(nd.hi - nd.lo), DRAW_BIN);
     stack[sp++] = Node{mid, nd.hi, 2 * nd.h + 1, nd.M - ML};
     stack[sp++] = Node{nd.lo, mid, 2 * nd.h, ML};
   }
@@ -157,6 +157,69 @@ DQ_HD void tree_split(int n, int64_t M, const EntryRng &rng, uint32_t draw_base,
 
 DQ_HD int64_t sgn64(int64_t x) { return (x > 0) - (x < 0); }
 DQ_HD int64_t sgnd(double x) { return (x > 0.0) - (x < 0.0); }
+
+// Everything the channel counts of one entry depend on.
+struct EntryProbs {
+  bool init;
+  int64_t sR, sI;
+  double d_r, d_i;
+  Geometry g;
+  HopClasses hc;
+  double Sc[6];
+  uint32_t jm;
+  int nJ;
+  double p8[8];
+  int64_t n8[8];
+  EntryCounter cnt;
+};
+
+DQ_HD EntryProbs entry_probs(const SlotParams &P, double S, uint32_t step, uint32_t l, uint32_t m,
+                             int32_t R, int32_t I) {
+  EntryProbs e;
+  const bool diag = (l == m);
+  const int64_t nR = R < 0 ? -(int64_t)R : (int64_t)R;
+  const int64_t nI = I < 0 ? -(int64_t)I : (int64_t)I;
+  e.sR = sgn64(R);
+  e.sI = sgn64(I);
+  e.init = diag || (nR + nI > P.n_a) || (P.flags & FLAG_NO_INITIATOR);
+  e.g = geometry(P, l, m);
+  // diagonal element: Re = -(gamma/2)(n_up(l) + n_up(m)) - S, Im = -(E_l - E_m)
+  e.d_r = -(P.half_gamma * (double)(popc(l) + popc(m))) - S;
+  e.d_i = P.half_jz * (double)(e.g.al[1] - e.g.al[0]);
+  const double p_r = P.dt * __builtin_fabs(e.d_r);
+  const double p_i = P.dt * __builtin_fabs(e.d_i);
+  e.hc = hop_classes(P, e.g, l, m);
+  e.Sc[5] = e.hc.W[5];
+  for (int c = 4; c >= 0; --c) e.Sc[c] = e.hc.W[c] + e.Sc[c + 1];
+  const double P_im = P.dt * e.Sc[0];
+  e.jm = l & m;  // jump sites: up in both ket and bra
+  e.nJ = popc(e.jm);
+  const double P_re = P.dt * ((double)e.nJ * P.gamma);
+  const double pp[4] = {p_r, p_i, P_re, P_im};
+  for (int k = 0; k < 4; ++k) {
+    e.p8[k] = pp[k];
+    e.p8[k + 4] = pp[k];
+    e.n8[k] = nR;
+    e.n8[k + 4] = nI;
+  }
+  e.cnt = EntryCounter{P.seed, ((uint64_t)l << P.N) | m, P.solve, step, 0};
+  return e;
+}
+
+// True when all eight channel counts of the entry are zero (decided by the
+// primary uniform exactly as channel_counts decides it).
+DQ_HD bool entry_quiet(const SlotParams &P, double S, uint32_t step, uint32_t l, uint32_t m,
+                       int32_t R, int32_t I) {
+  const EntryProbs e = entry_probs(P, S, step, l, m, R, I);
+  double g = 1.0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (e.n8[k] > 0 && e.p8[k] >= 1.0) return false;
+    if (e.n8[k] > 0 && e.p8[k] > 0.0) g = g * ipow(1.0 - e.p8[k], e.n8[k]);
+  }
+  Stream prim(e.cnt.seed, e.cnt.solve, e.cnt.cfg, e.cnt.step, 0, nullptr);
+  return prim.next() < g;
+}
 
 // One occupied configuration |l><m| with walkers R + iI: draw its clone/death
 // and spawning counts and hand every nonzero contribution to
@@ -166,46 +229,27 @@ DQ_HD int64_t sgnd(double x) { return (x > 0.0) - (x < 0.0); }
 template <typename Emit>
 DQ_HD void entry_events(const SlotParams &P, double S, uint32_t step, uint32_t l, uint32_t m,
                         int32_t R, int32_t I, int *err, Emit &&emit) {
-  const bool diag = (l == m);
-  const int64_t nR = R < 0 ? -(int64_t)R : (int64_t)R;
-  const int64_t nI = I < 0 ? -(int64_t)I : (int64_t)I;
-  const int64_t sR = sgn64(R), sI = sgn64(I);
-  const bool init = diag || (nR + nI > P.n_a) || (P.flags & FLAG_NO_INITIATOR);
-
-  const Geometry g = geometry(P, l, m);
-  // diagonal element: Re = -(gamma/2)(n_up(l) + n_up(m)) - S, Im = -(E_l - E_m)
-  const double d_r = -(P.half_gamma * (double)(popc(l) + popc(m))) - S;
-  const double d_i = P.half_jz * (double)(g.al[1] - g.al[0]);
-  const double p_r = P.dt * __builtin_fabs(d_r);
-  const double p_i = P.dt * __builtin_fabs(d_i);
-
-  const HopClasses hc = hop_classes(P, g, l, m);
-  double Sc[6];
-  Sc[5] = hc.W[5];
-  for (int c = 4; c >= 0; --c) Sc[c] = hc.W[c] + Sc[c + 1];
-  const double P_im = P.dt * Sc[0];
-  const uint32_t jm = l & m;  // jump sites: up in both ket and bra
-  const int nJ = popc(jm);
-  const double P_re = P.dt * ((double)nJ * P.gamma);
-
-  const double p8[8] = {p_r, p_i, P_re, P_im, p_r, p_i, P_re, P_im};
-  const int64_t n8[8] = {nR, nR, nR, nR, nI, nI, nI, nI};
-  const EntryRng rng{P.seed, ((uint64_t)l << P.N) | m, P.solve, step, err};
+  EntryProbs e = entry_probs(P, S, step, l, m, R, I);
+  const bool init = e.init;
+  const int64_t sR = e.sR, sI = e.sI;
+  EntryCounter &cnt = e.cnt;
   int64_t X[8];
-  channel_counts(p8, n8, rng, X);
+  channel_counts(e.p8, e.n8, cnt, X);
 
   // clone/death: dt (R + iI)(d_r + i d_i)
-  const int64_t dR = sR * sgnd(d_r) * X[0] - sI * sgnd(d_i) * X[5];
-  const int64_t dI = sI * sgnd(d_r) * X[4] + sR * sgnd(d_i) * X[1];
+  const int64_t dR = sR * sgnd(e.d_r) * X[0] - sI * sgnd(e.d_i) * X[5];
+  const int64_t dI = sI * sgnd(e.d_r) * X[4] + sR * sgnd(e.d_i) * X[1];
   if (dR != 0 || dI != 0) emit(l, m, dR, dI, true);
 
   // spawning along the real elements: the jump gamma S^-_k rho S^+_k
+  const uint32_t jm = e.jm;
+#pragma unroll
   for (int part = 0; part < 2; ++part) {
     const int ch = part ? 7 : 3;
-    const int64_t cnt = X[ch - 1];
-    if (cnt == 0) continue;
+    const int64_t c = X[ch - 1];
+    if (c == 0) continue;
     const int64_t sg = part ? sI : sR;
-    tree_split(nJ, cnt, rng, draw_channel(ch) + 64u, [&](int j, int64_t M) {
+    tree_split(e.nJ, c, cnt, draw_channel(ch) + 64u, [&](int j, int64_t M) {
       const uint32_t bit = 1u << nth_bit(jm, j);
       if (part == 0)
         emit(l & ~bit, m & ~bit, sg * M, 0, init);
@@ -216,29 +260,31 @@ DQ_HD void entry_events(const SlotParams &P, double S, uint32_t step, uint32_t l
 
   // spawning along the imaginary elements: -iH on the ket, +iH on the bra;
   // classes by sequential conditional binomials, members by the tree
+  const HopClasses &hc = e.hc;
+#pragma unroll
   for (int part = 0; part < 2; ++part) {
     const int ch = part ? 8 : 4;
     int64_t rem = X[ch - 1];
     if (rem == 0) continue;
     const int64_t sg = part ? sI : sR;
     int last = -1;
+#pragma unroll
     for (int c = 0; c < 6; ++c)
       if (hc.W[c] > 0.0) last = c;
-    for (int c = 0; c < 6 && rem > 0; ++c) {
-      if (hc.W[c] == 0.0) continue;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      if (rem == 0 || hc.W[c] == 0.0) continue;
       int64_t Mc;
-      if (c == last) {
+      if (c == last)
         Mc = rem;
-      } else {
-        Stream st = rng.at(draw_channel(ch) + 1u + (uint32_t)c);
-        Mc = binomial(rem, hc.W[c] / Sc[c], st);
-      }
+      else
+        Mc = cnt(draw_channel(ch) + 1u + (uint32_t)c, rem, hc.W[c] / e.Sc[c], DRAW_BIN);
       rem -= Mc;
       if (Mc == 0) continue;
       const uint32_t cr = hc.r[c], cu = hc.u[c];
       const int nr = popc(cr);
       const int64_t sv = sg * (int64_t)hc.sgn[c];
-      tree_split(hc.n[c], Mc, rng, draw_channel(ch) + 64u + 64u * (uint32_t)c,
+      tree_split(hc.n[c], Mc, cnt, draw_channel(ch) + 64u + 64u * (uint32_t)c,
                  [&](int j, int64_t M) {
                    uint32_t bm;
                    if (j < nr) {
@@ -260,6 +306,7 @@ DQ_HD void entry_events(const SlotParams &P, double S, uint32_t step, uint32_t l
                  });
     }
   }
+  if (cnt.dry) *err = 1;
 }
 
 // Estimator contributions of one entry of the new list (Sec. III.A, V.A).

@@ -82,15 +82,6 @@ struct Stream {
   }
 };
 
-// Per-entry stream factory: all draws of one configuration in one step.
-struct EntryRng {
-  uint64_t seed;
-  uint64_t cfg;
-  uint32_t solve, step;
-  int *err;
-  DQ_HD Stream at(uint32_t draw) const { return Stream(seed, solve, cfg, step, draw, err); }
-};
-
 // Draw-id layout: 0 = the entry's primary uniform; channel k (1..8) owns ids
 // k*1024 + [0, 1024): +0 its count, +1+c the class split of class c,
 // +64+64c+h node h of the member tree of class c.
@@ -202,8 +193,8 @@ DQ_HD int64_t bin_inversion(int64_t n, double p, Stream &st, bool positive) {
 }
 
 // Transformed rejection with decomposition (BTRD, Hormann 1993); p <= 1/2 and
-// n p >= 10.
-DQ_HD int64_t bin_btrd(int64_t n, double p, Stream &st) {
+// n p >= 10.  Out of line: only entries with many walkers get here.
+__host__ __device__ __attribute__((noinline)) int64_t bin_btrd(int64_t n, double p, Stream &st) {
   const double nd = (double)n;
   const double q = 1.0 - p;
   const double md = __builtin_floor((nd + 1.0) * p);
@@ -304,6 +295,43 @@ DQ_HD int64_t binomial_split(int64_t n, double P, Stream &st) {
   return n * (int64_t)f + binomial(n, P - f, st);
 }
 
+// One count drawn from its own stream (draw id `draw` of the entry's counter):
+// mode 0 Bin(n, p), 1 Bin(n, p) given >= 1, 2 integer part + Bin(n, fraction).
+// Out of line, so the generators exist once in a kernel however many call
+// sites it has.  Sets bit 0 of *err if the stream ran dry.
+struct Count {
+  int64_t x;
+  int dry;
+};
+enum { DRAW_BIN = 0, DRAW_POS = 1, DRAW_SPLIT = 2 };
+
+__host__ __device__ __attribute__((noinline)) Count draw_count(uint64_t seed, uint32_t solve,
+                                                               uint64_t cfg, uint32_t step,
+                                                               uint32_t draw, int64_t n, double p,
+                                                               int mode) {
+  int e = 0;
+  Stream st(seed, solve, cfg, step, draw, &e);
+  int64_t x;
+  if (mode == DRAW_BIN)
+    x = binomial(n, p, st);
+  else if (mode == DRAW_POS)
+    x = binomial_positive(n, p, st);
+  else
+    x = binomial_split(n, p, st);
+  return Count{x, e};
+}
+
+struct EntryCounter {
+  uint64_t seed, cfg;
+  uint32_t solve, step;
+  int dry;
+  DQ_HD int64_t operator()(uint32_t draw, int64_t n, double p, int mode) {
+    const Count c = draw_count(seed, solve, cfg, step, draw, n, p, mode);
+    dry |= c.dry;
+    return c.x;
+  }
+};
+
 // The eight channel counts of one entry (real walkers: death-re, death-im,
 // spawn along Re elements, spawn along Im elements; then the same for the
 // imaginary walkers) are independent Bsplit(n_k, p_k).  When all p_k < 1 a single
@@ -311,38 +339,39 @@ DQ_HD int64_t binomial_split(int64_t n, double P, Stream &st) {
 // G_k = prod_{j<=k} (1 - p_j)^{n_j}, whether every count is zero (u < G_8) or
 // which channel is the first nonzero one; that channel is then drawn given
 // >= 1 and the later ones as usual.
-DQ_HD void channel_counts(const double p[8], const int64_t n[8], const EntryRng &rng,
+DQ_HD void channel_counts(const double p[8], const int64_t n[8], EntryCounter &cnt,
                           int64_t X[8]) {
   bool loud = false;
+#pragma unroll
   for (int k = 0; k < 8; ++k) {
     X[k] = 0;
     loud = loud || (n[k] > 0 && p[k] >= 1.0);
   }
   if (loud) {
-    for (int k = 0; k < 8; ++k) {
-      Stream st = rng.at(draw_channel(k + 1));
-      X[k] = binomial_split(n[k], p[k], st);
-    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) X[k] = cnt(draw_channel(k + 1), n[k], p[k], DRAW_SPLIT);
     return;
   }
   double G[8];
   double g = 1.0;
+#pragma unroll
   for (int k = 0; k < 8; ++k) {
     if (n[k] > 0 && p[k] > 0.0) g = g * ipow(1.0 - p[k], n[k]);
     G[k] = g;
   }
-  Stream prim = rng.at(0);
+  Stream prim(cnt.seed, cnt.solve, cnt.cfg, cnt.step, 0, nullptr);
   const double u = prim.next();
   if (u < G[7]) return;
-  int first = 0;
-  while (u < G[first]) ++first;
-  {
-    Stream st = rng.at(draw_channel(first + 1));
-    X[first] = binomial_positive(n[first], p[first], st);
-  }
-  for (int k = first + 1; k < 8; ++k) {
-    Stream st = rng.at(draw_channel(k + 1));
-    X[k] = binomial(n[k], p[k], st);
+  int first = 8;
+#pragma unroll
+  for (int k = 7; k >= 0; --k)
+    if (u >= G[k]) first = k;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (k == first)
+      X[k] = cnt(draw_channel(k + 1), n[k], p[k], DRAW_POS);
+    else if (k > first && n[k] > 0 && p[k] > 0.0)
+      X[k] = cnt(draw_channel(k + 1), n[k], p[k], DRAW_BIN);
   }
 }
 
