@@ -368,12 +368,16 @@ int orc_binom_many(int64_t n, double p, int mode, uint64_t seed, int64_t count, 
 /* Channel k (1..8) draws X_k ~ Bsplit(n_k, p_k); k = 1..4 act on the real    */
 /* walkers (death-re, death-im, spawn along Re elements, spawn along Im),     */
 /* k = 5..8 on the imaginary walkers in the same order.  When every p_k < 1,  */
-/* one uniform from the primary stream (draw 0) decides by inversion whether  */
-/* all counts are zero and, if not, which channel is the first nonzero one;   */
-/* that channel is then drawn conditioned on >= 1 and the later channels      */
-/* unconditionally.  The joint law is that of eight independent counts.       */
+/* successive uniforms of the primary stream (draw 0) locate the nonzero      */
+/* channels one after the other: starting at channel `start`, a uniform u is  */
+/* compared by inversion with the running products of the zero probabilities  */
+/* from `start` on; u below the last product means no further channel fires,  */
+/* otherwise the first product u exceeds names the next nonzero channel,      */
+/* which is drawn conditioned on >= 1; the search resumes after it.  The      */
+/* joint law is that of eight independent counts.                             */
 /* ------------------------------------------------------------------------ */
 #define DRAW_CH(k) ((uint32_t)(k) << 10)
+#define DRAW_PICK 7u /* within a channel: the single-walker categorical draw */
 
 typedef struct {
   uint64_t seed;
@@ -388,9 +392,8 @@ static void channel_stream(const ectx_t *c, stream_t *s, uint32_t draw) {
 }
 
 static void sample_channels(const ectx_t *c, const double p[8], const int64_t n[8], int64_t X[8]) {
-  int k, loud = 0, first;
-  double G[8], g = 1.0, u;
-  stream_t s;
+  int k, loud = 0, start;
+  stream_t prim, s;
   for (k = 0; k < 8; k++) {
     X[k] = 0;
     if (n[k] > 0 && p[k] >= 1.0) loud = 1;
@@ -402,20 +405,22 @@ static void sample_channels(const ectx_t *c, const double p[8], const int64_t n[
     }
     return;
   }
-  for (k = 0; k < 8; k++) {
-    if (n[k] > 0 && p[k] > 0.0) g = g * powi(1.0 - p[k], n[k]);
-    G[k] = g;
-  }
-  channel_stream(c, &s, 0);
-  u = stream_next(&s);
-  if (u < G[7]) return;
-  first = 0;
-  while (u < G[first]) first++;
-  channel_stream(c, &s, DRAW_CH(first + 1));
-  X[first] = binom_trunc(n[first], p[first], &s);
-  for (k = first + 1; k < 8; k++) {
-    channel_stream(c, &s, DRAW_CH(k + 1));
-    X[k] = binom(n[k], p[k], &s);
+  channel_stream(c, &prim, 0);
+  start = 0;
+  while (start < 8) {
+    double G[8], g = 1.0, u;
+    int first;
+    for (k = start; k < 8; k++) {
+      if (n[k] > 0 && p[k] > 0.0) g = g * powi(1.0 - p[k], n[k]);
+      G[k] = g;
+    }
+    u = stream_next(&prim);
+    if (u < G[7]) break;
+    first = start;
+    while (u < G[first]) first++;
+    channel_stream(c, &s, DRAW_CH(first + 1));
+    X[first] = binom_trunc(n[first], p[first], &s);
+    start = first + 1;
   }
 }
 
@@ -743,8 +748,18 @@ static void process_entry(orc_t *h, uint64_t key, int32_t R, int32_t I, int64_t 
     int j;
     if (Xs == 0) continue;
     for (j = 0; j < nJ; j++) cnt[j] = 0;
-    t.ec = &ec; t.draw_base = DRAW_CH(ch) + 64u; t.out = cnt;
-    tree_split(&t, 0, nJ, 1, Xs);
+    if (Xs == 1) {
+      /* one walker: a uniform member */
+      stream_t s;
+      int jj;
+      channel_stream(&ec, &s, DRAW_CH(ch) + DRAW_PICK);
+      jj = (int)floor(stream_next(&s) * (double)nJ);
+      if (jj > nJ - 1) jj = nJ - 1;
+      cnt[jj] = 1;
+    } else {
+      t.ec = &ec; t.draw_base = DRAW_CH(ch) + 64u; t.out = cnt;
+      tree_split(&t, 0, nJ, 1, Xs);
+    }
     for (j = 0; j < nJ; j++) {
       if (cnt[j] == 0) continue;
       {
@@ -764,6 +779,29 @@ static void process_entry(orc_t *h, uint64_t key, int32_t R, int32_t I, int64_t 
     int64_t sg = k ? sI : sR;
     int last = -1;
     if (rem == 0) continue;
+    if (rem == 1) {
+      /* one walker: class by inversion on the weights, then a uniform member */
+      stream_t s;
+      double u1, u2, T;
+      int jj, b;
+      uint64_t cl, cm;
+      int64_t v;
+      channel_stream(&ec, &s, DRAW_CH(ch) + DRAW_PICK);
+      u1 = stream_next(&s);
+      u2 = stream_next(&s);
+      T = Sc[0] * (1.0 - u1);
+      c = 0;
+      while (!((c < 5 ? Sc[c + 1] : 0.0) < T)) c++;
+      jj = (int)floor(u2 * (double)hc.n[c]);
+      if (jj > hc.n[c] - 1) jj = hc.n[c] - 1;
+      b = hc.mem[c][jj];
+      v = sg * (int64_t)hc.sgn[c];
+      cl = c < 3 ? (l ^ md->bmask[b]) : l;
+      cm = c < 3 ? m : (m ^ md->bmask[b]);
+      if (k == 0) emit(&em, cl, cm, 0, v);
+      else emit(&em, cl, cm, -v, 0);
+      continue;
+    }
     for (c = 0; c < 6; c++)
       if (hc.W[c] > 0.0) last = c;
     for (c = 0; c < 6 && rem > 0; c++) {

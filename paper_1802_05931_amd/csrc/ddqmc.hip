@@ -25,7 +25,7 @@ namespace {
 
 constexpr uint32_t SERIES_CAP = 1024;  // steps per chunk between host synchronisations
 constexpr uint64_t MAX_CAP = 0xF0000000ull;
-constexpr int NSTAGE = 7;  // scan, loud, seal, histogram, sort, merge, finalize
+constexpr int NSTAGE = 8;  // scan, loud, heavy, seal, histogram, sort, merge, finalize
 
 struct StageEvents {
   hipEvent_t e[NSTAGE + 1];
@@ -65,6 +65,7 @@ struct ddqmc_t {
   uint32_t *loud = nullptr;    // indices of the entries where some event happens
   uint32_t *loud_cnt = nullptr;  // loud entries per scan block
   uint32_t *loud_off = nullptr;  // their offsets (nscan + 1)
+  uint32_t *heavy = nullptr;     // loud entries that need the general sampling code
   uint32_t *segcnt = nullptr;  // record counters of the spawn segments
   uint32_t nscan = 1;          // blocks of the scan kernel (fixed per list capacity)
   uint32_t coop_sort = 1, coop_merge = 1;  // co-resident block limits
@@ -80,7 +81,7 @@ struct ddqmc_t {
 
   bool profiling = false;
   std::vector<StageEvents> ev;
-  double stage_ms[NSTAGE] = {0, 0, 0, 0, 0, 0, 0};
+  double stage_ms[NSTAGE] = {0, 0, 0, 0, 0, 0, 0, 0};
   int64_t stage_steps = 0;
 };
 
@@ -174,7 +175,7 @@ SlotState fresh_state(const ddqmc_params &p, int status) {
 void free_all(ddqmc_t *h) {
   void *ptrs[] = {h->mk[0], h->mk[1], h->mv[0], h->mv[1], h->sk[0], h->sk[1], h->sv[0],
                   h->sv[1], h->sort_status, h->merge_status, h->partials, h->hist, h->ctrl,
-                  h->dsp, h->dss, h->spill, h->series, h->counts, h->loud, h->loud_cnt, h->loud_off, h->segcnt, h->inj_k,
+                  h->dsp, h->dss, h->spill, h->series, h->counts, h->loud, h->loud_cnt, h->loud_off, h->heavy, h->segcnt, h->inj_k,
                   h->inj_v};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -193,6 +194,8 @@ int alloc_loud(ddqmc_t *h) {
   if (h->loud) HIPC(hipFree(h->loud));
   if (h->loud_cnt) HIPC(hipFree(h->loud_cnt));
   if (h->loud_off) HIPC(hipFree(h->loud_off));
+  if (h->heavy) HIPC(hipFree(h->heavy));
+  h->heavy = nullptr;
   h->loud = nullptr;
   h->loud_cnt = nullptr;
   h->loud_off = nullptr;
@@ -202,6 +205,7 @@ int alloc_loud(ddqmc_t *h) {
   HIPC(hipMalloc((void **)&h->loud, (size_t)chunk * h->nscan * sizeof(uint32_t)));
   HIPC(hipMalloc((void **)&h->loud_cnt, (size_t)h->nscan * sizeof(uint32_t)));
   HIPC(hipMalloc((void **)&h->loud_off, (size_t)(h->nscan + 1) * sizeof(uint32_t)));
+  HIPC(hipMalloc((void **)&h->heavy, (size_t)h->cap_main * sizeof(uint32_t)));
   return DDQMC_OK;
 }
 
@@ -357,6 +361,7 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev) {
   const uint32_t segcap = (uint32_t)(h->cap_sp / NSEG);
   // grids from the capacities: every kernel loops over the device-side counts
   const uint32_t g_loud = clampu(h->nscan, 1, 1024);
+  const uint32_t g_heavy = 1024;
   const uint32_t g_h = clampu((h->cap_sp + NT * 64 - 1) / (NT * 64), 1, 128);
   const uint32_t g_s = clampu(sort_tiles(h->cap_sp), 1, h->coop_sort);
   const uint32_t g_m = clampu(merge_tiles(h->cap_main, h->cap_sp), 1, h->coop_merge);
@@ -366,16 +371,19 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev) {
   if (ev) HIPC(hipEventRecord(ev->e[1], s));
   k_loud_offsets<<<1, 1024, 0, s>>>(h->ctrl, h->loud_cnt, h->loud_off, h->nscan);
   k_spawn_loud<K><<<g_loud, NT, 0, s>>>(ak, av, h->ctrl, h->dsp, h->dss, h->loud, h->loud_off,
-                                        h->nscan, (K *)h->sk[0], h->sv[0], h->segcnt, segcap,
-                                        h->SB);
+                                        h->nscan, h->heavy, (K *)h->sk[0], h->sv[0], h->segcnt,
+                                        segcap, h->SB);
   if (ev) HIPC(hipEventRecord(ev->e[2], s));
+  k_spawn_heavy<K><<<g_heavy, 64, 0, s>>>(ak, av, h->ctrl, h->dsp, h->dss, h->heavy,
+                                          (K *)h->sk[0], h->sv[0], h->segcnt, segcap, h->SB);
+  if (ev) HIPC(hipEventRecord(ev->e[3], s));
   if (h->pool)
     k_inject<K><<<1, NT, 0, s>>>((const K *)h->inj_k, h->inj_v, h->ctrl, (K *)h->sk[0], h->sv[0],
                                  h->segcnt, segcap);
   k_seal<<<1, NSEG, 0, s>>>(h->ctrl, h->segcnt, segcap);
-  if (ev) HIPC(hipEventRecord(ev->e[3], s));
-  k_hist<K><<<g_h, NT, 0, s>>>((const K *)h->sk[0], h->ctrl, h->hist, h->passes, segcap);
   if (ev) HIPC(hipEventRecord(ev->e[4], s));
+  k_hist<K><<<g_h, NT, 0, s>>>((const K *)h->sk[0], h->ctrl, h->hist, h->passes, segcap);
+  if (ev) HIPC(hipEventRecord(ev->e[5], s));
   for (int p = 0; p < h->passes; ++p) {
     const K *ik = (const K *)h->sk[p & 1];
     const int2 *iv = h->sv[p & 1];
@@ -389,7 +397,7 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev) {
     void *args[] = {&ik, &iv, &ok, &ov, &ctrl, &hist, &status, &pass, &sc};
     HIPC(hipLaunchCooperativeKernel((const void *)k_sort_pass<K>, dim3(g_s), dim3(NT), args, 0, s));
   }
-  if (ev) HIPC(hipEventRecord(ev->e[5], s));
+  if (ev) HIPC(hipEventRecord(ev->e[6], s));
   {
     const int sp = h->passes & 1;
     const K *bk = (const K *)h->sk[sp];
@@ -405,11 +413,11 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev) {
                     &spill, &status, &SB};
     HIPC(hipLaunchCooperativeKernel((const void *)k_merge<K>, dim3(g_m), dim3(NT), args, 0, s));
   }
-  if (ev) HIPC(hipEventRecord(ev->e[6], s));
+  if (ev) HIPC(hipEventRecord(ev->e[7], s));
   k_finalize<<<1, 1024, 0, s>>>(h->ctrl, h->dsp, h->dss, h->partials, h->spill, h->nslots,
                                 h->hist, h->passes, capC, h->segcnt, h->series, h->counts,
                                 SERIES_CAP);
-  if (ev) HIPC(hipEventRecord(ev->e[7], s));
+  if (ev) HIPC(hipEventRecord(ev->e[8], s));
   HIPC(hipGetLastError());
   return DDQMC_OK;
 }
@@ -974,7 +982,7 @@ int ddqmc_set_profiling(ddqmc_t *h, int32_t on) {
   return DDQMC_OK;
 }
 
-int ddqmc_stage_times(ddqmc_t *h, double ms[7], int64_t *steps) {
+int ddqmc_stage_times(ddqmc_t *h, double ms[8], int64_t *steps) {
   if (!h || !ms) return DDQMC_EINVAL;
   for (int i = 0; i < NSTAGE; ++i) ms[i] = h->stage_ms[i];
   if (steps) *steps = h->stage_steps;

@@ -67,6 +67,7 @@ struct Ctrl {
   uint32_t extinct_slot;
   uint32_t last_spawn;  // records of the last completed step
   uint32_t seg_need;    // largest segment fill of a failed step
+  uint32_t n_heavy;     // loud entries that need the general sampling path
   uint32_t seg_prefix[NSEG + 1];  // record offsets of the segments
 };
 
@@ -294,16 +295,76 @@ __global__ __launch_bounds__(1024) void k_loud_offsets(Ctrl *ctrl, const uint32_
   if (tid == 1023) loud_off[nscan] = before + inc;
 }
 
+// seg_flush for a 64-thread block.
+template <typename K>
+__device__ __forceinline__ void seg_flush64(const K *sk, const int2 *sv, uint32_t c, int seg,
+                                            uint32_t *segcnt, K *ok, int2 *ov, uint32_t segcap,
+                                            uint32_t *sbase) {
+  if (threadIdx.x == 0) *sbase = c ? atomicAdd(&segcnt[seg * SEG_STRIDE], c) : 0u;
+  __syncthreads();
+  const uint32_t b = *sbase;
+  const size_t off = (size_t)seg * segcap;
+  for (uint32_t q = threadIdx.x; q < c; q += blockDim.x)
+    if (b + q < segcap) {
+      ok[off + b + q] = sk[q];
+      ov[off + b + q] = sv[q];
+    }
+  __syncthreads();
+}
+
 // Pass 2: the loud entries, densely (flat index over all scan blocks): clone/
 // death and spawning counts and their records.  The initiator rule is applied
 // in the merge: a record from a non-initiator parent carries NON_INIT in its
+// unused (re or im) part.
+// Emitter shared by the loud kernels: record (key, contribution) into the
+// block's LDS stage, or straight into its segment when the stage is full.
+template <typename K>
+struct RecordSink {
+  K *sk;
+  int2 *sv;
+  uint32_t *scount;
+  uint32_t *segcnt;
+  K *ok;
+  int2 *ov;
+  uint32_t segcap;
+  int seg;
+  bool *int_ovf;
+  __device__ void operator()(K ck, int64_t dr, int64_t di, bool keep) const {
+    if (dr > 2147483647LL || dr < -2147483647LL || di > 2147483647LL || di < -2147483647LL)
+      *int_ovf = true;
+    int2 rv = make_int2((int)dr, (int)di);
+    if (!keep) {
+      if (dr != 0)
+        rv.y = NON_INIT;
+      else
+        rv.x = NON_INIT;
+    }
+    const uint32_t s = atomicAdd(scount, 1u);
+    if (s < (uint32_t)STAGE) {
+      sk[s] = ck;
+      sv[s] = rv;
+    } else {
+      const uint32_t g = atomicAdd(&segcnt[seg * SEG_STRIDE], 1u);
+      if (g < segcap) {
+        ok[(size_t)seg * segcap + g] = ck;
+        ov[(size_t)seg * segcap + g] = rv;
+      }
+    }
+  }
+};
+
+// Pass 2: the loud entries, densely (flat index over all scan blocks).  Entries
+// whose draws all take the inversion branch are done here; the others (large
+// populations) are queued for k_spawn_heavy.  The initiator rule is applied in
+// the merge: a record from a non-initiator parent carries NON_INIT in its
 // unused (re or im) part.
 template <typename K>
 __global__ __launch_bounds__(NT) void k_spawn_loud(
     const K *__restrict__ keys, const int2 *__restrict__ vals, Ctrl *ctrl,
     const SlotParams *__restrict__ sp, const SlotState *__restrict__ ss,
     const uint32_t *__restrict__ loud, const uint32_t *__restrict__ loud_off, uint32_t nscan,
-    K *__restrict__ ok, int2 *__restrict__ ov, uint32_t *segcnt, uint32_t segcap, int SB) {
+    uint32_t *__restrict__ heavy, K *__restrict__ ok, int2 *__restrict__ ov, uint32_t *segcnt,
+    uint32_t segcap, int SB) {
   if (ctrl->abort) return;
   __shared__ K sk[STAGE];
   __shared__ int2 sv[STAGE];
@@ -315,6 +376,7 @@ __global__ __launch_bounds__(NT) void k_spawn_loud(
   const K lowm = low_mask<K>(SB);
   int rng_err = 0;
   bool int_ovf = false;
+  const RecordSink<K> sink{sk, sv, &scount, segcnt, ok, ov, segcap, seg, &int_ovf};
   for (uint32_t base = blockIdx.x * NT; base < nl; base += gridDim.x * NT) {
     if (threadIdx.x == 0) scount = 0;
     __syncthreads();
@@ -338,37 +400,223 @@ __global__ __launch_bounds__(NT) void k_spawn_loud(
       const uint32_t N = P.N;
       const uint32_t l = (uint32_t)(cfg >> N);
       const uint32_t m = (uint32_t)(cfg & ((N == 32) ? 0xffffffffull : ((1ull << N) - 1)));
-      entry_events(P, ss[slot].S, (uint32_t)ss[slot].step, l, m, v.x, v.y, &rng_err,
-                   [&](uint32_t cl, uint32_t cm, int64_t dr, int64_t di, bool keep) {
-                     const K ck = hibits | (K)(((uint64_t)cl << N) | cm);
-                     if (dr > 2147483647LL || dr < -2147483647LL || di > 2147483647LL ||
-                         di < -2147483647LL)
-                       int_ovf = true;
-                     int2 rv = make_int2((int)dr, (int)di);
-                     if (!keep) {
-                       if (dr != 0)
-                         rv.y = NON_INIT;
-                       else
-                         rv.x = NON_INIT;
-                     }
-                     const uint32_t s = atomicAdd(&scount, 1u);
-                     if (s < (uint32_t)STAGE) {
-                       sk[s] = ck;
-                       sv[s] = rv;
-                     } else {  // staging full: straight to the segment
-                       const uint32_t g = atomicAdd(&segcnt[seg * SEG_STRIDE], 1u);
-                       if (g < segcap) {
-                         ok[(size_t)seg * segcap + g] = ck;
-                         ov[(size_t)seg * segcap + g] = rv;
-                       }
-                     }
-                   });
+      const bool done = entry_events_small(
+          P, ss[slot].S, (uint32_t)ss[slot].step, l, m, v.x, v.y, &rng_err,
+          [&](uint32_t cl, uint32_t cm, int64_t dr, int64_t di, bool keep) {
+            sink(hibits | (K)(((uint64_t)cl << N) | cm), dr, di, keep);
+          });
+      if (!done) heavy[atomicAdd(&ctrl->n_heavy, 1u)] = i;
     }
     __syncthreads();
     seg_flush(sk, sv, scount < (uint32_t)STAGE ? scount : (uint32_t)STAGE, seg, segcnt, ok, ov,
               segcap, &sbase);
   }
   if (rng_err) atomicOr(&ctrl->flags, F_RNG);
+  if (int_ovf) atomicOr(&ctrl->flags, F_INT_OVF);
+}
+
+// Pass 3: the entries with large populations, one 64-lane block (one wave) per
+// entry.  Lanes 0..7 draw the eight channel counts at once; lanes 0 and 1 split
+// the two hop channels over their classes; then the binomial trees of all
+// classes are walked level by level from an LDS frontier, one node per lane.
+// Every draw uses the stream of the same (channel, class, node) as in
+// entry_events, so the records are the same.
+constexpr int HEAVY_FRONT = 1024;  // tree nodes per frontier level
+
+template <typename K>
+__global__ __launch_bounds__(64) void k_spawn_heavy(
+    const K *__restrict__ keys, const int2 *__restrict__ vals, Ctrl *ctrl,
+    const SlotParams *__restrict__ sp, const SlotState *__restrict__ ss,
+    const uint32_t *__restrict__ heavy, K *__restrict__ ok, int2 *__restrict__ ov,
+    uint32_t *segcnt, uint32_t segcap, int SB) {
+  if (ctrl->abort) return;
+  __shared__ K sk[STAGE];
+  __shared__ int2 sv[STAGE];
+  __shared__ uint32_t scount, sbase, fcount[2];
+  __shared__ uint32_t fnode[2][HEAVY_FRONT];  // tree | lo << 5 | hi << 12 | h << 19
+  __shared__ int64_t fM[2][HEAVY_FRONT];
+  const uint32_t nh = ctrl->n_heavy;
+  const int lane = threadIdx.x;
+  const int seg = (blockIdx.x + 17) % NSEG;
+  const K lowm = low_mask<K>(SB);
+  bool int_ovf = false;
+  int dry = 0;
+  const RecordSink<K> sink{sk, sv, &scount, segcnt, ok, ov, segcap, seg, &int_ovf};
+  for (uint32_t q = blockIdx.x; q < nh; q += gridDim.x) {
+    const uint32_t i = heavy[q];
+    const K key = keys[i];
+    const int2 v = vals[i];
+    const uint32_t slot = slot_of<K>(key, SB);
+    const SlotParams &P = sp[slot];
+    const K hibits = key & ~lowm;
+    const uint64_t cfg = (uint64_t)(key & lowm);
+    const uint32_t N = P.N;
+    const uint32_t l = (uint32_t)(cfg >> N);
+    const uint32_t m = (uint32_t)(cfg & ((N == 32) ? 0xffffffffull : ((1ull << N) - 1)));
+    EntryProbs e = entry_probs(P, ss[slot].S, (uint32_t)ss[slot].step, l, m, v.x, v.y);
+    if (lane == 0) scount = 0;
+    __syncthreads();
+    auto out = [&](uint32_t cl, uint32_t cm, int64_t dr, int64_t di, bool keep) {
+      sink(hibits | (K)(((uint64_t)cl << N) | cm), dr, di, keep);
+    };
+
+    // channel counts (a short sequential search: lane 0), then broadcast
+    int64_t x[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (lane == 0) channel_counts(e.p8, e.n8, e.cnt, x);
+    int64_t X[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) X[c] = __shfl(x[c], 0, 64);
+    if (lane == 0) {
+      const int64_t dR = e.sR * sgnd(e.d_r) * X[0] - e.sI * sgnd(e.d_i) * X[5];
+      const int64_t dI = e.sI * sgnd(e.d_r) * X[4] + e.sR * sgnd(e.d_i) * X[1];
+      if (dR != 0 || dI != 0) out(l, m, dR, dI, true);
+    }
+
+    // class splits of the two hop channels (lane 0: real walkers, lane 1:
+    // imaginary); a single walker is placed at once
+    int64_t Mc[6] = {0, 0, 0, 0, 0, 0};
+    if (lane < 2) {
+      const int part = lane;
+      const int ch = part ? 8 : 4;
+      int64_t rem = part ? X[7] : X[3];
+      const int64_t sg = part ? e.sI : e.sR;
+      if (rem == 1) {
+        int c, j;
+        pick_hop(e.cnt, draw_channel(ch) + DRAW_PICK, e.Sc, e.hc.n, c, j);
+        const uint32_t bm = class_member_mask(P, pick6(e.hc.r, c), pick6(e.hc.u, c), j);
+        const uint32_t cl = c < 3 ? (l ^ bm) : l;
+        const uint32_t cm = c < 3 ? m : (m ^ bm);
+        const int64_t val = sg * (int64_t)pick6(e.hc.sgn, c);
+        out(cl, cm, part ? -val : 0, part ? 0 : val, e.init || cl == cm);
+        rem = 0;
+      }
+      int last = -1;
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+        if (e.hc.W[c] > 0.0) last = c;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        if (rem == 0 || e.hc.W[c] == 0.0) continue;
+        const int64_t mc = (c == last) ? rem
+                                       : e.cnt(draw_channel(ch) + 1u + (uint32_t)c, rem,
+                                               e.hc.W[c] / e.Sc[c], DRAW_BIN);
+        Mc[c] = mc;
+        rem -= mc;
+      }
+    }
+    // the roots: tree 0/1 = jumps of the real/imaginary walkers (nJ members),
+    // tree 2 + 6 part + c = hop class c of that part; single jump walkers placed
+    if (lane == 0) {
+      uint32_t nf = 0;
+      const int64_t rootM[2] = {X[2], X[6]};
+      for (int part = 0; part < 2; ++part) {
+        if (rootM[part] == 1) {
+          const int j = pick_member(e.cnt, draw_channel(part ? 7 : 3) + DRAW_PICK, e.nJ);
+          const uint32_t bit = 1u << nth_bit(e.jm, j);
+          const int64_t val = part ? e.sI : e.sR;
+          out(l & ~bit, m & ~bit, part ? 0 : val, part ? val : 0, e.init);
+        } else if (rootM[part] > 1) {
+          fnode[0][nf] = (uint32_t)part | (uint32_t)e.nJ << 12 | 1u << 19;
+          fM[0][nf++] = rootM[part];
+        }
+      }
+      fcount[0] = nf;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int part = 0; part < 2; ++part)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const int64_t mc = __shfl(Mc[c], part, 64);
+        if (lane == 0 && mc > 0) {
+          const uint32_t f = fcount[0]++;
+          fnode[0][f] = (uint32_t)(2 + 6 * part + c) | (uint32_t)e.hc.n[c] << 12 | 1u << 19;
+          fM[0][f] = mc;
+        }
+      }
+    __syncthreads();
+
+    // level by level
+    int cur = 0;
+    while (fcount[cur] > 0) {
+      const uint32_t nf = fcount[cur];
+      if (lane == 0) fcount[cur ^ 1] = 0;
+      __syncthreads();
+      for (uint32_t b = 0; b < nf; b += 64) {
+        const uint32_t f = b + (uint32_t)lane;
+        uint32_t child[2] = {0, 0};
+        int64_t childM[2] = {0, 0};
+        int nchild = 0;
+        if (f < nf) {
+          const uint32_t w = fnode[cur][f];
+          const int64_t M = fM[cur][f];
+          const int t = (int)(w & 31u), lo = (int)((w >> 5) & 127u),
+                    hi = (int)((w >> 12) & 127u), h = (int)(w >> 19);
+          const int part = t < 2 ? t : (t - 2) / 6;
+          const int c = t < 2 ? 0 : (t - 2) % 6;
+          const uint32_t base = t < 2 ? draw_channel(part ? 7 : 3) + 64u
+                                      : draw_channel(part ? 8 : 4) + 64u + 64u * (uint32_t)c;
+          if (hi - lo == 1) {
+            const int64_t sg = part ? e.sI : e.sR;
+            if (t < 2) {
+              const uint32_t bit = 1u << nth_bit(e.jm, lo);
+              const int64_t val = sg * M;
+              out(l & ~bit, m & ~bit, part ? 0 : val, part ? val : 0, e.init);
+            } else {
+              const uint32_t cr = pick6(e.hc.r, c), cu = pick6(e.hc.u, c);
+              const int nr = popc(cr);
+              uint32_t bm;
+              if (lo < nr) {
+                const uint32_t s = nth_bit(cr, lo);
+                bm = (1u << s) | (1u << right_site(P, s));
+              } else {
+                const uint32_t s = nth_bit(cu, lo - nr);
+                bm = (1u << s) | (1u << up_site(P, s));
+              }
+              const uint32_t cl = c < 3 ? (l ^ bm) : l;
+              const uint32_t cm = c < 3 ? m : (m ^ bm);
+              const int64_t val = sg * (int64_t)pick6(e.hc.sgn, c) * M;
+              out(cl, cm, part ? -val : 0, part ? 0 : val, e.init || cl == cm);
+            }
+          } else {
+            const int mid = lo + (hi - lo) / 2;
+            const int64_t ML = e.cnt(base + (uint32_t)h, M,
+                                     (double)(mid - lo) / (double)(hi - lo), DRAW_BIN);
+            if (ML > 0) {
+              child[nchild] = (uint32_t)t | (uint32_t)lo << 5 | (uint32_t)mid << 12 |
+                              (uint32_t)(2 * h) << 19;
+              childM[nchild++] = ML;
+            }
+            if (M - ML > 0) {
+              child[nchild] = (uint32_t)t | (uint32_t)mid << 5 | (uint32_t)hi << 12 |
+                              (uint32_t)(2 * h + 1) << 19;
+              childM[nchild++] = M - ML;
+            }
+          }
+        }
+        // append the children to the next level
+        const uint32_t inc = wave_incl_scan((uint32_t)nchild);
+        const uint32_t tot = __shfl(inc, 63, 64);
+        const uint32_t nbase = fcount[cur ^ 1];
+        const uint32_t pos = nbase + inc - (uint32_t)nchild;
+        for (int cc = 0; cc < nchild; ++cc)
+          if (pos + cc < HEAVY_FRONT) {
+            fnode[cur ^ 1][pos + cc] = child[cc];
+            fM[cur ^ 1][pos + cc] = childM[cc];
+          }
+        __syncthreads();
+        if (lane == 0) fcount[cur ^ 1] = nbase + tot;
+        __syncthreads();
+      }
+      cur ^= 1;
+      __syncthreads();
+    }
+    dry |= e.cnt.dry;
+    __syncthreads();
+    seg_flush64(sk, sv, scount < (uint32_t)STAGE ? scount : (uint32_t)STAGE, seg, segcnt, ok, ov,
+                segcap, &sbase);
+  }
+  if (dry) atomicOr(&ctrl->flags, F_RNG);
   if (int_ovf) atomicOr(&ctrl->flags, F_INT_OVF);
 }
 
@@ -901,6 +1149,7 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctrl *ctrl, const SlotParams 
     ctrl->n_main = n_new;
     ctrl->last_spawn = ctrl->n_spawn;
     ctrl->n_spawn = 0;
+    ctrl->n_heavy = 0;
     ctrl->epoch += 1;
     ctrl->committed += 1;
     ctrl->series_pos = row + 1;
@@ -915,6 +1164,7 @@ __global__ void k_rearm(Ctrl *ctrl, uint32_t *hist, int passes, unsigned long lo
   for (int i = threadIdx.x; i < NSEG; i += blockDim.x) segcnt[i * SEG_STRIDE] = 0;
   if (threadIdx.x == 0) {
     ctrl->n_spawn = 0;
+    ctrl->n_heavy = 0;
     ctrl->n_new = 0;
     ctrl->flags = 0;
     ctrl->abort = 0;

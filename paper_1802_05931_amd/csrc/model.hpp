@@ -158,6 +158,55 @@ DQ_HD void tree_split(int n, int64_t M, EntryCounter &cnt, uint32_t draw_base, F
 DQ_HD int64_t sgn64(int64_t x) { return (x > 0) - (x < 0); }
 DQ_HD int64_t sgnd(double x) { return (x > 0.0) - (x < 0.0); }
 
+// Select element c of a 6-array (keeps the arrays in registers inside loops
+// that are not unrolled).
+template <typename T>
+DQ_HD T pick6(const T *a, int c) {
+  T v = a[0];
+#pragma unroll
+  for (int i = 1; i < 6; ++i) v = (c == i) ? a[i] : v;
+  return v;
+}
+
+// One spawned walker among n equal members: a uniform member from the pick
+// stream of the channel.
+DQ_HD int pick_member(const EntryCounter &c, uint32_t draw, int n) {
+  Stream st(c.seed, c.solve, c.cfg, c.step, draw, nullptr);
+  int j = (int)__builtin_floor(st.next() * (double)n);
+  return j > n - 1 ? n - 1 : j;
+}
+
+// One spawned walker among the hop classes: class c with probability W_c / S_0
+// (inversion: the smallest c with S_{c+1} < S_0 (1 - u1)), then a uniform
+// member j of it from u2.
+DQ_HD void pick_hop(const EntryCounter &cn, uint32_t draw, const double *Sc, const int *ncls,
+                    int &c, int &j) {
+  Stream st(cn.seed, cn.solve, cn.cfg, cn.step, draw, nullptr);
+  const double u1 = st.next();
+  const double u2 = st.next();
+  const double T = Sc[0] * (1.0 - u1);
+  c = 5;
+#pragma unroll
+  for (int k = 4; k >= 0; --k)
+    if (Sc[k + 1] < T) c = k;
+  int n = ncls[0];
+#pragma unroll
+  for (int k = 1; k < 6; ++k) n = c == k ? ncls[k] : n;
+  j = (int)__builtin_floor(u2 * (double)n);
+  j = j > n - 1 ? n - 1 : j;
+}
+
+// Bond mask of member j of hop class c (right bonds of the class first).
+DQ_HD uint32_t class_member_mask(const SlotParams &P, uint32_t cr, uint32_t cu, int j) {
+  const int nr = popc(cr);
+  if (j < nr) {
+    const uint32_t s = nth_bit(cr, j);
+    return (1u << s) | (1u << right_site(P, s));
+  }
+  const uint32_t s = nth_bit(cu, j - nr);
+  return (1u << s) | (1u << up_site(P, s));
+}
+
 // Everything the channel counts of one entry depend on.
 struct EntryProbs {
   bool init;
@@ -249,13 +298,17 @@ DQ_HD void entry_events(const SlotParams &P, double S, uint32_t step, uint32_t l
     const int64_t c = X[ch - 1];
     if (c == 0) continue;
     const int64_t sg = part ? sI : sR;
-    tree_split(e.nJ, c, cnt, draw_channel(ch) + 64u, [&](int j, int64_t M) {
+    auto leaf = [&](int j, int64_t M) {
       const uint32_t bit = 1u << nth_bit(jm, j);
       if (part == 0)
         emit(l & ~bit, m & ~bit, sg * M, 0, init);
       else
         emit(l & ~bit, m & ~bit, 0, sg * M, init);
-    });
+    };
+    if (c == 1)
+      leaf(pick_member(cnt, draw_channel(ch) + DRAW_PICK, e.nJ), 1);
+    else
+      tree_split(e.nJ, c, cnt, draw_channel(ch) + 64u, leaf);
   }
 
   // spawning along the imaginary elements: -iH on the ket, +iH on the bra;
@@ -267,6 +320,19 @@ DQ_HD void entry_events(const SlotParams &P, double S, uint32_t step, uint32_t l
     int64_t rem = X[ch - 1];
     if (rem == 0) continue;
     const int64_t sg = part ? sI : sR;
+    if (rem == 1) {  // one walker: class by inversion on the weights, then a member
+      int c, j;
+      pick_hop(cnt, draw_channel(ch) + DRAW_PICK, e.Sc, hc.n, c, j);
+      const uint32_t bm = class_member_mask(P, pick6(hc.r, c), pick6(hc.u, c), j);
+      const uint32_t cl = c < 3 ? (l ^ bm) : l;
+      const uint32_t cm = c < 3 ? m : (m ^ bm);
+      const int64_t v = sg * (int64_t)pick6(hc.sgn, c);
+      if (part == 0)
+        emit(cl, cm, 0, v, init || cl == cm);
+      else
+        emit(cl, cm, -v, 0, init || cl == cm);
+      continue;
+    }
     int last = -1;
 #pragma unroll
     for (int c = 0; c < 6; ++c)
@@ -307,6 +373,187 @@ DQ_HD void entry_events(const SlotParams &P, double S, uint32_t step, uint32_t l
     }
   }
   if (cnt.dry) *err = 1;
+}
+
+// Tree split for small counts (M < 32, n <= 64): the same draws and leaves as
+// tree_split, with each pending node packed into one word
+// (lo | hi << 7 | h << 14 | M << 21) and inversion-only draws.
+template <typename F>
+DQ_HD void tree_split_small(int n, int64_t M, const EntryCounter &c, uint32_t draw_base,
+                            int &dry, F &&emit) {
+  uint32_t st0 = 0, st1 = 0, st2 = 0, st3 = 0, st4 = 0, st5 = 0, st6 = 0, st7 = 0;
+  int sp = 0;
+  auto push = [&](uint32_t w) {
+    st7 = sp == 7 ? w : st7;
+    st6 = sp == 6 ? w : st6;
+    st5 = sp == 5 ? w : st5;
+    st4 = sp == 4 ? w : st4;
+    st3 = sp == 3 ? w : st3;
+    st2 = sp == 2 ? w : st2;
+    st1 = sp == 1 ? w : st1;
+    st0 = sp == 0 ? w : st0;
+    ++sp;
+  };
+  auto pop = [&]() -> uint32_t {
+    --sp;
+    uint32_t w = st0;
+    w = sp == 1 ? st1 : w;
+    w = sp == 2 ? st2 : w;
+    w = sp == 3 ? st3 : w;
+    w = sp == 4 ? st4 : w;
+    w = sp == 5 ? st5 : w;
+    w = sp == 6 ? st6 : w;
+    w = sp == 7 ? st7 : w;
+    return w;
+  };
+  push((uint32_t)n << 7 | 1u << 14 | (uint32_t)M << 21);
+#pragma unroll 1
+  while (sp > 0) {
+    const uint32_t w = pop();
+    const int lo = (int)(w & 127u), hi = (int)((w >> 7) & 127u), h = (int)((w >> 14) & 127u);
+    const int64_t Mn = (int64_t)(w >> 21);
+    if (Mn == 0) continue;
+    if (hi - lo == 1) {
+      emit(lo, Mn);
+      continue;
+    }
+    const int mid = lo + (hi - lo) / 2;
+    const int64_t ML = binomial_small(c.seed, c.solve, c.cfg, c.step, draw_base + (uint32_t)h, Mn,
+                                      (double)(mid - lo) / (double)(hi - lo), false, dry);
+    push((uint32_t)mid | (uint32_t)hi << 7 | (uint32_t)(2 * h + 1) << 14 |
+         (uint32_t)(Mn - ML) << 21);
+    push((uint32_t)lo | (uint32_t)mid << 7 | (uint32_t)(2 * h) << 14 | (uint32_t)ML << 21);
+  }
+}
+
+// entry_events for entries whose every draw uses inversion; returns false
+// (having emitted nothing) when the entry needs the general path.  The draws,
+// and so the contributions, are identical to entry_events'.
+template <typename Emit>
+DQ_HD bool entry_events_small(const SlotParams &P, double S, uint32_t step, uint32_t l,
+                              uint32_t m, int32_t R, int32_t I, int *err, Emit &&emit) {
+  const EntryProbs e = entry_probs(P, S, step, l, m, R, I);
+  const double pk[4] = {e.p8[0], e.p8[1], e.p8[2], e.p8[3]};
+  const int64_t nR = e.n8[0], nI = e.n8[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (!small_draw(nR, pk[k]) || !small_draw(nI, pk[k])) return false;
+  // successive primary uniforms locate the channels with events
+  Stream prim(e.cnt.seed, e.cnt.solve, e.cnt.cfg, e.cnt.step, 0, nullptr);
+  int64_t X0 = 0, X1 = 0, X2 = 0, X3 = 0, X4 = 0, X5 = 0, X6 = 0, X7 = 0;
+  int dry = 0;
+  int start = 0;
+#pragma unroll 1
+  while (start < 8) {
+    double G[8];
+    double g = 1.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int64_t nk = k < 4 ? nR : nI;
+      if (k >= start && nk > 0 && pk[k & 3] > 0.0) g = g * ipow(1.0 - pk[k & 3], nk);
+      G[k] = g;
+    }
+    const double u = prim.next();
+    if (u < G[7]) break;
+    int first = 8;
+#pragma unroll
+    for (int k = 7; k >= 0; --k)
+      if (k >= start && u >= G[k]) first = k;
+    const int64_t nk = first < 4 ? nR : nI;
+    double p = pk[0];
+    p = (first & 3) == 1 ? pk[1] : p;
+    p = (first & 3) == 2 ? pk[2] : p;
+    p = (first & 3) == 3 ? pk[3] : p;
+    const int64_t x = binomial_small(e.cnt.seed, e.cnt.solve, e.cnt.cfg, e.cnt.step,
+                                     draw_channel(first + 1), nk, p, true, dry);
+    X0 = first == 0 ? x : X0;
+    X1 = first == 1 ? x : X1;
+    X2 = first == 2 ? x : X2;
+    X3 = first == 3 ? x : X3;
+    X4 = first == 4 ? x : X4;
+    X5 = first == 5 ? x : X5;
+    X6 = first == 6 ? x : X6;
+    X7 = first == 7 ? x : X7;
+    start = first + 1;
+  }
+  // larger spawn counts can need the rejection sampler in their splits
+  if (X2 >= 20 || X3 >= 20 || X6 >= 20 || X7 >= 20) return false;
+  if (dry) *err = 1;
+
+  const int64_t sR = e.sR, sI = e.sI;
+  const int64_t dR = sR * sgnd(e.d_r) * X0 - sI * sgnd(e.d_i) * X5;
+  const int64_t dI = sI * sgnd(e.d_r) * X4 + sR * sgnd(e.d_i) * X1;
+  if (dR != 0 || dI != 0) emit(l, m, dR, dI, true);
+  const bool init = e.init;
+
+  // jumps, then hops; part 0 = real walkers, part 1 = imaginary walkers
+#pragma unroll 1
+  for (int part = 0; part < 2; ++part) {
+    const int64_t cj = part ? X6 : X2;
+    const int64_t sg = part ? sI : sR;
+    if (cj > 0) {
+      const uint32_t jm = e.jm;
+      auto leaf = [&](int j, int64_t M) {
+        const uint32_t bit = 1u << nth_bit(jm, j);
+        const int64_t v = sg * M;
+        emit(l & ~bit, m & ~bit, part ? 0 : v, part ? v : 0, init);
+      };
+      if (cj == 1)
+        leaf(pick_member(e.cnt, draw_channel(part ? 7 : 3) + DRAW_PICK, e.nJ), 1);
+      else
+        tree_split_small(e.nJ, cj, e.cnt, draw_channel(part ? 7 : 3) + 64u, dry, leaf);
+    }
+    int64_t rem = part ? X7 : X3;
+    if (rem == 0) continue;
+    const int ch = part ? 8 : 4;
+    if (rem == 1) {  // one walker: class by inversion on the weights, then a member
+      int c, j;
+      pick_hop(e.cnt, draw_channel(ch) + DRAW_PICK, e.Sc, e.hc.n, c, j);
+      const uint32_t bm = class_member_mask(P, pick6(e.hc.r, c), pick6(e.hc.u, c), j);
+      const uint32_t cl = c < 3 ? (l ^ bm) : l;
+      const uint32_t cm = c < 3 ? m : (m ^ bm);
+      const int64_t v = sg * (int64_t)pick6(e.hc.sgn, c);
+      emit(cl, cm, part ? -v : 0, part ? 0 : v, init || cl == cm);
+      continue;
+    }
+    int last = -1;
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+      if (e.hc.W[c] > 0.0) last = c;
+#pragma unroll 1
+    for (int c = 0; c < 6; ++c) {
+      const double Wc = pick6(e.hc.W, c);
+      if (rem == 0 || Wc == 0.0) continue;
+      int64_t Mc = rem;
+      if (c != last)
+        Mc = binomial_small(e.cnt.seed, e.cnt.solve, e.cnt.cfg, e.cnt.step,
+                            draw_channel(ch) + 1u + (uint32_t)c, rem, Wc / pick6(e.Sc, c), false,
+                            dry);
+      rem -= Mc;
+      if (Mc == 0) continue;
+      const uint32_t cr = pick6(e.hc.r, c), cu = pick6(e.hc.u, c);
+      const int nr = popc(cr);
+      const int64_t sv = sg * (int64_t)pick6(e.hc.sgn, c);
+      tree_split_small(pick6(e.hc.n, c), Mc, e.cnt,
+                       draw_channel(ch) + 64u + 64u * (uint32_t)c, dry, [&](int j, int64_t M) {
+                         uint32_t bm;
+                         if (j < nr) {
+                           const uint32_t s = nth_bit(cr, j);
+                           bm = (1u << s) | (1u << right_site(P, s));
+                         } else {
+                           const uint32_t s = nth_bit(cu, j - nr);
+                           bm = (1u << s) | (1u << up_site(P, s));
+                         }
+                         const uint32_t cl = c < 3 ? (l ^ bm) : l;
+                         const uint32_t cm = c < 3 ? m : (m ^ bm);
+                         const int64_t v = sv * M;
+                         // Re parent x Im element -> Im child; Im parent -> -Re child
+                         emit(cl, cm, part ? -v : 0, part ? 0 : v, init || cl == cm);
+                       });
+    }
+  }
+  if (dry) *err = 1;
+  return true;
 }
 
 // Estimator contributions of one entry of the new list (Sec. III.A, V.A).

@@ -295,6 +295,46 @@ DQ_HD int64_t binomial_split(int64_t n, double P, Stream &st) {
   return n * (int64_t)f + binomial(n, P - f, st);
 }
 
+// The same law as binomial() / binomial_positive() for draws where those use
+// inversion only: (double)n * min(p, 1 - p) < 10 and p < 1.  Inlined: the
+// callers keep one copy of it per loop.
+DQ_HD int64_t binomial_small(uint64_t seed, uint32_t solve, uint64_t cfg, uint32_t step,
+                             uint32_t draw, int64_t n, double p, bool positive, int &dry) {
+  int e = 0;
+  Stream st(seed, solve, cfg, step, draw, &e);
+  int64_t x;
+  if (p > 0.5) {
+    if (!positive) {
+      x = n - bin_inversion(n, 1.0 - p, st, false);
+    } else {
+      for (;;) {
+        const int64_t y = bin_inversion(n, 1.0 - p, st, false);
+        if (y < n) {
+          x = n - y;
+          break;
+        }
+        if (st.dry()) {
+          x = 1;
+          break;
+        }
+      }
+    }
+  } else {
+    x = bin_inversion(n, p, st, positive);
+  }
+  dry |= e;
+  return x;
+}
+
+// True if binomial(n, p) (or its positive variant) takes the inversion branch
+// for every p in the argument's reflection, i.e. binomial_small applies.
+DQ_HD bool small_draw(int64_t n, double p) {
+  if (n <= 0 || p <= 0.0) return true;
+  if (p >= 1.0) return false;
+  const double q = p > 0.5 ? 1.0 - p : p;
+  return (double)n * q < 10.0;
+}
+
 // One count drawn from its own stream (draw id `draw` of the entry's counter):
 // mode 0 Bin(n, p), 1 Bin(n, p) given >= 1, 2 integer part + Bin(n, fraction).
 // Out of line, so the generators exist once in a kernel however many call
@@ -332,13 +372,17 @@ struct EntryCounter {
   }
 };
 
+// Draw id, within a channel, of the single-walker categorical pick.
+constexpr uint32_t DRAW_PICK = 7u;
+
 // The eight channel counts of one entry (real walkers: death-re, death-im,
 // spawn along Re elements, spawn along Im elements; then the same for the
-// imaginary walkers) are independent Bsplit(n_k, p_k).  When all p_k < 1 a single
-// primary uniform u decides, by inversion against the running products
-// G_k = prod_{j<=k} (1 - p_j)^{n_j}, whether every count is zero (u < G_8) or
-// which channel is the first nonzero one; that channel is then drawn given
-// >= 1 and the later ones as usual.
+// imaginary walkers) are independent Bsplit(n_k, p_k).  When all p_k < 1,
+// successive uniforms of the primary stream (draw 0) locate the nonzero
+// channels one after the other: from channel `start` on, u is inverted against
+// the running products of the zero probabilities; below the last product no
+// further channel fires, otherwise the first product u exceeds names the next
+// nonzero channel, drawn given >= 1, and the search resumes after it.
 DQ_HD void channel_counts(const double p[8], const int64_t n[8], EntryCounter &cnt,
                           int64_t X[8]) {
   bool loud = false;
@@ -352,26 +396,26 @@ DQ_HD void channel_counts(const double p[8], const int64_t n[8], EntryCounter &c
     for (int k = 0; k < 8; ++k) X[k] = cnt(draw_channel(k + 1), n[k], p[k], DRAW_SPLIT);
     return;
   }
-  double G[8];
-  double g = 1.0;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    if (n[k] > 0 && p[k] > 0.0) g = g * ipow(1.0 - p[k], n[k]);
-    G[k] = g;
-  }
   Stream prim(cnt.seed, cnt.solve, cnt.cfg, cnt.step, 0, nullptr);
-  const double u = prim.next();
-  if (u < G[7]) return;
-  int first = 8;
+  int start = 0;
+  while (start < 8) {
+    double G[8];
+    double g = 1.0;
 #pragma unroll
-  for (int k = 7; k >= 0; --k)
-    if (u >= G[k]) first = k;
+    for (int k = 0; k < 8; ++k) {
+      if (k >= start && n[k] > 0 && p[k] > 0.0) g = g * ipow(1.0 - p[k], n[k]);
+      G[k] = g;
+    }
+    const double u = prim.next();
+    if (u < G[7]) break;
+    int first = 8;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    if (k == first)
-      X[k] = cnt(draw_channel(k + 1), n[k], p[k], DRAW_POS);
-    else if (k > first && n[k] > 0 && p[k] > 0.0)
-      X[k] = cnt(draw_channel(k + 1), n[k], p[k], DRAW_BIN);
+    for (int k = 7; k >= 0; --k)
+      if (k >= start && u >= G[k]) first = k;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k == first) X[k] = cnt(draw_channel(k + 1), n[k], p[k], DRAW_POS);
+    start = first + 1;
   }
 }
 

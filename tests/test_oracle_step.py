@@ -50,7 +50,9 @@ def _z_check(samples, expected, zmax=5.5):
         sd = part(samples).std(axis=0, ddof=1)
         diff = part(mean) - part(expected)
         fixed = sd == 0
-        assert np.all(np.abs(diff[fixed]) < 1e-9), "deterministic element off"
+        # no event seen in M samples: the expected change must be small enough
+        # for that to be likely (events move at least one walker)
+        assert np.all(np.abs(diff[fixed]) < 12.0 / M), "element without events off"
         z = diff[~fixed] / (sd[~fixed] / np.sqrt(M))
         assert np.abs(z).max() < zmax, np.abs(z).max()
         chi = np.mean(z ** 2)
