@@ -14,6 +14,10 @@ bytes per launch / its mean duration from HIP events on the handle's stream),
 and the CPU oracle timed on a bounded sample of the same workload.
 
 Usage: python bench.py [--steps K] [--warmup W] [--workload d3|d3l] [--no-cpu]
+       python bench.py --trace-summary DIR --steps K
+The second form reads the kernel trace rocprofv3 wrote into DIR for a run of the
+first form and prints, per kernel, the mean dispatch duration over the last K
+steps (the timed region) as a markdown table.
 """
 import argparse
 import hashlib
@@ -86,15 +90,58 @@ def cpu_baseline(cfg, keys, re, im, sc, budget_s=15.0):
                        f"{sc['step']} ({len(keys)} entries), {dt:.1f} s on one host core")
 
 
+def trace_summary(directory, steps):
+    """Per-kernel dispatch statistics of the last `steps` steps of a rocprofv3
+    kernel trace (one k_finalize dispatch ends every step)."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(directory, "**", "*kernel_trace.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no *kernel_trace.csv under {directory}")
+    rows = []
+    for fn in files:
+        with open(fn) as f:
+            for r in csv.DictReader(f):
+                name = r["Kernel_Name"]
+                short = name.split("(")[0].replace("void ", "").replace("ddqmc::", "")
+                rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short))
+    rows.sort()
+    fin = [i for i, r in enumerate(rows) if r[2].startswith("k_finalize")]
+    if len(fin) < steps + 1:
+        raise SystemExit(f"trace holds {len(fin)} steps, fewer than {steps} + 1")
+    lo, hi = fin[-steps - 1] + 1, fin[-1] + 1
+    stats = {}
+    for t0, t1, name in rows[lo:hi]:
+        d = stats.setdefault(name, [0, 0.0, float("inf"), 0.0])
+        dur = (t1 - t0) / 1e3
+        d[0] += 1
+        d[1] += dur
+        d[2] = min(d[2], dur)
+        d[3] = max(d[3], dur)
+    span = (rows[hi - 1][1] - rows[lo][0]) / 1e6
+    out = [f"timed region: the last {steps} steps, {hi - lo} dispatches, "
+           f"{span:.1f} ms from the first dispatch start to the last dispatch end", "",
+           "| kernel | calls | calls/step | mean us | min us | max us | us/step |",
+           "|---|---:|---:|---:|---:|---:|---:|"]
+    for name, (n, tot, mn, mx) in sorted(stats.items(), key=lambda kv: -kv[1][1]):
+        out.append(f"| {name} | {n} | {n / steps:g} | {tot / n:.2f} | {mn:.2f} | {mx:.2f} | "
+                   f"{tot / steps:.2f} |")
+    print("\n".join(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3000)
-    ap.add_argument("--warmup", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=15000)
     ap.add_argument("--workload", default="d3", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--trace-summary", metavar="DIR")
     args = ap.parse_args()
+    if args.trace_summary:
+        trace_summary(args.trace_summary, args.steps)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the "
               "multi-GPU sharding of the step is a design, not an implementation.",
@@ -136,12 +183,15 @@ def main():
         "scan": float((n_in * rec).sum()),
         "histogram": float((n_sp * KEY_BYTES[k64]).sum()),
         "sort": float((2 * passes * n_sp * rec).sum()),
+        # survivors per tile: the list's keys and the records
+        "count": float((n_in * KEY_BYTES[k64] + n_sp * rec).sum()),
+        # the list and the records in, the new list out
         "merge": float(((n_in + n_sp + n_out) * rec).sum()),
     }
     launches = {"scan": args.steps, "histogram": args.steps, "sort": args.steps * passes,
-                "merge": args.steps}
+                "count": args.steps, "merge": args.steps}
     kernel_names = {"scan": "k_spawn_scan", "histogram": "k_hist", "sort": "k_sort_pass",
-                    "merge": "k_merge"}
+                    "count": "k_merge<count>", "merge": "k_merge<write>"}
     dominant = max(alg_bytes, key=lambda k: stage_ms[k])
     dur_s = stage_ms[dominant] / 1e3 / launches[dominant]
     per_launch = alg_bytes[dominant] / launches[dominant]

@@ -172,10 +172,12 @@ int ddqmc_workspace_query(const ddqmc_params *p, int64_t capacity, size_t *bytes
 
 /* Wall time of the kernels of the last ddqmc_step call, per stage, from HIP
  * events on the handle's stream when profiling is on (ddqmc_set_profiling);
- * ms[8] = quiet scan, loud spawn, heavy spawn, record seal, histogram, sort,
- * merge, finalize, summed over the call's steps. */
+ * ms[9] = quiet scan, loud spawn, heavy spawn, record seal, histogram, sort
+ * (the radix passes and the merge-path partition), merge count (survivors per
+ * tile and their offsets), merge (the merge kernel that writes the new list),
+ * finalize, summed over the call's steps. */
 int ddqmc_set_profiling(ddqmc_t *h, int32_t on);
-int ddqmc_stage_times(ddqmc_t *h, double ms[8], int64_t *steps);
+int ddqmc_stage_times(ddqmc_t *h, double ms[9], int64_t *steps);
 
 /* ---- device self-checks of the sampling primitives --------------------------
  * Same streams as the step (Philox4x32-10, key (seed_lo, seed_hi ^ solve),

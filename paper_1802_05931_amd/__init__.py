@@ -13,7 +13,7 @@ import numpy as np
 from ._lib import (DDQMCError, NO_INITIATOR, NSUM, Obs, Params, SERIES_W, SUM_NAMES, check, lib,
                    make_params, ptr)
 
-STAGES = ("scan", "loud", "heavy", "seal", "histogram", "sort", "merge", "finalize")
+STAGES = ("scan", "loud", "heavy", "seal", "histogram", "sort", "count", "merge", "finalize")
 
 __all__ = ["Solve", "Batch", "Pool", "make_params", "DDQMCError", "NO_INITIATOR", "SUM_NAMES",
            "dev_uniforms", "dev_binom", "dev_math", "workspace_query"]
@@ -113,7 +113,7 @@ class _Handle:
         check(lib().ddqmc_set_profiling(self._h, 1 if on else 0), "set_profiling")
 
     def stage_times(self):
-        ms = (ctypes.c_double * 8)()
+        ms = (ctypes.c_double * len(STAGES))()
         steps = ctypes.c_int64()
         check(lib().ddqmc_stage_times(self._h, ms, ctypes.byref(steps)), "stage_times")
         return dict(zip(STAGES, list(ms))), steps.value

@@ -25,7 +25,7 @@ namespace {
 
 constexpr uint32_t SERIES_CAP = 1024;  // steps per chunk between host synchronisations
 constexpr uint64_t MAX_CAP = 0xF0000000ull;
-constexpr int NSTAGE = 8;  // scan, loud, heavy, seal, histogram, sort, merge, finalize
+constexpr int NSTAGE = 9;  // scan, loud, heavy, seal, histogram, sort, count, merge, finalize
 
 struct StageEvents {
   hipEvent_t e[NSTAGE + 1];
@@ -53,7 +53,7 @@ struct ddqmc_t {
   void *sk[2] = {nullptr, nullptr};
   int2 *sv[2] = {nullptr, nullptr};
   uint64_t *sort_status = nullptr;
-  uint64_t *merge_status = nullptr;
+  uint32_t *tile_cnt = nullptr;  // merge: survivors per tile, then offsets
   Partial *partials = nullptr;
   uint32_t *hist = nullptr;
   Ctrl *ctrl = nullptr;
@@ -66,9 +66,13 @@ struct ddqmc_t {
   uint32_t *loud_cnt = nullptr;  // loud entries per scan block
   uint32_t *loud_off = nullptr;  // their offsets (nscan + 1)
   uint32_t *heavy = nullptr;     // loud entries that need the general sampling code
+  uint32_t *lidx = nullptr;      // flat loud list: entry index, key, value
+  void *lkey = nullptr;
+  int2 *lval = nullptr;
+  uint32_t *part = nullptr;      // merge tile boundaries
   uint32_t *segcnt = nullptr;  // record counters of the spawn segments
   uint32_t nscan = 1;          // blocks of the scan kernel (fixed per list capacity)
-  uint32_t coop_sort = 1, coop_merge = 1;  // co-resident block limits
+  uint32_t coop_sort = 1;  // co-resident block limit of the sort
   void *inj_k = nullptr;
   int2 *inj_v = nullptr;
   uint32_t n_inject_host = 0;
@@ -81,7 +85,7 @@ struct ddqmc_t {
 
   bool profiling = false;
   std::vector<StageEvents> ev;
-  double stage_ms[NSTAGE] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double stage_ms[NSTAGE] = {};
   int64_t stage_steps = 0;
 };
 
@@ -110,7 +114,7 @@ size_t spawn_bytes(size_t ks, uint64_t cap) {
   return 2 * cap * (ks + sizeof(int2)) + sort_tiles(cap) * 256 * sizeof(uint64_t);
 }
 size_t merge_bytes(uint64_t cm, uint64_t cs) {
-  return merge_tiles(cm, cs) * (sizeof(uint64_t) + sizeof(Partial));
+  return merge_tiles(cm, cs) * (2 * sizeof(uint32_t) + sizeof(Partial)) + 2 * sizeof(uint32_t);
 }
 
 int validate(const ddqmc_params *p) {
@@ -174,8 +178,9 @@ SlotState fresh_state(const ddqmc_params &p, int status) {
 
 void free_all(ddqmc_t *h) {
   void *ptrs[] = {h->mk[0], h->mk[1], h->mv[0], h->mv[1], h->sk[0], h->sk[1], h->sv[0],
-                  h->sv[1], h->sort_status, h->merge_status, h->partials, h->hist, h->ctrl,
-                  h->dsp, h->dss, h->spill, h->series, h->counts, h->loud, h->loud_cnt, h->loud_off, h->heavy, h->segcnt, h->inj_k,
+                  h->sv[1], h->sort_status, h->tile_cnt, h->partials, h->hist, h->ctrl,
+                  h->dsp, h->dss, h->spill, h->series, h->counts, h->loud, h->loud_cnt, h->loud_off, h->heavy, h->lidx, h->lkey, h->lval,
+                  h->part, h->segcnt, h->inj_k,
                   h->inj_v};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -195,7 +200,13 @@ int alloc_loud(ddqmc_t *h) {
   if (h->loud_cnt) HIPC(hipFree(h->loud_cnt));
   if (h->loud_off) HIPC(hipFree(h->loud_off));
   if (h->heavy) HIPC(hipFree(h->heavy));
+  if (h->lidx) HIPC(hipFree(h->lidx));
+  if (h->lkey) HIPC(hipFree(h->lkey));
+  if (h->lval) HIPC(hipFree(h->lval));
   h->heavy = nullptr;
+  h->lidx = nullptr;
+  h->lkey = nullptr;
+  h->lval = nullptr;
   h->loud = nullptr;
   h->loud_cnt = nullptr;
   h->loud_off = nullptr;
@@ -206,6 +217,9 @@ int alloc_loud(ddqmc_t *h) {
   HIPC(hipMalloc((void **)&h->loud_cnt, (size_t)h->nscan * sizeof(uint32_t)));
   HIPC(hipMalloc((void **)&h->loud_off, (size_t)(h->nscan + 1) * sizeof(uint32_t)));
   HIPC(hipMalloc((void **)&h->heavy, (size_t)h->cap_main * sizeof(uint32_t)));
+  HIPC(hipMalloc((void **)&h->lidx, (size_t)h->cap_main * sizeof(uint32_t)));
+  HIPC(hipMalloc(&h->lkey, (size_t)h->cap_main * key_size(h)));
+  HIPC(hipMalloc((void **)&h->lval, (size_t)h->cap_main * sizeof(int2)));
   return DDQMC_OK;
 }
 
@@ -235,9 +249,9 @@ int alloc_spawn(ddqmc_t *h, uint64_t cap) {
 
 int alloc_merge(ddqmc_t *h) {
   const uint64_t t = merge_tiles(h->cap_main, h->cap_sp);
-  HIPC(hipMalloc((void **)&h->merge_status, t * sizeof(uint64_t)));
-  HIPC(hipMemsetAsync(h->merge_status, 0, t * sizeof(uint64_t), h->stream));
+  HIPC(hipMalloc((void **)&h->tile_cnt, (t + 1) * sizeof(uint32_t)));
   HIPC(hipMalloc((void **)&h->partials, t * sizeof(Partial)));
+  HIPC(hipMalloc((void **)&h->part, (t + 1) * sizeof(uint32_t)));
   return DDQMC_OK;
 }
 
@@ -269,22 +283,16 @@ int build(ddqmc_t *h, int nslots, int Nmax, uint64_t cap, void *stream) {
   HIPC(hipMalloc((void **)&h->segcnt, NSEG * SEG_STRIDE * sizeof(uint32_t)));
   HIPC(hipMemsetAsync(h->segcnt, 0, NSEG * SEG_STRIDE * sizeof(uint32_t), h->stream));
   {
-    int cus = 0, nb_sort = 0, nb_merge = 0;
+    int cus = 0, nb_sort = 0;
     HIPC(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
-    if (h->k64) {
+    if (h->k64)
       HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(
           &nb_sort, (const void *)k_sort_pass<uint64_t>, NT, 0));
-      HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &nb_merge, (const void *)k_merge<uint64_t>, NT, 0));
-    } else {
+    else
       HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(
           &nb_sort, (const void *)k_sort_pass<uint32_t>, NT, 0));
-      HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &nb_merge, (const void *)k_merge<uint32_t>, NT, 0));
-    }
-    if (cus < 1 || nb_sort < 1 || nb_merge < 1) return DDQMC_EHIP;
+    if (cus < 1 || nb_sort < 1) return DDQMC_EHIP;
     h->coop_sort = (uint32_t)(nb_sort * cus);
-    h->coop_merge = (uint32_t)(nb_merge * cus);
   }
   HIPC(hipMalloc((void **)&h->hist, MAX_PASSES * 256 * sizeof(uint32_t)));
   HIPC(hipMemsetAsync(h->hist, 0, MAX_PASSES * 256 * sizeof(uint32_t), h->stream));
@@ -364,15 +372,17 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev) {
   const uint32_t g_heavy = 1024;
   const uint32_t g_h = clampu((h->cap_sp + NT * 64 - 1) / (NT * 64), 1, 128);
   const uint32_t g_s = clampu(sort_tiles(h->cap_sp), 1, h->coop_sort);
-  const uint32_t g_m = clampu(merge_tiles(h->cap_main, h->cap_sp), 1, h->coop_merge);
+  const uint32_t g_m = clampu(merge_tiles(h->cap_main, h->cap_sp), 1, 1u << 20);
   if (ev) HIPC(hipEventRecord(ev->e[0], s));
   k_spawn_scan<K><<<h->nscan, NT, 0, s>>>(ak, av, h->ctrl, h->dsp, h->dss, h->loud, h->loud_cnt,
                                          h->SB);
   if (ev) HIPC(hipEventRecord(ev->e[1], s));
   k_loud_offsets<<<1, 1024, 0, s>>>(h->ctrl, h->loud_cnt, h->loud_off, h->nscan);
-  k_spawn_loud<K><<<g_loud, NT, 0, s>>>(ak, av, h->ctrl, h->dsp, h->dss, h->loud, h->loud_off,
-                                        h->nscan, h->heavy, (K *)h->sk[0], h->sv[0], h->segcnt,
-                                        segcap, h->SB);
+  k_loud_gather<K><<<g_loud, NT, 0, s>>>(ak, av, h->ctrl, h->loud, h->loud_cnt, h->loud_off,
+                                         h->nscan, h->lidx, (K *)h->lkey, h->lval);
+  k_spawn_loud<K><<<g_loud, NT, 0, s>>>(h->ctrl, h->dsp, h->dss, h->lidx, (const K *)h->lkey,
+                                        h->lval, h->loud_off, h->nscan, h->heavy, (K *)h->sk[0],
+                                        h->sv[0], h->segcnt, segcap, h->SB);
   if (ev) HIPC(hipEventRecord(ev->e[2], s));
   k_spawn_heavy<K><<<g_heavy, 64, 0, s>>>(ak, av, h->ctrl, h->dsp, h->dss, h->heavy,
                                           (K *)h->sk[0], h->sv[0], h->segcnt, segcap, h->SB);
@@ -397,27 +407,30 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev) {
     void *args[] = {&ik, &iv, &ok, &ov, &ctrl, &hist, &status, &pass, &sc};
     HIPC(hipLaunchCooperativeKernel((const void *)k_sort_pass<K>, dim3(g_s), dim3(NT), args, 0, s));
   }
+  {
+    // the merge-path partition is timed with the sort stage, so that the merge
+    // stage is the merge kernel alone
+    const int spb = h->passes & 1;
+    const uint32_t g_p = clampu((merge_tiles(h->cap_main, h->cap_sp) + NT) / NT, 1, 1024);
+    k_merge_partition<K><<<g_p, NT, 0, s>>>(ak, (const K *)h->sk[spb], h->ctrl, h->part);
+  }
   if (ev) HIPC(hipEventRecord(ev->e[6], s));
   {
     const int sp = h->passes & 1;
     const K *bk = (const K *)h->sk[sp];
     const int2 *bv = h->sv[sp];
-    Ctrl *ctrl = h->ctrl;
-    const SlotParams *dsp = h->dsp;
-    const SlotState *dss = h->dss;
-    Partial *partials = h->partials;
-    unsigned long long *spill = h->spill;
-    uint64_t *status = h->merge_status;
-    int SB = h->SB;
-    void *args[] = {&ak, &av, &bk, &bv, &ck, &cv, (void *)&capC, &ctrl, &dsp, &dss, &partials,
-                    &spill, &status, &SB};
-    HIPC(hipLaunchCooperativeKernel((const void *)k_merge<K>, dim3(g_m), dim3(NT), args, 0, s));
+    k_merge<K, false><<<g_m, NT, 0, s>>>(ak, av, bk, bv, ck, cv, capC, h->ctrl, h->dsp, h->dss,
+                                         h->partials, h->spill, h->tile_cnt, h->part, h->SB);
+    k_merge_offsets<<<1, 1024, 0, s>>>(h->ctrl, h->tile_cnt);
+    if (ev) HIPC(hipEventRecord(ev->e[7], s));
+    k_merge<K, true><<<g_m, NT, 0, s>>>(ak, av, bk, bv, ck, cv, capC, h->ctrl, h->dsp, h->dss,
+                                        h->partials, h->spill, h->tile_cnt, h->part, h->SB);
   }
-  if (ev) HIPC(hipEventRecord(ev->e[7], s));
+  if (ev) HIPC(hipEventRecord(ev->e[8], s));
   k_finalize<<<1, 1024, 0, s>>>(h->ctrl, h->dsp, h->dss, h->partials, h->spill, h->nslots,
                                 h->hist, h->passes, capC, h->segcnt, h->series, h->counts,
                                 SERIES_CAP);
-  if (ev) HIPC(hipEventRecord(ev->e[8], s));
+  if (ev) HIPC(hipEventRecord(ev->e[9], s));
   HIPC(hipGetLastError());
   return DDQMC_OK;
 }
@@ -465,10 +478,12 @@ int regrow(ddqmc_t *h, uint64_t need_main, uint64_t need_sp) {
     int rc = alloc_spawn(h, cap);
     if (rc != DDQMC_OK) return rc;
   }
-  HIPC(hipFree(h->merge_status));
+  HIPC(hipFree(h->tile_cnt));
   HIPC(hipFree(h->partials));
-  h->merge_status = nullptr;
+  HIPC(hipFree(h->part));
+  h->tile_cnt = nullptr;
   h->partials = nullptr;
+  h->part = nullptr;
   int rc = alloc_merge(h);
   if (rc != DDQMC_OK) return rc;
   HIPC(hipStreamSynchronize(h->stream));
@@ -932,6 +947,14 @@ int ddqmc_set_state(ddqmc_t *h, const void *buf, size_t n) {
   std::vector<int2> v(hd.n);
   std::memcpy(k.data(), c + sizeof(hd), hd.n * 8);
   std::memcpy(v.data(), c + sizeof(hd) + hd.n * 8, hd.n * sizeof(int2));
+  // the list invariants the step relies on: keys in range and strictly
+  // increasing, values nonzero and representable with a sign flip
+  const uint64_t lim = (h->SB >= 64) ? ~0ull : ((1ull << h->SB) - 1);
+  for (uint64_t i = 0; i < hd.n; ++i) {
+    if (k[i] > lim || (i > 0 && k[i] <= k[i - 1])) return DDQMC_EINVAL;
+    if ((v[i].x == 0 && v[i].y == 0) || v[i].x == INT32_MIN || v[i].y == INT32_MIN)
+      return DDQMC_EINVAL;
+  }
   if (hd.n > h->cap_main) {
     int rc = regrow(h, hd.n, 0);
     if (rc != DDQMC_OK) return rc;
@@ -982,7 +1005,7 @@ int ddqmc_set_profiling(ddqmc_t *h, int32_t on) {
   return DDQMC_OK;
 }
 
-int ddqmc_stage_times(ddqmc_t *h, double ms[8], int64_t *steps) {
+int ddqmc_stage_times(ddqmc_t *h, double ms[9], int64_t *steps) {
   if (!h || !ms) return DDQMC_EINVAL;
   for (int i = 0; i < NSTAGE; ++i) ms[i] = h->stage_ms[i];
   if (steps) *steps = h->stage_steps;

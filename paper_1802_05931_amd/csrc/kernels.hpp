@@ -145,6 +145,42 @@ __device__ uint32_t look_back(uint64_t *base, size_t stride, uint32_t t, uint32_
   return excl;
 }
 
+// The same for one full wave: lane i reads tile t-1-i of a window of 64 tiles,
+// so a run of aggregates costs one round trip per 64 tiles.  All 64 lanes must
+// call it; every lane returns the prefix.
+__device__ uint32_t look_back_wave(uint64_t *base, uint32_t t, uint32_t epoch) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t ep = (uint64_t)(epoch & 0x3fffffffu);
+  uint32_t excl = 0;
+  int64_t top = (int64_t)t - 1;  // the window is tiles top, top-1, ..., top-63
+  while (top >= 0) {
+    const int64_t j = top - lane;
+    uint64_t w = 0;
+    bool ready = true;
+    if (j >= 0) {
+      w = lb_load(base + j);
+      ready = ((w >> 34) == ep) && (((uint32_t)(w >> 32) & 3u) != 0);
+    }
+    // wait until every word of the window up to the nearest prefix is ready
+    const uint64_t is_prefix = __ballot(j >= 0 && ready && (((uint32_t)(w >> 32) & 3u) == 2u));
+    const int stop = is_prefix ? __builtin_ctzll(is_prefix) : 64;  // nearest prefix lane
+    const uint64_t not_ready = __ballot(!ready);
+    const uint64_t need = stop >= 63 ? ~0ull : ((2ull << stop) - 1ull);
+    if (not_ready & need) {
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    const uint32_t v = (j >= 0 && lane <= stop) ? (uint32_t)w : 0u;
+    uint32_t s = v;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+    excl += s;
+    if (stop < 64) break;
+    top -= 64;
+  }
+  return excl;
+}
+
 template <typename K>
 __device__ __forceinline__ uint32_t lower_bound(const K *a, uint32_t n, K key) {
   uint32_t lo = 0, hi = n;
@@ -353,6 +389,27 @@ struct RecordSink {
   }
 };
 
+// The loud queues of all scan blocks as one flat list (entry index, key, value),
+// so the loud kernel reads them with coalesced loads.
+template <typename K>
+__global__ __launch_bounds__(NT) void k_loud_gather(
+    const K *__restrict__ keys, const int2 *__restrict__ vals, Ctrl *ctrl,
+    const uint32_t *__restrict__ loud, const uint32_t *__restrict__ loud_cnt,
+    const uint32_t *__restrict__ loud_off, uint32_t nscan, uint32_t *__restrict__ lidx,
+    K *__restrict__ lkey, int2 *__restrict__ lval) {
+  if (ctrl->abort) return;
+  const uint32_t chunk = scan_chunk(ctrl->n_main, nscan);
+  for (uint32_t b = blockIdx.x; b < nscan; b += gridDim.x) {
+    const uint32_t cnt = loud_cnt[b], off = loud_off[b];
+    for (uint32_t q = threadIdx.x; q < cnt; q += NT) {
+      const uint32_t i = loud[b * chunk + q];
+      lidx[off + q] = i;
+      lkey[off + q] = keys[i];
+      lval[off + q] = vals[i];
+    }
+  }
+}
+
 // Pass 2: the loud entries, densely (flat index over all scan blocks).  Entries
 // whose draws all take the inversion branch are done here; the others (large
 // populations) are queued for k_spawn_heavy.  The initiator rule is applied in
@@ -360,17 +417,14 @@ struct RecordSink {
 // unused (re or im) part.
 template <typename K>
 __global__ __launch_bounds__(NT) void k_spawn_loud(
-    const K *__restrict__ keys, const int2 *__restrict__ vals, Ctrl *ctrl,
-    const SlotParams *__restrict__ sp, const SlotState *__restrict__ ss,
-    const uint32_t *__restrict__ loud, const uint32_t *__restrict__ loud_off, uint32_t nscan,
-    uint32_t *__restrict__ heavy, K *__restrict__ ok, int2 *__restrict__ ov, uint32_t *segcnt,
-    uint32_t segcap, int SB) {
+    Ctrl *ctrl, const SlotParams *__restrict__ sp, const SlotState *__restrict__ ss,
+    const uint32_t *__restrict__ lidx, const K *__restrict__ lkey, const int2 *__restrict__ lval,
+    const uint32_t *__restrict__ loud_off, uint32_t nscan, uint32_t *__restrict__ heavy,
+    K *__restrict__ ok, int2 *__restrict__ ov, uint32_t *segcnt, uint32_t segcap, int SB) {
   if (ctrl->abort) return;
   __shared__ K sk[STAGE];
   __shared__ int2 sv[STAGE];
   __shared__ uint32_t scount, sbase;
-  const uint32_t n = ctrl->n_main;
-  const uint32_t chunk = scan_chunk(n, nscan);
   const uint32_t nl = loud_off[nscan];
   const int seg = blockIdx.x % NSEG;
   const K lowm = low_mask<K>(SB);
@@ -382,17 +436,8 @@ __global__ __launch_bounds__(NT) void k_spawn_loud(
     __syncthreads();
     const uint32_t q = base + threadIdx.x;
     if (q < nl) {
-      uint32_t lo = 0, hi = nscan;  // loud_off[lo] <= q < loud_off[hi]
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (loud_off[mid] <= q)
-          lo = mid;
-        else
-          hi = mid;
-      }
-      const uint32_t i = loud[lo * chunk + (q - loud_off[lo])];
-      const K key = keys[i];
-      const int2 v = vals[i];
+      const K key = lkey[q];
+      const int2 v = lval[q];
       const uint32_t slot = slot_of<K>(key, SB);
       const SlotParams &P = sp[slot];
       const K hibits = key & ~lowm;
@@ -405,7 +450,7 @@ __global__ __launch_bounds__(NT) void k_spawn_loud(
           [&](uint32_t cl, uint32_t cm, int64_t dr, int64_t di, bool keep) {
             sink(hibits | (K)(((uint64_t)cl << N) | cm), dr, di, keep);
           });
-      if (!done) heavy[atomicAdd(&ctrl->n_heavy, 1u)] = i;
+      if (!done) heavy[atomicAdd(&ctrl->n_heavy, 1u)] = lidx[q];
     }
     __syncthreads();
     seg_flush(sk, sv, scount < (uint32_t)STAGE ? scount : (uint32_t)STAGE, seg, segcnt, ok, ov,
@@ -808,16 +853,32 @@ __global__ __launch_bounds__(NT) void k_sort_pass(const K *__restrict__ ik,
 struct RunSum {
   int64_t aR, aI, iR, iI;
 };
+// (selects rather than branches, so the sums stay in registers)
 __device__ __forceinline__ void run_add(RunSum &s, int2 v) {
-  if (v.x == NON_INIT) {
-    s.aI += v.y;
-  } else if (v.y == NON_INIT) {
-    s.aR += v.x;
-  } else {
-    s.aR += v.x;
-    s.aI += v.y;
-    s.iR += v.x;
-    s.iI += v.y;
+  const bool nx = v.x == NON_INIT;         // non-initiator record, imaginary part only
+  const bool ny = !nx && v.y == NON_INIT;  // non-initiator record, real part only
+  const int64_t x = nx ? 0 : (int64_t)v.x;
+  const int64_t y = ny ? 0 : (int64_t)v.y;
+  const bool ini = !nx && !ny;
+  s.aR += x;
+  s.aI += y;
+  s.iR += ini ? x : 0;
+  s.iI += ini ? y : 0;
+}
+
+// Tile boundaries of the merge: part[t] = A elements among the first t*TILE of
+// the merged sequence (all tiles in parallel; the merge reads them).
+template <typename K>
+__global__ __launch_bounds__(NT) void k_merge_partition(const K *__restrict__ Ak,
+                                                        const K *__restrict__ Bk, Ctrl *ctrl,
+                                                        uint32_t *__restrict__ part) {
+  if (ctrl->abort || (ctrl->flags & F_SPAWN_CAP)) return;
+  const uint32_t na = ctrl->n_main, nb = ctrl->n_spawn;
+  const uint32_t total = na + nb;
+  const uint32_t ntiles = (total + MERGE_TILE - 1) / MERGE_TILE;
+  for (uint32_t t = blockIdx.x * NT + threadIdx.x; t <= ntiles; t += gridDim.x * NT) {
+    const uint32_t d = t * MERGE_TILE < total ? t * MERGE_TILE : total;
+    part[t] = merge_path(Ak, na, Bk, nb, d);
   }
 }
 
@@ -826,51 +887,75 @@ __device__ __forceinline__ void run_add(RunSum &s, int2 v) {
 // a run without a key in A becomes a new entry with the sum of all its records
 // if the configuration is diagonal, else of its initiator records only
 // (Sec. IV.A).  Empty entries are dropped, the rest compacted in order.
-// Launched cooperatively; block b takes tiles b, b + G, ... (see k_sort_pass).
-template <typename K>
+// Two launches over the same tiles (the merge path cut into MERGE_TILE merged
+// positions): COUNT writes each tile's number of survivors, k_merge_offsets
+// turns them into output offsets, WRITE stores the survivors there and the
+// tile's estimator sums.  Both decide survival with the same code, so their
+// counts agree; no tile waits on another.
+template <typename K, bool WRITE>
 __global__ __launch_bounds__(NT) void k_merge(
     const K *__restrict__ Ak, const int2 *__restrict__ Av, const K *__restrict__ Bk,
     const int2 *__restrict__ Bv, K *__restrict__ Ck, int2 *__restrict__ Cv, uint32_t capC,
     Ctrl *ctrl, const SlotParams *__restrict__ sp, const SlotState *__restrict__ ss,
-    Partial *__restrict__ partials, unsigned long long *__restrict__ spill, uint64_t *status,
-    int SB) {
+    Partial *__restrict__ partials, unsigned long long *__restrict__ spill,
+    uint32_t *__restrict__ tile_cnt, const uint32_t *__restrict__ part, int SB) {
   if (ctrl->abort || (ctrl->flags & F_SPAWN_CAP)) return;
   const uint32_t na = ctrl->n_main;
   const uint32_t nb = ctrl->n_spawn;
   const uint32_t total = na + nb;
   const uint32_t ntiles = (total + MERGE_TILE - 1) / MERGE_TILE;
-  const uint32_t epoch = ctrl->epoch;
   const K lowm = low_mask<K>(SB);
 
   __shared__ K sAk[MERGE_TILE], sBk[MERGE_TILE];
-  __shared__ int2 sAv[MERGE_TILE];
-  __shared__ uint32_t s_i0, s_i1, s_excl;
+  __shared__ int2 sBv[MERGE_TILE];
+  __shared__ int2 sAv[WRITE ? MERGE_TILE : 1];
+  __shared__ uint32_t s_i0, s_i1;
+  __shared__ K s_aprev, s_bprev, s_bnext;  // the keys just outside the tile
   __shared__ uint32_t scan4[NT / 64];
-  __shared__ int64_t red[NT / 64][S_NSUM];
+  __shared__ int64_t red[WRITE ? NT / 64 : 1][S_NSUM];
   bool int_ovf = false;
 
   for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     __syncthreads();
     const uint32_t d0 = t * MERGE_TILE;
     const uint32_t d1 = (d0 + MERGE_TILE < total) ? d0 + MERGE_TILE : total;
-    if (threadIdx.x == 0) s_i0 = merge_path(Ak, na, Bk, nb, d0);
-    if (threadIdx.x == 64) s_i1 = merge_path(Ak, na, Bk, nb, d1);
+    if (threadIdx.x == 0) s_i0 = part[t];
+    if (threadIdx.x == 64) s_i1 = part[t + 1];
     __syncthreads();
     const uint32_t i0 = s_i0, i1 = s_i1, j0 = d0 - i0, j1 = d1 - i1;
     const uint32_t nA = i1 - i0, nB = j1 - j0;
     for (uint32_t q = threadIdx.x; q < nA; q += NT) {
       sAk[q] = Ak[i0 + q];
-      sAv[q] = Av[i0 + q];
+      if (WRITE) sAv[q] = Av[i0 + q];
     }
-    for (uint32_t q = threadIdx.x; q < nB; q += NT) sBk[q] = Bk[j0 + q];
+    for (uint32_t q = threadIdx.x; q < nB; q += NT) {
+      sBk[q] = Bk[j0 + q];
+      sBv[q] = Bv[j0 + q];
+    }
+    if (threadIdx.x == NT - 1) {
+      s_aprev = i0 > 0 ? Ak[i0 - 1] : (K)0;
+      s_bprev = j0 > 0 ? Bk[j0 - 1] : (K)0;
+      s_bnext = j1 < nb ? Bk[j1] : (K)0;
+    }
     __syncthreads();
-    auto bkey = [&](uint32_t j) -> K { return (j >= j0 && j < j1) ? sBk[j - j0] : Bk[j]; };
-    auto akey = [&](uint32_t i) -> K { return (i >= i0 && i < i1) ? sAk[i - i0] : Ak[i]; };
+    // keys by global index; callers pass indices inside the arrays
+    auto bkey = [&](uint32_t j) -> K {
+      if (j >= j0 && j < j1) return sBk[j - j0];
+      if (j == j1) return s_bnext;
+      if (j + 1 == j0) return s_bprev;
+      return Bk[j];
+    };
+    auto bval = [&](uint32_t j) -> int2 { return (j >= j0 && j < j1) ? sBv[j - j0] : Bv[j]; };
+    auto akey = [&](uint32_t i) -> K {
+      if (i >= i0 && i < i1) return sAk[i - i0];
+      if (i + 1 == i0) return s_aprev;
+      return Ak[i];
+    };
     // the run of records with key k starting at global index j
     auto run_from = [&](uint32_t j, K k) -> RunSum {
       RunSum s{0, 0, 0, 0};
       while (j < nb && bkey(j) == k) {
-        run_add(s, Bv[j]);
+        run_add(s, bval(j));
         ++j;
       }
       return s;
@@ -895,26 +980,39 @@ __global__ __launch_bounds__(NT) void k_merge(
     }
     K ck[MERGE_IT];
     int2 cv[MERGE_IT];
-    bool ok_it[MERGE_IT];
+    uint32_t okm = 0;  // bit it: position it survives
     uint32_t nsurv = 0;
     const uint32_t s0 = slot_of<K>((nA > 0 && (nB == 0 || sAk[0] <= sBk[0])) ? sAk[0] : sBk[0], SB);
+    // the tile's first solve: its parameters once, in registers
+    const SlotParams P0 = sp[s0];
+    const bool leaving0 = ss[s0].status == 3;
     int64_t acc[S_NSUM];
 #pragma unroll
     for (int s = 0; s < S_NSUM; ++s) acc[s] = 0;
 
 #pragma unroll
     for (int it = 0; it < MERGE_IT; ++it) {
-      ok_it[it] = false;
       if (dd + (uint32_t)it >= len) continue;
       K k;
-      int64_t R = 0, I = 0;
-      bool emit = false;
+      RunSum rs{0, 0, 0, 0};
+      int64_t aR = 0, aI = 0;  // A's value when k is in the step-start list
+      bool inA = false, emit = false;
       if (a < nA && (b >= nB || sAk[a] <= sBk[b])) {
         k = sAk[a];
-        const RunSum s = run_from(j0 + b, k);
-        R = (int64_t)sAv[a].x + s.aR;
-        I = (int64_t)sAv[a].y + s.aI;
-        emit = true;
+        inA = emit = true;
+        if (WRITE) {
+          aR = sAv[a].x;
+          aI = sAv[a].y;
+          rs = run_from(j0 + b, k);
+        } else if (j0 + b < nb && bkey(j0 + b) == k) {
+          // counting: A's value matters only when records land on it
+          const int2 av = Av[i0 + a];
+          aR = av.x;
+          aI = av.y;
+          rs = run_from(j0 + b, k);
+        } else {
+          aR = 1;  // occupied entries are nonzero
+        }
         ++a;
       } else {
         k = sBk[b];
@@ -922,72 +1020,79 @@ __global__ __launch_bounds__(NT) void k_merge(
         const bool head = (gj == 0) || bkey(gj - 1) != k;
         const bool matched = (gi > 0) && akey(gi - 1) == k;
         if (head && !matched) {
-          const RunSum s = run_from(gj, k);
-          const SlotParams &P = sp[slot_of<K>(k, SB)];
-          const uint64_t cfg = (uint64_t)(k & lowm);
-          const uint64_t lm = (P.N == 32) ? 0xffffffffull : ((1ull << P.N) - 1);
-          const bool diag = (cfg >> P.N) == (cfg & lm);
-          R = diag ? s.aR : s.iR;
-          I = diag ? s.aI : s.iI;
+          rs = run_from(gj, k);
           emit = true;
         }
         ++b;
       }
-      if (!emit || (R == 0 && I == 0)) continue;
+      if (!emit) continue;
       const uint32_t slot = slot_of<K>(k, SB);
-      if (ss[slot].status == 3) continue;  // solve leaving the list
-      if (R > 2147483647LL || R < -2147483647LL || I > 2147483647LL || I < -2147483647LL)
-        int_ovf = true;
-      ck[it] = k;
-      cv[it] = make_int2((int)R, (int)I);
-      ok_it[it] = true;
-      ++nsurv;
-      const SlotParams &P = sp[slot];
-      const uint64_t cfg = (uint64_t)(k & lowm);
-      const uint32_t l = (uint32_t)(cfg >> P.N);
-      const uint32_t m = (uint32_t)(cfg & ((P.N == 32) ? 0xffffffffull : ((1ull << P.N) - 1)));
-      if (slot == s0) {
-        entry_sums(P, l, m, R, I, acc);
-      } else {
-        int64_t one[S_NSUM];
+      auto finish = [&](const SlotParams &P, bool leaving) {
+        const uint64_t cfg = (uint64_t)(k & lowm);
+        const uint32_t l = (uint32_t)(cfg >> P.N);
+        const uint32_t m = (uint32_t)(cfg & ((P.N == 32) ? 0xffffffffull : ((1ull << P.N) - 1)));
+        int64_t R, I;
+        if (inA || l == m) {  // occupied or diagonal: every record counts
+          R = aR + rs.aR;
+          I = aI + rs.aI;
+        } else {  // new off-diagonal entry: initiator records only (Sec. IV.A)
+          R = rs.iR;
+          I = rs.iI;
+        }
+        if ((R == 0 && I == 0) || leaving) return;
+        ++nsurv;
+        if (!WRITE) return;
+        if (R > 2147483647LL || R < -2147483647LL || I > 2147483647LL || I < -2147483647LL)
+          int_ovf = true;
+        ck[it] = k;
+        cv[it] = make_int2((int)R, (int)I);
+        okm |= 1u << it;
+        if (slot == s0) {
+          entry_sums(P, l, m, R, I, acc);
+        } else {
+          int64_t one[S_NSUM];
 #pragma unroll
-        for (int s = 0; s < S_NSUM; ++s) one[s] = 0;
-        entry_sums(P, l, m, R, I, one);
+          for (int s = 0; s < S_NSUM; ++s) one[s] = 0;
+          entry_sums(P, l, m, R, I, one);
 #pragma unroll
-        for (int s = 0; s < S_NSUM; ++s)
-          if (one[s]) atomicAdd(&spill[(size_t)slot * S_NSUM + s], (unsigned long long)one[s]);
-      }
+          for (int s = 0; s < S_NSUM; ++s)
+            if (one[s]) atomicAdd(&spill[(size_t)slot * S_NSUM + s], (unsigned long long)one[s]);
+        }
+      };
+      if (slot == s0)
+        finish(P0, leaving0);
+      else
+        finish(sp[slot], ss[slot].status == 3);
     }
-    // compaction: position of this thread's survivors
+    if (!WRITE) {
+      const uint32_t v = wave_sum(nsurv);
+      if ((threadIdx.x & 63) == 0) scan4[threadIdx.x >> 6] = v;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) c += scan4[w];
+        tile_cnt[t] = c;
+      }
+      continue;
+    }
+    // compaction: position of this thread's survivors; the tile's offset
     uint32_t ttot;
     const uint32_t lpos = block_excl_scan(nsurv, scan4, &ttot);
-    if (threadIdx.x == 0) {
-      uint64_t *st = status + t;
-      uint32_t excl = 0;
-      if (t == 0) {
-        lb_store(st, lb_pack(epoch, 2u, ttot));
-      } else {
-        lb_store(st, lb_pack(epoch, 1u, ttot));
-        excl = look_back(status, 1, t, epoch);
-        lb_store(st, lb_pack(epoch, 2u, excl + ttot));
-      }
-      s_excl = excl;
-      if (t == ntiles - 1) ctrl->n_new = excl + ttot;
-    }
+    const uint32_t gbase = tile_cnt[t];
     // stage survivors in LDS (reuse the A arrays), then write them coalesced
     __syncthreads();
     {
       uint32_t q = lpos;
 #pragma unroll
       for (int it = 0; it < MERGE_IT; ++it)
-        if (ok_it[it]) {
+        if (okm & (1u << it)) {
           sAk[q] = ck[it];
           sAv[q] = cv[it];
           ++q;
         }
     }
     __syncthreads();
-    const uint32_t gbase = s_excl;
     for (uint32_t q = threadIdx.x; q < ttot; q += NT) {
       const uint32_t g = gbase + q;
       if (g < capC) {
@@ -1012,6 +1117,33 @@ __global__ __launch_bounds__(NT) void k_merge(
     }
   }
   if (int_ovf) atomicOr(&ctrl->flags, F_INT_OVF);
+}
+
+// Output offsets of the merge tiles, in place: cnt[t] <- survivors of tiles
+// < t; the new list size goes to ctrl->n_new.  One block of 1024 threads.
+__global__ __launch_bounds__(1024) void k_merge_offsets(Ctrl *ctrl, uint32_t *cnt) {
+  if (ctrl->abort || (ctrl->flags & F_SPAWN_CAP)) return;
+  __shared__ uint32_t wsum[16];
+  const uint32_t total = ctrl->n_main + ctrl->n_spawn;
+  const uint32_t n = (total + MERGE_TILE - 1) / MERGE_TILE;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint32_t per = (n + 1023) / 1024;
+  const uint32_t b0 = tid * per < n ? tid * per : n;
+  const uint32_t b1 = (b0 + per < n) ? b0 + per : n;
+  uint32_t local = 0;
+  for (uint32_t b = b0; b < b1; ++b) local += cnt[b];
+  const uint32_t inc = wave_incl_scan(local);
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  uint32_t before = 0;
+  for (int i = 0; i < w; ++i) before += wsum[i];
+  uint32_t run = before + inc - local;
+  for (uint32_t b = b0; b < b1; ++b) {
+    const uint32_t c = cnt[b];
+    cnt[b] = run;
+    run += c;
+  }
+  if (tid == 1023) ctrl->n_new = before + inc;
 }
 
 // ---- finalize (one block) ---------------------------------------------------

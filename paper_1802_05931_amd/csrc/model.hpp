@@ -168,6 +168,19 @@ DQ_HD T pick6(const T *a, int c) {
   return v;
 }
 
+// Element c of six values held in registers (a select chain on values, so no
+// array has to live in memory to be indexed).
+template <typename T>
+DQ_HD T sel6(int c, T a0, T a1, T a2, T a3, T a4, T a5) {
+  T v = a0;
+  v = c == 1 ? a1 : v;
+  v = c == 2 ? a2 : v;
+  v = c == 3 ? a3 : v;
+  v = c == 4 ? a4 : v;
+  v = c == 5 ? a5 : v;
+  return v;
+}
+
 // One spawned walker among n equal members: a uniform member from the pick
 // stream of the channel.
 DQ_HD int pick_member(const EntryCounter &c, uint32_t draw, int n) {
@@ -376,53 +389,50 @@ DQ_HD void entry_events(const SlotParams &P, double S, uint32_t step, uint32_t l
 }
 
 // Tree split for small counts (M < 32, n <= 64): the same draws and leaves as
-// tree_split, with each pending node packed into one word
-// (lo | hi << 7 | h << 14 | M << 21) and inversion-only draws.
+// tree_split, by a depth-first walk without a stack.  The walk goes left
+// first; the right child of a split waits as a 5-bit count in the field of its
+// depth (at most one per depth), and is found again from the current heap
+// index, its range rebuilt from the root.  Inversion-only draws.
 template <typename F>
 DQ_HD void tree_split_small(int n, int64_t M, const EntryCounter &c, uint32_t draw_base,
                             int &dry, F &&emit) {
-  uint32_t st0 = 0, st1 = 0, st2 = 0, st3 = 0, st4 = 0, st5 = 0, st6 = 0, st7 = 0;
-  int sp = 0;
-  auto push = [&](uint32_t w) {
-    st7 = sp == 7 ? w : st7;
-    st6 = sp == 6 ? w : st6;
-    st5 = sp == 5 ? w : st5;
-    st4 = sp == 4 ? w : st4;
-    st3 = sp == 3 ? w : st3;
-    st2 = sp == 2 ? w : st2;
-    st1 = sp == 1 ? w : st1;
-    st0 = sp == 0 ? w : st0;
-    ++sp;
-  };
-  auto pop = [&]() -> uint32_t {
-    --sp;
-    uint32_t w = st0;
-    w = sp == 1 ? st1 : w;
-    w = sp == 2 ? st2 : w;
-    w = sp == 3 ? st3 : w;
-    w = sp == 4 ? st4 : w;
-    w = sp == 5 ? st5 : w;
-    w = sp == 6 ? st6 : w;
-    w = sp == 7 ? st7 : w;
-    return w;
-  };
-  push((uint32_t)n << 7 | 1u << 14 | (uint32_t)M << 21);
+  uint64_t pend = 0;  // bits [5d, 5d + 5): count of the right child waiting at depth d
+  int lo = 0, hi = n, depth = 0;
+  uint32_t h = 1;
+  int64_t Mn = M;
 #pragma unroll 1
-  while (sp > 0) {
-    const uint32_t w = pop();
-    const int lo = (int)(w & 127u), hi = (int)((w >> 7) & 127u), h = (int)((w >> 14) & 127u);
-    const int64_t Mn = (int64_t)(w >> 21);
-    if (Mn == 0) continue;
-    if (hi - lo == 1) {
-      emit(lo, Mn);
-      continue;
+  for (;;) {
+    if (Mn > 0) {
+      if (hi - lo == 1) {
+        emit(lo, Mn);
+      } else {
+        const int mid = lo + (hi - lo) / 2;
+        const int64_t ML = binomial_small(c.seed, c.solve, c.cfg, c.step, draw_base + h, Mn,
+                                          (double)(mid - lo) / (double)(hi - lo), false, dry);
+        ++depth;
+        pend |= (uint64_t)(Mn - ML) << (5 * depth);
+        hi = mid;  // the left child next
+        h = 2 * h;
+        Mn = ML;
+        continue;
+      }
     }
-    const int mid = lo + (hi - lo) / 2;
-    const int64_t ML = binomial_small(c.seed, c.solve, c.cfg, c.step, draw_base + (uint32_t)h, Mn,
-                                      (double)(mid - lo) / (double)(hi - lo), false, dry);
-    push((uint32_t)mid | (uint32_t)hi << 7 | (uint32_t)(2 * h + 1) << 14 |
-         (uint32_t)(Mn - ML) << 21);
-    push((uint32_t)lo | (uint32_t)mid << 7 | (uint32_t)(2 * h) << 14 | (uint32_t)ML << 21);
+    if (pend == 0) break;
+    const int d = (63 - __builtin_clzll(pend)) / 5;  // the deepest waiting child
+    Mn = (int64_t)((pend >> (5 * d)) & 31u);
+    pend &= ~(31ull << (5 * d));
+    h = (h >> (depth - d)) | 1u;  // right sibling of the path's node at depth d
+    depth = d;
+    lo = 0;
+    hi = n;
+#pragma unroll 1
+    for (int k = d - 1; k >= 0; --k) {
+      const int mid = lo + (hi - lo) / 2;
+      if ((h >> k) & 1u)
+        lo = mid;
+      else
+        hi = mid;
+    }
   }
 }
 
@@ -433,6 +443,19 @@ template <typename Emit>
 DQ_HD bool entry_events_small(const SlotParams &P, double S, uint32_t step, uint32_t l,
                               uint32_t m, int32_t R, int32_t I, int *err, Emit &&emit) {
   const EntryProbs e = entry_probs(P, S, step, l, m, R, I);
+  // the class tables as values in registers, picked by sel6
+  const uint32_t cr0 = e.hc.r[0], cr1 = e.hc.r[1], cr2 = e.hc.r[2], cr3 = e.hc.r[3],
+                 cr4 = e.hc.r[4], cr5 = e.hc.r[5];
+  const uint32_t cu0 = e.hc.u[0], cu1 = e.hc.u[1], cu2 = e.hc.u[2], cu3 = e.hc.u[3],
+                 cu4 = e.hc.u[4], cu5 = e.hc.u[5];
+  const int cn0 = e.hc.n[0], cn1 = e.hc.n[1], cn2 = e.hc.n[2], cn3 = e.hc.n[3], cn4 = e.hc.n[4],
+            cn5 = e.hc.n[5];
+  const int cs0 = e.hc.sgn[0], cs1 = e.hc.sgn[1], cs2 = e.hc.sgn[2], cs3 = e.hc.sgn[3],
+            cs4 = e.hc.sgn[4], cs5 = e.hc.sgn[5];
+  const double cw0 = e.hc.W[0], cw1 = e.hc.W[1], cw2 = e.hc.W[2], cw3 = e.hc.W[3],
+               cw4 = e.hc.W[4], cw5 = e.hc.W[5];
+  const double sc0 = e.Sc[0], sc1 = e.Sc[1], sc2 = e.Sc[2], sc3 = e.Sc[3], sc4 = e.Sc[4],
+               sc5 = e.Sc[5];
   const double pk[4] = {e.p8[0], e.p8[1], e.p8[2], e.p8[3]};
   const int64_t nR = e.n8[0], nI = e.n8[4];
 #pragma unroll
@@ -507,34 +530,53 @@ DQ_HD bool entry_events_small(const SlotParams &P, double S, uint32_t step, uint
     if (rem == 0) continue;
     const int ch = part ? 8 : 4;
     if (rem == 1) {  // one walker: class by inversion on the weights, then a member
-      int c, j;
-      pick_hop(e.cnt, draw_channel(ch) + DRAW_PICK, e.Sc, e.hc.n, c, j);
-      const uint32_t bm = class_member_mask(P, pick6(e.hc.r, c), pick6(e.hc.u, c), j);
+      // class by inversion on the weights (the smallest c with S_{c+1} < S_0 (1 - u1)),
+      // then a uniform member from u2, as pick_hop
+      Stream st(e.cnt.seed, e.cnt.solve, e.cnt.cfg, e.cnt.step, draw_channel(ch) + DRAW_PICK,
+                nullptr);
+      const double u1 = st.next();
+      const double u2 = st.next();
+      const double T = sc0 * (1.0 - u1);
+      int c = 5;
+      c = sc5 < T ? 4 : c;
+      c = sc4 < T ? 3 : c;
+      c = sc3 < T ? 2 : c;
+      c = sc2 < T ? 1 : c;
+      c = sc1 < T ? 0 : c;
+      const int nc = sel6(c, cn0, cn1, cn2, cn3, cn4, cn5);
+      int j = (int)__builtin_floor(u2 * (double)nc);
+      j = j > nc - 1 ? nc - 1 : j;
+      const uint32_t bm = class_member_mask(P, sel6(c, cr0, cr1, cr2, cr3, cr4, cr5),
+                                            sel6(c, cu0, cu1, cu2, cu3, cu4, cu5), j);
       const uint32_t cl = c < 3 ? (l ^ bm) : l;
       const uint32_t cm = c < 3 ? m : (m ^ bm);
-      const int64_t v = sg * (int64_t)pick6(e.hc.sgn, c);
+      const int64_t v = sg * (int64_t)sel6(c, cs0, cs1, cs2, cs3, cs4, cs5);
       emit(cl, cm, part ? -v : 0, part ? 0 : v, init || cl == cm);
       continue;
     }
     int last = -1;
-#pragma unroll
-    for (int c = 0; c < 6; ++c)
-      if (e.hc.W[c] > 0.0) last = c;
+    last = cw0 > 0.0 ? 0 : last;
+    last = cw1 > 0.0 ? 1 : last;
+    last = cw2 > 0.0 ? 2 : last;
+    last = cw3 > 0.0 ? 3 : last;
+    last = cw4 > 0.0 ? 4 : last;
+    last = cw5 > 0.0 ? 5 : last;
 #pragma unroll 1
     for (int c = 0; c < 6; ++c) {
-      const double Wc = pick6(e.hc.W, c);
+      const double Wc = sel6(c, cw0, cw1, cw2, cw3, cw4, cw5);
       if (rem == 0 || Wc == 0.0) continue;
       int64_t Mc = rem;
       if (c != last)
         Mc = binomial_small(e.cnt.seed, e.cnt.solve, e.cnt.cfg, e.cnt.step,
-                            draw_channel(ch) + 1u + (uint32_t)c, rem, Wc / pick6(e.Sc, c), false,
-                            dry);
+                            draw_channel(ch) + 1u + (uint32_t)c, rem,
+                            Wc / sel6(c, sc0, sc1, sc2, sc3, sc4, sc5), false, dry);
       rem -= Mc;
       if (Mc == 0) continue;
-      const uint32_t cr = pick6(e.hc.r, c), cu = pick6(e.hc.u, c);
+      const uint32_t cr = sel6(c, cr0, cr1, cr2, cr3, cr4, cr5);
+      const uint32_t cu = sel6(c, cu0, cu1, cu2, cu3, cu4, cu5);
       const int nr = popc(cr);
-      const int64_t sv = sg * (int64_t)pick6(e.hc.sgn, c);
-      tree_split_small(pick6(e.hc.n, c), Mc, e.cnt,
+      const int64_t sv = sg * (int64_t)sel6(c, cs0, cs1, cs2, cs3, cs4, cs5);
+      tree_split_small(sel6(c, cn0, cn1, cn2, cn3, cn4, cn5), Mc, e.cnt,
                        draw_channel(ch) + 64u + 64u * (uint32_t)c, dry, [&](int j, int64_t M) {
                          uint32_t bm;
                          if (j < nr) {
