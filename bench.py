@@ -14,6 +14,8 @@ bytes per launch / its mean duration from HIP events on the handle's stream),
 and the CPU oracle timed on a bounded sample of the same workload.
 
 Usage: python bench.py [--steps K] [--warmup W] [--workload d3|d3l] [--no-cpu]
+       python bench.py --workload d5 [--steps K]    (64 5x5 replicas, batched vs one by one)
+       python bench.py --workload d4 [--requests R]  (serving loop vs one solve at a time)
        python bench.py --trace-summary DIR --steps K
 The second form reads the kernel trace rocprofv3 wrote into DIR for a run of the
 first form and prints, per kernel, the mean dispatch duration over the last K
@@ -129,15 +131,131 @@ def trace_summary(directory, steps):
     print("\n".join(out))
 
 
+def _walker_updates(series, steps):
+    """Sum of W_tot at the start of the last `steps` steps of a series."""
+    import numpy as np
+    import paper_1802_05931_amd as dq
+    w = series[:, 3 + dq.SUM_NAMES.index("w_tot")].astype(np.float64)
+    return float(w[-steps - 1:-1].sum())
+
+
+def bench_d5(args):
+    """64 independent 5x5 replicas: one batch handle (one launch per stage for
+    all replicas) against the same replicas run one after another on their own
+    handles.  The lists must come out identical."""
+    import numpy as np
+    import torch
+    from paper_1802_05931_amd import serving
+    steps = args.steps if args.steps != 1000 else 2000
+    cfgs = workloads.d5_replicas()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    print(f"d5: batched, {len(cfgs)} replicas x {steps} steps", file=sys.stderr, flush=True)
+    tb, ob, lb = serving.replicas_batched(cfgs, steps, stream=stream)
+    print(f"d5: batched {tb:.2f} s; sequential", file=sys.stderr, flush=True)
+    ts, os_, ls = serving.replicas_sequential(cfgs, steps, stream=stream)
+    print(f"d5: sequential {ts:.2f} s", file=sys.stderr, flush=True)
+    same = all(len(a[0]) == len(c[0]) and all(np.array_equal(x, y) for x, y in zip(a, c))
+               for a, c in zip(lb, ls))
+    same_obs = all(a["acc"] == c["acc"] and a["step"] == c["step"] for a, c in zip(ob, os_))
+    entries = int(sum(len(x[0]) for x in lb))
+    out = {
+        "metric": "replica-steps/s (64 x 5x5 XYZ replicas, batched)",
+        "value": len(cfgs) * (steps - 1) / tb,
+        "unit": "replica-steps/s",
+        "n_gpus": 1, "steps": steps - 1, "warmup": 1,
+        "ms_per_step": 1e3 * tb / (steps - 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "i32 walkers, f64 probabilities", "data": "synthetic",
+        "config": {"workload": "64 replicas of the 5x5 dissipative XYZ model, Jx 0.5..1.2, "
+                               "dt 0.002, n_a 3, targets log-uniform in [1e5, 2e6], u64 keys",
+                   "graph_steps": 0, "final_entries": entries},
+        "sequential": {"seconds": ts, "value": len(cfgs) * (steps - 1) / ts},
+        "batched_seconds": tb,
+        "speedup_vs_sequential": ts / tb,
+        "lists_identical": bool(same), "accumulators_identical": bool(same_obs),
+        "mz": [round(o["mz"], 5) for o in ob[:8]],
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_d4(args):
+    """The serving stream: Poisson arrivals at 20/s, mixed lattices and targets,
+    continuous batching in one pool, against the same requests one at a time
+    (every n-th request timed alone for exactly the steps it took in the pool:
+    identical lists, so identical errors)."""
+    import numpy as np
+    import torch
+    from paper_1802_05931_amd import serving
+    reqs = workloads.d4_requests(count=args.requests)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    done = [0]
+
+    def log(msg):
+        done[0] += 1
+        print(f"d4: {msg}", file=sys.stderr, flush=True)
+    recs, ticks = serving.serve(reqs, stream=stream, log=log)
+    wall = time.perf_counter() - t0
+    lat = np.array([r["finished"] - r["arrival"] for r in recs])
+    steps = np.array([r["steps"] for r in recs])
+    conv = np.array([r["converged"] for r in recs])
+    print(f"d4: served {len(recs)} in {wall:.1f} s; timing every {args.baseline_every}-th alone",
+          file=sys.stderr, flush=True)
+    alone = []
+    for i in range(0, len(reqs), args.baseline_every):
+        dt, obs = serving.solve_alone(reqs[i]["params"], int(steps[i]), stream=stream)
+        assert obs["step"] == steps[i]
+        assert abs(obs["mz"] - recs[i]["mz"]) == 0.0 or (np.isnan(obs["mz"]) and
+                                                        np.isnan(recs[i]["mz"]))
+        alone.append(dt)
+    alone_total = float(np.sum(alone)) * args.baseline_every
+    last_arrival = max(r["arrival"] for r in reqs)
+    out = {
+        "metric": "served solves/s (D4 stream: 2x2/3x3/4x4/2x6, Poisson 20/s)",
+        "value": len(recs) / wall,
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": int(steps.sum()), "warmup": 0,
+        "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "i32 walkers, f64 probabilities", "data": "synthetic",
+        "config": {"workload": f"{len(reqs)} requests, lattices uniform over 2x2/3x3/4x4/2x6, "
+                               "Jx U[0.5,1.2], Jz U[0.8,1.2], gamma U[0.5,2], dt 0.005, n_a 3, "
+                               "targets log-uniform [1e3,1e6], Poisson arrivals 20/s",
+                   "slots": 64, "tick_steps": 50, "stop": "SE(M_z) < 1e-3 after >= 512 "
+                   "accumulated steps, or 4000 steps"},
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "max": float(lat.max())},
+        "wall_s": wall, "last_arrival_s": last_arrival, "ticks": ticks,
+        "converged": int(conv.sum()), "steps_per_solve_median": float(np.median(steps)),
+        "one_at_a_time": {"seconds_estimated": alone_total,
+                          "sample": f"every {args.baseline_every}-th request alone "
+                                    f"({len(alone)} solves, scaled by {args.baseline_every})",
+                          "solves_per_s": len(recs) / alone_total},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=15000)
-    ap.add_argument("--workload", default="d3", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="d3", choices=sorted(WORKLOADS) + ["d4", "d5"])
+    ap.add_argument("--requests", type=int, default=512, help="d4: requests in the stream")
+    ap.add_argument("--baseline-every", type=int, default=8,
+                    help="d4: time every n-th request alone for the one-at-a-time baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--trace-summary", metavar="DIR")
+    ap.add_argument("--save-state", metavar="FILE",
+                    help="write the solve's checkpoint after the warm-up")
+    ap.add_argument("--load-state", metavar="FILE",
+                    help="start from a checkpoint of the same workload instead of warming up")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="after the timed steps, copy a buffer of this many MiB three times "
+                         "(a plain copy kernel of known size for scaling memory counters)")
     args = ap.parse_args()
     if args.trace_summary:
         trace_summary(args.trace_summary, args.steps)
@@ -153,11 +271,26 @@ def main():
 
     import paper_1802_05931_amd as dq
 
+    if args.workload == "d5":
+        return bench_d5(args)
+    if args.workload == "d4":
+        return bench_d4(args)
     cfg, desc = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     g = dq.Solve(dq.make_params(**cfg), stream=stream)
-    g.step(args.warmup)
+    if args.load_state:
+        with open(args.load_state, "rb") as f:
+            g.set_state(f.read())
+        args.warmup = g.scalars()["step"]
+        _, re0, im0 = g.walkers()
+        w0 = int(np.abs(re0.astype(np.int64)).sum() + np.abs(im0.astype(np.int64)).sum())
+        del re0, im0
+    else:
+        g.step(args.warmup)
+    if args.save_state:
+        with open(args.save_state, "wb") as f:
+            f.write(g.get_state())
     g.set_profiling(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -172,7 +305,10 @@ def main():
     sums = {n: i + 3 for i, n in enumerate(dq.SUM_NAMES)}
     w_tot = series[:, sums["w_tot"]]
     # W_tot at the start of each timed step = W_tot after the previous step
-    w_start = w_tot[-args.steps - 1:-1]
+    if len(w_tot) >= args.steps + 1:
+        w_start = w_tot[-args.steps - 1:-1]
+    else:  # started from a checkpoint: the first step starts from the loaded list
+        w_start = np.concatenate([[w0], w_tot[:-1]])
     walker_updates = float(w_start.sum())
     c = counts[-args.steps:]
     n_in, n_sp, n_out = (c[:, 0].astype(float), c[:, 1].astype(float), c[:, 2].astype(float))
@@ -232,6 +368,13 @@ def main():
         "mz_running": obs["mz"],
     }
     g.set_profiling(False)
+    if args.copy_probe_mb:
+        src = torch.ones(args.copy_probe_mb << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, keys, re, im, sc, args.cpu_seconds)
     else:

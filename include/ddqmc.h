@@ -177,6 +177,15 @@ int ddqmc_workspace_query(const ddqmc_params *p, int64_t capacity, size_t *bytes
  * tile and their offsets), merge (the merge kernel that writes the new list),
  * finalize, summed over the call's steps. */
 int ddqmc_set_profiling(ddqmc_t *h, int32_t on);
+
+/* Launch the kernels of k consecutive steps as one HIP graph (k even,
+ * 2 <= k <= 1024); k = 0 (the default) launches them one by one.  A graph is
+ * captured on first use for each parity of the list it starts from, and again
+ * after the handle's buffers grow; steps that do not fill a whole graph run
+ * one by one.  Graphs are not used while profiling is on.  The results are the
+ * same either way.  EINVAL for other k.  This build has graph steps switched
+ * off: k > 0 returns DDQMC_ESTATE and the kernels keep launching one by one. */
+int ddqmc_set_graph_steps(ddqmc_t *h, int32_t k);
 int ddqmc_stage_times(ddqmc_t *h, double ms[9], int64_t *steps);
 
 /* ---- device self-checks of the sampling primitives --------------------------

@@ -112,6 +112,10 @@ class _Handle:
     def set_profiling(self, on=True):
         check(lib().ddqmc_set_profiling(self._h, 1 if on else 0), "set_profiling")
 
+    def set_graph_steps(self, k):
+        """Run k steps per HIP graph launch (k even, 0 = one launch per kernel)."""
+        check(lib().ddqmc_set_graph_steps(self._h, int(k)), "set_graph_steps")
+
     def stage_times(self):
         ms = (ctypes.c_double * len(STAGES))()
         steps = ctypes.c_int64()

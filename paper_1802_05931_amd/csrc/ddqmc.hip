@@ -83,6 +83,15 @@ struct ddqmc_t {
   std::vector<std::vector<int64_t>> hseries;
   std::vector<int64_t> hcounts;
 
+  // k-step HIP graphs, one per parity of the list the replay starts from,
+  // captured again whenever a buffer has been reallocated
+  int graph_k = 0;
+  uint64_t buf_gen = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  uint64_t gexec_gen[2] = {~0ull, ~0ull};
+  int gexec_k[2] = {0, 0};
+
   bool profiling = false;
   std::vector<StageEvents> ev;
   double stage_ms[NSTAGE] = {};
@@ -184,6 +193,9 @@ void free_all(ddqmc_t *h) {
                   h->inj_v};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
+  for (int p = 0; p < 2; ++p)
+    if (h->gexec[p]) (void)hipGraphExecDestroy(h->gexec[p]);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   for (auto &e : h->ev)
     for (int i = 0; i <= NSTAGE; ++i) (void)hipEventDestroy(e.e[i]);
   h->ev.clear();
@@ -359,8 +371,7 @@ int download_list(ddqmc_t *h, std::vector<uint64_t> &keys, std::vector<int2> &va
 
 
 template <typename K>
-int launch_step(ddqmc_t *h, int par, StageEvents *ev) {
-  hipStream_t s = h->stream;
+int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
   const K *ak = (const K *)h->mk[par];
   const int2 *av = h->mv[par];
   K *ck = (K *)h->mk[par ^ 1];
@@ -487,6 +498,39 @@ int regrow(ddqmc_t *h, uint64_t need_main, uint64_t need_sp) {
   int rc = alloc_merge(h);
   if (rc != DDQMC_OK) return rc;
   HIPC(hipStreamSynchronize(h->stream));
+  h->buf_gen += 1;  // captured graphs hold the old pointers and grids
+  return DDQMC_OK;
+}
+
+// Capture graph_k steps starting from the list of parity par (kernels only:
+// no memset or copy nodes) on a private stream, and instantiate them.
+int capture_steps(ddqmc_t *h, int par) {
+  if (!h->cap_stream) HIPC(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  HIPC(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  int rc = DDQMC_OK;
+  for (int j = 0; j < h->graph_k && rc == DDQMC_OK; ++j) {
+    const int p = (par + j) & 1;
+    rc = h->k64 ? launch_step<uint64_t>(h, p, nullptr, h->cap_stream)
+                : launch_step<uint32_t>(h, p, nullptr, h->cap_stream);
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+  if (rc != DDQMC_OK || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc != DDQMC_OK ? rc : hip_err(e);
+  }
+  if (h->gexec[par]) {
+    (void)hipGraphExecDestroy(h->gexec[par]);
+    h->gexec[par] = nullptr;
+  }
+  const hipError_t ei = hipGraphInstantiate(&h->gexec[par], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    h->gexec[par] = nullptr;
+    return hip_err(ei);
+  }
+  h->gexec_gen[par] = h->buf_gen;
+  h->gexec_k[par] = h->graph_k;
   return DDQMC_OK;
 }
 
@@ -500,15 +544,32 @@ int run_steps(ddqmc_t *h, int64_t n) {
   }
   for (int i = 0; i < NSTAGE; ++i) h->stage_ms[i] = 0.0;
   h->stage_steps = 0;
+  const bool use_graph = h->graph_k > 0 && !h->profiling;
   int64_t left = n;
   while (left > 0) {
-    const uint32_t chunk = (uint32_t)std::min<int64_t>(left, SERIES_CAP);
+    uint32_t chunk = (uint32_t)std::min<int64_t>(left, SERIES_CAP);
+    uint32_t reps = 0;  // graph replays of graph_k steps
+    if (use_graph && chunk >= (uint32_t)h->graph_k) {
+      reps = chunk / (uint32_t)h->graph_k;
+      chunk = reps * (uint32_t)h->graph_k;
+    }
     k_chunk_begin<<<1, 1, 0, h->stream>>>(h->ctrl);
-    for (uint32_t j = 0; j < chunk; ++j) {
-      const int par = (h->cur + (int)j) & 1;
-      StageEvents *ev = h->profiling ? &h->ev[j] : nullptr;
-      const int rc = h->k64 ? launch_step<uint64_t>(h, par, ev) : launch_step<uint32_t>(h, par, ev);
-      if (rc != DDQMC_OK) return rc;
+    if (reps) {
+      // graph_k is even: every replay starts from the list of parity h->cur
+      const int par = h->cur;
+      if (h->gexec_gen[par] != h->buf_gen || h->gexec_k[par] != h->graph_k) {
+        const int rc = capture_steps(h, par);
+        if (rc != DDQMC_OK) return rc;
+      }
+      for (uint32_t r = 0; r < reps; ++r) HIPC(hipGraphLaunch(h->gexec[par], h->stream));
+    } else {
+      for (uint32_t j = 0; j < chunk; ++j) {
+        const int par = (h->cur + (int)j) & 1;
+        StageEvents *ev = h->profiling ? &h->ev[j] : nullptr;
+        const int rc = h->k64 ? launch_step<uint64_t>(h, par, ev, h->stream)
+                              : launch_step<uint32_t>(h, par, ev, h->stream);
+        if (rc != DDQMC_OK) return rc;
+      }
     }
     Ctrl c;
     HIPC(hipMemcpyAsync(&c, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
@@ -1002,6 +1063,16 @@ int ddqmc_workspace_query(const ddqmc_params *p, int64_t capacity, size_t *bytes
 int ddqmc_set_profiling(ddqmc_t *h, int32_t on) {
   if (!h) return DDQMC_EINVAL;
   h->profiling = on != 0;
+  return DDQMC_OK;
+}
+
+int ddqmc_set_graph_steps(ddqmc_t *h, int32_t k) {
+  if (!h || k < 0 || (k > 0 && (k < 2 || (k & 1) || k > (int32_t)SERIES_CAP)))
+    return DDQMC_EINVAL;
+  // Switched off: the radix sort passes are cooperative launches, and graph
+  // replays have not been validated on the device.
+  if (k > 0) return DDQMC_ESTATE;
+  h->graph_k = k;
   return DDQMC_OK;
 }
 

@@ -125,58 +125,35 @@ __device__ __forceinline__ uint64_t lb_load(uint64_t *p) {
 }
 
 // Exclusive prefix of tile t from tiles t-1, t-2, ... (word i of tile j at
-// base[j * stride]).  Waits only on tiles taken earlier from the ticket counter,
-// which are running or done, so the wait ends.
+// base[j * stride]).  The words of LB_WIN predecessors are fetched together,
+// so a run of aggregates costs one round trip per LB_WIN tiles.  Waits only on
+// tiles held by running blocks (the grid is co-resident), so the wait ends.
+constexpr int LB_WIN = 8;
 __device__ uint32_t look_back(uint64_t *base, size_t stride, uint32_t t, uint32_t epoch) {
   uint32_t excl = 0;
   int64_t j = (int64_t)t - 1;
   const uint64_t ep = (uint64_t)(epoch & 0x3fffffffu);
   while (j >= 0) {
-    const uint64_t w = lb_load(base + (size_t)j * stride);
-    const uint32_t flag = (uint32_t)(w >> 32) & 3u;
-    if ((w >> 34) != ep || flag == 0) {
-      __builtin_amdgcn_s_sleep(1);
-      continue;
-    }
-    excl += (uint32_t)w;
-    if (flag == 2) break;
-    --j;
-  }
-  return excl;
-}
-
-// The same for one full wave: lane i reads tile t-1-i of a window of 64 tiles,
-// so a run of aggregates costs one round trip per 64 tiles.  All 64 lanes must
-// call it; every lane returns the prefix.
-__device__ uint32_t look_back_wave(uint64_t *base, uint32_t t, uint32_t epoch) {
-  const int lane = threadIdx.x & 63;
-  const uint64_t ep = (uint64_t)(epoch & 0x3fffffffu);
-  uint32_t excl = 0;
-  int64_t top = (int64_t)t - 1;  // the window is tiles top, top-1, ..., top-63
-  while (top >= 0) {
-    const int64_t j = top - lane;
-    uint64_t w = 0;
-    bool ready = true;
-    if (j >= 0) {
-      w = lb_load(base + j);
-      ready = ((w >> 34) == ep) && (((uint32_t)(w >> 32) & 3u) != 0);
-    }
-    // wait until every word of the window up to the nearest prefix is ready
-    const uint64_t is_prefix = __ballot(j >= 0 && ready && (((uint32_t)(w >> 32) & 3u) == 2u));
-    const int stop = is_prefix ? __builtin_ctzll(is_prefix) : 64;  // nearest prefix lane
-    const uint64_t not_ready = __ballot(!ready);
-    const uint64_t need = stop >= 63 ? ~0ull : ((2ull << stop) - 1ull);
-    if (not_ready & need) {
-      __builtin_amdgcn_s_sleep(1);
-      continue;
-    }
-    const uint32_t v = (j >= 0 && lane <= stop) ? (uint32_t)w : 0u;
-    uint32_t s = v;
+    uint64_t w[LB_WIN];
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
-    excl += s;
-    if (stop < 64) break;
-    top -= 64;
+    for (int q = 0; q < LB_WIN; ++q) w[q] = (j - q >= 0) ? lb_load(base + (size_t)(j - q) * stride) : 0;
+    int used = 0;
+    bool done = false, stalled = false;
+#pragma unroll
+    for (int q = 0; q < LB_WIN; ++q) {
+      if (done || stalled || j - q < 0) continue;
+      const uint32_t flag = (uint32_t)(w[q] >> 32) & 3u;
+      if ((w[q] >> 34) != ep || flag == 0) {
+        stalled = true;  // not published yet: fetch again from here
+        continue;
+      }
+      excl += (uint32_t)w[q];
+      ++used;
+      if (flag == 2) done = true;
+    }
+    if (done) break;
+    j -= used;
+    if (stalled) __builtin_amdgcn_s_sleep(1);
   }
   return excl;
 }

@@ -192,6 +192,70 @@ def test_pool_admit_retire_equals_alone(dq, orc):
     pool.close()
 
 
+GRAPHS_OFF = ("graph steps are switched off: a device run with them faulted and its cause "
+              "is not yet shown")
+
+
+@pytest.mark.skip(reason=GRAPHS_OFF)
+def test_graph_steps_equal_eager(dq, orc):
+    """k-step HIP graphs (replayed several times per call, re-captured after
+    the buffers grow from a tiny capacity) give the eager launches' lists, which
+    the oracle checks too."""
+    cfg = dict(workloads.d2(0.6), target_walkers=20000, capacity_hint=16, n_equil=60)
+    a = dq.Solve(dq.make_params(**cfg))
+    b = dq.Solve(dq.make_params(**cfg))
+    b.set_graph_steps(10)
+    o = orc.Oracle(**{k: v for k, v in cfg.items() if k != "capacity_hint"})
+    for per in (35, 35, 120, 7, 64):
+        a.step(per)
+        b.step(per)
+        o.step(per)
+        assert _same_list(a.walkers(), b.walkers())
+        assert _same_list(b.walkers(), o.get_list())
+        assert a.scalars() == b.scalars() == o.scalars()
+        print(f"  graph steps: {o.scalars()['step']} steps, {len(o.get_list()[0])} entries ok",
+              flush=True)
+    assert np.array_equal(b.series(), o.series())
+    b.set_graph_steps(0)
+    a.step(20)
+    b.step(20)
+    assert _same_list(a.walkers(), b.walkers())
+    a.close()
+    b.close()
+
+
+@pytest.mark.skip(reason=GRAPHS_OFF)
+def test_graph_steps_batch_equals_alone(dq, orc):
+    cfgs = [dict(workloads.D1, solve_id=0, n_equil=40),
+            dict(workloads.d2(0.9), solve_id=1, target_walkers=3000, n_equil=40),
+            dict(workloads.D1, solve_id=2, seed=3, n_equil=40)]
+    b = dq.Batch([dq.make_params(**c) for c in cfgs])
+    b.set_graph_steps(16)
+    orcs = [orc.Oracle(**c) for c in cfgs]
+    for per in (48, 100):
+        b.step(per)
+        for i, o in enumerate(orcs):
+            o.step(per)
+            assert _same_list(b.walkers(i), o.get_list()), i
+            assert b.scalars(i) == o.scalars(), i
+    b.close()
+
+
+def test_graph_steps_invalid(dq):
+    from paper_1802_05931_amd import DDQMCError
+    g = dq.Solve(dq.make_params(**workloads.D1))
+    for k in (-2, 1, 3, 2048):
+        with pytest.raises(DDQMCError) as e:
+            g.set_graph_steps(k)
+        assert e.value.code == -1
+    with pytest.raises(DDQMCError) as e:  # switched off in this build
+        g.set_graph_steps(10)
+    assert e.value.code == -7
+    g.set_graph_steps(0)
+    g.step(3)
+    g.close()
+
+
 def test_int32_overflow_reports_and_keeps_state(dq):
     from paper_1802_05931_amd import DDQMCError
     g = dq.Solve(dq.make_params(Lx=2, Ly=2, dt=0.5, shift_init=-3.0, target_walkers=2 ** 62,
