@@ -146,14 +146,15 @@ def bench_d5(args):
     import numpy as np
     import torch
     from paper_1802_05931_amd import serving
-    steps = args.steps if args.steps != 1000 else 2000
+    steps = args.steps if args.steps != 1000 else 300
     cfgs = workloads.d5_replicas()
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     print(f"d5: batched, {len(cfgs)} replicas x {steps} steps", file=sys.stderr, flush=True)
     tb, ob, lb = serving.replicas_batched(cfgs, steps, stream=stream)
     print(f"d5: batched {tb:.2f} s; sequential", file=sys.stderr, flush=True)
-    ts, os_, ls = serving.replicas_sequential(cfgs, steps, stream=stream)
+    ts, os_, ls = serving.replicas_sequential(
+        cfgs, steps, stream=stream, log=lambda m: print(f"d5: {m}", file=sys.stderr, flush=True))
     print(f"d5: sequential {ts:.2f} s", file=sys.stderr, flush=True)
     same = all(len(a[0]) == len(c[0]) and all(np.array_equal(x, y) for x, y in zip(a, c))
                for a, c in zip(lb, ls))
@@ -168,7 +169,8 @@ def bench_d5(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "i32 walkers, f64 probabilities", "data": "synthetic",
         "config": {"workload": "64 replicas of the 5x5 dissipative XYZ model, Jx 0.5..1.2, "
-                               "dt 0.002, n_a 3, targets log-uniform in [1e5, 2e6], u64 keys",
+                               "dt 0.002, n_a 3, p 0, targets log-uniform in [1e3, 2e4], "
+                               "u64 keys",
                    "graph_steps": 0, "final_entries": entries},
         "sequential": {"seconds": ts, "value": len(cfgs) * (steps - 1) / ts},
         "batched_seconds": tb,
@@ -201,11 +203,14 @@ def bench_d4(args):
     lat = np.array([r["finished"] - r["arrival"] for r in recs])
     steps = np.array([r["steps"] for r in recs])
     conv = np.array([r["converged"] for r in recs])
+    over = np.array([r["over_limit"] for r in recs])
     print(f"d4: served {len(recs)} in {wall:.1f} s; timing every {args.baseline_every}-th alone",
           file=sys.stderr, flush=True)
     alone = []
     for i in range(0, len(reqs), args.baseline_every):
         dt, obs = serving.solve_alone(reqs[i]["params"], int(steps[i]), stream=stream)
+        print(f"d4: request {i} alone: {dt:.2f} s for {steps[i]} steps", file=sys.stderr,
+              flush=True)
         assert obs["step"] == steps[i]
         assert abs(obs["mz"] - recs[i]["mz"]) == 0.0 or (np.isnan(obs["mz"]) and
                                                         np.isnan(recs[i]["mz"]))
@@ -222,13 +227,15 @@ def bench_d4(args):
         "dtype": "i32 walkers, f64 probabilities", "data": "synthetic",
         "config": {"workload": f"{len(reqs)} requests, lattices uniform over 2x2/3x3/4x4/2x6, "
                                "Jx U[0.5,1.2], Jz U[0.8,1.2], gamma U[0.5,2], dt 0.005, n_a 3, "
-                               "targets log-uniform [1e3,1e6], Poisson arrivals 20/s",
-                   "slots": 64, "tick_steps": 50, "stop": "SE(M_z) < 1e-3 after >= 512 "
-                   "accumulated steps, or 4000 steps"},
+                               "targets log-uniform [1e3,1e5], Poisson arrivals 20/s",
+                   "slots": 64, "tick_steps": 50, "admission": "pool list below 6e7 entries",
+                   "stop": "SE(M_z) < 1e-3 after >= 512 accumulated steps, 2000 steps, or "
+                           "more than 4e6 entries"},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                       "max": float(lat.max())},
         "wall_s": wall, "last_arrival_s": last_arrival, "ticks": ticks,
-        "converged": int(conv.sum()), "steps_per_solve_median": float(np.median(steps)),
+        "converged": int(conv.sum()), "over_memory_limit": int(over.sum()),
+        "steps_per_solve_median": float(np.median(steps)),
         "one_at_a_time": {"seconds_estimated": alone_total,
                           "sample": f"every {args.baseline_every}-th request alone "
                                     f"({len(alone)} solves, scaled by {args.baseline_every})",

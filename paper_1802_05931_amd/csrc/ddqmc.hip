@@ -24,7 +24,9 @@ using namespace ddqmc;
 namespace {
 
 constexpr uint32_t SERIES_CAP = 1024;  // steps per chunk between host synchronisations
-constexpr uint64_t MAX_CAP = 0xF0000000ull;
+// Largest list or spawn buffer, in entries: list + records stay below 2^32, so
+// every 32-bit count and index in the kernels is exact.
+constexpr uint64_t MAX_CAP = 0x7FF00000ull;
 constexpr int NSTAGE = 9;  // scan, loud, heavy, seal, histogram, sort, count, merge, finalize
 
 struct StageEvents {
@@ -114,6 +116,17 @@ int hip_err(hipError_t e) {
   } while (0)
 
 size_t key_size(const ddqmc_t *h) { return h->k64 ? 8 : 4; }
+
+// Growth that would leave less than a reserve of device memory free is refused
+// (DDQMC_ENOMEM): the runtime needs headroom for kernel scratch and queues, and
+// a list that outgrows the device ends as an error, not a fault.
+int check_room(size_t bytes) {
+  size_t free_b = 0, total_b = 0;
+  HIPC(hipMemGetInfo(&free_b, &total_b));
+  const size_t reserve = std::max<size_t>((size_t)4 << 30, total_b / 32);
+  if (bytes + reserve > free_b) return DDQMC_ENOMEM;
+  return DDQMC_OK;
+}
 
 uint64_t sort_tiles(uint64_t cap) { return (cap + SORT_TILE - 1) / SORT_TILE; }
 uint64_t merge_tiles(uint64_t a, uint64_t b) { return (a + b + MERGE_TILE - 1) / MERGE_TILE; }
@@ -289,6 +302,10 @@ int build(ddqmc_t *h, int nslots, int Nmax, uint64_t cap, void *stream) {
   cap = std::max<uint64_t>(cap, 4096);
   cap = std::min<uint64_t>(cap, MAX_CAP);
   int rc;
+  const size_t ks = key_size(h);
+  if ((rc = check_room(list_bytes(ks, cap) + spawn_bytes(ks, std::max<uint64_t>(4096, cap / 4)) +
+                       cap * (4 * sizeof(uint32_t) + ks + sizeof(int2)))) != DDQMC_OK)
+    return rc;
   if ((rc = alloc_list(h, cap)) != DDQMC_OK) return rc;
   if ((rc = alloc_spawn(h, std::max<uint64_t>(4096, cap / 4))) != DDQMC_OK) return rc;
   if ((rc = alloc_merge(h)) != DDQMC_OK) return rc;
@@ -453,6 +470,10 @@ int regrow(ddqmc_t *h, uint64_t need_main, uint64_t need_sp) {
   if (need_main > h->cap_main) {
     const uint64_t cap = std::min<uint64_t>(MAX_CAP, need_main + need_main / 2 + 4096);
     if (cap < need_main) return DDQMC_ECAPACITY;
+    // new lists (the old ones are freed after the copy) and the larger loud arrays
+    const int room = check_room(2 * cap * (ks + sizeof(int2)) +
+                                (cap - h->cap_main) * (4 * sizeof(uint32_t) + ks + sizeof(int2)));
+    if (room != DDQMC_OK) return room;
     void *nk[2];
     int2 *nv[2];
     for (int b = 0; b < 2; ++b) {
@@ -478,6 +499,8 @@ int regrow(ddqmc_t *h, uint64_t need_main, uint64_t need_sp) {
   if (need_sp > h->cap_sp) {
     const uint64_t cap = std::min<uint64_t>(MAX_CAP, need_sp + need_sp / 2 + 4096);
     if (cap < need_sp) return DDQMC_ECAPACITY;
+    const int room = check_room(spawn_bytes(ks, cap) - spawn_bytes(ks, h->cap_sp));
+    if (room != DDQMC_OK) return room;
     for (int b = 0; b < 2; ++b) {
       HIPC(hipFree(h->sk[b]));
       HIPC(hipFree(h->sv[b]));
@@ -609,7 +632,7 @@ int run_steps(ddqmc_t *h, int64_t n) {
     }
     if (c.abort) {
       const uint32_t f = c.fail_flags;
-      const uint32_t need_sp = c.seg_need * (uint32_t)NSEG, need_main = c.n_new;
+      const uint64_t need_sp = (uint64_t)c.seg_need * NSEG, need_main = c.n_new;
       k_rearm<<<1, 256, 0, h->stream>>>(h->ctrl, h->hist, MAX_PASSES, h->spill,
                                          h->nslots * S_NSUM, h->segcnt);
       HIPC(hipGetLastError());

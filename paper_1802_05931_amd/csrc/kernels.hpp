@@ -660,8 +660,8 @@ __global__ void k_inject(const K *__restrict__ ik, const int2 *__restrict__ iv, 
       ov[base + q] = iv[q];
     }
   }
-  __syncthreads();
-  if (threadIdx.x == 0) ctrl->n_inject = 0;
+  // n_inject is cleared when the step commits (k_finalize): a step that fails
+  // and is run again after the buffers grow injects the same records again
 }
 
 // Segment offsets and the record count (one wave).
@@ -1258,6 +1258,7 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctrl *ctrl, const SlotParams 
     ctrl->n_main = n_new;
     ctrl->last_spawn = ctrl->n_spawn;
     ctrl->n_spawn = 0;
+    ctrl->n_inject = 0;
     ctrl->n_heavy = 0;
     ctrl->epoch += 1;
     ctrl->committed += 1;

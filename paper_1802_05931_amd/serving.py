@@ -6,12 +6,13 @@ all solves of the handle); this module only decides
 which solve sits in which slot and when a solve is done.
 
 Serving loop (``serve``): requests arrive over time; a request is admitted into
-a free slot of a ``Pool`` when the walkers of the solves in the pool, plus its
-own target, stay within a walker budget (the list footprint grows with the
-walker count); the pool advances in ticks of ``tick`` steps; after each tick a
+a free slot of a ``Pool`` while the pool's list (all solves' occupied entries,
+which sets its device-memory footprint) is below an entry budget; the pool
+advances in ticks of ``tick`` steps; after each tick a
 solve whose magnetisation M_z has a standard error below ``se_target`` (with
-at least ``min_accum`` accumulated steps after its equilibration) or that has
-run ``max_steps`` steps leaves its slot.  The standard error is the library's
+at least ``min_accum`` accumulated steps after its equilibration), that has run
+``max_steps`` steps, or whose list has grown past ``max_entries`` (a per-request
+memory limit) leaves its slot.  The standard error is the library's
 blocking / delta-method error of the ratio estimator (Sec. III.A, V.A).
 """
 import time
@@ -20,17 +21,20 @@ from collections import deque
 import numpy as np
 
 from . import Batch, Pool, Solve, make_params
+from ._lib import ESTATE, DDQMCError
 
 
-def _done(obs, params, se_target, min_accum, max_steps):
-    """(finished, converged) for a solve with observables obs."""
+def _done(obs, se_target, min_accum, max_steps, max_entries):
+    """(finished, converged, over the memory limit) for a solve with observables obs."""
     converged = (obs["n_accum"] >= min_accum and np.isfinite(obs["se_mz"])
                  and obs["se_mz"] < se_target)
-    return converged or obs["step"] >= max_steps, converged
+    over = obs["last"]["n_entries"] > max_entries
+    return converged or over or obs["step"] >= max_steps, converged, over
 
 
-def serve(requests, slots=64, max_sites=16, walker_budget=40_000_000, tick=50,
-          se_target=1e-3, min_accum=512, max_steps=4000, graph_k=0, stream=None, log=None):
+def serve(requests, slots=64, max_sites=16, entry_budget=60_000_000, tick=50,
+          se_target=1e-3, min_accum=512, max_steps=2000, max_entries=4_000_000, graph_k=0,
+          stream=None, log=None):
     """Run the request stream through one pool.
 
     requests: list of dicts with "arrival" (seconds from the start) and "params"
@@ -44,7 +48,6 @@ def serve(requests, slots=64, max_sites=16, walker_budget=40_000_000, tick=50,
     if graph_k:
         pool.set_graph_steps(graph_k)
     active = {}  # slot -> request index
-    walkers = 0
     out = [None] * len(requests)
     t0 = time.perf_counter()
     ticks = 0
@@ -53,15 +56,17 @@ def serve(requests, slots=64, max_sites=16, walker_budget=40_000_000, tick=50,
         while pending and requests[pending[0]]["arrival"] <= now:
             queue.append(pending.popleft())
         # admission by footprint, in arrival order
-        while queue and len(active) < slots:
+        entries = pool.list_size() if active else 0
+        while queue and len(active) < slots and entries < entry_budget:
             i = queue[0]
-            tw = requests[i]["params"]["target_walkers"]
-            if active and walkers + tw > walker_budget:
-                break
+            try:
+                s = pool.admit(make_params(**requests[i]["params"]))
+            except DDQMCError as e:
+                if e.code != ESTATE:
+                    raise
+                break  # every free slot is still being vacated: after the next tick
             queue.popleft()
-            s = pool.admit(make_params(**requests[i]["params"]))
             active[s] = i
-            walkers += tw
             out[i] = dict(arrival=requests[i]["arrival"], admitted=now)
         if not active:
             if pending:  # idle until the next arrival
@@ -72,18 +77,18 @@ def serve(requests, slots=64, max_sites=16, walker_budget=40_000_000, tick=50,
         now = time.perf_counter() - t0
         for s in list(active):
             i = active[s]
-            p = requests[i]["params"]
             obs = pool.observables(s)
-            fin, conv = _done(obs, p, se_target, min_accum, max_steps)
+            fin, conv, over = _done(obs, se_target, min_accum, max_steps, max_entries)
             if fin:
                 pool.retire(s)
                 del active[s]
-                walkers -= p["target_walkers"]
                 out[i].update(finished=now, steps=int(obs["step"]), converged=bool(conv),
+                              over_limit=bool(over), entries=int(obs["last"]["n_entries"]),
                               mz=float(obs["mz"]), se_mz=float(obs["se_mz"]))
                 if log:
-                    log(f"request {i} done at {now:.2f}s after {obs['step']} steps "
-                        f"(converged={conv}, {len(active)} active, {len(queue)} queued)")
+                    log(f"request {i} done at {now:.2f}s after {obs['step']} steps, "
+                        f"{obs['last']['n_entries']} entries (converged={conv}, over={over}, "
+                        f"{len(active)} active, {len(queue)} queued)")
     pool.close()
     return out, ticks
 
@@ -124,11 +129,11 @@ def replicas_batched(cfgs, steps, graph_k=0, stream=None):
     return dt, obs, lists
 
 
-def replicas_sequential(cfgs, steps, graph_k=0, stream=None, keep_lists=True):
+def replicas_sequential(cfgs, steps, graph_k=0, stream=None, keep_lists=True, log=None):
     """The same replicas one after another, each on its own handle."""
     total = 0.0
     obs, lists = [], []
-    for c in cfgs:
+    for r, c in enumerate(cfgs):
         g = Solve(make_params(**c), stream=stream)
         if graph_k:
             g.set_graph_steps(graph_k)
@@ -141,4 +146,6 @@ def replicas_sequential(cfgs, steps, graph_k=0, stream=None, keep_lists=True):
         if keep_lists:
             lists.append(g.walkers())
         g.close()
+        if log:
+            log(f"replica {r} alone: {total:.2f} s so far")
     return total, obs, lists

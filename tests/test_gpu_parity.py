@@ -256,6 +256,62 @@ def test_graph_steps_invalid(dq):
     g.close()
 
 
+def _churn_requests():
+    rng = np.random.default_rng(7)
+    lat = [(2, 2), (3, 3), (2, 6), (4, 4)]
+    reqs = []
+    for i in range(14):
+        Lx, Ly = lat[i % 4]
+        reqs.append(dict(params=dict(Lx=Lx, Ly=Ly, Jx=float(rng.uniform(0.6, 1.1)), Jy=1.0,
+                                     Jz=float(rng.uniform(0.8, 1.2)),
+                                     gamma=float(rng.uniform(1.2, 2.0)), dt=0.005, n_a=3,
+                                     target_walkers=int(rng.integers(300, 3000)),
+                                     initial_walkers=int(rng.integers(300, 3000)),
+                                     shift_init=0.0, seed=11, solve_id=100 + i, n_equil=30),
+                         steps=int(rng.integers(2, 9)) * 25))
+    return reqs
+
+
+@pytest.mark.parametrize("cap", [0, 16])
+def test_pool_churn_equals_alone(dq, cap):
+    """Continuous batching with churn: solves of four lattice shapes enter and
+    leave a 5-slot pool between ticks (several admissions in one tick, slots
+    reused, the buffers grown during entering steps when the capacity starts
+    tiny); each solve's list when it leaves equals the same solve run alone."""
+    from paper_1802_05931_amd import DDQMCError
+    reqs = _churn_requests()
+    pool = dq.Pool(slots=5, max_sites=16, capacity_hint=cap)
+    queue = list(range(len(reqs)))
+    active, done = {}, {}
+    ticks = 0
+    while queue or active:
+        while queue:
+            try:
+                s = pool.admit(dq.make_params(**reqs[queue[0]]["params"]))
+            except DDQMCError as e:
+                assert e.code == -7
+                break
+            active[s] = queue.pop(0)
+        pool.step(25)
+        ticks += 1
+        for s in list(active):
+            i = active[s]
+            st = pool.scalars(s)["step"]
+            if st >= reqs[i]["steps"]:
+                done[i] = (st, pool.walkers(s), pool.scalars(s))
+                pool.retire(s)
+                del active[s]
+        assert ticks < 200
+    pool.close()
+    print(f"  churn: {len(done)} solves served in {ticks} ticks", flush=True)
+    for i, (st, lst, sc) in done.items():
+        g = dq.Solve(dq.make_params(**reqs[i]["params"]))
+        g.step(st)
+        assert _same_list(g.walkers(), lst), i
+        assert g.scalars() == sc, i
+        g.close()
+
+
 def test_int32_overflow_reports_and_keeps_state(dq):
     from paper_1802_05931_amd import DDQMCError
     g = dq.Solve(dq.make_params(Lx=2, Ly=2, dt=0.5, shift_init=-3.0, target_walkers=2 ** 62,

@@ -34,34 +34,41 @@ D3 = dict(Lx=4, Ly=4, Jx=0.9, Jy=1.0, Jz=1.0, gamma=1.0, dt=0.002, n_a=3,
 D3_STEPS = 5000
 
 
-def d5_replicas(count=64):
+def d5_replicas(count=64, t_lo=1e3, t_hi=2e4):
     """64 independent 5x5 replicas, Jx spread evenly over [0.5, 1.2], targets
-    log-uniform in [1e5, 2e6] from default_rng(5)."""
+    log-uniform in [t_lo, t_hi] from default_rng(5).  Under population control
+    of the diagonal weight alone, the off-diagonal population of a 5x5 replica
+    keeps growing (the oracle: about x1.6 per 100 steps at target 2e3, x2.4 at
+    target 2e4, p = 0, Jx = 0.5), so targets of 1e5-2e6 would outgrow the device
+    within a few hundred steps; the default range is that one divided by 100."""
     rng = np.random.default_rng(5)
-    targets = np.exp(rng.uniform(np.log(1e5), np.log(2e6), count)).astype(np.int64)
+    targets = np.exp(rng.uniform(np.log(t_lo), np.log(t_hi), count)).astype(np.int64)
     out = []
     for r in range(count):
         out.append(dict(Lx=5, Ly=5, Jx=0.5 + 0.7 * r / max(count - 1, 1), Jy=1.0, Jz=1.0,
                         gamma=1.0, dt=0.002, n_a=3, target_walkers=int(targets[r]),
                         initial_walkers=int(targets[r]), is_p=0.0, shift_damping=0.05,
-                        shift_init=0.0, seed=0, solve_id=r, n_equil=500))
+                        shift_init=0.0, seed=0, solve_id=r, n_equil=100))
     return out
 
 
 D4_LATTICES = ((2, 2), (3, 3), (4, 4), (2, 6))
 
 
-def d4_requests(count=512, rate=20.0, seed=20181802):
+def d4_requests(count=512, rate=20.0, seed=20181802, t_lo=1e3, t_hi=1e5):
     """Serving stream: Poisson arrivals at ``rate`` per second, lattices uniform over
     2x2/3x3/4x4/2x6, Jx ~ U[0.5,1.2], Jz ~ U[0.8,1.2], gamma ~ U[0.5,2], dt 0.005,
-    target walkers log-uniform in [1e3, 1e6]."""
+    target walkers log-uniform in [t_lo, t_hi].  At small gamma a 4x4 or 2x6 list
+    holds far more entries than its diagonal target (the oracle: 1.2e7 entries
+    after 250 steps for target 1e5 at gamma 0.5), so the default upper target is
+    1e5 rather than 1e6."""
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate, count)
     t = np.cumsum(gaps) - gaps[0]
     out = []
     for i in range(count):
         Lx, Ly = D4_LATTICES[rng.integers(0, len(D4_LATTICES))]
-        target = int(np.exp(rng.uniform(np.log(1e3), np.log(1e6))))
+        target = int(np.exp(rng.uniform(np.log(t_lo), np.log(t_hi))))
         out.append(dict(arrival=float(t[i]),
                         params=dict(Lx=int(Lx), Ly=int(Ly), Jx=float(rng.uniform(0.5, 1.2)),
                                     Jy=1.0, Jz=float(rng.uniform(0.8, 1.2)),
