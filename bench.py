@@ -34,6 +34,7 @@ sys.path.insert(0, ROOT)
 import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+VALU_PEAK_G = 256 * 4 * 2.4 / 4  # G wave64 VALU instructions/s: 256 CUs x 4 SIMDs, 4 cycles each
 KEY_BYTES = {True: 8, False: 4}
 
 WORKLOADS = {
@@ -67,6 +68,19 @@ def traffic_from_profile(kernel, workload, per_launch_alg):
     if d.get("source_hash") != kernel_source_hash():
         return None
     return d.get("bytes_per_launch")
+
+
+def valu_from_profile(kernel, workload):
+    """VALU wave-instructions per launch from the committed counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_valu.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return d.get("valu_per_launch")
 
 
 def cpu_baseline(cfg, keys, re, im, sc, budget_s=15.0):
@@ -129,6 +143,79 @@ def trace_summary(directory, steps):
         out.append(f"| {name} | {n} | {n / steps:g} | {tot / n:.2f} | {mn:.2f} | {mx:.2f} | "
                    f"{tot / steps:.2f} |")
     print("\n".join(out))
+
+
+def counter_summary(fetch_dir, write_dir, probe_mb, workload, valu_dir=None):
+    """Mean FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the step kernels from two
+    rocprofv3 --pmc runs, scaled by what the same counters read for the probe
+    kernel of known traffic (an elementwise add over probe_mb MiB: reads and
+    writes probe_mb MiB).  Prints a markdown table and, for the merge kernels,
+    the traffic records bench.py reads."""
+    import csv
+    import glob
+    import collections
+
+    def load(d, counter):
+        fn = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        if not fn:
+            raise SystemExit(f"no counter_collection.csv under {d}")
+        vals = collections.defaultdict(list)
+        for r in csv.DictReader(open(fn[0])):
+            if r["Counter_Name"] != counter:
+                continue
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "").replace("ddqmc::", "")
+            vals[name].append(float(r["Counter_Value"]))
+        return vals
+    fetch, write = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    # the probe is the elementwise kernel that reads (the fill before it only writes)
+    probe = [k for k in fetch if "elementwise" in k]
+    if not probe:
+        raise SystemExit("probe kernel not found in the counters")
+    probe = [max(probe, key=lambda k: max(fetch[k]))]
+    kib = probe_mb * 1024.0
+    f_scale = kib / max(fetch[probe[0]])
+    w_scale = kib / max(write[probe[0]])
+    out = [f"FETCH_SIZE / WRITE_SIZE per dispatch; the probe (elementwise add over {probe_mb} MiB) "
+           f"read {max(fetch[probe[0]]):.0f} KiB and wrote {max(write[probe[0]]):.0f} KiB, so the "
+           f"scale factors are {f_scale:.4f} (fetch) and {w_scale:.4f} (write)", "",
+           "| kernel | dispatches | fetch MB | write MB | HBM MB (scaled) |",
+           "|---|---:|---:|---:|---:|"]
+    rec = {}
+    for name in sorted(fetch):
+        if "elementwise" in name or name.startswith("__amd"):
+            continue
+        fm = sum(fetch[name]) / len(fetch[name]) * 1024 / 1e6
+        wm = (sum(write[name]) / len(write[name]) * 1024 / 1e6) if name in write else 0.0
+        tot = fm * f_scale + wm * w_scale
+        out.append(f"| {name} | {len(fetch[name])} | {fm:.2f} | {wm:.2f} | {tot:.2f} |")
+        rec[name] = tot * 1e6
+    print("\n".join(out))
+    for short, name in (("k_merge_write", "k_merge<unsigned int, true>"),
+                        ("k_merge_count", "k_merge<unsigned int, false>"),
+                        ("k_sort_pass", "k_sort_pass<unsigned int>"),
+                        ("k_spawn_scan", "k_spawn_scan<unsigned int>")):
+        if name in rec:
+            path = os.path.join(ROOT, "profiles", f"{short}_{workload}_traffic.json")
+            with open(path, "w") as f:
+                json.dump({"bytes_per_launch": rec[name], "source_hash": kernel_source_hash(),
+                           "fetch_scale": f_scale, "write_scale": w_scale}, f, indent=1)
+            print(f"wrote {path}")
+    if valu_dir:
+        valu, waves = load(valu_dir, "SQ_INSTS_VALU"), load(valu_dir, "SQ_WAVES")
+        print("\n| kernel | dispatches | waves | VALU wave-instructions |\n|---|---:|---:|---:|")
+        for name in sorted(valu):
+            if "elementwise" in name or name.startswith("__amd"):
+                continue
+            v = sum(valu[name]) / len(valu[name])
+            w = sum(waves[name]) / len(waves[name]) if name in waves else 0
+            print(f"| {name} | {len(valu[name])} | {w:.0f} | {v:.0f} |")
+            for short in ("k_spawn_loud", "k_spawn_heavy", "k_spawn_scan"):
+                if name.startswith(short + "<unsigned int>"):
+                    path = os.path.join(ROOT, "profiles", f"{short}_{workload}_valu.json")
+                    with open(path, "w") as f:
+                        json.dump({"valu_per_launch": v, "source_hash": kernel_source_hash()},
+                                  f, indent=1)
+                    print(f"wrote {path}")
 
 
 def _walker_updates(series, steps):
@@ -256,6 +343,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--trace-summary", metavar="DIR")
+    ap.add_argument("--counter-summary", nargs="+", metavar="DIR",
+                    help="FETCH_DIR WRITE_DIR [VALU_DIR]: summarise rocprofv3 --pmc runs")
     ap.add_argument("--save-state", metavar="FILE",
                     help="write the solve's checkpoint after the warm-up")
     ap.add_argument("--load-state", metavar="FILE",
@@ -266,6 +355,11 @@ def main():
     args = ap.parse_args()
     if args.trace_summary:
         trace_summary(args.trace_summary, args.steps)
+        return
+    if args.counter_summary:
+        d = args.counter_summary
+        counter_summary(d[0], d[1], args.copy_probe_mb, args.workload,
+                        d[2] if len(d) > 2 else None)
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the "
@@ -285,10 +379,16 @@ def main():
     cfg, desc = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    g = dq.Solve(dq.make_params(**cfg), stream=stream)
+    blob = None
     if args.load_state:
         with open(args.load_state, "rb") as f:
-            g.set_state(f.read())
+            blob = f.read()
+        # room for the loaded list to grow without a reallocation (16 bytes an entry)
+        cfg = dict(cfg, capacity_hint=2 * (len(blob) // 16))
+    g = dq.Solve(dq.make_params(**cfg), stream=stream)
+    if blob is not None:
+        g.set_state(blob)
+        del blob
         args.warmup = g.scalars()["step"]
         _, re0, im0 = g.walkers()
         w0 = int(np.abs(re0.astype(np.int64)).sum() + np.abs(im0.astype(np.int64)).sum())
@@ -334,16 +434,43 @@ def main():
     launches = {"scan": args.steps, "histogram": args.steps, "sort": args.steps * passes,
                 "count": args.steps, "merge": args.steps}
     kernel_names = {"scan": "k_spawn_scan", "histogram": "k_hist", "sort": "k_sort_pass",
-                    "count": "k_merge<count>", "merge": "k_merge<write>"}
-    dominant = max(alg_bytes, key=lambda k: stage_ms[k])
-    dur_s = stage_ms[dominant] / 1e3 / launches[dominant]
-    per_launch = alg_bytes[dominant] / launches[dominant]
-    achieved = per_launch / dur_s / 1e9
-    traffic = traffic_from_profile(kernel_names[dominant], args.workload, per_launch)
-    roofline = dict(kernel=kernel_names[dominant], bound="hbm", achieved=round(achieved, 1),
-                    peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
-                    traffic=traffic, bytes_per_launch=round(per_launch),
-                    mean_launch_us=round(dur_s * 1e6, 2))
+                    "count": "k_merge_count", "merge": "k_merge_write"}
+    # HBM roofline of the merge (the annihilation join, where the list is
+    # streamed in and out): algorithmic bytes / mean launch time
+    m_dur = stage_ms["merge"] / 1e3 / launches["merge"]
+    m_bytes = alg_bytes["merge"] / launches["merge"]
+    m_ach = m_bytes / m_dur / 1e9
+    hbm_roofline = dict(kernel="k_merge_write", bound="hbm", achieved=round(m_ach, 1),
+                        peak=HBM_PEAK_GBS, unit="GB/s", frac=round(m_ach / HBM_PEAK_GBS, 4),
+                        traffic=traffic_from_profile("k_merge_write", args.workload, m_bytes),
+                        bytes_per_launch=round(m_bytes), mean_launch_us=round(m_dur * 1e6, 2))
+    # the dominant kernel by time
+    dominant = max((k for k in stage_ms if k != "finalize"), key=lambda k: stage_ms[k])
+    if dominant in alg_bytes:
+        dur_s = stage_ms[dominant] / 1e3 / launches[dominant]
+        per_launch = alg_bytes[dominant] / launches[dominant]
+        achieved = per_launch / dur_s / 1e9
+        roofline = dict(kernel=kernel_names[dominant], bound="hbm", achieved=round(achieved, 1),
+                        peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
+                        traffic=traffic_from_profile(kernel_names[dominant], args.workload,
+                                                     per_launch),
+                        bytes_per_launch=round(per_launch), mean_launch_us=round(dur_s * 1e6, 2))
+    else:
+        # a sampling kernel: bound by vector ALU issue, measured as VALU
+        # instructions per launch (committed counter profile) over the live launch
+        # time, against 256 CUs x 4 SIMDs issuing one wave64 instruction per 4
+        # cycles at 2.4 GHz
+        kname = {"loud": "k_spawn_loud", "heavy": "k_spawn_heavy", "gather": "k_loud_gather"}.get(
+            dominant, dominant)
+        dur_s = stage_ms[dominant] / 1e3 / args.steps
+        valu = valu_from_profile(kname, args.workload)
+        achieved = valu / dur_s / 1e9 if valu else None
+        roofline = dict(kernel=kname, bound="alu", achieved=(round(achieved, 1) if achieved
+                                                              else None),
+                        peak=VALU_PEAK_G, unit="G VALU wave-instructions/s",
+                        frac=(round(achieved / VALU_PEAK_G, 4) if achieved else None),
+                        traffic=traffic_from_profile(kname, args.workload, 0),
+                        valu_instructions_per_launch=valu, mean_launch_us=round(dur_s * 1e6, 2))
     stages = {k: dict(ms_per_step=round(v / args.steps, 5),
                       achieved_GBs=(round(alg_bytes[k] / (v / 1e3) / 1e9, 1)
                                     if k in alg_bytes and v > 0 else None))
@@ -370,6 +497,7 @@ def main():
                    "mean_spawn_records": float(n_sp.mean())},
         "entry_updates_per_s": float(n_in.sum()) / wall,
         "roofline": roofline,
+        "hbm_roofline": hbm_roofline,
         "stages": stages,
         "shift": sc["S"],
         "mz_running": obs["mz"],
@@ -378,8 +506,8 @@ def main():
     if args.copy_probe_mb:
         src = torch.ones(args.copy_probe_mb << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
+        for _ in range(3):  # reads and writes copy_probe_mb MiB each
+            torch.add(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
     if not args.no_cpu:

@@ -172,10 +172,11 @@ int ddqmc_workspace_query(const ddqmc_params *p, int64_t capacity, size_t *bytes
 
 /* Wall time of the kernels of the last ddqmc_step call, per stage, from HIP
  * events on the handle's stream when profiling is on (ddqmc_set_profiling);
- * ms[9] = quiet scan, loud spawn, heavy spawn, record seal, histogram, sort
- * (the radix passes and the merge-path partition), merge count (survivors per
- * tile and their offsets), merge (the merge kernel that writes the new list),
- * finalize, summed over the call's steps. */
+ * ms[10] = quiet scan, loud gather (queue offsets and the flat loud list),
+ * loud spawn (the spawn kernel alone), heavy spawn, record seal, histogram,
+ * sort (the radix passes and the merge-path partition), merge count
+ * (survivors per tile and their offsets), merge (the merge kernel that writes
+ * the new list), finalize, summed over the call's steps. */
 int ddqmc_set_profiling(ddqmc_t *h, int32_t on);
 
 /* Launch the kernels of k consecutive steps as one HIP graph (k even,
@@ -186,7 +187,7 @@ int ddqmc_set_profiling(ddqmc_t *h, int32_t on);
  * same either way.  EINVAL for other k.  This build has graph steps switched
  * off: k > 0 returns DDQMC_ESTATE and the kernels keep launching one by one. */
 int ddqmc_set_graph_steps(ddqmc_t *h, int32_t k);
-int ddqmc_stage_times(ddqmc_t *h, double ms[9], int64_t *steps);
+int ddqmc_stage_times(ddqmc_t *h, double ms[10], int64_t *steps);
 
 /* ---- device self-checks of the sampling primitives --------------------------
  * Same streams as the step (Philox4x32-10, key (seed_lo, seed_hi ^ solve),

@@ -13,7 +13,8 @@ import numpy as np
 from ._lib import (DDQMCError, NO_INITIATOR, NSUM, Obs, Params, SERIES_W, SUM_NAMES, check, lib,
                    make_params, ptr)
 
-STAGES = ("scan", "loud", "heavy", "seal", "histogram", "sort", "count", "merge", "finalize")
+STAGES = ("scan", "gather", "loud", "heavy", "seal", "histogram", "sort", "count", "merge",
+          "finalize")
 
 __all__ = ["Solve", "Batch", "Pool", "make_params", "DDQMCError", "NO_INITIATOR", "SUM_NAMES",
            "dev_uniforms", "dev_binom", "dev_math", "workspace_query"]

@@ -27,7 +27,8 @@ constexpr uint32_t SERIES_CAP = 1024;  // steps per chunk between host synchroni
 // Largest list or spawn buffer, in entries: list + records stay below 2^32, so
 // every 32-bit count and index in the kernels is exact.
 constexpr uint64_t MAX_CAP = 0x7FF00000ull;
-constexpr int NSTAGE = 9;  // scan, loud, heavy, seal, histogram, sort, count, merge, finalize
+constexpr int NSTAGE = 10;  // scan, gather, loud, heavy, seal, histogram, sort, count, merge,
+                            // finalize
 
 struct StageEvents {
   hipEvent_t e[NSTAGE + 1];
@@ -408,20 +409,21 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
   k_loud_offsets<<<1, 1024, 0, s>>>(h->ctrl, h->loud_cnt, h->loud_off, h->nscan);
   k_loud_gather<K><<<g_loud, NT, 0, s>>>(ak, av, h->ctrl, h->loud, h->loud_cnt, h->loud_off,
                                          h->nscan, h->lidx, (K *)h->lkey, h->lval);
+  if (ev) HIPC(hipEventRecord(ev->e[2], s));
   k_spawn_loud<K><<<g_loud, NT, 0, s>>>(h->ctrl, h->dsp, h->dss, h->lidx, (const K *)h->lkey,
                                         h->lval, h->loud_off, h->nscan, h->heavy, (K *)h->sk[0],
                                         h->sv[0], h->segcnt, segcap, h->SB);
-  if (ev) HIPC(hipEventRecord(ev->e[2], s));
+  if (ev) HIPC(hipEventRecord(ev->e[3], s));
   k_spawn_heavy<K><<<g_heavy, 64, 0, s>>>(ak, av, h->ctrl, h->dsp, h->dss, h->heavy,
                                           (K *)h->sk[0], h->sv[0], h->segcnt, segcap, h->SB);
-  if (ev) HIPC(hipEventRecord(ev->e[3], s));
+  if (ev) HIPC(hipEventRecord(ev->e[4], s));
   if (h->pool)
     k_inject<K><<<1, NT, 0, s>>>((const K *)h->inj_k, h->inj_v, h->ctrl, (K *)h->sk[0], h->sv[0],
                                  h->segcnt, segcap);
   k_seal<<<1, NSEG, 0, s>>>(h->ctrl, h->segcnt, segcap);
-  if (ev) HIPC(hipEventRecord(ev->e[4], s));
-  k_hist<K><<<g_h, NT, 0, s>>>((const K *)h->sk[0], h->ctrl, h->hist, h->passes, segcap);
   if (ev) HIPC(hipEventRecord(ev->e[5], s));
+  k_hist<K><<<g_h, NT, 0, s>>>((const K *)h->sk[0], h->ctrl, h->hist, h->passes, segcap);
+  if (ev) HIPC(hipEventRecord(ev->e[6], s));
   for (int p = 0; p < h->passes; ++p) {
     const K *ik = (const K *)h->sk[p & 1];
     const int2 *iv = h->sv[p & 1];
@@ -442,7 +444,7 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
     const uint32_t g_p = clampu((merge_tiles(h->cap_main, h->cap_sp) + NT) / NT, 1, 1024);
     k_merge_partition<K><<<g_p, NT, 0, s>>>(ak, (const K *)h->sk[spb], h->ctrl, h->part);
   }
-  if (ev) HIPC(hipEventRecord(ev->e[6], s));
+  if (ev) HIPC(hipEventRecord(ev->e[7], s));
   {
     const int sp = h->passes & 1;
     const K *bk = (const K *)h->sk[sp];
@@ -450,15 +452,15 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
     k_merge<K, false><<<g_m, NT, 0, s>>>(ak, av, bk, bv, ck, cv, capC, h->ctrl, h->dsp, h->dss,
                                          h->partials, h->spill, h->tile_cnt, h->part, h->SB);
     k_merge_offsets<<<1, 1024, 0, s>>>(h->ctrl, h->tile_cnt);
-    if (ev) HIPC(hipEventRecord(ev->e[7], s));
+    if (ev) HIPC(hipEventRecord(ev->e[8], s));
     k_merge<K, true><<<g_m, NT, 0, s>>>(ak, av, bk, bv, ck, cv, capC, h->ctrl, h->dsp, h->dss,
                                         h->partials, h->spill, h->tile_cnt, h->part, h->SB);
   }
-  if (ev) HIPC(hipEventRecord(ev->e[8], s));
+  if (ev) HIPC(hipEventRecord(ev->e[9], s));
   k_finalize<<<1, 1024, 0, s>>>(h->ctrl, h->dsp, h->dss, h->partials, h->spill, h->nslots,
                                 h->hist, h->passes, capC, h->segcnt, h->series, h->counts,
                                 SERIES_CAP);
-  if (ev) HIPC(hipEventRecord(ev->e[9], s));
+  if (ev) HIPC(hipEventRecord(ev->e[10], s));
   HIPC(hipGetLastError());
   return DDQMC_OK;
 }
@@ -1099,7 +1101,7 @@ int ddqmc_set_graph_steps(ddqmc_t *h, int32_t k) {
   return DDQMC_OK;
 }
 
-int ddqmc_stage_times(ddqmc_t *h, double ms[9], int64_t *steps) {
+int ddqmc_stage_times(ddqmc_t *h, double ms[10], int64_t *steps) {
   if (!h || !ms) return DDQMC_EINVAL;
   for (int i = 0; i < NSTAGE; ++i) ms[i] = h->stage_ms[i];
   if (steps) *steps = h->stage_steps;
