@@ -239,20 +239,35 @@ __global__ __launch_bounds__(NT) void k_spawn_scan(const K *__restrict__ keys,
   __syncthreads();
   // the loop bound is wave-uniform so every lane reaches the ballot
   for (uint32_t base = b0 + (threadIdx.x & ~63u); base < b1; base += NT) {
-    const uint32_t i = base + (uint32_t)lane;
+    const uint32_t i = base + (uint32_t)lane;  // lane 0 always holds an entry
+    const bool valid = i < b1;
+    K key = 0;
+    uint32_t slot = 0;
+    if (valid) {
+      key = keys[i];
+      slot = slot_of<K>(key, SB);
+    }
+    auto quiet_test = [&](const SlotParams &P, double S, uint32_t step) {
+      const int2 v = vals[i];
+      const uint64_t cfg = (uint64_t)(key & lowm);
+      const uint32_t N = P.N;
+      const uint32_t l = (uint32_t)(cfg >> N);
+      const uint32_t m = (uint32_t)(cfg & ((N == 32) ? 0xffffffffull : ((1ull << N) - 1)));
+      return !entry_quiet(P, S, step, l, m, v.x, v.y);
+    };
     bool is_loud = false;
-    if (i < b1) {
-      const K key = keys[i];
-      const uint32_t slot = slot_of<K>(key, SB);
-      if (ss[slot].status == 1) {
-        const int2 v = vals[i];
-        const SlotParams &P = sp[slot];
-        const uint64_t cfg = (uint64_t)(key & lowm);
-        const uint32_t N = P.N;
-        const uint32_t l = (uint32_t)(cfg >> N);
-        const uint32_t m = (uint32_t)(cfg & ((N == 32) ? 0xffffffffull : ((1ull << N) - 1)));
-        is_loud = !entry_quiet(P, ss[slot].S, (uint32_t)ss[slot].step, l, m, v.x, v.y);
+    // the wave's entries almost always belong to one solve: its parameters are
+    // then loaded once, into scalar registers
+    const uint32_t s0 = __builtin_amdgcn_readfirstlane(slot);
+    if (__ballot(valid && slot != s0) == 0) {
+      if (ss[s0].status == 1) {
+        const SlotParams &P = sp[s0];
+        const double S = ss[s0].S;
+        const uint32_t step = (uint32_t)ss[s0].step;
+        if (valid) is_loud = quiet_test(P, S, step);
       }
+    } else if (valid && ss[slot].status == 1) {
+      is_loud = quiet_test(sp[slot], ss[slot].S, (uint32_t)ss[slot].step);
     }
     const uint64_t mask = __ballot(is_loud);
     if (mask) {
@@ -869,6 +884,13 @@ __global__ __launch_bounds__(NT) void k_merge_partition(const K *__restrict__ Ak
 // turns them into output offsets, WRITE stores the survivors there and the
 // tile's estimator sums.  Both decide survival with the same code, so their
 // counts agree; no tile waits on another.
+// Inside a tile, the runs whose first record lies in the tile are summed once
+// (one thread per record, the run's head does the work): a run on an occupied
+// configuration patches that entry, any other run becomes a candidate entry.
+// The entry that ends a tile and whose run starts in the next one is patched
+// by the tile that holds the entry.  The write pass then walks the merged
+// order with two compares per position and sums the estimators over the
+// compacted survivors.
 template <typename K, bool WRITE>
 __global__ __launch_bounds__(NT) void k_merge(
     const K *__restrict__ Ak, const int2 *__restrict__ Av, const K *__restrict__ Bk,
@@ -886,6 +908,8 @@ __global__ __launch_bounds__(NT) void k_merge(
   __shared__ K sAk[MERGE_TILE], sBk[MERGE_TILE];
   __shared__ int2 sBv[MERGE_TILE];
   __shared__ int2 sAv[WRITE ? MERGE_TILE : 1];
+  __shared__ uint8_t sAdel[MERGE_TILE];  // entry annihilated by its records
+  __shared__ uint8_t sBout[MERGE_TILE];  // record heads that become new entries
   __shared__ uint32_t s_i0, s_i1;
   __shared__ K s_aprev, s_bprev, s_bnext;  // the keys just outside the tile
   __shared__ uint32_t scan4[NT / 64];
@@ -904,6 +928,7 @@ __global__ __launch_bounds__(NT) void k_merge(
     for (uint32_t q = threadIdx.x; q < nA; q += NT) {
       sAk[q] = Ak[i0 + q];
       if (WRITE) sAv[q] = Av[i0 + q];
+      sAdel[q] = 0;
     }
     for (uint32_t q = threadIdx.x; q < nB; q += NT) {
       sBk[q] = Bk[j0 + q];
@@ -915,20 +940,13 @@ __global__ __launch_bounds__(NT) void k_merge(
       s_bnext = j1 < nb ? Bk[j1] : (K)0;
     }
     __syncthreads();
-    // keys by global index; callers pass indices inside the arrays
+    // keys and values by global record index; callers pass indices < nb
     auto bkey = [&](uint32_t j) -> K {
       if (j >= j0 && j < j1) return sBk[j - j0];
       if (j == j1) return s_bnext;
-      if (j + 1 == j0) return s_bprev;
       return Bk[j];
     };
     auto bval = [&](uint32_t j) -> int2 { return (j >= j0 && j < j1) ? sBv[j - j0] : Bv[j]; };
-    auto akey = [&](uint32_t i) -> K {
-      if (i >= i0 && i < i1) return sAk[i - i0];
-      if (i + 1 == i0) return s_aprev;
-      return Ak[i];
-    };
-    // the run of records with key k starting at global index j
     auto run_from = [&](uint32_t j, K k) -> RunSum {
       RunSum s{0, 0, 0, 0};
       while (j < nb && bkey(j) == k) {
@@ -937,8 +955,92 @@ __global__ __launch_bounds__(NT) void k_merge(
       }
       return s;
     };
+    // the tile's first solve: its parameters once, in registers
+    const uint32_t s0 = slot_of<K>((nA > 0 && (nB == 0 || sAk[0] <= sBk[0])) ? sAk[0] : sBk[0], SB);
+    const SlotParams P0 = sp[s0];
+    const bool leaving0 = ss[s0].status == 3;
+    auto leaving = [&](uint32_t slot) { return slot == s0 ? leaving0 : ss[slot].status == 3; };
+    auto ket_bra = [&](K k, uint32_t N, uint32_t &l, uint32_t &m) {
+      const uint64_t cfg = (uint64_t)(k & lowm);
+      l = (uint32_t)(cfg >> N);
+      m = (uint32_t)(cfg & ((N == 32) ? 0xffffffffull : ((1ull << N) - 1)));
+    };
+    auto fits = [](int64_t R, int64_t I) {
+      return R <= 2147483647LL && R >= -2147483647LL && I <= 2147483647LL && I >= -2147483647LL;
+    };
+    // an occupied entry and the sums of its run: annihilated, or its new value
+    auto patch = [&](uint32_t p, const RunSum &rs) {
+      int64_t R, I;
+      if (WRITE) {
+        R = (int64_t)sAv[p].x + rs.aR;
+        I = (int64_t)sAv[p].y + rs.aI;
+      } else {
+        const int2 av = Av[i0 + p];
+        R = (int64_t)av.x + rs.aR;
+        I = (int64_t)av.y + rs.aI;
+      }
+      if (R == 0 && I == 0) {
+        sAdel[p] = 1;
+      } else if (WRITE) {
+        if (!fits(R, I)) int_ovf = true;
+        sAv[p] = make_int2((int)R, (int)I);
+      }
+    };
 
-    // this thread's merged positions [dd, dd + MERGE_IT)
+    // runs whose first record is in this tile
+    for (uint32_t j = threadIdx.x; j < nB; j += NT) {
+      const K k = sBk[j];
+      const uint32_t gj = j0 + j;
+      const bool head = j > 0 ? sBk[j - 1] != k : (gj == 0 || s_bprev != k);
+      uint8_t out = 0;
+      // an entry right before the tile with this key already took the run
+      if (head && !(i0 > 0 && s_aprev == k)) {
+        const RunSum rs = run_from(gj, k);
+        const uint32_t p = lower_bound(sAk, nA, k);
+        if (p < nA && sAk[p] == k) {
+          patch(p, rs);
+        } else {
+          const uint32_t slot = slot_of<K>(k, SB);
+          uint32_t l, m;
+          ket_bra(k, slot == s0 ? P0.N : sp[slot].N, l, m);
+          // new configuration: every record if diagonal, else initiator records only
+          const int64_t R = (l == m) ? rs.aR : rs.iR;
+          const int64_t I = (l == m) ? rs.aI : rs.iI;
+          if ((R != 0 || I != 0) && !leaving(slot)) {
+            out = 1;
+            if (WRITE) {
+              if (!fits(R, I)) int_ovf = true;
+              sBv[j] = make_int2((int)R, (int)I);
+            }
+          }
+        }
+      }
+      sBout[j] = out;
+    }
+    // the tile's last entry, when its run starts right after the tile
+    if (threadIdx.x == 0 && nA > 0 && j1 < nb && s_bnext == sAk[nA - 1] &&
+        (nB == 0 || sBk[nB - 1] != s_bnext))
+      patch(nA - 1, run_from(j1, s_bnext));
+    __syncthreads();
+
+    if (!WRITE) {
+      uint32_t c = 0;
+      for (uint32_t q = threadIdx.x; q < nA; q += NT)
+        c += (!sAdel[q] && !leaving(slot_of<K>(sAk[q], SB))) ? 1u : 0u;
+      for (uint32_t q = threadIdx.x; q < nB; q += NT) c += sBout[q];
+      const uint32_t v = wave_sum(c);
+      if ((threadIdx.x & 63) == 0) scan4[threadIdx.x >> 6] = v;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) s += scan4[w];
+        tile_cnt[t] = s;
+      }
+      continue;
+    }
+
+    // this thread's merged positions [dd, dd + MERGE_IT): survivors in order
     const uint32_t len = nA + nB;
     const uint32_t dd = (uint32_t)threadIdx.x * MERGE_IT < len ? (uint32_t)threadIdx.x * MERGE_IT
                                                                : len;
@@ -957,107 +1059,33 @@ __global__ __launch_bounds__(NT) void k_merge(
     }
     K ck[MERGE_IT];
     int2 cv[MERGE_IT];
-    uint32_t okm = 0;  // bit it: position it survives
-    uint32_t nsurv = 0;
-    const uint32_t s0 = slot_of<K>((nA > 0 && (nB == 0 || sAk[0] <= sBk[0])) ? sAk[0] : sBk[0], SB);
-    // the tile's first solve: its parameters once, in registers
-    const SlotParams P0 = sp[s0];
-    const bool leaving0 = ss[s0].status == 3;
-    int64_t acc[S_NSUM];
-#pragma unroll
-    for (int s = 0; s < S_NSUM; ++s) acc[s] = 0;
-
+    uint32_t okm = 0, nsurv = 0;
 #pragma unroll
     for (int it = 0; it < MERGE_IT; ++it) {
       if (dd + (uint32_t)it >= len) continue;
-      K k;
-      RunSum rs{0, 0, 0, 0};
-      int64_t aR = 0, aI = 0;  // A's value when k is in the step-start list
-      bool inA = false, emit = false;
       if (a < nA && (b >= nB || sAk[a] <= sBk[b])) {
-        k = sAk[a];
-        inA = emit = true;
-        if (WRITE) {
-          aR = sAv[a].x;
-          aI = sAv[a].y;
-          rs = run_from(j0 + b, k);
-        } else if (j0 + b < nb && bkey(j0 + b) == k) {
-          // counting: A's value matters only when records land on it
-          const int2 av = Av[i0 + a];
-          aR = av.x;
-          aI = av.y;
-          rs = run_from(j0 + b, k);
-        } else {
-          aR = 1;  // occupied entries are nonzero
+        const K k = sAk[a];
+        if (!sAdel[a] && !leaving(slot_of<K>(k, SB))) {
+          ck[it] = k;
+          cv[it] = sAv[a];
+          okm |= 1u << it;
+          ++nsurv;
         }
         ++a;
       } else {
-        k = sBk[b];
-        const uint32_t gj = j0 + b, gi = i0 + a;
-        const bool head = (gj == 0) || bkey(gj - 1) != k;
-        const bool matched = (gi > 0) && akey(gi - 1) == k;
-        if (head && !matched) {
-          rs = run_from(gj, k);
-          emit = true;
+        if (sBout[b]) {
+          ck[it] = sBk[b];
+          cv[it] = sBv[b];
+          okm |= 1u << it;
+          ++nsurv;
         }
         ++b;
       }
-      if (!emit) continue;
-      const uint32_t slot = slot_of<K>(k, SB);
-      auto finish = [&](const SlotParams &P, bool leaving) {
-        const uint64_t cfg = (uint64_t)(k & lowm);
-        const uint32_t l = (uint32_t)(cfg >> P.N);
-        const uint32_t m = (uint32_t)(cfg & ((P.N == 32) ? 0xffffffffull : ((1ull << P.N) - 1)));
-        int64_t R, I;
-        if (inA || l == m) {  // occupied or diagonal: every record counts
-          R = aR + rs.aR;
-          I = aI + rs.aI;
-        } else {  // new off-diagonal entry: initiator records only (Sec. IV.A)
-          R = rs.iR;
-          I = rs.iI;
-        }
-        if ((R == 0 && I == 0) || leaving) return;
-        ++nsurv;
-        if (!WRITE) return;
-        if (R > 2147483647LL || R < -2147483647LL || I > 2147483647LL || I < -2147483647LL)
-          int_ovf = true;
-        ck[it] = k;
-        cv[it] = make_int2((int)R, (int)I);
-        okm |= 1u << it;
-        if (slot == s0) {
-          entry_sums(P, l, m, R, I, acc);
-        } else {
-          int64_t one[S_NSUM];
-#pragma unroll
-          for (int s = 0; s < S_NSUM; ++s) one[s] = 0;
-          entry_sums(P, l, m, R, I, one);
-#pragma unroll
-          for (int s = 0; s < S_NSUM; ++s)
-            if (one[s]) atomicAdd(&spill[(size_t)slot * S_NSUM + s], (unsigned long long)one[s]);
-        }
-      };
-      if (slot == s0)
-        finish(P0, leaving0);
-      else
-        finish(sp[slot], ss[slot].status == 3);
     }
-    if (!WRITE) {
-      const uint32_t v = wave_sum(nsurv);
-      if ((threadIdx.x & 63) == 0) scan4[threadIdx.x >> 6] = v;
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        uint32_t c = 0;
-#pragma unroll
-        for (int w = 0; w < NT / 64; ++w) c += scan4[w];
-        tile_cnt[t] = c;
-      }
-      continue;
-    }
-    // compaction: position of this thread's survivors; the tile's offset
     uint32_t ttot;
     const uint32_t lpos = block_excl_scan(nsurv, scan4, &ttot);
     const uint32_t gbase = tile_cnt[t];
-    // stage survivors in LDS (reuse the A arrays), then write them coalesced
+    // stage the survivors in LDS (reuse the A arrays)
     __syncthreads();
     {
       uint32_t q = lpos;
@@ -1070,14 +1098,35 @@ __global__ __launch_bounds__(NT) void k_merge(
         }
     }
     __syncthreads();
+    // write them coalesced, and their estimator sums (Sec. III.A, V.A)
+    int64_t acc[S_NSUM];
+#pragma unroll
+    for (int s = 0; s < S_NSUM; ++s) acc[s] = 0;
     for (uint32_t q = threadIdx.x; q < ttot; q += NT) {
+      const K k = sAk[q];
+      const int2 v = sAv[q];
       const uint32_t g = gbase + q;
       if (g < capC) {
-        Ck[g] = sAk[q];
-        Cv[g] = sAv[q];
+        Ck[g] = k;
+        Cv[g] = v;
+      }
+      const uint32_t slot = slot_of<K>(k, SB);
+      uint32_t l, m;
+      if (slot == s0) {
+        ket_bra(k, P0.N, l, m);
+        entry_sums(P0, l, m, v.x, v.y, acc);
+      } else {
+        const SlotParams &P = sp[slot];
+        ket_bra(k, P.N, l, m);
+        int64_t one[S_NSUM];
+#pragma unroll
+        for (int s = 0; s < S_NSUM; ++s) one[s] = 0;
+        entry_sums(P, l, m, v.x, v.y, one);
+#pragma unroll
+        for (int s = 0; s < S_NSUM; ++s)
+          if (one[s]) atomicAdd(&spill[(size_t)slot * S_NSUM + s], (unsigned long long)one[s]);
       }
     }
-    // estimator sums of the tile's first solve
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
 #pragma unroll
     for (int s = 0; s < S_NSUM; ++s) {

@@ -132,9 +132,17 @@ DQ_HD double dexp(double x) {
   return q * __builtin_bit_cast(double, (uint64_t)(k + 1023) << 52);
 }
 
-// b^e by squaring over the bits of e, low to high.
+// b^e by squaring over the bits of e, low to high.  The low four bits (all of
+// e for the small populations that dominate) without a loop: squaring b after
+// the last set bit is never used, so the products are those of the plain loop.
 DQ_HD double ipow(double b, int64_t e) {
   double r = 1.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    r = (e & 1) ? r * b : r;
+    e >>= 1;
+    b = b * b;
+  }
   while (e > 0) {
     if (e & 1) r = r * b;
     e >>= 1;
