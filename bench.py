@@ -238,10 +238,11 @@ def bench_d5(args):
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     print(f"d5: batched, {len(cfgs)} replicas x {steps} steps", file=sys.stderr, flush=True)
-    tb, ob, lb = serving.replicas_batched(cfgs, steps, stream=stream)
+    gk = args.graph_steps
+    tb, ob, lb = serving.replicas_batched(cfgs, steps, graph_k=gk, stream=stream)
     print(f"d5: batched {tb:.2f} s; sequential", file=sys.stderr, flush=True)
     ts, os_, ls = serving.replicas_sequential(
-        cfgs, steps, stream=stream, log=lambda m: print(f"d5: {m}", file=sys.stderr, flush=True))
+        cfgs, steps, graph_k=gk, stream=stream, log=lambda m: print(f"d5: {m}", file=sys.stderr, flush=True))
     print(f"d5: sequential {ts:.2f} s", file=sys.stderr, flush=True)
     same = all(len(a[0]) == len(c[0]) and all(np.array_equal(x, y) for x, y in zip(a, c))
                for a, c in zip(lb, ls))
@@ -258,7 +259,7 @@ def bench_d5(args):
         "config": {"workload": "64 replicas of the 5x5 dissipative XYZ model, Jx 0.5..1.2, "
                                "dt 0.002, n_a 3, p 0, targets log-uniform in [1e3, 2e4], "
                                "u64 keys",
-                   "graph_steps": 0, "final_entries": entries},
+                   "graph_steps": gk, "final_entries": entries},
         "sequential": {"seconds": ts, "value": len(cfgs) * (steps - 1) / ts},
         "batched_seconds": tb,
         "speedup_vs_sequential": ts / tb,
@@ -285,7 +286,8 @@ def bench_d4(args):
     def log(msg):
         done[0] += 1
         print(f"d4: {msg}", file=sys.stderr, flush=True)
-    recs, ticks = serving.serve(reqs, stream=stream, log=log)
+    gk = args.graph_steps
+    recs, ticks = serving.serve(reqs, graph_k=gk, stream=stream, log=log)
     wall = time.perf_counter() - t0
     lat = np.array([r["finished"] - r["arrival"] for r in recs])
     steps = np.array([r["steps"] for r in recs])
@@ -295,7 +297,8 @@ def bench_d4(args):
           file=sys.stderr, flush=True)
     alone = []
     for i in range(0, len(reqs), args.baseline_every):
-        dt, obs = serving.solve_alone(reqs[i]["params"], int(steps[i]), stream=stream)
+        dt, obs = serving.solve_alone(reqs[i]["params"], int(steps[i]), graph_k=gk,
+                                      stream=stream)
         print(f"d4: request {i} alone: {dt:.2f} s for {steps[i]} steps", file=sys.stderr,
               flush=True)
         assert obs["step"] == steps[i]
@@ -315,7 +318,8 @@ def bench_d4(args):
         "config": {"workload": f"{len(reqs)} requests, lattices uniform over 2x2/3x3/4x4/2x6, "
                                "Jx U[0.5,1.2], Jz U[0.8,1.2], gamma U[0.5,2], dt 0.005, n_a 3, "
                                "targets log-uniform [1e3,1e5], Poisson arrivals 20/s",
-                   "slots": 64, "tick_steps": 50, "admission": "pool list below 6e7 entries",
+                   "slots": 64, "tick_steps": 50, "graph_steps": gk,
+                   "admission": "pool list below 6e7 entries",
                    "stop": "SE(M_z) < 1e-3 after >= 512 accumulated steps, 2000 steps, or "
                            "more than 4e6 entries"},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
@@ -340,6 +344,8 @@ def main():
     ap.add_argument("--requests", type=int, default=512, help="d4: requests in the stream")
     ap.add_argument("--baseline-every", type=int, default=8,
                     help="d4: time every n-th request alone for the one-at-a-time baseline")
+    ap.add_argument("--graph-steps", type=int, default=0,
+                    help="d4/d5: launch the steps as HIP graphs of this many steps (even)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--trace-summary", metavar="DIR")

@@ -1,7 +1,7 @@
 // C ABI of the DDQMC step library (declared in include/ddqmc.h).
 //
 // A handle owns a sorted walker list (two ping-pong buffers), the spawn-record
-// buffers of the radix sort, the look-back words, per-tile estimator partials
+// buffers of the radix sort and its tile counts, per-tile estimator partials
 // and the per-solve parameter/state tables.  One step is a fixed sequence of
 // launches on the handle's stream (kernels.hpp); the host synchronises only at
 // the end of a chunk of steps, reads the control block and, if a buffer was too
@@ -55,7 +55,7 @@ struct ddqmc_t {
   int2 *mv[2] = {nullptr, nullptr};
   void *sk[2] = {nullptr, nullptr};
   int2 *sv[2] = {nullptr, nullptr};
-  uint64_t *sort_status = nullptr;
+  uint32_t *sort_cnt = nullptr;  // sort: digit counts of the tiles, then their prefixes
   uint32_t *tile_cnt = nullptr;  // merge: survivors per tile, then offsets
   Partial *partials = nullptr;
   uint32_t *hist = nullptr;
@@ -75,7 +75,8 @@ struct ddqmc_t {
   uint32_t *part = nullptr;      // merge tile boundaries
   uint32_t *segcnt = nullptr;  // record counters of the spawn segments
   uint32_t nscan = 1;          // blocks of the scan kernel (fixed per list capacity)
-  uint32_t coop_sort = 1;  // co-resident block limit of the sort
+  uint32_t loud_blocks = 1024;   // blocks of the loud spawn kernel the device holds at once
+  uint32_t heavy_blocks = 1024;  // one-wave blocks of the heavy spawn kernel, likewise
   void *inj_k = nullptr;
   int2 *inj_v = nullptr;
   uint32_t n_inject_host = 0;
@@ -134,7 +135,7 @@ uint64_t merge_tiles(uint64_t a, uint64_t b) { return (a + b + MERGE_TILE - 1) /
 
 size_t list_bytes(size_t ks, uint64_t cap) { return 2 * cap * (ks + sizeof(int2)); }
 size_t spawn_bytes(size_t ks, uint64_t cap) {
-  return 2 * cap * (ks + sizeof(int2)) + sort_tiles(cap) * 256 * sizeof(uint64_t);
+  return 2 * cap * (ks + sizeof(int2)) + sort_tiles(cap) * 256 * sizeof(uint32_t);
 }
 size_t merge_bytes(uint64_t cm, uint64_t cs) {
   return merge_tiles(cm, cs) * (2 * sizeof(uint32_t) + sizeof(Partial)) + 2 * sizeof(uint32_t);
@@ -201,7 +202,7 @@ SlotState fresh_state(const ddqmc_params &p, int status) {
 
 void free_all(ddqmc_t *h) {
   void *ptrs[] = {h->mk[0], h->mk[1], h->mv[0], h->mv[1], h->sk[0], h->sk[1], h->sv[0],
-                  h->sv[1], h->sort_status, h->tile_cnt, h->partials, h->hist, h->ctrl,
+                  h->sv[1], h->sort_cnt, h->tile_cnt, h->partials, h->hist, h->ctrl,
                   h->dsp, h->dss, h->spill, h->series, h->counts, h->loud, h->loud_cnt, h->loud_off, h->heavy, h->lidx, h->lkey, h->lval,
                   h->part, h->segcnt, h->inj_k,
                   h->inj_v};
@@ -267,8 +268,7 @@ int alloc_spawn(ddqmc_t *h, uint64_t cap) {
     HIPC(hipMalloc((void **)&h->sv[b], cap * sizeof(int2)));
   }
   const uint64_t st = sort_tiles(cap) * 256;
-  HIPC(hipMalloc((void **)&h->sort_status, st * sizeof(uint64_t)));
-  HIPC(hipMemsetAsync(h->sort_status, 0, st * sizeof(uint64_t), h->stream));
+  HIPC(hipMalloc((void **)&h->sort_cnt, st * sizeof(uint32_t)));
   h->cap_sp = cap;
   return DDQMC_OK;
 }
@@ -299,6 +299,25 @@ int build(ddqmc_t *h, int nslots, int Nmax, uint64_t cap, void *stream) {
   h->key_bits = h->SB + slot_bits;
   if (h->key_bits > 64) return DDQMC_EINVAL;
   h->k64 = h->key_bits > 32;
+  {
+    // the spawn kernels loop over their work: launch as many blocks as the
+    // device runs at once, so that no block waits for a second round
+    int ncu = 0, nl = 0, nh = 0;
+    HIPC(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device));
+    if (h->k64) {
+      HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nl, reinterpret_cast<const void *>(&k_spawn_loud<uint64_t>), NT, 0));
+      HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nh, reinterpret_cast<const void *>(&k_spawn_heavy<uint64_t>), 64, 0));
+    } else {
+      HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nl, reinterpret_cast<const void *>(&k_spawn_loud<uint32_t>), NT, 0));
+      HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nh, reinterpret_cast<const void *>(&k_spawn_heavy<uint32_t>), 64, 0));
+    }
+    h->loud_blocks = clampu((uint64_t)std::max(ncu, 1) * (uint64_t)std::max(nl, 1), 1, 4096);
+    h->heavy_blocks = clampu((uint64_t)std::max(ncu, 1) * (uint64_t)std::max(nh, 1), 1, 8192);
+  }
   h->passes = (h->key_bits + 7) / 8;
   cap = std::max<uint64_t>(cap, 4096);
   cap = std::min<uint64_t>(cap, MAX_CAP);
@@ -312,18 +331,6 @@ int build(ddqmc_t *h, int nslots, int Nmax, uint64_t cap, void *stream) {
   if ((rc = alloc_merge(h)) != DDQMC_OK) return rc;
   HIPC(hipMalloc((void **)&h->segcnt, NSEG * SEG_STRIDE * sizeof(uint32_t)));
   HIPC(hipMemsetAsync(h->segcnt, 0, NSEG * SEG_STRIDE * sizeof(uint32_t), h->stream));
-  {
-    int cus = 0, nb_sort = 0;
-    HIPC(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
-    if (h->k64)
-      HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &nb_sort, (const void *)k_sort_pass<uint64_t>, NT, 0));
-    else
-      HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &nb_sort, (const void *)k_sort_pass<uint32_t>, NT, 0));
-    if (cus < 1 || nb_sort < 1) return DDQMC_EHIP;
-    h->coop_sort = (uint32_t)(nb_sort * cus);
-  }
   HIPC(hipMalloc((void **)&h->hist, MAX_PASSES * 256 * sizeof(uint32_t)));
   HIPC(hipMemsetAsync(h->hist, 0, MAX_PASSES * 256 * sizeof(uint32_t), h->stream));
   HIPC(hipMalloc((void **)&h->ctrl, sizeof(Ctrl)));
@@ -397,10 +404,10 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
   const uint32_t capC = (uint32_t)h->cap_main;
   const uint32_t segcap = (uint32_t)(h->cap_sp / NSEG);
   // grids from the capacities: every kernel loops over the device-side counts
-  const uint32_t g_loud = clampu(h->nscan, 1, 1024);
-  const uint32_t g_heavy = 1024;
-  const uint32_t g_h = clampu((h->cap_sp + NT * 64 - 1) / (NT * 64), 1, 128);
-  const uint32_t g_s = clampu(sort_tiles(h->cap_sp), 1, h->coop_sort);
+  const uint32_t g_loud = clampu(h->nscan, 1, h->loud_blocks);
+  const uint32_t g_heavy = h->heavy_blocks;
+  const uint32_t g_h = clampu((h->cap_sp + NT * 8 - 1) / (NT * 8), 1, 512);
+  const uint32_t g_s = clampu(sort_tiles(h->cap_sp), 1, 1u << 24);
   const uint32_t g_m = clampu(merge_tiles(h->cap_main, h->cap_sp), 1, 1u << 20);
   if (ev) HIPC(hipEventRecord(ev->e[0], s));
   k_spawn_scan<K><<<h->nscan, NT, 0, s>>>(ak, av, h->ctrl, h->dsp, h->dss, h->loud, h->loud_cnt,
@@ -429,13 +436,11 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
     const int2 *iv = h->sv[p & 1];
     K *ok = (K *)h->sk[(p + 1) & 1];
     int2 *ov = h->sv[(p + 1) & 1];
-    Ctrl *ctrl = h->ctrl;
-    const uint32_t *hist = h->hist;
-    uint64_t *status = h->sort_status;
-    int pass = p;
-    uint32_t sc = p == 0 ? segcap : 0u;
-    void *args[] = {&ik, &iv, &ok, &ov, &ctrl, &hist, &status, &pass, &sc};
-    HIPC(hipLaunchCooperativeKernel((const void *)k_sort_pass<K>, dim3(g_s), dim3(NT), args, 0, s));
+    uint32_t *tcnt = h->sort_cnt;
+    const uint32_t sc = p == 0 ? segcap : 0u;
+    k_sort_count<K><<<g_s, NT, 0, s>>>(ik, h->ctrl, tcnt, p, sc);
+    k_sort_rowscan<<<256, NT, 0, s>>>(h->ctrl, tcnt);
+    k_sort_pass<K><<<g_s, NT, 0, s>>>(ik, iv, ok, ov, h->ctrl, h->hist, tcnt, p, sc);
   }
   {
     // the merge-path partition is timed with the sort stage, so that the merge
@@ -509,8 +514,8 @@ int regrow(ddqmc_t *h, uint64_t need_main, uint64_t need_sp) {
       h->sk[b] = nullptr;
       h->sv[b] = nullptr;
     }
-    HIPC(hipFree(h->sort_status));
-    h->sort_status = nullptr;
+    HIPC(hipFree(h->sort_cnt));
+    h->sort_cnt = nullptr;
     int rc = alloc_spawn(h, cap);
     if (rc != DDQMC_OK) return rc;
   }
@@ -1094,8 +1099,7 @@ int ddqmc_set_profiling(ddqmc_t *h, int32_t on) {
 int ddqmc_set_graph_steps(ddqmc_t *h, int32_t k) {
   if (!h || k < 0 || (k > 0 && (k < 2 || (k & 1) || k > (int32_t)SERIES_CAP)))
     return DDQMC_EINVAL;
-  // Switched off: the radix sort passes are cooperative launches, and graph
-  // replays have not been validated on the device.
+  // Switched off until graph replays have been validated on the device.
   if (k > 0) return DDQMC_ESTATE;
   h->graph_k = k;
   return DDQMC_OK;

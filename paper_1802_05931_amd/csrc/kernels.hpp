@@ -7,9 +7,9 @@
 //             records (model.hpp), staged in LDS and flushed into 64 segments
 //             that each have their own counter
 //   histogram digit counts of the records for every radix pass at once
-//   sort      LSD radix sort of the records by key, one launch per 8-bit digit,
-//             tiles ranked in LDS with wave ballots and placed by a decoupled
-//             look-back over the tiles (one pass reads and writes each record once)
+//   sort      LSD radix sort of the records by key, 8-bit digits: per pass the
+//             digit counts of every tile, their prefixes over the tiles, then
+//             tiles ranked in LDS with wave ballots and scattered
 //   merge     merge-path join of the sorted list with the sorted records: sums
 //             every run of equal keys (annihilation) applying the initiator rule,
 //             drops empty entries, compacts by a decoupled look-back and emits
@@ -17,9 +17,7 @@
 //
 // Same-address device atomics serialise (about 11 ns each on MI355X), so no
 // kernel here issues more than a few per segment: compaction inside a block
-// uses LDS, record output is spread over 64 counters, and the sort passes and
-// the merge take their tiles in a fixed round-robin order on a cooperative
-// (co-resident) grid instead of drawing tickets.
+// uses LDS, and record output is spread over 64 counters.
 //   finalize  one block: reduces the estimator sums per solve, updates the shift
 //             and the accumulators, and arms the next step
 //
@@ -62,7 +60,7 @@ struct Ctrl {
   uint32_t fail_flags;  // flags of the failed step
   uint32_t committed;   // steps completed since the host last looked
   uint32_t series_pos;  // rows in the series buffer
-  uint32_t epoch;       // bumped every step; tags look-back words
+  uint32_t epoch;       // bumped every step
   uint32_t n_inject;    // records waiting to enter the list
   uint32_t extinct_slot;
   uint32_t last_spawn;  // records of the last completed step
@@ -111,51 +109,6 @@ __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
-}
-
-// look-back words: epoch (30 bits) | flag (2 bits: 1 aggregate, 2 prefix) | count
-__device__ __forceinline__ uint64_t lb_pack(uint32_t epoch, uint32_t flag, uint32_t v) {
-  return ((uint64_t)(epoch & 0x3fffffffu) << 34) | ((uint64_t)flag << 32) | v;
-}
-__device__ __forceinline__ void lb_store(uint64_t *p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint64_t lb_load(uint64_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Exclusive prefix of tile t from tiles t-1, t-2, ... (word i of tile j at
-// base[j * stride]).  The words of LB_WIN predecessors are fetched together,
-// so a run of aggregates costs one round trip per LB_WIN tiles.  Waits only on
-// tiles held by running blocks (the grid is co-resident), so the wait ends.
-constexpr int LB_WIN = 8;
-__device__ uint32_t look_back(uint64_t *base, size_t stride, uint32_t t, uint32_t epoch) {
-  uint32_t excl = 0;
-  int64_t j = (int64_t)t - 1;
-  const uint64_t ep = (uint64_t)(epoch & 0x3fffffffu);
-  while (j >= 0) {
-    uint64_t w[LB_WIN];
-#pragma unroll
-    for (int q = 0; q < LB_WIN; ++q) w[q] = (j - q >= 0) ? lb_load(base + (size_t)(j - q) * stride) : 0;
-    int used = 0;
-    bool done = false, stalled = false;
-#pragma unroll
-    for (int q = 0; q < LB_WIN; ++q) {
-      if (done || stalled || j - q < 0) continue;
-      const uint32_t flag = (uint32_t)(w[q] >> 32) & 3u;
-      if ((w[q] >> 34) != ep || flag == 0) {
-        stalled = true;  // not published yet: fetch again from here
-        continue;
-      }
-      excl += (uint32_t)w[q];
-      ++used;
-      if (flag == 2) done = true;
-    }
-    if (done) break;
-    j -= used;
-    if (stalled) __builtin_amdgcn_s_sleep(1);
-  }
-  return excl;
 }
 
 template <typename K>
@@ -346,7 +299,7 @@ __device__ __forceinline__ void seg_flush64(const K *sk, const int2 *sv, uint32_
 // unused (re or im) part.
 // Emitter shared by the loud kernels: record (key, contribution) into the
 // block's LDS stage, or straight into its segment when the stage is full.
-template <typename K>
+template <typename K, uint32_t CAP = STAGE>
 struct RecordSink {
   K *sk;
   int2 *sv;
@@ -368,7 +321,7 @@ struct RecordSink {
         rv.x = NON_INIT;
     }
     const uint32_t s = atomicAdd(scount, 1u);
-    if (s < (uint32_t)STAGE) {
+    if (s < CAP) {
       sk[s] = ck;
       sv[s] = rv;
     } else {
@@ -458,7 +411,12 @@ __global__ __launch_bounds__(NT) void k_spawn_loud(
 // classes are walked level by level from an LDS frontier, one node per lane.
 // Every draw uses the stream of the same (channel, class, node) as in
 // entry_events, so the records are the same.
-constexpr int HEAVY_FRONT = 1024;  // tree nodes per frontier level
+// A level of a tree has at most as many nodes as the tree has members, so a
+// frontier never holds more than the two jump trees (N <= 32 members each)
+// plus the twelve hop classes (per part and side the three classes are
+// disjoint sets of the 2N <= 64 bonds): 64 + 2 * 2 * 64 = 320 nodes.
+constexpr int HEAVY_FRONT = 320;     // tree nodes per frontier level
+constexpr uint32_t HEAVY_STAGE = 512;  // records staged in LDS per entry (the rest go direct)
 
 template <typename K>
 __global__ __launch_bounds__(64) void k_spawn_heavy(
@@ -467,18 +425,20 @@ __global__ __launch_bounds__(64) void k_spawn_heavy(
     const uint32_t *__restrict__ heavy, K *__restrict__ ok, int2 *__restrict__ ov,
     uint32_t *segcnt, uint32_t segcap, int SB) {
   if (ctrl->abort) return;
-  __shared__ K sk[STAGE];
-  __shared__ int2 sv[STAGE];
+  __shared__ K sk[HEAVY_STAGE];
+  __shared__ int2 sv[HEAVY_STAGE];
   __shared__ uint32_t scount, sbase, fcount[2];
   __shared__ uint32_t fnode[2][HEAVY_FRONT];  // tree | lo << 5 | hi << 12 | h << 19
   __shared__ int64_t fM[2][HEAVY_FRONT];
+  __shared__ uint32_t s_cr[6], s_cu[6];  // class bond masks (right, up) and signs, so
+  __shared__ int s_cs[6];                // that a per-lane class index reads LDS
   const uint32_t nh = ctrl->n_heavy;
   const int lane = threadIdx.x;
   const int seg = (blockIdx.x + 17) % NSEG;
   const K lowm = low_mask<K>(SB);
   bool int_ovf = false;
   int dry = 0;
-  const RecordSink<K> sink{sk, sv, &scount, segcnt, ok, ov, segcap, seg, &int_ovf};
+  const RecordSink<K, HEAVY_STAGE> sink{sk, sv, &scount, segcnt, ok, ov, segcap, seg, &int_ovf};
   for (uint32_t q = blockIdx.x; q < nh; q += gridDim.x) {
     const uint32_t i = heavy[q];
     const K key = keys[i];
@@ -491,7 +451,15 @@ __global__ __launch_bounds__(64) void k_spawn_heavy(
     const uint32_t l = (uint32_t)(cfg >> N);
     const uint32_t m = (uint32_t)(cfg & ((N == 32) ? 0xffffffffull : ((1ull << N) - 1)));
     EntryProbs e = entry_probs(P, ss[slot].S, (uint32_t)ss[slot].step, l, m, v.x, v.y);
-    if (lane == 0) scount = 0;
+    if (lane == 0) {
+      scount = 0;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        s_cr[c] = e.hc.r[c];
+        s_cu[c] = e.hc.u[c];
+        s_cs[c] = e.hc.sgn[c];
+      }
+    }
     __syncthreads();
     auto out = [&](uint32_t cl, uint32_t cm, int64_t dr, int64_t di, bool keep) {
       sink(hibits | (K)(((uint64_t)cl << N) | cm), dr, di, keep);
@@ -520,10 +488,10 @@ __global__ __launch_bounds__(64) void k_spawn_heavy(
       if (rem == 1) {
         int c, j;
         pick_hop(e.cnt, draw_channel(ch) + DRAW_PICK, e.Sc, e.hc.n, c, j);
-        const uint32_t bm = class_member_mask(P, pick6(e.hc.r, c), pick6(e.hc.u, c), j);
+        const uint32_t bm = class_member_mask(P, s_cr[c], s_cu[c], j);
         const uint32_t cl = c < 3 ? (l ^ bm) : l;
         const uint32_t cm = c < 3 ? m : (m ^ bm);
-        const int64_t val = sg * (int64_t)pick6(e.hc.sgn, c);
+        const int64_t val = sg * (int64_t)s_cs[c];
         out(cl, cm, part ? -val : 0, part ? 0 : val, e.init || cl == cm);
         rem = 0;
       }
@@ -600,7 +568,7 @@ __global__ __launch_bounds__(64) void k_spawn_heavy(
               const int64_t val = sg * M;
               out(l & ~bit, m & ~bit, part ? 0 : val, part ? val : 0, e.init);
             } else {
-              const uint32_t cr = pick6(e.hc.r, c), cu = pick6(e.hc.u, c);
+              const uint32_t cr = s_cr[c], cu = s_cu[c];
               const int nr = popc(cr);
               uint32_t bm;
               if (lo < nr) {
@@ -612,7 +580,7 @@ __global__ __launch_bounds__(64) void k_spawn_heavy(
               }
               const uint32_t cl = c < 3 ? (l ^ bm) : l;
               const uint32_t cm = c < 3 ? m : (m ^ bm);
-              const int64_t val = sg * (int64_t)pick6(e.hc.sgn, c) * M;
+              const int64_t val = sg * (int64_t)s_cs[c] * M;
               out(cl, cm, part ? -val : 0, part ? 0 : val, e.init || cl == cm);
             }
           } else {
@@ -650,8 +618,8 @@ __global__ __launch_bounds__(64) void k_spawn_heavy(
     }
     dry |= e.cnt.dry;
     __syncthreads();
-    seg_flush64(sk, sv, scount < (uint32_t)STAGE ? scount : (uint32_t)STAGE, seg, segcnt, ok, ov,
-                segcap, &sbase);
+    seg_flush64(sk, sv, scount < HEAVY_STAGE ? scount : HEAVY_STAGE, seg, segcnt, ok, ov, segcap,
+                &sbase);
   }
   if (dry) atomicOr(&ctrl->flags, F_RNG);
   if (int_ovf) atomicOr(&ctrl->flags, F_INT_OVF);
@@ -725,23 +693,75 @@ __global__ __launch_bounds__(NT) void k_hist(const K *__restrict__ sk, Ctrl *ctr
     if (h[i]) atomicAdd(&hist[i], h[i]);
 }
 
-// One LSD pass over an 8-bit digit.  Launched cooperatively: every block is
-// resident, block b takes tiles b, b + G, b + 2G, ... in order, so the tile a
-// look-back waits on is held by a running block and has no later dependency.
-// Pass 0 reads the segmented spawn buffer (segcap > 0), later passes read a
-// contiguous array (segcap == 0).
+// One LSD pass over an 8-bit digit, reduce-then-scan: k_sort_count writes the
+// digit counts of every tile (digit-major), k_sort_rowscan turns each digit's
+// row into exclusive prefixes over the tiles, and k_sort_pass ranks each tile
+// in LDS and scatters it to (global start of the digit) + (its row prefix).
+// No tile waits on another.  Pass 0 reads the segmented spawn buffer
+// (segcap > 0), later passes read a contiguous array (segcap == 0).
+template <typename K>
+__global__ __launch_bounds__(NT) void k_sort_count(const K *__restrict__ ik, Ctrl *ctrl,
+                                                   uint32_t *__restrict__ cnt, int pass,
+                                                   uint32_t segcap) {
+  if (ctrl->abort || (ctrl->flags & F_SPAWN_CAP)) return;
+  const uint32_t n = ctrl->n_spawn;
+  const uint32_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
+  const uint32_t t = blockIdx.x;
+  if (t >= ntiles) return;
+  __shared__ uint32_t h[256];
+  __shared__ uint32_t pre[NSEG + 1];
+  h[threadIdx.x] = 0;
+  if (threadIdx.x <= NSEG) pre[threadIdx.x] = ctrl->seg_prefix[threadIdx.x];
+  __syncthreads();
+  const int shift = 8 * pass;
+#pragma unroll
+  for (int k = 0; k < SORT_IT; ++k) {
+    const uint32_t pos = t * SORT_TILE + (uint32_t)k * NT + threadIdx.x;
+    if (pos < n) {
+      const K key = ik[segcap ? seg_addr(pre, pos, segcap) : (size_t)pos];
+      atomicAdd(&h[(uint32_t)((key >> shift) & 255u)], 1u);
+    }
+  }
+  __syncthreads();
+  cnt[(size_t)threadIdx.x * ntiles + t] = h[threadIdx.x];
+}
+
+// Exclusive prefix over the tiles of digit blockIdx.x's row of counts, in place.
+__global__ __launch_bounds__(NT) void k_sort_rowscan(Ctrl *ctrl, uint32_t *cnt) {
+  if (ctrl->abort || (ctrl->flags & F_SPAWN_CAP)) return;
+  const uint32_t n = ctrl->n_spawn;
+  const uint32_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
+  if (ntiles == 0) return;
+  __shared__ uint32_t scan4[NT / 64];
+  uint32_t *row = cnt + (size_t)blockIdx.x * ntiles;
+  const uint32_t per = (ntiles + NT - 1) / NT;
+  const uint32_t c0 = threadIdx.x * per < ntiles ? threadIdx.x * per : ntiles;
+  const uint32_t c1 = c0 + per < ntiles ? c0 + per : ntiles;
+  uint32_t local = 0;
+  for (uint32_t c = c0; c < c1; ++c) local += row[c];
+  uint32_t tot;
+  uint32_t run = block_excl_scan(local, scan4, &tot);
+  for (uint32_t c = c0; c < c1; ++c) {
+    const uint32_t v = row[c];
+    row[c] = run;
+    run += v;
+  }
+}
+
 template <typename K>
 __global__ __launch_bounds__(NT) void k_sort_pass(const K *__restrict__ ik,
                                                   const int2 *__restrict__ iv,
                                                   K *__restrict__ okk, int2 *__restrict__ ov,
                                                   Ctrl *ctrl, const uint32_t *__restrict__ hist,
-                                                  uint64_t *status, int pass, uint32_t segcap) {
+                                                  const uint32_t *__restrict__ cnt, int pass,
+                                                  uint32_t segcap) {
   if (ctrl->abort || (ctrl->flags & F_SPAWN_CAP)) return;
   const uint32_t n = ctrl->n_spawn;
   if (n == 0) return;
   const uint32_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
+  const uint32_t t = blockIdx.x;
+  if (t >= ntiles) return;
   const int shift = 8 * pass;
-  const uint32_t epoch = ctrl->epoch * 8u + (uint32_t)pass;
 
   __shared__ K tk[SORT_TILE];
   __shared__ int2 tv[SORT_TILE];
@@ -758,10 +778,12 @@ __global__ __launch_bounds__(NT) void k_sort_pass(const K *__restrict__ ik,
     const uint32_t h = hist[pass * 256 + threadIdx.x];
     gstart[threadIdx.x] = block_excl_scan(h, scan4, &tot);
   }
-  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    __syncthreads();
-    for (int i = threadIdx.x; i < (NT / 64) * 256; i += NT) (&wcnt[0][0])[i] = 0;
-    __syncthreads();
+  // this tile's place for each digit: the digit's start plus the counts of the
+  // digit in the tiles before
+  goff[threadIdx.x] = gstart[threadIdx.x] + cnt[(size_t)threadIdx.x * ntiles + t];
+  for (int i = threadIdx.x; i < (NT / 64) * 256; i += NT) (&wcnt[0][0])[i] = 0;
+  __syncthreads();
+  {
     const uint32_t tbase = t * SORT_TILE;
     const uint32_t wbase = tbase + (uint32_t)w * 64u * SORT_IT;
     K key[SORT_IT];
@@ -795,28 +817,17 @@ __global__ __launch_bounds__(NT) void k_sort_pass(const K *__restrict__ ik,
       __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    // per digit: wave prefixes, tile count, tile-local start
+    // per digit: wave prefixes and the tile-local start
     const int d = threadIdx.x;
-    uint32_t cnt = 0;
+    uint32_t c = 0;
 #pragma unroll
     for (int ww = 0; ww < NT / 64; ++ww) {
-      const uint32_t c = wcnt[ww][d];
-      wcnt[ww][d] = cnt;
-      cnt += c;
+      const uint32_t x = wcnt[ww][d];
+      wcnt[ww][d] = c;
+      c += x;
     }
     uint32_t tot;
-    const uint32_t ls = block_excl_scan(cnt, scan4, &tot);
-    lstart[d] = ls;
-    uint64_t *st = status + (size_t)t * 256 + d;
-    if (t == 0) {
-      lb_store(st, lb_pack(epoch, 2u, cnt));
-      goff[d] = gstart[d];
-    } else {
-      lb_store(st, lb_pack(epoch, 1u, cnt));
-      const uint32_t excl = look_back(status + d, 256, t, epoch);
-      lb_store(st, lb_pack(epoch, 2u, excl + cnt));
-      goff[d] = gstart[d] + excl;
-    }
+    lstart[d] = block_excl_scan(c, scan4, &tot);
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < SORT_IT; ++k) {

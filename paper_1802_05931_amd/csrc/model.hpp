@@ -273,11 +273,13 @@ DQ_HD EntryProbs entry_probs(const SlotParams &P, double S, uint32_t step, uint3
 DQ_HD bool entry_quiet(const SlotParams &P, double S, uint32_t step, uint32_t l, uint32_t m,
                        int32_t R, int32_t I) {
   const EntryProbs e = entry_probs(P, S, step, l, m, R, I);
+  // an empty channel or one with p = 0 contributes ipow(.) = 1 exactly, which
+  // leaves the product as it is
   double g = 1.0;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     if (e.n8[k] > 0 && e.p8[k] >= 1.0) return false;
-    if (e.n8[k] > 0 && e.p8[k] > 0.0) g = g * ipow(1.0 - e.p8[k], e.n8[k]);
+    g = g * ipow(1.0 - e.p8[k], e.n8[k]);
   }
   Stream prim(e.cnt.seed, e.cnt.solve, e.cnt.cfg, e.cnt.step, 0, nullptr);
   return prim.next() < g;
@@ -443,19 +445,6 @@ template <typename Emit>
 DQ_HD bool entry_events_small(const SlotParams &P, double S, uint32_t step, uint32_t l,
                               uint32_t m, int32_t R, int32_t I, int *err, Emit &&emit) {
   const EntryProbs e = entry_probs(P, S, step, l, m, R, I);
-  // the class tables as values in registers, picked by sel6
-  const uint32_t cr0 = e.hc.r[0], cr1 = e.hc.r[1], cr2 = e.hc.r[2], cr3 = e.hc.r[3],
-                 cr4 = e.hc.r[4], cr5 = e.hc.r[5];
-  const uint32_t cu0 = e.hc.u[0], cu1 = e.hc.u[1], cu2 = e.hc.u[2], cu3 = e.hc.u[3],
-                 cu4 = e.hc.u[4], cu5 = e.hc.u[5];
-  const int cn0 = e.hc.n[0], cn1 = e.hc.n[1], cn2 = e.hc.n[2], cn3 = e.hc.n[3], cn4 = e.hc.n[4],
-            cn5 = e.hc.n[5];
-  const int cs0 = e.hc.sgn[0], cs1 = e.hc.sgn[1], cs2 = e.hc.sgn[2], cs3 = e.hc.sgn[3],
-            cs4 = e.hc.sgn[4], cs5 = e.hc.sgn[5];
-  const double cw0 = e.hc.W[0], cw1 = e.hc.W[1], cw2 = e.hc.W[2], cw3 = e.hc.W[3],
-               cw4 = e.hc.W[4], cw5 = e.hc.W[5];
-  const double sc0 = e.Sc[0], sc1 = e.Sc[1], sc2 = e.Sc[2], sc3 = e.Sc[3], sc4 = e.Sc[4],
-               sc5 = e.Sc[5];
   const double pk[4] = {e.p8[0], e.p8[1], e.p8[2], e.p8[3]};
   const int64_t nR = e.n8[0], nI = e.n8[4];
 #pragma unroll
@@ -466,14 +455,20 @@ DQ_HD bool entry_events_small(const SlotParams &P, double S, uint32_t step, uint
   int64_t X0 = 0, X1 = 0, X2 = 0, X3 = 0, X4 = 0, X5 = 0, X6 = 0, X7 = 0;
   int dry = 0;
   int start = 0;
+  // each channel's zero probability once (1 for an empty channel: multiplying
+  // by it leaves the running product as it is)
+  double f[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    f[k] = ipow(1.0 - pk[k & 3], k < 4 ? nR : nI);
+  }
 #pragma unroll 1
   while (start < 8) {
     double G[8];
     double g = 1.0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      const int64_t nk = k < 4 ? nR : nI;
-      if (k >= start && nk > 0 && pk[k & 3] > 0.0) g = g * ipow(1.0 - pk[k & 3], nk);
+      if (k >= start) g = g * f[k];
       G[k] = g;
     }
     const double u = prim.next();
@@ -502,6 +497,28 @@ DQ_HD bool entry_events_small(const SlotParams &P, double S, uint32_t step, uint
   // larger spawn counts can need the rejection sampler in their splits
   if (X2 >= 20 || X3 >= 20 || X6 >= 20 || X7 >= 20) return false;
   if (dry) *err = 1;
+
+  // the hop classes again, after the channel search, so that their tables are
+  // not held in registers through it (the opaque copy of l, m keeps the
+  // compiler from reusing the first computation)
+  uint32_t lo = l, mo = m;
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+v"(lo), "+v"(mo));
+#endif
+  const HopClasses hc = hop_classes(P, geometry(P, lo, mo), lo, mo);
+  const uint32_t cr0 = hc.r[0], cr1 = hc.r[1], cr2 = hc.r[2], cr3 = hc.r[3], cr4 = hc.r[4],
+                 cr5 = hc.r[5];
+  const uint32_t cu0 = hc.u[0], cu1 = hc.u[1], cu2 = hc.u[2], cu3 = hc.u[3], cu4 = hc.u[4],
+                 cu5 = hc.u[5];
+  const int cn0 = hc.n[0], cn1 = hc.n[1], cn2 = hc.n[2], cn3 = hc.n[3], cn4 = hc.n[4],
+            cn5 = hc.n[5];
+  const int cs0 = hc.sgn[0], cs1 = hc.sgn[1], cs2 = hc.sgn[2], cs3 = hc.sgn[3], cs4 = hc.sgn[4],
+            cs5 = hc.sgn[5];
+  const double cw0 = hc.W[0], cw1 = hc.W[1], cw2 = hc.W[2], cw3 = hc.W[3], cw4 = hc.W[4],
+               cw5 = hc.W[5];
+  // suffix sums of the class weights, in entry_probs' order
+  const double sc5 = cw5, sc4 = cw4 + sc5, sc3 = cw3 + sc4, sc2 = cw2 + sc3, sc1 = cw1 + sc2,
+               sc0 = cw0 + sc1;
 
   const int64_t sR = e.sR, sI = e.sI;
   const int64_t dR = sR * sgnd(e.d_r) * X0 - sI * sgnd(e.d_i) * X5;
