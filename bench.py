@@ -344,8 +344,9 @@ def main():
     ap.add_argument("--requests", type=int, default=512, help="d4: requests in the stream")
     ap.add_argument("--baseline-every", type=int, default=8,
                     help="d4: time every n-th request alone for the one-at-a-time baseline")
-    ap.add_argument("--graph-steps", type=int, default=0,
-                    help="d4/d5: launch the steps as HIP graphs of this many steps (even)")
+    ap.add_argument("--graph-steps", type=int, default=10,
+                    help="d4/d5: launch the steps as HIP graphs of this many steps (even; 0 = "
+                         "one launch per kernel)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--trace-summary", metavar="DIR")

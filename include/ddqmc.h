@@ -184,8 +184,8 @@ int ddqmc_set_profiling(ddqmc_t *h, int32_t on);
  * captured on first use for each parity of the list it starts from, and again
  * after the handle's buffers grow; steps that do not fill a whole graph run
  * one by one.  Graphs are not used while profiling is on.  The results are the
- * same either way.  EINVAL for other k.  This build has graph steps switched
- * off: k > 0 returns DDQMC_ESTATE and the kernels keep launching one by one. */
+ * same either way: a graph holds the same kernels with the same grids, and
+ * each kernel reads its counts from device memory.  EINVAL for other k. */
 int ddqmc_set_graph_steps(ddqmc_t *h, int32_t k);
 int ddqmc_stage_times(ddqmc_t *h, double ms[10], int64_t *steps);
 

@@ -1099,8 +1099,6 @@ int ddqmc_set_profiling(ddqmc_t *h, int32_t on) {
 int ddqmc_set_graph_steps(ddqmc_t *h, int32_t k) {
   if (!h || k < 0 || (k > 0 && (k < 2 || (k & 1) || k > (int32_t)SERIES_CAP)))
     return DDQMC_EINVAL;
-  // Switched off until graph replays have been validated on the device.
-  if (k > 0) return DDQMC_ESTATE;
   h->graph_k = k;
   return DDQMC_OK;
 }

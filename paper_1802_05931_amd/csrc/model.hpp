@@ -279,7 +279,7 @@ DQ_HD bool entry_quiet(const SlotParams &P, double S, uint32_t step, uint32_t l,
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     if (e.n8[k] > 0 && e.p8[k] >= 1.0) return false;
-    g = g * ipow(1.0 - e.p8[k], e.n8[k]);
+    if (e.n8[k] > 0 && e.p8[k] > 0.0) g = g * ipow(1.0 - e.p8[k], e.n8[k]);
   }
   Stream prim(e.cnt.seed, e.cnt.solve, e.cnt.cfg, e.cnt.step, 0, nullptr);
   return prim.next() < g;
@@ -460,7 +460,8 @@ DQ_HD bool entry_events_small(const SlotParams &P, double S, uint32_t step, uint
   double f[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    f[k] = ipow(1.0 - pk[k & 3], k < 4 ? nR : nI);
+    const int64_t nk = k < 4 ? nR : nI;
+    f[k] = (nk > 0 && pk[k & 3] > 0.0) ? ipow(1.0 - pk[k & 3], nk) : 1.0;
   }
 #pragma unroll 1
   while (start < 8) {

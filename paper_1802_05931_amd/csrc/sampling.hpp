@@ -132,23 +132,21 @@ DQ_HD double dexp(double x) {
   return q * __builtin_bit_cast(double, (uint64_t)(k + 1023) << 52);
 }
 
-// b^e by squaring over the bits of e, low to high.  The first bit needs no
-// product (1 * b is b); on the device the loop runs while any lane of the wave
-// still has bits left, so its trip count is uniform and small for the small
-// populations that dominate.  A lane whose bits are used up keeps its result
-// (only its unused base is squared further), so the products are those of the
-// plain loop.
+// b^e by squaring over the bits of e, low to high.  The low four bits (all of
+// e for the small populations that dominate) without a loop: squaring b after
+// the last set bit is never used, so the products are those of the plain loop.
 DQ_HD double ipow(double b, int64_t e) {
-  double r = (e & 1) ? b : 1.0;
-  e >>= 1;
-#if defined(__HIP_DEVICE_COMPILE__)
-  while (__any(e > 0)) {
-#else
-  while (e > 0) {
-#endif
-    b = b * b;
+  double r = 1.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
     r = (e & 1) ? r * b : r;
     e >>= 1;
+    b = b * b;
+  }
+  while (e > 0) {
+    if (e & 1) r = r * b;
+    e >>= 1;
+    if (e > 0) b = b * b;
   }
   return r;
 }

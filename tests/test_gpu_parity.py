@@ -192,11 +192,6 @@ def test_pool_admit_retire_equals_alone(dq, orc):
     pool.close()
 
 
-GRAPHS_OFF = ("graph steps are switched off: a device run with them faulted and its cause "
-              "is not yet shown")
-
-
-@pytest.mark.skip(reason=GRAPHS_OFF)
 def test_graph_steps_equal_eager(dq, orc):
     """k-step HIP graphs (replayed several times per call, re-captured after
     the buffers grow from a tiny capacity) give the eager launches' lists, which
@@ -224,7 +219,6 @@ def test_graph_steps_equal_eager(dq, orc):
     b.close()
 
 
-@pytest.mark.skip(reason=GRAPHS_OFF)
 def test_graph_steps_batch_equals_alone(dq, orc):
     cfgs = [dict(workloads.D1, solve_id=0, n_equil=40),
             dict(workloads.d2(0.9), solve_id=1, target_walkers=3000, n_equil=40),
@@ -248,9 +242,7 @@ def test_graph_steps_invalid(dq):
         with pytest.raises(DDQMCError) as e:
             g.set_graph_steps(k)
         assert e.value.code == -1
-    with pytest.raises(DDQMCError) as e:  # switched off in this build
-        g.set_graph_steps(10)
-    assert e.value.code == -7
+    g.set_graph_steps(10)
     g.set_graph_steps(0)
     g.step(3)
     g.close()
@@ -272,15 +264,18 @@ def _churn_requests():
     return reqs
 
 
-@pytest.mark.parametrize("cap", [0, 16])
-def test_pool_churn_equals_alone(dq, cap):
+@pytest.mark.parametrize("cap,gk", [(0, 0), (16, 0), (16, 10)])
+def test_pool_churn_equals_alone(dq, cap, gk):
     """Continuous batching with churn: solves of four lattice shapes enter and
     leave a 5-slot pool between ticks (several admissions in one tick, slots
     reused, the buffers grown during entering steps when the capacity starts
-    tiny); each solve's list when it leaves equals the same solve run alone."""
+    tiny; with gk > 0 the ticks run as k-step graphs, re-captured after each
+    growth); each solve's list when it leaves equals the same solve run alone."""
     from paper_1802_05931_amd import DDQMCError
     reqs = _churn_requests()
     pool = dq.Pool(slots=5, max_sites=16, capacity_hint=cap)
+    if gk:
+        pool.set_graph_steps(gk)
     queue = list(range(len(reqs)))
     active, done = {}, {}
     ticks = 0
