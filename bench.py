@@ -430,9 +430,11 @@ def main():
     rec = KEY_BYTES[k64] + 8  # key + (re, im) int32
     passes = (2 * cfg["Lx"] * cfg["Ly"] + 7) // 8
     alg_bytes = {  # what each kernel must read and write, per the step's counts
-        "scan": float((n_in * rec).sum()),
+        # the list in, the loud entries out (index, key, value)
+        "scan": float((n_in * rec + c[:, 3] * (rec + 4)).sum()),
         "histogram": float((n_sp * KEY_BYTES[k64]).sum()),
-        "sort": float((2 * passes * n_sp * rec).sum()),
+        # per pass: the digit counts read the keys, the scatter reads and writes records
+        "sort": float((passes * n_sp * (KEY_BYTES[k64] + 2 * rec)).sum()),
         # survivors per tile: the list's keys and the records
         "count": float((n_in * KEY_BYTES[k64] + n_sp * rec).sum()),
         # the list and the records in, the new list out
@@ -467,8 +469,7 @@ def main():
         # instructions per launch (committed counter profile) over the live launch
         # time, against 256 CUs x 4 SIMDs issuing one wave64 instruction per 4
         # cycles at 2.4 GHz
-        kname = {"loud": "k_spawn_loud", "heavy": "k_spawn_heavy", "gather": "k_loud_gather"}.get(
-            dominant, dominant)
+        kname = {"loud": "k_spawn_loud", "heavy": "k_spawn_heavy"}.get(dominant, dominant)
         dur_s = stage_ms[dominant] / 1e3 / args.steps
         valu = valu_from_profile(kname, args.workload)
         achieved = valu / dur_s / 1e9 if valu else None
@@ -501,7 +502,9 @@ def main():
         "config": {"workload": desc, "lattice": "4x4", "target_walkers": cfg["target_walkers"],
                    "key_bits": 2 * cfg["Lx"] * cfg["Ly"], "mean_entries": float(n_in.mean()),
                    "mean_walkers": float(w_start.mean()),
-                   "mean_spawn_records": float(n_sp.mean())},
+                   "mean_spawn_records": float(n_sp.mean()),
+                   "mean_loud_entries": float(c[:, 3].mean()),
+                   "mean_heavy_entries": float(c[:, 4].mean())},
         "entry_updates_per_s": float(n_in.sum()) / wall,
         "roofline": roofline,
         "hbm_roofline": hbm_roofline,

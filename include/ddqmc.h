@@ -161,9 +161,11 @@ int ddqmc_set_state(ddqmc_t *h, const void *buf, size_t n);
  * mode, the DDQMC_NSUM sums), int64.  *n = rows available; copies min(cap, n). */
 int ddqmc_get_series(ddqmc_t *h, int32_t slot, int64_t *rows, int64_t cap, int64_t *n);
 
-/* Per step since creation, over all slots: rows of (entries at the start of the
- * step, spawn records produced, entries after the step), int64.  These size the
- * memory traffic of each kernel launch (bytes per launch for a roofline). */
+/* Per step since creation, over all slots: rows of five int64 (entries at the
+ * start of the step, spawn records produced, entries after the step, entries
+ * with some event, of those the ones sampled one wave each).  These size the
+ * memory traffic of each kernel launch (bytes per launch for a roofline).
+ * rows holds cap rows (5 cap int64); *n receives the number of steps. */
 int ddqmc_get_step_counts(ddqmc_t *h, int64_t *rows, int64_t cap, int64_t *n);
 
 /* Device bytes a one-slot handle with the given capacity would allocate
@@ -172,7 +174,8 @@ int ddqmc_workspace_query(const ddqmc_params *p, int64_t capacity, size_t *bytes
 
 /* Wall time of the kernels of the last ddqmc_step call, per stage, from HIP
  * events on the handle's stream when profiling is on (ddqmc_set_profiling);
- * ms[10] = quiet scan, loud gather (queue offsets and the flat loud list),
+ * ms[10] = quiet scan (which also writes the list of loud entries), loud
+ * gather (kept for the layout of ms; empty, since the scan writes that list),
  * loud spawn (the spawn kernel alone), heavy spawn, record seal, histogram,
  * sort (the radix passes and the merge-path partition), merge count
  * (survivors per tile and their offsets), merge (the merge kernel that writes

@@ -97,10 +97,11 @@ class _Handle:
         return rows
 
     def step_counts(self):
-        """(entries in, spawn records, entries out) for every step so far."""
+        """(entries in, spawn records, entries out, loud entries, heavy entries)
+        for every step so far."""
         n = ctypes.c_int64()
         check(lib().ddqmc_get_step_counts(self._h, None, 0, ctypes.byref(n)), "step_counts")
-        rows = np.zeros((n.value, 3), np.int64)
+        rows = np.zeros((n.value, 5), np.int64)
         check(lib().ddqmc_get_step_counts(self._h, ptr(rows, ctypes.c_int64), n.value,
                                           ctypes.byref(n)), "step_counts")
         return rows

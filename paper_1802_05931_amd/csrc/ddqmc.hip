@@ -64,12 +64,9 @@ struct ddqmc_t {
   SlotState *dss = nullptr;
   unsigned long long *spill = nullptr;
   int64_t *series = nullptr;
-  uint32_t *counts = nullptr;  // per step: entries in, records, entries out
-  uint32_t *loud = nullptr;    // indices of the entries where some event happens
-  uint32_t *loud_cnt = nullptr;  // loud entries per scan block
-  uint32_t *loud_off = nullptr;  // their offsets (nscan + 1)
+  uint32_t *counts = nullptr;  // per step: entries in, records, entries out, loud, heavy
   uint32_t *heavy = nullptr;     // loud entries that need the general sampling code
-  uint32_t *lidx = nullptr;      // flat loud list: entry index, key, value
+  uint32_t *lidx = nullptr;      // loud list (entries with some event): index, key, value
   void *lkey = nullptr;
   int2 *lval = nullptr;
   uint32_t *part = nullptr;      // merge tile boundaries
@@ -134,6 +131,8 @@ uint64_t sort_tiles(uint64_t cap) { return (cap + SORT_TILE - 1) / SORT_TILE; }
 uint64_t merge_tiles(uint64_t a, uint64_t b) { return (a + b + MERGE_TILE - 1) / MERGE_TILE; }
 
 size_t list_bytes(size_t ks, uint64_t cap) { return 2 * cap * (ks + sizeof(int2)); }
+// the loud list (index, key, value) and the heavy queue
+size_t loud_bytes(size_t ks, uint64_t cap) { return cap * (2 * sizeof(uint32_t) + ks + sizeof(int2)); }
 size_t spawn_bytes(size_t ks, uint64_t cap) {
   return 2 * cap * (ks + sizeof(int2)) + sort_tiles(cap) * 256 * sizeof(uint32_t);
 }
@@ -203,7 +202,7 @@ SlotState fresh_state(const ddqmc_params &p, int status) {
 void free_all(ddqmc_t *h) {
   void *ptrs[] = {h->mk[0], h->mk[1], h->mv[0], h->mv[1], h->sk[0], h->sk[1], h->sv[0],
                   h->sv[1], h->sort_cnt, h->tile_cnt, h->partials, h->hist, h->ctrl,
-                  h->dsp, h->dss, h->spill, h->series, h->counts, h->loud, h->loud_cnt, h->loud_off, h->heavy, h->lidx, h->lkey, h->lval,
+                  h->dsp, h->dss, h->spill, h->series, h->counts, h->heavy, h->lidx, h->lkey, h->lval,
                   h->part, h->segcnt, h->inj_k,
                   h->inj_v};
   for (void *p : ptrs)
@@ -221,11 +220,9 @@ uint32_t clampu(uint64_t v, uint32_t lo, uint32_t hi) {
   return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(v, lo), hi);
 }
 
-// The loud queue: scan block b owns loud[b * chunk, (b + 1) * chunk).
+// The dense loud list (entry index, key, value) and the heavy queue, both at
+// most one slot per list entry.
 int alloc_loud(ddqmc_t *h) {
-  if (h->loud) HIPC(hipFree(h->loud));
-  if (h->loud_cnt) HIPC(hipFree(h->loud_cnt));
-  if (h->loud_off) HIPC(hipFree(h->loud_off));
   if (h->heavy) HIPC(hipFree(h->heavy));
   if (h->lidx) HIPC(hipFree(h->lidx));
   if (h->lkey) HIPC(hipFree(h->lkey));
@@ -234,15 +231,7 @@ int alloc_loud(ddqmc_t *h) {
   h->lidx = nullptr;
   h->lkey = nullptr;
   h->lval = nullptr;
-  h->loud = nullptr;
-  h->loud_cnt = nullptr;
-  h->loud_off = nullptr;
   h->nscan = clampu((h->cap_main + NT - 1) / NT, 1, 4096);
-  const uint64_t per = (h->cap_main + h->nscan - 1) / h->nscan;
-  const uint64_t chunk = (per + NT - 1) / NT * NT;
-  HIPC(hipMalloc((void **)&h->loud, (size_t)chunk * h->nscan * sizeof(uint32_t)));
-  HIPC(hipMalloc((void **)&h->loud_cnt, (size_t)h->nscan * sizeof(uint32_t)));
-  HIPC(hipMalloc((void **)&h->loud_off, (size_t)(h->nscan + 1) * sizeof(uint32_t)));
   HIPC(hipMalloc((void **)&h->heavy, (size_t)h->cap_main * sizeof(uint32_t)));
   HIPC(hipMalloc((void **)&h->lidx, (size_t)h->cap_main * sizeof(uint32_t)));
   HIPC(hipMalloc(&h->lkey, (size_t)h->cap_main * key_size(h)));
@@ -324,7 +313,7 @@ int build(ddqmc_t *h, int nslots, int Nmax, uint64_t cap, void *stream) {
   int rc;
   const size_t ks = key_size(h);
   if ((rc = check_room(list_bytes(ks, cap) + spawn_bytes(ks, std::max<uint64_t>(4096, cap / 4)) +
-                       cap * (4 * sizeof(uint32_t) + ks + sizeof(int2)))) != DDQMC_OK)
+                       loud_bytes(ks, cap))) != DDQMC_OK)
     return rc;
   if ((rc = alloc_list(h, cap)) != DDQMC_OK) return rc;
   if ((rc = alloc_spawn(h, std::max<uint64_t>(4096, cap / 4))) != DDQMC_OK) return rc;
@@ -342,7 +331,7 @@ int build(ddqmc_t *h, int nslots, int Nmax, uint64_t cap, void *stream) {
   HIPC(hipMalloc((void **)&h->spill, nslots * S_NSUM * sizeof(unsigned long long)));
   HIPC(hipMemsetAsync(h->spill, 0, nslots * S_NSUM * sizeof(unsigned long long), h->stream));
   HIPC(hipMalloc((void **)&h->series, (size_t)SERIES_CAP * nslots * SERIES_W * sizeof(int64_t)));
-  HIPC(hipMalloc((void **)&h->counts, (size_t)SERIES_CAP * 3 * sizeof(uint32_t)));
+  HIPC(hipMalloc((void **)&h->counts, (size_t)SERIES_CAP * COUNT_W * sizeof(uint32_t)));
   HIPC(hipMalloc(&h->inj_k, nslots * key_size(h)));
   HIPC(hipMalloc((void **)&h->inj_v, nslots * sizeof(int2)));
   h->hp.assign(nslots, SlotParams{});
@@ -410,16 +399,14 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
   const uint32_t g_s = clampu(sort_tiles(h->cap_sp), 1, 1u << 24);
   const uint32_t g_m = clampu(merge_tiles(h->cap_main, h->cap_sp), 1, 1u << 20);
   if (ev) HIPC(hipEventRecord(ev->e[0], s));
-  k_spawn_scan<K><<<h->nscan, NT, 0, s>>>(ak, av, h->ctrl, h->dsp, h->dss, h->loud, h->loud_cnt,
-                                         h->SB);
+  k_spawn_scan<K><<<h->nscan, NT, 0, s>>>(ak, av, h->ctrl, h->dsp, h->dss, h->lidx,
+                                         (K *)h->lkey, h->lval, h->SB);
   if (ev) HIPC(hipEventRecord(ev->e[1], s));
-  k_loud_offsets<<<1, 1024, 0, s>>>(h->ctrl, h->loud_cnt, h->loud_off, h->nscan);
-  k_loud_gather<K><<<g_loud, NT, 0, s>>>(ak, av, h->ctrl, h->loud, h->loud_cnt, h->loud_off,
-                                         h->nscan, h->lidx, (K *)h->lkey, h->lval);
+  // (the loud list is written by the scan: the gather stage is empty)
   if (ev) HIPC(hipEventRecord(ev->e[2], s));
   k_spawn_loud<K><<<g_loud, NT, 0, s>>>(h->ctrl, h->dsp, h->dss, h->lidx, (const K *)h->lkey,
-                                        h->lval, h->loud_off, h->nscan, h->heavy, (K *)h->sk[0],
-                                        h->sv[0], h->segcnt, segcap, h->SB);
+                                        h->lval, h->heavy, (K *)h->sk[0], h->sv[0], h->segcnt,
+                                        segcap, h->SB);
   if (ev) HIPC(hipEventRecord(ev->e[3], s));
   k_spawn_heavy<K><<<g_heavy, 64, 0, s>>>(ak, av, h->ctrl, h->dsp, h->dss, h->heavy,
                                           (K *)h->sk[0], h->sv[0], h->segcnt, segcap, h->SB);
@@ -478,8 +465,7 @@ int regrow(ddqmc_t *h, uint64_t need_main, uint64_t need_sp) {
     const uint64_t cap = std::min<uint64_t>(MAX_CAP, need_main + need_main / 2 + 4096);
     if (cap < need_main) return DDQMC_ECAPACITY;
     // new lists (the old ones are freed after the copy) and the larger loud arrays
-    const int room = check_room(2 * cap * (ks + sizeof(int2)) +
-                                (cap - h->cap_main) * (4 * sizeof(uint32_t) + ks + sizeof(int2)));
+    const int room = check_room(list_bytes(ks, cap) + loud_bytes(ks, cap - h->cap_main));
     if (room != DDQMC_OK) return room;
     void *nk[2];
     int2 *nv[2];
@@ -614,7 +600,7 @@ int run_steps(ddqmc_t *h, int64_t n) {
           const int64_t *row = &rows[((size_t)r * h->nslots + s) * SERIES_W];
           if (row[0] >= 1) h->hseries[s].insert(h->hseries[s].end(), row, row + SERIES_W);
         }
-      std::vector<uint32_t> cnt((size_t)done * 3);
+      std::vector<uint32_t> cnt((size_t)done * COUNT_W);
       HIPC(hipMemcpy(cnt.data(), h->counts, cnt.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
       h->hcounts.insert(h->hcounts.end(), cnt.begin(), cnt.end());
     }
@@ -1069,10 +1055,10 @@ int ddqmc_get_series(ddqmc_t *h, int32_t slot, int64_t *rows, int64_t cap, int64
 
 int ddqmc_get_step_counts(ddqmc_t *h, int64_t *rows, int64_t cap, int64_t *n) {
   if (!h || !n) return DDQMC_EINVAL;
-  const int64_t nr = (int64_t)(h->hcounts.size() / 3);
+  const int64_t nr = (int64_t)(h->hcounts.size() / COUNT_W);
   *n = nr;
   if (rows && cap > 0)
-    std::memcpy(rows, h->hcounts.data(), (size_t)std::min(cap, nr) * 3 * sizeof(int64_t));
+    std::memcpy(rows, h->hcounts.data(), (size_t)std::min(cap, nr) * COUNT_W * sizeof(int64_t));
   return DDQMC_OK;
 }
 
@@ -1084,7 +1070,7 @@ int ddqmc_workspace_query(const ddqmc_params *p, int64_t capacity, size_t *bytes
   const size_t ks = (2 * N > 32) ? 8 : 4;
   const uint64_t cm = capacity > 0 ? (uint64_t)capacity : auto_capacity(*p);
   const uint64_t cs = std::max<uint64_t>(4096, cm / 4);
-  *bytes = list_bytes(ks, cm) + spawn_bytes(ks, cs) + merge_bytes(cm, cs) +
+  *bytes = list_bytes(ks, cm) + loud_bytes(ks, cm) + spawn_bytes(ks, cs) + merge_bytes(cm, cs) +
            MAX_PASSES * 256 * 4 + sizeof(Ctrl) + sizeof(SlotParams) + sizeof(SlotState) +
            SERIES_CAP * SERIES_W * 8;
   return DDQMC_OK;

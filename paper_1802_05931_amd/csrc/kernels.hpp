@@ -38,6 +38,7 @@ constexpr int MERGE_TILE = NT * MERGE_IT;
 constexpr int STAGE = 2048;          // spawn records staged in LDS per block iteration
 constexpr int MAX_PASSES = 8;
 constexpr int NSEG = 64;             // spawn-record segments
+constexpr int COUNT_W = 5;           // per-step counts: in, records, out, loud, heavy
 constexpr int SEG_STRIDE = 32;       // their counters sit 128 bytes apart
 constexpr int32_t NON_INIT = INT32_MIN;  // marks the unused part of a non-initiator record
 constexpr int MAX_SLOTS = 512;
@@ -66,6 +67,8 @@ struct Ctrl {
   uint32_t last_spawn;  // records of the last completed step
   uint32_t seg_need;    // largest segment fill of a failed step
   uint32_t n_heavy;     // loud entries that need the general sampling path
+  uint32_t n_loud;      // entries with some event this step
+  uint32_t loud_next;   // next chunk of loud entries to hand out
   uint32_t seg_prefix[NSEG + 1];  // record offsets of the segments
 };
 
@@ -170,17 +173,25 @@ __device__ __forceinline__ K low_mask(int SB) {
 
 // ---- spawn ----------------------------------------------------------------
 // Pass 1: the quiet test of every entry (one Philox block).  Block b owns the
-// entries [b*chunk, (b+1)*chunk); the loud ones go to loud[b*chunk + ...] in any
-// order, their number to loud_cnt[b].
+// entries [b*chunk, (b+1)*chunk).  The loud ones are staged in LDS with their
+// key and value and appended to one dense list (entry index, key, value) of
+// ctrl->n_loud entries; a block reserves its room with one atomic per flush,
+// so the list's order varies between runs (nothing downstream depends on it).
+constexpr uint32_t LOUD_STAGE = 1024;  // staged loud entries per block (>= 2 NT)
+
 template <typename K>
 __global__ __launch_bounds__(NT) void k_spawn_scan(const K *__restrict__ keys,
                                                    const int2 *__restrict__ vals, Ctrl *ctrl,
                                                    const SlotParams *__restrict__ sp,
                                                    const SlotState *__restrict__ ss,
-                                                   uint32_t *__restrict__ loud,
-                                                   uint32_t *__restrict__ loud_cnt, int SB) {
+                                                   uint32_t *__restrict__ lidx,
+                                                   K *__restrict__ lkey, int2 *__restrict__ lval,
+                                                   int SB) {
   if (ctrl->abort) return;
-  __shared__ uint32_t lcount;
+  __shared__ uint32_t lcount, lbase;
+  __shared__ uint32_t s_i[LOUD_STAGE];
+  __shared__ K s_k[LOUD_STAGE];
+  __shared__ int2 s_v[LOUD_STAGE];
   const uint32_t n = ctrl->n_main;
   const uint32_t chunk = scan_chunk(n, gridDim.x);
   const uint32_t b0 = blockIdx.x * chunk;
@@ -190,18 +201,34 @@ __global__ __launch_bounds__(NT) void k_spawn_scan(const K *__restrict__ keys,
   const uint64_t lt = (1ull << lane) - 1ull;
   if (threadIdx.x == 0) lcount = 0;
   __syncthreads();
-  // the loop bound is wave-uniform so every lane reaches the ballot
-  for (uint32_t base = b0 + (threadIdx.x & ~63u); base < b1; base += NT) {
-    const uint32_t i = base + (uint32_t)lane;  // lane 0 always holds an entry
+  // called by the whole block: the staged entries go to the dense list
+  auto flush = [&]() {
+    const uint32_t c = lcount;
+    if (threadIdx.x == 0) lbase = c ? atomicAdd(&ctrl->n_loud, c) : 0u;
+    __syncthreads();
+    const uint32_t b = lbase;
+    for (uint32_t q = threadIdx.x; q < c; q += NT) {
+      lidx[b + q] = s_i[q];
+      lkey[b + q] = s_k[q];
+      lval[b + q] = s_v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) lcount = 0;
+    __syncthreads();
+  };
+  // block-uniform trip count: every thread reaches the ballots and barriers
+  for (uint32_t base = b0; base < b1; base += NT) {
+    const uint32_t i = base + threadIdx.x;
     const bool valid = i < b1;
     K key = 0;
+    int2 v = make_int2(0, 0);
     uint32_t slot = 0;
     if (valid) {
       key = keys[i];
+      v = vals[i];
       slot = slot_of<K>(key, SB);
     }
     auto quiet_test = [&](const SlotParams &P, double S, uint32_t step) {
-      const int2 v = vals[i];
       const uint64_t cfg = (uint64_t)(key & lowm);
       const uint32_t N = P.N;
       const uint32_t l = (uint32_t)(cfg >> N);
@@ -228,11 +255,18 @@ __global__ __launch_bounds__(NT) void k_spawn_scan(const K *__restrict__ keys,
       uint32_t qbase = 0;
       if (lane == leader) qbase = atomicAdd(&lcount, (uint32_t)__popcll(mask));
       qbase = __shfl(qbase, leader, 64);
-      if (is_loud) loud[b0 + qbase + (uint32_t)__popcll(mask & lt)] = i;
+      if (is_loud) {
+        const uint32_t pos = qbase + (uint32_t)__popcll(mask & lt);
+        s_i[pos] = i;
+        s_k[pos] = key;
+        s_v[pos] = v;
+      }
     }
+    __syncthreads();
+    // room for the next iteration's NT entries
+    if (lcount > LOUD_STAGE - NT) flush();
   }
-  __syncthreads();
-  if (threadIdx.x == 0) loud_cnt[blockIdx.x] = lcount;
+  flush();
 }
 
 // Append records to segment seg (its counter is segcnt[seg * SEG_STRIDE]).
@@ -252,30 +286,6 @@ __device__ __forceinline__ void seg_flush(const K *sk, const int2 *sv, uint32_t 
   __syncthreads();
 }
 
-// Offsets of the scan blocks' loud queues: loud_off[b] = sum of loud_cnt[< b],
-// loud_off[nscan] = all loud entries.  One block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_loud_offsets(Ctrl *ctrl, const uint32_t *loud_cnt,
-                                                       uint32_t *loud_off, uint32_t nscan) {
-  if (ctrl->abort) return;
-  __shared__ uint32_t wsum[16];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const uint32_t per = (nscan + 1023) / 1024;
-  const uint32_t b0 = tid * per, b1 = (b0 + per < nscan) ? b0 + per : nscan;
-  uint32_t local = 0;
-  for (uint32_t b = b0; b < b1; ++b) local += loud_cnt[b];
-  const uint32_t inc = wave_incl_scan(local);
-  if (lane == 63) wsum[w] = inc;
-  __syncthreads();
-  uint32_t before = 0;
-  for (int i = 0; i < w; ++i) before += wsum[i];
-  uint32_t run = before + inc - local;
-  for (uint32_t b = b0; b < b1; ++b) {
-    loud_off[b] = run;
-    run += loud_cnt[b];
-  }
-  if (tid == 1023) loud_off[nscan] = before + inc;
-}
-
 // seg_flush for a 64-thread block.
 template <typename K>
 __device__ __forceinline__ void seg_flush64(const K *sk, const int2 *sv, uint32_t c, int seg,
@@ -293,10 +303,6 @@ __device__ __forceinline__ void seg_flush64(const K *sk, const int2 *sv, uint32_
   __syncthreads();
 }
 
-// Pass 2: the loud entries, densely (flat index over all scan blocks): clone/
-// death and spawning counts and their records.  The initiator rule is applied
-// in the merge: a record from a non-initiator parent carries NON_INIT in its
-// unused (re or im) part.
 // Emitter shared by the loud kernels: record (key, contribution) into the
 // block's LDS stage, or straight into its segment when the stage is full.
 template <typename K, uint32_t CAP = STAGE>
@@ -334,51 +340,40 @@ struct RecordSink {
   }
 };
 
-// The loud queues of all scan blocks as one flat list (entry index, key, value),
-// so the loud kernel reads them with coalesced loads.
-template <typename K>
-__global__ __launch_bounds__(NT) void k_loud_gather(
-    const K *__restrict__ keys, const int2 *__restrict__ vals, Ctrl *ctrl,
-    const uint32_t *__restrict__ loud, const uint32_t *__restrict__ loud_cnt,
-    const uint32_t *__restrict__ loud_off, uint32_t nscan, uint32_t *__restrict__ lidx,
-    K *__restrict__ lkey, int2 *__restrict__ lval) {
-  if (ctrl->abort) return;
-  const uint32_t chunk = scan_chunk(ctrl->n_main, nscan);
-  for (uint32_t b = blockIdx.x; b < nscan; b += gridDim.x) {
-    const uint32_t cnt = loud_cnt[b], off = loud_off[b];
-    for (uint32_t q = threadIdx.x; q < cnt; q += NT) {
-      const uint32_t i = loud[b * chunk + q];
-      lidx[off + q] = i;
-      lkey[off + q] = keys[i];
-      lval[off + q] = vals[i];
-    }
-  }
-}
-
-// Pass 2: the loud entries, densely (flat index over all scan blocks).  Entries
-// whose draws all take the inversion branch are done here; the others (large
+// Pass 2: the loud entries, densely (the list the scan wrote).  Entries whose
+// draws all take the inversion branch are done here; the others (large
 // populations) are queued for k_spawn_heavy.  The initiator rule is applied in
 // the merge: a record from a non-initiator parent carries NON_INIT in its
 // unused (re or im) part.
 template <typename K>
-__global__ __launch_bounds__(NT) void k_spawn_loud(
+__global__ __launch_bounds__(NT, 3) void k_spawn_loud(
     Ctrl *ctrl, const SlotParams *__restrict__ sp, const SlotState *__restrict__ ss,
     const uint32_t *__restrict__ lidx, const K *__restrict__ lkey, const int2 *__restrict__ lval,
-    const uint32_t *__restrict__ loud_off, uint32_t nscan, uint32_t *__restrict__ heavy,
-    K *__restrict__ ok, int2 *__restrict__ ov, uint32_t *segcnt, uint32_t segcap, int SB) {
+    uint32_t *__restrict__ heavy, K *__restrict__ ok, int2 *__restrict__ ov, uint32_t *segcnt,
+    uint32_t segcap, int SB) {
   if (ctrl->abort) return;
   __shared__ K sk[STAGE];
   __shared__ int2 sv[STAGE];
   __shared__ uint32_t scount, sbase;
-  const uint32_t nl = loud_off[nscan];
+  const uint32_t nl = ctrl->n_loud;
   const int seg = blockIdx.x % NSEG;
   const K lowm = low_mask<K>(SB);
   int rng_err = 0;
   bool int_ovf = false;
   const RecordSink<K> sink{sk, sv, &scount, segcnt, ok, ov, segcap, seg, &int_ovf};
-  for (uint32_t base = blockIdx.x * NT; base < nl; base += gridDim.x * NT) {
+  // chunks of NT entries are handed out by a counter, so that blocks that drew
+  // cheap chunks take more of them; the next chunk is claimed while the
+  // current one is sampled
+  __shared__ uint32_t s_chunk, s_next;
+  if (threadIdx.x == 0) s_chunk = atomicAdd(&ctrl->loud_next, 1u);
+  __syncthreads();
+  for (;;) {
+    const uint32_t base = s_chunk * NT;
+    if (base >= nl) break;
     if (threadIdx.x == 0) scount = 0;
     __syncthreads();
+    // the last wave claims the next chunk (its wait overlaps the other waves' sampling)
+    if (threadIdx.x == NT - 64) s_next = atomicAdd(&ctrl->loud_next, 1u);
     const uint32_t q = base + threadIdx.x;
     if (q < nl) {
       const K key = lkey[q];
@@ -400,6 +395,9 @@ __global__ __launch_bounds__(NT) void k_spawn_loud(
     __syncthreads();
     seg_flush(sk, sv, scount < (uint32_t)STAGE ? scount : (uint32_t)STAGE, seg, segcnt, ok, ov,
               segcap, &sbase);
+    // seg_flush ends with a barrier: every thread has read s_chunk
+    if (threadIdx.x == 0) s_chunk = s_next;
+    __syncthreads();
   }
   if (rng_err) atomicOr(&ctrl->flags, F_RNG);
   if (int_ovf) atomicOr(&ctrl->flags, F_INT_OVF);
@@ -465,12 +463,25 @@ __global__ __launch_bounds__(64) void k_spawn_heavy(
       sink(hibits | (K)(((uint64_t)cl << N) | cm), dr, di, keep);
     };
 
-    // channel counts (a short sequential search: lane 0), then broadcast
-    int64_t x[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (lane == 0) channel_counts(e.p8, e.n8, e.cnt, x);
+    // which channels fire (the primary stream's search, the same on every lane),
+    // then lanes 0..7 draw the firing channels' counts at once: each count has
+    // its own stream, so the order of the draws does not matter
+    bool split_all;
+    const uint32_t ev = event_channels(e.p8, e.n8, e.cnt, &split_all);
+    int64_t x = 0;
+    if (lane < 8 && ((ev >> lane) & 1u)) {
+      double pl = e.p8[0];
+      int64_t nl = e.n8[0];
+#pragma unroll
+      for (int k = 1; k < 8; ++k) {
+        pl = lane == k ? e.p8[k] : pl;
+        nl = lane == k ? e.n8[k] : nl;
+      }
+      x = e.cnt.inl(draw_channel((uint32_t)lane + 1u), nl, pl, split_all ? DRAW_SPLIT : DRAW_POS);
+    }
     int64_t X[8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) X[c] = __shfl(x[c], 0, 64);
+    for (int c = 0; c < 8; ++c) X[c] = __shfl(x, c, 64);
     if (lane == 0) {
       const int64_t dR = e.sR * sgnd(e.d_r) * X[0] - e.sI * sgnd(e.d_i) * X[5];
       const int64_t dI = e.sI * sgnd(e.d_r) * X[4] + e.sR * sgnd(e.d_i) * X[1];
@@ -503,8 +514,8 @@ __global__ __launch_bounds__(64) void k_spawn_heavy(
       for (int c = 0; c < 6; ++c) {
         if (rem == 0 || e.hc.W[c] == 0.0) continue;
         const int64_t mc = (c == last) ? rem
-                                       : e.cnt(draw_channel(ch) + 1u + (uint32_t)c, rem,
-                                               e.hc.W[c] / e.Sc[c], DRAW_BIN);
+                                       : e.cnt.inl(draw_channel(ch) + 1u + (uint32_t)c, rem,
+                                                   e.hc.W[c] / e.Sc[c], DRAW_BIN);
         Mc[c] = mc;
         rem -= mc;
       }
@@ -585,8 +596,8 @@ __global__ __launch_bounds__(64) void k_spawn_heavy(
             }
           } else {
             const int mid = lo + (hi - lo) / 2;
-            const int64_t ML = e.cnt(base + (uint32_t)h, M,
-                                     (double)(mid - lo) / (double)(hi - lo), DRAW_BIN);
+            const int64_t ML = e.cnt.inl(base + (uint32_t)h, M,
+                                         (double)(mid - lo) / (double)(hi - lo), DRAW_BIN);
             if (ML > 0) {
               child[nchild] = (uint32_t)t | (uint32_t)lo << 5 | (uint32_t)mid << 12 |
                               (uint32_t)(2 * h) << 19;
@@ -1211,13 +1222,13 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctrl *ctrl, const SlotParams 
   const uint32_t total = ctrl->n_main + ctrl->n_spawn;
   const uint32_t ntiles = (total + MERGE_TILE - 1) / MERGE_TILE;
   {
-    // contiguous chunk of tiles per thread; tiles are ordered by solve
-    const uint32_t per = (ntiles + nt - 1) / nt;
-    const uint32_t c0 = per * tid, c1 = (c0 + per < ntiles) ? c0 + per : ntiles;
+    // tiles strided over the threads (coalesced reads); a thread's sums go to
+    // LDS whenever its solve changes, and at the end a wave whose lanes all
+    // hold the same solve adds its sums once
     int cur = -1;
     int64_t a[S_NSUM];
     for (int s = 0; s < S_NSUM; ++s) a[s] = 0;
-    for (uint32_t t = c0; t < c1; ++t) {
+    for (uint32_t t = (uint32_t)tid; t < ntiles; t += (uint32_t)nt) {
       const int sl = partials[t].slot;
       if (sl != cur) {
         if (cur >= 0)
@@ -1228,9 +1239,19 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctrl *ctrl, const SlotParams 
       }
       for (int s = 0; s < S_NSUM; ++s) a[s] += partials[t].s[s];
     }
-    if (cur >= 0)
+    const int c0 = __shfl(cur, 0, 64);
+    const bool same = __ballot(cur != c0) == 0;  // wave-uniform
+    if (same) {
+#pragma unroll
+      for (int s = 0; s < S_NSUM; ++s) {
+        const int64_t v = wave_sum(a[s]);
+        if ((tid & 63) == 0 && c0 >= 0 && v)
+          atomicAdd(&sums[c0 * S_NSUM + s], (unsigned long long)v);
+      }
+    } else if (cur >= 0) {
       for (int s = 0; s < S_NSUM; ++s)
         if (a[s]) atomicAdd(&sums[cur * S_NSUM + s], (unsigned long long)a[s]);
+    }
   }
   __syncthreads();
   uint32_t flags = ctrl->flags;
@@ -1311,15 +1332,19 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctrl *ctrl, const SlotParams 
   for (int i = tid; i < NSEG; i += nt) segcnt[i * SEG_STRIDE] = 0;
   if (tid == 0) {
     if (row < series_cap) {
-      counts[3 * row + 0] = ctrl->n_main;
-      counts[3 * row + 1] = ctrl->n_spawn;
-      counts[3 * row + 2] = n_new;
+      counts[COUNT_W * row + 0] = ctrl->n_main;
+      counts[COUNT_W * row + 1] = ctrl->n_spawn;
+      counts[COUNT_W * row + 2] = n_new;
+      counts[COUNT_W * row + 3] = ctrl->n_loud;
+      counts[COUNT_W * row + 4] = ctrl->n_heavy;
     }
     ctrl->n_main = n_new;
     ctrl->last_spawn = ctrl->n_spawn;
     ctrl->n_spawn = 0;
     ctrl->n_inject = 0;
     ctrl->n_heavy = 0;
+    ctrl->n_loud = 0;
+    ctrl->loud_next = 0;
     ctrl->epoch += 1;
     ctrl->committed += 1;
     ctrl->series_pos = row + 1;
@@ -1335,6 +1360,8 @@ __global__ void k_rearm(Ctrl *ctrl, uint32_t *hist, int passes, unsigned long lo
   if (threadIdx.x == 0) {
     ctrl->n_spawn = 0;
     ctrl->n_heavy = 0;
+    ctrl->n_loud = 0;
+    ctrl->loud_next = 0;
     ctrl->n_new = 0;
     ctrl->flags = 0;
     ctrl->abort = 0;

@@ -353,10 +353,9 @@ struct Count {
 };
 enum { DRAW_BIN = 0, DRAW_POS = 1, DRAW_SPLIT = 2 };
 
-__host__ __device__ __attribute__((noinline)) Count draw_count(uint64_t seed, uint32_t solve,
-                                                               uint64_t cfg, uint32_t step,
-                                                               uint32_t draw, int64_t n, double p,
-                                                               int mode) {
+__host__ __device__ __attribute__((always_inline)) inline Count draw_count_inline(
+    uint64_t seed, uint32_t solve, uint64_t cfg, uint32_t step, uint32_t draw, int64_t n, double p,
+    int mode) {
   int e = 0;
   Stream st(seed, solve, cfg, step, draw, &e);
   int64_t x;
@@ -369,12 +368,26 @@ __host__ __device__ __attribute__((noinline)) Count draw_count(uint64_t seed, ui
   return Count{x, e};
 }
 
+__host__ __device__ __attribute__((noinline)) Count draw_count(uint64_t seed, uint32_t solve,
+                                                               uint64_t cfg, uint32_t step,
+                                                               uint32_t draw, int64_t n, double p,
+                                                               int mode) {
+  return draw_count_inline(seed, solve, cfg, step, draw, n, p, mode);
+}
+
 struct EntryCounter {
   uint64_t seed, cfg;
   uint32_t solve, step;
   int dry;
   DQ_HD int64_t operator()(uint32_t draw, int64_t n, double p, int mode) {
     const Count c = draw_count(seed, solve, cfg, step, draw, n, p, mode);
+    dry |= c.dry;
+    return c.x;
+  }
+  // the same draw inline, for a chain of dependent draws where a call would
+  // spill the caller's live registers to scratch memory around every draw
+  DQ_HD int64_t inl(uint32_t draw, int64_t n, double p, int mode) {
+    const Count c = draw_count_inline(seed, solve, cfg, step, draw, n, p, mode);
     dry |= c.dry;
     return c.x;
   }
@@ -391,27 +404,31 @@ constexpr uint32_t DRAW_PICK = 7u;
 // the running products of the zero probabilities; below the last product no
 // further channel fires, otherwise the first product u exceeds names the next
 // nonzero channel, drawn given >= 1, and the search resumes after it.
-DQ_HD void channel_counts(const double p[8], const int64_t n[8], EntryCounter &cnt,
-                          int64_t X[8]) {
+//
+// event_channels: which channels fire (bit k for channel k), from the search
+// alone, which needs only the primary stream.  *all is set when some p_k >= 1;
+// then every channel is drawn as integer part + Bin(n, fraction).
+DQ_HD uint32_t event_channels(const double p[8], const int64_t n[8], const EntryCounter &cnt,
+                              bool *all) {
   bool loud = false;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    X[k] = 0;
-    loud = loud || (n[k] > 0 && p[k] >= 1.0);
-  }
-  if (loud) {
+  for (int k = 0; k < 8; ++k) loud = loud || (n[k] > 0 && p[k] >= 1.0);
+  *all = loud;
+  if (loud) return 0xffu;
+  // each channel's zero probability once (1 for a channel that cannot fire:
+  // multiplying by it leaves the running product as it is)
+  double f[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) X[k] = cnt(draw_channel(k + 1), n[k], p[k], DRAW_SPLIT);
-    return;
-  }
+  for (int k = 0; k < 8; ++k) f[k] = (n[k] > 0 && p[k] > 0.0) ? ipow(1.0 - p[k], n[k]) : 1.0;
   Stream prim(cnt.seed, cnt.solve, cnt.cfg, cnt.step, 0, nullptr);
+  uint32_t ev = 0;
   int start = 0;
   while (start < 8) {
     double G[8];
     double g = 1.0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      if (k >= start && n[k] > 0 && p[k] > 0.0) g = g * ipow(1.0 - p[k], n[k]);
+      if (k >= start) g = g * f[k];
       G[k] = g;
     }
     const double u = prim.next();
@@ -420,11 +437,22 @@ DQ_HD void channel_counts(const double p[8], const int64_t n[8], EntryCounter &c
 #pragma unroll
     for (int k = 7; k >= 0; --k)
       if (k >= start && u >= G[k]) first = k;
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (k == first) X[k] = cnt(draw_channel(k + 1), n[k], p[k], DRAW_POS);
+    ev |= 1u << first;
     start = first + 1;
   }
+  return ev;
+}
+
+// The counts of the firing channels, each from its own stream (so the draws do
+// not depend on the order they are taken in).
+DQ_HD void channel_counts(const double p[8], const int64_t n[8], EntryCounter &cnt,
+                          int64_t X[8]) {
+  bool all;
+  const uint32_t ev = event_channels(p, n, cnt, &all);
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    X[k] = ((ev >> k) & 1u) ? cnt(draw_channel(k + 1), n[k], p[k], all ? DRAW_SPLIT : DRAW_POS)
+                            : 0;
 }
 
 }  // namespace ddqmc
