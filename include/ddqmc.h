@@ -176,7 +176,9 @@ int ddqmc_workspace_query(const ddqmc_params *p, int64_t capacity, size_t *bytes
  * events on the handle's stream when profiling is on (ddqmc_set_profiling);
  * ms[10] = quiet scan (which also writes the list of loud entries), loud
  * gather (kept for the layout of ms; empty, since the scan writes that list),
- * loud spawn (the spawn kernel alone), heavy spawn, record seal, histogram,
+ * loud spawn (the spawn kernel alone), heavy spawn (the entries the loud
+ * kernel passed on, and the wait for the heavy kernel that ran on a second
+ * stream next to the loud one), record seal, histogram,
  * sort (the radix passes and the merge-path partition), merge count
  * (survivors per tile and their offsets), merge (the merge kernel that writes
  * the new list), finalize, summed over the call's steps. */
@@ -190,6 +192,15 @@ int ddqmc_set_profiling(ddqmc_t *h, int32_t on);
  * same either way: a graph holds the same kernels with the same grids, and
  * each kernel reads its counts from device memory.  EINVAL for other k. */
 int ddqmc_set_graph_steps(ddqmc_t *h, int32_t k);
+
+/* Where the entries with large populations are sampled.  They are known after
+ * the quiet scan; with the fork on, their kernel runs on a second stream of
+ * the handle, next to the kernel that samples the other loud entries, and the
+ * main stream waits for it before the records are sorted.  mode 0 (default):
+ * on when the list capacity is at least 2^23 entries (below that a fork and
+ * join cost more than they save), 1: always, -1: never.  The results are the
+ * same either way.  EINVAL for other modes. */
+int ddqmc_set_heavy_fork(ddqmc_t *h, int32_t mode);
 int ddqmc_stage_times(ddqmc_t *h, double ms[10], int64_t *steps);
 
 /* ---- device self-checks of the sampling primitives --------------------------

@@ -118,6 +118,10 @@ class _Handle:
         """Run k steps per HIP graph launch (k even, 0 = one launch per kernel)."""
         check(lib().ddqmc_set_graph_steps(self._h, int(k)), "set_graph_steps")
 
+    def set_heavy_fork(self, mode):
+        """Large-population entries on a second stream: 0 by list size, 1 always, -1 never."""
+        check(lib().ddqmc_set_heavy_fork(self._h, int(mode)), "set_heavy_fork")
+
     def stage_times(self):
         ms = (ctypes.c_double * len(STAGES))()
         steps = ctypes.c_int64()

@@ -100,6 +100,7 @@ SIGNATURES = {
     "ddqmc_workspace_query": (ctypes.c_int, [_P(Params), ctypes.c_int64, _P(ctypes.c_size_t)]),
     "ddqmc_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "ddqmc_set_graph_steps": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "ddqmc_set_heavy_fork": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "ddqmc_stage_times": (ctypes.c_int, [_vp, _P(ctypes.c_double), _P(ctypes.c_int64)]),
     "ddqmc_dev_uniforms": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
                                           ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64,

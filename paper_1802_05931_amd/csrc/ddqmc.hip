@@ -27,6 +27,7 @@ constexpr uint32_t SERIES_CAP = 1024;  // steps per chunk between host synchroni
 // Largest list or spawn buffer, in entries: list + records stay below 2^32, so
 // every 32-bit count and index in the kernels is exact.
 constexpr uint64_t MAX_CAP = 0x7FF00000ull;
+constexpr uint64_t FORK_MIN_CAP = 1ull << 23;  // list capacity from which heavy runs beside loud
 constexpr int NSTAGE = 10;  // scan, gather, loud, heavy, seal, histogram, sort, count, merge,
                             // finalize
 
@@ -65,7 +66,8 @@ struct ddqmc_t {
   unsigned long long *spill = nullptr;
   int64_t *series = nullptr;
   uint32_t *counts = nullptr;  // per step: entries in, records, entries out, loud, heavy
-  uint32_t *heavy = nullptr;     // loud entries that need the general sampling code
+  uint32_t *heavy = nullptr;     // loud entries that need the general sampling code (scan)
+  uint32_t *late = nullptr;      // loud entries the light path passed on (loud kernel)
   uint32_t *lidx = nullptr;      // loud list (entries with some event): index, key, value
   void *lkey = nullptr;
   int2 *lval = nullptr;
@@ -89,6 +91,13 @@ struct ddqmc_t {
   int graph_k = 0;
   uint64_t buf_gen = 0;
   hipStream_t cap_stream = nullptr;
+  // second stream: the scan's heavy entries are sampled on it while the loud
+  // kernel runs on the main stream (fork and join by events)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool fork_heavy = false;  // only for large lists: a fork and join cost more than
+                            // the heavy kernel saves on a short step
+  int fork_mode = 0;        // 0 by list capacity, 1 always, -1 never
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   uint64_t gexec_gen[2] = {~0ull, ~0ull};
   int gexec_k[2] = {0, 0};
@@ -131,8 +140,8 @@ uint64_t sort_tiles(uint64_t cap) { return (cap + SORT_TILE - 1) / SORT_TILE; }
 uint64_t merge_tiles(uint64_t a, uint64_t b) { return (a + b + MERGE_TILE - 1) / MERGE_TILE; }
 
 size_t list_bytes(size_t ks, uint64_t cap) { return 2 * cap * (ks + sizeof(int2)); }
-// the loud list (index, key, value) and the heavy queue
-size_t loud_bytes(size_t ks, uint64_t cap) { return cap * (2 * sizeof(uint32_t) + ks + sizeof(int2)); }
+// the loud list (index, key, value) and the two heavy queues
+size_t loud_bytes(size_t ks, uint64_t cap) { return cap * (3 * sizeof(uint32_t) + ks + sizeof(int2)); }
 size_t spawn_bytes(size_t ks, uint64_t cap) {
   return 2 * cap * (ks + sizeof(int2)) + sort_tiles(cap) * 256 * sizeof(uint32_t);
 }
@@ -202,7 +211,7 @@ SlotState fresh_state(const ddqmc_params &p, int status) {
 void free_all(ddqmc_t *h) {
   void *ptrs[] = {h->mk[0], h->mk[1], h->mv[0], h->mv[1], h->sk[0], h->sk[1], h->sv[0],
                   h->sv[1], h->sort_cnt, h->tile_cnt, h->partials, h->hist, h->ctrl,
-                  h->dsp, h->dss, h->spill, h->series, h->counts, h->heavy, h->lidx, h->lkey, h->lval,
+                  h->dsp, h->dss, h->spill, h->series, h->counts, h->heavy, h->late, h->lidx, h->lkey, h->lval,
                   h->part, h->segcnt, h->inj_k,
                   h->inj_v};
   for (void *p : ptrs)
@@ -210,6 +219,9 @@ void free_all(ddqmc_t *h) {
   for (int p = 0; p < 2; ++p)
     if (h->gexec[p]) (void)hipGraphExecDestroy(h->gexec[p]);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  if (h->side) (void)hipStreamDestroy(h->side);
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
   for (auto &e : h->ev)
     for (int i = 0; i <= NSTAGE; ++i) (void)hipEventDestroy(e.e[i]);
   h->ev.clear();
@@ -224,6 +236,8 @@ uint32_t clampu(uint64_t v, uint32_t lo, uint32_t hi) {
 // most one slot per list entry.
 int alloc_loud(ddqmc_t *h) {
   if (h->heavy) HIPC(hipFree(h->heavy));
+  if (h->late) HIPC(hipFree(h->late));
+  h->late = nullptr;
   if (h->lidx) HIPC(hipFree(h->lidx));
   if (h->lkey) HIPC(hipFree(h->lkey));
   if (h->lval) HIPC(hipFree(h->lval));
@@ -232,7 +246,9 @@ int alloc_loud(ddqmc_t *h) {
   h->lkey = nullptr;
   h->lval = nullptr;
   h->nscan = clampu((h->cap_main + NT - 1) / NT, 1, 4096);
+  h->fork_heavy = h->fork_mode > 0 || (h->fork_mode == 0 && h->cap_main >= FORK_MIN_CAP);
   HIPC(hipMalloc((void **)&h->heavy, (size_t)h->cap_main * sizeof(uint32_t)));
+  HIPC(hipMalloc((void **)&h->late, (size_t)h->cap_main * sizeof(uint32_t)));
   HIPC(hipMalloc((void **)&h->lidx, (size_t)h->cap_main * sizeof(uint32_t)));
   HIPC(hipMalloc(&h->lkey, (size_t)h->cap_main * key_size(h)));
   HIPC(hipMalloc((void **)&h->lval, (size_t)h->cap_main * sizeof(int2)));
@@ -280,6 +296,9 @@ int build(ddqmc_t *h, int nslots, int Nmax, uint64_t cap, void *stream) {
     HIPC(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
     h->own_stream = true;
   }
+  HIPC(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+  HIPC(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming | hipEventReleaseToDevice));
+  HIPC(hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming | hipEventReleaseToDevice));
   h->nslots = nslots;
   h->Nmax = Nmax;
   h->SB = 2 * Nmax;
@@ -400,16 +419,30 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
   const uint32_t g_m = clampu(merge_tiles(h->cap_main, h->cap_sp), 1, 1u << 20);
   if (ev) HIPC(hipEventRecord(ev->e[0], s));
   k_spawn_scan<K><<<h->nscan, NT, 0, s>>>(ak, av, h->ctrl, h->dsp, h->dss, h->lidx,
-                                         (K *)h->lkey, h->lval, h->SB);
+                                         (K *)h->lkey, h->lval, h->heavy, h->SB);
   if (ev) HIPC(hipEventRecord(ev->e[1], s));
-  // (the loud list is written by the scan: the gather stage is empty)
+  Ctrl *c = h->ctrl;
+  if (h->fork_heavy) {
+    // the scan's heavy list on the second stream, alongside the loud kernel
+    HIPC(hipEventRecord(h->ev_fork, s));
+    HIPC(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+    k_spawn_heavy<K><<<g_heavy, 64, 0, h->side>>>(ak, av, c, h->dsp, h->dss, h->heavy,
+                                                  &c->n_heavy, (K *)h->sk[0], h->sv[0],
+                                                  h->segcnt, segcap, h->SB);
+    HIPC(hipEventRecord(h->ev_join, h->side));
+  }
   if (ev) HIPC(hipEventRecord(ev->e[2], s));
-  k_spawn_loud<K><<<g_loud, NT, 0, s>>>(h->ctrl, h->dsp, h->dss, h->lidx, (const K *)h->lkey,
-                                        h->lval, h->heavy, (K *)h->sk[0], h->sv[0], h->segcnt,
-                                        segcap, h->SB);
+  uint32_t *late = h->fork_heavy ? h->late : h->heavy;
+  uint32_t *nlate = h->fork_heavy ? &c->n_late : &c->n_heavy;
+  k_spawn_loud<K><<<g_loud, NT, 0, s>>>(c, h->dsp, h->dss, h->lidx, (const K *)h->lkey, h->lval,
+                                        late, nlate, (K *)h->sk[0], h->sv[0], h->segcnt, segcap,
+                                        h->SB);
   if (ev) HIPC(hipEventRecord(ev->e[3], s));
-  k_spawn_heavy<K><<<g_heavy, 64, 0, s>>>(ak, av, h->ctrl, h->dsp, h->dss, h->heavy,
-                                          (K *)h->sk[0], h->sv[0], h->segcnt, segcap, h->SB);
+  // the entries the loud kernel passed on (with the fork: usually none), then
+  // the join
+  k_spawn_heavy<K><<<h->fork_heavy ? clampu(g_heavy, 1, 512) : g_heavy, 64, 0, s>>>(
+      ak, av, c, h->dsp, h->dss, late, nlate, (K *)h->sk[0], h->sv[0], h->segcnt, segcap, h->SB);
+  if (h->fork_heavy) HIPC(hipStreamWaitEvent(s, h->ev_join, 0));
   if (ev) HIPC(hipEventRecord(ev->e[4], s));
   if (h->pool)
     k_inject<K><<<1, NT, 0, s>>>((const K *)h->inj_k, h->inj_v, h->ctrl, (K *)h->sk[0], h->sv[0],
@@ -556,7 +589,8 @@ int run_steps(ddqmc_t *h, int64_t n) {
     const size_t old = h->ev.size();
     h->ev.resize(SERIES_CAP);
     for (size_t i = old; i < h->ev.size(); ++i)
-      for (int j = 0; j <= NSTAGE; ++j) HIPC(hipEventCreate(&h->ev[i].e[j]));
+      for (int j = 0; j <= NSTAGE; ++j)
+        HIPC(hipEventCreateWithFlags(&h->ev[i].e[j], hipEventReleaseToDevice));
   }
   for (int i = 0; i < NSTAGE; ++i) h->stage_ms[i] = 0.0;
   h->stage_steps = 0;
@@ -1086,6 +1120,14 @@ int ddqmc_set_graph_steps(ddqmc_t *h, int32_t k) {
   if (!h || k < 0 || (k > 0 && (k < 2 || (k & 1) || k > (int32_t)SERIES_CAP)))
     return DDQMC_EINVAL;
   h->graph_k = k;
+  return DDQMC_OK;
+}
+
+int ddqmc_set_heavy_fork(ddqmc_t *h, int32_t mode) {
+  if (!h || mode < -1 || mode > 1) return DDQMC_EINVAL;
+  h->fork_mode = mode;
+  h->fork_heavy = mode > 0 || (mode == 0 && h->cap_main >= FORK_MIN_CAP);
+  h->buf_gen += 1;  // captured graphs hold the other launch sequence
   return DDQMC_OK;
 }
 

@@ -66,7 +66,8 @@ struct Ctrl {
   uint32_t extinct_slot;
   uint32_t last_spawn;  // records of the last completed step
   uint32_t seg_need;    // largest segment fill of a failed step
-  uint32_t n_heavy;     // loud entries that need the general sampling path
+  uint32_t n_heavy;     // loud entries that need the general sampling path (scan)
+  uint32_t n_late;      // loud entries the light path passed on (loud kernel)
   uint32_t n_loud;      // entries with some event this step
   uint32_t loud_next;   // next chunk of loud entries to hand out
   uint32_t seg_prefix[NSEG + 1];  // record offsets of the segments
@@ -173,10 +174,12 @@ __device__ __forceinline__ K low_mask(int SB) {
 
 // ---- spawn ----------------------------------------------------------------
 // Pass 1: the quiet test of every entry (one Philox block).  Block b owns the
-// entries [b*chunk, (b+1)*chunk).  The loud ones are staged in LDS with their
-// key and value and appended to one dense list (entry index, key, value) of
-// ctrl->n_loud entries; a block reserves its room with one atomic per flush,
-// so the list's order varies between runs (nothing downstream depends on it).
+// entries [b*chunk, (b+1)*chunk).  The loud ones whose channels can all be
+// drawn by inversion are staged in LDS with their key and value and appended
+// to one dense list (entry index, key, value) of ctrl->n_loud entries; a block
+// reserves its room with one atomic per flush, so the list's order varies
+// between runs (nothing downstream depends on it).  The other loud entries
+// (large populations, a few hundred) go straight to the heavy list.
 constexpr uint32_t LOUD_STAGE = 1024;  // staged loud entries per block (>= 2 NT)
 
 template <typename K>
@@ -186,7 +189,7 @@ __global__ __launch_bounds__(NT) void k_spawn_scan(const K *__restrict__ keys,
                                                    const SlotState *__restrict__ ss,
                                                    uint32_t *__restrict__ lidx,
                                                    K *__restrict__ lkey, int2 *__restrict__ lval,
-                                                   int SB) {
+                                                   uint32_t *__restrict__ heavy, int SB) {
   if (ctrl->abort) return;
   __shared__ uint32_t lcount, lbase;
   __shared__ uint32_t s_i[LOUD_STAGE];
@@ -228,14 +231,14 @@ __global__ __launch_bounds__(NT) void k_spawn_scan(const K *__restrict__ keys,
       v = vals[i];
       slot = slot_of<K>(key, SB);
     }
-    auto quiet_test = [&](const SlotParams &P, double S, uint32_t step) {
+    auto kind_of = [&](const SlotParams &P, double S, uint32_t step) {
       const uint64_t cfg = (uint64_t)(key & lowm);
       const uint32_t N = P.N;
       const uint32_t l = (uint32_t)(cfg >> N);
       const uint32_t m = (uint32_t)(cfg & ((N == 32) ? 0xffffffffull : ((1ull << N) - 1)));
-      return !entry_quiet(P, S, step, l, m, v.x, v.y);
+      return entry_kind(P, S, step, l, m, v.x, v.y);
     };
-    bool is_loud = false;
+    int kind = ENTRY_QUIET;
     // the wave's entries almost always belong to one solve: its parameters are
     // then loaded once, into scalar registers
     const uint32_t s0 = __builtin_amdgcn_readfirstlane(slot);
@@ -244,11 +247,20 @@ __global__ __launch_bounds__(NT) void k_spawn_scan(const K *__restrict__ keys,
         const SlotParams &P = sp[s0];
         const double S = ss[s0].S;
         const uint32_t step = (uint32_t)ss[s0].step;
-        if (valid) is_loud = quiet_test(P, S, step);
+        if (valid) kind = kind_of(P, S, step);
       }
     } else if (valid && ss[slot].status == 1) {
-      is_loud = quiet_test(sp[slot], ss[slot].S, (uint32_t)ss[slot].step);
+      kind = kind_of(sp[slot], ss[slot].S, (uint32_t)ss[slot].step);
     }
+    const uint64_t hmask = __ballot(kind == ENTRY_HEAVY);
+    if (hmask) {
+      const int leader = __builtin_ctzll(hmask);
+      uint32_t hb = 0;
+      if (lane == leader) hb = atomicAdd(&ctrl->n_heavy, (uint32_t)__popcll(hmask));
+      hb = __shfl(hb, leader, 64);
+      if (kind == ENTRY_HEAVY) heavy[hb + (uint32_t)__popcll(hmask & lt)] = i;
+    }
+    const bool is_loud = kind == ENTRY_LIGHT;
     const uint64_t mask = __ballot(is_loud);
     if (mask) {
       const int leader = __builtin_ctzll(mask);
@@ -341,16 +353,17 @@ struct RecordSink {
 };
 
 // Pass 2: the loud entries, densely (the list the scan wrote).  Entries whose
-// draws all take the inversion branch are done here; the others (large
-// populations) are queued for k_spawn_heavy.  The initiator rule is applied in
+// draws all take the inversion branch are done here; the few whose channel
+// search finds a spawn count too large for it are appended to late[*nlate]
+// for k_spawn_heavy.  The initiator rule is applied in
 // the merge: a record from a non-initiator parent carries NON_INIT in its
 // unused (re or im) part.
 template <typename K>
-__global__ __launch_bounds__(NT, 3) void k_spawn_loud(
+__global__ __launch_bounds__(NT) void k_spawn_loud(
     Ctrl *ctrl, const SlotParams *__restrict__ sp, const SlotState *__restrict__ ss,
     const uint32_t *__restrict__ lidx, const K *__restrict__ lkey, const int2 *__restrict__ lval,
-    uint32_t *__restrict__ heavy, K *__restrict__ ok, int2 *__restrict__ ov, uint32_t *segcnt,
-    uint32_t segcap, int SB) {
+    uint32_t *__restrict__ late, uint32_t *nlate, K *__restrict__ ok, int2 *__restrict__ ov,
+    uint32_t *segcnt, uint32_t segcap, int SB) {
   if (ctrl->abort) return;
   __shared__ K sk[STAGE];
   __shared__ int2 sv[STAGE];
@@ -390,7 +403,7 @@ __global__ __launch_bounds__(NT, 3) void k_spawn_loud(
           [&](uint32_t cl, uint32_t cm, int64_t dr, int64_t di, bool keep) {
             sink(hibits | (K)(((uint64_t)cl << N) | cm), dr, di, keep);
           });
-      if (!done) heavy[atomicAdd(&ctrl->n_heavy, 1u)] = lidx[q];
+      if (!done) late[atomicAdd(nlate, 1u)] = lidx[q];
     }
     __syncthreads();
     seg_flush(sk, sv, scount < (uint32_t)STAGE ? scount : (uint32_t)STAGE, seg, segcnt, ok, ov,
@@ -404,7 +417,10 @@ __global__ __launch_bounds__(NT, 3) void k_spawn_loud(
 }
 
 // Pass 3: the entries with large populations, one 64-lane block (one wave) per
-// entry.  Lanes 0..7 draw the eight channel counts at once; lanes 0 and 1 split
+// entry, for the list heavy[0, *nheavy).  For a large list it runs on a second
+// stream next to the loud kernel (the scan's heavy list) and again after it
+// (the loud kernel's late list); for a small one, once after the loud kernel,
+// which then appends to the scan's list.  Lanes 0..7 draw the eight channel counts at once; lanes 0 and 1 split
 // the two hop channels over their classes; then the binomial trees of all
 // classes are walked level by level from an LDS frontier, one node per lane.
 // Every draw uses the stream of the same (channel, class, node) as in
@@ -420,8 +436,8 @@ template <typename K>
 __global__ __launch_bounds__(64) void k_spawn_heavy(
     const K *__restrict__ keys, const int2 *__restrict__ vals, Ctrl *ctrl,
     const SlotParams *__restrict__ sp, const SlotState *__restrict__ ss,
-    const uint32_t *__restrict__ heavy, K *__restrict__ ok, int2 *__restrict__ ov,
-    uint32_t *segcnt, uint32_t segcap, int SB) {
+    const uint32_t *__restrict__ heavy, const uint32_t *__restrict__ nheavy, K *__restrict__ ok,
+    int2 *__restrict__ ov, uint32_t *segcnt, uint32_t segcap, int SB) {
   if (ctrl->abort) return;
   __shared__ K sk[HEAVY_STAGE];
   __shared__ int2 sv[HEAVY_STAGE];
@@ -430,7 +446,7 @@ __global__ __launch_bounds__(64) void k_spawn_heavy(
   __shared__ int64_t fM[2][HEAVY_FRONT];
   __shared__ uint32_t s_cr[6], s_cu[6];  // class bond masks (right, up) and signs, so
   __shared__ int s_cs[6];                // that a per-lane class index reads LDS
-  const uint32_t nh = ctrl->n_heavy;
+  const uint32_t nh = *nheavy;
   const int lane = threadIdx.x;
   const int seg = (blockIdx.x + 17) % NSEG;
   const K lowm = low_mask<K>(SB);
@@ -1336,13 +1352,14 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctrl *ctrl, const SlotParams 
       counts[COUNT_W * row + 1] = ctrl->n_spawn;
       counts[COUNT_W * row + 2] = n_new;
       counts[COUNT_W * row + 3] = ctrl->n_loud;
-      counts[COUNT_W * row + 4] = ctrl->n_heavy;
+      counts[COUNT_W * row + 4] = ctrl->n_heavy + ctrl->n_late;
     }
     ctrl->n_main = n_new;
     ctrl->last_spawn = ctrl->n_spawn;
     ctrl->n_spawn = 0;
     ctrl->n_inject = 0;
     ctrl->n_heavy = 0;
+    ctrl->n_late = 0;
     ctrl->n_loud = 0;
     ctrl->loud_next = 0;
     ctrl->epoch += 1;
@@ -1360,6 +1377,7 @@ __global__ void k_rearm(Ctrl *ctrl, uint32_t *hist, int passes, unsigned long lo
   if (threadIdx.x == 0) {
     ctrl->n_spawn = 0;
     ctrl->n_heavy = 0;
+    ctrl->n_late = 0;
     ctrl->n_loud = 0;
     ctrl->loud_next = 0;
     ctrl->n_new = 0;

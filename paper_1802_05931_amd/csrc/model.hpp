@@ -268,13 +268,34 @@ DQ_HD EntryProbs entry_probs(const SlotParams &P, double S, uint32_t step, uint3
   return e;
 }
 
-// True when all eight channel counts of the entry are zero (decided by the
-// primary uniform exactly as channel_counts decides it).
+// What the step does with an entry: 0 (quiet) when all eight channel counts
+// are zero (decided by the primary uniform exactly as channel_counts decides
+// it); otherwise 2 when some channel may be too large to draw by inversion
+// (max(n_R, n_I) max_k p_k >= 10, or some p_k >= 1: a superset of the entries
+// the light path refuses, which tests n_k min(p_k, 1 - p_k) per channel),
+// else 1.  Either path gives the same counts; this only routes
+// the large populations to the general path early.
+enum { ENTRY_QUIET = 0, ENTRY_LIGHT = 1, ENTRY_HEAVY = 2 };
+DQ_HD int entry_kind(const SlotParams &P, double S, uint32_t step, uint32_t l, uint32_t m,
+                     int32_t R, int32_t I) {
+  const EntryProbs e = entry_probs(P, S, step, l, m, R, I);
+  double g = 1.0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (e.n8[k] > 0 && e.p8[k] >= 1.0) return ENTRY_HEAVY;
+    if (e.n8[k] > 0 && e.p8[k] > 0.0) g = g * ipow(1.0 - e.p8[k], e.n8[k]);
+  }
+  Stream prim(e.cnt.seed, e.cnt.solve, e.cnt.cfg, e.cnt.step, 0, nullptr);
+  if (prim.next() < g) return ENTRY_QUIET;
+  const double pm = __builtin_fmax(__builtin_fmax(e.p8[0], e.p8[1]),
+                                   __builtin_fmax(e.p8[2], e.p8[3]));
+  const int64_t nm = e.n8[0] > e.n8[4] ? e.n8[0] : e.n8[4];
+  return (double)nm * pm >= 10.0 ? ENTRY_HEAVY : ENTRY_LIGHT;
+}
+
 DQ_HD bool entry_quiet(const SlotParams &P, double S, uint32_t step, uint32_t l, uint32_t m,
                        int32_t R, int32_t I) {
   const EntryProbs e = entry_probs(P, S, step, l, m, R, I);
-  // an empty channel or one with p = 0 contributes ipow(.) = 1 exactly, which
-  // leaves the product as it is
   double g = 1.0;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {

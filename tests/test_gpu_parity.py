@@ -29,8 +29,9 @@ def _same_list(a, b):
             and np.array_equal(a[2], b[2]))
 
 
-def _compare_run(dq, orc, cfg, chunks, per, check_series=True):
+def _compare_run(dq, orc, cfg, chunks, per, check_series=True, fork=0):
     g = dq.Solve(dq.make_params(**cfg))
+    g.set_heavy_fork(fork)
     o = orc.Oracle(**{k: v for k, v in cfg.items() if k != "capacity_hint"})
     for c in range(chunks):
         g.step(per)
@@ -89,9 +90,10 @@ def test_plain_2x2_d1(dq, orc):
     assert n > 5
 
 
-def test_plain_3x3_jx06(dq, orc):
+@pytest.mark.parametrize("fork", [0, 1])
+def test_plain_3x3_jx06(dq, orc, fork):
     cfg = dict(workloads.d2(0.6), target_walkers=20000, n_equil=200)
-    n = _compare_run(dq, orc, cfg, chunks=4, per=250)
+    n = _compare_run(dq, orc, cfg, chunks=4, per=250, fork=fork)
     assert n > 2 * 2048, "should span several tiles"
 
 
@@ -101,10 +103,11 @@ def test_plain_2x6_initiator_off(dq, orc):
     _compare_run(dq, orc, cfg, chunks=3, per=60)
 
 
-def test_5x5_u64_keys(dq, orc):
+@pytest.mark.parametrize("fork", [0, 1])
+def test_5x5_u64_keys(dq, orc, fork):
     cfg = dict(Lx=5, Ly=5, Jx=0.7, Jy=1.0, Jz=1.0, gamma=1.0, dt=0.002, n_a=3,
                target_walkers=20000, initial_walkers=20000, shift_init=0.0, n_equil=10, seed=3)
-    _compare_run(dq, orc, cfg, chunks=3, per=40)
+    _compare_run(dq, orc, cfg, chunks=3, per=40, fork=fork)
 
 
 @pytest.mark.parametrize("Lx,Ly,is_p,dt,S,nent,pop,n_a", [
@@ -192,13 +195,16 @@ def test_pool_admit_retire_equals_alone(dq, orc):
     pool.close()
 
 
-def test_graph_steps_equal_eager(dq, orc):
+@pytest.mark.parametrize("fork", [0, 1])
+def test_graph_steps_equal_eager(dq, orc, fork):
     """k-step HIP graphs (replayed several times per call, re-captured after
     the buffers grow from a tiny capacity) give the eager launches' lists, which
-    the oracle checks too."""
+    the oracle checks too; with fork = 1 the heavy entries run on the second
+    stream (fork and join inside the graph)."""
     cfg = dict(workloads.d2(0.6), target_walkers=20000, capacity_hint=16, n_equil=60)
     a = dq.Solve(dq.make_params(**cfg))
     b = dq.Solve(dq.make_params(**cfg))
+    b.set_heavy_fork(fork)
     b.set_graph_steps(10)
     o = orc.Oracle(**{k: v for k, v in cfg.items() if k != "capacity_hint"})
     for per in (35, 35, 120, 7, 64):
@@ -244,6 +250,10 @@ def test_graph_steps_invalid(dq):
         assert e.value.code == -1
     g.set_graph_steps(10)
     g.set_graph_steps(0)
+    for m in (-2, 2):
+        with pytest.raises(DDQMCError) as e:
+            g.set_heavy_fork(m)
+        assert e.value.code == -1
     g.step(3)
     g.close()
 
