@@ -193,7 +193,8 @@ def counter_summary(fetch_dir, write_dir, probe_mb, workload, valu_dir=None):
     for short, name in (("k_merge_write", "k_merge<unsigned int, true>"),
                         ("k_merge_count", "k_merge<unsigned int, false>"),
                         ("k_sort_pass", "k_sort_pass<unsigned int>"),
-                        ("k_spawn_scan", "k_spawn_scan<unsigned int>")):
+                        ("k_spawn_scan", "k_spawn_scan<unsigned int>"),
+                        ("k_spawn_loud", "k_spawn_loud<unsigned int>")):
         if name in rec:
             path = os.path.join(ROOT, "profiles", f"{short}_{workload}_traffic.json")
             with open(path, "w") as f:
