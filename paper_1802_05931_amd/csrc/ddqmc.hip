@@ -414,7 +414,6 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
   // grids from the capacities: every kernel loops over the device-side counts
   const uint32_t g_loud = clampu(h->nscan, 1, h->loud_blocks);
   const uint32_t g_heavy = h->heavy_blocks;
-  const uint32_t g_h = clampu((h->cap_sp + NT * 8 - 1) / (NT * 8), 1, 512);
   const uint32_t g_s = clampu(sort_tiles(h->cap_sp), 1, 1u << 24);
   const uint32_t g_m = clampu(merge_tiles(h->cap_main, h->cap_sp), 1, 1u << 20);
   if (ev) HIPC(hipEventRecord(ev->e[0], s));
@@ -449,7 +448,7 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
                                  h->segcnt, segcap);
   k_seal<<<1, NSEG, 0, s>>>(h->ctrl, h->segcnt, segcap);
   if (ev) HIPC(hipEventRecord(ev->e[5], s));
-  k_hist<K><<<g_h, NT, 0, s>>>((const K *)h->sk[0], h->ctrl, h->hist, h->passes, segcap);
+  // (the digit totals of every pass come from the sort's row scans)
   if (ev) HIPC(hipEventRecord(ev->e[6], s));
   for (int p = 0; p < h->passes; ++p) {
     const K *ik = (const K *)h->sk[p & 1];
@@ -459,7 +458,7 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
     uint32_t *tcnt = h->sort_cnt;
     const uint32_t sc = p == 0 ? segcap : 0u;
     k_sort_count<K><<<g_s, NT, 0, s>>>(ik, h->ctrl, tcnt, p, sc);
-    k_sort_rowscan<<<256, NT, 0, s>>>(h->ctrl, tcnt);
+    k_sort_rowscan<<<256, NT, 0, s>>>(h->ctrl, tcnt, h->hist, p);
     k_sort_pass<K><<<g_s, NT, 0, s>>>(ik, iv, ok, ov, h->ctrl, h->hist, tcnt, p, sc);
   }
   {

@@ -698,32 +698,11 @@ __global__ void k_seal(Ctrl *ctrl, const uint32_t *segcnt, uint32_t segcap) {
 }
 
 // ---- radix sort -------------------------------------------------------------
-// Digit counts of all passes; the records are read through the segment map.
-template <typename K>
-__global__ __launch_bounds__(NT) void k_hist(const K *__restrict__ sk, Ctrl *ctrl,
-                                             uint32_t *__restrict__ hist, int passes,
-                                             uint32_t segcap) {
-  if (ctrl->abort || (ctrl->flags & F_SPAWN_CAP)) return;
-  __shared__ uint32_t h[MAX_PASSES * 256];
-  __shared__ uint32_t pre[NSEG + 1];
-  const uint32_t n = ctrl->n_spawn;
-  for (int i = threadIdx.x; i < passes * 256; i += NT) h[i] = 0;
-  for (int i = threadIdx.x; i <= NSEG; i += NT) pre[i] = ctrl->seg_prefix[i];
-  __syncthreads();
-  for (uint32_t i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
-    const K kk = sk[seg_addr(pre, i, segcap)];
-    for (int q = 0; q < passes; ++q)
-      atomicAdd(&h[q * 256 + (uint32_t)((kk >> (8 * q)) & 255u)], 1u);
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < passes * 256; i += NT)
-    if (h[i]) atomicAdd(&hist[i], h[i]);
-}
-
 // One LSD pass over an 8-bit digit, reduce-then-scan: k_sort_count writes the
 // digit counts of every tile (digit-major), k_sort_rowscan turns each digit's
-// row into exclusive prefixes over the tiles, and k_sort_pass ranks each tile
-// in LDS and scatters it to (global start of the digit) + (its row prefix).
+// row into exclusive prefixes over the tiles (and records the row's total),
+// and k_sort_pass ranks each tile in LDS and scatters it to (global start of
+// the digit, from the totals) + (its row prefix).
 // No tile waits on another.  Pass 0 reads the segmented spawn buffer
 // (segcap > 0), later passes read a contiguous array (segcap == 0).
 template <typename K>
@@ -753,12 +732,18 @@ __global__ __launch_bounds__(NT) void k_sort_count(const K *__restrict__ ik, Ctr
   cnt[(size_t)threadIdx.x * ntiles + t] = h[threadIdx.x];
 }
 
-// Exclusive prefix over the tiles of digit blockIdx.x's row of counts, in place.
-__global__ __launch_bounds__(NT) void k_sort_rowscan(Ctrl *ctrl, uint32_t *cnt) {
+// Exclusive prefix over the tiles of digit blockIdx.x's row of counts, in place;
+// the row's total (the digit's count over all records) goes to
+// hist[pass * 256 + digit].
+__global__ __launch_bounds__(NT) void k_sort_rowscan(Ctrl *ctrl, uint32_t *cnt, uint32_t *hist,
+                                                     int pass) {
   if (ctrl->abort || (ctrl->flags & F_SPAWN_CAP)) return;
   const uint32_t n = ctrl->n_spawn;
   const uint32_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
-  if (ntiles == 0) return;
+  if (ntiles == 0) {
+    if (threadIdx.x == 0) hist[pass * 256 + blockIdx.x] = 0;
+    return;
+  }
   __shared__ uint32_t scan4[NT / 64];
   uint32_t *row = cnt + (size_t)blockIdx.x * ntiles;
   const uint32_t per = (ntiles + NT - 1) / NT;
@@ -773,6 +758,7 @@ __global__ __launch_bounds__(NT) void k_sort_rowscan(Ctrl *ctrl, uint32_t *cnt) 
     row[c] = run;
     run += v;
   }
+  if (threadIdx.x == 0) hist[pass * 256 + blockIdx.x] = tot;
 }
 
 template <typename K>
