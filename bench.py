@@ -433,7 +433,6 @@ def main():
     alg_bytes = {  # what each kernel must read and write, per the step's counts
         # the list in, the loud entries out (index, key, value)
         "scan": float((n_in * rec + c[:, 3] * (rec + 4)).sum()),
-        "histogram": float((n_sp * KEY_BYTES[k64]).sum()),
         # per pass: the digit counts read the keys, the scatter reads and writes records
         "sort": float((passes * n_sp * (KEY_BYTES[k64] + 2 * rec)).sum()),
         # survivors per tile: the list's keys and the records
@@ -441,9 +440,9 @@ def main():
         # the list and the records in, the new list out
         "merge": float(((n_in + n_sp + n_out) * rec).sum()),
     }
-    launches = {"scan": args.steps, "histogram": args.steps, "sort": args.steps * passes,
+    launches = {"scan": args.steps, "sort": args.steps * passes,
                 "count": args.steps, "merge": args.steps}
-    kernel_names = {"scan": "k_spawn_scan", "histogram": "k_hist", "sort": "k_sort_pass",
+    kernel_names = {"scan": "k_spawn_scan", "sort": "k_sort_pass",
                     "count": "k_merge_count", "merge": "k_merge_write"}
     # HBM roofline of the merge (the annihilation join, where the list is
     # streamed in and out): algorithmic bytes / mean launch time

@@ -175,10 +175,13 @@ int ddqmc_workspace_query(const ddqmc_params *p, int64_t capacity, size_t *bytes
 /* Wall time of the kernels of the last ddqmc_step call, per stage, from HIP
  * events on the handle's stream when profiling is on (ddqmc_set_profiling);
  * ms[10] = quiet scan (which also writes the list of loud entries), loud
- * gather (kept for the layout of ms; empty, since the scan writes that list),
+ * gather (kept for the layout of ms: the scan writes that list; with the
+ * second stream on, the fork to it),
  * loud spawn (the spawn kernel alone), heavy spawn (the entries the loud
  * kernel passed on, and the wait for the heavy kernel that ran on a second
- * stream next to the loud one), record seal, histogram,
+ * stream next to the loud one), record seal and histogram (both kept for the
+ * layout and empty: the first sort pass seals the records, and the sort's
+ * row scans give the digit totals),
  * sort (the radix passes and the merge-path partition), merge count
  * (survivors per tile and their offsets), merge (the merge kernel that writes
  * the new list), finalize, summed over the call's steps. */

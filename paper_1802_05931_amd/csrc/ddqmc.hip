@@ -446,7 +446,7 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
   if (h->pool)
     k_inject<K><<<1, NT, 0, s>>>((const K *)h->inj_k, h->inj_v, h->ctrl, (K *)h->sk[0], h->sv[0],
                                  h->segcnt, segcap);
-  k_seal<<<1, NSEG, 0, s>>>(h->ctrl, h->segcnt, segcap);
+  // (the records' segment offsets and count are sealed by the first sort pass)
   if (ev) HIPC(hipEventRecord(ev->e[5], s));
   // (the digit totals of every pass come from the sort's row scans)
   if (ev) HIPC(hipEventRecord(ev->e[6], s));
@@ -457,7 +457,7 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
     int2 *ov = h->sv[(p + 1) & 1];
     uint32_t *tcnt = h->sort_cnt;
     const uint32_t sc = p == 0 ? segcap : 0u;
-    k_sort_count<K><<<g_s, NT, 0, s>>>(ik, h->ctrl, tcnt, p, sc);
+    k_sort_count<K><<<g_s, NT, 0, s>>>(ik, h->ctrl, tcnt, p, sc, h->segcnt);
     k_sort_rowscan<<<256, NT, 0, s>>>(h->ctrl, tcnt, h->hist, p);
     k_sort_pass<K><<<g_s, NT, 0, s>>>(ik, iv, ok, ov, h->ctrl, h->hist, tcnt, p, sc);
   }

@@ -674,29 +674,6 @@ __global__ void k_inject(const K *__restrict__ ik, const int2 *__restrict__ iv, 
   // and is run again after the buffers grow injects the same records again
 }
 
-// Segment offsets and the record count (one wave).
-__global__ void k_seal(Ctrl *ctrl, const uint32_t *segcnt, uint32_t segcap) {
-  if (ctrl->abort) return;
-  const int s = threadIdx.x;  // 64 threads
-  const uint32_t c = segcnt[s * SEG_STRIDE];
-  const uint32_t inc = wave_incl_scan(c);
-  ctrl->seg_prefix[s] = inc - c;
-  if (s == NSEG - 1) {
-    ctrl->seg_prefix[NSEG] = inc;
-    ctrl->n_spawn = inc;
-  }
-  uint32_t mx = c;
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    const uint32_t t = __shfl_xor(mx, o, 64);
-    mx = t > mx ? t : mx;
-  }
-  if (s == 0 && mx > segcap) {
-    ctrl->seg_need = mx;
-    atomicOr(&ctrl->flags, F_SPAWN_CAP);
-  }
-}
-
 // ---- radix sort -------------------------------------------------------------
 // One LSD pass over an 8-bit digit, reduce-then-scan: k_sort_count writes the
 // digit counts of every tile (digit-major), k_sort_rowscan turns each digit's
@@ -708,16 +685,50 @@ __global__ void k_seal(Ctrl *ctrl, const uint32_t *segcnt, uint32_t segcap) {
 template <typename K>
 __global__ __launch_bounds__(NT) void k_sort_count(const K *__restrict__ ik, Ctrl *ctrl,
                                                    uint32_t *__restrict__ cnt, int pass,
-                                                   uint32_t segcap) {
+                                                   uint32_t segcap,
+                                                   const uint32_t *__restrict__ segcnt) {
   if (ctrl->abort || (ctrl->flags & F_SPAWN_CAP)) return;
-  const uint32_t n = ctrl->n_spawn;
+  __shared__ uint32_t h[256];
+  __shared__ uint32_t pre[NSEG + 1];
+  __shared__ uint32_t s_over;
+  if (pass == 0) {
+    // the records' segment offsets (every block computes them; block 0 also
+    // publishes them, the record count and a segment overflow for the later
+    // kernels)
+    if (threadIdx.x < NSEG) {
+      const uint32_t c = segcnt[threadIdx.x * SEG_STRIDE];
+      const uint32_t inc = wave_incl_scan(c);
+      pre[threadIdx.x] = inc - c;
+      if (threadIdx.x == NSEG - 1) pre[NSEG] = inc;
+      uint32_t mx = c;
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        const uint32_t t = __shfl_xor(mx, o, 64);
+        mx = t > mx ? t : mx;
+      }
+      if (threadIdx.x == 0) s_over = mx > segcap ? mx : 0u;
+    }
+    __syncthreads();
+    if (blockIdx.x == 0) {
+      if (threadIdx.x <= NSEG) ctrl->seg_prefix[threadIdx.x] = pre[threadIdx.x];
+      if (threadIdx.x == 0) {
+        ctrl->n_spawn = pre[NSEG];
+        if (s_over) {
+          ctrl->seg_need = s_over;
+          atomicOr(&ctrl->flags, F_SPAWN_CAP);
+        }
+      }
+    }
+    if (s_over) return;
+  } else {
+    if (threadIdx.x <= NSEG) pre[threadIdx.x] = ctrl->seg_prefix[threadIdx.x];
+  }
+  __syncthreads();
+  const uint32_t n = pre[NSEG];
   const uint32_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
   const uint32_t t = blockIdx.x;
   if (t >= ntiles) return;
-  __shared__ uint32_t h[256];
-  __shared__ uint32_t pre[NSEG + 1];
   h[threadIdx.x] = 0;
-  if (threadIdx.x <= NSEG) pre[threadIdx.x] = ctrl->seg_prefix[threadIdx.x];
   __syncthreads();
   const int shift = 8 * pass;
 #pragma unroll
