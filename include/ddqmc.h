@@ -184,7 +184,11 @@ int ddqmc_workspace_query(const ddqmc_params *p, int64_t capacity, size_t *bytes
  * row scans give the digit totals),
  * sort (the radix passes and the merge-path partition), merge count
  * (survivors per tile and their offsets), merge (the merge kernel that writes
- * the new list), finalize, summed over the call's steps. */
+ * the new list), finalize, summed over the steps that carried events;
+ * *steps receives their number.  ddqmc_set_profiling(h, k): k = 0 off, k >= 1
+ * events on every k-th step of each chunk of steps (an event costs a few
+ * microseconds of the step it is in, so sampling keeps the other steps
+ * undisturbed).  EINVAL for k < 0. */
 int ddqmc_set_profiling(ddqmc_t *h, int32_t on);
 
 /* Launch the kernels of k consecutive steps as one HIP graph (k even,

@@ -111,8 +111,9 @@ class _Handle:
         check(lib().ddqmc_list_size(self._h, ctypes.byref(n)), "list_size")
         return n.value
 
-    def set_profiling(self, on=True):
-        check(lib().ddqmc_set_profiling(self._h, 1 if on else 0), "set_profiling")
+    def set_profiling(self, every=1):
+        """Stage events on every `every`-th step (True: every step, 0 or False: off)."""
+        check(lib().ddqmc_set_profiling(self._h, int(every)), "set_profiling")
 
     def set_graph_steps(self, k):
         """Run k steps per HIP graph launch (k even, 0 = one launch per kernel)."""

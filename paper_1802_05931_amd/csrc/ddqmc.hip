@@ -28,8 +28,9 @@ constexpr uint32_t SERIES_CAP = 1024;  // steps per chunk between host synchroni
 // every 32-bit count and index in the kernels is exact.
 constexpr uint64_t MAX_CAP = 0x7FF00000ull;
 constexpr uint64_t FORK_MIN_CAP = 1ull << 23;  // list capacity from which heavy runs beside loud
-constexpr int NSTAGE = 10;  // scan, gather, loud, heavy, seal, histogram, sort, count, merge,
-                            // finalize
+// stages: scan, gather, loud, heavy, seal, histogram, sort, count, merge, finalize
+constexpr int NSTAGE = 10;
+constexpr int STAGE_SEAL = 4, STAGE_HIST = 5, STAGE_SORT = 6;
 
 struct StageEvents {
   hipEvent_t e[NSTAGE + 1];
@@ -103,6 +104,7 @@ struct ddqmc_t {
   int gexec_k[2] = {0, 0};
 
   bool profiling = false;
+  int prof_every = 1;  // stage events on every prof_every-th step of a chunk
   std::vector<StageEvents> ev;
   double stage_ms[NSTAGE] = {};
   int64_t stage_steps = 0;
@@ -446,10 +448,9 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
   if (h->pool)
     k_inject<K><<<1, NT, 0, s>>>((const K *)h->inj_k, h->inj_v, h->ctrl, (K *)h->sk[0], h->sv[0],
                                  h->segcnt, segcap);
-  // (the records' segment offsets and count are sealed by the first sort pass)
-  if (ev) HIPC(hipEventRecord(ev->e[5], s));
-  // (the digit totals of every pass come from the sort's row scans)
-  if (ev) HIPC(hipEventRecord(ev->e[6], s));
+  // (the records' segment offsets and count are sealed by the first sort pass,
+  // and the digit totals of every pass come from the sort's row scans: the
+  // seal and histogram stages are empty, and no events are recorded for them)
   for (int p = 0; p < h->passes; ++p) {
     const K *ik = (const K *)h->sk[p & 1];
     const int2 *iv = h->sv[p & 1];
@@ -614,7 +615,7 @@ int run_steps(ddqmc_t *h, int64_t n) {
     } else {
       for (uint32_t j = 0; j < chunk; ++j) {
         const int par = (h->cur + (int)j) & 1;
-        StageEvents *ev = h->profiling ? &h->ev[j] : nullptr;
+        StageEvents *ev = h->profiling && j % (uint32_t)h->prof_every == 0 ? &h->ev[j] : nullptr;
         const int rc = h->k64 ? launch_step<uint64_t>(h, par, ev, h->stream)
                               : launch_step<uint32_t>(h, par, ev, h->stream);
         if (rc != DDQMC_OK) return rc;
@@ -638,13 +639,18 @@ int run_steps(ddqmc_t *h, int64_t n) {
       h->hcounts.insert(h->hcounts.end(), cnt.begin(), cnt.end());
     }
     if (h->profiling) {
-      for (uint32_t j = 0; j < done; ++j)
+      for (uint32_t j = 0; j < done; j += (uint32_t)h->prof_every) {
         for (int st = 0; st < NSTAGE; ++st) {
+          if (st == STAGE_SEAL || st == STAGE_HIST) continue;  // empty stages
+          // the sort stage starts where the heavy stage ends (its pool
+          // injection included)
+          const int from = st == STAGE_SORT ? STAGE_SEAL : st;
           float ms = 0.f;
-          HIPC(hipEventElapsedTime(&ms, h->ev[j].e[st], h->ev[j].e[st + 1]));
+          HIPC(hipEventElapsedTime(&ms, h->ev[j].e[from], h->ev[j].e[st + 1]));
           h->stage_ms[st] += ms;
         }
-      h->stage_steps += done;
+        h->stage_steps += 1;
+      }
     }
     h->cur = (h->cur + (int)done) & 1;
     h->n_main_known = c.n_main;
@@ -1111,7 +1117,9 @@ int ddqmc_workspace_query(const ddqmc_params *p, int64_t capacity, size_t *bytes
 
 int ddqmc_set_profiling(ddqmc_t *h, int32_t on) {
   if (!h) return DDQMC_EINVAL;
+  if (on < 0) return DDQMC_EINVAL;
   h->profiling = on != 0;
+  h->prof_every = on > 0 ? on : 1;
   return DDQMC_OK;
 }
 

@@ -258,6 +258,32 @@ def test_graph_steps_invalid(dq):
     g.close()
 
 
+def test_stage_times_sampled(dq):
+    """Stage events on every k-th step: the step count and the stage layout
+    (seal and histogram empty), and the same lists as without events."""
+    from paper_1802_05931_amd import DDQMCError
+    cfg = dict(workloads.d2(0.6), target_walkers=20000, n_equil=20)
+    a = dq.Solve(dq.make_params(**cfg))
+    b = dq.Solve(dq.make_params(**cfg))
+    with pytest.raises(DDQMCError) as e:
+        b.set_profiling(-1)
+    assert e.value.code == -1
+    b.set_profiling(3)
+    a.step(10)
+    b.step(10)
+    ms, n = b.stage_times()
+    assert n == 4  # steps 0, 3, 6, 9 of the call
+    assert ms["seal"] == 0.0 and ms["histogram"] == 0.0
+    assert all(v >= 0.0 for v in ms.values()) and ms["loud"] > 0.0 and ms["merge"] > 0.0
+    assert _same_list(a.walkers(), b.walkers())
+    b.set_profiling(0)
+    a.step(5)
+    b.step(5)
+    assert _same_list(a.walkers(), b.walkers())
+    a.close()
+    b.close()
+
+
 def _churn_requests():
     rng = np.random.default_rng(7)
     lat = [(2, 2), (3, 3), (2, 6), (4, 4)]
