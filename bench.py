@@ -25,6 +25,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -50,11 +51,19 @@ WORKLOADS = {
 }
 
 
-def kernel_source_hash():
+def kernel_source_hash(texts=None):
+    """Hash of the kernel sources with comments and blank space removed, so that
+    a counter record stays valid across comment-only edits."""
     h = hashlib.sha256()
     for f in ("kernels.hpp", "model.hpp", "sampling.hpp", "ddqmc.hip"):
-        with open(os.path.join(ROOT, "paper_1802_05931_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        if texts is None:
+            with open(os.path.join(ROOT, "paper_1802_05931_amd", "csrc", f)) as fh:
+                text = fh.read()
+        else:
+            text = texts[f]
+        text = re.sub(r"//[^\n]*", "", text)
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        h.update("".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

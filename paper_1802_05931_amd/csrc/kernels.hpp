@@ -2,24 +2,28 @@
 //
 //   scan      one thread per occupied configuration: the cheap test whether any
 //             clone/death or spawning event happens (most entries: none); the
-//             others are compacted into a per-block queue
-//   loud      the entries with events, densely: counts, multinomial splits and
-//             records (model.hpp), staged in LDS and flushed into 64 segments
-//             that each have their own counter
-//   histogram digit counts of the records for every radix pass at once
+//             others are staged in LDS and appended to one dense list (large
+//             populations to the heavy list)
+//   loud      the entries with events, densely, in 256-entry chunks handed out
+//             by a counter: counts, multinomial splits and records
+//             (model.hpp), staged in LDS and flushed into 64 segments that
+//             each have their own counter
+//   heavy     the entries with large populations, one wave each (for large
+//             lists on a second stream, beside the loud kernel)
 //   sort      LSD radix sort of the records by key, 8-bit digits: per pass the
-//             digit counts of every tile, their prefixes over the tiles, then
-//             tiles ranked in LDS with wave ballots and scattered
+//             digit counts of every tile (the first pass also seals the
+//             segments), their prefixes over the tiles with the digit totals,
+//             then tiles ranked in LDS with wave ballots and scattered
 //   merge     merge-path join of the sorted list with the sorted records: sums
-//             every run of equal keys (annihilation) applying the initiator rule,
-//             drops empty entries, compacts by a decoupled look-back and emits
-//             estimator sums
-//
-// Same-address device atomics serialise (about 11 ns each on MI355X), so no
-// kernel here issues more than a few per segment: compaction inside a block
-// uses LDS, and record output is spread over 64 counters.
+//             every run of equal keys (annihilation) applying the initiator
+//             rule, drops empty entries; a count pass, the tile offsets, and a
+//             write pass that compacts and emits estimator sums
 //   finalize  one block: reduces the estimator sums per solve, updates the shift
 //             and the accumulators, and arms the next step
+//
+// Same-address device atomics serialise (about 11 ns each on MI355X), so no
+// kernel here issues more than a few per block or chunk: compaction inside a
+// block uses LDS, and record output is spread over 64 counters.
 //
 // Counts live in device memory (Ctrl) so the host never waits between steps; a
 // step that overflows a buffer sets a flag and every later kernel returns at
