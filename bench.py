@@ -355,7 +355,7 @@ def main():
     ap.add_argument("--requests", type=int, default=512, help="d4: requests in the stream")
     ap.add_argument("--baseline-every", type=int, default=8,
                     help="d4: time every n-th request alone for the one-at-a-time baseline")
-    ap.add_argument("--graph-steps", type=int, default=10,
+    ap.add_argument("--graph-steps", type=int, default=50,
                     help="d4/d5: launch the steps as HIP graphs of this many steps (even; 0 = "
                          "one launch per kernel)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -412,7 +412,13 @@ def main():
         w0 = int(np.abs(re0.astype(np.int64)).sum() + np.abs(im0.astype(np.int64)).sum())
         del re0, im0
     else:
-        g.step(args.warmup)
+        # in chunks, with a line per chunk on stderr (large workloads warm up for minutes)
+        done = 0
+        while done < args.warmup:
+            n = min(2000, args.warmup - done)
+            g.step(n)
+            done += n
+            print(f"warm-up: {done} steps, {g.list_size()} entries", file=sys.stderr, flush=True)
     if args.save_state:
         with open(args.save_state, "wb") as f:
             f.write(g.get_state())
@@ -467,6 +473,18 @@ def main():
                         peak=HBM_PEAK_GBS, unit="GB/s", frac=round(m_ach / HBM_PEAK_GBS, 4),
                         traffic=traffic_from_profile("k_merge_write", args.workload, m_bytes),
                         bytes_per_launch=round(m_bytes), mean_launch_us=round(m_dur * 1e6, 2))
+    # the annihilation stages together (sort, merge count, merge write) on
+    # their algorithmic bytes, and the method's minimal traffic per step
+    # (read and write the list, write the records and read them back)
+    a_stages = ("sort", "count", "merge")
+    a_bytes = sum(alg_bytes[k] for k in a_stages)
+    a_s = sum(stage_ms[k] for k in a_stages) / 1e3
+    a_ach = a_bytes / a_s / 1e9
+    b_alg = float((2 * n_in * rec + 2 * n_sp * (rec + 1)).sum()) / args.steps
+    annihilation = dict(stages=list(a_stages), bytes_per_step=round(a_bytes / args.steps),
+                        achieved=round(a_ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                        frac=round(a_ach / HBM_PEAK_GBS, 4),
+                        method_min_bytes_per_step=round(b_alg))
     # the dominant kernel by time
     dominant = max((k for k in stage_ms if k != "finalize"), key=lambda k: stage_ms[k])
     if dominant in alg_bytes:
@@ -522,6 +540,7 @@ def main():
         "entry_updates_per_s": float(n_in.sum()) / wall,
         "roofline": roofline,
         "hbm_roofline": hbm_roofline,
+        "hbm_annihilation": annihilation,
         "stages": stages,
         "stage_events": f"HIP events on every {PROF_EVERY}-th timed step ({stage_steps} steps)",
         "shift": sc["S"],
