@@ -1,0 +1,87 @@
+"""bench.py's measurement helpers on synthetic inputs (no GPU): the source hash
+that ties counter records to the kernels, the per-kernel summary of a
+rocprofv3 kernel trace, and the counter summary that turns FETCH_SIZE /
+WRITE_SIZE into HBM bytes with the probe's scale factors."""
+import csv
+import json
+import os
+
+import bench
+
+
+def _sources():
+    d = os.path.join(bench.ROOT, "paper_1802_05931_amd", "csrc")
+    return {f: open(os.path.join(d, f)).read()
+            for f in ("kernels.hpp", "model.hpp", "sampling.hpp", "ddqmc.hip")}
+
+
+def test_source_hash_ignores_comments_but_not_code():
+    src = _sources()
+    h = bench.kernel_source_hash(src)
+    assert h == bench.kernel_source_hash()
+    commented = dict(src, **{"kernels.hpp": "// a new comment\n" + src["kernels.hpp"] +
+                             "\n/* and a block\n comment */\n"})
+    assert bench.kernel_source_hash(commented) == h
+    changed = dict(src, **{"kernels.hpp": src["kernels.hpp"].replace(
+        "constexpr int NT = 256;", "constexpr int NT = 128;")})
+    assert changed["kernels.hpp"] != src["kernels.hpp"]
+    assert bench.kernel_source_hash(changed) != h
+
+
+def _write_trace(path, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        for name, t0, t1 in rows:
+            w.writerow({"Kernel_Name": name, "Start_Timestamp": t0, "End_Timestamp": t1})
+
+
+def test_trace_summary_counts_the_last_steps(tmp_path, capsys):
+    # three steps, each: scan 10 us, loud 30 us, finalize 5 us (ns timestamps)
+    rows, t = [], 0
+    for _ in range(3):
+        for name, dur in (("void ddqmc::k_spawn_scan<unsigned int>(...)", 10_000),
+                          ("void ddqmc::k_spawn_loud<unsigned int>(...)", 30_000),
+                          ("ddqmc::k_finalize(...)", 5_000)):
+            rows.append((name, t, t + dur))
+            t += dur + 1_000
+    _write_trace(tmp_path / "x_kernel_trace.csv", rows)
+    bench.trace_summary(str(tmp_path), 2)
+    out = capsys.readouterr().out
+    # the last two steps start after the first step's finalize
+    assert "the last 2 steps, 6 dispatches" in out
+    loud = [line for line in out.splitlines() if line.startswith("| k_spawn_loud")][0]
+    cells = [c.strip() for c in loud.strip("|").split("|")]
+    assert cells[1] == "2" and float(cells[3]) == 30.0 and float(cells[6]) == 30.0
+
+
+def _write_counters(path, counter, values):
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for name, v in values:
+            w.writerow({"Kernel_Name": name, "Counter_Name": counter, "Counter_Value": v})
+
+
+def test_counter_summary_scales_by_the_probe(tmp_path, monkeypatch, capsys):
+    fetch, write = tmp_path / "fetch", tmp_path / "write"
+    fetch.mkdir()
+    write.mkdir()
+    probe = "void at::native::elementwise_kernel<...>(...)"
+    merge = "void ddqmc::k_merge<unsigned int, true>(...)"
+    # the probe moves 1 MiB each way; FETCH_SIZE reports half of its reads
+    _write_counters(fetch / "a_counter_collection.csv", "FETCH_SIZE",
+                    [(probe, 512.0), (merge, 1000.0), (merge, 1000.0)])
+    _write_counters(write / "a_counter_collection.csv", "WRITE_SIZE",
+                    [(probe, 1024.0), (merge, 300.0), (merge, 300.0)])
+    profiles = tmp_path / "profiles"
+    profiles.mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda texts=None: "feedfacefeedface")
+    bench.counter_summary(str(fetch), str(write), 1, "t")
+    out = capsys.readouterr().out
+    assert "scale factors are 2.0000 (fetch) and 1.0000 (write)" in out
+    rec = json.load(open(profiles / "k_merge_write_t_traffic.json"))
+    # (1000 KiB x 2 + 300 KiB x 1) per dispatch
+    assert abs(rec["bytes_per_launch"] - 2300 * 1024) < 1.0
+    assert rec["source_hash"] == "feedfacefeedface"
