@@ -225,11 +225,13 @@ def test_graph_steps_equal_eager(dq, orc, fork):
     b.close()
 
 
-def test_graph_steps_batch_equals_alone(dq, orc):
+@pytest.mark.parametrize("fork", [0, 1])
+def test_graph_steps_batch_equals_alone(dq, orc, fork):
     cfgs = [dict(workloads.D1, solve_id=0, n_equil=40),
             dict(workloads.d2(0.9), solve_id=1, target_walkers=3000, n_equil=40),
             dict(workloads.D1, solve_id=2, seed=3, n_equil=40)]
     b = dq.Batch([dq.make_params(**c) for c in cfgs])
+    b.set_heavy_fork(fork)
     b.set_graph_steps(16)
     orcs = [orc.Oracle(**c) for c in cfgs]
     for per in (48, 100):
@@ -300,16 +302,18 @@ def _churn_requests():
     return reqs
 
 
-@pytest.mark.parametrize("cap,gk", [(0, 0), (16, 0), (16, 10)])
-def test_pool_churn_equals_alone(dq, cap, gk):
+@pytest.mark.parametrize("cap,gk,fork", [(0, 0, 0), (16, 0, 0), (16, 10, 0), (16, 10, 1)])
+def test_pool_churn_equals_alone(dq, cap, gk, fork):
     """Continuous batching with churn: solves of four lattice shapes enter and
     leave a 5-slot pool between ticks (several admissions in one tick, slots
     reused, the buffers grown during entering steps when the capacity starts
     tiny; with gk > 0 the ticks run as k-step graphs, re-captured after each
-    growth); each solve's list when it leaves equals the same solve run alone."""
+    growth; with fork = 1 the large entries run on the second stream); each
+    solve's list when it leaves equals the same solve run alone."""
     from paper_1802_05931_amd import DDQMCError
     reqs = _churn_requests()
     pool = dq.Pool(slots=5, max_sites=16, capacity_hint=cap)
+    pool.set_heavy_fork(fork)
     if gk:
         pool.set_graph_steps(gk)
     queue = list(range(len(reqs)))
