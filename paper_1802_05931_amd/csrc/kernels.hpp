@@ -450,6 +450,8 @@ __global__ __launch_bounds__(64) void k_spawn_heavy(
   __shared__ int64_t fM[2][HEAVY_FRONT];
   __shared__ uint32_t s_cr[6], s_cu[6];  // class bond masks (right, up) and signs, so
   __shared__ int s_cs[6];                // that a per-lane class index reads LDS
+  __shared__ EntryProbs s_e;             // the entry's probabilities, read from LDS by
+                                         // every lane instead of held in its registers
   const uint32_t nh = *nheavy;
   const int lane = threadIdx.x;
   const int seg = (blockIdx.x + 17) % NSEG;
@@ -468,17 +470,19 @@ __global__ __launch_bounds__(64) void k_spawn_heavy(
     const uint32_t N = P.N;
     const uint32_t l = (uint32_t)(cfg >> N);
     const uint32_t m = (uint32_t)(cfg & ((N == 32) ? 0xffffffffull : ((1ull << N) - 1)));
-    EntryProbs e = entry_probs(P, ss[slot].S, (uint32_t)ss[slot].step, l, m, v.x, v.y);
     if (lane == 0) {
+      s_e = entry_probs(P, ss[slot].S, (uint32_t)ss[slot].step, l, m, v.x, v.y);
       scount = 0;
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
-        s_cr[c] = e.hc.r[c];
-        s_cu[c] = e.hc.u[c];
-        s_cs[c] = e.hc.sgn[c];
+        s_cr[c] = s_e.hc.r[c];
+        s_cu[c] = s_e.hc.u[c];
+        s_cs[c] = s_e.hc.sgn[c];
       }
     }
     __syncthreads();
+    const EntryProbs &e = s_e;
+    EntryCounter cnt = s_e.cnt;  // per lane: the draws set its dry flag
     auto out = [&](uint32_t cl, uint32_t cm, int64_t dr, int64_t di, bool keep) {
       sink(hibits | (K)(((uint64_t)cl << N) | cm), dr, di, keep);
     };
@@ -487,7 +491,7 @@ __global__ __launch_bounds__(64) void k_spawn_heavy(
     // then lanes 0..7 draw the firing channels' counts at once: each count has
     // its own stream, so the order of the draws does not matter
     bool split_all;
-    const uint32_t ev = event_channels(e.p8, e.n8, e.cnt, &split_all);
+    const uint32_t ev = event_channels(e.p8, e.n8, cnt, &split_all);
     int64_t x = 0;
     if (lane < 8 && ((ev >> lane) & 1u)) {
       double pl = e.p8[0];
@@ -497,7 +501,7 @@ __global__ __launch_bounds__(64) void k_spawn_heavy(
         pl = lane == k ? e.p8[k] : pl;
         nl = lane == k ? e.n8[k] : nl;
       }
-      x = e.cnt.inl(draw_channel((uint32_t)lane + 1u), nl, pl, split_all ? DRAW_SPLIT : DRAW_POS);
+      x = cnt.inl(draw_channel((uint32_t)lane + 1u), nl, pl, split_all ? DRAW_SPLIT : DRAW_POS);
     }
     int64_t X[8];
 #pragma unroll
@@ -518,7 +522,7 @@ __global__ __launch_bounds__(64) void k_spawn_heavy(
       const int64_t sg = part ? e.sI : e.sR;
       if (rem == 1) {
         int c, j;
-        pick_hop(e.cnt, draw_channel(ch) + DRAW_PICK, e.Sc, e.hc.n, c, j);
+        pick_hop(cnt, draw_channel(ch) + DRAW_PICK, e.Sc, e.hc.n, c, j);
         const uint32_t bm = class_member_mask(P, s_cr[c], s_cu[c], j);
         const uint32_t cl = c < 3 ? (l ^ bm) : l;
         const uint32_t cm = c < 3 ? m : (m ^ bm);
@@ -534,7 +538,7 @@ __global__ __launch_bounds__(64) void k_spawn_heavy(
       for (int c = 0; c < 6; ++c) {
         if (rem == 0 || e.hc.W[c] == 0.0) continue;
         const int64_t mc = (c == last) ? rem
-                                       : e.cnt.inl(draw_channel(ch) + 1u + (uint32_t)c, rem,
+                                       : cnt.inl(draw_channel(ch) + 1u + (uint32_t)c, rem,
                                                    e.hc.W[c] / e.Sc[c], DRAW_BIN);
         Mc[c] = mc;
         rem -= mc;
@@ -547,7 +551,7 @@ __global__ __launch_bounds__(64) void k_spawn_heavy(
       const int64_t rootM[2] = {X[2], X[6]};
       for (int part = 0; part < 2; ++part) {
         if (rootM[part] == 1) {
-          const int j = pick_member(e.cnt, draw_channel(part ? 7 : 3) + DRAW_PICK, e.nJ);
+          const int j = pick_member(cnt, draw_channel(part ? 7 : 3) + DRAW_PICK, e.nJ);
           const uint32_t bit = 1u << nth_bit(e.jm, j);
           const int64_t val = part ? e.sI : e.sR;
           out(l & ~bit, m & ~bit, part ? 0 : val, part ? val : 0, e.init);
@@ -616,7 +620,7 @@ __global__ __launch_bounds__(64) void k_spawn_heavy(
             }
           } else {
             const int mid = lo + (hi - lo) / 2;
-            const int64_t ML = e.cnt.inl(base + (uint32_t)h, M,
+            const int64_t ML = cnt.inl(base + (uint32_t)h, M,
                                          (double)(mid - lo) / (double)(hi - lo), DRAW_BIN);
             if (ML > 0) {
               child[nchild] = (uint32_t)t | (uint32_t)lo << 5 | (uint32_t)mid << 12 |
@@ -647,7 +651,7 @@ __global__ __launch_bounds__(64) void k_spawn_heavy(
       cur ^= 1;
       __syncthreads();
     }
-    dry |= e.cnt.dry;
+    dry |= cnt.dry;
     __syncthreads();
     seg_flush64(sk, sv, scount < HEAVY_STAGE ? scount : HEAVY_STAGE, seg, segcnt, ok, ov, segcap,
                 &sbase);
