@@ -934,8 +934,11 @@ __global__ __launch_bounds__(NT) void k_merge_partition(const K *__restrict__ Ak
 // by the tile that holds the entry.  The write pass then walks the merged
 // order with two compares per position and sums the estimators over the
 // compacted survivors.
+// Tiles per CU: with 32-bit keys a tile's LDS is 27 KB and five fit; the
+// bound holds the write pass to 96 VGPRs (without it, 101: four tiles).  With
+// 64-bit keys the LDS (35 KB) allows four.
 template <typename K, bool WRITE>
-__global__ __launch_bounds__(NT) void k_merge(
+__global__ __launch_bounds__(NT, sizeof(K) == 4 ? 5 : 4) void k_merge(
     const K *__restrict__ Ak, const int2 *__restrict__ Av, const K *__restrict__ Bk,
     const int2 *__restrict__ Bv, K *__restrict__ Ck, int2 *__restrict__ Cv, uint32_t capC,
     Ctrl *ctrl, const SlotParams *__restrict__ sp, const SlotState *__restrict__ ss,
@@ -948,11 +951,13 @@ __global__ __launch_bounds__(NT) void k_merge(
   const uint32_t ntiles = (total + MERGE_TILE - 1) / MERGE_TILE;
   const K lowm = low_mask<K>(SB);
 
-  __shared__ K sAk[MERGE_TILE], sBk[MERGE_TILE];
-  __shared__ int2 sBv[MERGE_TILE];
-  __shared__ int2 sAv[WRITE ? MERGE_TILE : 1];
-  __shared__ uint8_t sAdel[MERGE_TILE];  // entry annihilated by its records
-  __shared__ uint8_t sBout[MERGE_TILE];  // record heads that become new entries
+  // A tile holds nA entries and nB records with nA + nB <= MERGE_TILE: both
+  // live in one set of arrays, the entries first, the records after them
+  // (half the LDS of separate arrays, so more tiles per CU).
+  __shared__ K sK[MERGE_TILE];
+  __shared__ int2 sV[MERGE_TILE];
+  __shared__ uint8_t sF[MERGE_TILE];  // entries: annihilated by their records;
+                                      // records: run heads that become new entries
   __shared__ uint32_t s_i0, s_i1;
   __shared__ K s_aprev, s_bprev, s_bnext;  // the keys just outside the tile
   __shared__ uint32_t scan4[NT / 64];
@@ -968,6 +973,9 @@ __global__ __launch_bounds__(NT) void k_merge(
     __syncthreads();
     const uint32_t i0 = s_i0, i1 = s_i1, j0 = d0 - i0, j1 = d1 - i1;
     const uint32_t nA = i1 - i0, nB = j1 - j0;
+    K *const sAk = sK, *const sBk = sK + nA;
+    int2 *const sAv = sV, *const sBv = sV + nA;
+    uint8_t *const sAdel = sF, *const sBout = sF + nA;
     for (uint32_t q = threadIdx.x; q < nA; q += NT) {
       sAk[q] = Ak[i0 + q];
       if (WRITE) sAv[q] = Av[i0 + q];
@@ -1128,7 +1136,7 @@ __global__ __launch_bounds__(NT) void k_merge(
     uint32_t ttot;
     const uint32_t lpos = block_excl_scan(nsurv, scan4, &ttot);
     const uint32_t gbase = tile_cnt[t];
-    // stage the survivors in LDS (reuse the A arrays)
+    // stage the survivors in LDS (over the tile's entries and records)
     __syncthreads();
     {
       uint32_t q = lpos;
@@ -1157,17 +1165,14 @@ __global__ __launch_bounds__(NT) void k_merge(
       uint32_t l, m;
       if (slot == s0) {
         ket_bra(k, P0.N, l, m);
-        entry_sums(P0, l, m, v.x, v.y, acc);
+        entry_sums(P0, l, m, v.x, v.y, [&](int s, int64_t x) { acc[s] += x; });
       } else {
         const SlotParams &P = sp[slot];
         ket_bra(k, P.N, l, m);
-        int64_t one[S_NSUM];
-#pragma unroll
-        for (int s = 0; s < S_NSUM; ++s) one[s] = 0;
-        entry_sums(P, l, m, v.x, v.y, one);
-#pragma unroll
-        for (int s = 0; s < S_NSUM; ++s)
-          if (one[s]) atomicAdd(&spill[(size_t)slot * S_NSUM + s], (unsigned long long)one[s]);
+        unsigned long long *const sums = spill + (size_t)slot * S_NSUM;
+        entry_sums(P, l, m, v.x, v.y, [&](int s, int64_t x) {
+          if (x) atomicAdd(&sums[s], (unsigned long long)x);
+        });
       }
     }
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;

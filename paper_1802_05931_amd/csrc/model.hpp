@@ -637,34 +637,36 @@ DQ_HD bool entry_events_small(const SlotParams &P, double S, uint32_t step, uint
   return true;
 }
 
-// Estimator contributions of one entry of the new list (Sec. III.A, V.A).
+// Estimator contributions of one entry of the new list (Sec. III.A, V.A),
+// each handed to add(sum index, value).
+template <class Add>
 DQ_HD void entry_sums(const SlotParams &P, uint32_t l, uint32_t m, int64_t R, int64_t I,
-                      int64_t s[S_NSUM]) {
+                      Add &&add) {
   const int64_t aR = R < 0 ? -R : R, aI = I < 0 ? -I : I;
-  s[S_WTOT] += aR + aI;
-  s[S_NENT] += 1;
+  add(S_WTOT, aR + aI);
+  add(S_NENT, 1);
   if (l == m) {
     const uint32_t alr = ~(l ^ right_of(P, l)) & P.rmask;
     const uint32_t alu = ~(l ^ up_of(P, l)) & P.umask;
-    s[S_T_RE] += R;
-    s[S_T_IM] += I;
-    s[S_NW] += aR;
-    s[S_Z] += R * (int64_t)(2 * popc(l) - (int)P.N);
-    s[S_CZZ] += R * (int64_t)(2 * (popc(alr) + popc(alu)) - (int)P.nb);
+    add(S_T_RE, R);
+    add(S_T_IM, I);
+    add(S_NW, aR);
+    add(S_Z, R * (int64_t)(2 * popc(l) - (int)P.N));
+    add(S_CZZ, R * (int64_t)(2 * (popc(alr) + popc(alu)) - (int)P.nb));
     return;
   }
   const uint32_t d = l ^ m;
   const int pd = popc(d);
   if (pd == 1) {
-    s[S_X] += R;
-    s[S_Y] += (l & d) ? -I : I;
+    add(S_X, R);
+    add(S_Y, (l & d) ? -I : I);
   } else if (pd == 2) {
     const uint32_t tr = d & right_of(P, d) & P.rmask;
     const uint32_t tu = d & up_of(P, d) & P.umask;
     if (tr | tu) {
       const bool al = ((~(l ^ right_of(P, l)) & tr) | (~(l ^ up_of(P, l)) & tu)) != 0;
-      s[S_CXX] += R;
-      s[S_CYY] += al ? -R : R;
+      add(S_CXX, R);
+      add(S_CYY, al ? -R : R);
     }
   }
 }
