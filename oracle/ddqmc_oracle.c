@@ -390,6 +390,24 @@ typedef struct {
 static void channel_stream(const ectx_t *c, stream_t *s, uint32_t draw) {
   stream_init(s, c->seed, c->solve_id, c->cfg, c->step, draw, c->err);
 }
+/* G[k] = prod over j = start..k of (1 - p_j)^n_j (Sec. III.B): the
+ * probability that none of the channels start..k fires; channels with no
+ * walkers or zero probability contribute 1. */
+static void no_event_products(const double p[8], const int64_t n[8], int start, double G[8]) {
+  double g = 1.0;
+  int k;
+  for (k = start; k < 8; k++) {
+    if (n[k] > 0 && p[k] > 0.0) g = g * powi(1.0 - p[k], n[k]);
+    G[k] = g;
+  }
+}
+
+double orc_no_event_prob(const double p[8], const int64_t n[8]) {
+  double G[8];
+  no_event_products(p, n, 0, G);
+  return G[7];
+}
+
 
 static void sample_channels(const ectx_t *c, const double p[8], const int64_t n[8], int64_t X[8]) {
   int k, loud = 0, start;
@@ -408,12 +426,9 @@ static void sample_channels(const ectx_t *c, const double p[8], const int64_t n[
   channel_stream(c, &prim, 0);
   start = 0;
   while (start < 8) {
-    double G[8], g = 1.0, u;
+    double G[8], u;
     int first;
-    for (k = start; k < 8; k++) {
-      if (n[k] > 0 && p[k] > 0.0) g = g * powi(1.0 - p[k], n[k]);
-      G[k] = g;
-    }
+    no_event_products(p, n, start, G);
     u = stream_next(&prim);
     if (u < G[7]) break;
     first = start;

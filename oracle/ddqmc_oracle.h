@@ -75,6 +75,9 @@ void orc_uniforms(uint64_t seed, uint32_t solve_id, uint64_t cfg, uint32_t step,
 /* mode 0: Bin(n,p); 1: Bin(n,p) conditioned on >= 1; 2: Bsplit(n,p).
  * Sample i uses the stream (seed, solve 0, cfg = i, step 0, draw 1). */
 int orc_binom_many(int64_t n, double p, int mode, uint64_t seed, int64_t count, int64_t *out);
+/* Probability that no channel fires: prod_k (1 - p_k)^n_k in fp64, k = 0..7,
+ * each factor by binary powers (Sec. III.B). */
+double orc_no_event_prob(const double p[8], const int64_t n[8]);
 /* entry-level channel sampler on its own: probabilities p[8], counts n[8];
  * sample i uses cfg = i.  out is count x 8. */
 int orc_channels_many(const double p[8], const int64_t n[8], uint64_t seed, int64_t count,

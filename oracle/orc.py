@@ -96,6 +96,7 @@ def lib():
         "orc_binom_many": (ctypes.c_int, [ctypes.c_int64, ctypes.c_double, ctypes.c_int,
                                           ctypes.c_uint64, ctypes.c_int64, i64p]),
         "orc_channels_many": (ctypes.c_int, [dp, i64p, ctypes.c_uint64, ctypes.c_int64, i64p]),
+        "orc_no_event_prob": (ctypes.c_double, [dp, i64p]),
         "orc_bonds": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, i32p, i32p]),
         "orc_connections": (ctypes.c_int, [_P(Params), ctypes.c_uint64, ctypes.c_uint64,
                                            ctypes.c_double, u64p, u64p, dp, dp, ctypes.c_int32,
@@ -226,6 +227,15 @@ def binom_many(n, p, mode, seed, count):
     _check(lib().orc_binom_many(int(n), float(p), int(mode), int(seed), int(count),
                                 _ptr(out, ctypes.c_int64)), "binom_many")
     return out
+
+
+def no_event_prob(p, n):
+    """prod_k (1 - p_k)^n_k over the eight channels, in fp64 (Sec. III.B)."""
+    pa = np.ascontiguousarray(p, np.float64)
+    na = np.ascontiguousarray(n, np.int64)
+    if pa.shape != (8,) or na.shape != (8,):
+        raise ValueError("no_event_prob: p and n must hold eight channels")
+    return float(lib().orc_no_event_prob(_ptr(pa, ctypes.c_double), _ptr(na, ctypes.c_int64)))
 
 
 def channels_many(p, n, seed, count):

@@ -142,3 +142,27 @@ def test_channel_counts_are_independent_binomials(orc, p, n):
     p_none = np.prod([(1 - pk) ** nk if pk < 1 else (0.0 if nk else 1.0) for pk, nk in zip(p, n)])
     obs = np.mean(np.all(X == 0, axis=1))
     assert abs(obs - p_none) <= 5 * np.sqrt(max(p_none * (1 - p_none), 1e-12) / len(X)) + 1e-12
+
+
+@pytest.mark.parametrize("p,n", CH_CASES[:3])
+def test_no_event_prob_is_the_all_zero_frequency(orc, p, n):
+    """The no-event probability is prod_k (1 - p_k)^n_k: against the exact power
+    product (math.prod of real powers, within rounding) and against the
+    frequency with which the channel sampler returns eight zero counts."""
+    import math
+    g = orc.no_event_prob(p, n)
+    exact = math.prod((1.0 - pk) ** nk for pk, nk in zip(p, n))
+    assert abs(g - exact) <= 1e-12 * exact
+    X = orc.channels_many(p, n, seed=33, count=200000)
+    freq = np.mean(np.all(X == 0, axis=1))
+    sd = math.sqrt(g * (1 - g) / len(X))
+    assert abs(freq - g) < 5 * sd + 1e-12, (freq, g)
+
+
+def test_no_event_prob_special_cases(orc):
+    z = [0.0] * 8
+    assert orc.no_event_prob(z, [7] * 8) == 1.0
+    assert orc.no_event_prob([0.3] * 8, [0] * 8) == 1.0
+    # one channel: (1 - p)^n by binary powers, 0.75^4 = 0.31640625 exactly
+    assert orc.no_event_prob([0.25] + [0.0] * 7, [4] + [0] * 7) == 0.31640625
+    assert orc.no_event_prob([0.5] * 4 + [0.0] * 4, [3] * 4 + [9] * 4) == 2.0 ** -12
