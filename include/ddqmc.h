@@ -217,12 +217,23 @@ int ddqmc_stage_times(ddqmc_t *h, double ms[10], int64_t *steps);
  * ddqmc_dev_binom: sample i uses stream (seed, 0, cfg = i, 0, draw 1);
  *   mode 0 Bin(n,p), 1 Bin(n,p | >= 1), 2 integer part + Bin(n, fraction).
  * ddqmc_dev_math: out[4i..4i+3] = det_log(x_i), det_exp(x_i), sqrt(x_i), 1/x_i.
+ * ddqmc_dev_quiet: the spawn scan's test of whether an entry spawns nothing in
+ *   a step (Sec. III.B: every channel count zero).  Entry i has the channel
+ *   probabilities p[4i..4i+3] (diagonal real, diagonal imaginary, jump, hop),
+ *   the same for its real and its imaginary walkers, walker counts
+ *   n[2i] = |R|, n[2i+1] = |I|, and primary uniform u[i].  Bit 0 of out[i] is
+ *   1 iff u[i] < prod over the four channels and both parts of (1 - p)^n,
+ *   the product taken in fp64 in that order by binary powers; bit 1 is 1 when
+ *   the scan's single-precision estimate decided it without the product.
+ *   EINVAL for p outside [0, 1) or negative n.
  * All pointers are host memory.                                               */
 int ddqmc_dev_uniforms(uint64_t seed, uint32_t solve_id, uint64_t cfg, uint32_t step,
                        uint32_t draw, int64_t count, double *out);
 int ddqmc_dev_binom(int64_t n, double p, int32_t mode, uint64_t seed, int64_t count,
                     int64_t *out);
 int ddqmc_dev_math(const double *x, int64_t count, double *out);
+int ddqmc_dev_quiet(const double *p, const int64_t *n, const double *u, int64_t count,
+                    int32_t *out);
 
 const char *ddqmc_strerror(int code);
 

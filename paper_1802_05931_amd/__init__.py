@@ -17,7 +17,7 @@ STAGES = ("scan", "gather", "loud", "heavy", "seal", "histogram", "sort", "count
           "finalize")
 
 __all__ = ["Solve", "Batch", "Pool", "make_params", "DDQMCError", "NO_INITIATOR", "SUM_NAMES",
-           "dev_uniforms", "dev_binom", "dev_math", "workspace_query"]
+           "dev_uniforms", "dev_binom", "dev_math", "dev_quiet", "workspace_query"]
 
 
 def _stream_ptr(stream):
@@ -217,6 +217,23 @@ def dev_binom(n, p, mode, seed, count):
     out = np.zeros(count, np.int64)
     check(lib().ddqmc_dev_binom(int(n), float(p), int(mode), int(seed), int(count),
                                 ptr(out, ctypes.c_int64)), "dev_binom")
+    return out
+
+
+def dev_quiet(p, n, u):
+    """The spawn scan's quiet test on given inputs: p (count, 4) channel
+    probabilities, n (count, 2) walker counts |R|, |I|, u (count,) primary
+    uniforms.  Returns int32 (count,): bit 0 quiet, bit 1 decided by the
+    single-precision estimate."""
+    p = np.ascontiguousarray(p, np.float64).reshape(-1, 4)
+    n = np.ascontiguousarray(n, np.int64).reshape(-1, 2)
+    u = np.ascontiguousarray(u, np.float64).ravel()
+    if not (len(p) == len(n) == len(u)):
+        raise ValueError("dev_quiet: p, n and u must describe the same number of entries")
+    out = np.zeros(len(u), np.int32)
+    check(lib().ddqmc_dev_quiet(ptr(p, ctypes.c_double), ptr(n, ctypes.c_int64),
+                                ptr(u, ctypes.c_double), len(u), ptr(out, ctypes.c_int32)),
+          "dev_quiet")
     return out
 
 

@@ -1181,6 +1181,37 @@ int ddqmc_dev_binom(int64_t n, double p, int32_t mode, uint64_t seed, int64_t co
   return he ? DDQMC_ERNG : DDQMC_OK;
 }
 
+int ddqmc_dev_quiet(const double *p, const int64_t *n, const double *u, int64_t count,
+                    int32_t *out) {
+  if (!p || !n || !u || !out || count < 0) return DDQMC_EINVAL;
+  for (int64_t i = 0; i < count; ++i) {
+    if (n[2 * i] < 0 || n[2 * i + 1] < 0) return DDQMC_EINVAL;
+    for (int k = 0; k < 4; ++k)
+      if (!(p[4 * i + k] >= 0.0 && p[4 * i + k] < 1.0)) return DDQMC_EINVAL;
+  }
+  if (count == 0) return DDQMC_OK;
+  double *dp = nullptr, *du = nullptr;
+  int64_t *dn = nullptr;
+  int32_t *dout = nullptr;
+  HIPC(hipMalloc((void **)&dp, 4 * count * sizeof(double)));
+  HIPC(hipMalloc((void **)&dn, 2 * count * sizeof(int64_t)));
+  HIPC(hipMalloc((void **)&du, count * sizeof(double)));
+  HIPC(hipMalloc((void **)&dout, count * sizeof(int32_t)));
+  hipError_t e = hipMemcpy(dp, p, 4 * count * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dn, n, 2 * count * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(du, u, count * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    k_dev_quiet<<<(uint32_t)((count + 255) / 256), 256>>>(dp, dn, du, count, dout);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpy(out, dout, count * sizeof(int32_t), hipMemcpyDeviceToHost);
+  (void)hipFree(dp);
+  (void)hipFree(dn);
+  (void)hipFree(du);
+  (void)hipFree(dout);
+  return hip_err(e);
+}
+
 int ddqmc_dev_math(const double *x, int64_t count, double *out) {
   if (!x || !out || count < 0) return DDQMC_EINVAL;
   if (count == 0) return DDQMC_OK;

@@ -739,13 +739,17 @@ __global__ __launch_bounds__(NT) void k_sort_count(const K *__restrict__ ik, Ctr
   h[threadIdx.x] = 0;
   __syncthreads();
   const int shift = 8 * pass;
+  // the thread's keys are all loaded before the first is counted
+  K key[SORT_IT];
 #pragma unroll
   for (int k = 0; k < SORT_IT; ++k) {
     const uint32_t pos = t * SORT_TILE + (uint32_t)k * NT + threadIdx.x;
-    if (pos < n) {
-      const K key = ik[segcap ? seg_addr(pre, pos, segcap) : (size_t)pos];
-      atomicAdd(&h[(uint32_t)((key >> shift) & 255u)], 1u);
-    }
+    if (pos < n) key[k] = ik[segcap ? seg_addr(pre, pos, segcap) : (size_t)pos];
+  }
+#pragma unroll
+  for (int k = 0; k < SORT_IT; ++k) {
+    const uint32_t pos = t * SORT_TILE + (uint32_t)k * NT + threadIdx.x;
+    if (pos < n) atomicAdd(&h[(uint32_t)((key[k] >> shift) & 255u)], 1u);
   }
   __syncthreads();
   cnt[(size_t)threadIdx.x * ntiles + t] = h[threadIdx.x];
@@ -821,15 +825,21 @@ __global__ __launch_bounds__(NT) void k_sort_pass(const K *__restrict__ ik,
     K key[SORT_IT];
     int2 val[SORT_IT];
     uint32_t rank[SORT_IT];
+    // all of the lane's records are loaded before the first is ranked, so
+    // that their loads are in flight together
 #pragma unroll
     for (int k = 0; k < SORT_IT; ++k) {
       const uint32_t pos = wbase + (uint32_t)k * 64u + (uint32_t)lane;
-      const bool valid = pos < n;
-      if (valid) {
+      if (pos < n) {
         const size_t a = segcap ? seg_addr(pre, pos, segcap) : (size_t)pos;
         key[k] = ik[a];
         val[k] = iv[a];
       }
+    }
+#pragma unroll
+    for (int k = 0; k < SORT_IT; ++k) {
+      const uint32_t pos = wbase + (uint32_t)k * 64u + (uint32_t)lane;
+      const bool valid = pos < n;
       const uint32_t d = valid ? (uint32_t)((key[k] >> shift) & 255u) : 0u;
       uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -1251,19 +1261,33 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctrl *ctrl, const SlotParams 
     // tiles strided over the threads (coalesced reads); a thread's sums go to
     // LDS whenever its solve changes, and at the end a wave whose lanes all
     // hold the same solve adds its sums once
+    // (FIN_BATCH tiles per thread are loaded before any is added, so that
+    // their loads are in flight together)
+    constexpr int FIN_BATCH = 4;
     int cur = -1;
     int64_t a[S_NSUM];
     for (int s = 0; s < S_NSUM; ++s) a[s] = 0;
-    for (uint32_t t = (uint32_t)tid; t < ntiles; t += (uint32_t)nt) {
-      const int sl = partials[t].slot;
-      if (sl != cur) {
-        if (cur >= 0)
-          for (int s = 0; s < S_NSUM; ++s)
-            if (a[s]) atomicAdd(&sums[cur * S_NSUM + s], (unsigned long long)a[s]);
-        cur = sl;
-        for (int s = 0; s < S_NSUM; ++s) a[s] = 0;
+    for (uint32_t t0 = (uint32_t)tid; t0 < ntiles; t0 += FIN_BATCH * (uint32_t)nt) {
+      Partial pb[FIN_BATCH];
+#pragma unroll
+      for (int u = 0; u < FIN_BATCH; ++u) {
+        const uint32_t t = t0 + (uint32_t)u * (uint32_t)nt;
+        if (t < ntiles) pb[u] = partials[t];
       }
-      for (int s = 0; s < S_NSUM; ++s) a[s] += partials[t].s[s];
+#pragma unroll
+      for (int u = 0; u < FIN_BATCH; ++u) {
+        if (t0 + (uint32_t)u * (uint32_t)nt >= ntiles) break;
+        const int sl = pb[u].slot;
+        if (sl != cur) {
+          if (cur >= 0)
+            for (int s = 0; s < S_NSUM; ++s)
+              if (a[s]) atomicAdd(&sums[cur * S_NSUM + s], (unsigned long long)a[s]);
+          cur = sl;
+          for (int s = 0; s < S_NSUM; ++s) a[s] = 0;
+        }
+#pragma unroll
+        for (int s = 0; s < S_NSUM; ++s) a[s] += pb[u].s[s];
+      }
     }
     const int c0 = __shfl(cur, 0, 64);
     const bool same = __ballot(cur != c0) == 0;  // wave-uniform
@@ -1427,6 +1451,20 @@ __global__ void k_dev_binom(int64_t n, double p, int mode, uint64_t seed, int64_
     x = binomial_split(n, p, st);
   out[i] = x;
   if (e) atomicOr(err, 1);
+}
+
+__global__ void k_dev_quiet(const double *p4, const int64_t *n2, const double *u, int64_t count,
+                            int32_t *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  double p8[8];
+  int64_t n8[8];
+  for (int k = 0; k < 4; ++k) {
+    p8[k] = p8[k + 4] = p4[4 * i + k];
+    n8[k] = n2[2 * i];
+    n8[k + 4] = n2[2 * i + 1];
+  }
+  out[i] = quiet_test(p8, n8, u[i]);
 }
 
 __global__ void k_dev_math(const double *x, int64_t count, double *out) {

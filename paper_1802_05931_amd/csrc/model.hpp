@@ -268,6 +268,56 @@ DQ_HD EntryProbs entry_probs(const SlotParams &P, double S, uint32_t step, uint3
   return e;
 }
 
+enum { ENTRY_QUIET = 0, ENTRY_LIGHT = 1, ENTRY_HEAVY = 2 };
+
+// The quiet test u < g, g = prod_k (1 - p_k)^n_k, where g is the fp64 product
+// of the k = 0..7 factors, each by ipow.  Decided from a single-precision
+// estimate where possible: with every p_k <= 1/2 and n = n_R + n_I <= 1024,
+// ga = 2^(n_R sum_k<4 log2(1 - p_k) + n_I sum_k>=4 ...) computed in float
+// differs from the exact product by a relative error below 2e-7 + 2e-6 n: per
+// channel, the float rounding of p_k and of 1 - p_k (6e-8 together, times at
+// most 2.9 through log2) and 2 ulps of log2 give 3e-7 in the logarithm; the
+// two four-term sums add 7e-7 and the products and their sum 5e-7 n; ln 2
+// turns 2.4e-6 n in the exponent into 1.7e-6 n, and exp2 adds 2 ulps.  The
+// fp64 product itself is within (n + 100) 2^-52 of the real value.  With the
+// margin mg = 1e-5 (1 + n), u < ga (1 - mg) implies u < g and u >= ga (1 + mg)
+// implies u >= g; only a u inside the band, or ga below 2^-30, takes the
+// exact product.  Returns 1 (quiet), 0 (not quiet) or -1 (undecided).  The
+// counts are those of an entry: n8[0..3] = n_R and n8[4..7] = n_I (anything
+// else is left undecided).
+DQ_HD int quiet_estimate(const double p8[8], const int64_t n8[8], double u) {
+  const int64_t nR = n8[0], nI = n8[4];
+  if (nR + nI > 1024) return -1;
+  if (n8[1] != nR || n8[2] != nR || n8[3] != nR || n8[5] != nI || n8[6] != nI || n8[7] != nI)
+    return -1;
+  float lr = 0.0f, li = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (!(p8[k] <= 0.5) || !(p8[k + 4] <= 0.5)) return -1;
+    lr += log2f(1.0f - (float)p8[k]);
+    li += log2f(1.0f - (float)p8[k + 4]);
+  }
+  const float E = (float)nR * lr + (float)nI * li;
+  if (!(E > -30.0f)) return -1;
+  const double ga = (double)exp2f(E);
+  const double mg = 1e-5 * (double)(1 + nR + nI);
+  if (u < ga * (1.0 - mg)) return 1;
+  if (u >= ga * (1.0 + mg)) return 0;
+  return -1;
+}
+
+// u < g exactly, by the estimate where it decides, else by the fp64 product.
+// Bit 0: quiet; bit 1: the estimate decided.
+DQ_HD int quiet_test(const double p8[8], const int64_t n8[8], double u) {
+  const int q = quiet_estimate(p8, n8, u);
+  if (q >= 0) return q | 2;
+  double g = 1.0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (n8[k] > 0 && p8[k] > 0.0) g = g * ipow(1.0 - p8[k], n8[k]);
+  return u < g ? 1 : 0;
+}
+
 // What the step does with an entry: 0 (quiet) when all eight channel counts
 // are zero (decided by the primary uniform exactly as channel_counts decides
 // it); otherwise 2 when some channel may be too large to draw by inversion
@@ -275,35 +325,18 @@ DQ_HD EntryProbs entry_probs(const SlotParams &P, double S, uint32_t step, uint3
 // the light path refuses, which tests n_k min(p_k, 1 - p_k) per channel),
 // else 1.  Either path gives the same counts; this only routes
 // the large populations to the general path early.
-enum { ENTRY_QUIET = 0, ENTRY_LIGHT = 1, ENTRY_HEAVY = 2 };
 DQ_HD int entry_kind(const SlotParams &P, double S, uint32_t step, uint32_t l, uint32_t m,
                      int32_t R, int32_t I) {
   const EntryProbs e = entry_probs(P, S, step, l, m, R, I);
-  double g = 1.0;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < 8; ++k)
     if (e.n8[k] > 0 && e.p8[k] >= 1.0) return ENTRY_HEAVY;
-    if (e.n8[k] > 0 && e.p8[k] > 0.0) g = g * ipow(1.0 - e.p8[k], e.n8[k]);
-  }
   Stream prim(e.cnt.seed, e.cnt.solve, e.cnt.cfg, e.cnt.step, 0, nullptr);
-  if (prim.next() < g) return ENTRY_QUIET;
+  if (quiet_test(e.p8, e.n8, prim.next()) & 1) return ENTRY_QUIET;
   const double pm = __builtin_fmax(__builtin_fmax(e.p8[0], e.p8[1]),
                                    __builtin_fmax(e.p8[2], e.p8[3]));
   const int64_t nm = e.n8[0] > e.n8[4] ? e.n8[0] : e.n8[4];
   return (double)nm * pm >= 10.0 ? ENTRY_HEAVY : ENTRY_LIGHT;
-}
-
-DQ_HD bool entry_quiet(const SlotParams &P, double S, uint32_t step, uint32_t l, uint32_t m,
-                       int32_t R, int32_t I) {
-  const EntryProbs e = entry_probs(P, S, step, l, m, R, I);
-  double g = 1.0;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    if (e.n8[k] > 0 && e.p8[k] >= 1.0) return false;
-    if (e.n8[k] > 0 && e.p8[k] > 0.0) g = g * ipow(1.0 - e.p8[k], e.n8[k]);
-  }
-  Stream prim(e.cnt.seed, e.cnt.solve, e.cnt.cfg, e.cnt.step, 0, nullptr);
-  return prim.next() < g;
 }
 
 // One occupied configuration |l><m| with walkers R + iI: draw its clone/death

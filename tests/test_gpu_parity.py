@@ -70,6 +70,47 @@ def test_device_math_bit_exact(dq, orc):
     assert np.array_equal(out[:, 3], 1.0 / x), "device division is not correctly rounded"
 
 
+def test_device_quiet_test_matches_the_product(dq, orc):
+    """The scan's quiet test (a single-precision estimate of the no-event
+    probability with an error band, the fp64 product inside the band) must
+    decide u < g exactly as the oracle's product g does, also for uniforms
+    placed on both sides of g at the band's edges and one ulp away."""
+    rng = np.random.default_rng(12)
+    m = 1500
+    p = rng.uniform(0, 0.06, (m, 4)) * (rng.random((m, 4)) < 0.85)
+    p[: m // 10] = rng.uniform(0, 0.9, (m // 10, 4))        # p > 1/2: the product path
+    n = rng.integers(0, 40, (m, 2))
+    n[m // 10: m // 5] = rng.integers(0, 3000, (m // 10, 2))  # n > 1024: the product path
+    n[n.sum(axis=1) == 0, 0] = 1
+    g = np.array([orc.no_event_prob(np.tile(p[i], 2), np.repeat(n[i], 4)) for i in range(m)])
+    mg = 1e-5 * (1.0 + n.sum(axis=1))
+    rel = [0.0, -1e-12, 1e-12, -1e-7, 1e-7, -0.5, 0.5, -1.0, 1.0, -1.01, 1.01, -2.0, 2.0]
+    us, ps, ns, gs = [], [], [], []
+    for r in rel:
+        us.append(g * (1.0 + r * mg) if r not in (0.0,) else g.copy())
+        ps.append(p)
+        ns.append(n)
+        gs.append(g)
+    for d in (-np.inf, np.inf):  # one ulp below and above
+        us.append(np.nextafter(g, d))
+        ps.append(p)
+        ns.append(n)
+        gs.append(g)
+    us.append(rng.random(m))
+    ps.append(p)
+    ns.append(n)
+    gs.append(g)
+    u, pa, na, ga = (np.concatenate(x) for x in (us, ps, ns, gs))
+    keep = (u >= 0) & (u < 1)
+    u, pa, na, ga = u[keep], pa[keep], na[keep], ga[keep]
+    out = dq.dev_quiet(pa, na, u)
+    assert np.array_equal(out & 1, (u < ga).astype(np.int32))
+    est = (out & 2) != 0
+    assert est.sum() > len(u) // 6 and (~est).sum() > len(u) // 6  # both paths taken
+    with pytest.raises(dq.DDQMCError):
+        dq.dev_quiet([[1.0, 0, 0, 0]], [[1, 0]], [0.5])
+
+
 def test_device_uniforms_bit_exact(dq, orc):
     for args in [(0, 0, 0, 0, 0), (0x123456789ABCDEF0, 17, 0xDEADBEEF12, 44, 3077),
                  (2 ** 64 - 1, 65535, 2 ** 64 - 1, 2 ** 32 - 1, 0xFFFF)]:
