@@ -40,6 +40,12 @@ constexpr int SORT_TILE = NT * SORT_IT;
 constexpr int MERGE_IT = 8;          // merged positions per thread
 constexpr int MERGE_TILE = NT * MERGE_IT;
 constexpr int STAGE = 2048;          // spawn records staged in LDS per block iteration
+// member trees queued per loud chunk (an entry finding no room takes the
+// general path): as many as keep three loud blocks per CU in LDS
+template <typename K>
+constexpr uint32_t tree_jobs() {
+  return sizeof(K) == 4 ? 1024u : 768u;
+}
 constexpr int MAX_PASSES = 8;
 constexpr int NSEG = 64;             // spawn-record segments
 constexpr int COUNT_W = 5;           // per-step counts: in, records, out, loud, heavy
@@ -356,6 +362,40 @@ struct RecordSink {
   }
 };
 
+// The loud kernel's queue of member trees in LDS: an entry reserves places
+// for all of its trees at once (reserve fails when the queue is full; the
+// entry then takes the general path, having emitted nothing), pushes its
+// trees into them, and marks the places it did not use as empty.  Every
+// place below min(*count, cap) is thus written by the entry that took
+// it before the block's barrier.
+static_assert(sizeof(TreeJob) == 24, "tree jobs are sized for the LDS queue");
+struct TreeQueue {
+  TreeJob *jobs;
+  uint32_t *count;
+  uint32_t cap;
+  uint32_t slot;
+  uint32_t at, end;
+  __device__ bool reserve(int k) {
+    const uint32_t b = atomicAdd(count, (uint32_t)k);
+    if (b + (uint32_t)k > cap) {
+      // the places below the end of the queue that this failed reservation
+      // took are read by the walk: mark them empty
+      for (uint32_t i = b; i < cap; ++i) jobs[i].M = 0;
+      return false;
+    }
+    at = b;
+    end = b + (uint32_t)k;
+    return true;
+  }
+  __device__ void push(TreeJob t) {
+    t.slot = (uint16_t)slot;
+    jobs[at++] = t;
+  }
+  __device__ void close() {
+    for (; at < end; ++at) jobs[at].M = 0;
+  }
+};
+
 // Pass 2: the loud entries, densely (the list the scan wrote).  Entries whose
 // draws all take the inversion branch are done here; the few whose channel
 // search finds a spawn count too large for it are appended to late[*nlate]
@@ -363,7 +403,7 @@ struct RecordSink {
 // the merge: a record from a non-initiator parent carries NON_INIT in its
 // unused (re or im) part.
 template <typename K>
-__global__ __launch_bounds__(NT) void k_spawn_loud(
+__global__ __launch_bounds__(NT, 3) void k_spawn_loud(
     Ctrl *ctrl, const SlotParams *__restrict__ sp, const SlotState *__restrict__ ss,
     const uint32_t *__restrict__ lidx, const K *__restrict__ lkey, const int2 *__restrict__ lval,
     uint32_t *__restrict__ late, uint32_t *nlate, K *__restrict__ ok, int2 *__restrict__ ov,
@@ -372,10 +412,14 @@ __global__ __launch_bounds__(NT) void k_spawn_loud(
   __shared__ K sk[STAGE];
   __shared__ int2 sv[STAGE];
   __shared__ uint32_t scount, sbase;
+  // the chunk's member trees, walked after its entries (see below)
+  constexpr uint32_t TREE_JOBS = tree_jobs<K>();
+  __shared__ TreeJob s_jobs[TREE_JOBS];
+  __shared__ uint32_t s_njobs;
   const uint32_t nl = ctrl->n_loud;
   const int seg = blockIdx.x % NSEG;
   const K lowm = low_mask<K>(SB);
-  int rng_err = 0;
+  int rng_err = 0, tree_dry = 0;
   bool int_ovf = false;
   const RecordSink<K> sink{sk, sv, &scount, segcnt, ok, ov, segcap, seg, &int_ovf};
   // chunks of NT entries are handed out by a counter, so that blocks that drew
@@ -387,7 +431,10 @@ __global__ __launch_bounds__(NT) void k_spawn_loud(
   for (;;) {
     const uint32_t base = s_chunk * NT;
     if (base >= nl) break;
-    if (threadIdx.x == 0) scount = 0;
+    if (threadIdx.x == 0) {
+      scount = 0;
+      s_njobs = 0;
+    }
     __syncthreads();
     // the last wave claims the next chunk (its wait overlaps the other waves' sampling)
     if (threadIdx.x == NT - 64) s_next = atomicAdd(&ctrl->loud_next, 1u);
@@ -402,12 +449,32 @@ __global__ __launch_bounds__(NT) void k_spawn_loud(
       const uint32_t N = P.N;
       const uint32_t l = (uint32_t)(cfg >> N);
       const uint32_t m = (uint32_t)(cfg & ((N == 32) ? 0xffffffffull : ((1ull << N) - 1)));
-      const bool done = entry_events_small(
-          P, ss[slot].S, (uint32_t)ss[slot].step, l, m, v.x, v.y, &rng_err,
-          [&](uint32_t cl, uint32_t cm, int64_t dr, int64_t di, bool keep) {
-            sink(hibits | (K)(((uint64_t)cl << N) | cm), dr, di, keep);
-          });
+      const uint32_t step = (uint32_t)ss[slot].step;
+      auto rec = [&](uint32_t cl, uint32_t cm, int64_t dr, int64_t di, bool keep) {
+        sink(hibits | (K)(((uint64_t)cl << N) | cm), dr, di, keep);
+      };
+      TreeQueue tq{s_jobs, &s_njobs, TREE_JOBS, slot, 0, 0};
+      const bool done = entry_events_small(P, ss[slot].S, step, l, m, v.x, v.y, &rng_err, rec, tq);
       if (!done) late[atomicAdd(nlate, 1u)] = lidx[q];
+      tq.close();
+    }
+    __syncthreads();
+    // The member trees (entries spawning two or more walkers into one class:
+    // a few per wave, each a chain of binomial draws) are walked here, one per
+    // thread, instead of by their entry's lane while its 63 neighbours wait.
+    {
+      const uint32_t nj = s_njobs < TREE_JOBS ? s_njobs : TREE_JOBS;
+      for (uint32_t jq = threadIdx.x; jq < nj; jq += NT) {
+        const TreeJob t = s_jobs[jq];
+        if (t.M == 0) continue;  // a reserved place the entry did not use
+        const SlotParams &P = sp[t.slot];
+        const uint32_t N = P.N;
+        const K hib = (SB >= (int)(8 * sizeof(K))) ? (K)0 : (K)((K)t.slot << SB);
+        run_tree_job(P, (uint32_t)ss[t.slot].step, t, tree_dry,
+                     [&](uint32_t cl, uint32_t cm, int64_t dr, int64_t di, bool keep) {
+                       sink(hib | (K)(((uint64_t)cl << N) | cm), dr, di, keep);
+                     });
+      }
     }
     __syncthreads();
     seg_flush(sk, sv, scount < (uint32_t)STAGE ? scount : (uint32_t)STAGE, seg, segcnt, ok, ov,
@@ -416,7 +483,7 @@ __global__ __launch_bounds__(NT) void k_spawn_loud(
     if (threadIdx.x == 0) s_chunk = s_next;
     __syncthreads();
   }
-  if (rng_err) atomicOr(&ctrl->flags, F_RNG);
+  if (rng_err || tree_dry) atomicOr(&ctrl->flags, F_RNG);
   if (int_ovf) atomicOr(&ctrl->flags, F_INT_OVF);
 }
 

@@ -492,12 +492,72 @@ DQ_HD void tree_split_small(int n, int64_t M, const EntryCounter &c, uint32_t dr
   }
 }
 
+// A member tree of the light path, handed to the caller instead of walked in
+// place: the caller walks it later with run_tree_job (the same streams, so
+// the same records), next to the trees of other entries.  The caller's queue
+// has trees.reserve(k) (room for k more trees of this entry, or false) and
+// trees.push(job).
+struct TreeJob {
+  uint32_t l, m;    // the parent configuration
+  uint32_t cr, cu;  // hop: the class's right / up bond origins; jump: cr = jump sites
+  uint16_t slot;    // the parent's solve (set by the caller)
+  uint8_t n, M;     // members; walkers to place (M < 32)
+  uint8_t flags;    // TJ_* below
+  uint8_t cls;      // hop class (its tree's streams)
+  uint16_t pad;
+};
+enum : uint8_t { TJ_IM = 1, TJ_HOP = 2, TJ_KET = 4, TJ_INIT = 8, TJ_NEG = 16 };
+
+// Walk tree job t of solve P (at step `step`): each leaf goes to
+// emit(child_l, child_m, d_re, d_im, survives_filter_unconditionally).
+template <typename Emit>
+DQ_HD void run_tree_job(const SlotParams &P, uint32_t step, const TreeJob &t, int &dry,
+                        Emit &&emit) {
+  const EntryCounter cnt{P.seed, ((uint64_t)t.l << P.N) | t.m, P.solve, step, 0};
+  const int64_t sg = (t.flags & TJ_NEG) ? -1 : 1;
+  const bool part = (t.flags & TJ_IM) != 0;
+  // the root's stream: jumps of channel 3 / 7, hops of channel 4 / 8 by class
+  const uint32_t draw_base = (t.flags & TJ_HOP)
+                                 ? draw_channel(part ? 8 : 4) + 64u + 64u * (uint32_t)t.cls
+                                 : draw_channel(part ? 7 : 3) + 64u;
+  const bool init = (t.flags & TJ_INIT) != 0;
+  const uint32_t l = t.l, m = t.m;
+  if (!(t.flags & TJ_HOP)) {
+    const uint32_t jm = t.cr;
+    tree_split_small(t.n, t.M, cnt, draw_base, dry, [&](int j, int64_t M) {
+      const uint32_t bit = 1u << nth_bit(jm, j);
+      const int64_t v = sg * M;
+      emit(l & ~bit, m & ~bit, part ? 0 : v, part ? v : 0, init);
+    });
+    return;
+  }
+  const uint32_t cr = t.cr, cu = t.cu;
+  const int nr = popc(cr);
+  const bool ket = (t.flags & TJ_KET) != 0;
+  tree_split_small(t.n, t.M, cnt, draw_base, dry, [&](int j, int64_t M) {
+    uint32_t bm;
+    if (j < nr) {
+      const uint32_t s = nth_bit(cr, j);
+      bm = (1u << s) | (1u << right_site(P, s));
+    } else {
+      const uint32_t s = nth_bit(cu, j - nr);
+      bm = (1u << s) | (1u << up_site(P, s));
+    }
+    const uint32_t cl = ket ? (l ^ bm) : l;
+    const uint32_t cm = ket ? m : (m ^ bm);
+    const int64_t v = sg * M;
+    // Re parent x Im element -> Im child; Im parent -> -Re child
+    emit(cl, cm, part ? -v : 0, part ? 0 : v, init || cl == cm);
+  });
+}
+
 // entry_events for entries whose every draw uses inversion; returns false
 // (having emitted nothing) when the entry needs the general path.  The draws,
 // and so the contributions, are identical to entry_events'.
-template <typename Emit>
+template <typename Emit, typename Trees>
 DQ_HD bool entry_events_small(const SlotParams &P, double S, uint32_t step, uint32_t l,
-                              uint32_t m, int32_t R, int32_t I, int *err, Emit &&emit) {
+                              uint32_t m, int32_t R, int32_t I, int *err, Emit &&emit,
+                              Trees &trees) {
   const EntryProbs e = entry_probs(P, S, step, l, m, R, I);
   const double pk[4] = {e.p8[0], e.p8[1], e.p8[2], e.p8[3]};
   const int64_t nR = e.n8[0], nI = e.n8[4];
@@ -551,6 +611,12 @@ DQ_HD bool entry_events_small(const SlotParams &P, double S, uint32_t step, uint
   }
   // larger spawn counts can need the rejection sampler in their splits
   if (X2 >= 20 || X3 >= 20 || X6 >= 20 || X7 >= 20) return false;
+  // room for the entry's member trees (one per jump part with two or more
+  // walkers, one per hop class reached by a part with two or more), else the
+  // general path takes the entry
+  const int ntree = (X2 >= 2 ? 1 : 0) + (X6 >= 2 ? 1 : 0) + (X3 >= 2 ? (X3 < 6 ? (int)X3 : 6) : 0) +
+                    (X7 >= 2 ? (X7 < 6 ? (int)X7 : 6) : 0);
+  if (ntree > 0 && !trees.reserve(ntree)) return false;
   if (dry) *err = 1;
 
   // the hop classes again, after the channel search, so that their tables are
@@ -596,7 +662,10 @@ DQ_HD bool entry_events_small(const SlotParams &P, double S, uint32_t step, uint
       if (cj == 1)
         leaf(pick_member(e.cnt, draw_channel(part ? 7 : 3) + DRAW_PICK, e.nJ), 1);
       else
-        tree_split_small(e.nJ, cj, e.cnt, draw_channel(part ? 7 : 3) + 64u, dry, leaf);
+        trees.push(TreeJob{l, m, jm, 0u, 0, (uint8_t)e.nJ, (uint8_t)cj,
+                           (uint8_t)((part ? TJ_IM : 0) | (init ? TJ_INIT : 0) |
+                                     (sg < 0 ? TJ_NEG : 0)),
+                           0, 0});
     }
     int64_t rem = part ? X7 : X3;
     if (rem == 0) continue;
@@ -646,24 +715,12 @@ DQ_HD bool entry_events_small(const SlotParams &P, double S, uint32_t step, uint
       if (Mc == 0) continue;
       const uint32_t cr = sel6(c, cr0, cr1, cr2, cr3, cr4, cr5);
       const uint32_t cu = sel6(c, cu0, cu1, cu2, cu3, cu4, cu5);
-      const int nr = popc(cr);
       const int64_t sv = sg * (int64_t)sel6(c, cs0, cs1, cs2, cs3, cs4, cs5);
-      tree_split_small(sel6(c, cn0, cn1, cn2, cn3, cn4, cn5), Mc, e.cnt,
-                       draw_channel(ch) + 64u + 64u * (uint32_t)c, dry, [&](int j, int64_t M) {
-                         uint32_t bm;
-                         if (j < nr) {
-                           const uint32_t s = nth_bit(cr, j);
-                           bm = (1u << s) | (1u << right_site(P, s));
-                         } else {
-                           const uint32_t s = nth_bit(cu, j - nr);
-                           bm = (1u << s) | (1u << up_site(P, s));
-                         }
-                         const uint32_t cl = c < 3 ? (l ^ bm) : l;
-                         const uint32_t cm = c < 3 ? m : (m ^ bm);
-                         const int64_t v = sv * M;
-                         // Re parent x Im element -> Im child; Im parent -> -Re child
-                         emit(cl, cm, part ? -v : 0, part ? 0 : v, init || cl == cm);
-                       });
+      trees.push(TreeJob{l, m, cr, cu, 0, (uint8_t)sel6(c, cn0, cn1, cn2, cn3, cn4, cn5),
+                         (uint8_t)Mc,
+                         (uint8_t)(TJ_HOP | (part ? TJ_IM : 0) | (c < 3 ? TJ_KET : 0) |
+                                   (init ? TJ_INIT : 0) | (sv < 0 ? TJ_NEG : 0)),
+                         (uint8_t)c, 0});
     }
   }
   if (dry) *err = 1;
