@@ -208,6 +208,13 @@ int ddqmc_set_graph_steps(ddqmc_t *h, int32_t k);
  * join cost more than they save), 1: always, -1: never.  The results are the
  * same either way.  EINVAL for other modes. */
 int ddqmc_set_heavy_fork(ddqmc_t *h, int32_t mode);
+/* Places in the loud kernel's per-chunk queue of member trees (the binomial
+ * trees that spread two or more walkers over the members of a class,
+ * Sec. III.B): an entry whose trees find no room takes the general path,
+ * and the results are the same either way.  0 (default): the most the
+ * kernel holds, 1024 with 32-bit keys and 768 with 64-bit keys.  EINVAL
+ * below 0 or above that. */
+int ddqmc_set_tree_queue(ddqmc_t *h, int32_t places);
 int ddqmc_stage_times(ddqmc_t *h, double ms[10], int64_t *steps);
 
 /* ---- device self-checks of the sampling primitives --------------------------

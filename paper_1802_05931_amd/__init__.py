@@ -123,6 +123,11 @@ class _Handle:
         """Large-population entries on a second stream: 0 by list size, 1 always, -1 never."""
         check(lib().ddqmc_set_heavy_fork(self._h, int(mode)), "set_heavy_fork")
 
+    def set_tree_queue(self, places):
+        """Member-tree places per loud chunk (0: the most the kernel holds); entries
+        whose trees find no room take the general path, with the same results."""
+        check(lib().ddqmc_set_tree_queue(self._h, int(places)), "set_tree_queue")
+
     def stage_times(self):
         ms = (ctypes.c_double * len(STAGES))()
         steps = ctypes.c_int64()

@@ -99,6 +99,7 @@ struct ddqmc_t {
   bool fork_heavy = false;  // only for large lists: a fork and join cost more than
                             // the heavy kernel saves on a short step
   int fork_mode = 0;        // 0 by list capacity, 1 always, -1 never
+  uint32_t tree_cap = 0;    // member-tree places per loud chunk (0: all the kernel holds)
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   uint64_t gexec_gen[2] = {~0ull, ~0ull};
   int gexec_k[2] = {0, 0};
@@ -435,9 +436,10 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
   if (ev) HIPC(hipEventRecord(ev->e[2], s));
   uint32_t *late = h->fork_heavy ? h->late : h->heavy;
   uint32_t *nlate = h->fork_heavy ? &c->n_late : &c->n_heavy;
+  const uint32_t tcap = h->tree_cap ? h->tree_cap : tree_jobs<K>();
   k_spawn_loud<K><<<g_loud, NT, 0, s>>>(c, h->dsp, h->dss, h->lidx, (const K *)h->lkey, h->lval,
                                         late, nlate, (K *)h->sk[0], h->sv[0], h->segcnt, segcap,
-                                        h->SB);
+                                        tcap, h->SB);
   if (ev) HIPC(hipEventRecord(ev->e[3], s));
   // the entries the loud kernel passed on (with the fork: usually none), then
   // the join
@@ -1135,6 +1137,15 @@ int ddqmc_set_heavy_fork(ddqmc_t *h, int32_t mode) {
   h->fork_mode = mode;
   h->fork_heavy = mode > 0 || (mode == 0 && h->cap_main >= FORK_MIN_CAP);
   h->buf_gen += 1;  // captured graphs hold the other launch sequence
+  return DDQMC_OK;
+}
+
+int ddqmc_set_tree_queue(ddqmc_t *h, int32_t places) {
+  if (!h || places < 0) return DDQMC_EINVAL;
+  const uint32_t most = h->k64 ? tree_jobs<uint64_t>() : tree_jobs<uint32_t>();
+  if ((uint32_t)places > most) return DDQMC_EINVAL;
+  h->tree_cap = (uint32_t)places;
+  h->buf_gen += 1;  // captured graphs hold the old kernel argument
   return DDQMC_OK;
 }
 

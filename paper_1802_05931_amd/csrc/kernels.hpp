@@ -407,7 +407,7 @@ __global__ __launch_bounds__(NT, 3) void k_spawn_loud(
     Ctrl *ctrl, const SlotParams *__restrict__ sp, const SlotState *__restrict__ ss,
     const uint32_t *__restrict__ lidx, const K *__restrict__ lkey, const int2 *__restrict__ lval,
     uint32_t *__restrict__ late, uint32_t *nlate, K *__restrict__ ok, int2 *__restrict__ ov,
-    uint32_t *segcnt, uint32_t segcap, int SB) {
+    uint32_t *segcnt, uint32_t segcap, uint32_t tree_cap, int SB) {
   if (ctrl->abort) return;
   __shared__ K sk[STAGE];
   __shared__ int2 sv[STAGE];
@@ -416,6 +416,7 @@ __global__ __launch_bounds__(NT, 3) void k_spawn_loud(
   constexpr uint32_t TREE_JOBS = tree_jobs<K>();
   __shared__ TreeJob s_jobs[TREE_JOBS];
   __shared__ uint32_t s_njobs;
+  const uint32_t tcap = tree_cap < TREE_JOBS ? tree_cap : TREE_JOBS;
   const uint32_t nl = ctrl->n_loud;
   const int seg = blockIdx.x % NSEG;
   const K lowm = low_mask<K>(SB);
@@ -453,7 +454,7 @@ __global__ __launch_bounds__(NT, 3) void k_spawn_loud(
       auto rec = [&](uint32_t cl, uint32_t cm, int64_t dr, int64_t di, bool keep) {
         sink(hibits | (K)(((uint64_t)cl << N) | cm), dr, di, keep);
       };
-      TreeQueue tq{s_jobs, &s_njobs, TREE_JOBS, slot, 0, 0};
+      TreeQueue tq{s_jobs, &s_njobs, tcap, slot, 0, 0};
       const bool done = entry_events_small(P, ss[slot].S, step, l, m, v.x, v.y, &rng_err, rec, tq);
       if (!done) late[atomicAdd(nlate, 1u)] = lidx[q];
       tq.close();
@@ -463,7 +464,7 @@ __global__ __launch_bounds__(NT, 3) void k_spawn_loud(
     // a few per wave, each a chain of binomial draws) are walked here, one per
     // thread, instead of by their entry's lane while its 63 neighbours wait.
     {
-      const uint32_t nj = s_njobs < TREE_JOBS ? s_njobs : TREE_JOBS;
+      const uint32_t nj = s_njobs < tcap ? s_njobs : tcap;
       for (uint32_t jq = threadIdx.x; jq < nj; jq += NT) {
         const TreeJob t = s_jobs[jq];
         if (t.M == 0) continue;  // a reserved place the entry did not use

@@ -29,9 +29,11 @@ def _same_list(a, b):
             and np.array_equal(a[2], b[2]))
 
 
-def _compare_run(dq, orc, cfg, chunks, per, check_series=True, fork=0):
+def _compare_run(dq, orc, cfg, chunks, per, check_series=True, fork=0, tree_queue=0,
+                 stats=None):
     g = dq.Solve(dq.make_params(**cfg))
     g.set_heavy_fork(fork)
+    g.set_tree_queue(tree_queue)
     o = orc.Oracle(**{k: v for k, v in cfg.items() if k != "capacity_hint"})
     for c in range(chunks):
         g.step(per)
@@ -53,6 +55,8 @@ def _compare_run(dq, orc, cfg, chunks, per, check_series=True, fork=0):
     for k, v in ratios.items():
         assert go[k] == v or (np.isnan(go[k]) and np.isnan(v)), k
     n = len(gl[0])
+    if stats is not None:
+        stats["general_path_entries"] = int(g.step_counts()[:, 4].sum())
     g.close()
     return n
 
@@ -149,6 +153,25 @@ def test_5x5_u64_keys(dq, orc, fork):
     cfg = dict(Lx=5, Ly=5, Jx=0.7, Jy=1.0, Jz=1.0, gamma=1.0, dt=0.002, n_a=3,
                target_walkers=20000, initial_walkers=20000, shift_init=0.0, n_equil=10, seed=3)
     _compare_run(dq, orc, cfg, chunks=3, per=40, fork=fork)
+
+
+@pytest.mark.parametrize("lattice,places", [("3x3", 1), ("3x3", 6), ("5x5", 2)])
+def test_tree_queue_full_takes_the_general_path(dq, orc, lattice, places):
+    """With a member-tree queue of a few places most entries with trees find no
+    room and take the general path: the lists stay the oracle's, and more
+    entries take the general path than with the full queue."""
+    if lattice == "3x3":
+        cfg = dict(workloads.d2(0.6), target_walkers=20000, n_equil=200)
+        chunks, per = 2, 250
+    else:
+        cfg = dict(Lx=5, Ly=5, Jx=0.7, Jy=1.0, Jz=1.0, gamma=1.0, dt=0.002, n_a=3,
+                   target_walkers=20000, initial_walkers=20000, shift_init=0.0, n_equil=10,
+                   seed=3)
+        chunks, per = 2, 40
+    full, small = {}, {}
+    _compare_run(dq, orc, cfg, chunks=chunks, per=per, stats=full)
+    _compare_run(dq, orc, cfg, chunks=chunks, per=per, tree_queue=places, stats=small)
+    assert small["general_path_entries"] > full["general_path_entries"], (small, full)
 
 
 @pytest.mark.parametrize("Lx,Ly,is_p,dt,S,nent,pop,n_a", [
@@ -297,6 +320,12 @@ def test_graph_steps_invalid(dq):
         with pytest.raises(DDQMCError) as e:
             g.set_heavy_fork(m)
         assert e.value.code == -1
+    for q in (-1, 1025):
+        with pytest.raises(DDQMCError) as e:
+            g.set_tree_queue(q)
+        assert e.value.code == -1
+    g.set_tree_queue(1024)
+    g.set_tree_queue(3)
     g.step(3)
     g.close()
 
