@@ -262,16 +262,19 @@ def test_pool_admit_retire_equals_alone(dq, orc):
 @pytest.mark.parametrize("fork", [0, 1])
 def test_graph_steps_equal_eager(dq, orc, fork):
     """k-step HIP graphs (replayed several times per call, re-captured after
-    the buffers grow from a tiny capacity) give the eager launches' lists, which
-    the oracle checks too; with fork = 1 the heavy entries run on the second
-    stream (fork and join inside the graph)."""
+    the buffers grow from a tiny capacity and after the tree queue shrinks)
+    give the eager launches' lists, which the oracle checks too; with fork = 1
+    the heavy entries run on the second stream (fork and join inside the
+    graph)."""
     cfg = dict(workloads.d2(0.6), target_walkers=20000, capacity_hint=16, n_equil=60)
     a = dq.Solve(dq.make_params(**cfg))
     b = dq.Solve(dq.make_params(**cfg))
     b.set_heavy_fork(fork)
     b.set_graph_steps(10)
     o = orc.Oracle(**{k: v for k, v in cfg.items() if k != "capacity_hint"})
-    for per in (35, 35, 120, 7, 64):
+    for i, per in enumerate((35, 35, 120, 7, 64)):
+        if i == 3:
+            b.set_tree_queue(2)  # a new kernel argument: the graph is captured again
         a.step(per)
         b.step(per)
         o.step(per)
