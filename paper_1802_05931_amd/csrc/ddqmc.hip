@@ -100,6 +100,8 @@ struct ddqmc_t {
                             // the heavy kernel saves on a short step
   int fork_mode = 0;        // 0 by list capacity, 1 always, -1 never
   uint32_t tree_cap = 0;    // member-tree places per loud chunk (0: all the kernel holds)
+  bool loud_dyn = false;    // loud kernel: resident blocks and a chunk counter (else a
+                            // block per chunk); chosen per chunk of steps, see run_steps
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   uint64_t gexec_gen[2] = {~0ull, ~0ull};
   int gexec_k[2] = {0, 0};
@@ -415,7 +417,8 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
   const uint32_t capC = (uint32_t)h->cap_main;
   const uint32_t segcap = (uint32_t)(h->cap_sp / NSEG);
   // grids from the capacities: every kernel loops over the device-side counts
-  const uint32_t g_loud = clampu(h->nscan, 1, h->loud_blocks);
+  const uint32_t g_loud = h->loud_dyn ? clampu(h->nscan, 1, h->loud_blocks)
+                                      : clampu((h->cap_main + NT - 1) / NT, 1, 8 * h->loud_blocks);
   const uint32_t g_heavy = h->heavy_blocks;
   const uint32_t g_s = clampu(sort_tiles(h->cap_sp), 1, 1u << 24);
   const uint32_t g_m = clampu(merge_tiles(h->cap_main, h->cap_sp), 1, 1u << 20);
@@ -439,7 +442,7 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
   const uint32_t tcap = h->tree_cap ? h->tree_cap : tree_jobs<K>();
   k_spawn_loud<K><<<g_loud, NT, 0, s>>>(c, h->dsp, h->dss, h->lidx, (const K *)h->lkey, h->lval,
                                         late, nlate, (K *)h->sk[0], h->sv[0], h->segcnt, segcap,
-                                        tcap, h->SB);
+                                        tcap, h->loud_dyn ? 1 : 0, h->SB);
   if (ev) HIPC(hipEventRecord(ev->e[3], s));
   // the entries the loud kernel passed on (with the fork: usually none), then
   // the join
@@ -639,6 +642,19 @@ int run_steps(ddqmc_t *h, int64_t n) {
       std::vector<uint32_t> cnt((size_t)done * COUNT_W);
       HIPC(hipMemcpy(cnt.data(), h->counts, cnt.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
       h->hcounts.insert(h->hcounts.end(), cnt.begin(), cnt.end());
+      // The loud kernel's grid for the next chunk of steps, from the last
+      // step's loud and large-population entries: while the heavy kernel's
+      // list is small (below 0.25% of the loud list), one block per chunk of
+      // entries, so that the heavy waves find room as loud blocks retire; when
+      // it is large (above 1%), resident blocks, so that the loud kernel keeps
+      // its CUs.  In between the grid stays as it is.
+      const uint64_t n_loud = cnt[((size_t)done - 1) * COUNT_W + 3];
+      const uint64_t n_heavy = cnt[((size_t)done - 1) * COUNT_W + 4];
+      const bool dyn = h->loud_dyn ? !(n_heavy * 400 < n_loud) : (n_heavy * 100 > n_loud);
+      if (dyn != h->loud_dyn) {
+        h->loud_dyn = dyn;
+        h->buf_gen += 1;  // captured graphs hold the other grid
+      }
     }
     if (h->profiling) {
       for (uint32_t j = 0; j < done; j += (uint32_t)h->prof_every) {

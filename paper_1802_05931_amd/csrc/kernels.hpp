@@ -407,7 +407,7 @@ __global__ __launch_bounds__(NT, 3) void k_spawn_loud(
     Ctrl *ctrl, const SlotParams *__restrict__ sp, const SlotState *__restrict__ ss,
     const uint32_t *__restrict__ lidx, const K *__restrict__ lkey, const int2 *__restrict__ lval,
     uint32_t *__restrict__ late, uint32_t *nlate, K *__restrict__ ok, int2 *__restrict__ ov,
-    uint32_t *segcnt, uint32_t segcap, uint32_t tree_cap, int SB) {
+    uint32_t *segcnt, uint32_t segcap, uint32_t tree_cap, int dyn, int SB) {
   if (ctrl->abort) return;
   __shared__ K sk[STAGE];
   __shared__ int2 sv[STAGE];
@@ -423,11 +423,13 @@ __global__ __launch_bounds__(NT, 3) void k_spawn_loud(
   int rng_err = 0, tree_dry = 0;
   bool int_ovf = false;
   const RecordSink<K> sink{sk, sv, &scount, segcnt, ok, ov, segcap, seg, &int_ovf};
-  // chunks of NT entries are handed out by a counter, so that blocks that drew
-  // cheap chunks take more of them; the next chunk is claimed while the
-  // current one is sampled
+  // chunks of NT entries: with dyn, handed out by a counter to blocks that
+  // stay resident (blocks that drew cheap chunks take more of them; the next
+  // chunk is claimed while the current one is sampled); otherwise block b
+  // takes chunks b, b + gridDim.x, ..., and a grid of about one block per
+  // chunk retires block by block, which lets the heavy kernel beside it in
   __shared__ uint32_t s_chunk, s_next;
-  if (threadIdx.x == 0) s_chunk = atomicAdd(&ctrl->loud_next, 1u);
+  if (threadIdx.x == 0) s_chunk = dyn ? atomicAdd(&ctrl->loud_next, 1u) : blockIdx.x;
   __syncthreads();
   for (;;) {
     const uint32_t base = s_chunk * NT;
@@ -438,7 +440,7 @@ __global__ __launch_bounds__(NT, 3) void k_spawn_loud(
     }
     __syncthreads();
     // the last wave claims the next chunk (its wait overlaps the other waves' sampling)
-    if (threadIdx.x == NT - 64) s_next = atomicAdd(&ctrl->loud_next, 1u);
+    if (threadIdx.x == NT - 64) s_next = dyn ? atomicAdd(&ctrl->loud_next, 1u) : s_chunk + gridDim.x;
     const uint32_t q = base + threadIdx.x;
     if (q < nl) {
       const K key = lkey[q];
