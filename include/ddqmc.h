@@ -215,6 +215,13 @@ int ddqmc_set_heavy_fork(ddqmc_t *h, int32_t mode);
  * kernel holds, 1024 with 32-bit keys and 768 with 64-bit keys.  EINVAL
  * below 0 or above that. */
 int ddqmc_set_tree_queue(ddqmc_t *h, int32_t places);
+/* Grid of the loud spawn kernel.  0 (default): chosen per chunk of steps from
+ * the last step's counts (one block per 256-entry chunk while the list of
+ * large-population entries is small beside the loud list, resident blocks
+ * taking chunks from a counter when it is large); 1: always resident blocks;
+ * 2: always a block per chunk.  The results are the same either way.  EINVAL
+ * for other modes. */
+int ddqmc_set_loud_grid(ddqmc_t *h, int32_t mode);
 int ddqmc_stage_times(ddqmc_t *h, double ms[10], int64_t *steps);
 
 /* ---- device self-checks of the sampling primitives --------------------------

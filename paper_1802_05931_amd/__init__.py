@@ -128,6 +128,11 @@ class _Handle:
         whose trees find no room take the general path, with the same results."""
         check(lib().ddqmc_set_tree_queue(self._h, int(places)), "set_tree_queue")
 
+    def set_loud_grid(self, mode):
+        """Loud kernel grid: 0 chosen per chunk of steps, 1 resident blocks, 2 a block
+        per chunk of entries (same results either way)."""
+        check(lib().ddqmc_set_loud_grid(self._h, int(mode)), "set_loud_grid")
+
     def stage_times(self):
         ms = (ctypes.c_double * len(STAGES))()
         steps = ctypes.c_int64()

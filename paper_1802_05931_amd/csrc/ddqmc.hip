@@ -102,6 +102,7 @@ struct ddqmc_t {
   uint32_t tree_cap = 0;    // member-tree places per loud chunk (0: all the kernel holds)
   bool loud_dyn = false;    // loud kernel: resident blocks and a chunk counter (else a
                             // block per chunk); chosen per chunk of steps, see run_steps
+  int loud_grid = 0;        // 0 chosen per chunk of steps, 1 resident, 2 block per chunk
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   uint64_t gexec_gen[2] = {~0ull, ~0ull};
   int gexec_k[2] = {0, 0};
@@ -650,7 +651,10 @@ int run_steps(ddqmc_t *h, int64_t n) {
       // its CUs.  In between the grid stays as it is.
       const uint64_t n_loud = cnt[((size_t)done - 1) * COUNT_W + 3];
       const uint64_t n_heavy = cnt[((size_t)done - 1) * COUNT_W + 4];
-      const bool dyn = h->loud_dyn ? !(n_heavy * 400 < n_loud) : (n_heavy * 100 > n_loud);
+      const bool dyn = h->loud_grid == 1   ? true
+                       : h->loud_grid == 2 ? false
+                       : h->loud_dyn       ? !(n_heavy * 400 < n_loud)
+                                           : (n_heavy * 100 > n_loud);
       if (dyn != h->loud_dyn) {
         h->loud_dyn = dyn;
         h->buf_gen += 1;  // captured graphs hold the other grid
@@ -1153,6 +1157,17 @@ int ddqmc_set_heavy_fork(ddqmc_t *h, int32_t mode) {
   h->fork_mode = mode;
   h->fork_heavy = mode > 0 || (mode == 0 && h->cap_main >= FORK_MIN_CAP);
   h->buf_gen += 1;  // captured graphs hold the other launch sequence
+  return DDQMC_OK;
+}
+
+int ddqmc_set_loud_grid(ddqmc_t *h, int32_t mode) {
+  if (!h || mode < 0 || mode > 2) return DDQMC_EINVAL;
+  h->loud_grid = mode;
+  const bool dyn = mode == 1 || (mode == 0 && h->loud_dyn);
+  if (dyn != h->loud_dyn) {
+    h->loud_dyn = dyn;
+    h->buf_gen += 1;  // captured graphs hold the other grid
+  }
   return DDQMC_OK;
 }
 

@@ -30,10 +30,11 @@ def _same_list(a, b):
 
 
 def _compare_run(dq, orc, cfg, chunks, per, check_series=True, fork=0, tree_queue=0,
-                 stats=None):
+                 stats=None, loud_grid=0):
     g = dq.Solve(dq.make_params(**cfg))
     g.set_heavy_fork(fork)
     g.set_tree_queue(tree_queue)
+    g.set_loud_grid(loud_grid)
     o = orc.Oracle(**{k: v for k, v in cfg.items() if k != "capacity_hint"})
     for c in range(chunks):
         g.step(per)
@@ -135,10 +136,10 @@ def test_plain_2x2_d1(dq, orc):
     assert n > 5
 
 
-@pytest.mark.parametrize("fork", [0, 1])
-def test_plain_3x3_jx06(dq, orc, fork):
+@pytest.mark.parametrize("fork,loud_grid", [(0, 0), (1, 0), (0, 1), (1, 2)])
+def test_plain_3x3_jx06(dq, orc, fork, loud_grid):
     cfg = dict(workloads.d2(0.6), target_walkers=20000, n_equil=200)
-    n = _compare_run(dq, orc, cfg, chunks=4, per=250, fork=fork)
+    n = _compare_run(dq, orc, cfg, chunks=4, per=250, fork=fork, loud_grid=loud_grid)
     assert n > 2 * 2048, "should span several tiles"
 
 
@@ -273,6 +274,8 @@ def test_graph_steps_equal_eager(dq, orc, fork):
     b.set_graph_steps(10)
     o = orc.Oracle(**{k: v for k, v in cfg.items() if k != "capacity_hint"})
     for i, per in enumerate((35, 35, 120, 7, 64)):
+        if i == 2:
+            b.set_loud_grid(1)  # another loud grid: the graph is captured again
         if i == 3:
             b.set_tree_queue(2)  # a new kernel argument: the graph is captured again
         a.step(per)
@@ -327,6 +330,12 @@ def test_graph_steps_invalid(dq):
         with pytest.raises(DDQMCError) as e:
             g.set_tree_queue(q)
         assert e.value.code == -1
+    for q in (-1, 3):
+        with pytest.raises(DDQMCError) as e:
+            g.set_loud_grid(q)
+        assert e.value.code == -1
+    g.set_loud_grid(2)
+    g.set_loud_grid(1)
     g.set_tree_queue(1024)
     g.set_tree_queue(3)
     g.step(3)
