@@ -214,6 +214,7 @@ def counter_summary(fetch_dir, write_dir, probe_mb, workload, valu_dir=None):
     if valu_dir:
         valu, waves = load(valu_dir, "SQ_INSTS_VALU"), load(valu_dir, "SQ_WAVES")
         print("\n| kernel | dispatches | waves | VALU wave-instructions |\n|---|---:|---:|---:|")
+        best = {}  # per kernel, the instantiation with the most instructions per launch
         for name in sorted(valu):
             if "elementwise" in name or name.startswith("__amd"):
                 continue
@@ -221,12 +222,13 @@ def counter_summary(fetch_dir, write_dir, probe_mb, workload, valu_dir=None):
             w = sum(waves[name]) / len(waves[name]) if name in waves else 0
             print(f"| {name} | {len(valu[name])} | {w:.0f} | {v:.0f} |")
             for short in ("k_spawn_loud", "k_spawn_heavy", "k_spawn_scan"):
-                if name.startswith(short + "<unsigned int>"):
-                    path = os.path.join(ROOT, "profiles", f"{short}_{workload}_valu.json")
-                    with open(path, "w") as f:
-                        json.dump({"valu_per_launch": v, "source_hash": kernel_source_hash()},
-                                  f, indent=1)
-                    print(f"wrote {path}")
+                if name.startswith(short + "<unsigned int") and v > best.get(short, -1.0):
+                    best[short] = v
+        for short, v in best.items():
+            path = os.path.join(ROOT, "profiles", f"{short}_{workload}_valu.json")
+            with open(path, "w") as f:
+                json.dump({"valu_per_launch": v, "source_hash": kernel_source_hash()}, f, indent=1)
+            print(f"wrote {path}")
 
 
 def _walker_updates(series, steps):

@@ -322,12 +322,12 @@ int build(ddqmc_t *h, int nslots, int Nmax, uint64_t cap, void *stream) {
       HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(
           &nl, reinterpret_cast<const void *>(&k_spawn_loud<uint64_t>), NT, 0));
       HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &nh, reinterpret_cast<const void *>(&k_spawn_heavy<uint64_t>), 64, 0));
+          &nh, reinterpret_cast<const void *>(&k_spawn_heavy<uint64_t, 1>), 64, 0));
     } else {
       HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(
           &nl, reinterpret_cast<const void *>(&k_spawn_loud<uint32_t>), NT, 0));
       HIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &nh, reinterpret_cast<const void *>(&k_spawn_heavy<uint32_t>), 64, 0));
+          &nh, reinterpret_cast<const void *>(&k_spawn_heavy<uint32_t, 1>), 64, 0));
     }
     h->loud_blocks = clampu((uint64_t)std::max(ncu, 1) * (uint64_t)std::max(nl, 1), 1, 4096);
     h->heavy_blocks = clampu((uint64_t)std::max(ncu, 1) * (uint64_t)std::max(nh, 1), 1, 8192);
@@ -432,9 +432,16 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
     // the scan's heavy list on the second stream, alongside the loud kernel
     HIPC(hipEventRecord(h->ev_fork, s));
     HIPC(hipStreamWaitEvent(h->side, h->ev_fork, 0));
-    k_spawn_heavy<K><<<g_heavy, 64, 0, h->side>>>(ak, av, c, h->dsp, h->dss, h->heavy,
-                                                  &c->n_heavy, (K *)h->sk[0], h->sv[0],
-                                                  h->segcnt, segcap, h->SB);
+    // (a short list, with the loud kernel's grid of a block per chunk: the
+    // kernel built for three waves per SIMD, whose waves find room sooner)
+    if (h->loud_dyn)
+      k_spawn_heavy<K, 1><<<g_heavy, 64, 0, h->side>>>(ak, av, c, h->dsp, h->dss, h->heavy,
+                                                       &c->n_heavy, (K *)h->sk[0], h->sv[0],
+                                                       h->segcnt, segcap, h->SB);
+    else
+      k_spawn_heavy<K, 3><<<g_heavy, 64, 0, h->side>>>(ak, av, c, h->dsp, h->dss, h->heavy,
+                                                       &c->n_heavy, (K *)h->sk[0], h->sv[0],
+                                                       h->segcnt, segcap, h->SB);
     HIPC(hipEventRecord(h->ev_join, h->side));
   }
   if (ev) HIPC(hipEventRecord(ev->e[2], s));
@@ -447,7 +454,7 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
   if (ev) HIPC(hipEventRecord(ev->e[3], s));
   // the entries the loud kernel passed on (with the fork: usually none), then
   // the join
-  k_spawn_heavy<K><<<h->fork_heavy ? clampu(g_heavy, 1, 512) : g_heavy, 64, 0, s>>>(
+  k_spawn_heavy<K, 1><<<h->fork_heavy ? clampu(g_heavy, 1, 512) : g_heavy, 64, 0, s>>>(
       ak, av, c, h->dsp, h->dss, late, nlate, (K *)h->sk[0], h->sv[0], h->segcnt, segcap, h->SB);
   if (h->fork_heavy) HIPC(hipStreamWaitEvent(s, h->ev_join, 0));
   if (ev) HIPC(hipEventRecord(ev->e[4], s));

@@ -506,8 +506,13 @@ __global__ __launch_bounds__(NT, 3) void k_spawn_loud(
 constexpr int HEAVY_FRONT = 320;     // tree nodes per frontier level
 constexpr uint32_t HEAVY_STAGE = 512;  // records staged in LDS per entry (the rest go direct)
 
-template <typename K>
-__global__ __launch_bounds__(64) void k_spawn_heavy(
+// MINW: waves per SIMD the kernel is compiled for.  1 leaves the compiler its
+// registers (two waves per SIMD): the most entries per second, for long
+// lists.  3 holds it to 168 VGPRs (with spills): beside the loud kernel its
+// waves then find room sooner, which shortens the spawn stage when the list
+// is short.  The draws, and so the records, are the same.
+template <typename K, int MINW>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MINW))) void k_spawn_heavy(
     const K *__restrict__ keys, const int2 *__restrict__ vals, Ctrl *ctrl,
     const SlotParams *__restrict__ sp, const SlotState *__restrict__ ss,
     const uint32_t *__restrict__ heavy, const uint32_t *__restrict__ nheavy, K *__restrict__ ok,
