@@ -467,7 +467,10 @@ __global__ __launch_bounds__(NT, 3) void k_spawn_loud(
     // thread, instead of by their entry's lane while its 63 neighbours wait.
     {
       const uint32_t nj = s_njobs < tcap ? s_njobs : tcap;
-      for (uint32_t jq = threadIdx.x; jq < nj; jq += NT) {
+      // job r * NT + 4 i + w goes to lane i of wave w: the jobs spread over
+      // the block's four waves (and SIMDs) instead of filling the first one
+      const uint32_t jt = (threadIdx.x & 63u) * (NT / 64) + (threadIdx.x >> 6);
+      for (uint32_t jq = jt; jq < nj; jq += NT) {
         const TreeJob t = s_jobs[jq];
         if (t.M == 0) continue;  // a reserved place the entry did not use
         const SlotParams &P = sp[t.slot];
