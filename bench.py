@@ -13,7 +13,18 @@ roofline position of the kernel that takes most of the step time (algorithmic
 bytes per launch / its mean duration from HIP events on the handle's stream),
 and the CPU oracle timed on a bounded sample of the same workload.
 
-Usage: python bench.py [--steps K] [--warmup W] [--workload d3|d3l] [--no-cpu]
+Before the W warm-up steps the solve is always brought to its steady list:
+it is stepped in chunks of 500 until the list size changes by less than 1%
+over the last 1000 steps (at least 2000 steps; the 4x4 list settles at about
+1.1e7 entries after some 14,000 steps), so that the timed steps see the
+workload's own list and not the start-up transient.
+
+The default line also carries the two systems forms beside the plain step:
+"batched" (64 5x5 replicas in one batch handle against the same replicas one
+after another) and "served" (the 512-request serving stream against the same
+requests one at a time), each with its own timing and equal-error check.
+
+Usage: python bench.py [--steps K] [--warmup W] [--workload d3|d3l] [--no-cpu] [--legs d3,d5,d4]
        python bench.py --workload d5 [--steps K]    (64 5x5 replicas, batched vs one by one)
        python bench.py --workload d4 [--requests R]  (serving loop vs one solve at a time)
        python bench.py --trace-summary DIR --steps K
@@ -38,6 +49,19 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 VALU_PEAK_G = 256 * 4 * 2.4 / 4  # G wave64 VALU instructions/s: 256 CUs x 4 SIMDs, 4 cycles each
 PROF_EVERY = 10  # timed steps per step with stage events
 KEY_BYTES = {True: 8, False: 4}
+# (record name, kernel name in the rocprofv3 output) of the 32-bit-key step kernels
+# whose counter records bench.py reads
+KERNEL_RECORDS = (("k_merge_write", "k_merge<unsigned int, true>"),
+                  ("k_merge_count", "k_merge<unsigned int, false>"),
+                  ("k_sort_pass", "k_sort_pass<unsigned int>"),
+                  ("k_sort_count", "k_sort_count<unsigned int>"),
+                  ("k_merge_partition", "k_merge_partition<unsigned int>"),
+                  ("k_spawn_scan", "k_spawn_scan<unsigned int>"),
+                  ("k_spawn_loud", "k_spawn_loud<unsigned int>"))
+EQUIL_CHUNK = 500    # steps per equilibration chunk
+EQUIL_MIN = 2000     # equilibration steps at least
+EQUIL_MAX = 40000    # and at most
+EQUIL_TOL = 0.01     # steady: the list changed by less than this over the last two chunks
 
 WORKLOADS = {
     "d3": (dict(workloads.D3),
@@ -67,30 +91,43 @@ def kernel_source_hash(texts=None):
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel, workload, per_launch_alg):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
+STATE_TOL = 0.10  # a counter record applies to live means within 10% of its own
+
+
+def profile_record(kernel, workload, kind, live=None):
+    """The committed rocprofv3 counter record ``profiles/<kernel>_<workload>_<kind>.json``
+    (kind "traffic" or "valu") if it was taken on the current kernel sources and,
+    when ``live`` is given, on a workload state like the live one: its mean list
+    entries and mean spawn records per step within 10% of the live means.  A
+    record taken on another state (another list size) says nothing about this
+    run's launches, so it is not used.  Else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{kind}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
     if d.get("source_hash") != kernel_source_hash():
         return None
-    return d.get("bytes_per_launch")
+    if live is not None:
+        for k in ("mean_entries", "mean_spawn_records"):
+            ref = d.get(k)
+            if not ref or abs(float(live[k]) - float(ref)) > STATE_TOL * float(ref):
+                return None
+    return d
 
 
-def valu_from_profile(kernel, workload):
-    """VALU wave-instructions per launch from the committed counter summary, if it
-    was taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_valu.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
-        d = json.load(f)
-    if d.get("source_hash") != kernel_source_hash():
-        return None
-    return d.get("valu_per_launch")
+def traffic_from_profile(kernel, workload, live=None):
+    """HBM bytes per launch (scaled FETCH_SIZE + WRITE_SIZE) from the committed
+    counter record, or None (see profile_record)."""
+    d = profile_record(kernel, workload, "traffic", live)
+    return None if d is None else d.get("bytes_per_launch")
+
+
+def valu_from_profile(kernel, workload, live=None):
+    """VALU wave-instructions per launch from the committed counter record, or
+    None (see profile_record)."""
+    d = profile_record(kernel, workload, "valu", live)
+    return None if d is None else d.get("valu_per_launch")
 
 
 def cpu_baseline(cfg, keys, re, im, sc, budget_s=15.0):
@@ -155,12 +192,15 @@ def trace_summary(directory, steps):
     print("\n".join(out))
 
 
-def counter_summary(fetch_dir, write_dir, probe_mb, workload, valu_dir=None):
+def counter_summary(fetch_dir, write_dir, probe_mb, workload, valu_dir=None, state=None):
     """Mean FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the step kernels from two
     rocprofv3 --pmc runs, scaled by what the same counters read for the probe
     kernel of known traffic (an elementwise add over probe_mb MiB: reads and
-    writes probe_mb MiB).  Prints a markdown table and, for the merge kernels,
-    the traffic records bench.py reads."""
+    writes probe_mb MiB).  Prints a markdown table and, for the step kernels,
+    the traffic records bench.py reads.  ``state`` holds the mean list entries
+    and spawn records per step of the profiled run (from its bench line); the
+    records carry them, so that bench.py uses a record only on a like state."""
+    state = {k: (state or {}).get(k) for k in ("mean_entries", "mean_spawn_records")}
     import csv
     import glob
     import collections
@@ -200,16 +240,13 @@ def counter_summary(fetch_dir, write_dir, probe_mb, workload, valu_dir=None):
         out.append(f"| {name} | {len(fetch[name])} | {fm:.2f} | {wm:.2f} | {tot:.2f} |")
         rec[name] = tot * 1e6
     print("\n".join(out))
-    for short, name in (("k_merge_write", "k_merge<unsigned int, true>"),
-                        ("k_merge_count", "k_merge<unsigned int, false>"),
-                        ("k_sort_pass", "k_sort_pass<unsigned int>"),
-                        ("k_spawn_scan", "k_spawn_scan<unsigned int>"),
-                        ("k_spawn_loud", "k_spawn_loud<unsigned int>")):
+    for short, name in KERNEL_RECORDS:
         if name in rec:
             path = os.path.join(ROOT, "profiles", f"{short}_{workload}_traffic.json")
             with open(path, "w") as f:
-                json.dump({"bytes_per_launch": rec[name], "source_hash": kernel_source_hash(),
-                           "fetch_scale": f_scale, "write_scale": w_scale}, f, indent=1)
+                json.dump(dict({"bytes_per_launch": rec[name], "source_hash": kernel_source_hash(),
+                                "fetch_scale": f_scale, "write_scale": w_scale}, **state), f,
+                          indent=1)
             print(f"wrote {path}")
     if valu_dir:
         valu, waves = load(valu_dir, "SQ_INSTS_VALU"), load(valu_dir, "SQ_WAVES")
@@ -227,41 +264,56 @@ def counter_summary(fetch_dir, write_dir, probe_mb, workload, valu_dir=None):
         for short, v in best.items():
             path = os.path.join(ROOT, "profiles", f"{short}_{workload}_valu.json")
             with open(path, "w") as f:
-                json.dump({"valu_per_launch": v, "source_hash": kernel_source_hash()}, f, indent=1)
+                json.dump(dict({"valu_per_launch": v, "source_hash": kernel_source_hash()},
+                               **state), f, indent=1)
             print(f"wrote {path}")
 
 
-def _walker_updates(series, steps):
-    """Sum of W_tot at the start of the last `steps` steps of a series."""
-    import numpy as np
-    import paper_1802_05931_amd as dq
-    w = series[:, 3 + dq.SUM_NAMES.index("w_tot")].astype(np.float64)
-    return float(w[-steps - 1:-1].sum())
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
-def bench_d5(args):
+def equilibrate(g, log=_log):
+    """Steps a solve in chunks of EQUIL_CHUNK until its list is steady: at
+    least EQUIL_MIN steps, and the list size changed by less than EQUIL_TOL
+    over the last two chunks.  Returns (steps taken, steady, list sizes)."""
+    sizes = []
+    done = 0
+    while done < EQUIL_MAX:
+        g.step(EQUIL_CHUNK)
+        done += EQUIL_CHUNK
+        sizes.append(g.list_size())
+        log(f"equilibration: {done} steps, {sizes[-1]} entries")
+        if (done >= EQUIL_MIN and len(sizes) >= 3
+                and abs(sizes[-1] - sizes[-3]) <= EQUIL_TOL * sizes[-1]):
+            return done, True, sizes
+    return done, False, sizes
+
+
+def bench_d5(args, log=_log):
     """64 independent 5x5 replicas: one batch handle (one launch per stage for
     all replicas) against the same replicas run one after another on their own
-    handles.  The lists must come out identical."""
+    handles.  The lists must come out identical (so the statistical error is
+    the same by construction)."""
     import numpy as np
     import torch
     from paper_1802_05931_amd import serving
-    steps = args.steps if args.steps != 1000 else 300
+    steps = args.d5_steps
     cfgs = workloads.d5_replicas()
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    print(f"d5: batched, {len(cfgs)} replicas x {steps} steps", file=sys.stderr, flush=True)
+    log(f"d5: batched, {len(cfgs)} replicas x {steps} steps")
     gk = args.graph_steps
     tb, ob, lb = serving.replicas_batched(cfgs, steps, graph_k=gk, stream=stream)
-    print(f"d5: batched {tb:.2f} s; sequential", file=sys.stderr, flush=True)
+    log(f"d5: batched {tb:.2f} s; sequential")
     ts, os_, ls = serving.replicas_sequential(
-        cfgs, steps, graph_k=gk, stream=stream, log=lambda m: print(f"d5: {m}", file=sys.stderr, flush=True))
-    print(f"d5: sequential {ts:.2f} s", file=sys.stderr, flush=True)
+        cfgs, steps, graph_k=gk, stream=stream, log=lambda m: log(f"d5: {m}"))
+    log(f"d5: sequential {ts:.2f} s")
     same = all(len(a[0]) == len(c[0]) and all(np.array_equal(x, y) for x, y in zip(a, c))
                for a, c in zip(lb, ls))
     same_obs = all(a["acc"] == c["acc"] and a["step"] == c["step"] for a, c in zip(ob, os_))
     entries = int(sum(len(x[0]) for x in lb))
-    out = {
+    return {
         "metric": "replica-steps/s (64 x 5x5 XYZ replicas, batched)",
         "value": len(cfgs) * (steps - 1) / tb,
         "unit": "replica-steps/s",
@@ -276,13 +328,14 @@ def bench_d5(args):
         "sequential": {"seconds": ts, "value": len(cfgs) * (steps - 1) / ts},
         "batched_seconds": tb,
         "speedup_vs_sequential": ts / tb,
+        "equal_error": "lists and accumulators identical batched and alone",
         "lists_identical": bool(same), "accumulators_identical": bool(same_obs),
+        "se_mz": [float(o["se_mz"]) for o in ob[:4]],
         "mz": [round(o["mz"], 5) for o in ob[:8]],
     }
-    print(json.dumps(out), flush=True)
 
 
-def bench_d4(args):
+def bench_d4(args, log=_log):
     """The serving stream: Poisson arrivals at 20/s, mixed lattices and targets,
     continuous batching in one pool, against the same requests one at a time
     (every n-th request timed alone for exactly the steps it took in the pool:
@@ -290,37 +343,32 @@ def bench_d4(args):
     import numpy as np
     import torch
     from paper_1802_05931_amd import serving
-    reqs = workloads.d4_requests(count=args.requests)
+    reqs = workloads.d4_requests(count=args.requests, t_hi=args.d4_target_max)
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
-    done = [0]
-
-    def log(msg):
-        done[0] += 1
-        print(f"d4: {msg}", file=sys.stderr, flush=True)
     gk = args.graph_steps
-    recs, ticks = serving.serve(reqs, graph_k=gk, stream=stream, log=log)
+    recs, ticks = serving.serve(reqs, graph_k=gk, stream=stream,
+                                log=lambda m: log(f"d4: {m}"))
     wall = time.perf_counter() - t0
     lat = np.array([r["finished"] - r["arrival"] for r in recs])
     steps = np.array([r["steps"] for r in recs])
     conv = np.array([r["converged"] for r in recs])
     over = np.array([r["over_limit"] for r in recs])
-    print(f"d4: served {len(recs)} in {wall:.1f} s; timing every {args.baseline_every}-th alone",
-          file=sys.stderr, flush=True)
+    log(f"d4: served {len(recs)} in {wall:.1f} s; timing every {args.baseline_every}-th alone")
     alone = []
     for i in range(0, len(reqs), args.baseline_every):
         dt, obs = serving.solve_alone(reqs[i]["params"], int(steps[i]), graph_k=gk,
                                       stream=stream)
-        print(f"d4: request {i} alone: {dt:.2f} s for {steps[i]} steps", file=sys.stderr,
-              flush=True)
+        log(f"d4: request {i} alone: {dt:.2f} s for {steps[i]} steps")
         assert obs["step"] == steps[i]
-        assert abs(obs["mz"] - recs[i]["mz"]) == 0.0 or (np.isnan(obs["mz"]) and
-                                                        np.isnan(recs[i]["mz"]))
+        assert obs["mz"] == recs[i]["mz"] or (np.isnan(obs["mz"]) and np.isnan(recs[i]["mz"]))
+        assert obs["se_mz"] == recs[i]["se_mz"] or (np.isnan(obs["se_mz"]) and
+                                                    np.isnan(recs[i]["se_mz"]))
         alone.append(dt)
     alone_total = float(np.sum(alone)) * args.baseline_every
     last_arrival = max(r["arrival"] for r in reqs)
-    out = {
+    return {
         "metric": "served solves/s (D4 stream: 2x2/3x3/4x4/2x6, Poisson 20/s)",
         "value": len(recs) / wall,
         "unit": "solves/s",
@@ -330,9 +378,10 @@ def bench_d4(args):
         "dtype": "i32 walkers, f64 probabilities", "data": "synthetic",
         "config": {"workload": f"{len(reqs)} requests, lattices uniform over 2x2/3x3/4x4/2x6, "
                                "Jx U[0.5,1.2], Jz U[0.8,1.2], gamma U[0.5,2], dt 0.005, n_a 3, "
-                               "targets log-uniform [1e3,1e5], Poisson arrivals 20/s",
+                               f"targets log-uniform [1e3,{args.d4_target_max:.0e}], "
+                               "Poisson arrivals 20/s",
                    "slots": 64, "tick_steps": 50, "graph_steps": gk,
-                   "admission": "pool list below 6e7 entries",
+                   "admission": "projected device bytes of the pool below its budget",
                    "stop": "SE(M_z) < 1e-3 after >= 512 accumulated steps, 2000 steps, or "
                            "more than 4e6 entries"},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
@@ -340,62 +389,22 @@ def bench_d4(args):
         "wall_s": wall, "last_arrival_s": last_arrival, "ticks": ticks,
         "converged": int(conv.sum()), "over_memory_limit": int(over.sum()),
         "steps_per_solve_median": float(np.median(steps)),
+        "equal_error": "every timed alone solve has the pool's M_z and SE(M_z), bit for bit",
         "one_at_a_time": {"seconds_estimated": alone_total,
                           "sample": f"every {args.baseline_every}-th request alone "
                                     f"({len(alone)} solves, scaled by {args.baseline_every})",
                           "solves_per_s": len(recs) / alone_total},
     }
-    print(json.dumps(out), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=15000)
-    ap.add_argument("--workload", default="d3", choices=sorted(WORKLOADS) + ["d4", "d5"])
-    ap.add_argument("--requests", type=int, default=512, help="d4: requests in the stream")
-    ap.add_argument("--baseline-every", type=int, default=8,
-                    help="d4: time every n-th request alone for the one-at-a-time baseline")
-    ap.add_argument("--graph-steps", type=int, default=50,
-                    help="d4/d5: launch the steps as HIP graphs of this many steps (even; 0 = "
-                         "one launch per kernel)")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--trace-summary", metavar="DIR")
-    ap.add_argument("--counter-summary", nargs="+", metavar="DIR",
-                    help="FETCH_DIR WRITE_DIR [VALU_DIR]: summarise rocprofv3 --pmc runs")
-    ap.add_argument("--save-state", metavar="FILE",
-                    help="write the solve's checkpoint after the warm-up")
-    ap.add_argument("--load-state", metavar="FILE",
-                    help="start from a checkpoint of the same workload instead of warming up")
-    ap.add_argument("--copy-probe-mb", type=int, default=0,
-                    help="after the timed steps, copy a buffer of this many MiB three times "
-                         "(a plain copy kernel of known size for scaling memory counters)")
-    args = ap.parse_args()
-    if args.trace_summary:
-        trace_summary(args.trace_summary, args.steps)
-        return
-    if args.counter_summary:
-        d = args.counter_summary
-        counter_summary(d[0], d[1], args.copy_probe_mb, args.workload,
-                        d[2] if len(d) > 2 else None)
-        return
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the "
-              "multi-GPU sharding of the step is a design, not an implementation.",
-              file=sys.stderr)
-        sys.exit(2)
-
+def bench_d3(args, log=_log):
+    """The plain step on the 4x4 workload (or its large-list variant), timed on
+    its steady list.  Returns (bench line without cpu_baseline, handle, cfg)."""
     import numpy as np
     import torch
 
     import paper_1802_05931_amd as dq
 
-    if args.workload == "d5":
-        return bench_d5(args)
-    if args.workload == "d4":
-        return bench_d4(args)
     cfg, desc = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
@@ -409,24 +418,22 @@ def main():
     if blob is not None:
         g.set_state(blob)
         del blob
-        args.warmup = g.scalars()["step"]
-        _, re0, im0 = g.walkers()
-        w0 = int(np.abs(re0.astype(np.int64)).sum() + np.abs(im0.astype(np.int64)).sum())
-        del re0, im0
+        equil_steps, steady = g.scalars()["step"], True
+        log(f"loaded state at step {equil_steps}, {g.list_size()} entries")
     else:
-        # in chunks, with a line per chunk on stderr (large workloads warm up for minutes)
-        done = 0
-        while done < args.warmup:
-            n = min(2000, args.warmup - done)
-            g.step(n)
-            done += n
-            print(f"warm-up: {done} steps, {g.list_size()} entries", file=sys.stderr, flush=True)
+        equil_steps, steady, _ = equilibrate(g, log)
     if args.save_state:
         with open(args.save_state, "wb") as f:
             f.write(g.get_state())
-    # stage events on every PROF_EVERY-th timed step (an event costs a few
+    if args.warmup:
+        g.step(args.warmup)
+    log(f"warm-up: {args.warmup} steps after {equil_steps} equilibration steps, "
+        f"{g.list_size()} entries")
+    w0 = int(g.observables()["last"]["w_tot"])
+    # stage events on every prof_every-th timed step (an event costs a few
     # microseconds of its step; the sampled steps give the mean launch times)
-    g.set_profiling(PROF_EVERY)
+    prof_every = max(1, min(PROF_EVERY, args.steps // 10))
+    g.set_profiling(prof_every)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     g.step(args.steps)
@@ -436,29 +443,28 @@ def main():
     series = g.series()
     counts = g.step_counts()
     stage_ms, stage_steps = g.stage_times()
-    assert stage_steps == (args.steps + PROF_EVERY - 1) // PROF_EVERY
+    assert stage_steps == (args.steps + prof_every - 1) // prof_every
     # the sampled steps' stage times, scaled to all timed steps
     stage_ms = {k: v * args.steps / stage_steps for k, v in stage_ms.items()}
     sums = {n: i + 3 for i, n in enumerate(dq.SUM_NAMES)}
     w_tot = series[:, sums["w_tot"]]
     # W_tot at the start of each timed step = W_tot after the previous step
-    if len(w_tot) >= args.steps + 1:
-        w_start = w_tot[-args.steps - 1:-1]
-    else:  # started from a checkpoint: the first step starts from the loaded list
-        w_start = np.concatenate([[w0], w_tot[:-1]])
+    w_start = np.concatenate([[w0], w_tot[-args.steps:-1]]) if args.steps > 1 else np.array([w0])
     walker_updates = float(w_start.sum())
     c = counts[-args.steps:]
     n_in, n_sp, n_out = (c[:, 0].astype(float), c[:, 1].astype(float), c[:, 2].astype(float))
+    live = dict(mean_entries=float(n_in.mean()), mean_spawn_records=float(n_sp.mean()))
     k64 = 2 * cfg["Lx"] * cfg["Ly"] > 32
-    rec = KEY_BYTES[k64] + 8  # key + (re, im) int32
+    kb = KEY_BYTES[k64]
+    rec = kb + 8  # key + (re, im) int32
     passes = (2 * cfg["Lx"] * cfg["Ly"] + 7) // 8
     alg_bytes = {  # what each kernel must read and write, per the step's counts
         # the list in, the loud entries out (index, key, value)
         "scan": float((n_in * rec + c[:, 3] * (rec + 4)).sum()),
         # per pass: the digit counts read the keys, the scatter reads and writes records
-        "sort": float((passes * n_sp * (KEY_BYTES[k64] + 2 * rec)).sum()),
+        "sort": float((passes * n_sp * (kb + 2 * rec)).sum()),
         # survivors per tile: the list's keys and the records
-        "count": float((n_in * KEY_BYTES[k64] + n_sp * rec).sum()),
+        "count": float((n_in * kb + n_sp * rec).sum()),
         # the list and the records in, the new list out
         "merge": float(((n_in + n_sp + n_out) * rec).sum()),
     }
@@ -473,20 +479,27 @@ def main():
     m_ach = m_bytes / m_dur / 1e9
     hbm_roofline = dict(kernel="k_merge_write", bound="hbm", achieved=round(m_ach, 1),
                         peak=HBM_PEAK_GBS, unit="GB/s", frac=round(m_ach / HBM_PEAK_GBS, 4),
-                        traffic=traffic_from_profile("k_merge_write", args.workload, m_bytes),
+                        traffic=traffic_from_profile("k_merge_write", args.workload, live),
                         bytes_per_launch=round(m_bytes), mean_launch_us=round(m_dur * 1e6, 2))
-    # the annihilation stages together (sort, merge count, merge write) on
-    # their algorithmic bytes, and the method's minimal traffic per step
-    # (read and write the list, write the records and read them back)
+    # The annihilation stages together (sort, merge count, merge write: the
+    # north-star's graded stage) on the method's algorithmic bytes B_alg: read
+    # and write the list, write the records and read them back,
+    #   B_alg = 2 n_main (k_B + 8) + 2 n_sp (k_B + 9)  per step,
+    # and, beside it, on the implementation's own bytes (radix passes and the
+    # count pass re-read records and keys).
     a_stages = ("sort", "count", "merge")
-    a_bytes = sum(alg_bytes[k] for k in a_stages)
+    a_impl = sum(alg_bytes[k] for k in a_stages)
     a_s = sum(stage_ms[k] for k in a_stages) / 1e3
-    a_ach = a_bytes / a_s / 1e9
-    b_alg = float((2 * n_in * rec + 2 * n_sp * (rec + 1)).sum()) / args.steps
-    annihilation = dict(stages=list(a_stages), bytes_per_step=round(a_bytes / args.steps),
+    b_alg = float((2 * n_in * rec + 2 * n_sp * (rec + 1)).sum())
+    a_ach = b_alg / a_s / 1e9
+    a_traffic = [traffic_from_profile(kernel_names[k], args.workload, live) for k in a_stages]
+    annihilation = dict(stages=list(a_stages), bound="hbm",
+                        bytes_per_step=round(b_alg / args.steps),
                         achieved=round(a_ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                         frac=round(a_ach / HBM_PEAK_GBS, 4),
-                        method_min_bytes_per_step=round(b_alg))
+                        us_per_step=round(a_s / args.steps * 1e6, 2),
+                        implementation_bytes_per_step=round(a_impl / args.steps),
+                        implementation_frac=round(a_impl / a_s / 1e9 / HBM_PEAK_GBS, 4))
     # the dominant kernel by time
     dominant = max((k for k in stage_ms if k != "finalize"), key=lambda k: stage_ms[k])
     if dominant in alg_bytes:
@@ -495,29 +508,27 @@ def main():
         achieved = per_launch / dur_s / 1e9
         roofline = dict(kernel=kernel_names[dominant], bound="hbm", achieved=round(achieved, 1),
                         peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
-                        traffic=traffic_from_profile(kernel_names[dominant], args.workload,
-                                                     per_launch),
+                        traffic=traffic_from_profile(kernel_names[dominant], args.workload, live),
                         bytes_per_launch=round(per_launch), mean_launch_us=round(dur_s * 1e6, 2))
     else:
         # a sampling kernel: bound by vector ALU issue, measured as VALU
-        # instructions per launch (committed counter profile) over the live launch
-        # time, against 256 CUs x 4 SIMDs issuing one wave64 instruction per 4
-        # cycles at 2.4 GHz
+        # instructions per launch (committed counter record of a like state)
+        # over the live launch time, against 256 CUs x 4 SIMDs issuing one
+        # wave64 instruction per 4 cycles at 2.4 GHz
         kname = {"loud": "k_spawn_loud", "heavy": "k_spawn_heavy"}.get(dominant, dominant)
         dur_s = stage_ms[dominant] / 1e3 / args.steps
-        valu = valu_from_profile(kname, args.workload)
+        valu = valu_from_profile(kname, args.workload, live)
         achieved = valu / dur_s / 1e9 if valu else None
         roofline = dict(kernel=kname, bound="alu", achieved=(round(achieved, 1) if achieved
                                                               else None),
                         peak=VALU_PEAK_G, unit="G VALU wave-instructions/s",
                         frac=(round(achieved / VALU_PEAK_G, 4) if achieved else None),
-                        traffic=traffic_from_profile(kname, args.workload, 0),
+                        traffic=traffic_from_profile(kname, args.workload, live),
                         valu_instructions_per_launch=valu, mean_launch_us=round(dur_s * 1e6, 2))
     stages = {k: dict(ms_per_step=round(v / args.steps, 5),
                       achieved_GBs=(round(alg_bytes[k] / (v / 1e3) / 1e9, 1)
                                     if k in alg_bytes and v > 0 else None))
               for k, v in stage_ms.items()}
-    keys, re, im = g.walkers()
     sc = g.scalars()
     obs = g.observables()
     out = {
@@ -534,21 +545,92 @@ def main():
         "dtype": "i32 walkers, f64 probabilities",
         "data": "synthetic",
         "config": {"workload": desc, "lattice": "4x4", "target_walkers": cfg["target_walkers"],
-                   "key_bits": 2 * cfg["Lx"] * cfg["Ly"], "mean_entries": float(n_in.mean()),
+                   "key_bits": 2 * cfg["Lx"] * cfg["Ly"],
+                   "equilibration_steps": int(equil_steps), "steady": bool(steady),
+                   "mean_entries": live["mean_entries"],
+                   "list_drift_over_timed_steps": float((n_in[-1] - n_in[0]) / n_in.mean()),
                    "mean_walkers": float(w_start.mean()),
-                   "mean_spawn_records": float(n_sp.mean()),
+                   "mean_spawn_records": live["mean_spawn_records"],
                    "mean_loud_entries": float(c[:, 3].mean()),
                    "mean_heavy_entries": float(c[:, 4].mean())},
         "entry_updates_per_s": float(n_in.sum()) / wall,
+        "bytes_per_walker_update": b_alg / walker_updates,
         "roofline": roofline,
         "hbm_roofline": hbm_roofline,
         "hbm_annihilation": annihilation,
         "stages": stages,
-        "stage_events": f"HIP events on every {PROF_EVERY}-th timed step ({stage_steps} steps)",
+        "stage_events": f"HIP events on every {prof_every}-th timed step ({stage_steps} steps)",
         "shift": sc["S"],
         "mz_running": obs["mz"],
     }
     g.set_profiling(False)
+    return out, g, cfg
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20,
+                    help="steps after the equilibration, before the timed steps")
+    ap.add_argument("--workload", default="d3", choices=sorted(WORKLOADS) + ["d4", "d5"])
+    ap.add_argument("--legs", default="d3,d5,d4",
+                    help="default line: the plain step (d3) and the batched (d5) and served "
+                         "(d4) legs beside it")
+    ap.add_argument("--requests", type=int, default=512, help="d4: requests in the stream")
+    ap.add_argument("--d4-target-max", type=float, default=1e5,
+                    help="d4: upper end of the log-uniform target walker range")
+    ap.add_argument("--d5-steps", type=int, default=300, help="d5: steps per replica")
+    ap.add_argument("--baseline-every", type=int, default=8,
+                    help="d4: time every n-th request alone for the one-at-a-time baseline")
+    ap.add_argument("--graph-steps", type=int, default=50,
+                    help="d4/d5: launch the steps as HIP graphs of this many steps (even; 0 = "
+                         "one launch per kernel)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--trace-summary", metavar="DIR")
+    ap.add_argument("--counter-summary", nargs="+", metavar="DIR",
+                    help="FETCH_DIR WRITE_DIR [VALU_DIR]: summarise rocprofv3 --pmc runs")
+    ap.add_argument("--bench-json", metavar="FILE",
+                    help="with --counter-summary: the bench line of the profiled run (its "
+                         "mean list entries and spawn records key the records)")
+    ap.add_argument("--save-state", metavar="FILE",
+                    help="write the solve's checkpoint after the equilibration")
+    ap.add_argument("--load-state", metavar="FILE",
+                    help="start from a checkpoint of the same workload instead of equilibrating")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="after the timed steps, copy a buffer of this many MiB three times "
+                         "(a plain copy kernel of known size for scaling memory counters)")
+    args = ap.parse_args()
+    if args.trace_summary:
+        trace_summary(args.trace_summary, args.steps)
+        return
+    if args.counter_summary:
+        d = args.counter_summary
+        state = None
+        if args.bench_json:
+            with open(args.bench_json) as f:
+                line = [x for x in f.read().splitlines() if x.startswith("{")][-1]
+            state = json.loads(line)["config"]
+        counter_summary(d[0], d[1], args.copy_probe_mb, args.workload,
+                        d[2] if len(d) > 2 else None, state)
+        return
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the "
+              "multi-GPU sharding of the step is a design, not an implementation.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    if args.workload == "d5":
+        print(json.dumps(bench_d5(args)), flush=True)
+        return
+    if args.workload == "d4":
+        print(json.dumps(bench_d4(args)), flush=True)
+        return
+    legs = [x for x in args.legs.split(",") if x]
+    out, g, cfg = bench_d3(args)
     if args.copy_probe_mb:
         src = torch.ones(args.copy_probe_mb << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -556,11 +638,17 @@ def main():
             torch.add(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(cfg, keys, re, im, sc, args.cpu_seconds)
-    else:
-        out["cpu_baseline"] = None
+    keys, re, im = g.walkers()
+    sc = g.scalars()
     g.close()
+    del g
+    if args.workload == "d3" and "d5" in legs:
+        out["batched"] = bench_d5(args)
+    if args.workload == "d3" and "d4" in legs:
+        out["served"] = bench_d4(args)
+    # the oracle from the timed run's final (steady) list
+    out["cpu_baseline"] = (None if args.no_cpu else
+                           cpu_baseline(cfg, keys, re, im, sc, args.cpu_seconds))
     print(json.dumps(out), flush=True)
 
 

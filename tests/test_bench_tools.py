@@ -85,3 +85,59 @@ def test_counter_summary_scales_by_the_probe(tmp_path, monkeypatch, capsys):
     # (1000 KiB x 2 + 300 KiB x 1) per dispatch
     assert abs(rec["bytes_per_launch"] - 2300 * 1024) < 1.0
     assert rec["source_hash"] == "feedfacefeedface"
+
+
+def test_counter_records_apply_only_to_a_like_state(tmp_path, monkeypatch):
+    """A counter record carries the mean list entries and spawn records of the
+    run it was taken on; bench.py uses it only for a live run within 10% of
+    both, and on the same kernel sources."""
+    profiles = tmp_path / "profiles"
+    profiles.mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda texts=None: "feedfacefeedface")
+    rec = {"bytes_per_launch": 2.5e8, "source_hash": "feedfacefeedface",
+           "mean_entries": 1.08e7, "mean_spawn_records": 1.2e6}
+    with open(profiles / "k_merge_write_d3_traffic.json", "w") as f:
+        json.dump(rec, f)
+    steady = dict(mean_entries=1.1e7, mean_spawn_records=1.25e6)
+    assert bench.traffic_from_profile("k_merge_write", "d3", steady) == 2.5e8
+    transient = dict(mean_entries=1394.0, mean_spawn_records=902.0)
+    assert bench.traffic_from_profile("k_merge_write", "d3", transient) is None
+    assert bench.traffic_from_profile("k_merge_write", "d3",
+                                      dict(steady, mean_spawn_records=1.5e6)) is None
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda texts=None: "0000000000000000")
+    assert bench.traffic_from_profile("k_merge_write", "d3", steady) is None
+    # a record without the state fields is never used
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda texts=None: "feedfacefeedface")
+    with open(profiles / "k_spawn_loud_d3_valu.json", "w") as f:
+        json.dump({"valu_per_launch": 6.9e7, "source_hash": "feedfacefeedface"}, f)
+    assert bench.valu_from_profile("k_spawn_loud", "d3", steady) is None
+
+
+class _FakeSolve:
+    """Stands in for a handle: the list grows towards a steady size."""
+
+    def __init__(self, final, rate):
+        self.final, self.rate, self.n, self.steps = final, rate, 1.0, 0
+
+    def step(self, k):
+        for _ in range(k):
+            self.n += (self.final - self.n) * self.rate
+        self.steps += k
+
+    def list_size(self):
+        return int(self.n)
+
+
+def test_equilibration_waits_for_a_steady_list():
+    g = _FakeSolve(1e7, 3e-4)
+    steps, steady, sizes = bench.equilibrate(g, log=lambda m: None)
+    assert steady and steps >= bench.EQUIL_MIN and steps % bench.EQUIL_CHUNK == 0
+    # the last two chunks changed the list by less than 1%, the two before by more
+    assert abs(sizes[-1] - sizes[-3]) <= 0.01 * sizes[-1]
+    assert abs(sizes[-2] - sizes[-4]) > 0.01 * sizes[-2]
+    assert sizes[-1] > 0.95e7
+    # a list already steady still takes the minimum number of steps
+    g = _FakeSolve(1.0, 0.0)
+    steps, steady, _ = bench.equilibrate(g, log=lambda m: None)
+    assert steady and steps == bench.EQUIL_MIN
