@@ -348,8 +348,8 @@ def bench_d4(args, log=_log):
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
     gk = args.graph_steps
-    recs, ticks = serving.serve(reqs, graph_k=gk, stream=stream,
-                                log=lambda m: log(f"d4: {m}"))
+    recs, st = serving.serve(reqs, graph_k=gk, stream=stream, log=lambda m: log(f"d4: {m}"))
+    ticks = st["ticks"]
     wall = time.perf_counter() - t0
     lat = np.array([r["finished"] - r["arrival"] for r in recs])
     steps = np.array([r["steps"] for r in recs])
@@ -381,7 +381,12 @@ def bench_d4(args, log=_log):
                                f"targets log-uniform [1e3,{args.d4_target_max:.0e}], "
                                "Poisson arrivals 20/s",
                    "slots": 64, "tick_steps": 50, "graph_steps": gk,
-                   "admission": "projected device bytes of the pool below its budget",
+                   "admission": "in arrival order while the projected device bytes of the "
+                                "admitted solves (the workspace of min(reachable "
+                                "configurations, 4e6) entries each) stay within 32 GiB",
+                   "max_active": st["max_active"],
+                   "max_projected_GiB": round(st["max_projected_bytes"] / 2 ** 30, 2),
+                   "evicted": st["evicted"],
                    "stop": "SE(M_z) < 1e-3 after >= 512 accumulated steps, 2000 steps, or "
                            "more than 4e6 entries"},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),

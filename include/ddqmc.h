@@ -109,6 +109,20 @@ int ddqmc_step(ddqmc_t *h, int64_t n_steps);
 int ddqmc_observables(ddqmc_t *h, ddqmc_obs *out);
 int ddqmc_destroy(ddqmc_t *h);
 
+/* ---- one solve inside a caller-owned device workspace ------------------------
+ * ddqmc_create_in: as ddqmc_create, but every device buffer of the handle lies
+ *   in [dev_ws, dev_ws + bytes), device memory the caller allocated (e.g. a
+ *   torch tensor) and keeps alive, unmoved, until ddqmc_destroy; the library
+ *   allocates no device memory for it and never frees it.  dev_ws must be
+ *   256-byte aligned (EINVAL otherwise, or when it is NULL).  The list capacity
+ *   is p->capacity_hint if it is nonzero (ECAPACITY if that handle does not fit
+ *   in bytes), else the largest that fits (ECAPACITY if not even the smallest,
+ *   4096 entries, does; ddqmc_workspace_query gives the bytes a capacity
+ *   needs).  The buffers never grow: a step that would outgrow them returns
+ *   ECAPACITY and leaves the handle at its last completed step. */
+int ddqmc_create_in(const ddqmc_params *p, void *dev_ws, size_t bytes, void *hip_stream,
+                    ddqmc_t **out);
+
 /* ---- many independent solves in one launch per stage (batched) --------------
  * The solves share one sorted list whose keys carry the slot number above the
  * configuration bits; each solve keeps its own parameters, shift and step count
@@ -168,9 +182,37 @@ int ddqmc_get_series(ddqmc_t *h, int32_t slot, int64_t *rows, int64_t cap, int64
  * rows holds cap rows (5 cap int64); *n receives the number of steps. */
 int ddqmc_get_step_counts(ddqmc_t *h, int64_t *rows, int64_t cap, int64_t *n);
 
-/* Device bytes a one-slot handle with the given capacity would allocate
- * (serving admission). */
+/* Device bytes of a one-slot handle with list capacity `capacity` entries
+ * (0: the capacity ddqmc_create would choose for *p): exactly what ddqmc_create
+ * allocates for it and what ddqmc_create_in needs, from the same layout of its
+ * buffers (the walker list twice, the spawn records twice at a quarter of the
+ * list capacity, the sort and merge tile arrays, the loud and heavy lists, and
+ * the fixed per-solve tables, each 256-byte aligned).  Serving admission sizes
+ * requests with it.  EINVAL on bad parameters or a negative capacity.
+ * ddqmc_device_bytes: the device bytes a handle holds now (both arenas) and its
+ *   current list capacity (capacity may be NULL). */
 int ddqmc_workspace_query(const ddqmc_params *p, int64_t capacity, size_t *bytes);
+int ddqmc_device_bytes(ddqmc_t *h, size_t *bytes, int64_t *capacity);
+
+/* Growth of a handle's buffers (host arithmetic only, no device call; the step
+ * uses it after a step outgrew its buffers).  Given the current list and record
+ * capacities, the entries the failed step needed (need_main, 0 if the list fit),
+ * the records its fullest spawn segment needed (seg_need, 0 if they fit; the
+ * record need is seg_need x 64 segments, taken in 64 bits), the key size (4 or
+ * 8 bytes), the device's free and total bytes and a capacity ceiling (0: the
+ * largest buffer, 0x7FF00000 entries): a short capacity grows to 1.5 x its need
+ * + 4096, at most the ceiling.  Writes the new capacities and the bytes of the
+ * new list and scratch arena.  Returns 0, ECAPACITY (a need above the
+ * ceiling), ENOMEM (the new arena would leave less than max(4 GiB, total/32)
+ * free; the old arena is still held while the list is copied) or EINVAL.
+ * ddqmc_set_capacity_limit: a ceiling (entries) for one handle's growth, 0 = the
+ *   largest buffer; a step that needs more returns ECAPACITY with the handle at
+ *   its last completed step. */
+int ddqmc_plan_growth(uint64_t cap_main, uint64_t cap_sp, uint64_t need_main, uint64_t seg_need,
+                      uint32_t key_bytes, uint64_t free_bytes, uint64_t total_bytes,
+                      uint64_t cap_limit, uint64_t *new_main, uint64_t *new_sp,
+                      uint64_t *bytes);
+int ddqmc_set_capacity_limit(ddqmc_t *h, int64_t max_entries);
 
 /* Wall time of the kernels of the last ddqmc_step call, per stage, from HIP
  * events on the handle's stream when profiling is on (ddqmc_set_profiling);

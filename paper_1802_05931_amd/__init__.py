@@ -17,7 +17,8 @@ STAGES = ("scan", "gather", "loud", "heavy", "seal", "histogram", "sort", "count
           "finalize")
 
 __all__ = ["Solve", "Batch", "Pool", "make_params", "DDQMCError", "NO_INITIATOR", "SUM_NAMES",
-           "dev_uniforms", "dev_binom", "dev_math", "dev_quiet", "workspace_query"]
+           "dev_uniforms", "dev_binom", "dev_math", "dev_quiet", "workspace_query",
+           "plan_growth"]
 
 
 def _stream_ptr(stream):
@@ -133,6 +134,18 @@ class _Handle:
         per chunk of entries (same results either way)."""
         check(lib().ddqmc_set_loud_grid(self._h, int(mode)), "set_loud_grid")
 
+    def device_bytes(self):
+        """(device bytes the handle holds, its list capacity in entries)."""
+        n = ctypes.c_size_t()
+        cap = ctypes.c_int64()
+        check(lib().ddqmc_device_bytes(self._h, ctypes.byref(n), ctypes.byref(cap)),
+              "device_bytes")
+        return n.value, cap.value
+
+    def set_capacity_limit(self, max_entries):
+        """Ceiling on the list and record capacities growth may reach (0: none)."""
+        check(lib().ddqmc_set_capacity_limit(self._h, int(max_entries)), "set_capacity_limit")
+
     def stage_times(self):
         ms = (ctypes.c_double * len(STAGES))()
         steps = ctypes.c_int64()
@@ -141,13 +154,27 @@ class _Handle:
 
 
 class Solve(_Handle):
-    """One steady-state solve (ddqmc_create)."""
+    """One steady-state solve (ddqmc_create).  With ``workspace`` (a device
+    buffer: a torch tensor, or an (address, bytes) pair) the handle lives in
+    that memory (ddqmc_create_in), which must stay alive and unmoved until
+    close(); its buffers then never grow."""
 
-    def __init__(self, params=None, stream=None, **kw):
+    def __init__(self, params=None, stream=None, workspace=None, **kw):
         self.params = params if params is not None else make_params(**kw)
         h = ctypes.c_void_p()
-        check(lib().ddqmc_create(ctypes.byref(self.params), _stream_ptr(stream), ctypes.byref(h)),
-              "ddqmc_create")
+        if workspace is None:
+            check(lib().ddqmc_create(ctypes.byref(self.params), _stream_ptr(stream),
+                                     ctypes.byref(h)), "ddqmc_create")
+        else:
+            if isinstance(workspace, tuple):
+                addr, nbytes = workspace
+            else:
+                addr = workspace.data_ptr()
+                nbytes = workspace.numel() * workspace.element_size()
+            self._workspace = workspace  # kept alive with the handle
+            check(lib().ddqmc_create_in(ctypes.byref(self.params), ctypes.c_void_p(int(addr)),
+                                        int(nbytes), _stream_ptr(stream), ctypes.byref(h)),
+                  "ddqmc_create_in")
         self._h = h
 
     def step(self, n=1):
@@ -214,6 +241,18 @@ def workspace_query(params, capacity=0):
     check(lib().ddqmc_workspace_query(ctypes.byref(params), int(capacity), ctypes.byref(n)),
           "workspace_query")
     return n.value
+
+
+def plan_growth(cap_main, cap_sp, need_main, seg_need, key_bytes, free_bytes, total_bytes,
+                cap_limit=0):
+    """The library's buffer-growth arithmetic (host only): returns (code, new list
+    capacity, new record capacity, bytes of the new list and scratch arena)."""
+    nm, ns, nb = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    rc = lib().ddqmc_plan_growth(int(cap_main), int(cap_sp), int(need_main), int(seg_need),
+                                 int(key_bytes), int(free_bytes), int(total_bytes),
+                                 int(cap_limit), ctypes.byref(nm), ctypes.byref(ns),
+                                 ctypes.byref(nb))
+    return rc, nm.value, ns.value, nb.value
 
 
 def dev_uniforms(seed, solve_id, cfg, step, draw, count):

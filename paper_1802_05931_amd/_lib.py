@@ -98,6 +98,13 @@ SIGNATURES = {
     "ddqmc_get_step_counts": (ctypes.c_int, [_vp, _P(ctypes.c_int64), ctypes.c_int64,
                                              _P(ctypes.c_int64)]),
     "ddqmc_workspace_query": (ctypes.c_int, [_P(Params), ctypes.c_int64, _P(ctypes.c_size_t)]),
+    "ddqmc_create_in": (ctypes.c_int, [_P(Params), _vp, ctypes.c_size_t, _vp, _P(_vp)]),
+    "ddqmc_device_bytes": (ctypes.c_int, [_vp, _P(ctypes.c_size_t), _P(ctypes.c_int64)]),
+    "ddqmc_set_capacity_limit": (ctypes.c_int, [_vp, ctypes.c_int64]),
+    "ddqmc_plan_growth": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                         ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
+                                         ctypes.c_uint64, ctypes.c_uint64, _P(ctypes.c_uint64),
+                                         _P(ctypes.c_uint64), _P(ctypes.c_uint64)]),
     "ddqmc_set_profiling": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "ddqmc_set_graph_steps": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "ddqmc_set_heavy_fork": (ctypes.c_int, [_vp, ctypes.c_int32]),

@@ -53,6 +53,15 @@ struct ddqmc_t {
   int cur = 0;
   uint32_t n_main_known = 0, n_spawn_known = 0;
 
+  // Device memory, two arenas (fixed_layout, sized_layout): the fixed one holds
+  // what depends on the slot count only, the sized one the lists and the
+  // per-step scratch, replaced whole when a step outgrows it.  Both are one
+  // allocation each, or pieces of a caller's workspace (ddqmc_create_in).
+  char *fixed = nullptr, *sized = nullptr;
+  size_t fixed_bytes = 0, sized_bytes = 0;
+  bool own_mem = true;     // false: in a caller's workspace, which is never regrown
+  uint64_t cap_limit = 0;  // largest capacity growth may reach (0: MAX_CAP)
+
   void *mk[2] = {nullptr, nullptr};
   int2 *mv[2] = {nullptr, nullptr};
   void *sk[2] = {nullptr, nullptr};
@@ -73,7 +82,7 @@ struct ddqmc_t {
   void *lkey = nullptr;
   int2 *lval = nullptr;
   uint32_t *part = nullptr;      // merge tile boundaries
-  uint32_t *segcnt = nullptr;  // record counters of the spawn segments
+  unsigned long long *segcnt = nullptr;  // record counters of the spawn segments
   uint32_t nscan = 1;          // blocks of the scan kernel (fixed per list capacity)
   uint32_t loud_blocks = 1024;   // blocks of the loud spawn kernel the device holds at once
   uint32_t heavy_blocks = 1024;  // one-wave blocks of the heavy spawn kernel, likewise
@@ -131,28 +140,91 @@ int hip_err(hipError_t e) {
 
 size_t key_size(const ddqmc_t *h) { return h->k64 ? 8 : 4; }
 
-// Growth that would leave less than a reserve of device memory free is refused
-// (DDQMC_ENOMEM): the runtime needs headroom for kernel scratch and queues, and
-// a list that outgrows the device ends as an error, not a fault.
-int check_room(size_t bytes) {
-  size_t free_b = 0, total_b = 0;
-  HIPC(hipMemGetInfo(&free_b, &total_b));
-  const size_t reserve = std::max<size_t>((size_t)4 << 30, total_b / 32);
-  if (bytes + reserve > free_b) return DDQMC_ENOMEM;
-  return DDQMC_OK;
-}
-
 uint64_t sort_tiles(uint64_t cap) { return (cap + SORT_TILE - 1) / SORT_TILE; }
 uint64_t merge_tiles(uint64_t a, uint64_t b) { return (a + b + MERGE_TILE - 1) / MERGE_TILE; }
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t list_bytes(size_t ks, uint64_t cap) { return 2 * cap * (ks + sizeof(int2)); }
-// the loud list (index, key, value) and the two heavy queues
-size_t loud_bytes(size_t ks, uint64_t cap) { return cap * (3 * sizeof(uint32_t) + ks + sizeof(int2)); }
-size_t spawn_bytes(size_t ks, uint64_t cap) {
-  return 2 * cap * (ks + sizeof(int2)) + sort_tiles(cap) * 256 * sizeof(uint32_t);
+// Byte offsets of the fixed arena's buffers (each 256-byte aligned).
+struct FixedLayout {
+  size_t ctrl, dsp, dss, spill, series, counts, inj_k, inj_v, segcnt, hist, total;
+};
+FixedLayout fixed_layout(int nslots, size_t ks) {
+  FixedLayout L;
+  size_t o = 0;
+  auto take = [&o](size_t bytes) {
+    const size_t at = o;
+    o += al256(bytes);
+    return at;
+  };
+  L.ctrl = take(sizeof(Ctrl));
+  L.dsp = take((size_t)nslots * sizeof(SlotParams));
+  L.dss = take((size_t)nslots * sizeof(SlotState));
+  L.spill = take((size_t)nslots * S_NSUM * sizeof(unsigned long long));
+  L.series = take((size_t)SERIES_CAP * nslots * SERIES_W * sizeof(int64_t));
+  L.counts = take((size_t)SERIES_CAP * COUNT_W * sizeof(uint32_t));
+  L.inj_k = take((size_t)nslots * ks);
+  L.inj_v = take((size_t)nslots * sizeof(int2));
+  L.segcnt = take((size_t)NSEG * SEG_STRIDE * sizeof(unsigned long long));
+  L.hist = take((size_t)MAX_PASSES * 256 * sizeof(uint32_t));
+  L.total = o;
+  return L;
 }
-size_t merge_bytes(uint64_t cm, uint64_t cs) {
-  return merge_tiles(cm, cs) * (2 * sizeof(uint32_t) + sizeof(Partial)) + 2 * sizeof(uint32_t);
+
+// Byte offsets of the sized arena's buffers for a list capacity cap_main and a
+// record capacity cap_sp (rounded up to whole segments).
+struct SizedLayout {
+  uint64_t cap_main, cap_sp;
+  size_t mk[2], mv[2], sk[2], sv[2], sort_cnt, tile_cnt, partials, part;
+  size_t heavy, late, lidx, lkey, lval, total;
+};
+SizedLayout sized_layout(size_t ks, uint64_t cap_main, uint64_t cap_sp) {
+  SizedLayout L;
+  cap_sp = (cap_sp + NSEG - 1) / NSEG * NSEG;
+  L.cap_main = cap_main;
+  L.cap_sp = cap_sp;
+  size_t o = 0;
+  auto take = [&o](size_t bytes) {
+    const size_t at = o;
+    o += al256(bytes);
+    return at;
+  };
+  for (int b = 0; b < 2; ++b) {  // the walker list, two ping-pong buffers
+    L.mk[b] = take(cap_main * ks);
+    L.mv[b] = take(cap_main * sizeof(int2));
+  }
+  for (int b = 0; b < 2; ++b) {  // spawn records: segments, then the sort's second buffer
+    L.sk[b] = take(cap_sp * ks);
+    L.sv[b] = take(cap_sp * sizeof(int2));
+  }
+  L.sort_cnt = take(sort_tiles(cap_sp) * 256 * sizeof(uint32_t));
+  const uint64_t t = merge_tiles(cap_main, cap_sp);
+  L.tile_cnt = take((t + 1) * sizeof(uint32_t));
+  L.partials = take(t * sizeof(Partial));
+  L.part = take((t + 1) * sizeof(uint32_t));
+  // the loud list (index, key, value) and the two heavy queues: at most one
+  // place per list entry each
+  L.heavy = take(cap_main * sizeof(uint32_t));
+  L.late = take(cap_main * sizeof(uint32_t));
+  L.lidx = take(cap_main * sizeof(uint32_t));
+  L.lkey = take(cap_main * ks);
+  L.lval = take(cap_main * sizeof(int2));
+  L.total = o;
+  return L;
+}
+
+// Capacities of a new handle: the list as asked (at least 4096 entries, at
+// most MAX_CAP), records a quarter of that (at least 4096).
+void initial_caps(uint64_t cap, uint64_t *cap_main, uint64_t *cap_sp) {
+  cap = std::min<uint64_t>(std::max<uint64_t>(cap, 4096), MAX_CAP);
+  *cap_main = cap;
+  *cap_sp = std::max<uint64_t>(4096, cap / 4);
+}
+
+// Reserve of device memory that growth must leave free: the runtime needs
+// headroom for kernel scratch and queues, so that a list that outgrows the
+// device ends as an error, not a fault.
+uint64_t memory_reserve(uint64_t total_b) {
+  return std::max<uint64_t>((uint64_t)4 << 30, total_b / 32);
 }
 
 int validate(const ddqmc_params *p) {
@@ -215,13 +287,11 @@ SlotState fresh_state(const ddqmc_params &p, int status) {
 }
 
 void free_all(ddqmc_t *h) {
-  void *ptrs[] = {h->mk[0], h->mk[1], h->mv[0], h->mv[1], h->sk[0], h->sk[1], h->sv[0],
-                  h->sv[1], h->sort_cnt, h->tile_cnt, h->partials, h->hist, h->ctrl,
-                  h->dsp, h->dss, h->spill, h->series, h->counts, h->heavy, h->late, h->lidx, h->lkey, h->lval,
-                  h->part, h->segcnt, h->inj_k,
-                  h->inj_v};
-  for (void *p : ptrs)
-    if (p) (void)hipFree(p);
+  if (h->own_mem) {
+    if (h->sized) (void)hipFree(h->sized);
+    if (h->fixed) (void)hipFree(h->fixed);
+  }
+  h->sized = h->fixed = nullptr;
   for (int p = 0; p < 2; ++p)
     if (h->gexec[p]) (void)hipGraphExecDestroy(h->gexec[p]);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
@@ -238,63 +308,75 @@ uint32_t clampu(uint64_t v, uint32_t lo, uint32_t hi) {
   return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(v, lo), hi);
 }
 
-// The dense loud list (entry index, key, value) and the heavy queue, both at
-// most one slot per list entry.
-int alloc_loud(ddqmc_t *h) {
-  if (h->heavy) HIPC(hipFree(h->heavy));
-  if (h->late) HIPC(hipFree(h->late));
-  h->late = nullptr;
-  if (h->lidx) HIPC(hipFree(h->lidx));
-  if (h->lkey) HIPC(hipFree(h->lkey));
-  if (h->lval) HIPC(hipFree(h->lval));
-  h->heavy = nullptr;
-  h->lidx = nullptr;
-  h->lkey = nullptr;
-  h->lval = nullptr;
+// Point the handle's buffers into a fixed arena at base.
+void bind_fixed(ddqmc_t *h, char *base) {
+  const FixedLayout L = fixed_layout(h->nslots, key_size(h));
+  h->fixed = base;
+  h->fixed_bytes = L.total;
+  h->ctrl = (Ctrl *)(base + L.ctrl);
+  h->dsp = (SlotParams *)(base + L.dsp);
+  h->dss = (SlotState *)(base + L.dss);
+  h->spill = (unsigned long long *)(base + L.spill);
+  h->series = (int64_t *)(base + L.series);
+  h->counts = (uint32_t *)(base + L.counts);
+  h->inj_k = base + L.inj_k;
+  h->inj_v = (int2 *)(base + L.inj_v);
+  h->segcnt = (unsigned long long *)(base + L.segcnt);
+  h->hist = (uint32_t *)(base + L.hist);
+}
+
+// Point the handle's buffers into a sized arena at base with layout L.
+void bind_sized(ddqmc_t *h, char *base, const SizedLayout &L) {
+  h->sized = base;
+  h->sized_bytes = L.total;
+  for (int b = 0; b < 2; ++b) {
+    h->mk[b] = base + L.mk[b];
+    h->mv[b] = (int2 *)(base + L.mv[b]);
+    h->sk[b] = base + L.sk[b];
+    h->sv[b] = (int2 *)(base + L.sv[b]);
+  }
+  h->sort_cnt = (uint32_t *)(base + L.sort_cnt);
+  h->tile_cnt = (uint32_t *)(base + L.tile_cnt);
+  h->partials = (Partial *)(base + L.partials);
+  h->part = (uint32_t *)(base + L.part);
+  h->heavy = (uint32_t *)(base + L.heavy);
+  h->late = (uint32_t *)(base + L.late);
+  h->lidx = (uint32_t *)(base + L.lidx);
+  h->lkey = base + L.lkey;
+  h->lval = (int2 *)(base + L.lval);
+  h->cap_main = L.cap_main;
+  h->cap_sp = L.cap_sp;
   h->nscan = clampu((h->cap_main + NT - 1) / NT, 1, 4096);
   h->fork_heavy = h->fork_mode > 0 || (h->fork_mode == 0 && h->cap_main >= FORK_MIN_CAP);
-  HIPC(hipMalloc((void **)&h->heavy, (size_t)h->cap_main * sizeof(uint32_t)));
-  HIPC(hipMalloc((void **)&h->late, (size_t)h->cap_main * sizeof(uint32_t)));
-  HIPC(hipMalloc((void **)&h->lidx, (size_t)h->cap_main * sizeof(uint32_t)));
-  HIPC(hipMalloc(&h->lkey, (size_t)h->cap_main * key_size(h)));
-  HIPC(hipMalloc((void **)&h->lval, (size_t)h->cap_main * sizeof(int2)));
-  return DDQMC_OK;
 }
 
-int alloc_list(ddqmc_t *h, uint64_t cap) {
-  const size_t ks = key_size(h);
-  for (int b = 0; b < 2; ++b) {
-    HIPC(hipMalloc(&h->mk[b], cap * ks));
-    HIPC(hipMalloc((void **)&h->mv[b], cap * sizeof(int2)));
+// Largest list capacity whose handle fits in `bytes` (0 if not even the
+// smallest one does).
+uint64_t fit_capacity(int nslots, size_t ks, size_t bytes) {
+  const size_t fixed = fixed_layout(nslots, ks).total;
+  auto need = [&](uint64_t c) {
+    uint64_t cm, cs;
+    initial_caps(c, &cm, &cs);
+    return fixed + sized_layout(ks, cm, cs).total;
+  };
+  if (need(4096) > bytes) return 0;
+  uint64_t lo = 4096, hi = MAX_CAP;
+  if (need(hi) <= bytes) return hi;
+  while (hi - lo > 1) {  // need(lo) fits, need(hi) does not
+    const uint64_t mid = lo + (hi - lo) / 2;
+    (need(mid) <= bytes ? lo : hi) = mid;
   }
-  h->cap_main = cap;
-  return alloc_loud(h);
+  return lo;
 }
 
-int alloc_spawn(ddqmc_t *h, uint64_t cap) {
-  const size_t ks = key_size(h);
-  cap = (cap + NSEG - 1) / NSEG * NSEG;
-  for (int b = 0; b < 2; ++b) {
-    HIPC(hipMalloc(&h->sk[b], cap * ks));
-    HIPC(hipMalloc((void **)&h->sv[b], cap * sizeof(int2)));
-  }
-  const uint64_t st = sort_tiles(cap) * 256;
-  HIPC(hipMalloc((void **)&h->sort_cnt, st * sizeof(uint32_t)));
-  h->cap_sp = cap;
-  return DDQMC_OK;
-}
-
-int alloc_merge(ddqmc_t *h) {
-  const uint64_t t = merge_tiles(h->cap_main, h->cap_sp);
-  HIPC(hipMalloc((void **)&h->tile_cnt, (t + 1) * sizeof(uint32_t)));
-  HIPC(hipMalloc((void **)&h->partials, t * sizeof(Partial)));
-  HIPC(hipMalloc((void **)&h->part, (t + 1) * sizeof(uint32_t)));
-  return DDQMC_OK;
-}
-
-// Common construction: slots, key layout, buffers.
-int build(ddqmc_t *h, int nslots, int Nmax, uint64_t cap, void *stream) {
+// Common construction: slots, key layout, buffers.  With ws == nullptr the
+// arenas are allocated (hipMalloc) for a list capacity cap; else they are
+// carved out of the caller's workspace [ws, ws + ws_bytes), with capacity cap
+// if it is nonzero, else the largest that fits.
+int build(ddqmc_t *h, int nslots, int Nmax, uint64_t cap, void *stream, void *ws = nullptr,
+          size_t ws_bytes = 0) {
   if (nslots < 1 || nslots > MAX_SLOTS || Nmax < 4 || Nmax > 32) return DDQMC_EINVAL;
+  if (ws && ((uintptr_t)ws & 255)) return DDQMC_EINVAL;
   HIPC(hipGetDevice(&h->device));
   if (stream) {
     h->stream = (hipStream_t)stream;
@@ -333,32 +415,32 @@ int build(ddqmc_t *h, int nslots, int Nmax, uint64_t cap, void *stream) {
     h->heavy_blocks = clampu((uint64_t)std::max(ncu, 1) * (uint64_t)std::max(nh, 1), 1, 8192);
   }
   h->passes = (h->key_bits + 7) / 8;
-  cap = std::max<uint64_t>(cap, 4096);
-  cap = std::min<uint64_t>(cap, MAX_CAP);
-  int rc;
   const size_t ks = key_size(h);
-  if ((rc = check_room(list_bytes(ks, cap) + spawn_bytes(ks, std::max<uint64_t>(4096, cap / 4)) +
-                       loud_bytes(ks, cap))) != DDQMC_OK)
-    return rc;
-  if ((rc = alloc_list(h, cap)) != DDQMC_OK) return rc;
-  if ((rc = alloc_spawn(h, std::max<uint64_t>(4096, cap / 4))) != DDQMC_OK) return rc;
-  if ((rc = alloc_merge(h)) != DDQMC_OK) return rc;
-  HIPC(hipMalloc((void **)&h->segcnt, NSEG * SEG_STRIDE * sizeof(uint32_t)));
-  HIPC(hipMemsetAsync(h->segcnt, 0, NSEG * SEG_STRIDE * sizeof(uint32_t), h->stream));
-  HIPC(hipMalloc((void **)&h->hist, MAX_PASSES * 256 * sizeof(uint32_t)));
-  HIPC(hipMemsetAsync(h->hist, 0, MAX_PASSES * 256 * sizeof(uint32_t), h->stream));
-  HIPC(hipMalloc((void **)&h->ctrl, sizeof(Ctrl)));
-  HIPC(hipMemsetAsync(h->ctrl, 0, sizeof(Ctrl), h->stream));
-  HIPC(hipMalloc((void **)&h->dsp, nslots * sizeof(SlotParams)));
-  HIPC(hipMemsetAsync(h->dsp, 0, nslots * sizeof(SlotParams), h->stream));
-  HIPC(hipMalloc((void **)&h->dss, nslots * sizeof(SlotState)));
-  HIPC(hipMemsetAsync(h->dss, 0, nslots * sizeof(SlotState), h->stream));
-  HIPC(hipMalloc((void **)&h->spill, nslots * S_NSUM * sizeof(unsigned long long)));
-  HIPC(hipMemsetAsync(h->spill, 0, nslots * S_NSUM * sizeof(unsigned long long), h->stream));
-  HIPC(hipMalloc((void **)&h->series, (size_t)SERIES_CAP * nslots * SERIES_W * sizeof(int64_t)));
-  HIPC(hipMalloc((void **)&h->counts, (size_t)SERIES_CAP * COUNT_W * sizeof(uint32_t)));
-  HIPC(hipMalloc(&h->inj_k, nslots * key_size(h)));
-  HIPC(hipMalloc((void **)&h->inj_v, nslots * sizeof(int2)));
+  const FixedLayout FL = fixed_layout(nslots, ks);
+  if (ws) {
+    h->own_mem = false;
+    if (cap == 0) cap = fit_capacity(nslots, ks, ws_bytes);
+    if (cap == 0) return DDQMC_ECAPACITY;
+  }
+  uint64_t cm, cs;
+  initial_caps(cap, &cm, &cs);
+  const SizedLayout SL = sized_layout(ks, cm, cs);
+  char *fixed = nullptr, *sized = nullptr;
+  if (ws) {
+    if (FL.total + SL.total > ws_bytes) return DDQMC_ECAPACITY;
+    fixed = (char *)ws;
+    sized = fixed + FL.total;
+  } else {
+    size_t free_b = 0, total_b = 0;
+    HIPC(hipMemGetInfo(&free_b, &total_b));
+    if (FL.total + SL.total + memory_reserve(total_b) > free_b) return DDQMC_ENOMEM;
+    HIPC(hipMalloc((void **)&fixed, FL.total));
+    h->fixed = fixed;  // owned from here on (free_all)
+    HIPC(hipMalloc((void **)&sized, SL.total));
+  }
+  bind_fixed(h, fixed);
+  bind_sized(h, sized, SL);
+  HIPC(hipMemsetAsync(h->fixed, 0, FL.total, h->stream));
   h->hp.assign(nslots, SlotParams{});
   h->up.assign(nslots, ddqmc_params{});
   h->slot_state.assign(nslots, 0);
@@ -503,63 +585,68 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
   return DDQMC_OK;
 }
 
-// Grow the list (keeping the current entries) or the spawn buffers.
-int regrow(ddqmc_t *h, uint64_t need_main, uint64_t need_sp) {
+// Growth of a handle's buffers after a step that outgrew them (host
+// arithmetic only; exported as ddqmc_plan_growth for tests).  A capacity that
+// is short grows to 1.5 x its need + 4096, at most the ceiling (MAX_CAP, or a
+// smaller cap_limit); a need above the ceiling is DDQMC_ECAPACITY.  The record
+// need is the fullest segment's fill times the segment count, in 64 bits.
+// Both capacities stay at most MAX_CAP, so list + records stay below 2^32 and
+// every 32-bit count, position and tile offset in the kernels is exact.  The
+// new sized arena is allocated while the old one is still held (the list is
+// copied across), so it must leave the reserve free: else DDQMC_ENOMEM.
+int plan_growth(uint64_t cap_main, uint64_t cap_sp, uint64_t need_main, uint64_t seg_need,
+                size_t ks, uint64_t free_b, uint64_t total_b, uint64_t cap_limit,
+                uint64_t *new_main, uint64_t *new_sp, uint64_t *bytes) {
+  const uint64_t ceil = cap_limit ? std::min<uint64_t>(cap_limit, MAX_CAP) : MAX_CAP;
+  const uint64_t need_sp = seg_need > ~0ull / NSEG ? ~0ull : seg_need * NSEG;
+  uint64_t nm = cap_main, ns = cap_sp;
+  if (need_main > cap_main) {
+    if (need_main > ceil) return DDQMC_ECAPACITY;
+    nm = std::min<uint64_t>(ceil, need_main + need_main / 2 + 4096);
+  }
+  if (need_sp > cap_sp) {
+    if (need_sp > ceil) return DDQMC_ECAPACITY;
+    ns = std::min<uint64_t>(ceil, need_sp + need_sp / 2 + 4096);
+  }
+  const uint64_t b = sized_layout(ks, nm, ns).total;
+  *new_main = nm;
+  *new_sp = sized_layout(ks, nm, ns).cap_sp;
+  *bytes = b;
+  if (b + memory_reserve(total_b) > free_b) return DDQMC_ENOMEM;
+  return DDQMC_OK;
+}
+
+// Grow the sized arena (keeping the current list) after a step that needed
+// need_main list entries or seg_need records in one segment.  A handle in a
+// caller's workspace cannot grow: DDQMC_ECAPACITY.
+int regrow(ddqmc_t *h, uint64_t need_main, uint64_t seg_need) {
   HIPC(hipStreamSynchronize(h->stream));
+  if (!h->own_mem) return DDQMC_ECAPACITY;
   const size_t ks = key_size(h);
-  if (need_main > h->cap_main) {
-    const uint64_t cap = std::min<uint64_t>(MAX_CAP, need_main + need_main / 2 + 4096);
-    if (cap < need_main) return DDQMC_ECAPACITY;
-    // new lists (the old ones are freed after the copy) and the larger loud arrays
-    const int room = check_room(list_bytes(ks, cap) + loud_bytes(ks, cap - h->cap_main));
-    if (room != DDQMC_OK) return room;
-    void *nk[2];
-    int2 *nv[2];
-    for (int b = 0; b < 2; ++b) {
-      HIPC(hipMalloc(&nk[b], cap * ks));
-      HIPC(hipMalloc((void **)&nv[b], cap * sizeof(int2)));
-    }
-    const uint32_t n = h->n_main_known;
-    HIPC(hipMemcpyAsync(nk[0], h->mk[h->cur], (size_t)n * ks, hipMemcpyDeviceToDevice, h->stream));
-    HIPC(hipMemcpyAsync(nv[0], h->mv[h->cur], (size_t)n * sizeof(int2), hipMemcpyDeviceToDevice,
-                        h->stream));
-    HIPC(hipStreamSynchronize(h->stream));
-    for (int b = 0; b < 2; ++b) {
-      HIPC(hipFree(h->mk[b]));
-      HIPC(hipFree(h->mv[b]));
-      h->mk[b] = nk[b];
-      h->mv[b] = nv[b];
-    }
-    h->cur = 0;
-    h->cap_main = cap;
-    const int rc = alloc_loud(h);
-    if (rc != DDQMC_OK) return rc;
-  }
-  if (need_sp > h->cap_sp) {
-    const uint64_t cap = std::min<uint64_t>(MAX_CAP, need_sp + need_sp / 2 + 4096);
-    if (cap < need_sp) return DDQMC_ECAPACITY;
-    const int room = check_room(spawn_bytes(ks, cap) - spawn_bytes(ks, h->cap_sp));
-    if (room != DDQMC_OK) return room;
-    for (int b = 0; b < 2; ++b) {
-      HIPC(hipFree(h->sk[b]));
-      HIPC(hipFree(h->sv[b]));
-      h->sk[b] = nullptr;
-      h->sv[b] = nullptr;
-    }
-    HIPC(hipFree(h->sort_cnt));
-    h->sort_cnt = nullptr;
-    int rc = alloc_spawn(h, cap);
-    if (rc != DDQMC_OK) return rc;
-  }
-  HIPC(hipFree(h->tile_cnt));
-  HIPC(hipFree(h->partials));
-  HIPC(hipFree(h->part));
-  h->tile_cnt = nullptr;
-  h->partials = nullptr;
-  h->part = nullptr;
-  int rc = alloc_merge(h);
+  size_t free_b = 0, total_b = 0;
+  HIPC(hipMemGetInfo(&free_b, &total_b));
+  uint64_t nm = 0, ns = 0, bytes = 0;
+  const int rc = plan_growth(h->cap_main, h->cap_sp, need_main, seg_need, ks, free_b, total_b,
+                             h->cap_limit, &nm, &ns, &bytes);
   if (rc != DDQMC_OK) return rc;
-  HIPC(hipStreamSynchronize(h->stream));
+  const SizedLayout L = sized_layout(ks, nm, ns);
+  char *base = nullptr;
+  HIPC(hipMalloc((void **)&base, L.total));
+  // the current list moves into the new arena's first list buffer
+  const size_t n = h->n_main_known;
+  hipError_t e = hipMemcpyAsync(base + L.mk[0], h->mk[h->cur], n * ks, hipMemcpyDeviceToDevice,
+                                h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(base + L.mv[0], h->mv[h->cur], n * sizeof(int2), hipMemcpyDeviceToDevice,
+                       h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    (void)hipFree(base);
+    return hip_err(e);
+  }
+  HIPC(hipFree(h->sized));
+  bind_sized(h, base, L);
+  h->cur = 0;
   h->buf_gen += 1;  // captured graphs hold the old pointers and grids
   return DDQMC_OK;
 }
@@ -693,7 +780,7 @@ int run_steps(ddqmc_t *h, int64_t n) {
     }
     if (c.abort) {
       const uint32_t f = c.fail_flags;
-      const uint64_t need_sp = (uint64_t)c.seg_need * NSEG, need_main = c.n_new;
+      const uint64_t seg_need = c.seg_need, need_main = c.n_new;
       k_rearm<<<1, 256, 0, h->stream>>>(h->ctrl, h->hist, MAX_PASSES, h->spill,
                                          h->nslots * S_NSUM, h->segcnt);
       HIPC(hipGetLastError());
@@ -702,7 +789,7 @@ int run_steps(ddqmc_t *h, int64_t n) {
       if (f & F_RNG) return DDQMC_ERNG;
       if (f & F_EXTINCT) return DDQMC_EEXTINCT;
       if (f & (F_SPAWN_CAP | F_MAIN_CAP)) {
-        const int rc = regrow(h, (f & F_MAIN_CAP) ? need_main : 0, (f & F_SPAWN_CAP) ? need_sp : 0);
+        const int rc = regrow(h, (f & F_MAIN_CAP) ? need_main : 0, (f & F_SPAWN_CAP) ? seg_need : 0);
         if (rc != DDQMC_OK) return rc;
         continue;
       }
@@ -833,7 +920,14 @@ const char *ddqmc_strerror(int code) {
   }
 }
 
-int ddqmc_batch_create(const ddqmc_params *p, int32_t count, void *hip_stream, ddqmc_t **out) {
+}  // extern "C"
+
+namespace {
+
+// Creation of a handle for count solves: in its own device memory (ws ==
+// nullptr) or inside a caller's workspace.
+int create_common(const ddqmc_params *p, int32_t count, void *hip_stream, void *ws,
+                  size_t ws_bytes, ddqmc_t **out) {
   if (!p || !out || count < 1 || count > MAX_SLOTS) return DDQMC_EINVAL;
   *out = nullptr;
   int Nmax = 0;
@@ -844,9 +938,17 @@ int ddqmc_batch_create(const ddqmc_params *p, int32_t count, void *hip_stream, d
     Nmax = std::max(Nmax, p[i].Lx * p[i].Ly);
     cap += auto_capacity(p[i]);
   }
+  // in a workspace: the capacity asked for, else the largest that fits
+  if (ws) {
+    cap = 0;
+    for (int i = 0; i < count; ++i) cap += (uint64_t)p[i].capacity_hint;
+    bool all = true;
+    for (int i = 0; i < count; ++i) all = all && p[i].capacity_hint > 0;
+    if (!all) cap = 0;
+  }
   ddqmc_t *h = new (std::nothrow) ddqmc_t();
   if (!h) return DDQMC_ENOMEM;
-  int rc = build(h, count, Nmax, cap, hip_stream);
+  int rc = build(h, count, Nmax, cap, hip_stream, ws, ws_bytes);
   if (rc != DDQMC_OK) {
     free_all(h);
     delete h;
@@ -876,6 +978,20 @@ int ddqmc_batch_create(const ddqmc_params *p, int32_t count, void *hip_stream, d
   }
   *out = h;
   return DDQMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ddqmc_batch_create(const ddqmc_params *p, int32_t count, void *hip_stream, ddqmc_t **out) {
+  return create_common(p, count, hip_stream, nullptr, 0, out);
+}
+
+int ddqmc_create_in(const ddqmc_params *p, void *dev_ws, size_t bytes, void *hip_stream,
+                    ddqmc_t **out) {
+  if (!dev_ws) return DDQMC_EINVAL;
+  return create_common(p, 1, hip_stream, dev_ws, bytes, out);
 }
 
 int ddqmc_create(const ddqmc_params *p, void *hip_stream, ddqmc_t **out) {
@@ -1131,17 +1247,37 @@ int ddqmc_get_step_counts(ddqmc_t *h, int64_t *rows, int64_t cap, int64_t *n) {
 }
 
 int ddqmc_workspace_query(const ddqmc_params *p, int64_t capacity, size_t *bytes) {
-  if (!bytes) return DDQMC_EINVAL;
+  if (!bytes || capacity < 0) return DDQMC_EINVAL;
   int rc = validate(p);
   if (rc != DDQMC_OK) return rc;
   const int N = p->Lx * p->Ly;
   const size_t ks = (2 * N > 32) ? 8 : 4;
-  const uint64_t cm = capacity > 0 ? (uint64_t)capacity : auto_capacity(*p);
-  const uint64_t cs = std::max<uint64_t>(4096, cm / 4);
-  *bytes = list_bytes(ks, cm) + loud_bytes(ks, cm) + spawn_bytes(ks, cs) + merge_bytes(cm, cs) +
-           MAX_PASSES * 256 * 4 + sizeof(Ctrl) + sizeof(SlotParams) + sizeof(SlotState) +
-           SERIES_CAP * SERIES_W * 8;
+  uint64_t cm, cs;
+  initial_caps(capacity > 0 ? (uint64_t)capacity : auto_capacity(*p), &cm, &cs);
+  *bytes = fixed_layout(1, ks).total + sized_layout(ks, cm, cs).total;
   return DDQMC_OK;
+}
+
+int ddqmc_device_bytes(ddqmc_t *h, size_t *bytes, int64_t *capacity) {
+  if (!h || !bytes) return DDQMC_EINVAL;
+  *bytes = h->fixed_bytes + h->sized_bytes;
+  if (capacity) *capacity = (int64_t)h->cap_main;
+  return DDQMC_OK;
+}
+
+int ddqmc_set_capacity_limit(ddqmc_t *h, int64_t max_entries) {
+  if (!h || max_entries < 0) return DDQMC_EINVAL;
+  h->cap_limit = (uint64_t)max_entries;
+  return DDQMC_OK;
+}
+
+int ddqmc_plan_growth(uint64_t cap_main, uint64_t cap_sp, uint64_t need_main, uint64_t seg_need,
+                      uint32_t key_bytes, uint64_t free_bytes, uint64_t total_bytes,
+                      uint64_t cap_limit, uint64_t *new_main, uint64_t *new_sp,
+                      uint64_t *bytes) {
+  if (!new_main || !new_sp || !bytes || (key_bytes != 4 && key_bytes != 8)) return DDQMC_EINVAL;
+  return plan_growth(cap_main, cap_sp, need_main, seg_need, key_bytes, free_bytes, total_bytes,
+                     cap_limit, new_main, new_sp, bytes);
 }
 
 int ddqmc_set_profiling(ddqmc_t *h, int32_t on) {

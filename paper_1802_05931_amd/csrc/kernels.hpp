@@ -49,7 +49,7 @@ constexpr uint32_t tree_jobs() {
 constexpr int MAX_PASSES = 8;
 constexpr int NSEG = 64;             // spawn-record segments
 constexpr int COUNT_W = 5;           // per-step counts: in, records, out, loud, heavy
-constexpr int SEG_STRIDE = 32;       // their counters sit 128 bytes apart
+constexpr int SEG_STRIDE = 16;       // their 64-bit counters sit 128 bytes apart
 constexpr int32_t NON_INIT = INT32_MIN;  // marks the unused part of a non-initiator record
 constexpr int MAX_SLOTS = 512;
 constexpr int SERIES_W = 3 + S_NSUM;
@@ -75,7 +75,9 @@ struct Ctrl {
   uint32_t n_inject;    // records waiting to enter the list
   uint32_t extinct_slot;
   uint32_t last_spawn;  // records of the last completed step
-  uint32_t seg_need;    // largest segment fill of a failed step
+  uint32_t pad0;
+  unsigned long long seg_need;  // largest segment fill of a failed step (64-bit: the
+                                // attempted records of a step may exceed 2^32)
   uint32_t n_heavy;     // loud entries that need the general sampling path (scan)
   uint32_t n_late;      // loud entries the light path passed on (loud kernel)
   uint32_t n_loud;      // entries with some event this step
@@ -294,11 +296,12 @@ __global__ __launch_bounds__(NT) void k_spawn_scan(const K *__restrict__ keys,
 // Append records to segment seg (its counter is segcnt[seg * SEG_STRIDE]).
 template <typename K>
 __device__ __forceinline__ void seg_flush(const K *sk, const int2 *sv, uint32_t c, int seg,
-                                          uint32_t *segcnt, K *ok, int2 *ov, uint32_t segcap,
-                                          uint32_t *sbase) {
-  if (threadIdx.x == 0) *sbase = c ? atomicAdd(&segcnt[seg * SEG_STRIDE], c) : 0u;
+                                          unsigned long long *segcnt, K *ok, int2 *ov,
+                                          uint32_t segcap, unsigned long long *sbase) {
+  if (threadIdx.x == 0)
+    *sbase = c ? atomicAdd(&segcnt[seg * SEG_STRIDE], (unsigned long long)c) : 0ull;
   __syncthreads();
-  const uint32_t b = *sbase;
+  const unsigned long long b = *sbase;
   const size_t off = (size_t)seg * segcap;
   for (uint32_t q = threadIdx.x; q < c; q += NT)
     if (b + q < segcap) {
@@ -311,11 +314,12 @@ __device__ __forceinline__ void seg_flush(const K *sk, const int2 *sv, uint32_t 
 // seg_flush for a 64-thread block.
 template <typename K>
 __device__ __forceinline__ void seg_flush64(const K *sk, const int2 *sv, uint32_t c, int seg,
-                                            uint32_t *segcnt, K *ok, int2 *ov, uint32_t segcap,
-                                            uint32_t *sbase) {
-  if (threadIdx.x == 0) *sbase = c ? atomicAdd(&segcnt[seg * SEG_STRIDE], c) : 0u;
+                                            unsigned long long *segcnt, K *ok, int2 *ov,
+                                            uint32_t segcap, unsigned long long *sbase) {
+  if (threadIdx.x == 0)
+    *sbase = c ? atomicAdd(&segcnt[seg * SEG_STRIDE], (unsigned long long)c) : 0ull;
   __syncthreads();
-  const uint32_t b = *sbase;
+  const unsigned long long b = *sbase;
   const size_t off = (size_t)seg * segcap;
   for (uint32_t q = threadIdx.x; q < c; q += blockDim.x)
     if (b + q < segcap) {
@@ -332,7 +336,7 @@ struct RecordSink {
   K *sk;
   int2 *sv;
   uint32_t *scount;
-  uint32_t *segcnt;
+  unsigned long long *segcnt;
   K *ok;
   int2 *ov;
   uint32_t segcap;
@@ -353,7 +357,7 @@ struct RecordSink {
       sk[s] = ck;
       sv[s] = rv;
     } else {
-      const uint32_t g = atomicAdd(&segcnt[seg * SEG_STRIDE], 1u);
+      const unsigned long long g = atomicAdd(&segcnt[seg * SEG_STRIDE], 1ull);
       if (g < segcap) {
         ok[(size_t)seg * segcap + g] = ck;
         ov[(size_t)seg * segcap + g] = rv;
@@ -407,11 +411,12 @@ __global__ __launch_bounds__(NT, 3) void k_spawn_loud(
     Ctrl *ctrl, const SlotParams *__restrict__ sp, const SlotState *__restrict__ ss,
     const uint32_t *__restrict__ lidx, const K *__restrict__ lkey, const int2 *__restrict__ lval,
     uint32_t *__restrict__ late, uint32_t *nlate, K *__restrict__ ok, int2 *__restrict__ ov,
-    uint32_t *segcnt, uint32_t segcap, uint32_t tree_cap, int dyn, int SB) {
+    unsigned long long *segcnt, uint32_t segcap, uint32_t tree_cap, int dyn, int SB) {
   if (ctrl->abort) return;
   __shared__ K sk[STAGE];
   __shared__ int2 sv[STAGE];
-  __shared__ uint32_t scount, sbase;
+  __shared__ uint32_t scount;
+  __shared__ unsigned long long sbase;
   // the chunk's member trees, walked after its entries (see below)
   constexpr uint32_t TREE_JOBS = tree_jobs<K>();
   __shared__ TreeJob s_jobs[TREE_JOBS];
@@ -519,11 +524,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MINW))) void
     const K *__restrict__ keys, const int2 *__restrict__ vals, Ctrl *ctrl,
     const SlotParams *__restrict__ sp, const SlotState *__restrict__ ss,
     const uint32_t *__restrict__ heavy, const uint32_t *__restrict__ nheavy, K *__restrict__ ok,
-    int2 *__restrict__ ov, uint32_t *segcnt, uint32_t segcap, int SB) {
+    int2 *__restrict__ ov, unsigned long long *segcnt, uint32_t segcap, int SB) {
   if (ctrl->abort) return;
   __shared__ K sk[HEAVY_STAGE];
   __shared__ int2 sv[HEAVY_STAGE];
-  __shared__ uint32_t scount, sbase, fcount[2];
+  __shared__ uint32_t scount, fcount[2];
+  __shared__ unsigned long long sbase;
   __shared__ uint32_t fnode[2][HEAVY_FRONT];  // tree | lo << 5 | hi << 12 | h << 19
   __shared__ int64_t fM[2][HEAVY_FRONT];
   __shared__ uint32_t s_cr[6], s_cu[6];  // class bond masks (right, up) and signs, so
@@ -741,13 +747,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MINW))) void
 // Records of solves entering the list this step (serving admissions).
 template <typename K>
 __global__ void k_inject(const K *__restrict__ ik, const int2 *__restrict__ iv, Ctrl *ctrl,
-                         K *__restrict__ ok, int2 *__restrict__ ov, uint32_t *segcnt,
-                         uint32_t segcap) {
+                         K *__restrict__ ok, int2 *__restrict__ ov,
+                         unsigned long long *segcnt, uint32_t segcap) {
   if (ctrl->abort) return;
-  __shared__ uint32_t cnt, base;
+  __shared__ uint32_t cnt;
+  __shared__ unsigned long long base;
   if (threadIdx.x == 0) {
     cnt = ctrl->n_inject;
-    base = cnt ? atomicAdd(&segcnt[0], cnt) : 0u;
+    base = cnt ? atomicAdd(&segcnt[0], (unsigned long long)cnt) : 0ull;
   }
   __syncthreads();
   for (uint32_t q = threadIdx.x; q < cnt; q += blockDim.x) {
@@ -772,27 +779,30 @@ template <typename K>
 __global__ __launch_bounds__(NT) void k_sort_count(const K *__restrict__ ik, Ctrl *ctrl,
                                                    uint32_t *__restrict__ cnt, int pass,
                                                    uint32_t segcap,
-                                                   const uint32_t *__restrict__ segcnt) {
+                                                   const unsigned long long *__restrict__ segcnt) {
   if (ctrl->abort || (ctrl->flags & F_SPAWN_CAP)) return;
   __shared__ uint32_t h[256];
   __shared__ uint32_t pre[NSEG + 1];
-  __shared__ uint32_t s_over;
+  __shared__ unsigned long long s_over;
   if (pass == 0) {
     // the records' segment offsets (every block computes them; block 0 also
     // publishes them, the record count and a segment overflow for the later
-    // kernels)
+    // kernels).  A segment's counter holds the records its step attempted,
+    // which may exceed its capacity (then the step is redone with larger
+    // buffers, and the offsets below are not used).
     if (threadIdx.x < NSEG) {
-      const uint32_t c = segcnt[threadIdx.x * SEG_STRIDE];
+      const unsigned long long c64 = segcnt[threadIdx.x * SEG_STRIDE];
+      const uint32_t c = c64 < segcap ? (uint32_t)c64 : segcap;
       const uint32_t inc = wave_incl_scan(c);
       pre[threadIdx.x] = inc - c;
       if (threadIdx.x == NSEG - 1) pre[NSEG] = inc;
-      uint32_t mx = c;
+      unsigned long long mx = c64;
 #pragma unroll
       for (int o = 32; o >= 1; o >>= 1) {
-        const uint32_t t = __shfl_xor(mx, o, 64);
+        const unsigned long long t = __shfl_xor(mx, o, 64);
         mx = t > mx ? t : mx;
       }
-      if (threadIdx.x == 0) s_over = mx > segcap ? mx : 0u;
+      if (threadIdx.x == 0) s_over = mx > segcap ? mx : 0ull;
     }
     __syncthreads();
     if (blockIdx.x == 0) {
@@ -1313,7 +1323,7 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctrl *ctrl, const SlotParams 
                                                    SlotState *ss, const Partial *partials,
                                                    unsigned long long *spill, int nslots,
                                                    uint32_t *hist, int passes, uint32_t capC,
-                                                   uint32_t *segcnt, int64_t *series,
+                                                   unsigned long long *segcnt, int64_t *series,
                                                    uint32_t *counts, uint32_t series_cap) {
   if (ctrl->abort) return;
   __shared__ unsigned long long sums[MAX_SLOTS * S_NSUM];
@@ -1482,7 +1492,7 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctrl *ctrl, const SlotParams 
 
 // After a failed step: re-arm the counters (the list is untouched).
 __global__ void k_rearm(Ctrl *ctrl, uint32_t *hist, int passes, unsigned long long *spill,
-                        int nspill, uint32_t *segcnt) {
+                        int nspill, unsigned long long *segcnt) {
   for (int i = threadIdx.x; i < passes * 256; i += blockDim.x) hist[i] = 0;
   for (int i = threadIdx.x; i < nspill; i += blockDim.x) spill[i] = 0;
   for (int i = threadIdx.x; i < NSEG; i += blockDim.x) segcnt[i * SEG_STRIDE] = 0;

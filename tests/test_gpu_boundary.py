@@ -1,0 +1,159 @@
+"""The C ABI's memory and error surface on the device: a handle carved out of a
+caller's (torch-allocated) workspace steps bit for bit like a library-allocated
+one; ddqmc_workspace_query equals what a handle holds; a capacity ceiling
+turns growth into DDQMC_ECAPACITY with the list of the last completed step
+kept (checked against the oracle); a population that dies out is reported as
+DDQMC_EEXTINCT with the handle unchanged."""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dq():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1802_05931_amd as m
+    return m
+
+
+def _same_list(a, b):
+    return (len(a[0]) == len(b[0]) and np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+            and np.array_equal(a[2], b[2]))
+
+
+def _workspace(nbytes, offset=0):
+    import torch
+    t = torch.empty(nbytes + 512, dtype=torch.uint8, device="cuda")
+    base = t.data_ptr()
+    start = (base + 255) // 256 * 256 + offset
+    return t, (start, nbytes)
+
+
+def test_device_bytes_equal_the_workspace_query(dq):
+    for cfg, cap in ((dict(workloads.d2(0.6)), 50_000), (dict(workloads.D1), 0),
+                     (dict(Lx=5, Ly=5, target_walkers=20000, initial_walkers=20000), 70_000)):
+        p = dq.make_params(**dict(cfg, capacity_hint=cap))
+        g = dq.Solve(p)
+        got, c = g.device_bytes()
+        assert got == dq.workspace_query(p, cap) == dq.workspace_query(p, c)
+        g.close()
+
+
+def test_create_in_steps_like_create(dq, orc):
+    """A D2-shaped solve in a torch-owned workspace sized by the query: the same
+    lists, scalars and series as a library-allocated handle, and the oracle's."""
+    import torch
+    # (the records get a quarter of the list capacity, split over 64 segments)
+    cfg = dict(workloads.d2(0.6), target_walkers=20000, n_equil=100, capacity_hint=400_000)
+    p = dq.make_params(**cfg)
+    need = dq.workspace_query(p, cfg["capacity_hint"])
+    t, ws = _workspace(need)
+    a = dq.Solve(p, workspace=ws)
+    assert a.device_bytes() == (need, cfg["capacity_hint"])
+    b = dq.Solve(dq.make_params(**cfg))
+    o = orc.Oracle(**{k: v for k, v in cfg.items() if k != "capacity_hint"})
+    for _ in range(3):
+        a.step(200)
+        b.step(200)
+        o.step(200)
+        assert _same_list(a.walkers(), b.walkers())
+        assert _same_list(a.walkers(), o.get_list())
+        assert a.scalars() == b.scalars() == o.scalars()
+    assert np.array_equal(a.series(), b.series())
+    assert a.observables()["acc"] == b.observables()["acc"]
+    a.close()
+    b.close()
+    torch.cuda.synchronize()
+    del t
+
+
+def test_create_in_argument_errors(dq):
+    cfg = dict(workloads.d2(0.6), capacity_hint=20_000)
+    p = dq.make_params(**cfg)
+    need = dq.workspace_query(p, 20_000)
+    t, ws = _workspace(need)
+    with pytest.raises(dq.DDQMCError) as e:  # one byte short
+        dq.Solve(p, workspace=(ws[0], need - 1))
+    assert e.value.code == -3
+    with pytest.raises(dq.DDQMCError) as e:  # not 256-byte aligned
+        dq.Solve(p, workspace=(ws[0] + 8, need))
+    assert e.value.code == -1
+    # no capacity asked for: the largest that fits
+    g = dq.Solve(dq.make_params(**dict(cfg, capacity_hint=0)), workspace=ws)
+    got, cap = g.device_bytes()
+    assert got <= need and cap >= 20_000
+    g.close()
+    del t
+
+
+def test_create_in_full_workspace_reports_capacity(dq, orc):
+    """A workspace too small for the run: the step that outgrows it returns
+    ECAPACITY (a workspace never grows), and the handle keeps the list of its
+    last completed step, the oracle's at that step."""
+    cfg = dict(workloads.d2(0.6), target_walkers=20000, n_equil=100, capacity_hint=4096)
+    p = dq.make_params(**cfg)
+    t, ws = _workspace(dq.workspace_query(p, 4096))
+    g = dq.Solve(p, workspace=ws)
+    o = orc.Oracle(**{k: v for k, v in cfg.items() if k != "capacity_hint"})
+    done = 0
+    with pytest.raises(dq.DDQMCError) as e:
+        for _ in range(100):
+            g.step(50)
+            o.step(50)
+            done += 50
+    assert e.value.code == -3
+    st = g.scalars()["step"]
+    assert done <= st < done + 50
+    o.step(st - done)
+    assert _same_list(g.walkers(), o.get_list())
+    assert g.scalars() == o.scalars()
+    # the handle stays usable for reads and the error repeats
+    with pytest.raises(dq.DDQMCError) as e:
+        g.step(1)
+    assert e.value.code == -3 and g.scalars()["step"] == st
+    g.close()
+    del t
+
+
+def test_capacity_ceiling_reports_capacity(dq, orc):
+    """A test ceiling on growth: ECAPACITY once the list needs more than the
+    ceiling, with the last completed step's list kept; lifting the ceiling
+    lets the same handle go on exactly as the oracle."""
+    cfg = dict(workloads.d2(0.6), target_walkers=20000, n_equil=100, capacity_hint=16)
+    g = dq.Solve(dq.make_params(**cfg))
+    g.set_capacity_limit(6000)
+    o = orc.Oracle(**{k: v for k, v in cfg.items() if k != "capacity_hint"})
+    with pytest.raises(dq.DDQMCError) as e:
+        for _ in range(100):
+            g.step(25)
+            o.step(25)
+    assert e.value.code == -3
+    st = g.scalars()["step"]
+    o.step(st - o.scalars()["step"])
+    assert _same_list(g.walkers(), o.get_list())
+    assert len(o.get_list()[0]) <= 6000
+    g.set_capacity_limit(0)
+    g.step(100)
+    o.step(100)
+    assert _same_list(g.walkers(), o.get_list())
+    assert g.scalars() == o.scalars()
+    g.close()
+
+
+def test_extinction_is_reported(dq):
+    """Jx = Jy leaves the all-down configuration without off-diagonal moves, and
+    dt * |d_r| = 0.5 * 2 = 1 kills every walker on it in one step: the list would
+    be empty, so the step reports EEXTINCT and the handle keeps its start."""
+    g = dq.Solve(dq.make_params(Lx=2, Ly=2, Jx=1.0, Jy=1.0, Jz=1.0, dt=0.5, shift_init=2.0,
+                                target_walkers=10 ** 9, initial_walkers=1000))
+    before = g.walkers()
+    with pytest.raises(dq.DDQMCError) as e:
+        g.step(1)
+    assert e.value.code == -5
+    assert _same_list(before, g.walkers()) and g.scalars()["step"] == 0
+    g.close()

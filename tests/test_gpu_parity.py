@@ -465,19 +465,26 @@ def test_checkpoint_resume_bit_exact(dq):
 
 
 def test_full_size_4x4_window(dq, orc):
-    """The 4x4 workload at its full population (1e7 walkers, IS p = 1.5): the GPU
-    runs its warm-up, then a window of steps from that state is checked against
-    the oracle started from the same snapshot."""
+    """The 4x4 workload at full size: the GPU steps it until its list is steady
+    (about 1.07e7 entries after some 14,500 steps, as the benchmark times it),
+    at which size the list capacity is above 2^23 entries, so the large-entry
+    kernel runs on the second stream beside the loud kernel, as in the timed
+    steps; then two steps from that snapshot are checked against the oracle."""
     cfg = dict(workloads.D3)
     g = dq.Solve(dq.make_params(**cfg))
-    g.step(300)
+    g.step(15000)
     keys, re, im = g.walkers()
     sc = g.scalars()
-    assert len(keys) > 10 * 2048
+    _, cap = g.device_bytes()
+    assert len(keys) > 10_000_000, len(keys)
+    assert cap >= 1 << 23  # the fork's threshold (ddqmc_set_heavy_fork mode 0)
+    counts = g.step_counts()[-1]
+    assert counts[4] > 100 and counts[3] > 1_000_000  # heavy and loud entries at full size
     o = orc.Oracle(**cfg)
     o.set_list(keys, re, im)
     o.set_scalars(sc["S"], sc["mode"], sc["step"], sc["nw_prev"])
     print(f"  4x4 snapshot at step {sc['step']}: {len(keys)} entries", flush=True)
+    del keys, re, im
     for i in range(2):
         g.step(1)
         o.step(1)
@@ -485,3 +492,54 @@ def test_full_size_4x4_window(dq, orc):
         assert g.scalars() == o.scalars()
         print(f"  4x4 window step {i + 1} bit-identical", flush=True)
     g.close()
+
+
+def test_d1_full_run(dq, orc):
+    """D1 (2x2) for all of its 10^4 steps, the series and accumulators included."""
+    cfg = dict(workloads.D1)
+    _compare_run(dq, orc, cfg, chunks=10, per=workloads.D1_STEPS // 10)
+
+
+@pytest.mark.parametrize("jx", [0.6, 0.9, 1.1])
+def test_d2_window_at_full_target(dq, orc, jx):
+    """D2 (3x3) at its full target of 1e5 walkers, seed 0: the GPU runs 3000
+    steps (past the growth phase), then the oracle follows a 1000-step window
+    from that snapshot, compared every 250 steps."""
+    cfg = dict(workloads.d2(jx))
+    g = dq.Solve(dq.make_params(**cfg))
+    g.step(3000)
+    keys, re, im = g.walkers()
+    sc = g.scalars()
+    assert sc["mode"] == 1  # the shift varies: the target was reached
+    o = orc.Oracle(**cfg)
+    o.set_list(keys, re, im)
+    o.set_scalars(sc["S"], sc["mode"], sc["step"], sc["nw_prev"])
+    for c in range(4):
+        g.step(250)
+        o.step(250)
+        assert _same_list(g.walkers(), o.get_list()), c
+        assert g.scalars() == o.scalars()
+        print(f"  3x3 Jx {jx}: step {o.scalars()['step']}, {len(o.get_list()[0])} entries ok",
+              flush=True)
+    g.close()
+
+
+def test_d5_replicas_batch_equals_oracle(dq, orc):
+    """Four of the 64 5x5 replicas of the batched workload (their own Jx,
+    targets and solve ids), in one batch handle with 50-step graphs as the
+    benchmark runs them, against the oracle run alone for each."""
+    cfgs = workloads.d5_replicas()
+    pick = [0, 21, 42, 63]
+    b = dq.Batch([dq.make_params(**cfgs[i]) for i in pick])
+    b.set_graph_steps(50)
+    orcs = [orc.Oracle(**cfgs[i]) for i in pick]
+    for c in range(3):
+        b.step(100)
+        for j, o in enumerate(orcs):
+            o.step(100)
+            assert _same_list(b.walkers(j), o.get_list()), (pick[j], c)
+            assert b.scalars(j) == o.scalars(), pick[j]
+        print(f"  5x5 replicas: {(c + 1) * 100} steps ok", flush=True)
+    for j, o in enumerate(orcs):
+        assert np.array_equal(b.series(j), o.series())
+    b.close()
