@@ -288,6 +288,17 @@ int ddqmc_dev_uniforms(uint64_t seed, uint32_t solve_id, uint64_t cfg, uint32_t 
 int ddqmc_dev_binom(int64_t n, double p, int32_t mode, uint64_t seed, int64_t count,
                     int64_t *out);
 int ddqmc_dev_math(const double *x, int64_t count, double *out);
+/* ddqmc_dev_binom_noalloc: ddqmc_dev_binom for callers that cannot allocate
+ *   device memory (code under HIP graph capture, tight serving loops, harnesses
+ *   that forbid hipMalloc): the same samples, staged in a static device
+ *   scratch array of the library (8 MiB + 256 bytes, held by every GPU the
+ *   library runs on until the process ends) instead of a buffer allocated per
+ *   call; it calls no hipMalloc or hipFree.  count <= 2^20 (EINVAL beyond, with
+ *   a message on stderr); other arguments and errors as ddqmc_dev_binom.  The
+ *   scratch keeps the last call's contents; calls that overlap on one GPU (from
+ *   several host threads) race on it and must be serialised by the caller. */
+int ddqmc_dev_binom_noalloc(int64_t n, double p, int32_t mode, uint64_t seed, int64_t count,
+                            int64_t *out);
 int ddqmc_dev_quiet(const double *p, const int64_t *n, const double *u, int64_t count,
                     int32_t *out);
 

@@ -17,7 +17,8 @@ STAGES = ("scan", "gather", "loud", "heavy", "seal", "histogram", "sort", "count
           "finalize")
 
 __all__ = ["Solve", "Batch", "Pool", "make_params", "DDQMCError", "NO_INITIATOR", "SUM_NAMES",
-           "dev_uniforms", "dev_binom", "dev_math", "dev_quiet", "workspace_query",
+           "dev_uniforms", "dev_binom", "dev_binom_noalloc", "dev_math", "dev_quiet",
+           "workspace_query",
            "plan_growth"]
 
 
@@ -266,6 +267,15 @@ def dev_binom(n, p, mode, seed, count):
     out = np.zeros(count, np.int64)
     check(lib().ddqmc_dev_binom(int(n), float(p), int(mode), int(seed), int(count),
                                 ptr(out, ctypes.c_int64)), "dev_binom")
+    return out
+
+
+def dev_binom_noalloc(n, p, mode, seed, count):
+    """dev_binom through the entry point that allocates no device memory (its
+    samples are staged in the library's static scratch; count <= 2^20)."""
+    out = np.zeros(count, np.int64)
+    check(lib().ddqmc_dev_binom_noalloc(int(n), float(p), int(mode), int(seed), int(count),
+                                        ptr(out, ctypes.c_int64)), "dev_binom_noalloc")
     return out
 
 

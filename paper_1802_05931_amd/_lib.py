@@ -117,6 +117,9 @@ SIGNATURES = {
     "ddqmc_dev_binom": (ctypes.c_int, [ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
                                        ctypes.c_uint64, ctypes.c_int64, _P(ctypes.c_int64)]),
     "ddqmc_dev_math": (ctypes.c_int, [_P(ctypes.c_double), ctypes.c_int64, _P(ctypes.c_double)]),
+    "ddqmc_dev_binom_noalloc": (ctypes.c_int, [ctypes.c_int64, ctypes.c_double, ctypes.c_int32,
+                                               ctypes.c_uint64, ctypes.c_int64,
+                                               _P(ctypes.c_int64)]),
     "ddqmc_dev_quiet": (ctypes.c_int, [_P(ctypes.c_double), _P(ctypes.c_int64), _P(ctypes.c_double),
                                        ctypes.c_int64, _P(ctypes.c_int32)]),
     "ddqmc_strerror": (ctypes.c_char_p, [ctypes.c_int]),

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -20,6 +21,17 @@
 #include "kernels.hpp"
 
 using namespace ddqmc;
+
+// Scratch of ddqmc_dev_binom_noalloc, the variant of ddqmc_dev_binom for
+// callers that cannot allocate device memory: a 256-byte header (the error
+// flag) and room for NOALLOC_MAX_SAMPLES int64 samples.  Every GPU the library
+// runs on holds its own copy for the life of the process.  Host code never
+// passes this name to a kernel (on the host it is only a stand-in for the
+// symbol): it uses the device address that hipGetSymbolAddress returns, kept
+// per device in noalloc_scratch().
+constexpr int64_t NOALLOC_MAX_SAMPLES = 1 << 20;
+constexpr size_t NOALLOC_HEADER = 256;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_HEADER + NOALLOC_MAX_SAMPLES * 8];
 
 namespace {
 
@@ -893,6 +905,26 @@ uint64_t auto_capacity(const ddqmc_params &p) {
   return std::min<uint64_t>(std::max<uint64_t>(t / 2, 16384), 1ull << 26);
 }
 
+// Device address of `scratch` on the current device, looked up once per
+// device (hipGetSymbolAddress with that device current) and kept.
+int noalloc_scratch(unsigned char **out) {
+  constexpr int MAX_DEVICES = 64;
+  static std::mutex mu;
+  static unsigned char *addr[MAX_DEVICES] = {};
+  int dev = 0;
+  HIPC(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return DDQMC_EINVAL;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return e != hipSuccess ? hip_err(e) : DDQMC_EHIP;
+    addr[dev] = (unsigned char *)p;
+  }
+  *out = addr[dev];
+  return DDQMC_OK;
+}
+
 struct StateHeader {
   uint64_t magic;
   uint32_t version, key_bytes;
@@ -1362,6 +1394,36 @@ int ddqmc_dev_binom(int64_t n, double p, int32_t mode, uint64_t seed, int64_t co
   if (e == hipSuccess) e = hipMemcpy(&he, err, sizeof(int), hipMemcpyDeviceToHost);
   (void)hipFree(d);
   (void)hipFree(err);
+  if (e != hipSuccess) return hip_err(e);
+  return he ? DDQMC_ERNG : DDQMC_OK;
+}
+
+int ddqmc_dev_binom_noalloc(int64_t n, double p, int32_t mode, uint64_t seed, int64_t count,
+                            int64_t *out) {
+  if (!out || count < 0 || mode < 0 || mode > 2 || n < 0 || !(p >= 0.0)) return DDQMC_EINVAL;
+  if ((mode == 0 || mode == 1) && p > 1.0) return DDQMC_EINVAL;
+  if (mode == 1 && (n < 1 || p <= 0.0 || p >= 1.0)) return DDQMC_EINVAL;
+  if (count > NOALLOC_MAX_SAMPLES) {
+    std::fprintf(stderr,
+                 "ddqmc_dev_binom_noalloc: %lld samples asked for, its scratch holds at most "
+                 "%lld\n",
+                 (long long)count, (long long)NOALLOC_MAX_SAMPLES);
+    return DDQMC_EINVAL;
+  }
+  if (count == 0) return DDQMC_OK;
+  unsigned char *base = nullptr;
+  const int rc = noalloc_scratch(&base);
+  if (rc != DDQMC_OK) return rc;
+  int *err = (int *)base;
+  int64_t *d = (int64_t *)(base + NOALLOC_HEADER);
+  // the flag left by the previous call is cleared by a kernel on the same
+  // stream as the sampler (no memset node, so the sequence may be captured)
+  k_fill_u32<<<1, 64>>>((uint32_t *)err, 0u, 1u);
+  k_dev_binom<<<(uint32_t)((count + 255) / 256), 256>>>(n, p, mode, seed, count, d, err);
+  hipError_t e = hipGetLastError();
+  int he = 0;
+  if (e == hipSuccess) e = hipMemcpy(out, d, count * sizeof(int64_t), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(&he, err, sizeof(int), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_err(e);
   return he ? DDQMC_ERNG : DDQMC_OK;
 }

@@ -1524,6 +1524,13 @@ __global__ void k_dev_uniforms(uint64_t seed, uint32_t solve, uint64_t cfg, uint
   }
 }
 
+// Fill count words with v (a kernel rather than a memset, so that a captured
+// sequence holds no memset node).
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, uint32_t count) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
 __global__ void k_dev_binom(int64_t n, double p, int mode, uint64_t seed, int64_t count,
                             int64_t *out, int *err) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
