@@ -214,6 +214,15 @@ int ddqmc_plan_growth(uint64_t cap_main, uint64_t cap_sp, uint64_t need_main, ui
                       uint64_t *bytes);
 int ddqmc_set_capacity_limit(ddqmc_t *h, int64_t max_entries);
 
+/* Standard error of the ratio of means of a per-step (numerator, denominator)
+ * series, as ddqmc_observables computes it (host arithmetic only): the series
+ * is blocked by successive halving (Flyvbjerg-Petersen) while at least 16
+ * blocks remain; at each level the error of mean(num) / mean(den) follows from
+ * the block means by the delta method, sqrt(var(num_b - r den_b) / n_b) /
+ * mean(den); the largest over the levels is returned (0 for fewer than 16
+ * points).  EINVAL on NULL pointers or n < 0. */
+int ddqmc_ratio_se(const double *num, const double *den, int64_t n, double *se);
+
 /* Wall time of the kernels of the last ddqmc_step call, per stage, from HIP
  * events on the handle's stream when profiling is on (ddqmc_set_profiling);
  * ms[10] = quiet scan (which also writes the list of loud entries), loud

@@ -707,6 +707,77 @@ static void tree_split(const tree_t *t, int lo, int hi, int hnode, int64_t M) {
   tree_split(t, mid, hi, 2 * hnode + 1, M - ML);
 }
 
+/* Placement of the Xs walkers a real-element (jump) channel spawns over the
+ * nJ sites where ket and bra are both up (Sec. III.B: the multinomial over
+ * equally weighted connections): one walker takes a uniform site, more are
+ * split by the balanced binomial tree.  cnt[j] receives site j's count. */
+static void place_jumps(const ectx_t *ec, int ch, int64_t Xs, int nJ, int64_t *cnt) {
+  int j;
+  for (j = 0; j < nJ; j++) cnt[j] = 0;
+  if (Xs == 0) return;
+  if (Xs == 1) {
+    stream_t s;
+    int jj;
+    channel_stream(ec, &s, DRAW_CH(ch) + DRAW_PICK);
+    jj = (int)floor(stream_next(&s) * (double)nJ);
+    if (jj > nJ - 1) jj = nJ - 1;
+    cnt[jj] = 1;
+  } else {
+    tree_t t;
+    t.ec = ec; t.draw_base = DRAW_CH(ch) + 64u; t.out = cnt;
+    tree_split(&t, 0, nJ, 1, Xs);
+  }
+}
+
+/* Placement of the rem walkers an imaginary-element (hop) channel spawns over
+ * the hop classes and their members (Sec. III.B: the multinomial over the
+ * connections with weights |element| x IS weight): one walker by one
+ * categorical pick (its class by inversion on the suffix sums Sc of the class
+ * weights, then a uniform member); more walkers by sequential conditional
+ * binomials over the classes (the last class with weight takes the rest), then
+ * the balanced binomial tree inside each class.  cnt[c][j] receives member j
+ * of class c. */
+static void place_hops(const ectx_t *ec, int ch, int64_t rem, const hop_classes_t *hc,
+                       const double Sc[6], int64_t cnt[6][64]) {
+  int c, j, last = -1;
+  for (c = 0; c < 6; c++)
+    for (j = 0; j < hc->n[c]; j++) cnt[c][j] = 0;
+  if (rem == 0) return;
+  if (rem == 1) {
+    stream_t s;
+    double u1, u2, T;
+    int jj;
+    channel_stream(ec, &s, DRAW_CH(ch) + DRAW_PICK);
+    u1 = stream_next(&s);
+    u2 = stream_next(&s);
+    T = Sc[0] * (1.0 - u1);
+    c = 0;
+    while (!((c < 5 ? Sc[c + 1] : 0.0) < T)) c++;
+    jj = (int)floor(u2 * (double)hc->n[c]);
+    if (jj > hc->n[c] - 1) jj = hc->n[c] - 1;
+    cnt[c][jj] = 1;
+    return;
+  }
+  for (c = 0; c < 6; c++)
+    if (hc->W[c] > 0.0) last = c;
+  for (c = 0; c < 6 && rem > 0; c++) {
+    int64_t Mc;
+    tree_t t;
+    stream_t s;
+    if (hc->W[c] == 0.0) continue;
+    if (c == last) {
+      Mc = rem;
+    } else {
+      channel_stream(ec, &s, DRAW_CH(ch) + 1u + (uint32_t)c);
+      Mc = binom(rem, hc->W[c] / Sc[c], &s);
+    }
+    rem -= Mc;
+    if (Mc == 0) continue;
+    t.ec = ec; t.draw_base = DRAW_CH(ch) + 64u + 64u * (uint32_t)c; t.out = cnt[c];
+    tree_split(&t, 0, hc->n[c], 1, Mc);
+  }
+}
+
 static void process_entry(orc_t *h, uint64_t key, int32_t R, int32_t I, int64_t *dR, int64_t *dI,
                           int *err) {
   const model_t *md = &h->md;
@@ -757,24 +828,11 @@ static void process_entry(orc_t *h, uint64_t key, int32_t R, int32_t I, int64_t 
   /* spawning along the real elements (jumps gamma S^- rho S^+) */
   for (k = 0; k < 2; k++) {
     int ch = k ? 7 : 3; /* 1-based channel number */
-    int64_t Xs = X[ch - 1], cnt[64];
+    int64_t cnt[64];
     int64_t sg = k ? sI : sR;
-    tree_t t;
     int j;
-    if (Xs == 0) continue;
-    for (j = 0; j < nJ; j++) cnt[j] = 0;
-    if (Xs == 1) {
-      /* one walker: a uniform member */
-      stream_t s;
-      int jj;
-      channel_stream(&ec, &s, DRAW_CH(ch) + DRAW_PICK);
-      jj = (int)floor(stream_next(&s) * (double)nJ);
-      if (jj > nJ - 1) jj = nJ - 1;
-      cnt[jj] = 1;
-    } else {
-      t.ec = &ec; t.draw_base = DRAW_CH(ch) + 64u; t.out = cnt;
-      tree_split(&t, 0, nJ, 1, Xs);
-    }
+    if (X[ch - 1] == 0) continue;
+    place_jumps(&ec, ch, X[ch - 1], nJ, cnt);
     for (j = 0; j < nJ; j++) {
       if (cnt[j] == 0) continue;
       {
@@ -786,62 +844,21 @@ static void process_entry(orc_t *h, uint64_t key, int32_t R, int32_t I, int64_t 
   }
 
   /* spawning along the imaginary elements (hops -iH on the ket, +iH on the bra):
-   * split N_sp over the classes by sequential conditional binomials, then over
-   * the members of each class by the tree */
+   * the channel's walkers placed over the classes and their members */
   for (k = 0; k < 2; k++) {
     int ch = k ? 8 : 4;
-    int64_t rem = X[ch - 1];
     int64_t sg = k ? sI : sR;
-    int last = -1;
-    if (rem == 0) continue;
-    if (rem == 1) {
-      /* one walker: class by inversion on the weights, then a uniform member */
-      stream_t s;
-      double u1, u2, T;
-      int jj, b;
-      uint64_t cl, cm;
-      int64_t v;
-      channel_stream(&ec, &s, DRAW_CH(ch) + DRAW_PICK);
-      u1 = stream_next(&s);
-      u2 = stream_next(&s);
-      T = Sc[0] * (1.0 - u1);
-      c = 0;
-      while (!((c < 5 ? Sc[c + 1] : 0.0) < T)) c++;
-      jj = (int)floor(u2 * (double)hc.n[c]);
-      if (jj > hc.n[c] - 1) jj = hc.n[c] - 1;
-      b = hc.mem[c][jj];
-      v = sg * (int64_t)hc.sgn[c];
-      cl = c < 3 ? (l ^ md->bmask[b]) : l;
-      cm = c < 3 ? m : (m ^ md->bmask[b]);
-      if (k == 0) emit(&em, cl, cm, 0, v);
-      else emit(&em, cl, cm, -v, 0);
-      continue;
-    }
-    for (c = 0; c < 6; c++)
-      if (hc.W[c] > 0.0) last = c;
-    for (c = 0; c < 6 && rem > 0; c++) {
-      int64_t Mc, cnt[64];
-      tree_t t;
+    int64_t cnt[6][64];
+    if (X[ch - 1] == 0) continue;
+    place_hops(&ec, ch, X[ch - 1], &hc, Sc, cnt);
+    for (c = 0; c < 6; c++) {
       int j;
-      stream_t s;
-      if (hc.W[c] == 0.0) continue;
-      if (c == last) {
-        Mc = rem;
-      } else {
-        channel_stream(&ec, &s, DRAW_CH(ch) + 1u + (uint32_t)c);
-        Mc = binom(rem, hc.W[c] / Sc[c], &s);
-      }
-      rem -= Mc;
-      if (Mc == 0) continue;
-      for (j = 0; j < hc.n[c]; j++) cnt[j] = 0;
-      t.ec = &ec; t.draw_base = DRAW_CH(ch) + 64u + 64u * (uint32_t)c; t.out = cnt;
-      tree_split(&t, 0, hc.n[c], 1, Mc);
       for (j = 0; j < hc.n[c]; j++) {
         int b = hc.mem[c][j];
         int64_t v;
         uint64_t cl, cm;
-        if (cnt[j] == 0) continue;
-        v = sg * (int64_t)hc.sgn[c] * cnt[j];
+        if (cnt[c][j] == 0) continue;
+        v = sg * (int64_t)hc.sgn[c] * cnt[c][j];
         cl = c < 3 ? (l ^ md->bmask[b]) : l;
         cm = c < 3 ? m : (m ^ md->bmask[b]);
         /* real parent x Im element -> imaginary child; imaginary parent x Im
@@ -1094,4 +1111,56 @@ int orc_get_series(const orc_t *h, int64_t *rows, int64_t cap_rows) {
   if (cap_rows < h->series_len) return ORC_EINVAL;
   memcpy(rows, h->series, (size_t)(h->series_len * SERIES_W) * sizeof(int64_t));
   return ORC_OK;
+}
+
+/* Test entry point: X walkers of spawning channel `channel` of the entry `key`
+ * placed over its connections by the step's own code (place_jumps /
+ * place_hops), count times, sample i drawing at step i.  Channels 3 and 7
+ * (jumps): rows of N counts by site (0 where ket and bra are not both up).
+ * Channels 4 and 8 (hops): rows of 2 nb counts, ket bond b at column b and bra
+ * bond b at column nb + b.  Returns the row width, or a negative code. */
+int orc_split_many(const orc_params *p, uint64_t key, int channel, int64_t X, int64_t count,
+                   int64_t *out) {
+  model_t md;
+  int N, rc, width, k, err = 0;
+  uint64_t mask, l, m;
+  int64_t i;
+  if (!p || !out || X < 0 || count < 0) return ORC_EINVAL;
+  if (channel != 3 && channel != 4 && channel != 7 && channel != 8) return ORC_EINVAL;
+  rc = model_init(&md, p);
+  if (rc != ORC_OK) return rc;
+  N = md.N;
+  mask = (N == 32) ? 0xffffffffull : ((1ull << N) - 1);
+  l = key >> N;
+  m = key & mask;
+  width = (channel == 3 || channel == 7) ? N : 2 * md.nb;
+  for (i = 0; i < count; i++) {
+    ectx_t ec;
+    int64_t *row = out + i * width;
+    ec.seed = p->seed; ec.solve_id = p->solve_id; ec.cfg = key; ec.step = (uint32_t)i;
+    ec.err = &err;
+    for (k = 0; k < width; k++) row[k] = 0;
+    if (channel == 3 || channel == 7) {
+      int jsite[64], nJ = 0, j;
+      int64_t cnt[64];
+      for (k = 0; k < N; k++)
+        if (bit(l, k) && bit(m, k)) jsite[nJ++] = k;
+      if (nJ == 0) return ORC_EINVAL;
+      place_jumps(&ec, channel, X, nJ, cnt);
+      for (j = 0; j < nJ; j++) row[jsite[j]] = cnt[j];
+    } else {
+      hop_classes_t hc;
+      double Sc[6];
+      int64_t cnt[6][64];
+      int c, j;
+      hop_classes(&md, l, m, &hc);
+      Sc[5] = hc.W[5];
+      for (c = 4; c >= 0; c--) Sc[c] = hc.W[c] + Sc[c + 1];
+      if (!(Sc[0] > 0.0)) return ORC_EINVAL;
+      place_hops(&ec, channel, X, &hc, Sc, cnt);
+      for (c = 0; c < 6; c++)
+        for (j = 0; j < hc.n[c]; j++) row[(c < 3 ? 0 : md.nb) + hc.mem[c][j]] += cnt[c][j];
+    }
+  }
+  return err ? err : width;
 }

@@ -83,6 +83,12 @@ double orc_no_event_prob(const double p[8], const int64_t n[8]);
 int orc_channels_many(const double p[8], const int64_t n[8], uint64_t seed, int64_t count,
                       int64_t *out);
 int orc_bonds(int32_t Lx, int32_t Ly, int32_t *s1, int32_t *s2);
+/* the placement of X walkers of one spawning channel (3/7 jumps, 4/8 hops) of
+ * the entry key over its connections, by the step's code; sample i at step i.
+ * Rows of N (jumps, by site) or 2 nb (hops: ket bonds, then bra bonds) counts;
+ * returns the row width or a negative code. */
+int orc_split_many(const orc_params *p, uint64_t key, int channel, int64_t X, int64_t count,
+                   int64_t *out);
 /* off-diagonal elements of the shifted, importance-sampled Liouvillian seen from
  * the parent (ket, bra): child configuration and element (re, im); plus diagonal. */
 int orc_connections(const orc_params *p, uint64_t ket, uint64_t bra, double S, uint64_t *cket,

@@ -98,6 +98,8 @@ def lib():
         "orc_channels_many": (ctypes.c_int, [dp, i64p, ctypes.c_uint64, ctypes.c_int64, i64p]),
         "orc_no_event_prob": (ctypes.c_double, [dp, i64p]),
         "orc_bonds": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, i32p, i32p]),
+        "orc_split_many": (ctypes.c_int, [_P(Params), ctypes.c_uint64, ctypes.c_int,
+                                          ctypes.c_int64, ctypes.c_int64, i64p]),
         "orc_connections": (ctypes.c_int, [_P(Params), ctypes.c_uint64, ctypes.c_uint64,
                                            ctypes.c_double, u64p, u64p, dp, dp, ctypes.c_int32,
                                            dp, dp]),
@@ -244,6 +246,21 @@ def channels_many(p, n, seed, count):
     out = np.zeros((count, 8), np.int64)
     _check(lib().orc_channels_many(_ptr(pa, ctypes.c_double), _ptr(na, ctypes.c_int64), int(seed),
                                    int(count), _ptr(out, ctypes.c_int64)), "channels_many")
+    return out
+
+
+def split_many(params, key, channel, X, count):
+    """X walkers of spawning channel `channel` (3/7 jumps, 4/8 hops) of the entry
+    `key` placed over its connections by the step's code, count times: rows of N
+    counts by site (jumps) or 2 nb counts, ket bonds then bra bonds (hops)."""
+    N = params.Lx * params.Ly
+    width = N if channel in (3, 7) else 2 * len(bonds(params.Lx, params.Ly))
+    out = np.zeros((count, width), np.int64)
+    rc = lib().orc_split_many(ctypes.byref(params), int(key), int(channel), int(X), int(count),
+                              _ptr(out, ctypes.c_int64))
+    if rc < 0:
+        raise OracleError(rc, "split_many")
+    assert rc == width
     return out
 
 

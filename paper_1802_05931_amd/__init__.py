@@ -18,7 +18,7 @@ STAGES = ("scan", "gather", "loud", "heavy", "seal", "histogram", "sort", "count
 
 __all__ = ["Solve", "Batch", "Pool", "make_params", "DDQMCError", "NO_INITIATOR", "SUM_NAMES",
            "dev_uniforms", "dev_binom", "dev_binom_noalloc", "dev_math", "dev_quiet",
-           "workspace_query",
+           "workspace_query", "ratio_se",
            "plan_growth"]
 
 
@@ -254,6 +254,18 @@ def plan_growth(cap_main, cap_sp, need_main, seg_need, key_bytes, free_bytes, to
                                  int(cap_limit), ctypes.byref(nm), ctypes.byref(ns),
                                  ctypes.byref(nb))
     return rc, nm.value, ns.value, nb.value
+
+
+def ratio_se(num, den):
+    """The library's blocking / delta-method error of mean(num) / mean(den) (host)."""
+    a = np.ascontiguousarray(num, np.float64)
+    b = np.ascontiguousarray(den, np.float64)
+    if a.shape != b.shape or a.ndim != 1:
+        raise ValueError("ratio_se: num and den must be 1-d series of one length")
+    se = ctypes.c_double()
+    check(lib().ddqmc_ratio_se(ptr(a, ctypes.c_double), ptr(b, ctypes.c_double), len(a),
+                               ctypes.byref(se)), "ratio_se")
+    return se.value
 
 
 def dev_uniforms(seed, solve_id, cfg, step, draw, count):

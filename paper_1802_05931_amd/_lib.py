@@ -101,6 +101,8 @@ SIGNATURES = {
     "ddqmc_create_in": (ctypes.c_int, [_P(Params), _vp, ctypes.c_size_t, _vp, _P(_vp)]),
     "ddqmc_device_bytes": (ctypes.c_int, [_vp, _P(ctypes.c_size_t), _P(ctypes.c_int64)]),
     "ddqmc_set_capacity_limit": (ctypes.c_int, [_vp, ctypes.c_int64]),
+    "ddqmc_ratio_se": (ctypes.c_int, [_P(ctypes.c_double), _P(ctypes.c_double), ctypes.c_int64,
+                                      _P(ctypes.c_double)]),
     "ddqmc_plan_growth": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                          ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
                                          ctypes.c_uint64, ctypes.c_uint64, _P(ctypes.c_uint64),

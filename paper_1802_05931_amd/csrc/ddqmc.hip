@@ -800,6 +800,10 @@ int run_steps(ddqmc_t *h, int64_t n) {
       if (f & F_INT_OVF) return DDQMC_EOVERFLOW;
       if (f & F_RNG) return DDQMC_ERNG;
       if (f & F_EXTINCT) return DDQMC_EEXTINCT;
+      if (f & F_ORDER) {
+        std::fprintf(stderr, "ddqmc: the merge found the list or the records out of order\n");
+        return DDQMC_EHIP;
+      }
       if (f & (F_SPAWN_CAP | F_MAIN_CAP)) {
         const int rc = regrow(h, (f & F_MAIN_CAP) ? need_main : 0, (f & F_SPAWN_CAP) ? seg_need : 0);
         if (rc != DDQMC_OK) return rc;
@@ -1294,6 +1298,12 @@ int ddqmc_device_bytes(ddqmc_t *h, size_t *bytes, int64_t *capacity) {
   if (!h || !bytes) return DDQMC_EINVAL;
   *bytes = h->fixed_bytes + h->sized_bytes;
   if (capacity) *capacity = (int64_t)h->cap_main;
+  return DDQMC_OK;
+}
+
+int ddqmc_ratio_se(const double *num, const double *den, int64_t n, double *se) {
+  if (!num || !den || !se || n < 0) return DDQMC_EINVAL;
+  *se = ratio_se(std::vector<double>(num, num + n), std::vector<double>(den, den + n));
   return DDQMC_OK;
 }
 

@@ -60,6 +60,7 @@ enum : uint32_t {
   F_INT_OVF = 4u,    // a walker count left int32
   F_EXTINCT = 8u,    // a solve lost all walkers / its diagonal weight
   F_RNG = 16u,       // a random stream ran dry
+  F_ORDER = 64u,     // merge cuts out of order: the list or the records are not sorted
 };
 
 struct Ctrl {
@@ -1070,6 +1071,19 @@ __global__ __launch_bounds__(NT, sizeof(K) == 4 ? 5 : 4) void k_merge(
     if (threadIdx.x == 64) s_i1 = part[t + 1];
     __syncthreads();
     const uint32_t i0 = s_i0, i1 = s_i1, j0 = d0 - i0, j1 = d1 - i1;
+    // the cuts of a sorted list and sorted records are monotone; anything else
+    // (a list whose order was broken) fails the step instead of being read
+    if (i1 < i0 || i1 > na || i0 > d0 || i1 > d1 || j1 < j0 || j1 > nb) {
+      if (threadIdx.x == 0) {
+        atomicOr(&ctrl->flags, F_ORDER);
+        if (WRITE)
+          partials[t].slot = 0;
+        else
+          tile_cnt[t] = 0;
+      }
+      if (WRITE && threadIdx.x < S_NSUM) partials[t].s[threadIdx.x] = 0;  // (finalize reads them)
+      continue;
+    }
     const uint32_t nA = i1 - i0, nB = j1 - j0;
     K *const sAk = sK, *const sBk = sK + nA;
     int2 *const sAv = sV, *const sBv = sV + nA;

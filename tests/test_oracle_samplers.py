@@ -14,13 +14,24 @@ from scipy import stats
 PTHRESH = 1e-4  # reject only on a gross mismatch; seeds are fixed
 
 
-def _chi2_pvalue(samples, pmf_support, pmf):
-    lo, hi = pmf_support
-    ks = np.arange(lo, hi + 1)
-    expected = pmf(ks) * len(samples)
-    counts = np.bincount(samples - lo, minlength=len(ks))[:len(ks)]
-    assert counts.sum() == len(samples), "sample outside the support"
-    # pool bins with small expectation into their neighbours
+def _chi2_pvalue(samples, support, core, pmf, cdf):
+    """Chi-square p-value of integer samples against a law on the full support
+    [support[0], support[1]]: one bin per value of the core range [a, b] (where
+    all but ~1e-10 of the mass lies) and one bin for each tail, whose
+    expectations come from the exact cdf, so that too many (or any impossible)
+    tail values count.  cdf(k) = P(X <= k) of the law itself (normalised on its
+    support).  Bins with small expectation are pooled with their neighbours."""
+    lo, hi = support
+    a, b = max(core[0], lo), min(core[1], hi)
+    x = np.asarray(samples)
+    assert x.min() >= lo and x.max() <= hi, "sample outside the support"
+    ks = np.arange(a, b + 1)
+    expected = np.concatenate([[cdf(a - 1) if a > lo else 0.0], pmf(ks),
+                               [1.0 - cdf(b) if b < hi else 0.0]]) * len(x)
+    counts = np.concatenate([[np.sum(x < a)],
+                             np.bincount(x[(x >= a) & (x <= b)] - a, minlength=len(ks))[:len(ks)],
+                             [np.sum(x > b)]])
+    assert abs(expected.sum() - len(x)) < 1e-6 * len(x), "the law's mass is not 1"
     e_b, c_b = [], []
     e_acc = c_acc = 0.0
     for e, c in zip(expected, counts):
@@ -30,7 +41,7 @@ def _chi2_pvalue(samples, pmf_support, pmf):
             e_b.append(e_acc)
             c_b.append(c_acc)
             e_acc = c_acc = 0.0
-    if e_acc > 0:
+    if e_acc > 0 or c_acc > 0:
         if e_b:
             e_b[-1] += e_acc
             c_b[-1] += c_acc
@@ -45,6 +56,10 @@ def _chi2_pvalue(samples, pmf_support, pmf):
     return stats.chi2.sf(chi2, len(e_b) - 1)
 
 
+def _binom_core(n, p):
+    return int(stats.binom.ppf(1e-10, n, p)), int(stats.binom.isf(1e-10, n, p))
+
+
 BIN_CASES = [(1, 0.3), (3, 0.001), (7, 0.2), (40, 0.2), (200, 0.049), (12, 0.5),
              (30, 0.34), (100, 0.1), (1000, 0.3), (100000, 0.02), (2 ** 31 - 1, 1e-6),
              (25, 0.6), (300, 0.9), (9, 0.999)]
@@ -54,9 +69,8 @@ BIN_CASES = [(1, 0.3), (3, 0.001), (7, 0.2), (40, 0.2), (200, 0.049), (12, 0.5),
 def test_binomial_pmf(orc, n, p):
     x = orc.binom_many(n, p, 0, seed=11, count=150000)
     assert x.min() >= 0 and x.max() <= n
-    lo, hi = int(x.min()), int(x.max())
-    pv = _chi2_pvalue(x, (lo, hi), lambda k: stats.binom.pmf(k, n, p) /
-                      (stats.binom.cdf(hi, n, p) - stats.binom.cdf(lo - 1, n, p)))
+    pv = _chi2_pvalue(x, (0, n), _binom_core(n, p), lambda k: stats.binom.pmf(k, n, p),
+                      lambda k: stats.binom.cdf(k, n, p))
     assert pv > PTHRESH
     # and the mean against n p to ~5 sigma
     assert abs(x.mean() - n * p) <= 5 * np.sqrt(n * p * (1 - p) / len(x)) + 1e-12
@@ -68,8 +82,9 @@ def test_truncated_binomial_pmf(orc, n, p):
     x = orc.binom_many(n, p, 1, seed=12, count=120000)
     assert x.min() >= 1 and x.max() <= n
     z = 1.0 - stats.binom.pmf(0, n, p)
-    hi = int(x.max())
-    pv = _chi2_pvalue(x, (1, hi), lambda k: stats.binom.pmf(k, n, p) / z)
+    a, b = _binom_core(n, p)
+    pv = _chi2_pvalue(x, (1, n), (max(a, 1), max(b, 1)), lambda k: stats.binom.pmf(k, n, p) / z,
+                      lambda k: (stats.binom.cdf(k, n, p) - stats.binom.pmf(0, n, p)) / z)
     assert pv > PTHRESH
 
 
@@ -82,12 +97,27 @@ def test_bsplit_integer_plus_fraction(orc, n, P):
     assert x.min() >= base and x.max() <= base + (n if frac > 0 else 0)
     y = x - base
     if frac > 0:
-        pv = _chi2_pvalue(y, (int(y.min()), int(y.max())),
-                          lambda k: stats.binom.pmf(k, n, frac) /
-                          (stats.binom.cdf(y.max(), n, frac) - stats.binom.cdf(y.min() - 1, n, frac)))
+        pv = _chi2_pvalue(y, (0, n), _binom_core(n, frac), lambda k: stats.binom.pmf(k, n, frac),
+                          lambda k: stats.binom.cdf(k, n, frac))
         assert pv > PTHRESH
     else:
         assert np.all(y == 0)
+
+
+def test_chi2_sees_a_tail_error():
+    """The full-support chi-square has teeth in the tails: a sampler that is
+    right in the core but puts 0.5% of its draws far in the right tail fails,
+    which the former range-normalised test (the pmf renormalised over the
+    observed min..max) could not see."""
+    rng = np.random.default_rng(5)
+    n, p = 1000, 0.3
+    good = rng.binomial(n, p, 150000)
+    core = _binom_core(n, p)
+    law = (lambda k: stats.binom.pmf(k, n, p), lambda k: stats.binom.cdf(k, n, p))
+    assert _chi2_pvalue(good, (0, n), core, *law) > PTHRESH
+    bad = good.copy()
+    bad[:750] = rng.integers(core[1] + 1, core[1] + 40, 750)
+    assert _chi2_pvalue(bad, (0, n), core, *law) < 1e-12
 
 
 def test_binomial_degenerate(orc):
@@ -122,9 +152,9 @@ def test_channel_counts_are_independent_binomials(orc, p, n):
         if frac == 0:
             assert np.all(y == 0)
             continue
-        lo, hi = int(y.min()), int(y.max())
-        pv = _chi2_pvalue(y, (lo, hi), lambda kk: stats.binom.pmf(kk, n[k], frac) /
-                          (stats.binom.cdf(hi, n[k], frac) - stats.binom.cdf(lo - 1, n[k], frac)))
+        pv = _chi2_pvalue(y, (0, n[k]), _binom_core(n[k], frac),
+                          lambda kk: stats.binom.pmf(kk, n[k], frac),
+                          lambda kk: stats.binom.cdf(kk, n[k], frac))
         assert pv > PTHRESH, (k, pv)
     # independence: joint zero pattern of channel pairs against the product law
     zero = X == 0
@@ -166,3 +196,134 @@ def test_no_event_prob_special_cases(orc):
     # one channel: (1 - p)^n by binary powers, 0.75^4 = 0.31640625 exactly
     assert orc.no_event_prob([0.25] + [0.0] * 7, [4] + [0] * 7) == 0.31640625
     assert orc.no_event_prob([0.5] * 4 + [0.0] * 4, [3] * 4 + [9] * 4) == 2.0 ** -12
+
+
+# ---- the joint law of a channel's placement over its connections -------------
+# Sec. III.B: the N_sp walkers a configuration spawns along one part of the
+# Liouvillian are distributed over its connected configurations by a
+# multinomial law whose cell probabilities are proportional to the elements'
+# magnitudes (here with the importance-sampling weights).  The oracle realises
+# it as a class split (sequential conditional binomials), a balanced binary tree
+# of binomials inside a class, and one categorical pick for a single walker.
+# The tests below compare the joint law of the placed counts with the
+# multinomial whose cell probabilities come from the connection elements
+# (orc.connections, pinned against the Kronecker-form Liouvillian), by chi-square
+# over every joint outcome for small counts, and by the means, variances and
+# covariances for a large count (a split with the right means but correlated
+# cells fails the latter).
+
+def _hop_cells(orc, p, l, m):
+    """Cell probabilities of the hop channel over (ket bonds, bra bonds), from the
+    connections' imaginary elements."""
+    N = p.Lx * p.Ly
+    bl = orc.bonds(p.Lx, p.Ly)
+    ck, cb, re, im, _, _ = orc.connections(p, l, m)
+    el = {(int(a), int(b)): abs(v) for a, b, v in zip(ck, cb, im) if v != 0.0}
+    w = []
+    for side in (0, 1):
+        for s1, s2 in bl:
+            mask = (1 << s1) | (1 << s2)
+            child = (l ^ mask, m) if side == 0 else (l, m ^ mask)
+            w.append(el.get(child, 0.0))
+    w = np.array(w)
+    assert len(el) == np.count_nonzero(w) and w.sum() > 0
+    return w / w.sum(), N
+
+
+def _joint_chi2(counts, probs, X):
+    """Chi-square p-value of sampled count vectors against Multinomial(X, probs)
+    over every joint outcome (bins with small expectation pooled)."""
+    keep = probs > 0
+    assert np.all(counts[:, ~keep] == 0), "a walker placed on a zero-weight cell"
+    c = counts[:, keep]
+    pk = probs[keep] / probs[keep].sum()
+    assert np.all(c.sum(axis=1) == X)
+    outcomes, obs = np.unique(c, axis=0, return_counts=True)
+    exp = stats.multinomial.pmf(outcomes, X, pk) * len(c)
+    # outcomes never seen still carry expectation: the missing mass is one bin
+    missing = len(c) - exp.sum()
+    order = np.argsort(exp)
+    e_b, c_b, e_acc, c_acc = [], [], max(missing, 0.0), 0.0
+    for i in order:
+        e_acc += exp[i]
+        c_acc += obs[i]
+        if e_acc >= 20:
+            e_b.append(e_acc)
+            c_b.append(c_acc)
+            e_acc = c_acc = 0.0
+    if e_acc > 0:
+        e_b[-1] += e_acc
+        c_b[-1] += c_acc
+    e_b, c_b = np.array(e_b), np.array(c_b)
+    return stats.chi2.sf(((c_b - e_b) ** 2 / e_b).sum(), len(e_b) - 1)
+
+
+def _moments_check(counts, probs, X, zmax=5.0):
+    """Means X p, variances X p (1 - p) and covariances -X p_i p_j of the counts."""
+    n = len(counts)
+    mean = counts.mean(axis=0)
+    cov = np.cov(counts.T.astype(float))
+    m_exp = X * probs
+    c_exp = X * (np.diag(probs) - np.outer(probs, probs))
+    # standard error of a sample (co)variance ~ sqrt(var_i var_j / n) for large n
+    v = np.maximum(np.diag(c_exp), 1e-300)
+    se_mean = np.sqrt(v / n)
+    se_cov = np.sqrt(np.outer(v, v) * 2.0 / n)
+    live = probs > 0
+    zm = np.abs(mean[live] - m_exp[live]) / se_mean[live]
+    zc = np.abs(cov - c_exp)[np.ix_(live, live)] / se_cov[np.ix_(live, live)]
+    assert zm.max() < zmax, zm.max()
+    assert zc.max() < zmax, zc.max()
+
+
+# (ket, bra) parents on 2x3: an off-diagonal one with a to-diagonal bond (bond
+# (0,1) flipped on either side makes it diagonal: the e^{+p} weight), an
+# off-diagonal one without, and a diagonal one (all classes e^{-p})
+HOP_PARENTS = [(0b000001, 0b000010), (0b000111, 0b000101), (0b010110, 0b010110)]
+
+
+@pytest.mark.parametrize("l,m", HOP_PARENTS)
+@pytest.mark.parametrize("X", [1, 2, 3])
+def test_hop_placement_joint_law(orc, l, m, X):
+    p = orc.make_params(Lx=2, Ly=3, Jx=0.6, Jy=1.0, Jz=1.2, is_p=0.8, seed=21)
+    probs, N = _hop_cells(orc, p, l, m)
+    counts = orc.split_many(p, (l << N) | m, 4, X, 120000)
+    assert _joint_chi2(counts, probs, X) > PTHRESH
+
+
+@pytest.mark.parametrize("l,m", HOP_PARENTS[:2])
+def test_hop_placement_moments_many_walkers(orc, l, m):
+    p = orc.make_params(Lx=2, Ly=3, Jx=0.6, Jy=1.0, Jz=1.2, is_p=0.8, seed=22)
+    probs, N = _hop_cells(orc, p, l, m)
+    for ch, X in ((4, 37), (8, 400)):
+        _moments_check(orc.split_many(p, (l << N) | m, ch, X, 60000), probs, X)
+
+
+@pytest.mark.parametrize("X", [1, 2, 4, 50])
+def test_jump_placement_is_uniform_multinomial(orc, X):
+    """The jump channel: every site where ket and bra are both up equally likely."""
+    p = orc.make_params(Lx=2, Ly=3, seed=23)
+    l, m = 0b110111, 0b011101  # both up on sites 0, 2, 4
+    N = 6
+    probs = np.zeros(N)
+    probs[[0, 2, 4]] = 1.0 / 3.0
+    counts = orc.split_many(p, (l << N) | m, 3 if X % 2 else 7, X, 80000)
+    if X <= 4:
+        assert _joint_chi2(counts, probs, X) > PTHRESH
+    else:
+        _moments_check(counts, probs, X)
+
+
+def test_a_split_with_correlated_cells_is_caught(orc):
+    """The moment check has teeth: counts with the right means but all walkers
+    sent to one cell (perfectly correlated) fail it."""
+    rng = np.random.default_rng(3)
+    probs = np.array([0.2, 0.3, 0.5])
+    X = 20
+    cells = rng.choice(3, size=40000, p=probs)
+    bad = np.zeros((40000, 3), np.int64)
+    bad[np.arange(40000), cells] = X
+    with pytest.raises(AssertionError):
+        _moments_check(bad, probs, X)
+    good = rng.multinomial(X, probs, size=40000)
+    _moments_check(good, probs, X)

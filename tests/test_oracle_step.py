@@ -223,3 +223,75 @@ def test_ness_within_three_standard_errors(orc, Lx, Ly, steps, target, seed):
     S = rows[:, 1].view(np.float64)
     s_mean, s_se, _ = ratio_se(S, np.ones_like(S))
     assert abs(s_mean) < 4 * s_se + 1e-3
+
+
+@pytest.mark.parametrize("Lx,Ly,jx,steps,target,seed", [(2, 2, 0.3, 60000, 3000, 3),
+                                                        (2, 3, 0.6, 20000, 4000, 4)])
+def test_importance_sampled_ness(orc, Lx, Ly, jx, steps, target, seed):
+    """Sec. IV.B: with importance sampling (p = 1.5, off-diagonal configurations
+    carry weight e^{-p} relative to diagonal ones) the sampled population is the
+    weighted density matrix, and the estimators multiply off-diagonal numerators
+    by e^{p}.  At n_a = 0 the estimates must still match the exact steady state:
+    M_z within 3 standard errors, C_xx, C_yy, C_zz within 4; dividing by the
+    weight instead of multiplying would put C_yy e^{-2p} ~ 20x too small, far
+    outside.  The oracle's own ratio function (orc.ratios) is checked against
+    the same arithmetic done here with numpy."""
+    p = 1.5
+    equil = 3000
+    o = orc.Oracle(Lx=Lx, Ly=Ly, Jx=jx, dt=0.01, n_a=0, is_p=p, target_walkers=target,
+                   initial_walkers=100, seed=seed, n_equil=equil)
+    o.step(steps)
+    rows = o.series()
+    rows = rows[rows[:, 0] > equil]
+    col = {n: 3 + i for i, n in enumerate(orc.SUM_NAMES)}
+    ex = exact.observables(exact.ness(Lx, Ly, jx, 1.0, 1.0, 1.0), Lx, Ly)
+    N = Lx * Ly
+    nb = len(exact.bonds(Lx, Ly))
+    w = np.exp(p)
+    den = rows[:, col["t_re"]]
+    mz, se, _ = ratio_se(rows[:, col["z"]] / N, den)
+    assert abs(mz - ex["mz"]) < 3 * se, (mz, ex["mz"], se)
+    got = {}
+    for name, f in (("czz", 1.0), ("cxx", w), ("cyy", w)):
+        v, s2, _ = ratio_se(rows[:, col[name]] * f / nb, den)
+        assert abs(v - ex[name]) < 4 * s2, (name, v, ex[name], s2)
+        got[name] = (v, s2)
+    # the wrong weight (divided instead of multiplied) is rejected by far
+    v, s2 = got["cyy"]
+    assert abs(v / w ** 2 - ex["cyy"]) > 10 * s2
+    # the oracle's ratios of its accumulated sums: the same numbers
+    acc, n_acc = o.acc()
+    assert n_acc == len(rows)
+    r = orc.ratios(acc, N, nb, p)
+    a = dict(zip(orc.SUM_NAMES, acc.tolist()))
+    assert r["mz"] == pytest.approx(a["z"] / (N * a["t_re"]), rel=1e-14)
+    assert r["cyy"] == pytest.approx(a["cyy"] * w / (nb * a["t_re"]), rel=1e-14)
+    assert r["cxx"] == pytest.approx(a["cxx"] * w / (nb * a["t_re"]), rel=1e-14)
+    assert r["czz"] == pytest.approx(a["czz"] / (nb * a["t_re"]), rel=1e-14)
+
+
+def test_shift_update_follows_the_population(orc):
+    """Sec. III.C: once the diagonal weight reaches its target, every step sets
+    S <- S + (delta / dt) ln(N_w(t) / N_w(t - dt)); before that S stays at its
+    start value.  Checked row by row on the step series with numpy's log (the
+    oracle uses its own fixed-order log): a factor delta instead of delta / dt,
+    a wrong sign or a stale N_w all fail."""
+    cfg = dict(workloads.D1, n_equil=0)
+    o = orc.Oracle(**cfg)
+    o.step(4000)
+    rows = o.series()
+    S = rows[:, 1].view(np.float64)
+    mode = rows[:, 2]
+    nw = rows[:, 3 + orc.SUM_NAMES.index("n_w")].astype(np.float64)
+    grow = np.where(mode == 0)[0]
+    vary = np.where(mode == 1)[0]
+    assert len(grow) > 50 and len(vary) > 1000
+    assert np.all(S[grow] == cfg["shift_init"])
+    # the switch: the first row in vary mode is the first whose N_w reached the target
+    first = vary[0]
+    assert nw[first] >= cfg["target_walkers"] and np.all(nw[:first] < cfg["target_walkers"])
+    assert np.all(np.diff(vary) == 1)  # no return to the growth phase
+    k = vary[1:]
+    want = S[k - 1] + (cfg["shift_damping"] / cfg["dt"]) * np.log(nw[k] / nw[k - 1])
+    assert np.allclose(S[k], want, rtol=0, atol=1e-12)
+    assert np.abs(S[k] - S[k - 1]).max() > 1e-3  # the shift does move
