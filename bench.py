@@ -304,10 +304,13 @@ def bench_d5(args, log=_log):
     stream = torch.cuda.current_stream()
     log(f"d5: batched, {len(cfgs)} replicas x {steps} steps")
     gk = args.graph_steps
-    tb, ob, lb = serving.replicas_batched(cfgs, steps, graph_k=gk, stream=stream)
+    from paper_1802_05931_amd import autotune
+    t = None if args.no_tuned else autotune.load_table()
+    rows = [] if t is None else t["rows"].get("k8", [])  # 5x5: 50-bit keys, alone or batched
+    tb, ob, lb = serving.replicas_batched(cfgs, steps, graph_k=gk, stream=stream, tile_rows=rows)
     log(f"d5: batched {tb:.2f} s; sequential")
     ts, os_, ls = serving.replicas_sequential(
-        cfgs, steps, graph_k=gk, stream=stream, log=lambda m: log(f"d5: {m}"))
+        cfgs, steps, graph_k=gk, stream=stream, log=lambda m: log(f"d5: {m}"), tile_rows=rows)
     log(f"d5: sequential {ts:.2f} s")
     same = all(len(a[0]) == len(c[0]) and all(np.array_equal(x, y) for x, y in zip(a, c))
                for a, c in zip(lb, ls))
@@ -324,7 +327,7 @@ def bench_d5(args, log=_log):
         "config": {"workload": "64 replicas of the 5x5 dissipative XYZ model, Jx 0.5..1.2, "
                                "dt 0.002, n_a 3, p 0, targets log-uniform in [1e3, 2e4], "
                                "u64 keys",
-                   "graph_steps": gk, "final_entries": entries},
+                   "graph_steps": gk, "final_entries": entries, "tile_table": rows},
         "sequential": {"seconds": ts, "value": len(cfgs) * (steps - 1) / ts},
         "batched_seconds": tb,
         "speedup_vs_sequential": ts / tb,
@@ -420,6 +423,8 @@ def bench_d3(args, log=_log):
         # room for the loaded list to grow without a reallocation (16 bytes an entry)
         cfg = dict(cfg, capacity_hint=2 * (len(blob) // 16))
     g = dq.Solve(dq.make_params(**cfg), stream=stream)
+    from paper_1802_05931_amd import autotune
+    tile_rows = [] if args.no_tuned else autotune.apply(g, autotune.key_bytes(cfg["Lx"] * cfg["Ly"]))
     if blob is not None:
         g.set_state(blob)
         del blob
@@ -557,7 +562,8 @@ def bench_d3(args, log=_log):
                    "mean_walkers": float(w_start.mean()),
                    "mean_spawn_records": live["mean_spawn_records"],
                    "mean_loud_entries": float(c[:, 3].mean()),
-                   "mean_heavy_entries": float(c[:, 4].mean())},
+                   "mean_heavy_entries": float(c[:, 4].mean()),
+                   "tile_table": tile_rows, "tiles_in_use": list(g.tiles())},
         "entry_updates_per_s": float(n_in.sum()) / wall,
         "bytes_per_walker_update": b_alg / walker_updates,
         "roofline": roofline,
@@ -572,13 +578,60 @@ def bench_d3(args, log=_log):
     return out, g, cfg
 
 
+def bench_tune(args, log=_log):
+    """Tile-shape tuning (ddqmc_set_tiles): every shape timed on the 4x4
+    workload's steady list, on smaller 4x4 and 3x3 lists, and on the 64-replica
+    5x5 batch; the table goes to --tune-out (default the package's
+    tuned_tiles.json)."""
+    import torch
+
+    import paper_1802_05931_amd as dq
+    from paper_1802_05931_amd import autotune
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    runs = []
+
+    def one(label, g, kb):
+        r = autotune.tune(g, kb, label)
+        log(f"tune {label}: {r['n_entries']} entries, best {r['sort_it']}x{r['merge_it']}: "
+            f"{r['ms']}")
+        runs.append(r)
+
+    # 3x3 at its target of 1e5 walkers, and a 4x4 list of about 1e6 entries
+    g = dq.Solve(dq.make_params(**workloads.d2(0.6)), stream=stream)
+    g.step(3000)
+    one("3x3 Jx 0.6, target 1e5", g, 4)
+    g.close()
+    g = dq.Solve(dq.make_params(**dict(workloads.D3, target_walkers=1_000_000,
+                                       initial_walkers=1_000_000)), stream=stream)
+    g.step(6000)
+    one("4x4 target 1e6", g, 4)
+    g.close()
+    # the headline 4x4 list (steady, about 1.07e7 entries)
+    g = dq.Solve(dq.make_params(**workloads.D3), stream=stream)
+    equilibrate(g, log)
+    one("4x4 target 1e7 (steady)", g, 4)
+    g.close()
+    # the 64-replica 5x5 batch after 250 of its 300 steps
+    b = dq.Batch([dq.make_params(**c) for c in workloads.d5_replicas()], stream=stream)
+    b.step(250)
+    one("64 x 5x5 batch", b, 8)
+    b.close()
+    out = autotune.write_table(runs, args.tune_out or autotune.TABLE)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20,
                     help="steps after the equilibration, before the timed steps")
-    ap.add_argument("--workload", default="d3", choices=sorted(WORKLOADS) + ["d4", "d5"])
+    ap.add_argument("--workload", default="d3", choices=sorted(WORKLOADS) + ["d4", "d5", "tune"])
+    ap.add_argument("--tune-out", metavar="FILE",
+                    help="tune: where the tile table goes (default the package's table)")
+    ap.add_argument("--no-tuned", action="store_true",
+                    help="keep the default tile shapes instead of the tuned table")
     ap.add_argument("--legs", default="d3,d5,d4",
                     help="default line: the plain step (d3) and the batched (d5) and served "
                          "(d4) legs beside it")
@@ -628,6 +681,9 @@ def main():
 
     import torch
 
+    if args.workload == "tune":
+        bench_tune(args)
+        return
     if args.workload == "d5":
         print(json.dumps(bench_d5(args)), flush=True)
         return

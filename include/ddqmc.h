@@ -273,6 +273,21 @@ int ddqmc_set_tree_queue(ddqmc_t *h, int32_t places);
  * 2: always a block per chunk.  The results are the same either way.  EINVAL
  * for other modes. */
 int ddqmc_set_loud_grid(ddqmc_t *h, int32_t mode);
+/* Tile shapes of the annihilation stage (Sec. III.C rule (iii)): records per
+ * thread of a radix-sort tile (sort_it: 4, 8 or 16; a tile is 256 sort_it
+ * records) and merged positions per thread of a merge-path tile (merge_it: 4
+ * or 8).  Default 8 and 8.  The results are the same for every shape.
+ * ddqmc_set_tiles: one shape for every step (it clears a table).
+ * ddqmc_set_tile_table: rows (min_entries ascending, strictly; shapes as
+ *   above): before each chunk of steps the handle takes the shape of the last
+ *   row whose min_entries is at most its current list size (the first row
+ *   below all of them).  rows = 0 clears the table.  Written by the tuner,
+ *   which times every shape per key width and list-size bucket.
+ * ddqmc_get_tiles: the shape in use.  EINVAL for other values. */
+int ddqmc_set_tiles(ddqmc_t *h, int32_t sort_it, int32_t merge_it);
+int ddqmc_set_tile_table(ddqmc_t *h, int32_t rows, const int64_t *min_entries,
+                         const int32_t *sort_it, const int32_t *merge_it);
+int ddqmc_get_tiles(ddqmc_t *h, int32_t *sort_it, int32_t *merge_it);
 int ddqmc_stage_times(ddqmc_t *h, double ms[10], int64_t *steps);
 
 /* ---- device self-checks of the sampling primitives --------------------------

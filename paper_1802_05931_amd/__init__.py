@@ -135,6 +135,29 @@ class _Handle:
         per chunk of entries (same results either way)."""
         check(lib().ddqmc_set_loud_grid(self._h, int(mode)), "set_loud_grid")
 
+    def set_tiles(self, sort_it, merge_it):
+        """Sort tile: sort_it records per thread (4, 8, 16); merge tile: merge_it
+        merged positions per thread (4, 8).  Clears a tile table."""
+        check(lib().ddqmc_set_tiles(self._h, int(sort_it), int(merge_it)), "set_tiles")
+
+    def set_tile_table(self, rows):
+        """rows: [(min_entries, sort_it, merge_it), ...] ascending in min_entries;
+        before each chunk of steps the shape of the last row at or below the
+        list size is used.  [] clears it."""
+        n = len(rows)
+        me = np.array([r[0] for r in rows], np.int64)
+        si = np.array([r[1] for r in rows], np.int32)
+        mi = np.array([r[2] for r in rows], np.int32)
+        check(lib().ddqmc_set_tile_table(self._h, n, ptr(me, ctypes.c_int64),
+                                         ptr(si, ctypes.c_int32), ptr(mi, ctypes.c_int32)),
+              "set_tile_table")
+
+    def tiles(self):
+        """(sort_it, merge_it) in use."""
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().ddqmc_get_tiles(self._h, ctypes.byref(a), ctypes.byref(b)), "get_tiles")
+        return a.value, b.value
+
     def device_bytes(self):
         """(device bytes the handle holds, its list capacity in entries)."""
         n = ctypes.c_size_t()

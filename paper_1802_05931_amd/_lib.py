@@ -113,6 +113,10 @@ SIGNATURES = {
     "ddqmc_set_tree_queue": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "ddqmc_set_loud_grid": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "ddqmc_stage_times": (ctypes.c_int, [_vp, _P(ctypes.c_double), _P(ctypes.c_int64)]),
+    "ddqmc_set_tiles": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
+    "ddqmc_set_tile_table": (ctypes.c_int, [_vp, ctypes.c_int32, _P(ctypes.c_int64),
+                                            _P(ctypes.c_int32), _P(ctypes.c_int32)]),
+    "ddqmc_get_tiles": (ctypes.c_int, [_vp, _P(ctypes.c_int32), _P(ctypes.c_int32)]),
     "ddqmc_dev_uniforms": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
                                           ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64,
                                           _P(ctypes.c_double)]),

@@ -124,6 +124,14 @@ struct ddqmc_t {
   bool loud_dyn = false;    // loud kernel: resident blocks and a chunk counter (else a
                             // block per chunk); chosen per chunk of steps, see run_steps
   int loud_grid = 0;        // 0 chosen per chunk of steps, 1 resident, 2 block per chunk
+  // tile shapes (records / merged positions per thread) of the sort and the
+  // merge, and an optional table choosing them by list size before each chunk
+  int sort_it = SORT_IT_DEFAULT, merge_it = MERGE_IT_DEFAULT;
+  struct TileRow {
+    int64_t min_entries;
+    int sort_it, merge_it;
+  };
+  std::vector<TileRow> tile_table;
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   uint64_t gexec_gen[2] = {~0ull, ~0ull};
   int gexec_k[2] = {0, 0};
@@ -152,8 +160,9 @@ int hip_err(hipError_t e) {
 
 size_t key_size(const ddqmc_t *h) { return h->k64 ? 8 : 4; }
 
-uint64_t sort_tiles(uint64_t cap) { return (cap + SORT_TILE - 1) / SORT_TILE; }
-uint64_t merge_tiles(uint64_t a, uint64_t b) { return (a + b + MERGE_TILE - 1) / MERGE_TILE; }
+// (the tile arrays are laid out for the smallest tiles, so every shape fits)
+uint64_t sort_tiles(uint64_t cap) { return (cap + MIN_SORT_TILE - 1) / MIN_SORT_TILE; }
+uint64_t merge_tiles(uint64_t a, uint64_t b) { return (a + b + MIN_MERGE_TILE - 1) / MIN_MERGE_TILE; }
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Byte offsets of the fixed arena's buffers (each 256-byte aligned).
@@ -515,8 +524,9 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
   const uint32_t g_loud = h->loud_dyn ? clampu(h->nscan, 1, h->loud_blocks)
                                       : clampu((h->cap_main + NT - 1) / NT, 1, 8 * h->loud_blocks);
   const uint32_t g_heavy = h->heavy_blocks;
-  const uint32_t g_s = clampu(sort_tiles(h->cap_sp), 1, 1u << 24);
-  const uint32_t g_m = clampu(merge_tiles(h->cap_main, h->cap_sp), 1, 1u << 20);
+  const uint32_t sort_tile = (uint32_t)(NT * h->sort_it), merge_tile = (uint32_t)(NT * h->merge_it);
+  const uint32_t g_s = clampu((h->cap_sp + sort_tile - 1) / sort_tile, 1, 1u << 24);
+  const uint32_t g_m = clampu((h->cap_main + h->cap_sp + merge_tile - 1) / merge_tile, 1, 1u << 20);
   if (ev) HIPC(hipEventRecord(ev->e[0], s));
   k_spawn_scan<K><<<h->nscan, NT, 0, s>>>(ak, av, h->ctrl, h->dsp, h->dss, h->lidx,
                                          (K *)h->lkey, h->lval, h->heavy, h->SB);
@@ -565,33 +575,64 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
     int2 *ov = h->sv[(p + 1) & 1];
     uint32_t *tcnt = h->sort_cnt;
     const uint32_t sc = p == 0 ? segcap : 0u;
-    k_sort_count<K><<<g_s, NT, 0, s>>>(ik, h->ctrl, tcnt, p, sc, h->segcnt);
-    k_sort_rowscan<<<256, NT, 0, s>>>(h->ctrl, tcnt, h->hist, p);
-    k_sort_pass<K><<<g_s, NT, 0, s>>>(ik, iv, ok, ov, h->ctrl, h->hist, tcnt, p, sc);
+    switch (h->sort_it) {
+      case 4:
+        k_sort_count<K, 4><<<g_s, NT, 0, s>>>(ik, h->ctrl, tcnt, p, sc, h->segcnt);
+        break;
+      case 16:
+        k_sort_count<K, 16><<<g_s, NT, 0, s>>>(ik, h->ctrl, tcnt, p, sc, h->segcnt);
+        break;
+      default:
+        k_sort_count<K, 8><<<g_s, NT, 0, s>>>(ik, h->ctrl, tcnt, p, sc, h->segcnt);
+    }
+    k_sort_rowscan<<<256, NT, 0, s>>>(h->ctrl, tcnt, h->hist, p, sort_tile);
+    switch (h->sort_it) {
+      case 4:
+        k_sort_pass<K, 4><<<g_s, NT, 0, s>>>(ik, iv, ok, ov, h->ctrl, h->hist, tcnt, p, sc);
+        break;
+      case 16:
+        k_sort_pass<K, 16><<<g_s, NT, 0, s>>>(ik, iv, ok, ov, h->ctrl, h->hist, tcnt, p, sc);
+        break;
+      default:
+        k_sort_pass<K, 8><<<g_s, NT, 0, s>>>(ik, iv, ok, ov, h->ctrl, h->hist, tcnt, p, sc);
+    }
   }
   {
     // the merge-path partition is timed with the sort stage, so that the merge
     // stage is the merge kernel alone
     const int spb = h->passes & 1;
-    const uint32_t g_p = clampu((merge_tiles(h->cap_main, h->cap_sp) + NT) / NT, 1, 1024);
-    k_merge_partition<K><<<g_p, NT, 0, s>>>(ak, (const K *)h->sk[spb], h->ctrl, h->part);
+    const uint32_t g_p = clampu((g_m + NT) / NT, 1, 1024);
+    k_merge_partition<K><<<g_p, NT, 0, s>>>(ak, (const K *)h->sk[spb], h->ctrl, h->part,
+                                            merge_tile);
   }
   if (ev) HIPC(hipEventRecord(ev->e[7], s));
   {
     const int sp = h->passes & 1;
     const K *bk = (const K *)h->sk[sp];
     const int2 *bv = h->sv[sp];
-    k_merge<K, false><<<g_m, NT, 0, s>>>(ak, av, bk, bv, ck, cv, capC, h->ctrl, h->dsp, h->dss,
-                                         h->partials, h->spill, h->tile_cnt, h->part, h->SB);
-    k_merge_offsets<<<1, 1024, 0, s>>>(h->ctrl, h->tile_cnt);
+    if (h->merge_it == 4)
+      k_merge<K, false, 4><<<g_m, NT, 0, s>>>(ak, av, bk, bv, ck, cv, capC, h->ctrl, h->dsp,
+                                              h->dss, h->partials, h->spill, h->tile_cnt, h->part,
+                                              h->SB);
+    else
+      k_merge<K, false, 8><<<g_m, NT, 0, s>>>(ak, av, bk, bv, ck, cv, capC, h->ctrl, h->dsp,
+                                              h->dss, h->partials, h->spill, h->tile_cnt, h->part,
+                                              h->SB);
+    k_merge_offsets<<<1, 1024, 0, s>>>(h->ctrl, h->tile_cnt, merge_tile);
     if (ev) HIPC(hipEventRecord(ev->e[8], s));
-    k_merge<K, true><<<g_m, NT, 0, s>>>(ak, av, bk, bv, ck, cv, capC, h->ctrl, h->dsp, h->dss,
-                                        h->partials, h->spill, h->tile_cnt, h->part, h->SB);
+    if (h->merge_it == 4)
+      k_merge<K, true, 4><<<g_m, NT, 0, s>>>(ak, av, bk, bv, ck, cv, capC, h->ctrl, h->dsp,
+                                             h->dss, h->partials, h->spill, h->tile_cnt, h->part,
+                                             h->SB);
+    else
+      k_merge<K, true, 8><<<g_m, NT, 0, s>>>(ak, av, bk, bv, ck, cv, capC, h->ctrl, h->dsp,
+                                             h->dss, h->partials, h->spill, h->tile_cnt, h->part,
+                                             h->SB);
   }
   if (ev) HIPC(hipEventRecord(ev->e[9], s));
   k_finalize<<<1, 1024, 0, s>>>(h->ctrl, h->dsp, h->dss, h->partials, h->spill, h->nslots,
                                 h->hist, h->passes, capC, h->segcnt, h->series, h->counts,
-                                SERIES_CAP);
+                                SERIES_CAP, merge_tile);
   if (ev) HIPC(hipEventRecord(ev->e[10], s));
   HIPC(hipGetLastError());
   return DDQMC_OK;
@@ -714,6 +755,17 @@ int run_steps(ddqmc_t *h, int64_t n) {
     if (use_graph && chunk >= (uint32_t)h->graph_k) {
       reps = chunk / (uint32_t)h->graph_k;
       chunk = reps * (uint32_t)h->graph_k;
+    }
+    if (!h->tile_table.empty()) {
+      // the tuned shapes for the list size the chunk starts from
+      const ddqmc_t::TileRow *row = &h->tile_table[0];
+      for (const auto &r : h->tile_table)
+        if ((int64_t)h->n_main_known >= r.min_entries) row = &r;
+      if (row->sort_it != h->sort_it || row->merge_it != h->merge_it) {
+        h->sort_it = row->sort_it;
+        h->merge_it = row->merge_it;
+        h->buf_gen += 1;  // captured graphs hold the other kernels
+      }
     }
     k_chunk_begin<<<1, 1, 0, h->stream>>>(h->ctrl);
     if (reps) {
@@ -1353,6 +1405,41 @@ int ddqmc_set_loud_grid(ddqmc_t *h, int32_t mode) {
     h->loud_dyn = dyn;
     h->buf_gen += 1;  // captured graphs hold the other grid
   }
+  return DDQMC_OK;
+}
+
+int ddqmc_set_tiles(ddqmc_t *h, int32_t sort_it, int32_t merge_it) {
+  if (!h || (sort_it != 4 && sort_it != 8 && sort_it != 16) || (merge_it != 4 && merge_it != 8))
+    return DDQMC_EINVAL;
+  h->tile_table.clear();
+  if (sort_it != h->sort_it || merge_it != h->merge_it) {
+    h->sort_it = sort_it;
+    h->merge_it = merge_it;
+    h->buf_gen += 1;  // captured graphs hold the other kernels
+  }
+  return DDQMC_OK;
+}
+
+int ddqmc_set_tile_table(ddqmc_t *h, int32_t rows, const int64_t *min_entries,
+                         const int32_t *sort_it, const int32_t *merge_it) {
+  if (!h || rows < 0 || rows > 64 || (rows > 0 && (!min_entries || !sort_it || !merge_it)))
+    return DDQMC_EINVAL;
+  std::vector<ddqmc_t::TileRow> t;
+  for (int i = 0; i < rows; ++i) {
+    if ((sort_it[i] != 4 && sort_it[i] != 8 && sort_it[i] != 16) ||
+        (merge_it[i] != 4 && merge_it[i] != 8) || min_entries[i] < 0 ||
+        (i > 0 && min_entries[i] <= min_entries[i - 1]))
+      return DDQMC_EINVAL;
+    t.push_back({min_entries[i], sort_it[i], merge_it[i]});
+  }
+  h->tile_table.swap(t);
+  return DDQMC_OK;
+}
+
+int ddqmc_get_tiles(ddqmc_t *h, int32_t *sort_it, int32_t *merge_it) {
+  if (!h || !sort_it || !merge_it) return DDQMC_EINVAL;
+  *sort_it = h->sort_it;
+  *merge_it = h->merge_it;
   return DDQMC_OK;
 }
 

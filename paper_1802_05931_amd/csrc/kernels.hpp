@@ -35,10 +35,13 @@
 namespace ddqmc {
 
 constexpr int NT = 256;              // threads per block
-constexpr int SORT_IT = 8;           // records per thread in a sort tile
-constexpr int SORT_TILE = NT * SORT_IT;
-constexpr int MERGE_IT = 8;          // merged positions per thread
-constexpr int MERGE_TILE = NT * MERGE_IT;
+// Tile shapes are compiled for a few sizes and chosen per handle (and per list
+// size, from the tuner's table): records per thread in a sort tile, merged
+// positions per thread in a merge tile.  Buffers are laid out for the smallest.
+constexpr int SORT_IT_MIN = 4, SORT_IT_DEFAULT = 8;   // 4, 8 or 16
+constexpr int MERGE_IT_MIN = 4, MERGE_IT_DEFAULT = 8; // 4 or 8
+constexpr int MIN_SORT_TILE = NT * SORT_IT_MIN;
+constexpr int MIN_MERGE_TILE = NT * MERGE_IT_MIN;
 constexpr int STAGE = 2048;          // spawn records staged in LDS per block iteration
 // member trees queued per loud chunk (an entry finding no room takes the
 // general path): as many as keep three loud blocks per CU in LDS
@@ -776,7 +779,7 @@ __global__ void k_inject(const K *__restrict__ ik, const int2 *__restrict__ iv, 
 // the digit, from the totals) + (its row prefix).
 // No tile waits on another.  Pass 0 reads the segmented spawn buffer
 // (segcap > 0), later passes read a contiguous array (segcap == 0).
-template <typename K>
+template <typename K, int SORT_IT>
 __global__ __launch_bounds__(NT) void k_sort_count(const K *__restrict__ ik, Ctrl *ctrl,
                                                    uint32_t *__restrict__ cnt, int pass,
                                                    uint32_t segcap,
@@ -821,6 +824,7 @@ __global__ __launch_bounds__(NT) void k_sort_count(const K *__restrict__ ik, Ctr
     if (threadIdx.x <= NSEG) pre[threadIdx.x] = ctrl->seg_prefix[threadIdx.x];
   }
   __syncthreads();
+  constexpr uint32_t SORT_TILE = NT * SORT_IT;
   const uint32_t n = pre[NSEG];
   const uint32_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
   const uint32_t t = blockIdx.x;
@@ -848,10 +852,10 @@ __global__ __launch_bounds__(NT) void k_sort_count(const K *__restrict__ ik, Ctr
 // the row's total (the digit's count over all records) goes to
 // hist[pass * 256 + digit].
 __global__ __launch_bounds__(NT) void k_sort_rowscan(Ctrl *ctrl, uint32_t *cnt, uint32_t *hist,
-                                                     int pass) {
+                                                     int pass, uint32_t sort_tile) {
   if (ctrl->abort || (ctrl->flags & F_SPAWN_CAP)) return;
   const uint32_t n = ctrl->n_spawn;
-  const uint32_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
+  const uint32_t ntiles = (n + sort_tile - 1) / sort_tile;
   if (ntiles == 0) {
     if (threadIdx.x == 0) hist[pass * 256 + blockIdx.x] = 0;
     return;
@@ -873,7 +877,7 @@ __global__ __launch_bounds__(NT) void k_sort_rowscan(Ctrl *ctrl, uint32_t *cnt, 
   if (threadIdx.x == 0) hist[pass * 256 + blockIdx.x] = tot;
 }
 
-template <typename K>
+template <typename K, int SORT_IT>
 __global__ __launch_bounds__(NT) void k_sort_pass(const K *__restrict__ ik,
                                                   const int2 *__restrict__ iv,
                                                   K *__restrict__ okk, int2 *__restrict__ ov,
@@ -881,6 +885,7 @@ __global__ __launch_bounds__(NT) void k_sort_pass(const K *__restrict__ ik,
                                                   const uint32_t *__restrict__ cnt, int pass,
                                                   uint32_t segcap) {
   if (ctrl->abort || (ctrl->flags & F_SPAWN_CAP)) return;
+  constexpr uint32_t SORT_TILE = NT * SORT_IT;
   const uint32_t n = ctrl->n_spawn;
   if (n == 0) return;
   const uint32_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
@@ -1005,13 +1010,14 @@ __device__ __forceinline__ void run_add(RunSum &s, int2 v) {
 template <typename K>
 __global__ __launch_bounds__(NT) void k_merge_partition(const K *__restrict__ Ak,
                                                         const K *__restrict__ Bk, Ctrl *ctrl,
-                                                        uint32_t *__restrict__ part) {
+                                                        uint32_t *__restrict__ part,
+                                                        uint32_t merge_tile) {
   if (ctrl->abort || (ctrl->flags & F_SPAWN_CAP)) return;
   const uint32_t na = ctrl->n_main, nb = ctrl->n_spawn;
   const uint32_t total = na + nb;
-  const uint32_t ntiles = (total + MERGE_TILE - 1) / MERGE_TILE;
+  const uint32_t ntiles = (total + merge_tile - 1) / merge_tile;
   for (uint32_t t = blockIdx.x * NT + threadIdx.x; t <= ntiles; t += gridDim.x * NT) {
-    const uint32_t d = t * MERGE_TILE < total ? t * MERGE_TILE : total;
+    const uint32_t d = t * merge_tile < total ? t * merge_tile : total;
     part[t] = merge_path(Ak, na, Bk, nb, d);
   }
 }
@@ -1036,14 +1042,15 @@ __global__ __launch_bounds__(NT) void k_merge_partition(const K *__restrict__ Ak
 // Tiles per CU: with 32-bit keys a tile's LDS is 27 KB and five fit; the
 // bound holds the write pass to 96 VGPRs (without it, 101: four tiles).  With
 // 64-bit keys the LDS (35 KB) allows four.
-template <typename K, bool WRITE>
-__global__ __launch_bounds__(NT, sizeof(K) == 4 ? 5 : 4) void k_merge(
+template <typename K, bool WRITE, int MERGE_IT>
+__global__ __launch_bounds__(NT, sizeof(K) == 4 ? (MERGE_IT == 4 ? 8 : 5) : (MERGE_IT == 4 ? 6 : 4)) void k_merge(
     const K *__restrict__ Ak, const int2 *__restrict__ Av, const K *__restrict__ Bk,
     const int2 *__restrict__ Bv, K *__restrict__ Ck, int2 *__restrict__ Cv, uint32_t capC,
     Ctrl *ctrl, const SlotParams *__restrict__ sp, const SlotState *__restrict__ ss,
     Partial *__restrict__ partials, unsigned long long *__restrict__ spill,
     uint32_t *__restrict__ tile_cnt, const uint32_t *__restrict__ part, int SB) {
   if (ctrl->abort || (ctrl->flags & F_SPAWN_CAP)) return;
+  constexpr uint32_t MERGE_TILE = NT * MERGE_IT;
   const uint32_t na = ctrl->n_main;
   const uint32_t nb = ctrl->n_spawn;
   const uint32_t total = na + nb;
@@ -1307,11 +1314,12 @@ __global__ __launch_bounds__(NT, sizeof(K) == 4 ? 5 : 4) void k_merge(
 
 // Output offsets of the merge tiles, in place: cnt[t] <- survivors of tiles
 // < t; the new list size goes to ctrl->n_new.  One block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_merge_offsets(Ctrl *ctrl, uint32_t *cnt) {
+__global__ __launch_bounds__(1024) void k_merge_offsets(Ctrl *ctrl, uint32_t *cnt,
+                                                       uint32_t merge_tile) {
   if (ctrl->abort || (ctrl->flags & F_SPAWN_CAP)) return;
   __shared__ uint32_t wsum[16];
   const uint32_t total = ctrl->n_main + ctrl->n_spawn;
-  const uint32_t n = (total + MERGE_TILE - 1) / MERGE_TILE;
+  const uint32_t n = (total + merge_tile - 1) / merge_tile;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const uint32_t per = (n + 1023) / 1024;
   const uint32_t b0 = tid * per < n ? tid * per : n;
@@ -1338,7 +1346,8 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctrl *ctrl, const SlotParams 
                                                    unsigned long long *spill, int nslots,
                                                    uint32_t *hist, int passes, uint32_t capC,
                                                    unsigned long long *segcnt, int64_t *series,
-                                                   uint32_t *counts, uint32_t series_cap) {
+                                                   uint32_t *counts, uint32_t series_cap,
+                                                   uint32_t merge_tile) {
   if (ctrl->abort) return;
   __shared__ unsigned long long sums[MAX_SLOTS * S_NSUM];
   __shared__ uint32_t s_bad;
@@ -1358,7 +1367,7 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctrl *ctrl, const SlotParams 
   if (tid == 0) s_bad = 0;
   __syncthreads();
   const uint32_t total = ctrl->n_main + ctrl->n_spawn;
-  const uint32_t ntiles = (total + MERGE_TILE - 1) / MERGE_TILE;
+  const uint32_t ntiles = (total + merge_tile - 1) / merge_tile;
   {
     // tiles strided over the threads (coalesced reads); a thread's sums go to
     // LDS whenever its solve changes, and at the end a wave whose lanes all

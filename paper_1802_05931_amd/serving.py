@@ -161,11 +161,14 @@ def solve_alone(params, steps, tick=50, graph_k=0, stream=None):
     return dt, obs
 
 
-def replicas_batched(cfgs, steps, graph_k=0, stream=None):
-    """All replicas in one batch handle: (seconds, list of observables)."""
+def replicas_batched(cfgs, steps, graph_k=0, stream=None, tile_rows=None):
+    """All replicas in one batch handle: (seconds, list of observables).
+    tile_rows: a tuned tile table (rows (min_entries, sort_it, merge_it))."""
     b = Batch([make_params(**c) for c in cfgs], stream=stream)
     if graph_k:
         b.set_graph_steps(graph_k)
+    if tile_rows:
+        b.set_tile_table([tuple(r) for r in tile_rows])
     b.step(1)  # buffers sized, graphs not yet captured: excluded from the timing
     t0 = time.perf_counter()
     b.step(steps - 1)
@@ -177,7 +180,8 @@ def replicas_batched(cfgs, steps, graph_k=0, stream=None):
     return dt, obs, lists
 
 
-def replicas_sequential(cfgs, steps, graph_k=0, stream=None, keep_lists=True, log=None):
+def replicas_sequential(cfgs, steps, graph_k=0, stream=None, keep_lists=True, log=None,
+                        tile_rows=None):
     """The same replicas one after another, each on its own handle."""
     total = 0.0
     obs, lists = [], []
@@ -185,6 +189,8 @@ def replicas_sequential(cfgs, steps, graph_k=0, stream=None, keep_lists=True, lo
         g = Solve(make_params(**c), stream=stream)
         if graph_k:
             g.set_graph_steps(graph_k)
+        if tile_rows:
+            g.set_tile_table([tuple(r) for r in tile_rows])
         g.step(1)
         t0 = time.perf_counter()
         g.step(steps - 1)

@@ -543,3 +543,54 @@ def test_d5_replicas_batch_equals_oracle(dq, orc):
     for j, o in enumerate(orcs):
         assert np.array_equal(b.series(j), o.series())
     b.close()
+
+
+@pytest.mark.parametrize("sort_it,merge_it", [(4, 4), (4, 8), (8, 4), (16, 4), (16, 8)])
+def test_tile_shapes_equal_the_oracle(dq, orc, sort_it, merge_it):
+    """Every sort / merge tile shape the tuner may choose gives the oracle's lists
+    (3x3 over several tiles; one step of a 5x5 list with 64-bit keys)."""
+    cfg = dict(workloads.d2(0.6), target_walkers=20000, n_equil=100)
+    g = dq.Solve(dq.make_params(**cfg))
+    g.set_tiles(sort_it, merge_it)
+    assert g.tiles() == (sort_it, merge_it)
+    o = orc.Oracle(**cfg)
+    for _ in range(2):
+        g.step(250)
+        o.step(250)
+        assert _same_list(g.walkers(), o.get_list())
+        assert g.scalars() == o.scalars()
+    assert np.array_equal(g.series(), o.series())
+    g.close()
+    keys, re, im = workloads.random_list(5, 5, 30000, 40, seed=31)
+    c5 = dict(Lx=5, Ly=5, Jx=0.6, Jy=1.0, Jz=1.2, gamma=1.0, dt=0.01, n_a=3, is_p=0.5,
+              target_walkers=2 ** 62, seed=78)
+    g = dq.Solve(dq.make_params(**c5))
+    g.set_tiles(sort_it, merge_it)
+    o = orc.Oracle(**c5)
+    g.set_walkers(keys, re, im)
+    g.set_scalars(0.1, 1, 7, 10 ** 6)
+    o.set_list(keys, re, im)
+    o.set_scalars(0.1, 1, 7, 10 ** 6)
+    g.step(1)
+    o.step(1)
+    assert _same_list(g.walkers(), o.get_list())
+    g.close()
+
+
+def test_tile_table_switches_shapes(dq, orc):
+    """A tile table changes the shape as the list grows (between chunks of
+    steps, with 10-step graphs re-captured for each shape): the oracle's lists."""
+    cfg = dict(workloads.d2(0.6), target_walkers=20000, n_equil=60, capacity_hint=16)
+    g = dq.Solve(dq.make_params(**cfg))
+    g.set_graph_steps(10)
+    g.set_tile_table([(0, 16, 4), (500, 4, 8), (3000, 8, 4)])
+    o = orc.Oracle(**{k: v for k, v in cfg.items() if k != "capacity_hint"})
+    seen = set()
+    for _ in range(8):
+        g.step(60)
+        o.step(60)
+        seen.add(g.tiles())
+        assert _same_list(g.walkers(), o.get_list())
+    assert len(seen) >= 2, seen
+    assert g.scalars() == o.scalars()
+    g.close()
