@@ -67,11 +67,19 @@ WORKLOADS = {
     "d3": (dict(workloads.D3),
            "4x4 periodic dissipative XYZ, Jx 0.9 Jy 1 Jz 1 gamma 1, dt 0.002, n_a 3, "
            "IS p 1.5, 1e7 walkers"),
-    # same physics, population raised so the walker list outgrows the 256 MB
-    # last-level cache
-    "d3l": (dict(workloads.D3, target_walkers=400_000_000, initial_walkers=400_000_000),
+    # same physics and population without importance sampling: the list holds
+    # about ten times as many configurations (the occupancy census: 1.06e7 at
+    # 1e6 walkers against 6.1e6 with p 1.5), over 1 GB, so it outgrows the
+    # 256 MB last-level cache
+    # no initiator: the list grows without a steady size (past 2e8 entries
+    # within ~750 steps at 1e6 walkers); timed as it passes 1e8 entries
+    # (1.2 GB of list), far beyond the 256 MB last-level cache
+    "d3big": (dict(workloads.D3, n_a=0),
+              "4x4 periodic dissipative XYZ, Jx 0.9 Jy 1 Jz 1 gamma 1, dt 0.002, no initiator, "
+              "IS p 1.5, 1e7 walkers, timed as its growing list passes 1e8 entries"),
+    "d3l": (dict(workloads.D3, is_p=0.0),
             "4x4 periodic dissipative XYZ, Jx 0.9 Jy 1 Jz 1 gamma 1, dt 0.002, n_a 3, "
-            "IS p 1.5, 4e8 walkers"),
+            "no IS, 1e7 walkers"),
 }
 
 
@@ -430,6 +438,13 @@ def bench_d3(args, log=_log):
         del blob
         equil_steps, steady = g.scalars()["step"], True
         log(f"loaded state at step {equil_steps}, {g.list_size()} entries")
+    elif args.workload == "d3big":
+        # no steady list: step until it passes 1e8 entries
+        equil_steps, steady = 0, False
+        while g.list_size() < 100_000_000 and equil_steps < 5000:
+            g.step(25)
+            equil_steps += 25
+            log(f"growth: {equil_steps} steps, {g.list_size()} entries")
     else:
         equil_steps, steady, _ = equilibrate(g, log)
     if args.save_state:
@@ -621,13 +636,56 @@ def bench_tune(args, log=_log):
     print(json.dumps(out), flush=True)
 
 
+def bench_census(args, log=_log):
+    """Occupied configurations of the 4x4 workload's physics at 1e6 walkers, by
+    initiator threshold and importance-sampling parameter (Sec. IV.B)."""
+    import torch
+    from paper_1802_05931_amd import studies
+    torch.cuda.set_device(0)
+    base = dict(workloads.D3, target_walkers=1_000_000, initial_walkers=1_000_000)
+    grid = [(n, p) for p in (0.0, 1.5, 2.5) for n in (0, 3, 25, 75)]
+    t0 = time.perf_counter()
+    rows = studies.occupancy_census(base, grid, max_steps=args.census_steps, chunk=500,
+                                    cap_limit=200_000_000, stream=torch.cuda.current_stream(),
+                                    log=log)
+    return {"study": "occupancy census (4x4, Jx 0.9 Jy 1 Jz 1 gamma 1, dt 0.002, 1e6 walkers)",
+            "rows": rows, "seconds": time.perf_counter() - t0}
+
+
+def bench_extrapolate(args, log=_log):
+    """The initiator extrapolation on the 4x4 workload's physics with the
+    initiator figure's population and importance sampling (1e6 walkers, p 2.5):
+    replicas at n_a = 3, 5, 8, 12 in one batch, M_z and C_yy read at n_a -> 0."""
+    import torch
+    from paper_1802_05931_amd import studies
+    torch.cuda.set_device(0)
+    base = dict(workloads.D3, target_walkers=1_000_000, initial_walkers=1_000_000, is_p=2.5,
+                n_equil=args.extrap_steps // 2)
+    t0 = time.perf_counter()
+    recs = studies.initiator_runs(base, [3, 5, 8, 12], args.extrap_steps, graph_k=50,
+                                  stream=torch.cuda.current_stream(), chunk=1000, log=log)
+    for r in recs:
+        log(f"extrapolate n_a {r['n_a']}: M_z {r['mz']:.5f} +- {r['se_mz']:.5f}, "
+            f"C_yy {r['cyy']:.5f} +- {r['se_cyy']:.5f}, {r['entries']} entries")
+    return {"study": "initiator extrapolation (4x4, Jx 0.9 Jy 1 Jz 1 gamma 1, dt 0.002, "
+                     "1e6 walkers, p 2.5)",
+            "runs": recs, "mz": studies.extrapolate(recs, "mz"),
+            "cyy": studies.extrapolate(recs, "cyy"), "steps": args.extrap_steps,
+            "seconds": time.perf_counter() - t0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20,
                     help="steps after the equilibration, before the timed steps")
-    ap.add_argument("--workload", default="d3", choices=sorted(WORKLOADS) + ["d4", "d5", "tune"])
+    ap.add_argument("--workload", default="d3",
+                    choices=sorted(WORKLOADS) + ["d4", "d5", "tune", "census", "extrapolate"])
+    ap.add_argument("--census-steps", type=int, default=20000,
+                    help="census: most steps per run")
+    ap.add_argument("--extrap-steps", type=int, default=16000,
+                    help="extrapolate: steps of the batch (half of them accumulated)")
     ap.add_argument("--tune-out", metavar="FILE",
                     help="tune: where the tile table goes (default the package's table)")
     ap.add_argument("--no-tuned", action="store_true",
@@ -683,6 +741,12 @@ def main():
 
     if args.workload == "tune":
         bench_tune(args)
+        return
+    if args.workload == "census":
+        print(json.dumps(bench_census(args)), flush=True)
+        return
+    if args.workload == "extrapolate":
+        print(json.dumps(bench_extrapolate(args), default=float), flush=True)
         return
     if args.workload == "d5":
         print(json.dumps(bench_d5(args)), flush=True)

@@ -1,0 +1,56 @@
+"""The studies on the device: the initiator extrapolation (Sec. IV.A) on a 2x3
+lattice whose exact steady state is known, and the occupancy census
+(Sec. IV.B) against the oracle's list sizes."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dq():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1802_05931_amd as m
+    return m
+
+
+def test_initiator_extrapolation_recovers_the_exact_steady_state(dq):
+    """2x3, Jx 0.6, 500 walkers: replicas at n_a = 0, 2, 4, 6, 8 in one batch.
+    The thresholds bias M_z (n_a = 8 lies more than 5 standard errors off the
+    exact steady state); the straight line through n_a = 2..8 read at n_a -> 0
+    lies within 3 of its standard errors of it, as does the n_a = 0 run."""
+    from oracle import exact
+    from paper_1802_05931_amd import studies
+    base = dict(Lx=2, Ly=3, Jx=0.6, Jy=1.0, Jz=1.0, gamma=1.0, dt=0.01, target_walkers=500,
+                initial_walkers=500, shift_init=0.0, seed=7, n_equil=2000)
+    recs = studies.initiator_runs(base, [0, 2, 4, 6, 8], 60000, graph_k=50)
+    ex = exact.observables(exact.ness(2, 3, 0.6, 1.0, 1.0, 1.0), 2, 3)["mz"]
+    by = {r["n_a"]: r for r in recs}
+    assert all(r["n_accum"] == 58000 for r in recs)
+    assert abs(by[0]["mz"] - ex) < 3 * by[0]["se_mz"]
+    assert by[8]["mz"] - ex < -5 * by[8]["se_mz"]
+    e = studies.extrapolate([r for r in recs if r["n_a"] > 0], "mz")
+    print(f"  extrapolated M_z {e['value']:.5f} +- {e['se']:.5f}, exact {ex:.5f}", flush=True)
+    assert abs(e["value"] - ex) < 3 * e["se"]
+    assert e["slope"] < 0
+
+
+def test_occupancy_census_equals_the_oracle(dq, orc):
+    """A small census (3x3 at 2000 walkers; no initiator, the initiator, and the
+    initiator with importance sampling): each run's occupied configurations,
+    walkers and diagonal weight are the oracle's after the same steps."""
+    from paper_1802_05931_amd import studies
+    import workloads
+    base = dict(workloads.d2(0.6), target_walkers=2000, initial_walkers=2000, shift_init=0.0)
+    rows = studies.occupancy_census(base, [(0, 0.0), (3, 0.0), (3, 1.5)], max_steps=3000,
+                                    chunk=500)
+    for r in rows:
+        o = orc.Oracle(**dict(base, n_a=r["n_a"], is_p=r["is_p"]))
+        o.step(r["steps"])
+        last = o.last()
+        assert (r["entries"], r["walkers"], r["n_w"]) == (last["n_entries"], last["w_tot"],
+                                                           last["n_w"]), r
+    # the initiator rule and importance sampling each cut the occupied set
+    assert rows[1]["entries"] < rows[0]["entries"] and rows[2]["entries"] < rows[1]["entries"]
