@@ -484,6 +484,8 @@ typedef struct {
   int s1[64], s2[64];
   uint64_t bmask[64];
   double h_al, h_an, a_al, a_an, w_dn, w_up, half_gamma, half_jz;
+  int field;            /* the in-plane field is on */
+  double hx, hy, ahx, ahy;
 } model_t;
 
 static int model_init(model_t *md, const orc_params *p) {
@@ -500,6 +502,11 @@ static int model_init(model_t *md, const orc_params *p) {
   md->w_up = orc_det_exp(p->is_p);
   md->half_gamma = 0.5 * p->gamma;
   md->half_jz = 0.5 * p->Jz;
+  md->hx = p->hx;
+  md->hy = p->hy;
+  md->ahx = fabs(p->hx);
+  md->ahy = fabs(p->hy);
+  md->field = (p->hx != 0.0 || p->hy != 0.0);
   return ORC_OK;
 }
 
@@ -589,6 +596,24 @@ int orc_connections(const orc_params *p, uint64_t ket, uint64_t bra, double S, u
       im[cnt] = 0.0;
       cnt++;
     }
+  }
+  if (md.field) {
+    /* single flips of the in-plane field: Re part hy (-1 for a flip up, +1 for a
+     * flip down), Im part hx (-1 on the ket, +1 on the bra), times the IS weight */
+    uint64_t d = ket ^ bra;
+    int side;
+    for (side = 0; side < 2; side++)
+      for (k = 0; k < md.N; k++) {
+        uint64_t x = side ? bra : ket;
+        int to_diag = d == (1ull << k);
+        double w = (ket == bra) ? md.w_dn : (to_diag ? md.w_up : 1.0);
+        if (cnt >= cap) return ORC_ENOMEM;
+        cket[cnt] = side ? ket : (ket ^ (1ull << k));
+        cbra[cnt] = side ? (bra ^ (1ull << k)) : bra;
+        re[cnt] = (bit(x, k) ? md.hy : -md.hy) * w;
+        im[cnt] = (side ? md.hx : -md.hx) * w;
+        cnt++;
+      }
   }
   *d_re = -(md.half_gamma * (double)(popc(ket) + popc(bra))) - S;
   *d_im = md.half_jz * (double)(n_aligned(&md, bra) - n_aligned(&md, ket));
@@ -707,6 +732,158 @@ static void tree_split(const tree_t *t, int lo, int hi, int hnode, int64_t M) {
   tree_split(t, mid, hi, 2 * hnode + 1, M - ML);
 }
 
+/* The in-plane field of Sec. V.B, h (cos theta sigma^x + sin theta sigma^y) per
+ * site = hx sigma^x + hy sigma^y, flips one spin of the ket (-iH rho) or of the
+ * bra (+i rho H).  With sigma^y |dn> = -i |up> the element from |l><m| to the
+ * configuration with site s flipped has
+ *   Re part hy (-1 if the flipped bit was 0, +1 if it was 1), on either side,
+ *   Im part hx (-1 on the ket, +1 on the bra).
+ * With the field on, each element part gets four classes of equal-weight
+ * members: ket flips, the ket flip that makes the child diagonal (l ^ m one
+ * bit), bra flips, the bra flip to the diagonal; their IS weights are those of
+ * the hop classes.  The real part's classes come after the jump class, the
+ * imaginary part's after the six hop classes.  Each member carries its child
+ * and the sign of its element part. */
+#define FMAX 10
+typedef struct {
+  int ncls;
+  int n[FMAX];
+  double W[FMAX];            /* n_c |element part| w_child / w_parent */
+  double Sc[FMAX + 1];       /* suffix sums of W, Sc[ncls] = 0 */
+  uint64_t cl[FMAX][64], cm[FMAX][64];
+  int sgn[FMAX][64];         /* sign of the element part of each member */
+} fclasses_t;
+
+/* one class of single flips: side 0 ket, 1 bra; to_diag selects the flip of
+ * site T (if any) or all the others */
+static void field_class(const model_t *md, uint64_t l, uint64_t m, int side, int to_diag, int T,
+                        int re_part, fclasses_t *f) {
+  int c = f->ncls++, s;
+  int diag = (l == m);
+  double w = diag ? md->w_dn : (to_diag ? md->w_up : 1.0);
+  f->n[c] = 0;
+  for (s = 0; s < md->N; s++) {
+    uint64_t x = side ? m : l;
+    int k;
+    if ((s == T) != (to_diag != 0)) continue;
+    k = f->n[c]++;
+    f->cl[c][k] = side ? l : (l ^ (1ull << s));
+    f->cm[c][k] = side ? (m ^ (1ull << s)) : m;
+    if (re_part)
+      f->sgn[c][k] = sgnd(md->hy) * (bit(x, s) ? 1 : -1);
+    else
+      f->sgn[c][k] = sgnd(md->hx) * (side ? 1 : -1);
+  }
+  f->W[c] = ((double)f->n[c] * (re_part ? md->ahy : md->ahx)) * w;
+}
+
+/* The classes of the real element part with the field on: the jumps (weight
+ * gamma each, sign +1), then the four field classes. */
+static void field_re_classes(const model_t *md, double gamma, uint64_t l, uint64_t m,
+                             fclasses_t *f) {
+  int k, c, T = -1;
+  uint64_t d = l ^ m;
+  if (popc(d) == 1)
+    for (k = 0; k < md->N; k++)
+      if (d == (1ull << k)) T = k;
+  f->ncls = 1;
+  f->n[0] = 0;
+  for (k = 0; k < md->N; k++)
+    if (bit(l, k) && bit(m, k)) {
+      int j = f->n[0]++;
+      f->cl[0][j] = l & ~(1ull << k);
+      f->cm[0][j] = m & ~(1ull << k);
+      f->sgn[0][j] = 1;
+    }
+  f->W[0] = (double)f->n[0] * gamma;
+  field_class(md, l, m, 0, 0, T, 1, f);
+  field_class(md, l, m, 0, 1, T, 1, f);
+  field_class(md, l, m, 1, 0, T, 1, f);
+  field_class(md, l, m, 1, 1, T, 1, f);
+  f->Sc[f->ncls] = 0.0;
+  f->Sc[f->ncls - 1] = f->W[f->ncls - 1];
+  for (c = f->ncls - 2; c >= 0; c--) f->Sc[c] = f->W[c] + f->Sc[c + 1];
+}
+
+/* The classes of the imaginary element part with the field on: the six hop
+ * classes, then the four field classes. */
+static void field_im_classes(const model_t *md, const hop_classes_t *hc, uint64_t l, uint64_t m,
+                             fclasses_t *f) {
+  int k, c, j, T = -1;
+  uint64_t d = l ^ m;
+  if (popc(d) == 1)
+    for (k = 0; k < md->N; k++)
+      if (d == (1ull << k)) T = k;
+  f->ncls = 6;
+  for (c = 0; c < 6; c++) {
+    f->n[c] = hc->n[c];
+    f->W[c] = hc->W[c];
+    for (j = 0; j < hc->n[c]; j++) {
+      int b = hc->mem[c][j];
+      f->cl[c][j] = c < 3 ? (l ^ md->bmask[b]) : l;
+      f->cm[c][j] = c < 3 ? m : (m ^ md->bmask[b]);
+      f->sgn[c][j] = hc->sgn[c];
+    }
+  }
+  field_class(md, l, m, 0, 0, T, 0, f);
+  field_class(md, l, m, 0, 1, T, 0, f);
+  field_class(md, l, m, 1, 0, T, 0, f);
+  field_class(md, l, m, 1, 1, T, 0, f);
+  f->Sc[f->ncls] = 0.0;
+  f->Sc[f->ncls - 1] = f->W[f->ncls - 1];
+  for (c = f->ncls - 2; c >= 0; c--) f->Sc[c] = f->W[c] + f->Sc[c + 1];
+}
+
+/* Draw id, within a channel, of the class split of class c (the ids below 16
+ * keep their meaning of the field-free step; the pick is DRAW_PICK). */
+static uint32_t class_split_draw(int c) { return c < 6 ? 1u + (uint32_t)c : 16u + (uint32_t)c; }
+
+/* Placement of rem walkers of one channel over field-on classes (Sec. III.B):
+ * one walker by one categorical pick (class by inversion on the suffix sums,
+ * then a uniform member); more walkers by sequential conditional binomials over
+ * the classes (the last class with weight takes the rest) and the balanced tree
+ * inside each class.  cnt[c][j] receives member j of class c. */
+static void place_field(const ectx_t *ec, int ch, int64_t rem, const fclasses_t *f,
+                        int64_t cnt[FMAX][64]) {
+  int c, j, last = -1;
+  for (c = 0; c < f->ncls; c++)
+    for (j = 0; j < f->n[c]; j++) cnt[c][j] = 0;
+  if (rem == 0) return;
+  if (rem == 1) {
+    stream_t s;
+    double u1, u2, T;
+    int jj;
+    channel_stream(ec, &s, DRAW_CH(ch) + DRAW_PICK);
+    u1 = stream_next(&s);
+    u2 = stream_next(&s);
+    T = f->Sc[0] * (1.0 - u1);
+    c = 0;
+    while (!(f->Sc[c + 1] < T)) c++;
+    jj = (int)floor(u2 * (double)f->n[c]);
+    if (jj > f->n[c] - 1) jj = f->n[c] - 1;
+    cnt[c][jj] = 1;
+    return;
+  }
+  for (c = 0; c < f->ncls; c++)
+    if (f->W[c] > 0.0) last = c;
+  for (c = 0; c < f->ncls && rem > 0; c++) {
+    int64_t Mc;
+    tree_t t;
+    stream_t s;
+    if (f->W[c] == 0.0) continue;
+    if (c == last) {
+      Mc = rem;
+    } else {
+      channel_stream(ec, &s, DRAW_CH(ch) + class_split_draw(c));
+      Mc = binom(rem, f->W[c] / f->Sc[c], &s);
+    }
+    rem -= Mc;
+    if (Mc == 0) continue;
+    t.ec = ec; t.draw_base = DRAW_CH(ch) + 64u + 64u * (uint32_t)c; t.out = cnt[c];
+    tree_split(&t, 0, f->n[c], 1, Mc);
+  }
+}
+
 /* Placement of the Xs walkers a real-element (jump) channel spawns over the
  * nJ sites where ket and bra are both up (Sec. III.B: the multinomial over
  * equally weighted connections): one walker takes a uniform site, more are
@@ -815,6 +992,46 @@ static void process_entry(orc_t *h, uint64_t key, int32_t R, int32_t I, int64_t 
   for (k = 0; k < N; k++)
     if (bit(l, k) && bit(m, k)) jsite[nJ++] = k;
   P_re = h->p.dt * ((double)nJ * h->p.gamma);
+
+  if (md->field) {
+    /* the in-plane field adds single-flip classes to both element parts */
+    static fclasses_t fre, fim; /* (large; the oracle is single-threaded) */
+    int64_t fcnt[FMAX][64];
+    field_re_classes(md, h->p.gamma, l, m, &fre);
+    field_im_classes(md, &hc, l, m, &fim);
+    P_re = h->p.dt * fre.Sc[0];
+    P_im = h->p.dt * fim.Sc[0];
+    p[0] = p_r; p[1] = p_i; p[2] = P_re; p[3] = P_im;
+    p[4] = p_r; p[5] = p_i; p[6] = P_re; p[7] = P_im;
+    for (k = 0; k < 4; k++) { n[k] = nR; n[k + 4] = nI; }
+    sample_channels(&ec, p, n, X);
+    *dR = sR * sgnd(d_r) * X[0] - sI * sgnd(d_i) * X[5];
+    *dI = sI * sgnd(d_r) * X[4] + sR * sgnd(d_i) * X[1];
+    for (k = 0; k < 4; k++) {
+      int ch = (k & 1) ? (k < 2 ? 7 : 8) : (k < 2 ? 3 : 4); /* 3, 7, 4, 8 */
+      int im_el = k >= 2;           /* element part: 0 Re (channels 3, 7), 1 Im (4, 8) */
+      int im_par = (k & 1) != 0;    /* parent part: 0 real walkers, 1 imaginary */
+      const fclasses_t *f = im_el ? &fim : &fre;
+      int64_t sg = im_par ? sI : sR;
+      int j;
+      if (X[ch - 1] == 0) continue;
+      place_field(&ec, ch, X[ch - 1], f, fcnt);
+      for (c = 0; c < f->ncls; c++)
+        for (j = 0; j < f->n[c]; j++) {
+          int64_t v;
+          if (fcnt[c][j] == 0) continue;
+          v = sg * (int64_t)f->sgn[c][j] * fcnt[c][j];
+          /* (R + iI) x element part: Re x R -> re, Re x I -> im, Im x R -> im,
+           * Im x I -> -re (Sec. III.C rule (i)) */
+          if (!im_el && !im_par) emit(&em, f->cl[c][j], f->cm[c][j], v, 0);
+          else if (!im_el) emit(&em, f->cl[c][j], f->cm[c][j], 0, v);
+          else if (!im_par) emit(&em, f->cl[c][j], f->cm[c][j], 0, v);
+          else emit(&em, f->cl[c][j], f->cm[c][j], -v, 0);
+        }
+    }
+    if (em.rc != ORC_OK) *err = em.rc;
+    return;
+  }
 
   p[0] = p_r; p[1] = p_i; p[2] = P_re; p[3] = P_im;
   p[4] = p_r; p[5] = p_i; p[6] = P_re; p[7] = P_im;

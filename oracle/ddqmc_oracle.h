@@ -12,7 +12,8 @@
  *   bonds = unique nearest-neighbour pairs of the periodic Lx x Ly torus, ordered
  *   "right" bonds (origin site ascending) then "up" bonds (origin ascending);
  *   H = sum_bonds Jx SxSx + Jy SySy + Jz SzSz with S = sigma/2 (Sec. V, model
- *   Hamiltonian); one jump operator S^- per site with rate gamma.
+ *   Hamiltonian) + sum_sites hx sigma^x + hy sigma^y (the in-plane field of
+ *   Sec. V.B); one jump operator S^- per site with rate gamma.
  */
 #ifndef DDQMC_ORACLE_H
 #define DDQMC_ORACLE_H
@@ -44,6 +45,8 @@ typedef struct {
   uint32_t solve_id;
   int64_t n_equil;          /* steps after which estimators are accumulated       */
   uint32_t flags;
+  double hx, hy;            /* in-plane field sum_i (hx sigma^x_i + hy sigma^y_i),
+                               h (cos theta, sin theta) of Sec. V.B               */
 } orc_params;
 
 enum { ORC_T_RE, ORC_T_IM, ORC_NW, ORC_Z, ORC_X, ORC_Y, ORC_CXX, ORC_CYY, ORC_CZZ,

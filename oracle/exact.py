@@ -6,8 +6,10 @@ Everything here is built from 2x2 spin matrices with Kronecker products, with no
 bit tricks, so that it is an independent check of the walker step:
 
 * the model of Sec. V: H = sum over nearest-neighbour bonds of
-  Jx Sx Sx + Jy Sy Sy + Jz Sz Sz with S = sigma/2, jump operator S^- per site at
-  rate gamma, on a periodic Lx x Ly lattice;
+  Jx Sx Sx + Jy Sy Sy + Jz Sz Sz with S = sigma/2, plus the in-plane field of
+  Sec. V.B, sum over sites of h (cos theta sigma^x + sin theta sigma^y) =
+  hx sigma^x + hy sigma^y, jump operator S^- per site at rate gamma, on a
+  periodic Lx x Ly lattice;
 * the vectorised shifted Liouvillian of Sec. III.C (column stacking):
   L = -i(1 (x) H - H^T (x) 1) - S 1 (x) 1
       + sum_k gamma/2 (2 F_k^* (x) F_k - 1 (x) F_k^dag F_k - F_k^T F_k^* (x) 1);
@@ -61,7 +63,7 @@ def site_op(op, s, N):
     return sp.kron(sp.kron(left, sp.csr_matrix(op)), right, format="csr")
 
 
-def hamiltonian(Lx, Ly, Jx, Jy, Jz):
+def hamiltonian(Lx, Ly, Jx, Jy, Jz, hx=0.0, hy=0.0):
     N = Lx * Ly
     D = 2 ** N
     H = sp.csr_matrix((D, D), dtype=complex)
@@ -70,6 +72,8 @@ def hamiltonian(Lx, Ly, Jx, Jy, Jz):
         xa, ya, za = ops[a]
         xb, yb, zb = ops[b]
         H = H + 0.25 * (Jx * (xa @ xb) + Jy * (ya @ yb) + Jz * (za @ zb))
+    for s in range(N):
+        H = H + hx * ops[s][0] + hy * ops[s][1]
     return H.tocsr()
 
 
@@ -78,12 +82,12 @@ def jump_ops(Lx, Ly):
     return [site_op(SM, s, N) for s in range(N)]
 
 
-def liouvillian(Lx, Ly, Jx, Jy, Jz, gamma, S=0.0, is_p=0.0):
+def liouvillian(Lx, Ly, Jx, Jy, Jz, gamma, S=0.0, is_p=0.0, hx=0.0, hy=0.0):
     """Sparse shifted Liouvillian in the Kronecker form, with importance-sampling
     factors applied to the off-diagonal elements."""
     N = Lx * Ly
     D = 2 ** N
-    H = hamiltonian(Lx, Ly, Jx, Jy, Jz)
+    H = hamiltonian(Lx, Ly, Jx, Jy, Jz, hx, hy)
     I = sp.identity(D, dtype=complex, format="csr")
     L = -1j * (sp.kron(I, H) - sp.kron(H.T, I))
     for F in jump_ops(Lx, Ly):
@@ -107,14 +111,14 @@ def weights(N, is_p):
     return np.where(l == m, 1.0, np.exp(-is_p))
 
 
-def liouvillian_direct(Lx, Ly, Jx, Jy, Jz, gamma):
+def liouvillian_direct(Lx, Ly, Jx, Jy, Jz, gamma, hx=0.0, hy=0.0):
     """Dense Liouvillian built column by column from the master equation itself,
     L(|l><m|) = -i[H, |l><m|] + sum_k gamma (F |l><m| F^dag - {F^dag F, |l><m|}/2),
     with dense matrix products.  Small lattices only; used to pin the Kronecker
     form."""
     N = Lx * Ly
     D = 2 ** N
-    H = hamiltonian(Lx, Ly, Jx, Jy, Jz).toarray()
+    H = hamiltonian(Lx, Ly, Jx, Jy, Jz, hx, hy).toarray()
     Fs = [F.toarray() for F in jump_ops(Lx, Ly)]
     L = np.zeros((D * D, D * D), dtype=complex)
     for m in range(D):
@@ -129,20 +133,24 @@ def liouvillian_direct(Lx, Ly, Jx, Jy, Jz, gamma):
     return L
 
 
-def ness(Lx, Ly, Jx, Jy, Jz, gamma):
+def ness(Lx, Ly, Jx, Jy, Jz, gamma, hx=0.0, hy=0.0):
     """Steady state: L rho = 0 with Tr rho = 1.  One diagonal equation is replaced
     by the trace condition (the diagonal rows of L sum to zero because the
-    evolution preserves the trace).  Restricted to the even sector
-    popcount(l) + popcount(m) even, which the evolution from |dn..dn><dn..dn|
-    never leaves."""
+    evolution preserves the trace).  Without the field, restricted to the even
+    sector popcount(l) + popcount(m) even, which the evolution from
+    |dn..dn><dn..dn| never leaves; the field breaks that parity, and then the
+    whole space is used."""
     N = Lx * Ly
     D = 2 ** N
-    L = liouvillian(Lx, Ly, Jx, Jy, Jz, gamma)
+    L = liouvillian(Lx, Ly, Jx, Jy, Jz, gamma, hx=hx, hy=hy)
     idx = np.arange(D * D)
     l = idx % D
     m = idx // D
     pc = np.array([bin(i).count("1") for i in range(D)])
-    even = np.nonzero((pc[l] + pc[m]) % 2 == 0)[0]
+    if hx == 0.0 and hy == 0.0:
+        even = np.nonzero((pc[l] + pc[m]) % 2 == 0)[0]
+    else:
+        even = idx
     Le = L[even][:, even].tolil()
     diag_pos = np.nonzero(l[even] == m[even])[0]
     r = diag_pos[0]
@@ -188,14 +196,14 @@ def vec_index(key, N):
 
 
 def one_step_expectation(keys, re, im, Lx, Ly, Jx, Jy, Jz, gamma, dt, S, is_p=0.0,
-                         non_initiator=None):
+                         non_initiator=None, hx=0.0, hy=0.0):
     """Exact E[rho_{n+1} | rho_n] = (1 + dt L~) rho_n for the walker list, in the
     importance-sampled representation.  If ``non_initiator`` (bool per entry) is
     given, off-diagonal progeny of those parents on configurations that are
     neither occupied nor diagonal is removed (Sec. IV.A)."""
     N = Lx * Ly
     D = 2 ** N
-    L = liouvillian(Lx, Ly, Jx, Jy, Jz, gamma, S=S, is_p=is_p).tocsc()
+    L = liouvillian(Lx, Ly, Jx, Jy, Jz, gamma, S=S, is_p=is_p, hx=hx, hy=hy).tocsc()
     cols = vec_index(keys, N)
     v = np.asarray(re, float) + 1j * np.asarray(im, float)
     sub = L[:, cols].tocoo()
@@ -218,16 +226,17 @@ def one_step_expectation(keys, re, im, Lx, Ly, Jx, Jy, Jz, gamma, dt, S, is_p=0.
 _H_CACHE = {}
 
 
-def column(Lx, Ly, Jx, Jy, Jz, gamma, l, m, S=0.0, is_p=0.0):
+def column(Lx, Ly, Jx, Jy, Jz, gamma, l, m, S=0.0, is_p=0.0, hx=0.0, hy=0.0):
     """One column of the shifted, importance-sampled Liouvillian, for parent
     |l><m|, from the sparse H and the jump matrices (no Kronecker product of the
     full superoperator; usable up to 4x4).  Returns {(ket, bra): value}."""
     N = Lx * Ly
-    key = (Lx, Ly, Jx, Jy, Jz)
+    key = (Lx, Ly, Jx, Jy, Jz, hx, hy)
     if key not in _H_CACHE:
-        _H_CACHE[key] = (hamiltonian(Lx, Ly, Jx, Jy, Jz).tocsc(),
+        Hm = hamiltonian(Lx, Ly, Jx, Jy, Jz, hx, hy)
+        _H_CACHE[key] = ((Hm.tocsc(), Hm.tocsr()),
                          [F.tocsc() for F in jump_ops(Lx, Ly)])
-    H, Fs = _H_CACHE[key]
+    (H, Hr), Fs = _H_CACHE[key]
     out = {}
 
     def add(i, j, v):
@@ -239,7 +248,7 @@ def column(Lx, Ly, Jx, Jy, Jz, gamma, l, m, S=0.0, is_p=0.0):
     for i, v in zip(col.indices, col.data):
         add(int(i), m, -1j * v)
     # +i |l><m| H  : children |l><j| with +i H_mj
-    row = H[:, m]          # H is symmetric: H_mj = H_jm
+    row = Hr[m]            # H is Hermitian (not symmetric once the field has sigma^y)
     for j, v in zip(row.indices, row.data):
         add(l, int(j), 1j * v)
     for F in Fs:

@@ -6,7 +6,9 @@ estimators are checked against, Sec. V "solving the linear system").
 * The steady state has zero residual, unit trace, is Hermitian and positive.
 * Closed forms: Jx = Jy makes |dn..dn> an eigenstate of H with no up spin, so the
   steady state is |dn..dn><dn..dn| (M_z = -1); J = 0 likewise.
-* At zero field the parity selection rule forces <sigma^x> = <sigma^y> = 0.
+* At zero field the parity selection rule forces <sigma^x> = <sigma^y> = 0; with
+  the in-plane field of Sec. V.B they respond linearly at small field, along
+  and (through the anisotropy) across the field.
 * Trace preservation: the diagonal rows of L sum to zero.
 """
 import numpy as np
@@ -92,3 +94,44 @@ def test_single_spin_relaxation_closed_form():
     assert col[0] == pytest.approx(gamma)
     coh = L[:, 0 * D + up0]   # rho_{up0, 0}
     assert coh[0 * D + up0] == pytest.approx(-gamma / 2)
+
+
+def test_pauli_y_convention():
+    """sigma^y in the (down, up) basis of the bit: sigma^y |up> = i |down> and
+    sigma^y |down> = -i |up>, so <down|sigma^y|up> = i; and it squares to 1 and
+    anticommutes with sigma^x, with sigma^x sigma^y = i sigma^z."""
+    assert exact.SY[0, 1] == 1j and exact.SY[1, 0] == -1j
+    assert np.allclose(exact.SY @ exact.SY, np.eye(2))
+    assert np.allclose(exact.SX @ exact.SY, 1j * exact.SZ)
+
+
+@pytest.mark.parametrize("hx,hy", [(0.3, 0.0), (0.0, -0.2), (0.15, 0.25)])
+def test_kronecker_with_field_equals_master_equation(hx, hy):
+    """With the in-plane field of Sec. V.B in H (hx sigma^x + hy sigma^y per site)."""
+    Ld = exact.liouvillian_direct(2, 2, 0.9, 1.0, 1.3, 0.7, hx=hx, hy=hy)
+    Lk = exact.liouvillian(2, 2, 0.9, 1.0, 1.3, 0.7, hx=hx, hy=hy).toarray()
+    assert np.abs(Ld - Lk).max() < 1e-14
+    # the field term is H's only part between configurations one flip apart:
+    # <up|hx sigma^x + hy sigma^y|dn> = hx - i hy = h e^{-i theta}
+    H = exact.hamiltonian(2, 2, 0.9, 1.0, 1.3, hx, hy).toarray()
+    assert H[0b0001, 0b0000] == hx - 1j * hy and H[0b0000, 0b0001] == hx + 1j * hy
+
+
+def test_field_breaks_parity_and_gives_linear_response():
+    """The field makes the transverse magnetisation nonzero.  As for one driven
+    spin decaying to |dn> (the field resonant, no detuning), a field along x
+    gives <sigma^y> and no <sigma^x>: the response tensor is off-diagonal, and
+    a field along y gives mostly <sigma^x>, of opposite sign.  At small h the
+    response is linear (M(2h) = 2 M(h) up to 0.5% at h = 0.01)."""
+    Lx, Ly = 2, 2
+    r1 = exact.observables(exact.ness(Lx, Ly, 0.9, 1.0, 1.0, 1.0, hx=0.01), Lx, Ly)
+    r2 = exact.observables(exact.ness(Lx, Ly, 0.9, 1.0, 1.0, 1.0, hx=0.02), Lx, Ly)
+    assert abs(r1["mx"]) < 1e-14 and r1["my"] > 1e-2
+    assert abs(r2["my"] / r1["my"] - 2.0) < 1e-2
+    ry = exact.observables(exact.ness(Lx, Ly, 0.9, 1.0, 1.0, 1.0, hy=0.01), Lx, Ly)
+    assert ry["mx"] < -1e-2 and abs(ry["my"]) > 1e-3
+    rho = exact.ness(Lx, Ly, 0.9, 1.0, 1.0, 1.0, hx=0.2, hy=0.1)
+    L = exact.liouvillian(Lx, Ly, 0.9, 1.0, 1.0, 1.0, hx=0.2, hy=0.1)
+    assert np.abs(L @ rho.reshape(-1, order="F")).max() < 1e-12
+    assert abs(np.trace(rho) - 1) < 1e-12 and np.abs(rho - rho.conj().T).max() < 1e-12
+    assert np.linalg.eigvalsh(rho).min() > -1e-12

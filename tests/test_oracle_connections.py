@@ -15,8 +15,8 @@ from oracle import exact
 PARAMS = dict(Jx=0.9, Jy=1.0, Jz=1.3, gamma=0.8)
 
 
-def _oracle_column(orc, Lx, Ly, l, m, S, is_p):
-    p = orc.make_params(Lx=Lx, Ly=Ly, is_p=is_p, **PARAMS)
+def _oracle_column(orc, Lx, Ly, l, m, S, is_p, hx=0.0, hy=0.0):
+    p = orc.make_params(Lx=Lx, Ly=Ly, is_p=is_p, hx=hx, hy=hy, **PARAMS)
     ck, cb, re, im, dr, di = orc.connections(p, l, m, S)
     out = {}
     for a, b, x, y in zip(ck.tolist(), cb.tolist(), re.tolist(), im.tolist()):
@@ -70,3 +70,37 @@ def test_random_columns_larger_lattices(orc, Lx, Ly, ncols):
 def test_oracle_bond_order_matches_exact(orc):
     for Lx, Ly in [(2, 2), (3, 3), (4, 4), (2, 6), (5, 5), (4, 8)]:
         assert orc.bonds(Lx, Ly) == exact.bonds(Lx, Ly)
+
+
+@pytest.mark.parametrize("Lx,Ly,is_p,S,hx,hy", [(2, 2, 0.0, 0.0, 0.3, 0.0),
+                                               (2, 2, 1.5, 0.37, 0.0, -0.2),
+                                               (2, 3, 0.8, -0.2, 0.15, 0.25)])
+def test_every_column_with_field(orc, Lx, Ly, is_p, S, hx, hy):
+    """With the in-plane field (Sec. V.B): the single-flip children carry both a
+    real and an imaginary element part, each configuration of either parity."""
+    N = Lx * Ly
+    D = 2 ** N
+    L = exact.liouvillian(Lx, Ly, PARAMS["Jx"], PARAMS["Jy"], PARAMS["Jz"], PARAMS["gamma"],
+                          S=S, is_p=is_p, hx=hx, hy=hy).tocsc()
+    for m in range(D):
+        for l in range(D):
+            c = L[:, m * D + l]
+            col = {(int(i) % D, int(i) // D): v for i, v in zip(c.indices, c.data)}
+            ora, diag = _oracle_column(orc, Lx, Ly, l, m, S, is_p, hx, hy)
+            _compare(ora, diag, col, l, m)
+
+
+def test_random_columns_with_field_4x4(orc):
+    rng = np.random.default_rng(44)
+    for _ in range(25):
+        l = int(rng.integers(0, 2 ** 16))
+        m = int(rng.integers(0, 2 ** 16))
+        r = rng.random()
+        if r < 0.3:
+            m = l
+        elif r < 0.6:  # one flip away: the field's to-diagonal class
+            m = l ^ (1 << int(rng.integers(0, 16)))
+        col = exact.column(4, 4, PARAMS["Jx"], PARAMS["Jy"], PARAMS["Jz"], PARAMS["gamma"],
+                           l, m, S=0.11, is_p=1.5, hx=0.12, hy=-0.07)
+        ora, diag = _oracle_column(orc, 4, 4, l, m, 0.11, 1.5, 0.12, -0.07)
+        _compare(ora, diag, col, l, m)

@@ -295,3 +295,44 @@ def test_shift_update_follows_the_population(orc):
     want = S[k - 1] + (cfg["shift_damping"] / cfg["dt"]) * np.log(nw[k] / nw[k - 1])
     assert np.allclose(S[k], want, rtol=0, atol=1e-12)
     assert np.abs(S[k] - S[k - 1]).max() > 1e-3  # the shift does move
+
+
+@pytest.mark.parametrize("Lx,Ly,is_p,dt,S,nent,pop,hx,hy", [
+    (2, 2, 0.0, 0.02, 0.2, 128, 300, 0.3, 0.0),
+    (2, 2, 1.5, 0.05, -0.3, 90, 300, 0.1, -0.25),
+    (2, 3, 0.7, 0.02, 0.1, 250, 200, -0.2, 0.15),
+    (2, 2, 0.0, 0.6, -1.2, 60, 50, 0.4, 0.3),   # probabilities above 1
+])
+def test_one_step_expectation_with_field(orc, Lx, Ly, is_p, dt, S, nent, pop, hx, hy):
+    """Sec. V.B: with the in-plane field the step still samples the Euler map
+    (1 + dt L~) rho exactly, now from lists of both parities (the field flips
+    one spin), with and without importance sampling."""
+    keys, re, im = workloads.random_list(Lx, Ly, nent, pop, seed=nent + Lx + 7, even=False)
+    p = orc.make_params(Lx=Lx, Ly=Ly, Jx=0.6, Jy=1.0, Jz=1.2, gamma=1.0, dt=dt, n_a=0,
+                        is_p=is_p, target_walkers=2 ** 62, hx=hx, hy=hy)
+    samples = _one_step_samples(orc, p, keys, re, im, S, nseed=600)
+    expected = exact.one_step_expectation(keys, re, im, Lx, Ly, 0.6, 1.0, 1.2, 1.0, dt, S,
+                                          is_p=is_p, hx=hx, hy=hy)
+    _z_check(samples, expected)
+
+
+@pytest.mark.parametrize("hx,hy", [(0.15, 0.0), (0.0, 0.15)])
+def test_ness_with_field(orc, hx, hy):
+    """2x2 at n_a = 0 in a field along x, then along y: the transverse
+    magnetisations M_x, M_y (zero without the field) and M_z within 3
+    standard errors of the exact steady state in that field."""
+    Lx, Ly, jx = 2, 2, 0.6
+    equil = 3000
+    o = orc.Oracle(Lx=Lx, Ly=Ly, Jx=jx, dt=0.01, n_a=0, target_walkers=3000,
+                   initial_walkers=100, seed=11, n_equil=equil, hx=hx, hy=hy)
+    o.step(60000)
+    rows = o.series()
+    rows = rows[rows[:, 0] > equil]
+    col = {n: 3 + i for i, n in enumerate(orc.SUM_NAMES)}
+    ex = exact.observables(exact.ness(Lx, Ly, jx, 1.0, 1.0, 1.0, hx=hx, hy=hy), Lx, Ly)
+    den = rows[:, col["t_re"]]
+    for name, key in (("mz", "z"), ("mx", "x"), ("my", "y")):
+        v, se, _ = ratio_se(rows[:, col[key]] / 4.0, den)
+        assert abs(v - ex[name]) < 3 * se, (name, v, ex[name], se)
+    big = "my" if hx else "mx"  # the response is across the field (see test_exact)
+    assert abs(ex[big]) > 0.05
