@@ -14,7 +14,8 @@
  *   site s = x + Lx*y; bit s of a bitstring = 1 <=> spin up;
  *   configuration key = (ket << N) | bra, N = Lx*Ly <= 32 (a 64-bit value);
  *   H = sum over unique nearest-neighbour bonds of the periodic Lx x Ly lattice of
- *       Jx SxSx + Jy SySy + Jz SzSz with S = sigma/2; jump S^- per site, rate gamma;
+ *       Jx SxSx + Jy SySy + Jz SzSz with S = sigma/2, plus hx sigma^x + hy sigma^y
+ *       per site (the in-plane field of Sec. V.B); jump S^- per site, rate gamma;
  *   walkers are int32 (re, im) per configuration; all estimator sums are int64.
  *
  * Return codes: 0 on success, a negative DDQMC_E* code otherwise (see
@@ -64,6 +65,10 @@ typedef struct {
   int64_t n_equil;          /* steps before estimator accumulation starts          */
   int64_t capacity_hint;    /* initial list capacity in entries; 0 = automatic     */
   uint32_t flags;           /* DDQMC_NO_INITIATOR                                  */
+  double hx, hy;            /* in-plane field sum_i hx sigma^x_i + hy sigma^y_i, i.e.
+                               h (cos theta, sin theta) of Sec. V.B; 0, 0 = none.
+                               A handle with a field on takes the general spawn
+                               path (one thread per entry) for all its solves   */
 } ddqmc_params;
 
 /* Sums over the walker list after a step (Sec. III.A numerators/denominators):

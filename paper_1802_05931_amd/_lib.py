@@ -32,6 +32,7 @@ class Params(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("solve_id", ctypes.c_uint32),
         ("n_equil", ctypes.c_int64), ("capacity_hint", ctypes.c_int64),
         ("flags", ctypes.c_uint32),
+        ("hx", ctypes.c_double), ("hy", ctypes.c_double),
     ]
 
 
@@ -50,7 +51,8 @@ class Obs(ctypes.Structure):
 
 DEFAULTS = dict(Lx=2, Ly=2, Jx=0.9, Jy=1.0, Jz=1.0, gamma=1.0, dt=0.01, n_a=3,
                 target_walkers=1000, initial_walkers=100, is_p=0.0, shift_damping=0.05,
-                shift_init=-0.5, seed=0, solve_id=0, n_equil=0, capacity_hint=0, flags=0)
+                shift_init=-0.5, seed=0, solve_id=0, n_equil=0, capacity_hint=0, flags=0,
+                hx=0.0, hy=0.0)
 
 
 def make_params(**kw):

@@ -124,6 +124,8 @@ struct ddqmc_t {
   bool loud_dyn = false;    // loud kernel: resident blocks and a chunk counter (else a
                             // block per chunk); chosen per chunk of steps, see run_steps
   int loud_grid = 0;        // 0 chosen per chunk of steps, 1 resident, 2 block per chunk
+  bool general = false;     // some solve has the in-plane field: the general spawn path
+  uint32_t general_blocks = 1024;
   // tile shapes (records / merged positions per thread) of the sort and the
   // merge, and an optional table choosing them by list size before each chunk
   int sort_it = SORT_IT_DEFAULT, merge_it = MERGE_IT_DEFAULT;
@@ -256,6 +258,7 @@ int validate(const ddqmc_params *p) {
   if (p->initial_walkers <= 0 || p->initial_walkers > 2147483647LL) return DDQMC_EINVAL;
   if (p->solve_id >= 65536u || p->capacity_hint < 0 || p->n_equil < 0) return DDQMC_EINVAL;
   if (!std::isfinite(p->shift_damping) || !std::isfinite(p->shift_init)) return DDQMC_EINVAL;
+  if (!std::isfinite(p->hx) || !std::isfinite(p->hy)) return DDQMC_EINVAL;
   return DDQMC_OK;
 }
 
@@ -293,6 +296,11 @@ SlotParams make_slot(const ddqmc_params &p) {
   s.w_up = dexp(p.is_p);
   s.delta_over_dt = p.shift_damping / p.dt;
   s.shift_init = p.shift_init;
+  s.hx = p.hx;
+  s.hy = p.hy;
+  s.ahx = std::fabs(p.hx);
+  s.ahy = std::fabs(p.hy);
+  s.field = (p.hx != 0.0 || p.hy != 0.0) ? 1u : 0u;
   return s;
 }
 
@@ -434,6 +442,7 @@ int build(ddqmc_t *h, int nslots, int Nmax, uint64_t cap, void *stream, void *ws
     }
     h->loud_blocks = clampu((uint64_t)std::max(ncu, 1) * (uint64_t)std::max(nl, 1), 1, 4096);
     h->heavy_blocks = clampu((uint64_t)std::max(ncu, 1) * (uint64_t)std::max(nh, 1), 1, 8192);
+    h->general_blocks = clampu((uint64_t)std::max(ncu, 1) * 4, 1, 4096);
   }
   h->passes = (h->key_bits + 7) / 8;
   const size_t ks = key_size(h);
@@ -528,10 +537,20 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
   const uint32_t g_s = clampu((h->cap_sp + sort_tile - 1) / sort_tile, 1, 1u << 24);
   const uint32_t g_m = clampu((h->cap_main + h->cap_sp + merge_tile - 1) / merge_tile, 1, 1u << 20);
   if (ev) HIPC(hipEventRecord(ev->e[0], s));
+  Ctrl *c = h->ctrl;
+  if (h->general) {
+    // the in-plane field: every entry through the general path (timed as the
+    // loud stage; the scan, gather and heavy stages are empty)
+    if (ev) HIPC(hipEventRecord(ev->e[1], s));
+    if (ev) HIPC(hipEventRecord(ev->e[2], s));
+    k_spawn_general<K><<<h->general_blocks, NT, 0, s>>>(ak, av, c, h->dsp, h->dss, (K *)h->sk[0],
+                                                        h->sv[0], h->segcnt, segcap, h->SB);
+    if (ev) HIPC(hipEventRecord(ev->e[3], s));
+    if (ev) HIPC(hipEventRecord(ev->e[4], s));
+  } else {
   k_spawn_scan<K><<<h->nscan, NT, 0, s>>>(ak, av, h->ctrl, h->dsp, h->dss, h->lidx,
                                          (K *)h->lkey, h->lval, h->heavy, h->SB);
   if (ev) HIPC(hipEventRecord(ev->e[1], s));
-  Ctrl *c = h->ctrl;
   if (h->fork_heavy) {
     // the scan's heavy list on the second stream, alongside the loud kernel
     HIPC(hipEventRecord(h->ev_fork, s));
@@ -562,6 +581,7 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
       ak, av, c, h->dsp, h->dss, late, nlate, (K *)h->sk[0], h->sv[0], h->segcnt, segcap, h->SB);
   if (h->fork_heavy) HIPC(hipStreamWaitEvent(s, h->ev_join, 0));
   if (ev) HIPC(hipEventRecord(ev->e[4], s));
+  }
   if (h->pool)
     k_inject<K><<<1, NT, 0, s>>>((const K *)h->inj_k, h->inj_v, h->ctrl, (K *)h->sk[0], h->sv[0],
                                  h->segcnt, segcap);
@@ -1047,6 +1067,7 @@ int create_common(const ddqmc_params *p, int32_t count, void *hip_stream, void *
   std::vector<int2> vals(count);
   for (int i = 0; i < count; ++i) {
     h->hp[i] = make_slot(p[i]);
+    if (h->hp[i].field) h->general = true;
     h->up[i] = p[i];
     st[i] = fresh_state(p[i], 1);
     h->slot_state[i] = 1;
@@ -1141,6 +1162,10 @@ int ddqmc_slot_admit(ddqmc_t *h, const ddqmc_params *p, int32_t *slot) {
     }
   if (s < 0) return DDQMC_ESTATE;
   h->hp[s] = make_slot(*p);
+  if (h->hp[s].field && !h->general) {
+    h->general = true;  // (the handle keeps the general path from here on)
+    h->buf_gen += 1;    // captured graphs hold the other spawn kernels
+  }
   h->up[s] = *p;
   h->hseries[s].clear();
   const SlotState st = fresh_state(*p, 2);

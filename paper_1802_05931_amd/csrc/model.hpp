@@ -30,6 +30,9 @@ struct SlotParams {
   double h_al, h_an, a_al, a_an;  // signed / absolute hop amplitude, aligned / anti
   double w_dn, w_up;              // e^{-p}, e^{+p}
   double delta_over_dt, shift_init;
+  // in-plane field hx sigma^x + hy sigma^y per site (Sec. V.B); field = 1 if on
+  double hx, hy, ahx, ahy;
+  uint32_t field, pad;
 };
 
 // Per-solve evolving state (device, written by the step's last kernel).
@@ -439,6 +442,183 @@ DQ_HD void entry_events(const SlotParams &P, double S, uint32_t step, uint32_t l
                    else
                      emit(cl, cm, -v, 0, init || cl == cm);
                  });
+    }
+  }
+  if (cnt.dry) *err = 1;
+}
+
+// ---- the in-plane field (Sec. V.B) -----------------------------------------
+// hx sigma^x + hy sigma^y per site flips one spin of the ket (-iH rho) or of the
+// bra (+i rho H).  With sigma^y |dn> = -i |up>, the element from |l><m| to the
+// configuration with site s flipped has Re part hy (-1 for a flip up, +1 for a
+// flip down), on either side, and Im part hx (-1 on the ket, +1 on the bra).
+// Each element part gets four classes of single flips: ket, ket to the
+// diagonal (the flip of the one site where l and m differ, if they differ in
+// one), bra, bra to the diagonal, members by ascending site, with the hop
+// classes' importance-sampling weights.  The real part's classes follow the
+// jump class; the imaginary part's follow the six hop classes.
+constexpr int FIELD_CLASSES_MAX = 10;
+
+struct FieldParts {
+  int ncls[2];                        // classes of the Re (0) and Im (1) element parts
+  int n[2][FIELD_CLASSES_MAX];
+  double W[2][FIELD_CLASSES_MAX];     // n_c |element part| w_child / w_parent
+  double Sc[2][FIELD_CLASSES_MAX + 1];  // suffix sums of W, Sc[ncls] = 0
+  uint32_t fmask[4];                  // site masks of the field classes
+};
+
+// the draw id, within a channel, of the class split of class c
+DQ_HD uint32_t class_split_draw(int c) { return c < 6 ? 1u + (uint32_t)c : 16u + (uint32_t)c; }
+
+DQ_HD void field_parts(const SlotParams &P, const HopClasses &hc, uint32_t l, uint32_t m,
+                       FieldParts &f) {
+  const bool diag = (l == m);
+  const uint32_t d = l ^ m;
+  const uint32_t tbit = popc(d) == 1 ? d : 0u;
+  const uint32_t all = P.N == 32 ? 0xffffffffu : ((1u << P.N) - 1u);
+  f.fmask[0] = all & ~tbit;
+  f.fmask[1] = tbit;
+  f.fmask[2] = all & ~tbit;
+  f.fmask[3] = tbit;
+  // Re part: the jumps, then the field classes
+  f.ncls[0] = 5;
+  f.n[0][0] = popc(l & m);
+  f.W[0][0] = (double)f.n[0][0] * P.gamma;
+  // Im part: the six hop classes, then the field classes
+  f.ncls[1] = 10;
+  for (int c = 0; c < 6; ++c) {
+    f.n[1][c] = hc.n[c];
+    f.W[1][c] = hc.W[c];
+  }
+  for (int k = 0; k < 4; ++k) {
+    const bool to_diag = (k & 1) != 0;
+    const double w = diag ? P.w_dn : (to_diag ? P.w_up : 1.0);
+    const int n = popc(f.fmask[k]);
+    f.n[0][1 + k] = n;
+    f.W[0][1 + k] = ((double)n * P.ahy) * w;
+    f.n[1][6 + k] = n;
+    f.W[1][6 + k] = ((double)n * P.ahx) * w;
+  }
+  for (int part = 0; part < 2; ++part) {
+    const int nc = f.ncls[part];
+    f.Sc[part][nc] = 0.0;
+    f.Sc[part][nc - 1] = f.W[part][nc - 1];
+    for (int c = nc - 2; c >= 0; --c) f.Sc[part][c] = f.W[part][c] + f.Sc[part][c + 1];
+  }
+}
+
+// entry_events with the field on (the slot's P.field): the same clone/death,
+// the real element part's jumps and field flips, the imaginary part's hops
+// and field flips, each part's walkers placed by one class split (sequential
+// conditional binomials, the last class with weight taking the rest; one
+// walker by one categorical pick) and the member trees.
+template <typename Emit>
+DQ_HD void entry_events_field(const SlotParams &P, double S, uint32_t step, uint32_t l,
+                              uint32_t m, int32_t R, int32_t I, int *err, Emit &&emit) {
+  const bool diag = (l == m);
+  const int64_t nR = R < 0 ? -(int64_t)R : (int64_t)R;
+  const int64_t nI = I < 0 ? -(int64_t)I : (int64_t)I;
+  const int64_t sR = sgn64(R), sI = sgn64(I);
+  const bool init = diag || (nR + nI > P.n_a) || (P.flags & FLAG_NO_INITIATOR);
+  const Geometry g = geometry(P, l, m);
+  const double d_r = -(P.half_gamma * (double)(popc(l) + popc(m))) - S;
+  const double d_i = P.half_jz * (double)(g.al[1] - g.al[0]);
+  const double p_r = P.dt * __builtin_fabs(d_r);
+  const double p_i = P.dt * __builtin_fabs(d_i);
+  const HopClasses hc = hop_classes(P, g, l, m);
+  FieldParts f;
+  field_parts(P, hc, l, m, f);
+  const double P_re = P.dt * f.Sc[0][0];
+  const double P_im = P.dt * f.Sc[1][0];
+  double p8[8];
+  int64_t n8[8];
+  const double pp[4] = {p_r, p_i, P_re, P_im};
+  for (int k = 0; k < 4; ++k) {
+    p8[k] = pp[k];
+    p8[k + 4] = pp[k];
+    n8[k] = nR;
+    n8[k + 4] = nI;
+  }
+  EntryCounter cnt{P.seed, ((uint64_t)l << P.N) | m, P.solve, step, 0};
+  int64_t X[8];
+  channel_counts(p8, n8, cnt, X);
+  const int64_t dR = sR * sgnd(d_r) * X[0] - sI * sgnd(d_i) * X[5];
+  const int64_t dI = sI * sgnd(d_r) * X[4] + sR * sgnd(d_i) * X[1];
+  if (dR != 0 || dI != 0) emit(l, m, dR, dI, true);
+
+  const uint32_t jm = l & m;
+  for (int k = 0; k < 4; ++k) {
+    const int im_el = k >= 2;        // element part: 0 Re (channels 3, 7), 1 Im (4, 8)
+    const int im_par = k & 1;        // parent part: 0 real walkers, 1 imaginary
+    const int ch = im_el ? (im_par ? 8 : 4) : (im_par ? 7 : 3);
+    int64_t rem = X[ch - 1];
+    if (rem == 0) continue;
+    const int64_t sg = im_par ? sI : sR;
+    const int nc = f.ncls[im_el];
+    // member j of class c: its child and the sign of its element part
+    auto leaf = [&](int c, int j, int64_t M) {
+      uint32_t cl = l, cm = m;
+      int64_t sgn = 1;
+      bool keep = init;
+      if (!im_el && c == 0) {  // a jump: down in both ket and bra
+        const uint32_t bit = 1u << nth_bit(jm, j);
+        cl = l & ~bit;
+        cm = m & ~bit;
+      } else if (im_el && c < 6) {  // a hop of one bond
+        const uint32_t bm = class_member_mask(P, hc.r[c], hc.u[c], j);
+        cl = c < 3 ? (l ^ bm) : l;
+        cm = c < 3 ? m : (m ^ bm);
+        sgn = hc.sgn[c];
+        keep = init || cl == cm;
+      } else {  // a field flip
+        const int fk = im_el ? c - 6 : c - 1;
+        const bool bra = fk >= 2;
+        const uint32_t site = nth_bit(f.fmask[fk], j);
+        const uint32_t x = bra ? m : l;
+        if (bra)
+          cm = m ^ (1u << site);
+        else
+          cl = l ^ (1u << site);
+        sgn = im_el ? (bra ? sgnd(P.hx) : -sgnd(P.hx)) : (((x >> site) & 1u) ? sgnd(P.hy) : -sgnd(P.hy));
+        keep = init || cl == cm;
+      }
+      const int64_t v = sg * sgn * M;
+      // (R + iI) x element part: Re x R -> re, Re x I -> im, Im x R -> im,
+      // Im x I -> -re (Sec. III.C rule (i))
+      if (!im_el && !im_par)
+        emit(cl, cm, v, 0, keep);
+      else if (!im_el || !im_par)
+        emit(cl, cm, 0, v, keep);
+      else
+        emit(cl, cm, -v, 0, keep);
+    };
+    if (rem == 1) {
+      Stream st(cnt.seed, cnt.solve, cnt.cfg, cnt.step, draw_channel(ch) + DRAW_PICK, nullptr);
+      const double u1 = st.next();
+      const double u2 = st.next();
+      const double T = f.Sc[im_el][0] * (1.0 - u1);
+      int c = 0;
+      while (!(f.Sc[im_el][c + 1] < T)) ++c;
+      int j = (int)__builtin_floor(u2 * (double)f.n[im_el][c]);
+      j = j > f.n[im_el][c] - 1 ? f.n[im_el][c] - 1 : j;
+      leaf(c, j, 1);
+      continue;
+    }
+    int last = -1;
+    for (int c = 0; c < nc; ++c)
+      if (f.W[im_el][c] > 0.0) last = c;
+    for (int c = 0; c < nc; ++c) {
+      if (rem == 0 || f.W[im_el][c] == 0.0) continue;
+      int64_t Mc;
+      if (c == last)
+        Mc = rem;
+      else
+        Mc = cnt(draw_channel(ch) + class_split_draw(c), rem, f.W[im_el][c] / f.Sc[im_el][c],
+                 DRAW_BIN);
+      rem -= Mc;
+      if (Mc == 0) continue;
+      tree_split(f.n[im_el][c], Mc, cnt, draw_channel(ch) + 64u + 64u * (uint32_t)c,
+                 [&](int j, int64_t M) { leaf(c, j, M); });
     }
   }
   if (cnt.dry) *err = 1;

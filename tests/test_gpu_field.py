@@ -1,0 +1,142 @@
+"""GPU parity with the in-plane field of Sec. V.B (hx sigma^x + hy sigma^y per
+site): the general spawn path (one thread per entry) against the oracle, bit
+for bit; and a batch mixing solves with and without the field against each
+solve alone (a field-free solve alone takes the quiet scan and the loud and
+heavy kernels, in the batch the general path: the same draws)."""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dq():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1802_05931_amd as m
+    return m
+
+
+def _same_list(a, b):
+    return (len(a[0]) == len(b[0]) and np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+            and np.array_equal(a[2], b[2]))
+
+
+def _run(dq, orc, cfg, chunks, per, graph_k=0):
+    g = dq.Solve(dq.make_params(**cfg))
+    if graph_k:
+        g.set_graph_steps(graph_k)
+    o = orc.Oracle(**{k: v for k, v in cfg.items() if k != "capacity_hint"})
+    for c in range(chunks):
+        g.step(per)
+        o.step(per)
+        assert _same_list(g.walkers(), o.get_list()), f"list differs after {(c + 1) * per} steps"
+        assert g.scalars() == o.scalars()
+    assert np.array_equal(g.series(), o.series())
+    go = g.observables()
+    oacc, n_acc = o.acc()
+    assert go["n_accum"] == n_acc and list(go["acc"].values()) == oacc.tolist()
+    n = len(g.walkers()[0])
+    g.close()
+    return go, n
+
+
+def test_field_2x2(dq, orc):
+    cfg = dict(workloads.D1, hx=0.15, n_equil=500)
+    go, n = _run(dq, orc, cfg, chunks=6, per=500)
+    assert go["acc"]["y"] != 0  # the field along x gives sigma^y
+    keys = orc.Oracle(**cfg)
+    keys.step(3000)
+    k = keys.get_list()[0]
+    par = [(bin(int(x) >> 4).count("1") + bin(int(x) & 15).count("1")) % 2 for x in k]
+    assert 0 < sum(par) < len(par)  # both parities occupied
+
+
+@pytest.mark.parametrize("hx,hy,is_p,graph_k", [(0.1, -0.07, 0.0, 0), (0.0, 0.12, 0.5, 10)])
+def test_field_3x3(dq, orc, hx, hy, is_p, graph_k):
+    cfg = dict(workloads.d2(0.6), target_walkers=20000, n_equil=200, hx=hx, hy=hy, is_p=is_p)
+    _, n = _run(dq, orc, cfg, chunks=3, per=250, graph_k=graph_k)
+    assert n > 2 * 2048
+
+
+def test_field_5x5_u64(dq, orc):
+    cfg = dict(Lx=5, Ly=5, Jx=0.7, Jy=1.0, Jz=1.0, gamma=1.0, dt=0.002, n_a=3, hx=0.05,
+               hy=0.03, target_walkers=20000, initial_walkers=20000, shift_init=0.0, n_equil=10,
+               seed=3)
+    _run(dq, orc, cfg, chunks=2, per=40)
+
+
+@pytest.mark.parametrize("Lx,Ly,is_p,dt,S,nent,pop,n_a", [
+    (2, 2, 0.0, 0.6, -1.2, 100, 50, 0),       # probabilities above 1
+    (3, 3, 1.5, 0.02, 0.1, 5000, 300, 3),
+    (4, 4, 1.5, 0.002, 0.0, 20000, 40, 3),
+])
+def test_field_one_step_from_random_lists(dq, orc, Lx, Ly, is_p, dt, S, nent, pop, n_a):
+    keys, re, im = workloads.random_list(Lx, Ly, nent, pop, seed=nent + 5, even=False)
+    cfg = dict(Lx=Lx, Ly=Ly, Jx=0.6, Jy=1.0, Jz=1.2, gamma=1.0, dt=dt, n_a=n_a, is_p=is_p,
+               target_walkers=2 ** 62, seed=77, hx=0.21, hy=-0.13)
+    g = dq.Solve(dq.make_params(**cfg))
+    o = orc.Oracle(**cfg)
+    for step in (0, 1, 12345):
+        g.set_walkers(keys, re, im)
+        g.set_scalars(S, 1, step, 10 ** 6)
+        o.set_list(keys, re, im)
+        o.set_scalars(S, 1, step, 10 ** 6)
+        g.step(1)
+        o.step(1)
+        assert _same_list(g.walkers(), o.get_list())
+        assert g.scalars() == o.scalars()
+    g.close()
+
+
+def test_batch_mixing_field_and_no_field_equals_alone(dq, orc):
+    cfgs = [dict(workloads.d2(0.9), solve_id=1, target_walkers=3000, n_equil=100),
+            dict(workloads.d2(0.9), solve_id=2, target_walkers=3000, n_equil=100, hx=0.1),
+            dict(Lx=2, Ly=6, Jx=0.5, Jz=0.9, gamma=1.3, dt=0.005, n_a=3, target_walkers=2000,
+                 initial_walkers=2000, shift_init=0.0, solve_id=3, seed=5, n_equil=50),
+            dict(workloads.D1, solve_id=4, n_equil=100, hy=0.2)]
+    b = dq.Batch([dq.make_params(**c) for c in cfgs])
+    b.set_graph_steps(10)
+    alone = []
+    for c in cfgs:
+        alone.append(dq.Solve(dq.make_params(**c)))
+    orcs = [orc.Oracle(**c) for c in cfgs]
+    for _ in range(3):
+        b.step(200)
+        for i, (a, o) in enumerate(zip(alone, orcs)):
+            a.step(200)
+            o.step(200)
+            assert _same_list(b.walkers(i), a.walkers()), i
+            assert _same_list(a.walkers(), o.get_list()), i
+            assert b.scalars(i) == a.scalars() == o.scalars(), i
+    b.close()
+    for a in alone:
+        a.close()
+
+
+def test_pool_admits_a_field_solve(dq, orc):
+    """A pool switches to the general path when a solve with the field enters;
+    the solves before and after keep the oracle's lists."""
+    pool = dq.Pool(slots=3, max_sites=16)
+    pool.set_graph_steps(10)
+    c1 = dict(workloads.d2(1.1), solve_id=21, target_walkers=4000, n_equil=50)
+    c2 = dict(workloads.D1, solve_id=22, n_equil=50, hx=0.12, hy=0.05)
+    s1 = pool.admit(dq.make_params(**c1))
+    pool.step(1)
+    o1 = orc.Oracle(**c1)
+    pool.step(100)
+    o1.step(100)
+    s2 = pool.admit(dq.make_params(**c2))
+    pool.step(1)
+    o1.step(1)
+    o2 = orc.Oracle(**c2)
+    pool.step(150)
+    o1.step(150)
+    o2.step(150)
+    assert _same_list(pool.walkers(s1), o1.get_list())
+    assert _same_list(pool.walkers(s2), o2.get_list())
+    assert pool.scalars(s2) == o2.scalars()
+    pool.close()
