@@ -468,7 +468,9 @@ def bench_d3(args, log=_log):
     series = g.series()
     counts = g.step_counts()
     stage_ms, stage_steps = g.stage_times()
-    assert stage_steps == (args.steps + prof_every - 1) // prof_every
+    # (a step that regrows the buffers restarts the sampling for the rest of
+    # its chunk, so the count of sampled steps is read, not assumed)
+    assert stage_steps >= 1
     # the sampled steps' stage times, scaled to all timed steps
     stage_ms = {k: v * args.steps / stage_steps for k, v in stage_ms.items()}
     sums = {n: i + 3 for i, n in enumerate(dq.SUM_NAMES)}
@@ -674,6 +676,23 @@ def bench_extrapolate(args, log=_log):
             "seconds": time.perf_counter() - t0}
 
 
+def bench_susceptibility(args, log=_log):
+    """One point of the angle-averaged susceptibility (Sec. V.B) on the 3x3
+    lattice: the 3 + 3 + 1 field runs (h 0.01, 0.02, 0.03 along x and y, and
+    none) in one batch, at the 3x3 workload's couplings and 1e5 walkers."""
+    import torch
+    from paper_1802_05931_amd import studies
+    torch.cuda.set_device(0)
+    base = dict(workloads.d2(0.9), target_walkers=100_000, initial_walkers=100_000,
+                shift_init=0.0, n_equil=args.chi_steps // 4)
+    t0 = time.perf_counter()
+    r = studies.susceptibility(base, [0.01, 0.02, 0.03], args.chi_steps, graph_k=50,
+                               stream=torch.cuda.current_stream(), chunk=2000, log=log)
+    r.update(study="susceptibility (3x3, Jx 0.9 Jy 1 Jz 1 gamma 1, dt 0.005, n_a 3, 1e5 walkers)",
+             steps=args.chi_steps, seconds=time.perf_counter() - t0)
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -681,7 +700,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20,
                     help="steps after the equilibration, before the timed steps")
     ap.add_argument("--workload", default="d3",
-                    choices=sorted(WORKLOADS) + ["d4", "d5", "tune", "census", "extrapolate"])
+                    choices=sorted(WORKLOADS) + ["d4", "d5", "tune", "census", "extrapolate",
+                                                 "susceptibility"])
+    ap.add_argument("--chi-steps", type=int, default=20000,
+                    help="susceptibility: steps of the 3 + 3 + 1 runs")
     ap.add_argument("--census-steps", type=int, default=20000,
                     help="census: most steps per run")
     ap.add_argument("--extrap-steps", type=int, default=16000,
@@ -744,6 +766,9 @@ def main():
         return
     if args.workload == "census":
         print(json.dumps(bench_census(args)), flush=True)
+        return
+    if args.workload == "susceptibility":
+        print(json.dumps(bench_susceptibility(args), default=float), flush=True)
         return
     if args.workload == "extrapolate":
         print(json.dumps(bench_extrapolate(args), default=float), flush=True)

@@ -13,6 +13,11 @@ solve id.
 Occupancy census (Sec. IV.B, the occupied-element figure): how many
 configurations the walker list occupies at a given population, with and
 without the initiator rule and importance sampling.
+
+Susceptibility (Sec. V.B): the linear response of the transverse
+magnetisation to the in-plane field, chi_ab = dM_a / dh_b at h = 0, from 3 + 3
++ 1 runs (three field strengths along x, three along y, one without field) in
+one batch, and the angle-averaged chi_av = (1 / 2 pi) int |chi (cos t, sin t)| dt.
 """
 import numpy as np
 
@@ -121,3 +126,70 @@ def occupancy_census(base, grid, max_steps, chunk=500, tol=0.01, cap_limit=0, st
             log(f"census n_a {n_a} p {p}: {row}")
         g.close()
     return rows
+
+
+def chi_av(chi, n=3600):
+    """Angle average (1 / 2 pi) int_0^{2 pi} |chi (cos t, sin t)^T| dt of a 2x2
+    response tensor, by the midpoint rule over n angles (the integrand is
+    periodic, so the rule converges fast)."""
+    chi = np.asarray(chi, float)
+    t = (np.arange(n) + 0.5) * (2.0 * np.pi / n)
+    v = chi @ np.vstack([np.cos(t), np.sin(t)])
+    return float(np.mean(np.hypot(v[0], v[1])))
+
+
+def response_tensor(m0, mx_runs, my_runs, fields):
+    """chi_ab from magnetisations: m0 = (M_x, M_y, se_x, se_y) without field;
+    mx_runs / my_runs the same with the field along x / y at the strengths
+    `fields`.  chi_ab is the slope of a weighted line through M_a at h_b = 0
+    and the three fields along b (through the zero-field point itself when its
+    error is 0, as it is exactly 0 by the parity rule); returns (chi, se(chi))."""
+    chi = np.zeros((2, 2))
+    se = np.zeros((2, 2))
+    h = np.concatenate([[0.0], np.asarray(fields, float)])
+    for b, runs in enumerate((mx_runs, my_runs)):
+        for a in range(2):
+            y = np.array([m0[a]] + [r[a] for r in runs])
+            e = np.array([m0[2 + a]] + [r[2 + a] for r in runs])
+            if e[0] == 0.0:
+                # without the field the transverse magnetisation is exactly 0 (the
+                # parity rule): the line goes through that point
+                w = 1.0 / e[1:] ** 2
+                hh = h[1:]
+                chi[a, b] = float((w * hh * (y[1:] - y[0])).sum() / (w * hh * hh).sum())
+                se[a, b] = float(1.0 / np.sqrt((w * hh * hh).sum()))
+            else:
+                _, _, slope, s_slope, _ = linear_extrapolation(h, y, e)
+                chi[a, b] = slope
+                se[a, b] = s_slope
+    return chi, se
+
+
+def susceptibility(base, fields, steps, graph_k=0, stream=None, chunk=0, log=None):
+    """The 3 + 3 + 1 runs of one susceptibility point in one batch: no field,
+    the field along x at each strength of `fields`, then along y.  Returns chi,
+    its standard errors, chi_av and the runs' magnetisations."""
+    cfgs = [dict(base, hx=0.0, hy=0.0)]
+    cfgs += [dict(base, hx=float(h), hy=0.0) for h in fields]
+    cfgs += [dict(base, hx=0.0, hy=float(h)) for h in fields]
+    for i, c in enumerate(cfgs):
+        c["solve_id"] = int(base.get("solve_id", 0)) + i
+    b = Batch([make_params(**c) for c in cfgs], stream=stream)
+    if graph_k:
+        b.set_graph_steps(graph_k)
+    done = 0
+    while done < steps:
+        k = min(chunk or steps, steps - done)
+        b.step(k)
+        done += k
+        if log:
+            log(f"susceptibility runs: {done} of {steps} steps, {b.list_size()} entries")
+    m = []
+    for i in range(len(cfgs)):
+        o = b.observables(i)
+        m.append((o["mx"], o["my"], o["se_mx"], o["se_my"]))
+    b.close()
+    nf = len(fields)
+    chi, se = response_tensor(m[0], m[1:1 + nf], m[1 + nf:], fields)
+    return dict(chi=chi.tolist(), se_chi=se.tolist(), chi_av=chi_av(chi), runs=m,
+                fields=[float(h) for h in fields])

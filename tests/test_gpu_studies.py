@@ -54,3 +54,29 @@ def test_occupancy_census_equals_the_oracle(dq, orc):
                                                            last["n_w"]), r
     # the initiator rule and importance sampling each cut the occupied set
     assert rows[1]["entries"] < rows[0]["entries"] and rows[2]["entries"] < rows[1]["entries"]
+
+
+def test_susceptibility_matches_the_exact_response(dq):
+    """The 3 + 3 + 1 field runs of one susceptibility point (Sec. V.B) in one
+    batch on 2x2 at n_a = 0: every component of chi_ab = dM_a/dh_b (from lines
+    through the runs at h = 0.01, 0.02, 0.03) within 4 standard errors of the
+    same lines through the exact steady states, and chi_av likewise.  The
+    tensor is far from diagonal (a field along x turns the magnetisation to y)."""
+    from oracle import exact
+    from paper_1802_05931_amd import studies
+    base = dict(Lx=2, Ly=2, Jx=0.9, Jy=1.0, Jz=1.0, gamma=1.0, dt=0.01, n_a=0,
+                target_walkers=3000, initial_walkers=3000, shift_init=0.0, seed=17,
+                n_equil=3000)
+    fields = [0.01, 0.02, 0.03]
+    r = studies.susceptibility(base, fields, 60000, graph_k=50)
+
+    def ex(hx, hy):
+        o = exact.observables(exact.ness(2, 2, 0.9, 1.0, 1.0, 1.0, hx=hx, hy=hy), 2, 2)
+        return (o["mx"], o["my"], 0.0 if hx == hy == 0 else 1e-9, 0.0 if hx == hy == 0 else 1e-9)
+    chi_e, _ = studies.response_tensor(ex(0, 0), [ex(h, 0) for h in fields],
+                                       [ex(0, h) for h in fields], fields)
+    chi, se = np.array(r["chi"]), np.array(r["se_chi"])
+    print(f"  chi {chi.tolist()} +- {se.tolist()}; exact {chi_e.tolist()}", flush=True)
+    assert np.all(np.abs(chi - chi_e) < 4 * se)
+    assert abs(r["chi_av"] - studies.chi_av(chi_e)) < 4 * se.max()
+    assert abs(chi_e[1, 0]) > 3.0 and abs(chi_e[0, 0]) < 1e-12

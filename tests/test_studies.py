@@ -48,3 +48,49 @@ def test_extrapolate_uses_the_lowest_thresholds():
     assert e["n_a"] == [1, 2, 4, 8] and e["value"] == pytest.approx(-0.9, abs=1e-12)
     with pytest.raises(ValueError):
         studies.linear_extrapolation([1.0, 1.0], [0.0, 1.0], [1.0, 1.0])
+
+
+
+def test_chi_av_closed_forms():
+    """chi = c 1 gives |c|; a rank-one chi = u v^T gives |u| |v| 2 / pi (the mean
+    of |cos|); a rotation by 90 degrees (the field-across response of a driven
+    decaying spin) gives its scale; diag(a, b) gives the ellipse's mean radius."""
+    from scipy import integrate
+    assert studies.chi_av([[0.7, 0.0], [0.0, 0.7]]) == pytest.approx(0.7, rel=1e-12)
+    u, v = np.array([0.3, -0.4]), np.array([1.0, 2.0])
+    assert studies.chi_av(np.outer(u, v)) == pytest.approx(
+        np.linalg.norm(u) * np.linalg.norm(v) * 2 / np.pi, rel=1e-6)
+    assert studies.chi_av([[0.0, -2.0], [2.0, 0.0]]) == pytest.approx(2.0, rel=1e-12)
+    a, b = 1.0, 0.25
+    ell = integrate.quad(lambda t: np.hypot(a * np.cos(t), b * np.sin(t)), 0, 2 * np.pi)[0]
+    assert studies.chi_av([[a, 0.0], [0.0, b]]) == pytest.approx(ell / (2 * np.pi), rel=1e-9)
+
+
+def test_response_tensor_from_linear_magnetisations():
+    """Magnetisations exactly linear in the field give back the tensor."""
+    chi = np.array([[0.1, -3.0], [2.6, 0.4]])
+    fields = [0.01, 0.02, 0.03]
+    m0 = (0.0, 0.0, 1e-4, 1e-4)
+    mx = [(chi[0, 0] * h, chi[1, 0] * h, 1e-4, 1e-4) for h in fields]
+    my = [(chi[0, 1] * h, chi[1, 1] * h, 1e-4, 1e-4) for h in fields]
+    got, se = studies.response_tensor(m0, mx, my, fields)
+    assert np.allclose(got, chi, atol=1e-12) and np.all(se > 0)
+
+
+def test_response_tensor_through_an_exact_zero():
+    """A zero-field point with error 0 (exactly 0 by parity) pins the line to
+    the origin: the slope is sum w h y / sum w h^2."""
+    fields = [0.01, 0.02, 0.03]
+    rng = np.random.default_rng(9)
+    noise = rng.normal(0, 1e-4, (2, 3, 2))
+    m0 = (0.0, 0.0, 0.0, 0.0)
+    mx = [(0.5 * h + noise[0, i, 0], -2.0 * h + noise[0, i, 1], 1e-4, 1e-4)
+          for i, h in enumerate(fields)]
+    my = [(1.5 * h + noise[1, i, 0], 0.2 * h + noise[1, i, 1], 1e-4, 1e-4)
+          for i, h in enumerate(fields)]
+    chi, se = studies.response_tensor(m0, mx, my, fields)
+    h = np.array(fields)
+    want = (h * np.array([r[1] for r in mx])).sum() / (h * h).sum()
+    assert chi[1, 0] == pytest.approx(want, rel=1e-12)
+    assert se[1, 0] == pytest.approx(1e-4 / np.sqrt((h * h).sum()), rel=1e-12)
+    assert np.all(np.abs(chi - np.array([[0.5, 1.5], [-2.0, 0.2]])) < 5 * se)
