@@ -955,6 +955,107 @@ static void place_hops(const ectx_t *ec, int ch, int64_t rem, const hop_classes_
   }
 }
 
+/* Per-walker sampling, the rules of Sec. II taken walker by walker (the
+ * alternative to the multinomial formalism of Sec. III.B): each walker of the
+ * entry's real or imaginary part
+ *   - dies / clones along the diagonal element's real part (probability
+ *     dt |d_r|) and transfers along its imaginary part (dt |d_i|), each an
+ *     integer part realised for sure plus a Bernoulli draw of the fraction;
+ *   - makes one spawning attempt along the real element part: a jump site chosen
+ *     uniformly among the nJ connections, success probability nJ dt gamma;
+ *   - makes one along the imaginary element part: a hop chosen uniformly among
+ *     the nh hop connections (all six classes), success probability
+ *     nh dt |element| w_child / w_parent; a probability above 1 realises its
+ *     integer part for sure and draws the fraction.
+ * Walker w of part q draws its six uniforms from the stream with draw id
+ * 0x8000 + q * 2^13 + (w >> 14), blocks 4 (w mod 2^14) .. + 2 (so at most 2^27
+ * walkers per part of an entry).  The expectation is the Euler map, as with
+ * the multinomial scheme; the law of the spawned counts differs (a uniform
+ * choice of connection instead of one proportional to the element). */
+#define PW_MAX_WALKERS (1ll << 27)
+static double pw_frac_count(double p, double u, int64_t *c) {
+  double f = floor(p);
+  *c = (int64_t)f + ((u < p - f) ? 1 : 0);
+  return f;
+}
+
+static void per_walker_entry(orc_t *h, uint64_t key, uint64_t l, uint64_t m, int32_t R, int32_t I,
+                             double d_r, double d_i, double p_r, double p_i,
+                             const hop_classes_t *hc, const int *jsite, int nJ, emit_t *em,
+                             int64_t *dR, int64_t *dI, int *err) {
+  const model_t *md = &h->md;
+  int part, c;
+  int nh = 0;
+  uint64_t diag = (l == m);
+  for (c = 0; c < 6; c++) nh += hc->n[c];
+  *dR = 0;
+  *dI = 0;
+  for (part = 0; part < 2; part++) {
+    int64_t n = part ? (I < 0 ? -(int64_t)I : I) : (R < 0 ? -(int64_t)R : R);
+    int64_t sg = part ? sgn64(I) : sgn64(R);
+    int64_t w;
+    if (n > PW_MAX_WALKERS) {
+      *err = ORC_ERNG;
+      return;
+    }
+    for (w = 0; w < n; w++) {
+      stream_t s;
+      double u[6];
+      int64_t cr, ci, cs;
+      int k;
+      stream_init(&s, h->p.seed, h->p.solve_id, key, (uint32_t)h->step,
+                  0x8000u + ((uint32_t)part << 13) + (uint32_t)(w >> 14), err);
+      s.block = 4u * (uint32_t)(w & 0x3FFF);
+      for (k = 0; k < 6; k++) u[k] = stream_next(&s);
+      /* clone/death: (R + iI)(d_r + i d_i) dt, walker by walker */
+      pw_frac_count(p_r, u[0], &cr);
+      pw_frac_count(p_i, u[1], &ci);
+      if (part == 0) {
+        *dR += sg * sgnd(d_r) * cr;
+        *dI += sg * sgnd(d_i) * ci;
+      } else {
+        *dI += sg * sgnd(d_r) * cr;
+        *dR -= sg * sgnd(d_i) * ci;
+      }
+      /* one attempt along the real part: a uniform jump site */
+      if (nJ > 0) {
+        int j = (int)floor(u[2] * (double)nJ);
+        uint64_t bitk;
+        if (j > nJ - 1) j = nJ - 1;
+        pw_frac_count(h->p.dt * ((double)nJ * h->p.gamma), u[3], &cs);
+        bitk = 1ull << jsite[j];
+        if (cs) {
+          if (part == 0) emit(em, l & ~bitk, m & ~bitk, sg * cs, 0);
+          else emit(em, l & ~bitk, m & ~bitk, 0, sg * cs);
+        }
+      }
+      /* one attempt along the imaginary part: a uniform hop among all classes */
+      if (nh > 0) {
+        int j = (int)floor(u[4] * (double)nh), b, al, T = -1, bb;
+        double amp, wgt;
+        uint64_t cl, cm;
+        if (j > nh - 1) j = nh - 1;
+        c = 0;
+        while (j >= hc->n[c]) j -= hc->n[c++];
+        b = hc->mem[c][j];
+        for (bb = 0; bb < md->nb; bb++)
+          if ((l ^ m) == md->bmask[bb]) T = bb;
+        al = (c % 3 == 2) ? (T >= 0 ? aligned(md, l, T) : 1) : (c % 3 == 0);
+        amp = al ? md->a_al : md->a_an;
+        wgt = diag ? md->w_dn : (c % 3 == 2 ? md->w_up : 1.0);
+        pw_frac_count(h->p.dt * (((double)nh * amp) * wgt), u[5], &cs);
+        cl = c < 3 ? (l ^ md->bmask[b]) : l;
+        cm = c < 3 ? m : (m ^ md->bmask[b]);
+        if (cs) {
+          int64_t v = sg * (int64_t)hc->sgn[c] * cs;
+          if (part == 0) emit(em, cl, cm, 0, v);
+          else emit(em, cl, cm, -v, 0);
+        }
+      }
+    }
+  }
+}
+
 static void process_entry(orc_t *h, uint64_t key, int32_t R, int32_t I, int64_t *dR, int64_t *dI,
                           int *err) {
   const model_t *md = &h->md;
@@ -992,6 +1093,12 @@ static void process_entry(orc_t *h, uint64_t key, int32_t R, int32_t I, int64_t 
   for (k = 0; k < N; k++)
     if (bit(l, k) && bit(m, k)) jsite[nJ++] = k;
   P_re = h->p.dt * ((double)nJ * h->p.gamma);
+
+  if (h->p.flags & ORC_PER_WALKER) {
+    per_walker_entry(h, key, l, m, R, I, d_r, d_i, p_r, p_i, &hc, jsite, nJ, &em, dR, dI, err);
+    if (em.rc != ORC_OK) *err = em.rc;
+    return;
+  }
 
   if (md->field) {
     /* the in-plane field adds single-flip classes to both element parts */
@@ -1236,6 +1343,8 @@ int orc_create(const orc_params *p, orc_t **out) {
   orc_t *h;
   int rc;
   if (!p || !out) return ORC_EINVAL;
+  /* the per-walker sampler covers the field-free model only */
+  if ((p->flags & ORC_PER_WALKER) && (p->hx != 0.0 || p->hy != 0.0)) return ORC_EINVAL;
   if (p->Lx < 2 || p->Ly < 2 || p->Lx * p->Ly > 32 || !(p->gamma > 0.0) || !(p->dt > 0.0) ||
       p->n_a < 0 || p->initial_walkers <= 0 || p->initial_walkers > 2147483647LL ||
       p->is_p < 0.0 || p->solve_id >= 65536u)

@@ -31,6 +31,7 @@ extern "C" {
 #define ORC_ERNG (-8)
 
 #define ORC_NO_INITIATOR 1u
+#define ORC_PER_WALKER 2u   /* spawning and clone/death walker by walker (Sec. II)  */
 
 typedef struct {
   int32_t Lx, Ly;

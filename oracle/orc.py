@@ -16,6 +16,7 @@ LIB = os.path.join(HERE, "liborc.so")
 
 OK, EINVAL, ENOMEM, EOVERFLOW, EEXTINCT, ERNG = 0, -1, -2, -4, -5, -8
 NO_INITIATOR = 1
+PER_WALKER = 2
 SUM_NAMES = ("t_re", "t_im", "n_w", "z", "x", "y", "cxx", "cyy", "czz", "w_tot", "n_entries")
 NSUM = len(SUM_NAMES)
 SERIES_W = 3 + NSUM

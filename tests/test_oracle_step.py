@@ -336,3 +336,60 @@ def test_ness_with_field(orc, hx, hy):
         assert abs(v - ex[name]) < 3 * se, (name, v, ex[name], se)
     big = "my" if hx else "mx"  # the response is across the field (see test_exact)
     assert abs(ex[big]) > 0.05
+
+
+@pytest.mark.parametrize("Lx,Ly,is_p,dt,S,nent,pop", [
+    (2, 2, 0.0, 0.01, 0.2, 128, 60),
+    (2, 2, 1.5, 0.05, -0.3, 80, 60),
+    (2, 3, 0.7, 0.02, 0.1, 250, 40),
+    (2, 2, 0.0, 0.6, -1.2, 60, 20),     # probabilities above 1
+])
+def test_per_walker_one_step_expectation(orc, Lx, Ly, is_p, dt, S, nent, pop):
+    """The per-walker sampler (Sec. II rules, walker by walker: a uniformly chosen
+    connection, spawn probability n_conn dt |element|) samples the same Euler
+    map (1 + dt L~) rho as the multinomial one, element by element.  Its
+    spawned counts are rarer and larger (one walker's attempt carries the whole
+    n_conn-fold probability), so the per-element z-scores are heavier-tailed
+    and their mean square needs 2000 samples, not 600, to settle in the
+    calibration window."""
+    keys, re, im = workloads.random_list(Lx, Ly, nent, pop, seed=nent + Lx + 3)
+    p = orc.make_params(Lx=Lx, Ly=Ly, Jx=0.6, Jy=1.0, Jz=1.2, gamma=1.0, dt=dt, n_a=0,
+                        is_p=is_p, target_walkers=2 ** 62, flags=orc.PER_WALKER)
+    samples = _one_step_samples(orc, p, keys, re, im, S, nseed=2000)
+    expected = exact.one_step_expectation(keys, re, im, Lx, Ly, 0.6, 1.0, 1.2, 1.0, dt, S,
+                                          is_p=is_p)
+    _z_check(samples, expected)
+
+
+def test_per_walker_differs_in_law_but_not_in_mean(orc):
+    """Same list, same seeds: the per-walker and the multinomial samplers give
+    different lists (different laws for the spawned counts) whose means agree
+    with the Euler map (checked above); their death draws are Bsplit in both."""
+    keys, re, im = workloads.random_list(2, 2, 60, 30, seed=4)
+    a = orc.Oracle(Lx=2, Ly=2, dt=0.05, n_a=0, target_walkers=2 ** 62)
+    b = orc.Oracle(Lx=2, Ly=2, dt=0.05, n_a=0, target_walkers=2 ** 62, flags=orc.PER_WALKER)
+    for o in (a, b):
+        o.set_list(keys, re, im)
+        o.set_scalars(0.0, 0, 0, 1)
+        o.step(1)
+    la, lb = a.get_list(), b.get_list()
+    assert not (len(la[0]) == len(lb[0]) and all(np.array_equal(x, y) for x, y in zip(la, lb)))
+    with pytest.raises(orc.OracleError):
+        orc.Oracle(Lx=2, Ly=2, flags=orc.PER_WALKER, hx=0.1)
+
+
+def test_per_walker_ness(orc):
+    """The per-walker sampler reaches the exact steady state too (2x2, n_a = 0)."""
+    Lx, Ly = 2, 2
+    equil = 3000
+    o = orc.Oracle(Lx=Lx, Ly=Ly, Jx=0.6, dt=0.01, n_a=0, target_walkers=2000,
+                   initial_walkers=100, seed=5, n_equil=equil, flags=orc.PER_WALKER)
+    o.step(40000)
+    rows = o.series()
+    rows = rows[rows[:, 0] > equil]
+    col = {n: 3 + i for i, n in enumerate(orc.SUM_NAMES)}
+    ex = exact.observables(exact.ness(Lx, Ly, 0.6, 1.0, 1.0, 1.0), Lx, Ly)
+    mz, se, _ = ratio_se(rows[:, col["z"]] / 4.0, rows[:, col["t_re"]])
+    assert abs(mz - ex["mz"]) < 3 * se, (mz, ex["mz"], se)
+    v, s2, _ = ratio_se(rows[:, col["cyy"]] / 4.0, rows[:, col["t_re"]])
+    assert abs(v - ex["cyy"]) < 4 * s2, (v, ex["cyy"], s2)
