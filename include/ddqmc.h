@@ -45,6 +45,16 @@ extern "C" {
 
 /* flags */
 #define DDQMC_NO_INITIATOR 1u /* every parent counts as an initiator                */
+/* Spawning and clone/death walker by walker, by the rules of Sec. II: each
+ * walker dies / clones along the diagonal element with probability dt |d|,
+ * and makes one attempt per element part (real: jumps, imaginary: hops) at a
+ * connection chosen uniformly, with success probability n_conn dt |element|
+ * (importance-sampled).  Same expectation as the default per-entry sampling,
+ * which draws all of an entry's walkers at once; kept as its ablation.  All
+ * solves of a handle carry the flag or none does (DDQMC_EINVAL otherwise); not
+ * with the in-plane field, not in a serving pool (DDQMC_EINVAL); at most 2^27
+ * walkers on one part of one entry (DDQMC_ERNG beyond). */
+#define DDQMC_PER_WALKER 2u
 
 /* Parameters of one steady-state solve (Sec. V model; Sec. III.C shift;
  * Sec. IV.A initiator threshold; Sec. IV.B importance-sampling parameter). */
@@ -64,7 +74,7 @@ typedef struct {
   uint32_t solve_id;        /* < 65536; distinct solves draw distinct streams       */
   int64_t n_equil;          /* steps before estimator accumulation starts          */
   int64_t capacity_hint;    /* initial list capacity in entries; 0 = automatic     */
-  uint32_t flags;           /* DDQMC_NO_INITIATOR                                  */
+  uint32_t flags;           /* DDQMC_NO_INITIATOR | DDQMC_PER_WALKER                */
   double hx, hy;            /* in-plane field sum_i hx sigma^x_i + hy sigma^y_i, i.e.
                                h (cos theta, sin theta) of Sec. V.B; 0, 0 = none.
                                A handle with a field on takes the general spawn

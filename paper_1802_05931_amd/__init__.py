@@ -10,13 +10,14 @@ import ctypes
 
 import numpy as np
 
-from ._lib import (DDQMCError, NO_INITIATOR, NSUM, Obs, Params, SERIES_W, SUM_NAMES, check, lib,
+from ._lib import (DDQMCError, NO_INITIATOR, NSUM, PER_WALKER, Obs, Params, SERIES_W, SUM_NAMES, check, lib,
                    make_params, ptr)
 
 STAGES = ("scan", "gather", "loud", "heavy", "seal", "histogram", "sort", "count", "merge",
           "finalize")
 
-__all__ = ["Solve", "Batch", "Pool", "make_params", "DDQMCError", "NO_INITIATOR", "SUM_NAMES",
+__all__ = ["Solve", "Batch", "Pool", "make_params", "DDQMCError", "NO_INITIATOR", "PER_WALKER",
+           "SUM_NAMES",
            "dev_uniforms", "dev_binom", "dev_binom_noalloc", "dev_math", "dev_quiet",
            "workspace_query", "ratio_se",
            "plan_growth"]

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libddqmc.so")
 OK, EINVAL, ENOMEM, ECAPACITY, EOVERFLOW, EEXTINCT, EHIP, ESTATE, ERNG = 0, -1, -2, -3, -4, -5, \
     -6, -7, -8
 NO_INITIATOR = 1
+PER_WALKER = 2  # walker-by-walker sampling (Sec. II), the per-entry scheme's ablation
 SUM_NAMES = ("t_re", "t_im", "n_w", "z", "x", "y", "cxx", "cyy", "czz", "w_tot", "n_entries")
 NSUM = len(SUM_NAMES)
 SERIES_W = 3 + NSUM

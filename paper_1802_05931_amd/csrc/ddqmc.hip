@@ -125,6 +125,7 @@ struct ddqmc_t {
                             // block per chunk); chosen per chunk of steps, see run_steps
   int loud_grid = 0;        // 0 chosen per chunk of steps, 1 resident, 2 block per chunk
   bool general = false;     // some solve has the in-plane field: the general spawn path
+  bool per_walker = false;  // every solve samples walker by walker (the ablation path)
   uint32_t general_blocks = 1024;
   // tile shapes (records / merged positions per thread) of the sort and the
   // merge, and an optional table choosing them by list size before each chunk
@@ -259,6 +260,8 @@ int validate(const ddqmc_params *p) {
   if (p->solve_id >= 65536u || p->capacity_hint < 0 || p->n_equil < 0) return DDQMC_EINVAL;
   if (!std::isfinite(p->shift_damping) || !std::isfinite(p->shift_init)) return DDQMC_EINVAL;
   if (!std::isfinite(p->hx) || !std::isfinite(p->hy)) return DDQMC_EINVAL;
+  if (p->flags & ~(DDQMC_NO_INITIATOR | DDQMC_PER_WALKER)) return DDQMC_EINVAL;
+  if ((p->flags & DDQMC_PER_WALKER) && (p->hx != 0.0 || p->hy != 0.0)) return DDQMC_EINVAL;
   return DDQMC_OK;
 }
 
@@ -538,7 +541,23 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
   const uint32_t g_m = clampu((h->cap_main + h->cap_sp + merge_tile - 1) / merge_tile, 1, 1u << 20);
   if (ev) HIPC(hipEventRecord(ev->e[0], s));
   Ctrl *c = h->ctrl;
-  if (h->general) {
+  if (h->per_walker) {
+    // walker by walker: the walkers' prefix over the list (in the loud value
+    // buffer, 8 bytes per entry, and the heavy queue for the block offsets),
+    // then one thread per walker (timed as the loud stage)
+    if (ev) HIPC(hipEventRecord(ev->e[1], s));
+    static_assert(sizeof(int2) == sizeof(unsigned long long), "one prefix per list entry");
+    unsigned long long *pre = reinterpret_cast<unsigned long long *>(h->lval);
+    unsigned long long *boff = reinterpret_cast<unsigned long long *>(h->heavy);
+    k_pw_prefix<K><<<h->general_blocks, NT, 0, s>>>(ak, av, c, h->dss, pre, boff, h->SB);
+    k_pw_scan<<<1, 1024, 0, s>>>(c, boff);
+    if (ev) HIPC(hipEventRecord(ev->e[2], s));
+    k_pw_walk<K><<<h->general_blocks, NT, 0, s>>>(ak, av, c, h->dsp, h->dss, pre, boff,
+                                                  (K *)h->sk[0], h->sv[0], h->segcnt, segcap,
+                                                  h->SB);
+    if (ev) HIPC(hipEventRecord(ev->e[3], s));
+    if (ev) HIPC(hipEventRecord(ev->e[4], s));
+  } else if (h->general) {
     // the in-plane field: every entry through the general path (timed as the
     // loud stage; the scan, gather and heavy stages are empty)
     if (ev) HIPC(hipEventRecord(ev->e[1], s));
@@ -1045,6 +1064,7 @@ int create_common(const ddqmc_params *p, int32_t count, void *hip_stream, void *
     if (rc != DDQMC_OK) return rc;
     Nmax = std::max(Nmax, p[i].Lx * p[i].Ly);
     cap += auto_capacity(p[i]);
+    if ((p[i].flags ^ p[0].flags) & DDQMC_PER_WALKER) return DDQMC_EINVAL;
   }
   // in a workspace: the capacity asked for, else the largest that fits
   if (ws) {
@@ -1068,6 +1088,7 @@ int create_common(const ddqmc_params *p, int32_t count, void *hip_stream, void *
   for (int i = 0; i < count; ++i) {
     h->hp[i] = make_slot(p[i]);
     if (h->hp[i].field) h->general = true;
+    if (h->hp[i].flags & FLAG_PER_WALKER) h->per_walker = true;
     h->up[i] = p[i];
     st[i] = fresh_state(p[i], 1);
     h->slot_state[i] = 1;
@@ -1154,6 +1175,7 @@ int ddqmc_slot_admit(ddqmc_t *h, const ddqmc_params *p, int32_t *slot) {
   int rc = validate(p);
   if (rc != DDQMC_OK) return rc;
   if (p->Lx * p->Ly > h->Nmax) return DDQMC_EINVAL;
+  if (p->flags & DDQMC_PER_WALKER) return DDQMC_EINVAL;
   int s = -1;
   for (int i = 0; i < h->nslots; ++i)
     if (h->slot_state[i] == 0) {

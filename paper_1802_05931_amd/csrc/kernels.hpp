@@ -805,6 +805,159 @@ __global__ __launch_bounds__(NT) void k_spawn_general(const K *__restrict__ keys
   if (int_ovf) atomicOr(&ctrl->flags, F_INT_OVF);
 }
 
+// ---- per-walker sampling (ablation of the per-entry scheme) ----------------
+// k_pw_prefix: walkers of each entry (|re| + |im| of running solves), their
+// exclusive prefix within the block of NT entries (pre) and the block totals
+// (btot); k_pw_scan: the blocks' offsets in place, the total in btot[nblk];
+// k_pw_walk: one thread per walker (grid-stride), its entry found by binary
+// search over the block offsets and then over the block's prefixes.
+template <typename K>
+__global__ __launch_bounds__(NT) void k_pw_prefix(const K *__restrict__ keys,
+                                                  const int2 *__restrict__ vals, Ctrl *ctrl,
+                                                  const SlotState *__restrict__ ss,
+                                                  unsigned long long *__restrict__ pre,
+                                                  unsigned long long *__restrict__ btot, int SB) {
+  if (ctrl->abort) return;
+  __shared__ unsigned long long w4[NT / 64];
+  const uint32_t n = ctrl->n_main;
+  const uint32_t nblk = (n + NT - 1) / NT;
+  for (uint32_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+    const uint32_t q = b * NT + threadIdx.x;
+    unsigned long long c = 0;
+    if (q < n) {
+      const int2 v = vals[q];
+      if (ss[slot_of<K>(keys[q], SB)].status == 1)
+        c = (unsigned long long)(v.x < 0 ? -(int64_t)v.x : v.x) +
+            (unsigned long long)(v.y < 0 ? -(int64_t)v.y : v.y);
+    }
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    unsigned long long inc = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned long long t = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += t;
+    }
+    __syncthreads();
+    if (lane == 63) w4[w] = inc;
+    __syncthreads();
+    unsigned long long before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) {
+      before += i < w ? w4[i] : 0ull;
+      all += w4[i];
+    }
+    if (q < n) pre[q] = before + inc - c;
+    if (threadIdx.x == 0) btot[b] = all;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_pw_scan(Ctrl *ctrl, unsigned long long *btot) {
+  if (ctrl->abort) return;
+  __shared__ unsigned long long wsum[16];
+  const uint32_t n = ctrl->n_main;
+  const uint32_t nblk = (n + NT - 1) / NT;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint32_t per = (nblk + 1023) / 1024;
+  const uint32_t b0 = tid * per < nblk ? tid * per : nblk;
+  const uint32_t b1 = (b0 + per < nblk) ? b0 + per : nblk;
+  unsigned long long local = 0;
+  for (uint32_t b = b0; b < b1; ++b) local += btot[b];
+  unsigned long long inc = local;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned long long t = __shfl_up(inc, o, 64);
+    if (lane >= o) inc += t;
+  }
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  unsigned long long before = 0;
+  for (int i = 0; i < w; ++i) before += wsum[i];
+  unsigned long long run = before + inc - local;
+  for (uint32_t b = b0; b < b1; ++b) {
+    const unsigned long long c = btot[b];
+    btot[b] = run;
+    run += c;
+  }
+  __syncthreads();
+  if (tid == 1023) btot[nblk] = before + inc;
+}
+
+template <typename K>
+__global__ __launch_bounds__(NT) void k_pw_walk(const K *__restrict__ keys,
+                                                const int2 *__restrict__ vals, Ctrl *ctrl,
+                                                const SlotParams *__restrict__ sp,
+                                                const SlotState *__restrict__ ss,
+                                                const unsigned long long *__restrict__ pre,
+                                                const unsigned long long *__restrict__ boff,
+                                                K *__restrict__ ok, int2 *__restrict__ ov,
+                                                unsigned long long *segcnt, uint32_t segcap,
+                                                int SB) {
+  if (ctrl->abort) return;
+  __shared__ K sk[STAGE];
+  __shared__ int2 sv[STAGE];
+  __shared__ uint32_t scount;
+  __shared__ unsigned long long sbase;
+  const uint32_t n = ctrl->n_main;
+  const uint32_t nblk = (n + NT - 1) / NT;
+  const unsigned long long total = boff[nblk];
+  const int seg = blockIdx.x % NSEG;
+  const K lowm = low_mask<K>(SB);
+  int rng_err = 0;
+  bool int_ovf = false;
+  const RecordSink<K> sink{sk, sv, &scount, segcnt, ok, ov, segcap, seg, &int_ovf};
+  const unsigned long long stride = (unsigned long long)gridDim.x * NT;
+  for (unsigned long long base = (unsigned long long)blockIdx.x * NT; base < total;
+       base += stride) {
+    if (threadIdx.x == 0) scount = 0;
+    __syncthreads();
+    const unsigned long long g = base + threadIdx.x;
+    if (g < total) {
+      // the block of entries holding walker g, then the entry
+      uint32_t lo = 0, hi = nblk;  // the last b with boff[b] <= g
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (boff[mid] <= g) lo = mid; else hi = mid;
+      }
+      const unsigned long long r = g - boff[lo];
+      uint32_t qlo = lo * NT, qhi = (lo + 1) * NT < n ? (lo + 1) * NT : n;
+      while (qhi - qlo > 1) {
+        const uint32_t mid = (qlo + qhi) >> 1;
+        if (pre[mid] <= r) qlo = mid; else qhi = mid;
+      }
+      // (an entry without walkers shares its prefix with the next one: the
+      // search ends on the last entry of the run, which holds the walker)
+      const uint32_t q = qlo;
+      const unsigned long long k = r - pre[q];
+      const K key = keys[q];
+      const int2 v = vals[q];
+      const uint32_t slot = slot_of<K>(key, SB);
+      const SlotParams &P = sp[slot];
+      const unsigned long long nR = (unsigned long long)(v.x < 0 ? -(int64_t)v.x : v.x);
+      const int part = k < nR ? 0 : 1;
+      const unsigned long long w = part ? k - nR : k;
+      if (w >= (unsigned long long)PW_MAX_WALKERS) {
+        rng_err = 1;
+      } else {
+        const K hibits = key & ~lowm;
+        const uint64_t cfg = (uint64_t)(key & lowm);
+        const uint32_t N = P.N;
+        const uint32_t l = (uint32_t)(cfg >> N);
+        const uint32_t m = (uint32_t)(cfg & ((N == 32) ? 0xffffffffull : ((1ull << N) - 1)));
+        walker_events(P, ss[slot].S, (uint32_t)ss[slot].step, l, m, v.x, v.y, part,
+                      (uint32_t)w, &rng_err,
+                      [&](uint32_t cl, uint32_t cm, int64_t dr, int64_t di, bool keep) {
+                        sink(hibits | (K)(((uint64_t)cl << N) | cm), dr, di, keep);
+                      });
+      }
+    }
+    __syncthreads();
+    seg_flush(sk, sv, scount < (uint32_t)STAGE ? scount : (uint32_t)STAGE, seg, segcnt, ok, ov,
+              segcap, &sbase);
+  }
+  if (rng_err) atomicOr(&ctrl->flags, F_RNG);
+  if (int_ovf) atomicOr(&ctrl->flags, F_INT_OVF);
+}
+
 // Records of solves entering the list this step (serving admissions).
 template <typename K>
 __global__ void k_inject(const K *__restrict__ ik, const int2 *__restrict__ iv, Ctrl *ctrl,

@@ -16,7 +16,7 @@ namespace ddqmc {
 
 enum { S_T_RE = 0, S_T_IM, S_NW, S_Z, S_X, S_Y, S_CXX, S_CYY, S_CZZ, S_WTOT, S_NENT, S_NSUM };
 
-enum : uint32_t { FLAG_NO_INITIATOR = 1u };
+enum : uint32_t { FLAG_NO_INITIATOR = 1u, FLAG_PER_WALKER = 2u };
 
 // Per-solve constants (device, read-only during a step).
 struct SlotParams {
@@ -622,6 +622,84 @@ DQ_HD void entry_events_field(const SlotParams &P, double S, uint32_t step, uint
     }
   }
   if (cnt.dry) *err = 1;
+}
+
+// ---- per-walker sampling (the rules of Sec. II, walker by walker) ----------
+// Walker w of part q (0 real, 1 imaginary walkers) of the entry |l><m| with
+// walkers R + iI: its clone/death along the diagonal element (dt |d_r| on its
+// own part, dt |d_i| across), and one spawning attempt per element part at a
+// uniformly chosen connection (a jump site among nJ; a hop among all nh hop
+// connections) with success probability n_conn dt |element| w_child/w_parent;
+// each probability's integer part is realised for sure and its fraction
+// drawn.  Six uniforms from the stream with draw id 0x8000 + q 2^13 +
+// (w >> 14), blocks 4 (w mod 2^14) on.  emit as in entry_events.
+constexpr int64_t PW_MAX_WALKERS = 1ll << 27;
+
+DQ_HD int64_t pw_count(double p, double u) {
+  const double f = __builtin_floor(p);
+  return (int64_t)f + ((u < p - f) ? 1 : 0);
+}
+
+template <typename Emit>
+DQ_HD void walker_events(const SlotParams &P, double S, uint32_t step, uint32_t l, uint32_t m,
+                         int32_t R, int32_t I, int part, uint32_t w, int *err, Emit &&emit) {
+  const bool diag = (l == m);
+  const int64_t nR = R < 0 ? -(int64_t)R : (int64_t)R;
+  const int64_t nI = I < 0 ? -(int64_t)I : (int64_t)I;
+  const bool init = diag || (nR + nI > P.n_a) || (P.flags & FLAG_NO_INITIATOR);
+  const int64_t sg = part ? sgn64(I) : sgn64(R);
+  const Geometry g = geometry(P, l, m);
+  const double d_r = -(P.half_gamma * (double)(popc(l) + popc(m))) - S;
+  const double d_i = P.half_jz * (double)(g.al[1] - g.al[0]);
+  const double p_r = P.dt * __builtin_fabs(d_r);
+  const double p_i = P.dt * __builtin_fabs(d_i);
+  Stream st(P.seed, P.solve, ((uint64_t)l << P.N) | m, step,
+            0x8000u + ((uint32_t)part << 13) + (w >> 14), err);
+  st.block = 4u * (w & 0x3FFFu);
+  double u[6];
+  for (int k = 0; k < 6; ++k) u[k] = st.next();
+  const int64_t cr = pw_count(p_r, u[0]);
+  const int64_t ci = pw_count(p_i, u[1]);
+  const int64_t dR = part ? -sg * sgnd(d_i) * ci : sg * sgnd(d_r) * cr;
+  const int64_t dI = part ? sg * sgnd(d_r) * cr : sg * sgnd(d_i) * ci;
+  if (dR != 0 || dI != 0) emit(l, m, dR, dI, true);
+  // one attempt along the real element part: a uniform jump site
+  const uint32_t jm = l & m;
+  const int nJ = popc(jm);
+  if (nJ > 0) {
+    int j = (int)__builtin_floor(u[2] * (double)nJ);
+    j = j > nJ - 1 ? nJ - 1 : j;
+    const int64_t c = pw_count(P.dt * ((double)nJ * P.gamma), u[3]);
+    if (c) {
+      const uint32_t bit = 1u << nth_bit(jm, j);
+      emit(l & ~bit, m & ~bit, part ? 0 : sg * c, part ? sg * c : 0, init);
+    }
+  }
+  // one attempt along the imaginary element part: a uniform hop
+  const HopClasses hc = hop_classes(P, g, l, m);
+  int nh = 0;
+  for (int c = 0; c < 6; ++c) nh += hc.n[c];
+  if (nh > 0) {
+    int j = (int)__builtin_floor(u[4] * (double)nh);
+    j = j > nh - 1 ? nh - 1 : j;
+    int c = 0;
+    while (j >= hc.n[c]) j -= hc.n[c++];
+    const int kind = c % 3;
+    const bool al = (kind == 2) ? g.T_aligned : (kind == 0);
+    const double amp = al ? P.a_al : P.a_an;
+    const double wgt = diag ? P.w_dn : (kind == 2 ? P.w_up : 1.0);
+    const int64_t cs = pw_count(P.dt * (((double)nh * amp) * wgt), u[5]);
+    if (cs) {
+      const uint32_t bm = class_member_mask(P, hc.r[c], hc.u[c], j);
+      const uint32_t cl = c < 3 ? (l ^ bm) : l;
+      const uint32_t cm = c < 3 ? m : (m ^ bm);
+      const int64_t v = sg * (int64_t)hc.sgn[c] * cs;
+      if (part == 0)
+        emit(cl, cm, 0, v, init || cl == cm);
+      else
+        emit(cl, cm, -v, 0, init || cl == cm);
+    }
+  }
 }
 
 // Tree split for small counts (M < 32, n <= 64): the same draws and leaves as
