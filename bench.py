@@ -27,6 +27,7 @@ requests one at a time), each with its own timing and equal-error check.
 Usage: python bench.py [--steps K] [--warmup W] [--workload d3|d3l] [--no-cpu] [--legs d3,d5,d4]
        python bench.py --workload d5 [--steps K]    (64 5x5 replicas, batched vs one by one)
        python bench.py --workload d4 [--requests R]  (serving loop vs one solve at a time)
+       python bench.py --workload perwalker [--steps K]  (per-walker vs per-entry sampling)
        python bench.py --trace-summary DIR --steps K
 The second form reads the kernel trace rocprofv3 wrote into DIR for a run of the
 first form and prints, per kernel, the mean dispatch duration over the last K
@@ -595,6 +596,81 @@ def bench_d3(args, log=_log):
     return out, g, cfg
 
 
+def bench_perwalker(args, log=_log):
+    """Ablation of the per-entry sampling: the 4x4 workload's steady list
+    (equilibrated with the per-entry sampler, or loaded with --load-state)
+    stepped from the same list and scalars by each sampler in turn -- per
+    entry (all of an entry's walkers drawn at once, the default) and walker
+    by walker (the rules of Sec. II, one thread per walker) -- W warm-up
+    steps, then K timed steps each.  Both have the same expectation; the
+    per-walker law spawns onto a uniformly chosen connection."""
+    import numpy as np
+    import torch
+
+    import paper_1802_05931_amd as dq
+    from paper_1802_05931_amd import autotune
+
+    cfg, desc = WORKLOADS["d3"]
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    g = dq.Solve(dq.make_params(**cfg), stream=stream)
+    if args.load_state:
+        with open(args.load_state, "rb") as f:
+            g.set_state(f.read())
+        equil_steps = g.scalars()["step"]
+    else:
+        equil_steps, _, _ = equilibrate(g, log)
+    keys, re, im = g.walkers()
+    sc = g.scalars()
+    g.close()
+    log(f"perwalker: steady list of {len(keys)} entries after {equil_steps} steps")
+    out = {}
+    for name, flags in (("per_entry", 0), ("per_walker", dq.PER_WALKER)):
+        h = dq.Solve(dq.make_params(**dict(cfg, flags=flags, capacity_hint=2 * len(keys))),
+                     stream=stream)
+        if not args.no_tuned:
+            autotune.apply(h, autotune.key_bytes(cfg["Lx"] * cfg["Ly"]))
+        h.set_walkers(keys, re, im)
+        h.set_scalars(sc["S"], sc["mode"], sc["step"], sc["nw_prev"])
+        h.step(args.warmup)
+        w0 = int(h.observables()["last"]["w_tot"])
+        h.set_profiling(max(1, min(PROF_EVERY, args.steps // 10)))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h.step(args.steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        series = h.series()
+        w_tot = series[:, 3 + list(dq.SUM_NAMES).index("w_tot")]
+        w_start = np.concatenate([[w0], w_tot[-args.steps:-1]])
+        c = h.step_counts()[-args.steps:]
+        stage_ms, stage_steps = h.stage_times()
+        spawn = sum(stage_ms[k] for k in ("scan", "gather", "loud", "heavy")) / stage_steps
+        out[name] = dict(ms_per_step=1e3 * wall / args.steps,
+                         walker_updates_per_s=float(w_start.sum()) / wall,
+                         spawn_ms_per_step=round(spawn, 5),
+                         mean_entries=float(c[:, 0].mean()),
+                         mean_spawn_records=float(c[:, 1].mean()),
+                         mean_walkers=float(w_start.mean()))
+        log(f"perwalker: {name} {out[name]['ms_per_step']:.3f} ms/step, spawn "
+            f"{out[name]['spawn_ms_per_step']:.3f} ms")
+        h.set_profiling(False)
+        h.close()
+    pe, pw = out["per_entry"], out["per_walker"]
+    return {
+        "metric": "walker-updates/s (4x4 XYZ), per-walker sampling ablation",
+        "value": pw["walker_updates_per_s"], "unit": "walker-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": pw["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "i32 walkers, f64 probabilities", "data": "synthetic",
+        "config": {"workload": desc + "; both samplers from the per-entry sampler's steady "
+                                      "list", "equilibration_steps": int(equil_steps)},
+        "per_entry": pe, "per_walker": pw,
+        "per_entry_speedup": pw["ms_per_step"] / pe["ms_per_step"],
+        "spawn_speedup": pw["spawn_ms_per_step"] / pe["spawn_ms_per_step"],
+    }
+
+
 def bench_tune(args, log=_log):
     """Tile-shape tuning (ddqmc_set_tiles): every shape timed on the 4x4
     workload's steady list, on smaller 4x4 and 3x3 lists, and on the 64-replica
@@ -701,7 +777,7 @@ def main():
                     help="steps after the equilibration, before the timed steps")
     ap.add_argument("--workload", default="d3",
                     choices=sorted(WORKLOADS) + ["d4", "d5", "tune", "census", "extrapolate",
-                                                 "susceptibility"])
+                                                 "susceptibility", "perwalker"])
     ap.add_argument("--chi-steps", type=int, default=20000,
                     help="susceptibility: steps of the 3 + 3 + 1 runs")
     ap.add_argument("--census-steps", type=int, default=20000,
@@ -772,6 +848,9 @@ def main():
         return
     if args.workload == "extrapolate":
         print(json.dumps(bench_extrapolate(args), default=float), flush=True)
+        return
+    if args.workload == "perwalker":
+        print(json.dumps(bench_perwalker(args)), flush=True)
         return
     if args.workload == "d5":
         print(json.dumps(bench_d5(args)), flush=True)
