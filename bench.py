@@ -50,15 +50,17 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 VALU_PEAK_G = 256 * 4 * 2.4 / 4  # G wave64 VALU instructions/s: 256 CUs x 4 SIMDs, 4 cycles each
 PROF_EVERY = 10  # timed steps per step with stage events
 KEY_BYTES = {True: 8, False: 4}
-# (record name, kernel name in the rocprofv3 output) of the 32-bit-key step kernels
-# whose counter records bench.py reads
-KERNEL_RECORDS = (("k_merge_write", "k_merge<unsigned int, true>"),
-                  ("k_merge_count", "k_merge<unsigned int, false>"),
-                  ("k_sort_pass", "k_sort_pass<unsigned int>"),
-                  ("k_sort_count", "k_sort_count<unsigned int>"),
-                  ("k_merge_partition", "k_merge_partition<unsigned int>"),
-                  ("k_spawn_scan", "k_spawn_scan<unsigned int>"),
-                  ("k_spawn_loud", "k_spawn_loud<unsigned int>"))
+# (record name, start of the kernel name in the rocprofv3 output) of the
+# 32-bit-key step kernels whose counter records bench.py reads; the tile shape
+# follows in the template arguments (", 8>"), and of several instantiations the
+# one that moved the most bytes is the workload's
+KERNEL_RECORDS = (("k_merge_write", "k_merge<unsigned int, true"),
+                  ("k_merge_count", "k_merge<unsigned int, false"),
+                  ("k_sort_pass", "k_sort_pass<unsigned int"),
+                  ("k_sort_count", "k_sort_count<unsigned int"),
+                  ("k_merge_partition", "k_merge_partition<unsigned int"),
+                  ("k_spawn_scan", "k_spawn_scan<unsigned int"),
+                  ("k_spawn_loud", "k_spawn_loud<unsigned int"))
 EQUIL_CHUNK = 500    # steps per equilibration chunk
 EQUIL_MIN = 2000     # equilibration steps at least
 EQUIL_MAX = 40000    # and at most
@@ -201,14 +203,18 @@ def trace_summary(directory, steps):
     print("\n".join(out))
 
 
-def counter_summary(fetch_dir, write_dir, probe_mb, workload, valu_dir=None, state=None):
+def counter_summary(fetch_dir, write_dir, probe_mb, workload, valu_dir=None, state=None,
+                    req_dir=None):
     """Mean FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the step kernels from two
     rocprofv3 --pmc runs, scaled by what the same counters read for the probe
     kernel of known traffic (an elementwise add over probe_mb MiB: reads and
     writes probe_mb MiB).  Prints a markdown table and, for the step kernels,
     the traffic records bench.py reads.  ``state`` holds the mean list entries
     and spawn records per step of the profiled run (from its bench line); the
-    records carry them, so that bench.py uses a record only on a like state."""
+    records carry them, so that bench.py uses a record only on a like state.
+    ``req_dir``, a third run with TCC_EA0_RDREQ_{32B,64B,128B}_sum, gives each
+    kernel's read bytes from its own request sizes (32, 64 and 128 bytes), a
+    cross-check of the one probe factor applied to every kernel."""
     state = {k: (state or {}).get(k) for k in ("mean_entries", "mean_spawn_records")}
     import csv
     import glob
@@ -239,24 +245,48 @@ def counter_summary(fetch_dir, write_dir, probe_mb, workload, valu_dir=None, sta
            f"scale factors are {f_scale:.4f} (fetch) and {w_scale:.4f} (write)", "",
            "| kernel | dispatches | fetch MB | write MB | HBM MB (scaled) |",
            "|---|---:|---:|---:|---:|"]
-    rec = {}
+    req = None
+    if req_dir:
+        c32, c64, c128 = (load(req_dir, f"TCC_EA0_RDREQ_{b}_sum") for b in ("32B", "64B", "128B"))
+
+        def mean(d, k):
+            return sum(d[k]) / len(d[k]) if d.get(k) else 0.0
+        req = {k: 32 * mean(c32, k) + 64 * mean(c64, k) + 128 * mean(c128, k) for k in c32}
+        pk = [k for k in req if "elementwise" in k]
+        if pk:
+            pr = max(req[k] for k in pk)
+            out[0] += (f"; by request sizes the probe read {pr / 2 ** 20:.1f} MiB "
+                       f"(of {probe_mb} MiB)")
+        out[2] = out[2].rstrip("|") + " read MB by request size | HBM MB (request sizes) |"
+        out[3] = out[3] + "---:|---:|"
+    rec, rec_req = {}, {}
     for name in sorted(fetch):
         if "elementwise" in name or name.startswith("__amd"):
             continue
         fm = sum(fetch[name]) / len(fetch[name]) * 1024 / 1e6
         wm = (sum(write[name]) / len(write[name]) * 1024 / 1e6) if name in write else 0.0
         tot = fm * f_scale + wm * w_scale
-        out.append(f"| {name} | {len(fetch[name])} | {fm:.2f} | {wm:.2f} | {tot:.2f} |")
+        line = f"| {name} | {len(fetch[name])} | {fm:.2f} | {wm:.2f} | {tot:.2f} |"
         rec[name] = tot * 1e6
+        if req is not None:
+            rm = req.get(name, 0.0) / 1e6
+            rec_req[name] = (rm + wm) * 1e6
+            line += f" {rm:.2f} | {rm + wm:.2f} |"
+        out.append(line)
     print("\n".join(out))
-    for short, name in KERNEL_RECORDS:
-        if name in rec:
-            path = os.path.join(ROOT, "profiles", f"{short}_{workload}_traffic.json")
-            with open(path, "w") as f:
-                json.dump(dict({"bytes_per_launch": rec[name], "source_hash": kernel_source_hash(),
-                                "fetch_scale": f_scale, "write_scale": w_scale}, **state), f,
-                          indent=1)
-            print(f"wrote {path}")
+    for short, prefix in KERNEL_RECORDS:
+        names = [n for n in rec if n.startswith(prefix)]
+        if not names:
+            continue
+        name = max(names, key=lambda n: rec[n])
+        path = os.path.join(ROOT, "profiles", f"{short}_{workload}_traffic.json")
+        d = {"kernel": name, "bytes_per_launch": rec[name], "source_hash": kernel_source_hash(),
+             "fetch_scale": f_scale, "write_scale": w_scale}
+        if name in rec_req:
+            d["bytes_per_launch_by_request_size"] = rec_req[name]
+        with open(path, "w") as f:
+            json.dump(dict(d, **state), f, indent=1)
+        print(f"wrote {path}")
     if valu_dir:
         valu, waves = load(valu_dir, "SQ_INSTS_VALU"), load(valu_dir, "SQ_WAVES")
         print("\n| kernel | dispatches | waves | VALU wave-instructions |\n|---|---:|---:|---:|")
@@ -804,7 +834,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--trace-summary", metavar="DIR")
     ap.add_argument("--counter-summary", nargs="+", metavar="DIR",
-                    help="FETCH_DIR WRITE_DIR [VALU_DIR]: summarise rocprofv3 --pmc runs")
+                    help="FETCH_DIR WRITE_DIR [VALU_DIR [REQ_DIR]]: summarise rocprofv3 --pmc "
+                         "runs")
     ap.add_argument("--bench-json", metavar="FILE",
                     help="with --counter-summary: the bench line of the profiled run (its "
                          "mean list entries and spawn records key the records)")
@@ -827,7 +858,7 @@ def main():
                 line = [x for x in f.read().splitlines() if x.startswith("{")][-1]
             state = json.loads(line)["config"]
         counter_summary(d[0], d[1], args.copy_probe_mb, args.workload,
-                        d[2] if len(d) > 2 else None, state)
+                        d[2] if len(d) > 2 else None, state, d[3] if len(d) > 3 else None)
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the "

@@ -141,3 +141,42 @@ def test_equilibration_waits_for_a_steady_list():
     g = _FakeSolve(1.0, 0.0)
     steps, steady, _ = bench.equilibrate(g, log=lambda m: None)
     assert steady and steps == bench.EQUIL_MIN
+
+
+def test_counter_summary_by_request_size(tmp_path, monkeypatch, capsys):
+    """With the request-size run, a kernel's read bytes are 32, 64 and 128
+    bytes per request of each size; the record carries them beside the
+    probe-scaled figure, and the kernel of several tile shapes that moved the
+    most bytes is the one recorded."""
+    dirs = {k: tmp_path / k for k in ("fetch", "write", "valu", "req")}
+    for d in dirs.values():
+        d.mkdir()
+    probe = "void at::native::elementwise_kernel<...>(...)"
+    m8 = "void ddqmc::k_merge<unsigned int, true, 8>(...)"
+    m4 = "void ddqmc::k_merge<unsigned int, true, 4>(...)"
+    _write_counters(dirs["fetch"] / "a_counter_collection.csv", "FETCH_SIZE",
+                    [(probe, 512.0), (m8, 1000.0), (m4, 10.0)])
+    _write_counters(dirs["write"] / "a_counter_collection.csv", "WRITE_SIZE",
+                    [(probe, 1024.0), (m8, 300.0), (m4, 3.0)])
+    _write_counters(dirs["valu"] / "a_counter_collection.csv", "SQ_INSTS_VALU", [(m8, 5.0)])
+    with open(dirs["req"] / "a_counter_collection.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for name, c32, c64, c128 in ((probe, 0, 0, 8192), (m8, 1000, 4000, 2000),
+                                     (m4, 10, 10, 10)):
+            for b, c in (("32B", c32), ("64B", c64), ("128B", c128)):
+                w.writerow({"Kernel_Name": name, "Counter_Name": f"TCC_EA0_RDREQ_{b}_sum",
+                            "Counter_Value": c})
+    profiles = tmp_path / "profiles"
+    profiles.mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda texts=None: "feedfacefeedface")
+    bench.counter_summary(str(dirs["fetch"]), str(dirs["write"]), 1, "t", str(dirs["valu"]),
+                          None, str(dirs["req"]))
+    out = capsys.readouterr().out
+    assert "by request sizes the probe read 1.0 MiB" in out
+    rec = json.load(open(profiles / "k_merge_write_t_traffic.json"))
+    assert rec["kernel"] == "k_merge<unsigned int, true, 8>"
+    assert abs(rec["bytes_per_launch"] - 2300 * 1024) < 1.0
+    reads = 32 * 1000 + 64 * 4000 + 128 * 2000
+    assert abs(rec["bytes_per_launch_by_request_size"] - (reads + 300 * 1024)) < 1.0

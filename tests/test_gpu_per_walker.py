@@ -119,3 +119,22 @@ def test_per_walker_refusals(dq, orc):
     with pytest.raises(dq.DDQMCError):
         pool.admit(dq.make_params(**pw))
     pool.close()
+
+
+def test_per_walker_walker_limit(dq, orc):
+    """More than 2^27 walkers on one part of one entry: the step fails with
+    DDQMC_ERNG (as the oracle's with ORC_ERNG) and the list and scalars stay
+    at the last completed step."""
+    cfg = dict(workloads.D1, flags=orc.PER_WALKER, target_walkers=2 ** 62,
+               initial_walkers=2 ** 27 + 1)
+    g = dq.Solve(dq.make_params(**cfg))
+    before, sc = g.walkers(), g.scalars()
+    with pytest.raises(dq.DDQMCError) as e:
+        g.step(1)
+    assert e.value.code == -8
+    assert _same_list(before, g.walkers()) and g.scalars() == sc
+    o = orc.Oracle(**cfg)
+    with pytest.raises(orc.OracleError) as eo:
+        o.step(1)
+    assert eo.value.code == orc.ERNG
+    g.close()

@@ -393,3 +393,17 @@ def test_per_walker_ness(orc):
     assert abs(mz - ex["mz"]) < 3 * se, (mz, ex["mz"], se)
     v, s2, _ = ratio_se(rows[:, col["cyy"]] / 4.0, rows[:, col["t_re"]])
     assert abs(v - ex["cyy"]) < 4 * s2, (v, ex["cyy"], s2)
+
+
+def test_per_walker_walker_limit(orc):
+    """Walker w of an entry part draws from the stream with draw id
+    0x8000 + part 2^13 + (w >> 14), so at most 2^27 walkers fit one part; one
+    more fails the step with ORC_ERNG and leaves the list as it was."""
+    cfg = dict(workloads.D1, flags=orc.PER_WALKER, target_walkers=2 ** 62)
+    o = orc.Oracle(**dict(cfg, initial_walkers=2 ** 27 + 1))
+    before = o.get_list()
+    with pytest.raises(orc.OracleError) as e:
+        o.step(1)
+    assert e.value.code == orc.ERNG
+    after = o.get_list()
+    assert all(np.array_equal(a, b) for a, b in zip(before, after))
