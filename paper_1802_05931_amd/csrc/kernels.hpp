@@ -1249,9 +1249,14 @@ __global__ __launch_bounds__(NT) void k_merge_partition(const K *__restrict__ Ak
 // by the tile that holds the entry.  The write pass then walks the merged
 // order with two compares per position and sums the estimators over the
 // compacted survivors.
-// Tiles per CU: with 32-bit keys a tile's LDS is 27 KB and five fit; the
-// bound holds the write pass to 96 VGPRs (without it, 101: four tiles).  With
-// 64-bit keys the LDS (35 KB) allows four.
+// Tiles per CU: with 32-bit keys and 2048 positions a count tile's LDS is
+// 27 KB and six fit; a write tile also holds the survivors' places (31 KB) and
+// five fit, at 74 VGPRs.  (The write pass used to stage the survivors' keys
+// and values in registers: at the bound's 96 VGPRs it spilled 76 bytes a
+// lane, and its launch took 139 instead of 102 us on the 4x4 step.  A count
+// pass that read the record values from HBM, with 10 KB of LDS and eight
+// tiles per CU, was slower too: 88 against 70 us.)  With 64-bit keys and 2048
+// positions the write tile's 39 KB allow four.
 template <typename K, bool WRITE, int MERGE_IT>
 __global__ __launch_bounds__(NT, sizeof(K) == 4 ? (MERGE_IT == 4 ? 8 : 5) : (MERGE_IT == 4 ? 6 : 4)) void k_merge(
     const K *__restrict__ Ak, const int2 *__restrict__ Av, const K *__restrict__ Bk,
@@ -1274,6 +1279,7 @@ __global__ __launch_bounds__(NT, sizeof(K) == 4 ? (MERGE_IT == 4 ? 8 : 5) : (MER
   __shared__ int2 sV[MERGE_TILE];
   __shared__ uint8_t sF[MERGE_TILE];  // entries: annihilated by their records;
                                       // records: run heads that become new entries
+  __shared__ uint16_t sIdx[WRITE ? MERGE_TILE : 1];  // survivors' places in sK / sV, in order
   __shared__ uint32_t s_i0, s_i1;
   __shared__ K s_aprev, s_bprev, s_bnext;  // the keys just outside the tile
   __shared__ uint32_t scan4[NT / 64];
@@ -1327,12 +1333,11 @@ __global__ __launch_bounds__(NT, sizeof(K) == 4 ? (MERGE_IT == 4 ? 8 : 5) : (MER
       return Bk[j];
     };
     auto bval = [&](uint32_t j) -> int2 { return (j >= j0 && j < j1) ? sBv[j - j0] : Bv[j]; };
-    auto run_from = [&](uint32_t j, K k) -> RunSum {
+    // the run of key k from record j on, whose first value v0 the caller read
+    auto run_from = [&](uint32_t j, K k, int2 v0) -> RunSum {
       RunSum s{0, 0, 0, 0};
-      while (j < nb && bkey(j) == k) {
-        run_add(s, bval(j));
-        ++j;
-      }
+      run_add(s, v0);
+      for (++j; j < nb && bkey(j) == k; ++j) run_add(s, bval(j));
       return s;
     };
     // the tile's first solve: its parameters once, in registers
@@ -1348,17 +1353,11 @@ __global__ __launch_bounds__(NT, sizeof(K) == 4 ? (MERGE_IT == 4 ? 8 : 5) : (MER
     auto fits = [](int64_t R, int64_t I) {
       return R <= 2147483647LL && R >= -2147483647LL && I <= 2147483647LL && I >= -2147483647LL;
     };
-    // an occupied entry and the sums of its run: annihilated, or its new value
-    auto patch = [&](uint32_t p, const RunSum &rs) {
-      int64_t R, I;
-      if (WRITE) {
-        R = (int64_t)sAv[p].x + rs.aR;
-        I = (int64_t)sAv[p].y + rs.aI;
-      } else {
-        const int2 av = Av[i0 + p];
-        R = (int64_t)av.x + rs.aR;
-        I = (int64_t)av.y + rs.aI;
-      }
+    // an occupied entry (value av) and the sums of its run: annihilated, or
+    // its new value
+    auto patch = [&](uint32_t p, int2 av, const RunSum &rs) {
+      const int64_t R = (int64_t)av.x + rs.aR;
+      const int64_t I = (int64_t)av.y + rs.aI;
       if (R == 0 && I == 0) {
         sAdel[p] = 1;
       } else if (WRITE) {
@@ -1375,10 +1374,13 @@ __global__ __launch_bounds__(NT, sizeof(K) == 4 ? (MERGE_IT == 4 ? 8 : 5) : (MER
       uint8_t out = 0;
       // an entry right before the tile with this key already took the run
       if (head && !(i0 > 0 && s_aprev == k)) {
-        const RunSum rs = run_from(gj, k);
+        const int2 v0 = sBv[j];
         const uint32_t p = lower_bound(sAk, nA, k);
-        if (p < nA && sAk[p] == k) {
-          patch(p, rs);
+        const bool hit = p < nA && sAk[p] == k;
+        const int2 av = !hit ? make_int2(0, 0) : WRITE ? sAv[p] : Av[i0 + p];
+        const RunSum rs = run_from(gj, k, v0);
+        if (hit) {
+          patch(p, av, rs);
         } else {
           const uint32_t slot = slot_of<K>(k, SB);
           uint32_t l, m;
@@ -1400,7 +1402,7 @@ __global__ __launch_bounds__(NT, sizeof(K) == 4 ? (MERGE_IT == 4 ? 8 : 5) : (MER
     // the tile's last entry, when its run starts right after the tile
     if (threadIdx.x == 0 && nA > 0 && j1 < nb && s_bnext == sAk[nA - 1] &&
         (nB == 0 || sBk[nB - 1] != s_bnext))
-      patch(nA - 1, run_from(j1, s_bnext));
+      patch(nA - 1, WRITE ? sAv[nA - 1] : Av[i0 + nA - 1], run_from(j1, s_bnext, Bv[j1]));
     __syncthreads();
 
     if (!WRITE) {
@@ -1437,43 +1439,45 @@ __global__ __launch_bounds__(NT, sizeof(K) == 4 ? (MERGE_IT == 4 ? 8 : 5) : (MER
       a = lo;
       b = dd - lo;
     }
-    K ck[MERGE_IT];
-    int2 cv[MERGE_IT];
+    // each merged position's place in sK / sV (entries at a, records at
+    // nA + b < MERGE_TILE), 16 bits each, two to a register, and a mask of
+    // the survivors
+    static_assert(MERGE_IT % 2 == 0 && NT * MERGE_IT <= 65536, "16-bit places");
+    uint32_t src[MERGE_IT / 2];
+#pragma unroll
+    for (int i = 0; i < MERGE_IT / 2; ++i) src[i] = 0;
     uint32_t okm = 0, nsurv = 0;
 #pragma unroll
     for (int it = 0; it < MERGE_IT; ++it) {
       if (dd + (uint32_t)it >= len) continue;
+      uint32_t at;
+      bool ok;
       if (a < nA && (b >= nB || sAk[a] <= sBk[b])) {
-        const K k = sAk[a];
-        if (!sAdel[a] && !leaving(slot_of<K>(k, SB))) {
-          ck[it] = k;
-          cv[it] = sAv[a];
-          okm |= 1u << it;
-          ++nsurv;
-        }
+        ok = !sAdel[a] && !leaving(slot_of<K>(sAk[a], SB));
+        at = a;
         ++a;
       } else {
-        if (sBout[b]) {
-          ck[it] = sBk[b];
-          cv[it] = sBv[b];
-          okm |= 1u << it;
-          ++nsurv;
-        }
+        ok = sBout[b] != 0;
+        at = nA + b;
         ++b;
+      }
+      src[it >> 1] |= at << (16 * (it & 1));
+      if (ok) {
+        okm |= 1u << it;
+        ++nsurv;
       }
     }
     uint32_t ttot;
     const uint32_t lpos = block_excl_scan(nsurv, scan4, &ttot);
     const uint32_t gbase = tile_cnt[t];
-    // stage the survivors in LDS (over the tile's entries and records)
-    __syncthreads();
+    // the survivors' places in merged order, then the barrier (sK and sV
+    // stay as they are)
     {
       uint32_t q = lpos;
 #pragma unroll
       for (int it = 0; it < MERGE_IT; ++it)
         if (okm & (1u << it)) {
-          sAk[q] = ck[it];
-          sAv[q] = cv[it];
+          sIdx[q] = (uint16_t)(src[it >> 1] >> (16 * (it & 1)));
           ++q;
         }
     }
@@ -1483,8 +1487,9 @@ __global__ __launch_bounds__(NT, sizeof(K) == 4 ? (MERGE_IT == 4 ? 8 : 5) : (MER
 #pragma unroll
     for (int s = 0; s < S_NSUM; ++s) acc[s] = 0;
     for (uint32_t q = threadIdx.x; q < ttot; q += NT) {
-      const K k = sAk[q];
-      const int2 v = sAv[q];
+      const uint32_t at = sIdx[q];
+      const K k = sK[at];
+      const int2 v = sV[at];
       const uint32_t g = gbase + q;
       if (g < capC) {
         Ck[g] = k;
