@@ -1,7 +1,7 @@
 // C ABI of the DDQMC step library (declared in include/ddqmc.h).
 //
 // A handle owns a sorted walker list (two ping-pong buffers), the spawn-record
-// buffers of the radix sort and its tile counts, per-tile estimator partials
+// buffers of the radix sort and its tile counts, the estimator sums per solve
 // and the per-solve parameter/state tables.  One step is a fixed sequence of
 // launches on the handle's stream (kernels.hpp); the host synchronises only at
 // the end of a chunk of steps, reads the control block and, if a buffer was too
@@ -80,7 +80,6 @@ struct ddqmc_t {
   int2 *sv[2] = {nullptr, nullptr};
   uint32_t *sort_cnt = nullptr;  // sort: digit counts of the tiles, then their prefixes
   uint32_t *tile_cnt = nullptr;  // merge: survivors per tile, then offsets
-  Partial *partials = nullptr;
   uint32_t *hist = nullptr;
   Ctrl *ctrl = nullptr;
   SlotParams *dsp = nullptr;
@@ -183,7 +182,7 @@ FixedLayout fixed_layout(int nslots, size_t ks) {
   L.ctrl = take(sizeof(Ctrl));
   L.dsp = take((size_t)nslots * sizeof(SlotParams));
   L.dss = take((size_t)nslots * sizeof(SlotState));
-  L.spill = take((size_t)nslots * S_NSUM * sizeof(unsigned long long));
+  L.spill = take((size_t)nslots * SUM_BUCKETS * S_NSUM * sizeof(unsigned long long));
   L.series = take((size_t)SERIES_CAP * nslots * SERIES_W * sizeof(int64_t));
   L.counts = take((size_t)SERIES_CAP * COUNT_W * sizeof(uint32_t));
   L.inj_k = take((size_t)nslots * ks);
@@ -198,7 +197,7 @@ FixedLayout fixed_layout(int nslots, size_t ks) {
 // record capacity cap_sp (rounded up to whole segments).
 struct SizedLayout {
   uint64_t cap_main, cap_sp;
-  size_t mk[2], mv[2], sk[2], sv[2], sort_cnt, tile_cnt, partials, part;
+  size_t mk[2], mv[2], sk[2], sv[2], sort_cnt, tile_cnt, part;
   size_t heavy, late, lidx, lkey, lval, total;
 };
 SizedLayout sized_layout(size_t ks, uint64_t cap_main, uint64_t cap_sp) {
@@ -223,7 +222,6 @@ SizedLayout sized_layout(size_t ks, uint64_t cap_main, uint64_t cap_sp) {
   L.sort_cnt = take(sort_tiles(cap_sp) * 256 * sizeof(uint32_t));
   const uint64_t t = merge_tiles(cap_main, cap_sp);
   L.tile_cnt = take((t + 1) * sizeof(uint32_t));
-  L.partials = take(t * sizeof(Partial));
   L.part = take((t + 1) * sizeof(uint32_t));
   // the loud list (index, key, value) and the two heavy queues: at most one
   // place per list entry each
@@ -369,7 +367,6 @@ void bind_sized(ddqmc_t *h, char *base, const SizedLayout &L) {
   }
   h->sort_cnt = (uint32_t *)(base + L.sort_cnt);
   h->tile_cnt = (uint32_t *)(base + L.tile_cnt);
-  h->partials = (Partial *)(base + L.partials);
   h->part = (uint32_t *)(base + L.part);
   h->heavy = (uint32_t *)(base + L.heavy);
   h->late = (uint32_t *)(base + L.late);
@@ -651,25 +648,25 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
     const int2 *bv = h->sv[sp];
     if (h->merge_it == 4)
       k_merge<K, false, 4><<<g_m, NT, 0, s>>>(ak, av, bk, bv, ck, cv, capC, h->ctrl, h->dsp,
-                                              h->dss, h->partials, h->spill, h->tile_cnt, h->part,
+                                              h->dss, h->spill, h->tile_cnt, h->part,
                                               h->SB);
     else
       k_merge<K, false, 8><<<g_m, NT, 0, s>>>(ak, av, bk, bv, ck, cv, capC, h->ctrl, h->dsp,
-                                              h->dss, h->partials, h->spill, h->tile_cnt, h->part,
+                                              h->dss, h->spill, h->tile_cnt, h->part,
                                               h->SB);
     k_merge_offsets<<<1, 1024, 0, s>>>(h->ctrl, h->tile_cnt, merge_tile);
     if (ev) HIPC(hipEventRecord(ev->e[8], s));
     if (h->merge_it == 4)
       k_merge<K, true, 4><<<g_m, NT, 0, s>>>(ak, av, bk, bv, ck, cv, capC, h->ctrl, h->dsp,
-                                             h->dss, h->partials, h->spill, h->tile_cnt, h->part,
+                                             h->dss, h->spill, h->tile_cnt, h->part,
                                              h->SB);
     else
       k_merge<K, true, 8><<<g_m, NT, 0, s>>>(ak, av, bk, bv, ck, cv, capC, h->ctrl, h->dsp,
-                                             h->dss, h->partials, h->spill, h->tile_cnt, h->part,
+                                             h->dss, h->spill, h->tile_cnt, h->part,
                                              h->SB);
   }
   if (ev) HIPC(hipEventRecord(ev->e[9], s));
-  k_finalize<<<1, 1024, 0, s>>>(h->ctrl, h->dsp, h->dss, h->partials, h->spill, h->nslots,
+  k_finalize<<<1, 1024, 0, s>>>(h->ctrl, h->dsp, h->dss, h->spill, h->nslots,
                                 h->hist, h->passes, capC, h->segcnt, h->series, h->counts,
                                 SERIES_CAP, merge_tile);
   if (ev) HIPC(hipEventRecord(ev->e[10], s));
@@ -885,7 +882,7 @@ int run_steps(ddqmc_t *h, int64_t n) {
       const uint32_t f = c.fail_flags;
       const uint64_t seg_need = c.seg_need, need_main = c.n_new;
       k_rearm<<<1, 256, 0, h->stream>>>(h->ctrl, h->hist, MAX_PASSES, h->spill,
-                                         h->nslots * S_NSUM, h->segcnt);
+                                         h->nslots * SUM_BUCKETS * S_NSUM, h->segcnt);
       HIPC(hipGetLastError());
       HIPC(hipStreamSynchronize(h->stream));
       if (f & F_INT_OVF) return DDQMC_EOVERFLOW;

@@ -89,11 +89,11 @@ struct Ctrl {
   uint32_t seg_prefix[NSEG + 1];  // record offsets of the segments
 };
 
-struct Partial {
-  int32_t slot;
-  int32_t pad;
-  int64_t s[S_NSUM];
-};
+// The merge's estimator sums go to SUM_BUCKETS buckets per solve, tile t
+// into bucket t mod SUM_BUCKETS (with int64 atomics: exact, in any order), so
+// that no address takes more than a few hundred adds per step and the
+// finalize kernel reads SUM_BUCKETS x S_NSUM words per solve.
+constexpr int SUM_BUCKETS = 64;
 
 // ---- small helpers --------------------------------------------------------
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
@@ -1262,7 +1262,7 @@ __global__ __launch_bounds__(NT, sizeof(K) == 4 ? (MERGE_IT == 4 ? 8 : 5) : (MER
     const K *__restrict__ Ak, const int2 *__restrict__ Av, const K *__restrict__ Bk,
     const int2 *__restrict__ Bv, K *__restrict__ Ck, int2 *__restrict__ Cv, uint32_t capC,
     Ctrl *ctrl, const SlotParams *__restrict__ sp, const SlotState *__restrict__ ss,
-    Partial *__restrict__ partials, unsigned long long *__restrict__ spill,
+    unsigned long long *__restrict__ spill,
     uint32_t *__restrict__ tile_cnt, const uint32_t *__restrict__ part, int SB) {
   if (ctrl->abort || (ctrl->flags & F_SPAWN_CAP)) return;
   constexpr uint32_t MERGE_TILE = NT * MERGE_IT;
@@ -1299,12 +1299,8 @@ __global__ __launch_bounds__(NT, sizeof(K) == 4 ? (MERGE_IT == 4 ? 8 : 5) : (MER
     if (i1 < i0 || i1 > na || i0 > d0 || i1 > d1 || j1 < j0 || j1 > nb) {
       if (threadIdx.x == 0) {
         atomicOr(&ctrl->flags, F_ORDER);
-        if (WRITE)
-          partials[t].slot = 0;
-        else
-          tile_cnt[t] = 0;
+        if (!WRITE) tile_cnt[t] = 0;
       }
-      if (WRITE && threadIdx.x < S_NSUM) partials[t].s[threadIdx.x] = 0;  // (finalize reads them)
       continue;
     }
     const uint32_t nA = i1 - i0, nB = j1 - j0;
@@ -1503,7 +1499,8 @@ __global__ __launch_bounds__(NT, sizeof(K) == 4 ? (MERGE_IT == 4 ? 8 : 5) : (MER
       } else {
         const SlotParams &P = sp[slot];
         ket_bra(k, P.N, l, m);
-        unsigned long long *const sums = spill + (size_t)slot * S_NSUM;
+        unsigned long long *const sums =
+            spill + ((size_t)slot * SUM_BUCKETS + t % SUM_BUCKETS) * S_NSUM;
         entry_sums(P, l, m, v.x, v.y, [&](int s, int64_t x) {
           if (x) atomicAdd(&sums[s], (unsigned long long)x);
         });
@@ -1520,8 +1517,9 @@ __global__ __launch_bounds__(NT, sizeof(K) == 4 ? (MERGE_IT == 4 ? 8 : 5) : (MER
       int64_t v = 0;
 #pragma unroll
       for (int ww = 0; ww < NT / 64; ++ww) v += red[ww][threadIdx.x];
-      partials[t].s[threadIdx.x] = v;
-      if (threadIdx.x == 0) partials[t].slot = (int32_t)s0;
+      if (v)
+        atomicAdd(&spill[((size_t)s0 * SUM_BUCKETS + t % SUM_BUCKETS) * S_NSUM + threadIdx.x],
+                  (unsigned long long)v);
     }
   }
   if (int_ovf) atomicOr(&ctrl->flags, F_INT_OVF);
@@ -1557,8 +1555,8 @@ __global__ __launch_bounds__(1024) void k_merge_offsets(Ctrl *ctrl, uint32_t *cn
 
 // ---- finalize (one block) ---------------------------------------------------
 __global__ __launch_bounds__(1024) void k_finalize(Ctrl *ctrl, const SlotParams *__restrict__ sp,
-                                                   SlotState *ss, const Partial *partials,
-                                                   unsigned long long *spill, int nslots,
+                                                   SlotState *ss, unsigned long long *spill,
+                                                   int nslots,
                                                    uint32_t *hist, int passes, uint32_t capC,
                                                    unsigned long long *segcnt, int64_t *series,
                                                    uint32_t *counts, uint32_t series_cap,
@@ -1567,7 +1565,7 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctrl *ctrl, const SlotParams 
   __shared__ unsigned long long sums[MAX_SLOTS * S_NSUM];
   __shared__ uint32_t s_bad;
   const int tid = threadIdx.x, nt = blockDim.x;
-  // a spawn overflow means the merge did not run: its partials are not valid
+  // a spawn overflow means the merge did not run: its sums are not valid
   if (ctrl->flags & F_SPAWN_CAP) {
     if (tid == 0) {
       ctrl->fail_flags = ctrl->flags | F_SPAWN_CAP;
@@ -1575,61 +1573,24 @@ __global__ __launch_bounds__(1024) void k_finalize(Ctrl *ctrl, const SlotParams 
     }
     return;
   }
-  for (int i = tid; i < nslots * S_NSUM; i += nt) {
-    sums[i] = spill[i];
-    spill[i] = 0;
-  }
+  for (int i = tid; i < nslots * S_NSUM; i += nt) sums[i] = 0;
   if (tid == 0) s_bad = 0;
+  __syncthreads();
+  // every solve's buckets (a thread per bucket), cleared for the next step
+  for (int i = tid; i < nslots * SUM_BUCKETS; i += nt) {
+    unsigned long long *const b = spill + (size_t)i * S_NSUM;
+    unsigned long long v[S_NSUM];
+#pragma unroll
+    for (int k = 0; k < S_NSUM; ++k) v[k] = b[k];
+#pragma unroll
+    for (int k = 0; k < S_NSUM; ++k) {
+      b[k] = 0;
+      if (v[k]) atomicAdd(&sums[(i / SUM_BUCKETS) * S_NSUM + k], v[k]);
+    }
+  }
   __syncthreads();
   const uint32_t total = ctrl->n_main + ctrl->n_spawn;
   const uint32_t ntiles = (total + merge_tile - 1) / merge_tile;
-  {
-    // tiles strided over the threads (coalesced reads); a thread's sums go to
-    // LDS whenever its solve changes, and at the end a wave whose lanes all
-    // hold the same solve adds its sums once
-    // (FIN_BATCH tiles per thread are loaded before any is added, so that
-    // their loads are in flight together)
-    constexpr int FIN_BATCH = 4;
-    int cur = -1;
-    int64_t a[S_NSUM];
-    for (int s = 0; s < S_NSUM; ++s) a[s] = 0;
-    for (uint32_t t0 = (uint32_t)tid; t0 < ntiles; t0 += FIN_BATCH * (uint32_t)nt) {
-      Partial pb[FIN_BATCH];
-#pragma unroll
-      for (int u = 0; u < FIN_BATCH; ++u) {
-        const uint32_t t = t0 + (uint32_t)u * (uint32_t)nt;
-        if (t < ntiles) pb[u] = partials[t];
-      }
-#pragma unroll
-      for (int u = 0; u < FIN_BATCH; ++u) {
-        if (t0 + (uint32_t)u * (uint32_t)nt >= ntiles) break;
-        const int sl = pb[u].slot;
-        if (sl != cur) {
-          if (cur >= 0)
-            for (int s = 0; s < S_NSUM; ++s)
-              if (a[s]) atomicAdd(&sums[cur * S_NSUM + s], (unsigned long long)a[s]);
-          cur = sl;
-          for (int s = 0; s < S_NSUM; ++s) a[s] = 0;
-        }
-#pragma unroll
-        for (int s = 0; s < S_NSUM; ++s) a[s] += pb[u].s[s];
-      }
-    }
-    const int c0 = __shfl(cur, 0, 64);
-    const bool same = __ballot(cur != c0) == 0;  // wave-uniform
-    if (same) {
-#pragma unroll
-      for (int s = 0; s < S_NSUM; ++s) {
-        const int64_t v = wave_sum(a[s]);
-        if ((tid & 63) == 0 && c0 >= 0 && v)
-          atomicAdd(&sums[c0 * S_NSUM + s], (unsigned long long)v);
-      }
-    } else if (cur >= 0) {
-      for (int s = 0; s < S_NSUM; ++s)
-        if (a[s]) atomicAdd(&sums[cur * S_NSUM + s], (unsigned long long)a[s]);
-    }
-  }
-  __syncthreads();
   uint32_t flags = ctrl->flags;
   const uint32_t n_new = ntiles ? ctrl->n_new : 0u;
   if (n_new > capC) flags |= F_MAIN_CAP;
