@@ -24,7 +24,8 @@ The default line also carries the two systems forms beside the plain step:
 after another) and "served" (the 512-request serving stream against the same
 requests one at a time), each with its own timing and equal-error check.
 
-Usage: python bench.py [--steps K] [--warmup W] [--workload d3|d3l] [--no-cpu] [--legs d3,d5,d4]
+Usage: python bench.py [--steps K] [--warmup W] [--workload d3|d3l|d3f|d3big] [--no-cpu]
+                       [--legs d3,d5,d4]
        python bench.py --workload d5 [--steps K]    (64 5x5 replicas, batched vs one by one)
        python bench.py --workload d4 [--requests R]  (serving loop vs one solve at a time)
        python bench.py --workload perwalker [--steps K]  (per-walker vs per-entry sampling)
@@ -80,6 +81,11 @@ WORKLOADS = {
     "d3big": (dict(workloads.D3, n_a=0),
               "4x4 periodic dissipative XYZ, Jx 0.9 Jy 1 Jz 1 gamma 1, dt 0.002, no initiator, "
               "IS p 1.5, 1e7 walkers, timed as its growing list passes 1e8 entries"),
+    # the in-plane field along x (Sec. V.B): the parity rule no longer holds,
+    # and every spawn goes through the general sampling routine
+    "d3f": (dict(workloads.D3, hx=0.05),
+            "4x4 periodic dissipative XYZ, Jx 0.9 Jy 1 Jz 1 gamma 1, dt 0.002, n_a 3, "
+            "IS p 1.5, in-plane field hx 0.05, 1e7 walkers"),
     "d3l": (dict(workloads.D3, is_p=0.0),
             "4x4 periodic dissipative XYZ, Jx 0.9 Jy 1 Jz 1 gamma 1, dt 0.002, n_a 3, "
             "no IS, 1e7 walkers"),

@@ -77,8 +77,9 @@ typedef struct {
   uint32_t flags;           /* DDQMC_NO_INITIATOR | DDQMC_PER_WALKER                */
   double hx, hy;            /* in-plane field sum_i hx sigma^x_i + hy sigma^y_i, i.e.
                                h (cos theta, sin theta) of Sec. V.B; 0, 0 = none.
-                               A handle with a field on takes the general spawn
-                               path (one thread per entry) for all its solves   */
+                               In a handle with a field on, every solve's
+                               entries with events are sampled one thread
+                               each by the general routine (same results)     */
 } ddqmc_params;
 
 /* Sums over the walker list after a step (Sec. III.A numerators/denominators):

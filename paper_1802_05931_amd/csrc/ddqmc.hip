@@ -555,12 +555,16 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
     if (ev) HIPC(hipEventRecord(ev->e[3], s));
     if (ev) HIPC(hipEventRecord(ev->e[4], s));
   } else if (h->general) {
-    // the in-plane field: every entry through the general path (timed as the
-    // loud stage; the scan, gather and heavy stages are empty)
+    // the in-plane field: the quiet scan on the field's probabilities, then
+    // every entry with events, one thread each (timed as the loud stage; the
+    // gather and heavy stages are empty)
+    k_spawn_scan<K, true><<<h->nscan, NT, 0, s>>>(ak, av, h->ctrl, h->dsp, h->dss, h->lidx,
+                                                 (K *)h->lkey, h->lval, h->heavy, h->SB);
     if (ev) HIPC(hipEventRecord(ev->e[1], s));
     if (ev) HIPC(hipEventRecord(ev->e[2], s));
-    k_spawn_general<K><<<h->general_blocks, NT, 0, s>>>(ak, av, c, h->dsp, h->dss, (K *)h->sk[0],
-                                                        h->sv[0], h->segcnt, segcap, h->SB);
+    k_spawn_listed<K><<<h->general_blocks, NT, 0, s>>>(c, h->dsp, h->dss, (const K *)h->lkey,
+                                                       h->lval, (K *)h->sk[0], h->sv[0],
+                                                       h->segcnt, segcap, h->SB);
     if (ev) HIPC(hipEventRecord(ev->e[3], s));
     if (ev) HIPC(hipEventRecord(ev->e[4], s));
   } else {

@@ -198,7 +198,7 @@ __device__ __forceinline__ K low_mask(int SB) {
 // (large populations, a few hundred) go straight to the heavy list.
 constexpr uint32_t LOUD_STAGE = 1024;  // staged loud entries per block (>= 2 NT)
 
-template <typename K>
+template <typename K, bool GENERAL = false>
 __global__ __launch_bounds__(NT) void k_spawn_scan(const K *__restrict__ keys,
                                                    const int2 *__restrict__ vals, Ctrl *ctrl,
                                                    const SlotParams *__restrict__ sp,
@@ -252,6 +252,13 @@ __global__ __launch_bounds__(NT) void k_spawn_scan(const K *__restrict__ keys,
       const uint32_t N = P.N;
       const uint32_t l = (uint32_t)(cfg >> N);
       const uint32_t m = (uint32_t)(cfg & ((N == 32) ? 0xffffffffull : ((1ull << N) - 1)));
+      // (a handle with the field sends every entry with events to the loud
+      // list, sampled by k_spawn_listed)
+      if (GENERAL) {
+        const int k = P.field ? entry_kind_field(P, S, step, l, m, v.x, v.y)
+                              : entry_kind(P, S, step, l, m, v.x, v.y);
+        return k == ENTRY_QUIET ? (int)ENTRY_QUIET : (int)ENTRY_LIGHT;
+      }
       return entry_kind(P, S, step, l, m, v.x, v.y);
     };
     int kind = ENTRY_QUIET;
@@ -748,25 +755,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MINW))) void
   if (int_ovf) atomicOr(&ctrl->flags, F_INT_OVF);
 }
 
-// The general spawn path, one thread per entry of the whole list (no quiet
-// scan): taken when some solve of the handle has the in-plane field on (its
-// entries use entry_events_field; the others entry_events, the same draws as
-// the scan / loud / heavy kernels).  Records are staged in LDS per block
+// The loud list's entries (every entry with events, in a handle with the
+// field), one thread each: entry_events_field for the solves with the field,
+// entry_events for the others.  Records are staged in LDS per block
 // iteration and flushed into the block's segment.
 template <typename K>
-__global__ __launch_bounds__(NT) void k_spawn_general(const K *__restrict__ keys,
-                                                      const int2 *__restrict__ vals, Ctrl *ctrl,
-                                                      const SlotParams *__restrict__ sp,
-                                                      const SlotState *__restrict__ ss,
-                                                      K *__restrict__ ok, int2 *__restrict__ ov,
-                                                      unsigned long long *segcnt, uint32_t segcap,
-                                                      int SB) {
+__global__ __launch_bounds__(NT) void k_spawn_listed(Ctrl *ctrl,
+                                                     const SlotParams *__restrict__ sp,
+                                                     const SlotState *__restrict__ ss,
+                                                     const K *__restrict__ lkey,
+                                                     const int2 *__restrict__ lval,
+                                                     K *__restrict__ ok, int2 *__restrict__ ov,
+                                                     unsigned long long *segcnt, uint32_t segcap,
+                                                     int SB) {
   if (ctrl->abort) return;
   __shared__ K sk[STAGE];
   __shared__ int2 sv[STAGE];
   __shared__ uint32_t scount;
   __shared__ unsigned long long sbase;
-  const uint32_t n = ctrl->n_main;
+  const uint32_t n = ctrl->n_loud;
   const int seg = blockIdx.x % NSEG;
   const K lowm = low_mask<K>(SB);
   int rng_err = 0;
@@ -777,25 +784,23 @@ __global__ __launch_bounds__(NT) void k_spawn_general(const K *__restrict__ keys
     __syncthreads();
     const uint32_t q = base + threadIdx.x;
     if (q < n) {
-      const K key = keys[q];
-      const int2 v = vals[q];
+      const K key = lkey[q];
+      const int2 v = lval[q];
       const uint32_t slot = slot_of<K>(key, SB);
-      if (ss[slot].status == 1) {
-        const SlotParams &P = sp[slot];
-        const K hibits = key & ~lowm;
-        const uint64_t cfg = (uint64_t)(key & lowm);
-        const uint32_t N = P.N;
-        const uint32_t l = (uint32_t)(cfg >> N);
-        const uint32_t m = (uint32_t)(cfg & ((N == 32) ? 0xffffffffull : ((1ull << N) - 1)));
-        const uint32_t step = (uint32_t)ss[slot].step;
-        auto rec = [&](uint32_t cl, uint32_t cm, int64_t dr, int64_t di, bool keep) {
-          sink(hibits | (K)(((uint64_t)cl << N) | cm), dr, di, keep);
-        };
-        if (P.field)
-          entry_events_field(P, ss[slot].S, step, l, m, v.x, v.y, &rng_err, rec);
-        else
-          entry_events(P, ss[slot].S, step, l, m, v.x, v.y, &rng_err, rec);
-      }
+      const SlotParams &P = sp[slot];
+      const K hibits = key & ~lowm;
+      const uint64_t cfg = (uint64_t)(key & lowm);
+      const uint32_t N = P.N;
+      const uint32_t l = (uint32_t)(cfg >> N);
+      const uint32_t m = (uint32_t)(cfg & ((N == 32) ? 0xffffffffull : ((1ull << N) - 1)));
+      const uint32_t step = (uint32_t)ss[slot].step;
+      auto rec = [&](uint32_t cl, uint32_t cm, int64_t dr, int64_t di, bool keep) {
+        sink(hibits | (K)(((uint64_t)cl << N) | cm), dr, di, keep);
+      };
+      if (P.field)
+        entry_events_field(P, ss[slot].S, step, l, m, v.x, v.y, &rng_err, rec);
+      else
+        entry_events(P, ss[slot].S, step, l, m, v.x, v.y, &rng_err, rec);
     }
     __syncthreads();
     seg_flush(sk, sv, scount < (uint32_t)STAGE ? scount : (uint32_t)STAGE, seg, segcnt, ok, ov,

@@ -512,6 +512,50 @@ DQ_HD void field_parts(const SlotParams &P, const HopClasses &hc, uint32_t l, ui
 // and field flips, each part's walkers placed by one class split (sequential
 // conditional binomials, the last class with weight taking the rest; one
 // walker by one categorical pick) and the member trees.
+// The eight channel probabilities and walker counts of an entry of a solve
+// with the field (clone/death along the diagonal element; spawning along the
+// Re part: jumps and field flips; along the Im part: hops and field flips),
+// with the diagonal element (d_r, d_i), the hop classes and the field classes.
+DQ_HD void field_channels(const SlotParams &P, double S, uint32_t l, uint32_t m, int64_t nR,
+                          int64_t nI, double &d_r, double &d_i, HopClasses &hc, FieldParts &f,
+                          double p8[8], int64_t n8[8]) {
+  const Geometry g = geometry(P, l, m);
+  d_r = -(P.half_gamma * (double)(popc(l) + popc(m))) - S;
+  d_i = P.half_jz * (double)(g.al[1] - g.al[0]);
+  const double p_r = P.dt * __builtin_fabs(d_r);
+  const double p_i = P.dt * __builtin_fabs(d_i);
+  hc = hop_classes(P, g, l, m);
+  field_parts(P, hc, l, m, f);
+  const double P_re = P.dt * f.Sc[0][0];
+  const double P_im = P.dt * f.Sc[1][0];
+  const double pp[4] = {p_r, p_i, P_re, P_im};
+  for (int k = 0; k < 4; ++k) {
+    p8[k] = pp[k];
+    p8[k + 4] = pp[k];
+    n8[k] = nR;
+    n8[k + 4] = nI;
+  }
+}
+
+// The scan's decision for an entry of a solve with the field: quiet when the
+// primary uniform says that none of its eight channels fires (the test
+// channel_counts makes on the same probabilities), else sampled.
+DQ_HD int entry_kind_field(const SlotParams &P, double S, uint32_t step, uint32_t l, uint32_t m,
+                           int32_t R, int32_t I) {
+  const int64_t nR = R < 0 ? -(int64_t)R : (int64_t)R;
+  const int64_t nI = I < 0 ? -(int64_t)I : (int64_t)I;
+  double d_r, d_i, p8[8];
+  int64_t n8[8];
+  HopClasses hc;
+  FieldParts f;
+  field_channels(P, S, l, m, nR, nI, d_r, d_i, hc, f, p8, n8);
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (n8[k] > 0 && p8[k] >= 1.0) return ENTRY_LIGHT;
+  Stream prim(P.seed, P.solve, ((uint64_t)l << P.N) | m, step, 0, nullptr);
+  return (quiet_test(p8, n8, prim.next()) & 1) ? ENTRY_QUIET : ENTRY_LIGHT;
+}
+
 template <typename Emit>
 DQ_HD void entry_events_field(const SlotParams &P, double S, uint32_t step, uint32_t l,
                               uint32_t m, int32_t R, int32_t I, int *err, Emit &&emit) {
@@ -520,25 +564,11 @@ DQ_HD void entry_events_field(const SlotParams &P, double S, uint32_t step, uint
   const int64_t nI = I < 0 ? -(int64_t)I : (int64_t)I;
   const int64_t sR = sgn64(R), sI = sgn64(I);
   const bool init = diag || (nR + nI > P.n_a) || (P.flags & FLAG_NO_INITIATOR);
-  const Geometry g = geometry(P, l, m);
-  const double d_r = -(P.half_gamma * (double)(popc(l) + popc(m))) - S;
-  const double d_i = P.half_jz * (double)(g.al[1] - g.al[0]);
-  const double p_r = P.dt * __builtin_fabs(d_r);
-  const double p_i = P.dt * __builtin_fabs(d_i);
-  const HopClasses hc = hop_classes(P, g, l, m);
-  FieldParts f;
-  field_parts(P, hc, l, m, f);
-  const double P_re = P.dt * f.Sc[0][0];
-  const double P_im = P.dt * f.Sc[1][0];
-  double p8[8];
+  double d_r, d_i, p8[8];
   int64_t n8[8];
-  const double pp[4] = {p_r, p_i, P_re, P_im};
-  for (int k = 0; k < 4; ++k) {
-    p8[k] = pp[k];
-    p8[k + 4] = pp[k];
-    n8[k] = nR;
-    n8[k + 4] = nI;
-  }
+  HopClasses hc;
+  FieldParts f;
+  field_channels(P, S, l, m, nR, nI, d_r, d_i, hc, f, p8, n8);
   EntryCounter cnt{P.seed, ((uint64_t)l << P.N) | m, P.solve, step, 0};
   int64_t X[8];
   channel_counts(p8, n8, cnt, X);

@@ -1,5 +1,6 @@
 """GPU parity with the in-plane field of Sec. V.B (hx sigma^x + hy sigma^y per
-site): the general spawn path (one thread per entry) against the oracle, bit
+site): the quiet scan on the field's probabilities and the general sampling
+routine (one thread per entry with events) against the oracle, bit
 for bit; and a batch mixing solves with and without the field against each
 solve alone (a field-free solve alone takes the quiet scan and the loud and
 heavy kernels, in the batch the general path: the same draws)."""
