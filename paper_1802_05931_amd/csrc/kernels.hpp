@@ -760,7 +760,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MINW))) void
 // entry_events for the others.  Records are staged in LDS per block
 // iteration and flushed into the block's segment.
 template <typename K>
-__global__ __launch_bounds__(NT) void k_spawn_listed(Ctrl *ctrl,
+__global__ __launch_bounds__(NT, 2) void k_spawn_listed(Ctrl *ctrl,
                                                      const SlotParams *__restrict__ sp,
                                                      const SlotState *__restrict__ ss,
                                                      const K *__restrict__ lkey,
