@@ -594,3 +594,38 @@ def test_tile_table_switches_shapes(dq, orc):
     assert len(seen) >= 2, seen
     assert g.scalars() == o.scalars()
     g.close()
+
+
+@pytest.mark.parametrize("extra", [dict(), dict(hx=0.08, hy=-0.05), dict(flags=2)],
+                         ids=["plain", "field", "per_walker"])
+def test_32_sites(dq, orc, extra):
+    """N = 32 (4x8): the configuration fills a 64-bit key and the slot field is
+    empty (slot bits at position 64).  One step from a seeded random list at
+    three counters, then a short run from the all-down state, each against the
+    oracle bit for bit, for the plain, field and per-walker samplers."""
+    keys, re, im = workloads.random_list(4, 8, 4000, 60, seed=32, even="hx" not in extra)
+    cfg = dict(Lx=4, Ly=8, Jx=0.7, Jy=1.0, Jz=1.1, gamma=1.0, dt=0.01, n_a=3, is_p=0.5,
+               target_walkers=2 ** 62, seed=78, **extra)
+    g = dq.Solve(dq.make_params(**cfg))
+    o = orc.Oracle(**cfg)
+    for step in (0, 1, 12345):
+        g.set_walkers(keys, re, im)
+        g.set_scalars(0.1, 1, step, 10 ** 6)
+        o.set_list(keys, re, im)
+        o.set_scalars(0.1, 1, step, 10 ** 6)
+        g.step(1)
+        o.step(1)
+        assert _same_list(g.walkers(), o.get_list()), step
+        assert g.scalars() == o.scalars()
+    g.close()
+    run = dict(cfg, target_walkers=3000, initial_walkers=3000, shift_init=0.0, n_equil=20,
+               dt=0.004)
+    g = dq.Solve(dq.make_params(**run))
+    o = orc.Oracle(**run)
+    for _ in range(2):
+        g.step(30)
+        o.step(30)
+        assert _same_list(g.walkers(), o.get_list())
+        assert g.scalars() == o.scalars()
+    assert np.array_equal(g.series(), o.series())
+    g.close()
