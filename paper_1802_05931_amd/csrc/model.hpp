@@ -158,6 +158,63 @@ DQ_HD void tree_split(int n, int64_t M, EntryCounter &cnt, uint32_t draw_base, F
   }
 }
 
+// tree_split for n <= 64 members without an array: the same draws and leaves,
+// by a depth-first walk that goes left first and keeps the right child's
+// count of each split in the register of its depth (depths 1..6), read and
+// written through select chains; a waiting child is found again from the
+// current heap index, its range rebuilt from the root.
+template <typename F>
+DQ_HD void tree_split_flat(int n, int64_t M, EntryCounter &cnt, uint32_t draw_base, F &&emit) {
+  int64_t q1 = 0, q2 = 0, q3 = 0, q4 = 0, q5 = 0, q6 = 0;  // waiting right children
+  uint32_t wait = 0;                                         // bit d: depth d has one
+  int lo = 0, hi = n, depth = 0;
+  uint32_t h = 1;
+  int64_t Mn = M;
+#pragma unroll 1
+  for (;;) {
+    if (Mn > 0) {
+      if (hi - lo == 1) {
+        emit(lo, Mn);
+      } else {
+        const int mid = lo + (hi - lo) / 2;
+        const int64_t ML =
+            cnt.inl(draw_base + h, Mn, (double)(mid - lo) / (double)(hi - lo), DRAW_BIN);
+        ++depth;
+        const int64_t MR = Mn - ML;
+        if (MR > 0) {
+          q1 = depth == 1 ? MR : q1;
+          q2 = depth == 2 ? MR : q2;
+          q3 = depth == 3 ? MR : q3;
+          q4 = depth == 4 ? MR : q4;
+          q5 = depth == 5 ? MR : q5;
+          q6 = depth == 6 ? MR : q6;
+          wait |= 1u << depth;
+        }
+        hi = mid;  // the left child next
+        h = 2 * h;
+        Mn = ML;
+        continue;
+      }
+    }
+    if (wait == 0) break;
+    const int d = 31 - __builtin_clz(wait);  // the deepest waiting child
+    wait &= ~(1u << d);
+    Mn = d == 1 ? q1 : d == 2 ? q2 : d == 3 ? q3 : d == 4 ? q4 : d == 5 ? q5 : q6;
+    h = (h >> (depth - d)) | 1u;  // right sibling of the path's node at depth d
+    depth = d;
+    lo = 0;
+    hi = n;
+#pragma unroll 1
+    for (int k = d - 1; k >= 0; --k) {
+      const int mid = lo + (hi - lo) / 2;
+      if ((h >> k) & 1u)
+        lo = mid;
+      else
+        hi = mid;
+    }
+  }
+}
+
 DQ_HD int64_t sgn64(int64_t x) { return (x > 0) - (x < 0); }
 DQ_HD int64_t sgnd(double x) { return (x > 0.0) - (x < 0.0); }
 
@@ -577,78 +634,97 @@ DQ_HD void entry_events_field(const SlotParams &P, double S, uint32_t step, uint
   if (dR != 0 || dI != 0) emit(l, m, dR, dI, true);
 
   const uint32_t jm = l & m;
-  for (int k = 0; k < 4; ++k) {
-    const int im_el = k >= 2;        // element part: 0 Re (channels 3, 7), 1 Im (4, 8)
-    const int im_par = k & 1;        // parent part: 0 real walkers, 1 imaginary
-    const int ch = im_el ? (im_par ? 8 : 4) : (im_par ? 7 : 3);
-    int64_t rem = X[ch - 1];
-    if (rem == 0) continue;
-    const int64_t sg = im_par ? sI : sR;
-    const int nc = f.ncls[im_el];
-    // member j of class c: its child and the sign of its element part
-    auto leaf = [&](int c, int j, int64_t M) {
-      uint32_t cl = l, cm = m;
-      int64_t sgn = 1;
-      bool keep = init;
-      if (!im_el && c == 0) {  // a jump: down in both ket and bra
-        const uint32_t bit = 1u << nth_bit(jm, j);
-        cl = l & ~bit;
-        cm = m & ~bit;
-      } else if (im_el && c < 6) {  // a hop of one bond
-        const uint32_t bm = class_member_mask(P, hc.r[c], hc.u[c], j);
-        cl = c < 3 ? (l ^ bm) : l;
-        cm = c < 3 ? m : (m ^ bm);
-        sgn = hc.sgn[c];
-        keep = init || cl == cm;
-      } else {  // a field flip
-        const int fk = im_el ? c - 6 : c - 1;
-        const bool bra = fk >= 2;
-        const uint32_t site = nth_bit(f.fmask[fk], j);
-        const uint32_t x = bra ? m : l;
-        if (bra)
-          cm = m ^ (1u << site);
+  // (the element part and the class index are compile-time in every access
+  // to the class tables below, so that the tables stay in registers; a class
+  // chosen at run time is read through select chains)
+#pragma unroll
+  for (int im_el = 0; im_el < 2; ++im_el) {  // element part: 0 Re (channels 3, 7), 1 Im (4, 8)
+    constexpr int NCMAX = 10;
+    const int nc = im_el ? 10 : 5;
+    for (int im_par = 0; im_par < 2; ++im_par) {  // parent part: 0 real walkers, 1 imaginary
+      const int ch = im_el ? (im_par ? 8 : 4) : (im_par ? 7 : 3);
+      int64_t rem = im_el ? (im_par ? X[7] : X[3]) : (im_par ? X[6] : X[2]);
+      if (rem == 0) continue;
+      const int64_t sg = im_par ? sI : sR;
+      // member j of class c: its child and the sign of its element part
+      auto leaf = [&](int c, int j, int64_t M) {
+        uint32_t cl = l, cm = m;
+        int64_t sgn = 1;
+        bool keep = init;
+        if (!im_el && c == 0) {  // a jump: down in both ket and bra
+          const uint32_t bit = 1u << nth_bit(jm, j);
+          cl = l & ~bit;
+          cm = m & ~bit;
+        } else if (im_el && c < 6) {  // a hop of one bond
+          const uint32_t bm = class_member_mask(P, pick6(hc.r, c), pick6(hc.u, c), j);
+          cl = c < 3 ? (l ^ bm) : l;
+          cm = c < 3 ? m : (m ^ bm);
+          sgn = pick6(hc.sgn, c);
+          keep = init || cl == cm;
+        } else {  // a field flip
+          const int fk = im_el ? c - 6 : c - 1;
+          const bool bra = fk >= 2;
+          uint32_t fm = f.fmask[0];
+#pragma unroll
+          for (int i = 1; i < 4; ++i) fm = (fk == i) ? f.fmask[i] : fm;
+          const uint32_t site = nth_bit(fm, j);
+          const uint32_t x = bra ? m : l;
+          if (bra)
+            cm = m ^ (1u << site);
+          else
+            cl = l ^ (1u << site);
+          sgn = im_el ? (bra ? sgnd(P.hx) : -sgnd(P.hx))
+                      : (((x >> site) & 1u) ? sgnd(P.hy) : -sgnd(P.hy));
+          keep = init || cl == cm;
+        }
+        const int64_t v = sg * sgn * M;
+        // (R + iI) x element part: Re x R -> re, Re x I -> im, Im x R -> im,
+        // Im x I -> -re (Sec. III.C rule (i))
+        if (!im_el && !im_par)
+          emit(cl, cm, v, 0, keep);
+        else if (!im_el || !im_par)
+          emit(cl, cm, 0, v, keep);
         else
-          cl = l ^ (1u << site);
-        sgn = im_el ? (bra ? sgnd(P.hx) : -sgnd(P.hx)) : (((x >> site) & 1u) ? sgnd(P.hy) : -sgnd(P.hy));
-        keep = init || cl == cm;
+          emit(cl, cm, -v, 0, keep);
+      };
+      if (rem == 1) {
+        Stream st(cnt.seed, cnt.solve, cnt.cfg, cnt.step, draw_channel(ch) + DRAW_PICK, nullptr);
+        const double u1 = st.next();
+        const double u2 = st.next();
+        const double T = f.Sc[im_el][0] * (1.0 - u1);
+        // the first class c with Sc[c + 1] < T (the suffix sums fall, and
+        // Sc[nc] = 0 < T), and its member count
+        int c = 0, nmem = f.n[im_el][0];
+#pragma unroll
+        for (int cc = 1; cc < NCMAX; ++cc)
+          if (cc < nc && !(f.Sc[im_el][cc] < T)) {
+            c = cc;
+            nmem = f.n[im_el][cc];
+          }
+        int j = (int)__builtin_floor(u2 * (double)nmem);
+        j = j > nmem - 1 ? nmem - 1 : j;
+        leaf(c, j, 1);
+        continue;
       }
-      const int64_t v = sg * sgn * M;
-      // (R + iI) x element part: Re x R -> re, Re x I -> im, Im x R -> im,
-      // Im x I -> -re (Sec. III.C rule (i))
-      if (!im_el && !im_par)
-        emit(cl, cm, v, 0, keep);
-      else if (!im_el || !im_par)
-        emit(cl, cm, 0, v, keep);
-      else
-        emit(cl, cm, -v, 0, keep);
-    };
-    if (rem == 1) {
-      Stream st(cnt.seed, cnt.solve, cnt.cfg, cnt.step, draw_channel(ch) + DRAW_PICK, nullptr);
-      const double u1 = st.next();
-      const double u2 = st.next();
-      const double T = f.Sc[im_el][0] * (1.0 - u1);
-      int c = 0;
-      while (!(f.Sc[im_el][c + 1] < T)) ++c;
-      int j = (int)__builtin_floor(u2 * (double)f.n[im_el][c]);
-      j = j > f.n[im_el][c] - 1 ? f.n[im_el][c] - 1 : j;
-      leaf(c, j, 1);
-      continue;
-    }
-    int last = -1;
-    for (int c = 0; c < nc; ++c)
-      if (f.W[im_el][c] > 0.0) last = c;
-    for (int c = 0; c < nc; ++c) {
-      if (rem == 0 || f.W[im_el][c] == 0.0) continue;
-      int64_t Mc;
-      if (c == last)
-        Mc = rem;
-      else
-        Mc = cnt(draw_channel(ch) + class_split_draw(c), rem, f.W[im_el][c] / f.Sc[im_el][c],
-                 DRAW_BIN);
-      rem -= Mc;
-      if (Mc == 0) continue;
-      tree_split(f.n[im_el][c], Mc, cnt, draw_channel(ch) + 64u + 64u * (uint32_t)c,
-                 [&](int j, int64_t M) { leaf(c, j, M); });
+      int last = -1;
+#pragma unroll
+      for (int c = 0; c < NCMAX; ++c)
+        if (c < nc && f.W[im_el][c] > 0.0) last = c;
+#pragma unroll
+      for (int c = 0; c < NCMAX; ++c) {
+        if (c >= nc || rem == 0 || f.W[im_el][c] == 0.0) continue;
+        int64_t Mc;
+        if (c == last)
+          Mc = rem;
+        else
+          Mc = cnt.inl(draw_channel(ch) + class_split_draw(c), rem,
+                       f.W[im_el][c] / f.Sc[im_el][c], DRAW_BIN);
+        rem -= Mc;
+        if (Mc == 0) continue;
+        // (at most 64 members: bonds, jump and field sites of N <= 32 sites)
+        tree_split_flat(f.n[im_el][c], Mc, cnt, draw_channel(ch) + 64u + 64u * (uint32_t)c,
+                        [&](int j, int64_t M) { leaf(c, j, M); });
+      }
     }
   }
   if (cnt.dry) *err = 1;
