@@ -17,7 +17,10 @@ bit tricks, so that it is an independent check of the walker step:
   from parent (l,m) to child (i,j) is multiplied by w_ij / w_lm with
   w = e^{-p} off the diagonal and 1 on it;
 * the steady state as the null vector of L with unit trace ("solving the linear
-  system", Sec. V), and observables Tr(rho O) (Sec. III.A, Sec. V.A).
+  system", Sec. V), and observables Tr(rho O) (Sec. III.A, Sec. V.A); for
+  lattices where the direct sparse solve fills in too much (3x3), the
+  steady state as the long-time limit of the master equation, integrated
+  with the classical fourth-order Runge-Kutta rule.
 
 Basis: state index = bitstring, bit s = 1 <=> spin up at site s = x + Lx*y.
 The element rho_{lm} sits at vec index m*D + l (D = 2^N).
@@ -163,6 +166,43 @@ def ness(Lx, Ly, Jx, Jy, Jz, gamma, hx=0.0, hy=0.0):
     vec = np.zeros(D * D, dtype=complex)
     vec[even] = x
     return vec.reshape((D, D), order="F")
+
+
+def ness_evolve(Lx, Ly, Jx, Jy, Jz, gamma, tau=0.05, tol=1e-12, t_max=200.0):
+    """Steady state as the limit t -> infinity of d rho / dt = L rho, from the
+    all-down state, in the even sector popcount(l) + popcount(m) even (the
+    evolution never leaves it without a field): classical fourth-order
+    Runge-Kutta steps of length tau until max |L rho| / max |rho| < tol.
+    The trace is conserved by L; rho is returned with unit trace, and the
+    relative residual reached."""
+    N = Lx * Ly
+    D = 2 ** N
+    L = liouvillian(Lx, Ly, Jx, Jy, Jz, gamma)
+    idx = np.arange(D * D)
+    l = idx % D
+    m = idx // D
+    pc = np.array([bin(i).count("1") for i in range(D)])
+    even = np.nonzero((pc[l] + pc[m]) % 2 == 0)[0]
+    Le = L[even][:, even].tocsr()
+    x = np.zeros(len(even), dtype=complex)
+    x[np.nonzero(even == 0)[0][0]] = 1.0
+    t = 0.0
+    res = np.inf
+    while t < t_max:
+        for _ in range(100):
+            k1 = Le @ x
+            k2 = Le @ (x + 0.5 * tau * k1)
+            k3 = Le @ (x + 0.5 * tau * k2)
+            k4 = Le @ (x + tau * k3)
+            x = x + (tau / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+            t += tau
+        res = np.abs(Le @ x).max() / np.abs(x).max()
+        if res < tol:
+            break
+    vec = np.zeros(D * D, dtype=complex)
+    vec[even] = x
+    rho = vec.reshape((D, D), order="F")
+    return rho / np.trace(rho), res
 
 
 def observables(rho, Lx, Ly):

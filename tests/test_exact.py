@@ -135,3 +135,31 @@ def test_field_breaks_parity_and_gives_linear_response():
     assert np.abs(L @ rho.reshape(-1, order="F")).max() < 1e-12
     assert abs(np.trace(rho) - 1) < 1e-12 and np.abs(rho - rho.conj().T).max() < 1e-12
     assert np.linalg.eigvalsh(rho).min() > -1e-12
+
+
+def test_long_time_limit_equals_the_direct_solve():
+    """The steady state by integrating the master equation to its long-time
+    limit (the route used for 3x3, where the direct sparse solve fills in too
+    much) equals the direct solve of L rho = 0, Tr rho = 1 on 2x3."""
+    rho_d = exact.ness(2, 3, 0.6, 1.0, 1.0, 1.0)
+    rho_e, res = exact.ness_evolve(2, 3, 0.6, 1.0, 1.0, 1.0)
+    assert res < 1e-12
+    assert np.abs(rho_e - rho_d).max() < 1e-9
+    od, oe = exact.observables(rho_d, 2, 3), exact.observables(rho_e, 2, 3)
+    assert all(abs(od[k] - oe[k]) < 1e-9 for k in od)
+
+
+def test_golden_3x3_steady_states():
+    """tests/golden/ness_3x3.json (written by make_ness_3x3.py from the same
+    integration) holds converged 3x3 steady states: residual below 1e-12, and
+    the physics the 2x3 lattice shows too (M_z in (-1, 0), and closer to -1
+    the nearer Jx is to Jy, where the all-down state is exact)."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "ness_3x3.json")))
+    by = {s["Jx"]: s for s in g["states"]}
+    assert set(by) == {0.6, 0.9, 1.1}
+    for s in by.values():
+        assert s["residual"] < 1e-12 and -1.0 < s["mz"] < 0.0
+        assert s["mx"] == 0.0 and s["my"] == 0.0
+    assert by[0.6]["mz"] > by[0.9]["mz"]
