@@ -44,12 +44,16 @@ def test_device_bytes_equal_the_workspace_query(dq):
         g.close()
 
 
-def test_create_in_steps_like_create(dq, orc):
+@pytest.mark.parametrize("extra", [dict(), dict(hx=0.07), dict(flags=2)],
+                         ids=["plain", "field", "per_walker"])
+def test_create_in_steps_like_create(dq, orc, extra):
     """A D2-shaped solve in a torch-owned workspace sized by the query: the same
-    lists, scalars and series as a library-allocated handle, and the oracle's."""
+    lists, scalars and series as a library-allocated handle, and the oracle's,
+    for each sampler (the field's list holds both parities: at most 4^9)."""
     import torch
     # (the records get a quarter of the list capacity, split over 64 segments)
-    cfg = dict(workloads.d2(0.6), target_walkers=20000, n_equil=100, capacity_hint=400_000)
+    cfg = dict(workloads.d2(0.6), target_walkers=20000, n_equil=100, capacity_hint=400_000,
+               **extra)
     p = dq.make_params(**cfg)
     need = dq.workspace_query(p, cfg["capacity_hint"])
     t, ws = _workspace(need)

@@ -451,8 +451,13 @@ def test_invalid_parameters(dq):
         assert e.value.code == -1
 
 
-def test_checkpoint_resume_bit_exact(dq):
-    cfg = dict(workloads.d2(0.6), target_walkers=5000)
+@pytest.mark.parametrize("extra", [dict(), dict(hx=0.1, hy=-0.05), dict(flags=2)],
+                         ids=["plain", "field", "per_walker"])
+def test_checkpoint_resume_bit_exact(dq, extra):
+    """A handle restored from a checkpoint steps on exactly as the one it was
+    taken from, for each sampler (the random streams are keyed on the
+    configuration and the step, both in the checkpoint)."""
+    cfg = dict(workloads.d2(0.6), target_walkers=5000, **extra)
     a = dq.Solve(dq.make_params(**cfg))
     a.step(300)
     blob = a.get_state()
