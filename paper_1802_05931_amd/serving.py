@@ -10,8 +10,8 @@ arrival order, into a free slot of a ``Pool`` while the device bytes projected
 for the admitted solves stay within ``hbm_budget``.  A request's projection is
 the library's exact workspace size (ddqmc_workspace_query) for the largest list
 it may hold: its lattice's reachable configurations (the even-parity half of
-the 4^N density-matrix configurations), at most the per-request entry limit
-``max_entries``.  The pool advances in ticks of ``tick`` steps; after each tick a
+the 4^N density-matrix configurations, all of them with the in-plane field),
+at most the per-request entry limit ``max_entries``.  The pool advances in ticks of ``tick`` steps; after each tick a
 solve whose magnetisation M_z has a standard error below ``se_target`` (with
 at least ``min_accum`` accumulated steps after its equilibration), that has run
 ``max_steps`` steps, or whose list has grown past ``max_entries`` leaves its
@@ -33,10 +33,12 @@ from ._lib import ECAPACITY, ENOMEM, ESTATE, DDQMCError
 def projected_bytes(params, max_entries):
     """Device bytes a request may come to hold: the workspace of a one-slot
     handle whose list capacity is the smaller of the lattice's reachable
-    configurations (popcount(ket) + popcount(bra) even: 2^(2N-1)) and the
-    per-request entry limit."""
+    configurations (popcount(ket) + popcount(bra) even: 2^(2N-1); with the
+    in-plane field, which breaks that parity, all 4^N) and the per-request
+    entry limit."""
     n = int(params["Lx"]) * int(params["Ly"])
-    cap = min(1 << (2 * n - 1), int(max_entries))
+    field = params.get("hx", 0.0) != 0.0 or params.get("hy", 0.0) != 0.0
+    cap = min(1 << (2 * n if field else 2 * n - 1), int(max_entries))
     return workspace_query(make_params(**params), cap)
 
 

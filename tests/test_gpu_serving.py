@@ -32,7 +32,7 @@ class FakeClock:
         self.t += s
 
 
-def _requests():
+def _requests(field=False):
     rng = np.random.default_rng(31)
     lat = [(2, 2), (3, 3), (2, 6), (2, 2), (3, 3), (2, 6), (3, 3), (2, 2), (2, 6)]
     reqs = []
@@ -44,13 +44,19 @@ def _requests():
                                      gamma=float(rng.uniform(0.8, 2.0)), dt=0.005, n_a=3,
                                      target_walkers=t, initial_walkers=t, shift_init=0.0,
                                      seed=5, solve_id=200 + i, n_equil=100)))
+        if field and i in (2, 5):  # two requests with the in-plane field
+            reqs[-1]["params"]["hx"] = 0.1
     return reqs
 
 
-@pytest.mark.parametrize("budget_solves,graph_k", [(2, 0), (4, 10)])
-def test_replayed_arrivals(dq, budget_solves, graph_k):
+@pytest.mark.parametrize("budget_solves,graph_k,field", [(2, 0, False), (4, 10, False),
+                                                         (4, 10, True)])
+def test_replayed_arrivals(dq, budget_solves, graph_k, field):
+    """(With field: two of the requests carry the in-plane field, and the pool
+    samples every solve by the general routine from the first one on; the
+    others alone take the per-entry kernels: the same draws.)"""
     from paper_1802_05931_amd import serving
-    reqs = _requests()
+    reqs = _requests(field)
     max_entries = 30000
     proj = [serving.projected_bytes(r["params"], max_entries) for r in reqs]
     budget = int(budget_solves * max(proj))
