@@ -124,8 +124,10 @@ struct ddqmc_t {
                             // block per chunk); chosen per chunk of steps, see run_steps
   int loud_grid = 0;        // 0 chosen per chunk of steps, 1 resident, 2 block per chunk
   bool general = false;     // some solve has the in-plane field: the general spawn path
+  bool all_field = false;   // every solve has it (a batch or solve made so; not a pool)
   bool per_walker = false;  // every solve samples walker by walker (the ablation path)
   uint32_t general_blocks = 1024;
+  uint32_t ncu = 256;            // compute units of the device
   // tile shapes (records / merged positions per thread) of the sort and the
   // merge, and an optional table choosing them by list size before each chunk
   int sort_it = SORT_IT_DEFAULT, merge_it = MERGE_IT_DEFAULT;
@@ -443,6 +445,7 @@ int build(ddqmc_t *h, int nslots, int Nmax, uint64_t cap, void *stream, void *ws
     h->loud_blocks = clampu((uint64_t)std::max(ncu, 1) * (uint64_t)std::max(nl, 1), 1, 4096);
     h->heavy_blocks = clampu((uint64_t)std::max(ncu, 1) * (uint64_t)std::max(nh, 1), 1, 8192);
     h->general_blocks = clampu((uint64_t)std::max(ncu, 1) * 4, 1, 4096);
+    h->ncu = clampu((uint64_t)std::max(ncu, 1), 1, 4096);
   }
   h->passes = (h->key_bits + 7) / 8;
   const size_t ks = key_size(h);
@@ -557,14 +560,40 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
   } else if (h->general) {
     // the in-plane field: the quiet scan on the field's probabilities, then
     // every entry with events, one thread each (timed as the loud stage; the
-    // gather and heavy stages are empty)
+    // gather and heavy stages are empty).  When every solve has the field the
+    // scan sends the entries whose draws are not all small to the heavy list,
+    // sampled by the general routine (for large lists on the second stream,
+    // beside the call-free routine over the rest); the entries the call-free
+    // routine passes on (a spawn count of 20 or more) follow it.
+    const bool split = h->all_field;
     k_spawn_scan<K, true><<<h->nscan, NT, 0, s>>>(ak, av, h->ctrl, h->dsp, h->dss, h->lidx,
-                                                 (K *)h->lkey, h->lval, h->heavy, h->SB);
+                                                 (K *)h->lkey, h->lval, h->heavy, h->SB, split);
     if (ev) HIPC(hipEventRecord(ev->e[1], s));
     if (ev) HIPC(hipEventRecord(ev->e[2], s));
-    k_spawn_listed<K><<<h->general_blocks, NT, 0, s>>>(c, h->dsp, h->dss, (const K *)h->lkey,
-                                                       h->lval, (K *)h->sk[0], h->sv[0],
-                                                       h->segcnt, segcap, h->SB);
+    if (split) {
+      hipStream_t hs = h->fork_heavy ? h->side : s;
+      if (h->fork_heavy) {
+        HIPC(hipEventRecord(h->ev_fork, s));
+        HIPC(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+      }
+      // (the large entries on a quarter block per CU: one wave each, leaving
+      // the CUs to the call-free routine)
+      k_spawn_listed<K, false><<<clampu(h->ncu / 4, 1, 4096), NT, 0, hs>>>(
+          c, h->dsp, h->dss, ak, av, h->heavy, &c->n_heavy, nullptr, (K *)h->sk[0], h->sv[0],
+          h->segcnt, segcap, h->SB);
+      if (h->fork_heavy) HIPC(hipEventRecord(h->ev_join, h->side));
+      k_spawn_listed<K, true><<<h->general_blocks, NT, 0, s>>>(
+          c, h->dsp, h->dss, (const K *)h->lkey, h->lval, nullptr, &c->n_loud, h->late,
+          (K *)h->sk[0], h->sv[0], h->segcnt, segcap, h->SB);
+      k_spawn_listed<K, false><<<h->general_blocks, NT, 0, s>>>(
+          c, h->dsp, h->dss, (const K *)h->lkey, h->lval, h->late, &c->n_late, nullptr,
+          (K *)h->sk[0], h->sv[0], h->segcnt, segcap, h->SB);
+      if (h->fork_heavy) HIPC(hipStreamWaitEvent(s, h->ev_join, 0));
+    } else {
+      k_spawn_listed<K, false><<<h->general_blocks, NT, 0, s>>>(
+          c, h->dsp, h->dss, (const K *)h->lkey, h->lval, nullptr, &c->n_loud, nullptr,
+          (K *)h->sk[0], h->sv[0], h->segcnt, segcap, h->SB);
+    }
     if (ev) HIPC(hipEventRecord(ev->e[3], s));
     if (ev) HIPC(hipEventRecord(ev->e[4], s));
   } else {
@@ -1086,9 +1115,11 @@ int create_common(const ddqmc_params *p, int32_t count, void *hip_stream, void *
   std::vector<SlotState> st(count);
   std::vector<uint64_t> keys(count);
   std::vector<int2> vals(count);
+  h->all_field = count > 0;
   for (int i = 0; i < count; ++i) {
     h->hp[i] = make_slot(p[i]);
     if (h->hp[i].field) h->general = true;
+    if (!h->hp[i].field) h->all_field = false;
     if (h->hp[i].flags & FLAG_PER_WALKER) h->per_walker = true;
     h->up[i] = p[i];
     st[i] = fresh_state(p[i], 1);

@@ -205,7 +205,8 @@ __global__ __launch_bounds__(NT) void k_spawn_scan(const K *__restrict__ keys,
                                                    const SlotState *__restrict__ ss,
                                                    uint32_t *__restrict__ lidx,
                                                    K *__restrict__ lkey, int2 *__restrict__ lval,
-                                                   uint32_t *__restrict__ heavy, int SB) {
+                                                   uint32_t *__restrict__ heavy, int SB,
+                                                   bool split = false) {
   if (ctrl->abort) return;
   __shared__ uint32_t lcount, lbase;
   __shared__ uint32_t s_i[LOUD_STAGE];
@@ -253,11 +254,14 @@ __global__ __launch_bounds__(NT) void k_spawn_scan(const K *__restrict__ keys,
       const uint32_t l = (uint32_t)(cfg >> N);
       const uint32_t m = (uint32_t)(cfg & ((N == 32) ? 0xffffffffull : ((1ull << N) - 1)));
       // (a handle with the field sends every entry with events to the loud
-      // list, sampled by k_spawn_listed)
+      // list, sampled by k_spawn_listed; with split, every solve has the field
+      // and the entries whose draws are not all small go to the heavy list)
       if (GENERAL) {
-        const int k = P.field ? entry_kind_field(P, S, step, l, m, v.x, v.y)
+        const int k = P.field ? entry_kind_field(P, S, step, l, m, v.x, v.y, split)
                               : entry_kind(P, S, step, l, m, v.x, v.y);
-        return k == ENTRY_QUIET ? (int)ENTRY_QUIET : (int)ENTRY_LIGHT;
+        return k == ENTRY_QUIET                 ? (int)ENTRY_QUIET
+               : (split && k == ENTRY_HEAVY) ? (int)ENTRY_HEAVY
+                                               : (int)ENTRY_LIGHT;
       }
       return entry_kind(P, S, step, l, m, v.x, v.y);
     };
@@ -755,16 +759,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MINW))) void
   if (int_ovf) atomicOr(&ctrl->flags, F_INT_OVF);
 }
 
-// The loud list's entries (every entry with events, in a handle with the
-// field), one thread each: entry_events_field for the solves with the field,
-// entry_events for the others.  Records are staged in LDS per block
-// iteration and flushed into the block's segment.
-template <typename K>
+// Entries with events in a handle with the field, one thread each: *count
+// of them, entry q = idx ? idx[q] : q of (skey, sval).  FIELD_ONLY (every
+// solve of the handle has the field): the call-free routine, which takes the
+// entries whose draws are all small, the others' indices in (skey, sval) to
+// the late list (late, ctrl->n_late); else entry_events_field for the solves
+// with the field and entry_events for the others.  Records are staged in LDS
+// per block iteration and flushed into the block's segment.
+template <typename K, bool FIELD_ONLY>
 __global__ __launch_bounds__(NT, 2) void k_spawn_listed(Ctrl *ctrl,
                                                      const SlotParams *__restrict__ sp,
                                                      const SlotState *__restrict__ ss,
-                                                     const K *__restrict__ lkey,
-                                                     const int2 *__restrict__ lval,
+                                                     const K *__restrict__ skey,
+                                                     const int2 *__restrict__ sval,
+                                                     const uint32_t *__restrict__ idx,
+                                                     const uint32_t *count,
+                                                     uint32_t *__restrict__ late,
                                                      K *__restrict__ ok, int2 *__restrict__ ov,
                                                      unsigned long long *segcnt, uint32_t segcap,
                                                      int SB) {
@@ -773,19 +783,27 @@ __global__ __launch_bounds__(NT, 2) void k_spawn_listed(Ctrl *ctrl,
   __shared__ int2 sv[STAGE];
   __shared__ uint32_t scount;
   __shared__ unsigned long long sbase;
-  const uint32_t n = ctrl->n_loud;
+  const uint32_t n = *count;
   const int seg = blockIdx.x % NSEG;
   const K lowm = low_mask<K>(SB);
   int rng_err = 0;
   bool int_ovf = false;
   const RecordSink<K> sink{sk, sv, &scount, segcnt, ok, ov, segcap, seg, &int_ovf};
-  for (uint32_t base = blockIdx.x * NT; base < n; base += gridDim.x * NT) {
+  // a list through idx (the large entries, few and each a long chain of
+  // draws) is dealt one entry per wave first, so that they spread over the
+  // SIMDs; the loud list goes in contiguous runs of NT
+  const bool spread = idx != nullptr;
+  const uint32_t waves = gridDim.x * (NT / 64);
+  const uint32_t wave = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  for (uint32_t base = 0; base < n; base += gridDim.x * NT) {
     if (threadIdx.x == 0) scount = 0;
     __syncthreads();
-    const uint32_t q = base + threadIdx.x;
-    if (q < n) {
-      const K key = lkey[q];
-      const int2 v = lval[q];
+    const uint32_t i = base + (spread ? (threadIdx.x & 63) * waves + wave
+                                      : blockIdx.x * NT + threadIdx.x);
+    if (i < n) {
+      const uint32_t q = idx ? idx[i] : i;
+      const K key = skey[q];
+      const int2 v = sval[q];
       const uint32_t slot = slot_of<K>(key, SB);
       const SlotParams &P = sp[slot];
       const K hibits = key & ~lowm;
@@ -797,10 +815,15 @@ __global__ __launch_bounds__(NT, 2) void k_spawn_listed(Ctrl *ctrl,
       auto rec = [&](uint32_t cl, uint32_t cm, int64_t dr, int64_t di, bool keep) {
         sink(hibits | (K)(((uint64_t)cl << N) | cm), dr, di, keep);
       };
-      if (P.field)
-        entry_events_field(P, ss[slot].S, step, l, m, v.x, v.y, &rng_err, rec);
-      else
-        entry_events(P, ss[slot].S, step, l, m, v.x, v.y, &rng_err, rec);
+      if constexpr (FIELD_ONLY) {
+        if (!entry_events_field_small(P, ss[slot].S, step, l, m, v.x, v.y, &rng_err, rec))
+          late[atomicAdd(&ctrl->n_late, 1u)] = q;
+      } else {
+        if (P.field)
+          entry_events_field(P, ss[slot].S, step, l, m, v.x, v.y, &rng_err, rec);
+        else
+          entry_events(P, ss[slot].S, step, l, m, v.x, v.y, &rng_err, rec);
+      }
     }
     __syncthreads();
     seg_flush(sk, sv, scount < (uint32_t)STAGE ? scount : (uint32_t)STAGE, seg, segcnt, ok, ov,

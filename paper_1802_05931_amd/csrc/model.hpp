@@ -163,8 +163,9 @@ DQ_HD void tree_split(int n, int64_t M, EntryCounter &cnt, uint32_t draw_base, F
 // count of each split in the register of its depth (depths 1..6), read and
 // written through select chains; a waiting child is found again from the
 // current heap index, its range rebuilt from the root.
-template <typename F>
-DQ_HD void tree_split_flat(int n, int64_t M, EntryCounter &cnt, uint32_t draw_base, F &&emit) {
+// (draw(id, n, p) draws node id's Bin(n, p))
+template <typename D, typename F>
+DQ_HD void tree_split_flat_with(int n, int64_t M, uint32_t draw_base, D &&draw, F &&emit) {
   int64_t q1 = 0, q2 = 0, q3 = 0, q4 = 0, q5 = 0, q6 = 0;  // waiting right children
   uint32_t wait = 0;                                         // bit d: depth d has one
   int lo = 0, hi = n, depth = 0;
@@ -177,8 +178,7 @@ DQ_HD void tree_split_flat(int n, int64_t M, EntryCounter &cnt, uint32_t draw_ba
         emit(lo, Mn);
       } else {
         const int mid = lo + (hi - lo) / 2;
-        const int64_t ML =
-            cnt.inl(draw_base + h, Mn, (double)(mid - lo) / (double)(hi - lo), DRAW_BIN);
+        const int64_t ML = draw(draw_base + h, Mn, (double)(mid - lo) / (double)(hi - lo));
         ++depth;
         const int64_t MR = Mn - ML;
         if (MR > 0) {
@@ -213,6 +213,13 @@ DQ_HD void tree_split_flat(int n, int64_t M, EntryCounter &cnt, uint32_t draw_ba
         hi = mid;
     }
   }
+}
+
+template <typename F>
+DQ_HD void tree_split_flat(int n, int64_t M, EntryCounter &cnt, uint32_t draw_base, F &&emit) {
+  tree_split_flat_with(
+      n, M, draw_base,
+      [&](uint32_t id, int64_t nn, double p) { return cnt.inl(id, nn, p, DRAW_BIN); }, emit);
 }
 
 DQ_HD int64_t sgn64(int64_t x) { return (x > 0) - (x < 0); }
@@ -564,11 +571,6 @@ DQ_HD void field_parts(const SlotParams &P, const HopClasses &hc, uint32_t l, ui
   }
 }
 
-// entry_events with the field on (the slot's P.field): the same clone/death,
-// the real element part's jumps and field flips, the imaginary part's hops
-// and field flips, each part's walkers placed by one class split (sequential
-// conditional binomials, the last class with weight taking the rest; one
-// walker by one categorical pick) and the member trees.
 // The eight channel probabilities and walker counts of an entry of a solve
 // with the field (clone/death along the diagonal element; spawning along the
 // Re part: jumps and field flips; along the Im part: hops and field flips),
@@ -596,9 +598,12 @@ DQ_HD void field_channels(const SlotParams &P, double S, uint32_t l, uint32_t m,
 
 // The scan's decision for an entry of a solve with the field: quiet when the
 // primary uniform says that none of its eight channels fires (the test
-// channel_counts makes on the same probabilities), else sampled.
+// channel_counts makes on the same probabilities), else sampled.  With
+// heavy_ok, a sampled entry whose channel probabilities are not all small for
+// both parts' walkers (entry_events_field_small would refuse it) is
+// ENTRY_HEAVY.
 DQ_HD int entry_kind_field(const SlotParams &P, double S, uint32_t step, uint32_t l, uint32_t m,
-                           int32_t R, int32_t I) {
+                           int32_t R, int32_t I, bool heavy_ok = false) {
   const int64_t nR = R < 0 ? -(int64_t)R : (int64_t)R;
   const int64_t nI = I < 0 ? -(int64_t)I : (int64_t)I;
   double d_r, d_i, p8[8];
@@ -606,128 +611,312 @@ DQ_HD int entry_kind_field(const SlotParams &P, double S, uint32_t step, uint32_
   HopClasses hc;
   FieldParts f;
   field_channels(P, S, l, m, nR, nI, d_r, d_i, hc, f, p8, n8);
+  // (a probability of 1 or more is not small)
 #pragma unroll
   for (int k = 0; k < 8; ++k)
-    if (n8[k] > 0 && p8[k] >= 1.0) return ENTRY_LIGHT;
+    if (n8[k] > 0 && p8[k] >= 1.0) return heavy_ok ? ENTRY_HEAVY : ENTRY_LIGHT;
   Stream prim(P.seed, P.solve, ((uint64_t)l << P.N) | m, step, 0, nullptr);
-  return (quiet_test(p8, n8, prim.next()) & 1) ? ENTRY_QUIET : ENTRY_LIGHT;
+  if (quiet_test(p8, n8, prim.next()) & 1) return ENTRY_QUIET;
+  if (heavy_ok) {
+    bool small = true;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) small = small && small_draw(nR, p8[k]) && small_draw(nI, p8[k]);
+    if (!small) return ENTRY_HEAVY;
+  }
+  return ENTRY_LIGHT;
 }
 
-template <typename Emit>
-DQ_HD void entry_events_field(const SlotParams &P, double S, uint32_t step, uint32_t l,
-                              uint32_t m, int32_t R, int32_t I, int *err, Emit &&emit) {
+// Element c of ten values held in registers (a select chain on values).
+template <typename T>
+DQ_HD T sel10(int c, T a0, T a1, T a2, T a3, T a4, T a5, T a6, T a7, T a8, T a9) {
+  T v = a0;
+  v = c == 1 ? a1 : v;
+  v = c == 2 ? a2 : v;
+  v = c == 3 ? a3 : v;
+  v = c == 4 ? a4 : v;
+  v = c == 5 ? a5 : v;
+  v = c == 6 ? a6 : v;
+  v = c == 7 ? a7 : v;
+  v = c == 8 ? a8 : v;
+  v = c == 9 ? a9 : v;
+  return v;
+}
+
+// entry_events with the field on (the slot's P.field): the same clone/death,
+// the real element part's jumps and field flips, the imaginary part's hops
+// and field flips, each part's walkers placed by one class split (sequential
+// conditional binomials, the last class with weight taking the rest; one
+// walker by one categorical pick) and the member trees.  The same
+// probabilities, draws and records as field_channels / field_parts would
+// give, computed without arrays: every class table is a set of values (the
+// real part's five classes padded with empty ones to the imaginary part's
+// ten, which leaves its suffix sums as they are), and a class chosen at run
+// time is read through select chains, so the tables stay in registers.
+// SMALL: every draw by inversion (binomial_small, the same values), with no
+// out-of-line call, for entries whose channel probabilities are all small for
+// both parts' walkers and whose spawn counts stay below 20 (so that every
+// class and tree split is small too); false, before anything is emitted, for
+// an entry that is not such (the caller hands it to the general routine).
+template <bool SMALL, typename Emit>
+DQ_HD bool entry_events_field_impl(const SlotParams &P, double S, uint32_t step, uint32_t l,
+                                   uint32_t m, int32_t R, int32_t I, int *err, Emit &&emit) {
   const bool diag = (l == m);
   const int64_t nR = R < 0 ? -(int64_t)R : (int64_t)R;
   const int64_t nI = I < 0 ? -(int64_t)I : (int64_t)I;
   const int64_t sR = sgn64(R), sI = sgn64(I);
   const bool init = diag || (nR + nI > P.n_a) || (P.flags & FLAG_NO_INITIATOR);
-  double d_r, d_i, p8[8];
-  int64_t n8[8];
-  HopClasses hc;
-  FieldParts f;
-  field_channels(P, S, l, m, nR, nI, d_r, d_i, hc, f, p8, n8);
-  EntryCounter cnt{P.seed, ((uint64_t)l << P.N) | m, P.solve, step, 0};
-  int64_t X[8];
-  channel_counts(p8, n8, cnt, X);
-  const int64_t dR = sR * sgnd(d_r) * X[0] - sI * sgnd(d_i) * X[5];
-  const int64_t dI = sI * sgnd(d_r) * X[4] + sR * sgnd(d_i) * X[1];
-  if (dR != 0 || dI != 0) emit(l, m, dR, dI, true);
-
+  // geometry: aligned bonds of l and m, the bond l ^ m if it is one
+  const uint32_t al_r0 = ~(l ^ right_of(P, l)) & P.rmask;
+  const uint32_t al_u0 = ~(l ^ up_of(P, l)) & P.umask;
+  const uint32_t al_r1 = ~(m ^ right_of(P, m)) & P.rmask;
+  const uint32_t al_u1 = ~(m ^ up_of(P, m)) & P.umask;
+  const int al0 = popc(al_r0) + popc(al_u0);
+  const int al1 = popc(al_r1) + popc(al_u1);
+  const uint32_t d = l ^ m;
+  uint32_t Tr = 0, Tu = 0;
+  if (popc(d) == 2) {
+    Tr = d & right_of(P, d) & P.rmask;
+    Tu = d & up_of(P, d) & P.umask;
+  }
+  const bool T_al = ((Tr | Tu) == 0) || ((al_r0 & Tr) | (al_u0 & Tu)) != 0;
+  const double d_r = -(P.half_gamma * (double)(popc(l) + popc(m))) - S;
+  const double d_i = P.half_jz * (double)(al1 - al0);
+  // hop classes 0 ket-aligned, 1 ket-anti, 2 ket to-diagonal, 3-5 the bra's
+  const uint32_t r0 = al_r0 & ~Tr, u0 = al_u0 & ~Tu;
+  const uint32_t r1 = ~al_r0 & P.rmask & ~Tr, u1 = ~al_u0 & P.umask & ~Tu;
+  const uint32_t r3 = al_r1 & ~Tr, u3 = al_u1 & ~Tu;
+  const uint32_t r4 = ~al_r1 & P.rmask & ~Tr, u4 = ~al_u1 & P.umask & ~Tu;
+  const int hn0 = popc(r0) + popc(u0), hn1 = popc(r1) + popc(u1), hn2 = popc(Tr) + popc(Tu);
+  const int hn3 = popc(r3) + popc(u3), hn4 = popc(r4) + popc(u4);
+  const double w_al = diag ? P.w_dn : 1.0;    // weight ratio off the diagonal target
+  const double w_td = diag ? P.w_dn : P.w_up;  // ... onto it
+  const double amp2 = T_al ? P.a_al : P.a_an;
+  const double Wh0 = ((double)hn0 * P.a_al) * w_al, Wh1 = ((double)hn1 * P.a_an) * w_al;
+  const double Wh2 = ((double)hn2 * amp2) * w_td;
+  const double Wh3 = ((double)hn3 * P.a_al) * w_al, Wh4 = ((double)hn4 * P.a_an) * w_al;
+  const double Wh5 = ((double)hn2 * amp2) * w_td;
+  const int sh_al = (P.h_al > 0.0) - (P.h_al < 0.0), sh_an = (P.h_an > 0.0) - (P.h_an < 0.0);
+  const int sh2 = T_al ? sh_al : sh_an;
+  // field classes: flips of the sites where l and m agree (A) and of the one
+  // where they differ, if only one (B), on the ket and on the bra
+  const uint32_t all = P.N == 32 ? 0xffffffffu : ((1u << P.N) - 1u);
+  const uint32_t tbit = popc(d) == 1 ? d : 0u;
+  const uint32_t fA = all & ~tbit, fB = tbit;
+  const int nA = popc(fA), nB = popc(fB);
+  const double WyA = ((double)nA * P.ahy) * w_al, WyB = ((double)nB * P.ahy) * w_td;
+  const double WxA = ((double)nA * P.ahx) * w_al, WxB = ((double)nB * P.ahx) * w_td;
   const uint32_t jm = l & m;
-  // (the element part and the class index are compile-time in every access
-  // to the class tables below, so that the tables stay in registers; a class
-  // chosen at run time is read through select chains)
+  const int nJ = popc(jm);
+  const double WJ = (double)nJ * P.gamma;
+  // each part's total weight (the suffix sums from the last class down)
+  const double S0re = WJ + (WyA + (WyB + (WyA + WyB)));
+  const double S0im = Wh0 + (Wh1 + (Wh2 + (Wh3 + (Wh4 + (Wh5 + (WxA + (WxB + (WxA + WxB))))))));
+  const double p_r = P.dt * __builtin_fabs(d_r);
+  const double p_i = P.dt * __builtin_fabs(d_i);
+  const double P_re = P.dt * S0re;
+  const double P_im = P.dt * S0im;
+  EntryCounter cnt{P.seed, ((uint64_t)l << P.N) | m, P.solve, step, 0};
+  int dry = 0;
+  int64_t X0 = 0, X1 = 0, X2 = 0, X3 = 0, X4 = 0, X5 = 0, X6 = 0, X7 = 0;
+  if constexpr (SMALL) {
+    if (!small_draw(nR, p_r) || !small_draw(nI, p_r) || !small_draw(nR, p_i) ||
+        !small_draw(nI, p_i) || !small_draw(nR, P_re) || !small_draw(nI, P_re) ||
+        !small_draw(nR, P_im) || !small_draw(nI, P_im))
+      return false;
+    // successive primary uniforms locate the channels with events (as
+    // event_channels), each count then drawn from its own stream
+    const double pk[4] = {p_r, p_i, P_re, P_im};
+    double f[8];
 #pragma unroll
-  for (int im_el = 0; im_el < 2; ++im_el) {  // element part: 0 Re (channels 3, 7), 1 Im (4, 8)
-    constexpr int NCMAX = 10;
-    const int nc = im_el ? 10 : 5;
-    for (int im_par = 0; im_par < 2; ++im_par) {  // parent part: 0 real walkers, 1 imaginary
-      const int ch = im_el ? (im_par ? 8 : 4) : (im_par ? 7 : 3);
-      int64_t rem = im_el ? (im_par ? X[7] : X[3]) : (im_par ? X[6] : X[2]);
+    for (int k = 0; k < 8; ++k) {
+      const int64_t nk = k < 4 ? nR : nI;
+      f[k] = (nk > 0 && pk[k & 3] > 0.0) ? ipow(1.0 - pk[k & 3], nk) : 1.0;
+    }
+    Stream prim(cnt.seed, cnt.solve, cnt.cfg, cnt.step, 0, nullptr);
+    int start = 0;
+#pragma unroll 1
+    while (start < 8) {
+      double G[8];
+      double g = 1.0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        if (k >= start) g = g * f[k];
+        G[k] = g;
+      }
+      const double u = prim.next();
+      if (u < G[7]) break;
+      int first = 8;
+#pragma unroll
+      for (int k = 7; k >= 0; --k)
+        if (k >= start && u >= G[k]) first = k;
+      const int64_t nk = first < 4 ? nR : nI;
+      double p = pk[0];
+      p = (first & 3) == 1 ? pk[1] : p;
+      p = (first & 3) == 2 ? pk[2] : p;
+      p = (first & 3) == 3 ? pk[3] : p;
+      const int64_t x = binomial_small(cnt.seed, cnt.solve, cnt.cfg, cnt.step,
+                                       draw_channel(first + 1), nk, p, true, dry);
+      X0 = first == 0 ? x : X0;
+      X1 = first == 1 ? x : X1;
+      X2 = first == 2 ? x : X2;
+      X3 = first == 3 ? x : X3;
+      X4 = first == 4 ? x : X4;
+      X5 = first == 5 ? x : X5;
+      X6 = first == 6 ? x : X6;
+      X7 = first == 7 ? x : X7;
+      start = first + 1;
+    }
+    if (X2 >= 20 || X3 >= 20 || X6 >= 20 || X7 >= 20) return false;
+  } else {
+    const double p8[8] = {p_r, p_i, P_re, P_im, p_r, p_i, P_re, P_im};
+    const int64_t n8[8] = {nR, nR, nR, nR, nI, nI, nI, nI};
+    int64_t X[8];
+    channel_counts(p8, n8, cnt, X);
+    X0 = X[0], X1 = X[1], X2 = X[2], X3 = X[3], X4 = X[4], X5 = X[5], X6 = X[6], X7 = X[7];
+  }
+  const int64_t dR = sR * sgnd(d_r) * X0 - sI * sgnd(d_i) * X5;
+  const int64_t dI = sI * sgnd(d_r) * X4 + sR * sgnd(d_i) * X1;
+  if (dR != 0 || dI != 0) emit(l, m, dR, dI, true);
+  const int64_t x2 = X2, x3 = X3, x6 = X6, x7 = X7;
+  const int64_t sgx = sgnd(P.hx), sgy = sgnd(P.hy);
+  // one split's Bin(n, p) from draw id `id` of the entry's counter
+  auto draw = [&](uint32_t id, int64_t n, double p) -> int64_t {
+    if constexpr (SMALL)
+      return binomial_small(cnt.seed, cnt.solve, cnt.cfg, cnt.step, id, n, p, false, dry);
+    else
+      return cnt.inl(id, n, p, DRAW_BIN);
+  };
+
+#pragma unroll 1
+  for (int el = 0; el < 2; ++el) {  // element part: 0 Re (channels 3, 7), 1 Im (4, 8)
+    const int nc = el ? 10 : 5;
+    // the part's classes: weights, suffix sums, members
+    const double W0 = el ? Wh0 : WJ, W1 = el ? Wh1 : WyA, W2 = el ? Wh2 : WyB;
+    const double W3 = el ? Wh3 : WyA, W4 = el ? Wh4 : WyB, W5 = el ? Wh5 : 0.0;
+    const double W6 = el ? WxA : 0.0, W7 = el ? WxB : 0.0, W8 = el ? WxA : 0.0;
+    const double W9 = el ? WxB : 0.0;
+    const double Sc9 = W9, Sc8 = W8 + Sc9, Sc7 = W7 + Sc8, Sc6 = W6 + Sc7, Sc5 = W5 + Sc6;
+    const double Sc4 = W4 + Sc5, Sc3 = W3 + Sc4, Sc2 = W2 + Sc3, Sc1 = W1 + Sc2;
+    const double Sc0 = W0 + Sc1;
+    const int n0 = el ? hn0 : nJ, n1 = el ? hn1 : nA, n2 = el ? hn2 : nB, n3 = el ? hn3 : nA;
+    const int n4 = el ? hn4 : nB, n5 = el ? hn2 : 0, n6 = el ? nA : 0, n7 = el ? nB : 0;
+    const int n8c = el ? nA : 0, n9 = el ? nB : 0;
+#pragma unroll 1
+    for (int par = 0; par < 2; ++par) {  // parent part: 0 real walkers, 1 imaginary
+      const int ch = el ? (par ? 8 : 4) : (par ? 7 : 3);
+      int64_t rem = el ? (par ? x7 : x3) : (par ? x6 : x2);
       if (rem == 0) continue;
-      const int64_t sg = im_par ? sI : sR;
+      const int64_t sg = par ? sI : sR;
       // member j of class c: its child and the sign of its element part
       auto leaf = [&](int c, int j, int64_t M) {
         uint32_t cl = l, cm = m;
         int64_t sgn = 1;
         bool keep = init;
-        if (!im_el && c == 0) {  // a jump: down in both ket and bra
+        if (el == 0 && c == 0) {  // a jump: down in both ket and bra
           const uint32_t bit = 1u << nth_bit(jm, j);
           cl = l & ~bit;
           cm = m & ~bit;
-        } else if (im_el && c < 6) {  // a hop of one bond
-          const uint32_t bm = class_member_mask(P, pick6(hc.r, c), pick6(hc.u, c), j);
+        } else if (el == 1 && c < 6) {  // a hop of one bond
+          const uint32_t bm = class_member_mask(P, sel6(c, r0, r1, Tr, r3, r4, Tr),
+                                                sel6(c, u0, u1, Tu, u3, u4, Tu), j);
+          const int shc = sel6(c, sh_al, sh_an, sh2, sh_al, sh_an, sh2);
           cl = c < 3 ? (l ^ bm) : l;
           cm = c < 3 ? m : (m ^ bm);
-          sgn = pick6(hc.sgn, c);
+          sgn = c < 3 ? -shc : shc;  // ket: -i h, bra: +i h
           keep = init || cl == cm;
-        } else {  // a field flip
-          const int fk = im_el ? c - 6 : c - 1;
+        } else {  // a field flip: ket (k = 0, 1) or bra (2, 3), sites A (k even) or B
+          const int fk = el ? c - 6 : c - 1;
           const bool bra = fk >= 2;
-          uint32_t fm = f.fmask[0];
-#pragma unroll
-          for (int i = 1; i < 4; ++i) fm = (fk == i) ? f.fmask[i] : fm;
-          const uint32_t site = nth_bit(fm, j);
+          const uint32_t site = nth_bit((fk & 1) ? fB : fA, j);
           const uint32_t x = bra ? m : l;
           if (bra)
             cm = m ^ (1u << site);
           else
             cl = l ^ (1u << site);
-          sgn = im_el ? (bra ? sgnd(P.hx) : -sgnd(P.hx))
-                      : (((x >> site) & 1u) ? sgnd(P.hy) : -sgnd(P.hy));
+          sgn = el ? (bra ? sgx : -sgx) : (((x >> site) & 1u) ? sgy : -sgy);
           keep = init || cl == cm;
         }
         const int64_t v = sg * sgn * M;
         // (R + iI) x element part: Re x R -> re, Re x I -> im, Im x R -> im,
         // Im x I -> -re (Sec. III.C rule (i))
-        if (!im_el && !im_par)
+        if (!el && !par)
           emit(cl, cm, v, 0, keep);
-        else if (!im_el || !im_par)
+        else if (!el || !par)
           emit(cl, cm, 0, v, keep);
         else
           emit(cl, cm, -v, 0, keep);
       };
       if (rem == 1) {
         Stream st(cnt.seed, cnt.solve, cnt.cfg, cnt.step, draw_channel(ch) + DRAW_PICK, nullptr);
-        const double u1 = st.next();
-        const double u2 = st.next();
-        const double T = f.Sc[im_el][0] * (1.0 - u1);
+        const double u_1 = st.next();
+        const double u_2 = st.next();
+        const double T = Sc0 * (1.0 - u_1);
         // the first class c with Sc[c + 1] < T (the suffix sums fall, and
         // Sc[nc] = 0 < T), and its member count
-        int c = 0, nmem = f.n[im_el][0];
-#pragma unroll
-        for (int cc = 1; cc < NCMAX; ++cc)
-          if (cc < nc && !(f.Sc[im_el][cc] < T)) {
-            c = cc;
-            nmem = f.n[im_el][cc];
-          }
-        int j = (int)__builtin_floor(u2 * (double)nmem);
+        int c = 0, nmem = n0;
+        if (!(Sc1 < T)) c = 1, nmem = n1;
+        if (!(Sc2 < T)) c = 2, nmem = n2;
+        if (!(Sc3 < T)) c = 3, nmem = n3;
+        if (!(Sc4 < T)) c = 4, nmem = n4;
+        if (nc > 5) {
+          if (!(Sc5 < T)) c = 5, nmem = n5;
+          if (!(Sc6 < T)) c = 6, nmem = n6;
+          if (!(Sc7 < T)) c = 7, nmem = n7;
+          if (!(Sc8 < T)) c = 8, nmem = n8c;
+          if (!(Sc9 < T)) c = 9, nmem = n9;
+        }
+        int j = (int)__builtin_floor(u_2 * (double)nmem);
         j = j > nmem - 1 ? nmem - 1 : j;
         leaf(c, j, 1);
         continue;
       }
       int last = -1;
-#pragma unroll
-      for (int c = 0; c < NCMAX; ++c)
-        if (c < nc && f.W[im_el][c] > 0.0) last = c;
-#pragma unroll
-      for (int c = 0; c < NCMAX; ++c) {
-        if (c >= nc || rem == 0 || f.W[im_el][c] == 0.0) continue;
+      last = W0 > 0.0 ? 0 : last;
+      last = W1 > 0.0 ? 1 : last;
+      last = W2 > 0.0 ? 2 : last;
+      last = W3 > 0.0 ? 3 : last;
+      last = W4 > 0.0 ? 4 : last;
+      last = W5 > 0.0 ? 5 : last;
+      last = W6 > 0.0 ? 6 : last;
+      last = W7 > 0.0 ? 7 : last;
+      last = W8 > 0.0 ? 8 : last;
+      last = W9 > 0.0 ? 9 : last;
+#pragma unroll 1
+      for (int c = 0; c < nc; ++c) {
+        const double Wc = sel10(c, W0, W1, W2, W3, W4, W5, W6, W7, W8, W9);
+        if (rem == 0 || Wc == 0.0) continue;
         int64_t Mc;
-        if (c == last)
+        if (c == last) {
           Mc = rem;
-        else
-          Mc = cnt.inl(draw_channel(ch) + class_split_draw(c), rem,
-                       f.W[im_el][c] / f.Sc[im_el][c], DRAW_BIN);
+        } else {
+          const double Scc = sel10(c, Sc0, Sc1, Sc2, Sc3, Sc4, Sc5, Sc6, Sc7, Sc8, Sc9);
+          Mc = draw(draw_channel(ch) + class_split_draw(c), rem, Wc / Scc);
+        }
         rem -= Mc;
         if (Mc == 0) continue;
         // (at most 64 members: bonds, jump and field sites of N <= 32 sites)
-        tree_split_flat(f.n[im_el][c], Mc, cnt, draw_channel(ch) + 64u + 64u * (uint32_t)c,
-                        [&](int j, int64_t M) { leaf(c, j, M); });
+        const int nm = sel10(c, n0, n1, n2, n3, n4, n5, n6, n7, n8c, n9);
+        tree_split_flat_with(nm, Mc, draw_channel(ch) + 64u + 64u * (uint32_t)c, draw,
+                             [&](int j, int64_t M) { leaf(c, j, M); });
       }
     }
   }
-  if (cnt.dry) *err = 1;
+  if (cnt.dry || dry) *err = 1;
+  return true;
+}
+
+template <typename Emit>
+DQ_HD void entry_events_field(const SlotParams &P, double S, uint32_t step, uint32_t l,
+                              uint32_t m, int32_t R, int32_t I, int *err, Emit &&emit) {
+  (void)entry_events_field_impl<false>(P, S, step, l, m, R, I, err, emit);
+}
+
+// entry_events_field for an entry whose draws are all small (see above);
+// false, with nothing emitted, for any other.
+template <typename Emit>
+DQ_HD bool entry_events_field_small(const SlotParams &P, double S, uint32_t step, uint32_t l,
+                                    uint32_t m, int32_t R, int32_t I, int *err, Emit &&emit) {
+  return entry_events_field_impl<true>(P, S, step, l, m, R, I, err, emit);
 }
 
 // ---- per-walker sampling (the rules of Sec. II, walker by walker) ----------
