@@ -576,9 +576,9 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
         HIPC(hipEventRecord(h->ev_fork, s));
         HIPC(hipStreamWaitEvent(h->side, h->ev_fork, 0));
       }
-      // (the large entries on a quarter block per CU: one wave each, leaving
-      // the CUs to the call-free routine)
-      k_spawn_listed<K, false><<<clampu(h->ncu / 4, 1, 4096), NT, 0, hs>>>(
+      // (the large entries on half a block per CU, dealt one per wave first,
+      // leaving the rest of the CUs to the call-free routine)
+      k_spawn_listed<K, false><<<clampu(h->ncu / 2, 1, 4096), NT, 0, hs>>>(
           c, h->dsp, h->dss, ak, av, h->heavy, &c->n_heavy, nullptr, (K *)h->sk[0], h->sv[0],
           h->segcnt, segcap, h->SB);
       if (h->fork_heavy) HIPC(hipEventRecord(h->ev_join, h->side));

@@ -783,7 +783,19 @@ __global__ __launch_bounds__(NT, 2) void k_spawn_listed(Ctrl *ctrl,
   __shared__ int2 sv[STAGE];
   __shared__ uint32_t scount;
   __shared__ unsigned long long sbase;
+  // With the field's call-free routine, and for a list through idx (the
+  // field's large entries), the parts with two or more walkers (class splits
+  // and member trees) are queued, then sampled one per thread once NT of them
+  // wait (or at the end), so that a wave's lanes walk them together instead
+  // of idling beside the few that have them.
+  constexpr uint32_t JOBS = 4 * NT;
+  __shared__ uint32_t jq[JOBS];    // entry index in (skey, sval)
+  __shared__ uint32_t jrem[JOBS];  // walkers of the part
+  __shared__ uint8_t jinfo[JOBS];  // el | par << 1
+  __shared__ uint32_t jcount;
+  if (threadIdx.x == 0) jcount = 0;
   const uint32_t n = *count;
+  const bool queued = FIELD_ONLY || idx != nullptr;
   const int seg = blockIdx.x % NSEG;
   const K lowm = low_mask<K>(SB);
   int rng_err = 0;
@@ -815,14 +827,51 @@ __global__ __launch_bounds__(NT, 2) void k_spawn_listed(Ctrl *ctrl,
       auto rec = [&](uint32_t cl, uint32_t cm, int64_t dr, int64_t di, bool keep) {
         sink(hibits | (K)(((uint64_t)cl << N) | cm), dr, di, keep);
       };
+      auto queue = [&](int el, int par, int64_t rem) {
+        if (!queued) return false;
+        const uint32_t at = atomicAdd(&jcount, 1u);
+        if (at >= JOBS) return false;
+        jq[at] = q;
+        jrem[at] = (uint32_t)rem;
+        jinfo[at] = (uint8_t)(el | (par << 1));
+        return true;
+      };
       if constexpr (FIELD_ONLY) {
-        if (!entry_events_field_small(P, ss[slot].S, step, l, m, v.x, v.y, &rng_err, rec))
+        if (!entry_events_field_small(P, ss[slot].S, step, l, m, v.x, v.y, &rng_err, rec, queue))
           late[atomicAdd(&ctrl->n_late, 1u)] = q;
       } else {
         if (P.field)
-          entry_events_field(P, ss[slot].S, step, l, m, v.x, v.y, &rng_err, rec);
+          entry_events_field(P, ss[slot].S, step, l, m, v.x, v.y, &rng_err, rec, queue);
         else
           entry_events(P, ss[slot].S, step, l, m, v.x, v.y, &rng_err, rec);
+      }
+    }
+    __syncthreads();
+    if (queued) {
+      // (block-uniform: jcount and the last iteration are the same for all)
+      const uint32_t nj = jcount < JOBS ? jcount : JOBS;
+      if (nj >= NT || (nj > 0 && base + gridDim.x * NT >= n)) {
+        for (uint32_t t = threadIdx.x; t < nj; t += NT) {
+          const uint32_t q = jq[t];
+          const uint32_t info = jinfo[t];
+          const K key = skey[q];
+          const int2 v = sval[q];
+          const uint32_t slot = slot_of<K>(key, SB);
+          const SlotParams &P = sp[slot];
+          const K hibits = key & ~lowm;
+          const uint64_t cfg = (uint64_t)(key & lowm);
+          const uint32_t N = P.N;
+          const uint32_t l = (uint32_t)(cfg >> N);
+          const uint32_t m = (uint32_t)(cfg & ((N == 32) ? 0xffffffffull : ((1ull << N) - 1)));
+          auto rec = [&](uint32_t cl, uint32_t cm, int64_t dr, int64_t di, bool keep) {
+            sink(hibits | (K)(((uint64_t)cl << N) | cm), dr, di, keep);
+          };
+          field_part_job<FIELD_ONLY>(P, ss[slot].S, (uint32_t)ss[slot].step, l, m, v.x, v.y,
+                                     (int)(info & 1u), (int)((info >> 1) & 1u),
+                                     (int64_t)jrem[t], &rng_err, rec);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) jcount = 0;
       }
     }
     __syncthreads();

@@ -642,30 +642,27 @@ DQ_HD T sel10(int c, T a0, T a1, T a2, T a3, T a4, T a5, T a6, T a7, T a8, T a9)
   return v;
 }
 
-// entry_events with the field on (the slot's P.field): the same clone/death,
-// the real element part's jumps and field flips, the imaginary part's hops
-// and field flips, each part's walkers placed by one class split (sequential
-// conditional binomials, the last class with weight taking the rest; one
-// walker by one categorical pick) and the member trees.  The same
-// probabilities, draws and records as field_channels / field_parts would
-// give, computed without arrays: every class table is a set of values (the
-// real part's five classes padded with empty ones to the imaginary part's
-// ten, which leaves its suffix sums as they are), and a class chosen at run
-// time is read through select chains, so the tables stay in registers.
-// SMALL: every draw by inversion (binomial_small, the same values), with no
-// out-of-line call, for entries whose channel probabilities are all small for
-// both parts' walkers and whose spawn counts stay below 20 (so that every
-// class and tree split is small too); false, before anything is emitted, for
-// an entry that is not such (the caller hands it to the general routine).
-template <bool SMALL, typename Emit>
-DQ_HD bool entry_events_field_impl(const SlotParams &P, double S, uint32_t step, uint32_t l,
-                                   uint32_t m, int32_t R, int32_t I, int *err, Emit &&emit) {
+// The geometry and class weights of an entry |l><m| of a solve with the
+// field, as values (a struct of scalars, no arrays, so that they stay in
+// registers): aligned bonds, the bond l ^ m if it is one, the hop classes
+// (0 ket-aligned, 1 ket-anti, 2 ket to-diagonal, 3-5 the bra's) and the field
+// classes (flips of the sites where l and m agree, A, and of the one where
+// they differ if only one, B).  The same expressions as geometry /
+// hop_classes / field_parts.
+struct FieldGeom {
+  uint32_t r0, u0, r1, u1, r3, u3, r4, u4, Tr, Tu;  // hop classes' bond origins
+  int hn0, hn1, hn2, hn3, hn4;                       // their members (class 5 as 2)
+  int sh_al, sh_an, sh2;                             // sign of h: aligned, anti, class 2
+  double Wh0, Wh1, Wh2, Wh3, Wh4, Wh5;               // hop class weights
+  uint32_t fA, fB, jm;                               // field flip sites; jump sites
+  int nA, nB, nJ;
+  double WyA, WyB, WxA, WxB, WJ;                     // field and jump class weights
+  double d_r, d_i;                                   // the diagonal element
+};
+
+DQ_HD FieldGeom field_geom(const SlotParams &P, double S, uint32_t l, uint32_t m) {
+  FieldGeom g;
   const bool diag = (l == m);
-  const int64_t nR = R < 0 ? -(int64_t)R : (int64_t)R;
-  const int64_t nI = I < 0 ? -(int64_t)I : (int64_t)I;
-  const int64_t sR = sgn64(R), sI = sgn64(I);
-  const bool init = diag || (nR + nI > P.n_a) || (P.flags & FLAG_NO_INITIATOR);
-  // geometry: aligned bonds of l and m, the bond l ^ m if it is one
   const uint32_t al_r0 = ~(l ^ right_of(P, l)) & P.rmask;
   const uint32_t al_u0 = ~(l ^ up_of(P, l)) & P.umask;
   const uint32_t al_r1 = ~(m ^ right_of(P, m)) & P.rmask;
@@ -679,40 +676,191 @@ DQ_HD bool entry_events_field_impl(const SlotParams &P, double S, uint32_t step,
     Tu = d & up_of(P, d) & P.umask;
   }
   const bool T_al = ((Tr | Tu) == 0) || ((al_r0 & Tr) | (al_u0 & Tu)) != 0;
-  const double d_r = -(P.half_gamma * (double)(popc(l) + popc(m))) - S;
-  const double d_i = P.half_jz * (double)(al1 - al0);
-  // hop classes 0 ket-aligned, 1 ket-anti, 2 ket to-diagonal, 3-5 the bra's
-  const uint32_t r0 = al_r0 & ~Tr, u0 = al_u0 & ~Tu;
-  const uint32_t r1 = ~al_r0 & P.rmask & ~Tr, u1 = ~al_u0 & P.umask & ~Tu;
-  const uint32_t r3 = al_r1 & ~Tr, u3 = al_u1 & ~Tu;
-  const uint32_t r4 = ~al_r1 & P.rmask & ~Tr, u4 = ~al_u1 & P.umask & ~Tu;
-  const int hn0 = popc(r0) + popc(u0), hn1 = popc(r1) + popc(u1), hn2 = popc(Tr) + popc(Tu);
-  const int hn3 = popc(r3) + popc(u3), hn4 = popc(r4) + popc(u4);
+  g.d_r = -(P.half_gamma * (double)(popc(l) + popc(m))) - S;
+  g.d_i = P.half_jz * (double)(al1 - al0);
+  g.Tr = Tr;
+  g.Tu = Tu;
+  g.r0 = al_r0 & ~Tr, g.u0 = al_u0 & ~Tu;
+  g.r1 = ~al_r0 & P.rmask & ~Tr, g.u1 = ~al_u0 & P.umask & ~Tu;
+  g.r3 = al_r1 & ~Tr, g.u3 = al_u1 & ~Tu;
+  g.r4 = ~al_r1 & P.rmask & ~Tr, g.u4 = ~al_u1 & P.umask & ~Tu;
+  g.hn0 = popc(g.r0) + popc(g.u0), g.hn1 = popc(g.r1) + popc(g.u1);
+  g.hn2 = popc(Tr) + popc(Tu), g.hn3 = popc(g.r3) + popc(g.u3), g.hn4 = popc(g.r4) + popc(g.u4);
   const double w_al = diag ? P.w_dn : 1.0;    // weight ratio off the diagonal target
   const double w_td = diag ? P.w_dn : P.w_up;  // ... onto it
   const double amp2 = T_al ? P.a_al : P.a_an;
-  const double Wh0 = ((double)hn0 * P.a_al) * w_al, Wh1 = ((double)hn1 * P.a_an) * w_al;
-  const double Wh2 = ((double)hn2 * amp2) * w_td;
-  const double Wh3 = ((double)hn3 * P.a_al) * w_al, Wh4 = ((double)hn4 * P.a_an) * w_al;
-  const double Wh5 = ((double)hn2 * amp2) * w_td;
-  const int sh_al = (P.h_al > 0.0) - (P.h_al < 0.0), sh_an = (P.h_an > 0.0) - (P.h_an < 0.0);
-  const int sh2 = T_al ? sh_al : sh_an;
-  // field classes: flips of the sites where l and m agree (A) and of the one
-  // where they differ, if only one (B), on the ket and on the bra
+  g.Wh0 = ((double)g.hn0 * P.a_al) * w_al, g.Wh1 = ((double)g.hn1 * P.a_an) * w_al;
+  g.Wh2 = ((double)g.hn2 * amp2) * w_td;
+  g.Wh3 = ((double)g.hn3 * P.a_al) * w_al, g.Wh4 = ((double)g.hn4 * P.a_an) * w_al;
+  g.Wh5 = ((double)g.hn2 * amp2) * w_td;
+  g.sh_al = (P.h_al > 0.0) - (P.h_al < 0.0), g.sh_an = (P.h_an > 0.0) - (P.h_an < 0.0);
+  g.sh2 = T_al ? g.sh_al : g.sh_an;
   const uint32_t all = P.N == 32 ? 0xffffffffu : ((1u << P.N) - 1u);
   const uint32_t tbit = popc(d) == 1 ? d : 0u;
-  const uint32_t fA = all & ~tbit, fB = tbit;
-  const int nA = popc(fA), nB = popc(fB);
-  const double WyA = ((double)nA * P.ahy) * w_al, WyB = ((double)nB * P.ahy) * w_td;
-  const double WxA = ((double)nA * P.ahx) * w_al, WxB = ((double)nB * P.ahx) * w_td;
-  const uint32_t jm = l & m;
-  const int nJ = popc(jm);
-  const double WJ = (double)nJ * P.gamma;
+  g.fA = all & ~tbit, g.fB = tbit;
+  g.nA = popc(g.fA), g.nB = popc(g.fB);
+  g.WyA = ((double)g.nA * P.ahy) * w_al, g.WyB = ((double)g.nB * P.ahy) * w_td;
+  g.WxA = ((double)g.nA * P.ahx) * w_al, g.WxB = ((double)g.nB * P.ahx) * w_td;
+  g.jm = l & m;
+  g.nJ = popc(g.jm);
+  g.WJ = (double)g.nJ * P.gamma;
+  return g;
+}
+
+// The walkers one parent part (par: 0 real, 1 imaginary, sign sg) sends along
+// element part el (0 Re: jump and field classes, 1 Im: hop and field
+// classes), rem >= 1 of them: one by one categorical pick, else the class
+// split (sequential conditional binomials, the last class with weight taking
+// the rest) and the member trees.  The part's classes are values (the real
+// part's five padded with empty ones to the imaginary part's ten, which
+// leaves its suffix sums as they are); a class chosen at run time is read
+// through select chains.  SMALL: every split by the inline inversion sampler
+// (rem < 20, so each is small).
+template <bool SMALL, typename Emit>
+DQ_HD void field_part(const SlotParams &P, const FieldGeom &g, EntryCounter &cnt, int &dry,
+                      uint32_t l, uint32_t m, bool init, int el, int par, int64_t sg, int64_t rem,
+                      Emit &&emit) {
+  const int nc = el ? 10 : 5;
+  const int ch = el ? (par ? 8 : 4) : (par ? 7 : 3);
+  const double W0 = el ? g.Wh0 : g.WJ, W1 = el ? g.Wh1 : g.WyA, W2 = el ? g.Wh2 : g.WyB;
+  const double W3 = el ? g.Wh3 : g.WyA, W4 = el ? g.Wh4 : g.WyB, W5 = el ? g.Wh5 : 0.0;
+  const double W6 = el ? g.WxA : 0.0, W7 = el ? g.WxB : 0.0, W8 = el ? g.WxA : 0.0;
+  const double W9 = el ? g.WxB : 0.0;
+  const double Sc9 = W9, Sc8 = W8 + Sc9, Sc7 = W7 + Sc8, Sc6 = W6 + Sc7, Sc5 = W5 + Sc6;
+  const double Sc4 = W4 + Sc5, Sc3 = W3 + Sc4, Sc2 = W2 + Sc3, Sc1 = W1 + Sc2;
+  const double Sc0 = W0 + Sc1;
+  const int n0 = el ? g.hn0 : g.nJ, n1 = el ? g.hn1 : g.nA, n2 = el ? g.hn2 : g.nB;
+  const int n3 = el ? g.hn3 : g.nA, n4 = el ? g.hn4 : g.nB, n5 = el ? g.hn2 : 0;
+  const int n6 = el ? g.nA : 0, n7 = el ? g.nB : 0, n8 = el ? g.nA : 0, n9 = el ? g.nB : 0;
+  const int64_t sgx = sgnd(P.hx), sgy = sgnd(P.hy);
+  // member j of class c: its child and the sign of its element part
+  auto leaf = [&](int c, int j, int64_t M) {
+    uint32_t cl = l, cm = m;
+    int64_t sgn = 1;
+    bool keep = init;
+    if (el == 0 && c == 0) {  // a jump: down in both ket and bra
+      const uint32_t bit = 1u << nth_bit(g.jm, j);
+      cl = l & ~bit;
+      cm = m & ~bit;
+    } else if (el == 1 && c < 6) {  // a hop of one bond
+      const uint32_t bm = class_member_mask(P, sel6(c, g.r0, g.r1, g.Tr, g.r3, g.r4, g.Tr),
+                                            sel6(c, g.u0, g.u1, g.Tu, g.u3, g.u4, g.Tu), j);
+      const int shc = sel6(c, g.sh_al, g.sh_an, g.sh2, g.sh_al, g.sh_an, g.sh2);
+      cl = c < 3 ? (l ^ bm) : l;
+      cm = c < 3 ? m : (m ^ bm);
+      sgn = c < 3 ? -shc : shc;  // ket: -i h, bra: +i h
+      keep = init || cl == cm;
+    } else {  // a field flip: ket (k = 0, 1) or bra (2, 3), sites A (k even) or B
+      const int fk = el ? c - 6 : c - 1;
+      const bool bra = fk >= 2;
+      const uint32_t site = nth_bit((fk & 1) ? g.fB : g.fA, j);
+      const uint32_t x = bra ? m : l;
+      if (bra)
+        cm = m ^ (1u << site);
+      else
+        cl = l ^ (1u << site);
+      sgn = el ? (bra ? sgx : -sgx) : (((x >> site) & 1u) ? sgy : -sgy);
+      keep = init || cl == cm;
+    }
+    const int64_t v = sg * sgn * M;
+    // (R + iI) x element part: Re x R -> re, Re x I -> im, Im x R -> im,
+    // Im x I -> -re (Sec. III.C rule (i))
+    if (!el && !par)
+      emit(cl, cm, v, 0, keep);
+    else if (!el || !par)
+      emit(cl, cm, 0, v, keep);
+    else
+      emit(cl, cm, -v, 0, keep);
+  };
+  if (rem == 1) {
+    Stream st(cnt.seed, cnt.solve, cnt.cfg, cnt.step, draw_channel(ch) + DRAW_PICK, nullptr);
+    const double u_1 = st.next();
+    const double u_2 = st.next();
+    const double T = Sc0 * (1.0 - u_1);
+    // the first class c with Sc[c + 1] < T (the suffix sums fall, and
+    // Sc[nc] = 0 < T), and its member count
+    int c = 0, nmem = n0;
+    if (!(Sc1 < T)) c = 1, nmem = n1;
+    if (!(Sc2 < T)) c = 2, nmem = n2;
+    if (!(Sc3 < T)) c = 3, nmem = n3;
+    if (!(Sc4 < T)) c = 4, nmem = n4;
+    if (nc > 5) {
+      if (!(Sc5 < T)) c = 5, nmem = n5;
+      if (!(Sc6 < T)) c = 6, nmem = n6;
+      if (!(Sc7 < T)) c = 7, nmem = n7;
+      if (!(Sc8 < T)) c = 8, nmem = n8;
+      if (!(Sc9 < T)) c = 9, nmem = n9;
+    }
+    int j = (int)__builtin_floor(u_2 * (double)nmem);
+    j = j > nmem - 1 ? nmem - 1 : j;
+    leaf(c, j, 1);
+    return;
+  }
+  // one split's Bin(n, p) from draw id `id` of the entry's counter
+  auto draw = [&](uint32_t id, int64_t n, double p) -> int64_t {
+    if constexpr (SMALL)
+      return binomial_small(cnt.seed, cnt.solve, cnt.cfg, cnt.step, id, n, p, false, dry);
+    else
+      return cnt.inl(id, n, p, DRAW_BIN);
+  };
+  int last = -1;
+  last = W0 > 0.0 ? 0 : last;
+  last = W1 > 0.0 ? 1 : last;
+  last = W2 > 0.0 ? 2 : last;
+  last = W3 > 0.0 ? 3 : last;
+  last = W4 > 0.0 ? 4 : last;
+  last = W5 > 0.0 ? 5 : last;
+  last = W6 > 0.0 ? 6 : last;
+  last = W7 > 0.0 ? 7 : last;
+  last = W8 > 0.0 ? 8 : last;
+  last = W9 > 0.0 ? 9 : last;
+#pragma unroll 1
+  for (int c = 0; c < nc; ++c) {
+    const double Wc = sel10(c, W0, W1, W2, W3, W4, W5, W6, W7, W8, W9);
+    if (rem == 0 || Wc == 0.0) continue;
+    int64_t Mc;
+    if (c == last) {
+      Mc = rem;
+    } else {
+      const double Scc = sel10(c, Sc0, Sc1, Sc2, Sc3, Sc4, Sc5, Sc6, Sc7, Sc8, Sc9);
+      Mc = draw(draw_channel(ch) + class_split_draw(c), rem, Wc / Scc);
+    }
+    rem -= Mc;
+    if (Mc == 0) continue;
+    // (at most 64 members: bonds, jump and field sites of N <= 32 sites)
+    const int nm = sel10(c, n0, n1, n2, n3, n4, n5, n6, n7, n8, n9);
+    tree_split_flat_with(nm, Mc, draw_channel(ch) + 64u + 64u * (uint32_t)c, draw,
+                         [&](int j, int64_t M) { leaf(c, j, M); });
+  }
+}
+
+// entry_events with the field on (the slot's P.field): the same clone/death,
+// the real element part's jumps and field flips, the imaginary part's hops
+// and field flips (field_part).  The same probabilities, draws and records as
+// field_channels / field_parts would give.
+// SMALL: every draw by inversion (binomial_small, the same values), with no
+// out-of-line call, for entries whose channel probabilities are all small for
+// both parts' walkers and whose spawn counts stay below 20 (so that every
+// class and tree split is small too); false, before anything is emitted, for
+// an entry that is not such (the caller hands it to the general routine).
+// A part with two or more walkers may be handed to queue(el, par, rem),
+// which returns true when it takes it (field_part_job samples it later).
+template <bool SMALL, typename Emit, typename Queue>
+DQ_HD bool entry_events_field_impl(const SlotParams &P, double S, uint32_t step, uint32_t l,
+                                   uint32_t m, int32_t R, int32_t I, int *err, Emit &&emit,
+                                   Queue &&queue) {
+  const bool diag = (l == m);
+  const int64_t nR = R < 0 ? -(int64_t)R : (int64_t)R;
+  const int64_t nI = I < 0 ? -(int64_t)I : (int64_t)I;
+  const int64_t sR = sgn64(R), sI = sgn64(I);
+  const bool init = diag || (nR + nI > P.n_a) || (P.flags & FLAG_NO_INITIATOR);
+  const FieldGeom g = field_geom(P, S, l, m);
   // each part's total weight (the suffix sums from the last class down)
-  const double S0re = WJ + (WyA + (WyB + (WyA + WyB)));
-  const double S0im = Wh0 + (Wh1 + (Wh2 + (Wh3 + (Wh4 + (Wh5 + (WxA + (WxB + (WxA + WxB))))))));
-  const double p_r = P.dt * __builtin_fabs(d_r);
-  const double p_i = P.dt * __builtin_fabs(d_i);
+  const double S0re = g.WJ + (g.WyA + (g.WyB + (g.WyA + g.WyB)));
+  const double S0im =
+      g.Wh0 + (g.Wh1 + (g.Wh2 + (g.Wh3 + (g.Wh4 + (g.Wh5 + (g.WxA + (g.WxB + (g.WxA + g.WxB))))))));
+  const double p_r = P.dt * __builtin_fabs(g.d_r);
+  const double p_i = P.dt * __builtin_fabs(g.d_i);
   const double P_re = P.dt * S0re;
   const double P_im = P.dt * S0im;
   EntryCounter cnt{P.seed, ((uint64_t)l << P.N) | m, P.solve, step, 0};
@@ -737,11 +885,11 @@ DQ_HD bool entry_events_field_impl(const SlotParams &P, double S, uint32_t step,
 #pragma unroll 1
     while (start < 8) {
       double G[8];
-      double g = 1.0;
+      double gg = 1.0;
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        if (k >= start) g = g * f[k];
-        G[k] = g;
+        if (k >= start) gg = gg * f[k];
+        G[k] = gg;
       }
       const double u = prim.next();
       if (u < G[7]) break;
@@ -774,149 +922,57 @@ DQ_HD bool entry_events_field_impl(const SlotParams &P, double S, uint32_t step,
     channel_counts(p8, n8, cnt, X);
     X0 = X[0], X1 = X[1], X2 = X[2], X3 = X[3], X4 = X[4], X5 = X[5], X6 = X[6], X7 = X[7];
   }
-  const int64_t dR = sR * sgnd(d_r) * X0 - sI * sgnd(d_i) * X5;
-  const int64_t dI = sI * sgnd(d_r) * X4 + sR * sgnd(d_i) * X1;
+  const int64_t dR = sR * sgnd(g.d_r) * X0 - sI * sgnd(g.d_i) * X5;
+  const int64_t dI = sI * sgnd(g.d_r) * X4 + sR * sgnd(g.d_i) * X1;
   if (dR != 0 || dI != 0) emit(l, m, dR, dI, true);
-  const int64_t x2 = X2, x3 = X3, x6 = X6, x7 = X7;
-  const int64_t sgx = sgnd(P.hx), sgy = sgnd(P.hy);
-  // one split's Bin(n, p) from draw id `id` of the entry's counter
-  auto draw = [&](uint32_t id, int64_t n, double p) -> int64_t {
-    if constexpr (SMALL)
-      return binomial_small(cnt.seed, cnt.solve, cnt.cfg, cnt.step, id, n, p, false, dry);
-    else
-      return cnt.inl(id, n, p, DRAW_BIN);
-  };
-
 #pragma unroll 1
-  for (int el = 0; el < 2; ++el) {  // element part: 0 Re (channels 3, 7), 1 Im (4, 8)
-    const int nc = el ? 10 : 5;
-    // the part's classes: weights, suffix sums, members
-    const double W0 = el ? Wh0 : WJ, W1 = el ? Wh1 : WyA, W2 = el ? Wh2 : WyB;
-    const double W3 = el ? Wh3 : WyA, W4 = el ? Wh4 : WyB, W5 = el ? Wh5 : 0.0;
-    const double W6 = el ? WxA : 0.0, W7 = el ? WxB : 0.0, W8 = el ? WxA : 0.0;
-    const double W9 = el ? WxB : 0.0;
-    const double Sc9 = W9, Sc8 = W8 + Sc9, Sc7 = W7 + Sc8, Sc6 = W6 + Sc7, Sc5 = W5 + Sc6;
-    const double Sc4 = W4 + Sc5, Sc3 = W3 + Sc4, Sc2 = W2 + Sc3, Sc1 = W1 + Sc2;
-    const double Sc0 = W0 + Sc1;
-    const int n0 = el ? hn0 : nJ, n1 = el ? hn1 : nA, n2 = el ? hn2 : nB, n3 = el ? hn3 : nA;
-    const int n4 = el ? hn4 : nB, n5 = el ? hn2 : 0, n6 = el ? nA : 0, n7 = el ? nB : 0;
-    const int n8c = el ? nA : 0, n9 = el ? nB : 0;
+  for (int el = 0; el < 2; ++el)  // element part: 0 Re (channels 3, 7), 1 Im (4, 8)
 #pragma unroll 1
     for (int par = 0; par < 2; ++par) {  // parent part: 0 real walkers, 1 imaginary
-      const int ch = el ? (par ? 8 : 4) : (par ? 7 : 3);
-      int64_t rem = el ? (par ? x7 : x3) : (par ? x6 : x2);
-      if (rem == 0) continue;
-      const int64_t sg = par ? sI : sR;
-      // member j of class c: its child and the sign of its element part
-      auto leaf = [&](int c, int j, int64_t M) {
-        uint32_t cl = l, cm = m;
-        int64_t sgn = 1;
-        bool keep = init;
-        if (el == 0 && c == 0) {  // a jump: down in both ket and bra
-          const uint32_t bit = 1u << nth_bit(jm, j);
-          cl = l & ~bit;
-          cm = m & ~bit;
-        } else if (el == 1 && c < 6) {  // a hop of one bond
-          const uint32_t bm = class_member_mask(P, sel6(c, r0, r1, Tr, r3, r4, Tr),
-                                                sel6(c, u0, u1, Tu, u3, u4, Tu), j);
-          const int shc = sel6(c, sh_al, sh_an, sh2, sh_al, sh_an, sh2);
-          cl = c < 3 ? (l ^ bm) : l;
-          cm = c < 3 ? m : (m ^ bm);
-          sgn = c < 3 ? -shc : shc;  // ket: -i h, bra: +i h
-          keep = init || cl == cm;
-        } else {  // a field flip: ket (k = 0, 1) or bra (2, 3), sites A (k even) or B
-          const int fk = el ? c - 6 : c - 1;
-          const bool bra = fk >= 2;
-          const uint32_t site = nth_bit((fk & 1) ? fB : fA, j);
-          const uint32_t x = bra ? m : l;
-          if (bra)
-            cm = m ^ (1u << site);
-          else
-            cl = l ^ (1u << site);
-          sgn = el ? (bra ? sgx : -sgx) : (((x >> site) & 1u) ? sgy : -sgy);
-          keep = init || cl == cm;
-        }
-        const int64_t v = sg * sgn * M;
-        // (R + iI) x element part: Re x R -> re, Re x I -> im, Im x R -> im,
-        // Im x I -> -re (Sec. III.C rule (i))
-        if (!el && !par)
-          emit(cl, cm, v, 0, keep);
-        else if (!el || !par)
-          emit(cl, cm, 0, v, keep);
-        else
-          emit(cl, cm, -v, 0, keep);
-      };
-      if (rem == 1) {
-        Stream st(cnt.seed, cnt.solve, cnt.cfg, cnt.step, draw_channel(ch) + DRAW_PICK, nullptr);
-        const double u_1 = st.next();
-        const double u_2 = st.next();
-        const double T = Sc0 * (1.0 - u_1);
-        // the first class c with Sc[c + 1] < T (the suffix sums fall, and
-        // Sc[nc] = 0 < T), and its member count
-        int c = 0, nmem = n0;
-        if (!(Sc1 < T)) c = 1, nmem = n1;
-        if (!(Sc2 < T)) c = 2, nmem = n2;
-        if (!(Sc3 < T)) c = 3, nmem = n3;
-        if (!(Sc4 < T)) c = 4, nmem = n4;
-        if (nc > 5) {
-          if (!(Sc5 < T)) c = 5, nmem = n5;
-          if (!(Sc6 < T)) c = 6, nmem = n6;
-          if (!(Sc7 < T)) c = 7, nmem = n7;
-          if (!(Sc8 < T)) c = 8, nmem = n8c;
-          if (!(Sc9 < T)) c = 9, nmem = n9;
-        }
-        int j = (int)__builtin_floor(u_2 * (double)nmem);
-        j = j > nmem - 1 ? nmem - 1 : j;
-        leaf(c, j, 1);
-        continue;
-      }
-      int last = -1;
-      last = W0 > 0.0 ? 0 : last;
-      last = W1 > 0.0 ? 1 : last;
-      last = W2 > 0.0 ? 2 : last;
-      last = W3 > 0.0 ? 3 : last;
-      last = W4 > 0.0 ? 4 : last;
-      last = W5 > 0.0 ? 5 : last;
-      last = W6 > 0.0 ? 6 : last;
-      last = W7 > 0.0 ? 7 : last;
-      last = W8 > 0.0 ? 8 : last;
-      last = W9 > 0.0 ? 9 : last;
-#pragma unroll 1
-      for (int c = 0; c < nc; ++c) {
-        const double Wc = sel10(c, W0, W1, W2, W3, W4, W5, W6, W7, W8, W9);
-        if (rem == 0 || Wc == 0.0) continue;
-        int64_t Mc;
-        if (c == last) {
-          Mc = rem;
-        } else {
-          const double Scc = sel10(c, Sc0, Sc1, Sc2, Sc3, Sc4, Sc5, Sc6, Sc7, Sc8, Sc9);
-          Mc = draw(draw_channel(ch) + class_split_draw(c), rem, Wc / Scc);
-        }
-        rem -= Mc;
-        if (Mc == 0) continue;
-        // (at most 64 members: bonds, jump and field sites of N <= 32 sites)
-        const int nm = sel10(c, n0, n1, n2, n3, n4, n5, n6, n7, n8c, n9);
-        tree_split_flat_with(nm, Mc, draw_channel(ch) + 64u + 64u * (uint32_t)c, draw,
-                             [&](int j, int64_t M) { leaf(c, j, M); });
-      }
+      const int64_t rem = el ? (par ? X7 : X3) : (par ? X6 : X2);
+      if (rem == 0 || (rem >= 2 && queue(el, par, rem))) continue;
+      field_part<SMALL>(P, g, cnt, dry, l, m, init, el, par, par ? sI : sR, rem, emit);
     }
-  }
   if (cnt.dry || dry) *err = 1;
   return true;
+}
+
+template <typename Emit, typename Queue>
+DQ_HD void entry_events_field(const SlotParams &P, double S, uint32_t step, uint32_t l,
+                              uint32_t m, int32_t R, int32_t I, int *err, Emit &&emit,
+                              Queue &&queue) {
+  (void)entry_events_field_impl<false>(P, S, step, l, m, R, I, err, emit, queue);
 }
 
 template <typename Emit>
 DQ_HD void entry_events_field(const SlotParams &P, double S, uint32_t step, uint32_t l,
                               uint32_t m, int32_t R, int32_t I, int *err, Emit &&emit) {
-  (void)entry_events_field_impl<false>(P, S, step, l, m, R, I, err, emit);
+  entry_events_field(P, S, step, l, m, R, I, err, emit, [](int, int, int64_t) { return false; });
 }
 
 // entry_events_field for an entry whose draws are all small (see above);
-// false, with nothing emitted, for any other.
-template <typename Emit>
+// false, with nothing emitted, for any other.  queue as above.
+template <typename Emit, typename Queue>
 DQ_HD bool entry_events_field_small(const SlotParams &P, double S, uint32_t step, uint32_t l,
-                                    uint32_t m, int32_t R, int32_t I, int *err, Emit &&emit) {
-  return entry_events_field_impl<true>(P, S, step, l, m, R, I, err, emit);
+                                    uint32_t m, int32_t R, int32_t I, int *err, Emit &&emit,
+                                    Queue &&queue) {
+  return entry_events_field_impl<true>(P, S, step, l, m, R, I, err, emit, queue);
+}
+
+// A part that entry_events_field_impl<SMALL> queued: rem walkers of parent
+// part par along element part el of the entry |l><m| with walkers R + iI.
+template <bool SMALL, typename Emit>
+DQ_HD void field_part_job(const SlotParams &P, double S, uint32_t step, uint32_t l, uint32_t m,
+                          int32_t R, int32_t I, int el, int par, int64_t rem, int *err,
+                          Emit &&emit) {
+  const int64_t nR = R < 0 ? -(int64_t)R : (int64_t)R;
+  const int64_t nI = I < 0 ? -(int64_t)I : (int64_t)I;
+  const bool init = (l == m) || (nR + nI > P.n_a) || (P.flags & FLAG_NO_INITIATOR);
+  const FieldGeom g = field_geom(P, S, l, m);
+  EntryCounter cnt{P.seed, ((uint64_t)l << P.N) | m, P.solve, step, 0};
+  int dry = 0;
+  field_part<SMALL>(P, g, cnt, dry, l, m, init, el, par, par ? sgn64(I) : sgn64(R), rem, emit);
+  if (cnt.dry || dry) *err = 1;
 }
 
 // ---- per-walker sampling (the rules of Sec. II, walker by walker) ----------
