@@ -596,6 +596,16 @@ DQ_HD void field_channels(const SlotParams &P, double S, uint32_t l, uint32_t m,
   }
 }
 
+// small_draw for both parts' walkers (nR, nI) and the four channel
+// probabilities: every count of the entry by inversion.  With every p at most
+// 1/2 (the usual case) the largest n p decides it, in three instructions.
+DQ_HD bool all_small(int64_t nR, int64_t nI, double p0, double p1, double p2, double p3) {
+  const double pm = __builtin_fmax(__builtin_fmax(p0, p1), __builtin_fmax(p2, p3));
+  if (pm <= 0.5) return (double)(nR > nI ? nR : nI) * pm < 10.0;
+  return small_draw(nR, p0) && small_draw(nI, p0) && small_draw(nR, p1) && small_draw(nI, p1) &&
+         small_draw(nR, p2) && small_draw(nI, p2) && small_draw(nR, p3) && small_draw(nI, p3);
+}
+
 // The scan's decision for an entry of a solve with the field: quiet when the
 // primary uniform says that none of its eight channels fires (the test
 // channel_counts makes on the same probabilities), else sampled.  With
@@ -617,12 +627,7 @@ DQ_HD int entry_kind_field(const SlotParams &P, double S, uint32_t step, uint32_
     if (n8[k] > 0 && p8[k] >= 1.0) return heavy_ok ? ENTRY_HEAVY : ENTRY_LIGHT;
   Stream prim(P.seed, P.solve, ((uint64_t)l << P.N) | m, step, 0, nullptr);
   if (quiet_test(p8, n8, prim.next()) & 1) return ENTRY_QUIET;
-  if (heavy_ok) {
-    bool small = true;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) small = small && small_draw(nR, p8[k]) && small_draw(nI, p8[k]);
-    if (!small) return ENTRY_HEAVY;
-  }
+  if (heavy_ok && !all_small(nR, nI, p8[0], p8[1], p8[2], p8[3])) return ENTRY_HEAVY;
   return ENTRY_LIGHT;
 }
 
@@ -867,10 +872,7 @@ DQ_HD bool entry_events_field_impl(const SlotParams &P, double S, uint32_t step,
   int dry = 0;
   int64_t X0 = 0, X1 = 0, X2 = 0, X3 = 0, X4 = 0, X5 = 0, X6 = 0, X7 = 0;
   if constexpr (SMALL) {
-    if (!small_draw(nR, p_r) || !small_draw(nI, p_r) || !small_draw(nR, p_i) ||
-        !small_draw(nI, p_i) || !small_draw(nR, P_re) || !small_draw(nI, P_re) ||
-        !small_draw(nR, P_im) || !small_draw(nI, P_im))
-      return false;
+    if (!all_small(nR, nI, p_r, p_i, P_re, P_im)) return false;
     // successive primary uniforms locate the channels with events (as
     // event_channels), each count then drawn from its own stream
     const double pk[4] = {p_r, p_i, P_re, P_im};
