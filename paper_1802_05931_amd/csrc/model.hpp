@@ -1172,9 +1172,7 @@ DQ_HD bool entry_events_small(const SlotParams &P, double S, uint32_t step, uint
   const EntryProbs e = entry_probs(P, S, step, l, m, R, I);
   const double pk[4] = {e.p8[0], e.p8[1], e.p8[2], e.p8[3]};
   const int64_t nR = e.n8[0], nI = e.n8[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-    if (!small_draw(nR, pk[k]) || !small_draw(nI, pk[k])) return false;
+  if (!all_small(nR, nI, pk[0], pk[1], pk[2], pk[3])) return false;
   // successive primary uniforms locate the channels with events
   Stream prim(e.cnt.seed, e.cnt.solve, e.cnt.cfg, e.cnt.step, 0, nullptr);
   int64_t X0 = 0, X1 = 0, X2 = 0, X3 = 0, X4 = 0, X5 = 0, X6 = 0, X7 = 0;
