@@ -521,139 +521,17 @@ DQ_HD void entry_events(const SlotParams &P, double S, uint32_t step, uint32_t l
 // one), bra, bra to the diagonal, members by ascending site, with the hop
 // classes' importance-sampling weights.  The real part's classes follow the
 // jump class; the imaginary part's follow the six hop classes.
-constexpr int FIELD_CLASSES_MAX = 10;
-
-struct FieldParts {
-  int ncls[2];                        // classes of the Re (0) and Im (1) element parts
-  int n[2][FIELD_CLASSES_MAX];
-  double W[2][FIELD_CLASSES_MAX];     // n_c |element part| w_child / w_parent
-  double Sc[2][FIELD_CLASSES_MAX + 1];  // suffix sums of W, Sc[ncls] = 0
-  uint32_t fmask[4];                  // site masks of the field classes
-};
-
 // the draw id, within a channel, of the class split of class c
 DQ_HD uint32_t class_split_draw(int c) { return c < 6 ? 1u + (uint32_t)c : 16u + (uint32_t)c; }
-
-DQ_HD void field_parts(const SlotParams &P, const HopClasses &hc, uint32_t l, uint32_t m,
-                       FieldParts &f) {
-  const bool diag = (l == m);
-  const uint32_t d = l ^ m;
-  const uint32_t tbit = popc(d) == 1 ? d : 0u;
-  const uint32_t all = P.N == 32 ? 0xffffffffu : ((1u << P.N) - 1u);
-  f.fmask[0] = all & ~tbit;
-  f.fmask[1] = tbit;
-  f.fmask[2] = all & ~tbit;
-  f.fmask[3] = tbit;
-  // Re part: the jumps, then the field classes
-  f.ncls[0] = 5;
-  f.n[0][0] = popc(l & m);
-  f.W[0][0] = (double)f.n[0][0] * P.gamma;
-  // Im part: the six hop classes, then the field classes
-  f.ncls[1] = 10;
-  for (int c = 0; c < 6; ++c) {
-    f.n[1][c] = hc.n[c];
-    f.W[1][c] = hc.W[c];
-  }
-  for (int k = 0; k < 4; ++k) {
-    const bool to_diag = (k & 1) != 0;
-    const double w = diag ? P.w_dn : (to_diag ? P.w_up : 1.0);
-    const int n = popc(f.fmask[k]);
-    f.n[0][1 + k] = n;
-    f.W[0][1 + k] = ((double)n * P.ahy) * w;
-    f.n[1][6 + k] = n;
-    f.W[1][6 + k] = ((double)n * P.ahx) * w;
-  }
-  for (int part = 0; part < 2; ++part) {
-    const int nc = f.ncls[part];
-    f.Sc[part][nc] = 0.0;
-    f.Sc[part][nc - 1] = f.W[part][nc - 1];
-    for (int c = nc - 2; c >= 0; --c) f.Sc[part][c] = f.W[part][c] + f.Sc[part][c + 1];
-  }
-}
-
-// The eight channel probabilities and walker counts of an entry of a solve
-// with the field (clone/death along the diagonal element; spawning along the
-// Re part: jumps and field flips; along the Im part: hops and field flips),
-// with the diagonal element (d_r, d_i), the hop classes and the field classes.
-DQ_HD void field_channels(const SlotParams &P, double S, uint32_t l, uint32_t m, int64_t nR,
-                          int64_t nI, double &d_r, double &d_i, HopClasses &hc, FieldParts &f,
-                          double p8[8], int64_t n8[8]) {
-  const Geometry g = geometry(P, l, m);
-  d_r = -(P.half_gamma * (double)(popc(l) + popc(m))) - S;
-  d_i = P.half_jz * (double)(g.al[1] - g.al[0]);
-  const double p_r = P.dt * __builtin_fabs(d_r);
-  const double p_i = P.dt * __builtin_fabs(d_i);
-  hc = hop_classes(P, g, l, m);
-  field_parts(P, hc, l, m, f);
-  const double P_re = P.dt * f.Sc[0][0];
-  const double P_im = P.dt * f.Sc[1][0];
-  const double pp[4] = {p_r, p_i, P_re, P_im};
-  for (int k = 0; k < 4; ++k) {
-    p8[k] = pp[k];
-    p8[k + 4] = pp[k];
-    n8[k] = nR;
-    n8[k + 4] = nI;
-  }
-}
-
-// small_draw for both parts' walkers (nR, nI) and the four channel
-// probabilities: every count of the entry by inversion.  With every p at most
-// 1/2 (the usual case) the largest n p decides it, in three instructions.
-DQ_HD bool all_small(int64_t nR, int64_t nI, double p0, double p1, double p2, double p3) {
-  const double pm = __builtin_fmax(__builtin_fmax(p0, p1), __builtin_fmax(p2, p3));
-  if (pm <= 0.5) return (double)(nR > nI ? nR : nI) * pm < 10.0;
-  return small_draw(nR, p0) && small_draw(nI, p0) && small_draw(nR, p1) && small_draw(nI, p1) &&
-         small_draw(nR, p2) && small_draw(nI, p2) && small_draw(nR, p3) && small_draw(nI, p3);
-}
-
-// The scan's decision for an entry of a solve with the field: quiet when the
-// primary uniform says that none of its eight channels fires (the test
-// channel_counts makes on the same probabilities), else sampled.  With
-// heavy_ok, a sampled entry whose channel probabilities are not all small for
-// both parts' walkers (entry_events_field_small would refuse it) is
-// ENTRY_HEAVY.
-DQ_HD int entry_kind_field(const SlotParams &P, double S, uint32_t step, uint32_t l, uint32_t m,
-                           int32_t R, int32_t I, bool heavy_ok = false) {
-  const int64_t nR = R < 0 ? -(int64_t)R : (int64_t)R;
-  const int64_t nI = I < 0 ? -(int64_t)I : (int64_t)I;
-  double d_r, d_i, p8[8];
-  int64_t n8[8];
-  HopClasses hc;
-  FieldParts f;
-  field_channels(P, S, l, m, nR, nI, d_r, d_i, hc, f, p8, n8);
-  // (a probability of 1 or more is not small)
-#pragma unroll
-  for (int k = 0; k < 8; ++k)
-    if (n8[k] > 0 && p8[k] >= 1.0) return heavy_ok ? ENTRY_HEAVY : ENTRY_LIGHT;
-  Stream prim(P.seed, P.solve, ((uint64_t)l << P.N) | m, step, 0, nullptr);
-  if (quiet_test(p8, n8, prim.next()) & 1) return ENTRY_QUIET;
-  if (heavy_ok && !all_small(nR, nI, p8[0], p8[1], p8[2], p8[3])) return ENTRY_HEAVY;
-  return ENTRY_LIGHT;
-}
-
-// Element c of ten values held in registers (a select chain on values).
-template <typename T>
-DQ_HD T sel10(int c, T a0, T a1, T a2, T a3, T a4, T a5, T a6, T a7, T a8, T a9) {
-  T v = a0;
-  v = c == 1 ? a1 : v;
-  v = c == 2 ? a2 : v;
-  v = c == 3 ? a3 : v;
-  v = c == 4 ? a4 : v;
-  v = c == 5 ? a5 : v;
-  v = c == 6 ? a6 : v;
-  v = c == 7 ? a7 : v;
-  v = c == 8 ? a8 : v;
-  v = c == 9 ? a9 : v;
-  return v;
-}
 
 // The geometry and class weights of an entry |l><m| of a solve with the
 // field, as values (a struct of scalars, no arrays, so that they stay in
 // registers): aligned bonds, the bond l ^ m if it is one, the hop classes
 // (0 ket-aligned, 1 ket-anti, 2 ket to-diagonal, 3-5 the bra's) and the field
 // classes (flips of the sites where l and m agree, A, and of the one where
-// they differ if only one, B).  The same expressions as geometry /
-// hop_classes / field_parts.
+// they differ if only one, B; each element part's four field classes are ket
+// A, ket B, bra A, bra B, with the hop classes' importance-sampling weights).
+// The hop classes' expressions are hop_classes'.
 struct FieldGeom {
   uint32_t r0, u0, r1, u1, r3, u3, r4, u4, Tr, Tu;  // hop classes' bond origins
   int hn0, hn1, hn2, hn3, hn4;                       // their members (class 5 as 2)
@@ -710,6 +588,70 @@ DQ_HD FieldGeom field_geom(const SlotParams &P, double S, uint32_t l, uint32_t m
   g.nJ = popc(g.jm);
   g.WJ = (double)g.nJ * P.gamma;
   return g;
+}
+
+// The four channel probabilities of an entry of a solve with the field
+// (dt |d_r| and dt |d_i| along the diagonal element, dt x the total weight of
+// the real and of the imaginary element part's classes, each total the
+// classes' suffix sum from the last class down), for both parts' walkers.
+struct FieldProbs {
+  double p_r, p_i, P_re, P_im;
+};
+DQ_HD FieldProbs field_probs(const SlotParams &P, const FieldGeom &g) {
+  const double S0re = g.WJ + (g.WyA + (g.WyB + (g.WyA + g.WyB)));
+  const double S0im =
+      g.Wh0 + (g.Wh1 + (g.Wh2 + (g.Wh3 + (g.Wh4 + (g.Wh5 + (g.WxA + (g.WxB + (g.WxA + g.WxB))))))));
+  return FieldProbs{P.dt * __builtin_fabs(g.d_r), P.dt * __builtin_fabs(g.d_i), P.dt * S0re,
+                    P.dt * S0im};
+}
+
+// small_draw for both parts' walkers (nR, nI) and the four channel
+// probabilities: every count of the entry by inversion.  With every p at most
+// 1/2 (the usual case) the largest n p decides it, in three instructions.
+DQ_HD bool all_small(int64_t nR, int64_t nI, double p0, double p1, double p2, double p3) {
+  const double pm = __builtin_fmax(__builtin_fmax(p0, p1), __builtin_fmax(p2, p3));
+  if (pm <= 0.5) return (double)(nR > nI ? nR : nI) * pm < 10.0;
+  return small_draw(nR, p0) && small_draw(nI, p0) && small_draw(nR, p1) && small_draw(nI, p1) &&
+         small_draw(nR, p2) && small_draw(nI, p2) && small_draw(nR, p3) && small_draw(nI, p3);
+}
+
+// The scan's decision for an entry of a solve with the field: quiet when the
+// primary uniform says that none of its eight channels fires (the test
+// channel_counts makes on the same probabilities), else sampled.  With
+// heavy_ok, a sampled entry whose channel probabilities are not all small for
+// both parts' walkers (entry_events_field_small would refuse it) is
+// ENTRY_HEAVY.
+DQ_HD int entry_kind_field(const SlotParams &P, double S, uint32_t step, uint32_t l, uint32_t m,
+                           int32_t R, int32_t I, bool heavy_ok = false) {
+  const int64_t nR = R < 0 ? -(int64_t)R : (int64_t)R;
+  const int64_t nI = I < 0 ? -(int64_t)I : (int64_t)I;
+  const FieldProbs fp = field_probs(P, field_geom(P, S, l, m));
+  const double p8[8] = {fp.p_r, fp.p_i, fp.P_re, fp.P_im, fp.p_r, fp.p_i, fp.P_re, fp.P_im};
+  const int64_t n8[8] = {nR, nR, nR, nR, nI, nI, nI, nI};
+  // (a probability of 1 or more is not small)
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (n8[k] > 0 && p8[k] >= 1.0) return heavy_ok ? ENTRY_HEAVY : ENTRY_LIGHT;
+  Stream prim(P.seed, P.solve, ((uint64_t)l << P.N) | m, step, 0, nullptr);
+  if (quiet_test(p8, n8, prim.next()) & 1) return ENTRY_QUIET;
+  if (heavy_ok && !all_small(nR, nI, p8[0], p8[1], p8[2], p8[3])) return ENTRY_HEAVY;
+  return ENTRY_LIGHT;
+}
+
+// Element c of ten values held in registers (a select chain on values).
+template <typename T>
+DQ_HD T sel10(int c, T a0, T a1, T a2, T a3, T a4, T a5, T a6, T a7, T a8, T a9) {
+  T v = a0;
+  v = c == 1 ? a1 : v;
+  v = c == 2 ? a2 : v;
+  v = c == 3 ? a3 : v;
+  v = c == 4 ? a4 : v;
+  v = c == 5 ? a5 : v;
+  v = c == 6 ? a6 : v;
+  v = c == 7 ? a7 : v;
+  v = c == 8 ? a8 : v;
+  v = c == 9 ? a9 : v;
+  return v;
 }
 
 // The walkers one parent part (par: 0 real, 1 imaginary, sign sg) sends along
@@ -841,8 +783,8 @@ DQ_HD void field_part(const SlotParams &P, const FieldGeom &g, EntryCounter &cnt
 
 // entry_events with the field on (the slot's P.field): the same clone/death,
 // the real element part's jumps and field flips, the imaginary part's hops
-// and field flips (field_part).  The same probabilities, draws and records as
-// field_channels / field_parts would give.
+// and field flips (field_part), on the probabilities the scan's quiet test
+// used (field_probs).
 // SMALL: every draw by inversion (binomial_small, the same values), with no
 // out-of-line call, for entries whose channel probabilities are all small for
 // both parts' walkers and whose spawn counts stay below 20 (so that every
@@ -860,14 +802,8 @@ DQ_HD bool entry_events_field_impl(const SlotParams &P, double S, uint32_t step,
   const int64_t sR = sgn64(R), sI = sgn64(I);
   const bool init = diag || (nR + nI > P.n_a) || (P.flags & FLAG_NO_INITIATOR);
   const FieldGeom g = field_geom(P, S, l, m);
-  // each part's total weight (the suffix sums from the last class down)
-  const double S0re = g.WJ + (g.WyA + (g.WyB + (g.WyA + g.WyB)));
-  const double S0im =
-      g.Wh0 + (g.Wh1 + (g.Wh2 + (g.Wh3 + (g.Wh4 + (g.Wh5 + (g.WxA + (g.WxB + (g.WxA + g.WxB))))))));
-  const double p_r = P.dt * __builtin_fabs(g.d_r);
-  const double p_i = P.dt * __builtin_fabs(g.d_i);
-  const double P_re = P.dt * S0re;
-  const double P_im = P.dt * S0im;
+  const FieldProbs fp = field_probs(P, g);
+  const double p_r = fp.p_r, p_i = fp.p_i, P_re = fp.P_re, P_im = fp.P_im;
   EntryCounter cnt{P.seed, ((uint64_t)l << P.N) | m, P.solve, step, 0};
   int dry = 0;
   int64_t X0 = 0, X1 = 0, X2 = 0, X3 = 0, X4 = 0, X5 = 0, X6 = 0, X7 = 0;
