@@ -282,6 +282,14 @@ int ddqmc_set_heavy_fork(ddqmc_t *h, int32_t mode);
  * kernel holds, 1024 with 32-bit keys and 768 with 64-bit keys.  EINVAL
  * below 0 or above that. */
 int ddqmc_set_tree_queue(ddqmc_t *h, int32_t places);
+/* With the in-plane field in every solve of a handle, the entries whose
+ * draws are all small are sampled by a routine that draws by inversion
+ * only; an entry with `spawns` or more walkers spawned along one element part
+ * by one part of its walkers is passed on to the general routine, and the
+ * results are the same either way.  Default and most 20 (the inversion
+ * sampler then covers every split); smaller values are for tests of the
+ * passing on.  EINVAL outside 1..20. */
+int ddqmc_set_field_limit(ddqmc_t *h, int32_t spawns);
 /* Grid of the loud spawn kernel.  0 (default): chosen per chunk of steps from
  * the last step's counts (one block per 256-entry chunk while the list of
  * large-population entries is small beside the loud list, resident blocks

@@ -131,6 +131,12 @@ class _Handle:
         whose trees find no room take the general path, with the same results."""
         check(lib().ddqmc_set_tree_queue(self._h, int(places)), "set_tree_queue")
 
+    def set_field_limit(self, spawns):
+        """With the field in every solve: entries with this many walkers spawned
+        along one element part by one part of their walkers (1..20, default 20)
+        go to the general routine; the results are the same either way."""
+        check(lib().ddqmc_set_field_limit(self._h, int(spawns)), "set_field_limit")
+
     def set_loud_grid(self, mode):
         """Loud kernel grid: 0 chosen per chunk of steps, 1 resident blocks, 2 a block
         per chunk of entries (same results either way)."""

@@ -114,6 +114,7 @@ SIGNATURES = {
     "ddqmc_set_graph_steps": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "ddqmc_set_heavy_fork": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "ddqmc_set_tree_queue": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "ddqmc_set_field_limit": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "ddqmc_set_loud_grid": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "ddqmc_stage_times": (ctypes.c_int, [_vp, _P(ctypes.c_double), _P(ctypes.c_int64)]),
     "ddqmc_set_tiles": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),

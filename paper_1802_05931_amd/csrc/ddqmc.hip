@@ -120,6 +120,7 @@ struct ddqmc_t {
                             // the heavy kernel saves on a short step
   int fork_mode = 0;        // 0 by list capacity, 1 always, -1 never
   uint32_t tree_cap = 0;    // member-tree places per loud chunk (0: all the kernel holds)
+  int field_limit = 20;     // spawns in one part that send a field entry to the general routine
   bool loud_dyn = false;    // loud kernel: resident blocks and a chunk counter (else a
                             // block per chunk); chosen per chunk of steps, see run_steps
   int loud_grid = 0;        // 0 chosen per chunk of steps, 1 resident, 2 block per chunk
@@ -580,19 +581,19 @@ int launch_step(ddqmc_t *h, int par, StageEvents *ev, hipStream_t s) {
       // leaving the rest of the CUs to the call-free routine)
       k_spawn_listed<K, false><<<clampu(h->ncu / 2, 1, 4096), NT, 0, hs>>>(
           c, h->dsp, h->dss, ak, av, h->heavy, &c->n_heavy, nullptr, (K *)h->sk[0], h->sv[0],
-          h->segcnt, segcap, h->SB);
+          h->segcnt, segcap, h->SB, 0);
       if (h->fork_heavy) HIPC(hipEventRecord(h->ev_join, h->side));
       k_spawn_listed<K, true><<<h->general_blocks, NT, 0, s>>>(
           c, h->dsp, h->dss, (const K *)h->lkey, h->lval, nullptr, &c->n_loud, h->late,
-          (K *)h->sk[0], h->sv[0], h->segcnt, segcap, h->SB);
+          (K *)h->sk[0], h->sv[0], h->segcnt, segcap, h->SB, h->field_limit);
       k_spawn_listed<K, false><<<h->general_blocks, NT, 0, s>>>(
           c, h->dsp, h->dss, (const K *)h->lkey, h->lval, h->late, &c->n_late, nullptr,
-          (K *)h->sk[0], h->sv[0], h->segcnt, segcap, h->SB);
+          (K *)h->sk[0], h->sv[0], h->segcnt, segcap, h->SB, 0);
       if (h->fork_heavy) HIPC(hipStreamWaitEvent(s, h->ev_join, 0));
     } else {
       k_spawn_listed<K, false><<<h->general_blocks, NT, 0, s>>>(
           c, h->dsp, h->dss, (const K *)h->lkey, h->lval, nullptr, &c->n_loud, nullptr,
-          (K *)h->sk[0], h->sv[0], h->segcnt, segcap, h->SB);
+          (K *)h->sk[0], h->sv[0], h->segcnt, segcap, h->SB, 0);
     }
     if (ev) HIPC(hipEventRecord(ev->e[3], s));
     if (ev) HIPC(hipEventRecord(ev->e[4], s));
@@ -1527,6 +1528,13 @@ int ddqmc_set_tree_queue(ddqmc_t *h, int32_t places) {
   const uint32_t most = h->k64 ? tree_jobs<uint64_t>() : tree_jobs<uint32_t>();
   if ((uint32_t)places > most) return DDQMC_EINVAL;
   h->tree_cap = (uint32_t)places;
+  h->buf_gen += 1;  // captured graphs hold the old kernel argument
+  return DDQMC_OK;
+}
+
+int ddqmc_set_field_limit(ddqmc_t *h, int32_t spawns) {
+  if (!h || spawns < 1 || spawns > 20) return DDQMC_EINVAL;
+  h->field_limit = spawns;
   h->buf_gen += 1;  // captured graphs hold the old kernel argument
   return DDQMC_OK;
 }

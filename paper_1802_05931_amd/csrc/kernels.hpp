@@ -763,8 +763,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MINW))) void
 // of them, entry q = idx ? idx[q] : q of (skey, sval).  FIELD_ONLY (every
 // solve of the handle has the field): the call-free routine, which takes the
 // entries whose draws are all small, the others' indices in (skey, sval) to
-// the late list (late, ctrl->n_late); else entry_events_field for the solves
-// with the field and entry_events for the others.  Records are staged in LDS
+// the late list (late, ctrl->n_late), and so do those with limit or more
+// spawns in one part; else entry_events_field for the solves with the field
+// and entry_events for the others.  Records are staged in LDS
 // per block iteration and flushed into the block's segment.
 template <typename K, bool FIELD_ONLY>
 __global__ __launch_bounds__(NT, 2) void k_spawn_listed(Ctrl *ctrl,
@@ -777,7 +778,7 @@ __global__ __launch_bounds__(NT, 2) void k_spawn_listed(Ctrl *ctrl,
                                                      uint32_t *__restrict__ late,
                                                      K *__restrict__ ok, int2 *__restrict__ ov,
                                                      unsigned long long *segcnt, uint32_t segcap,
-                                                     int SB) {
+                                                     int SB, int limit) {
   if (ctrl->abort) return;
   __shared__ K sk[STAGE];
   __shared__ int2 sv[STAGE];
@@ -837,7 +838,8 @@ __global__ __launch_bounds__(NT, 2) void k_spawn_listed(Ctrl *ctrl,
         return true;
       };
       if constexpr (FIELD_ONLY) {
-        if (!entry_events_field_small(P, ss[slot].S, step, l, m, v.x, v.y, &rng_err, rec, queue))
+        if (!entry_events_field_small(P, ss[slot].S, step, l, m, v.x, v.y, &rng_err, rec, queue,
+                                      (int64_t)limit))
           late[atomicAdd(&ctrl->n_late, 1u)] = q;
       } else {
         if (P.field)

@@ -787,15 +787,16 @@ DQ_HD void field_part(const SlotParams &P, const FieldGeom &g, EntryCounter &cnt
 // used (field_probs).
 // SMALL: every draw by inversion (binomial_small, the same values), with no
 // out-of-line call, for entries whose channel probabilities are all small for
-// both parts' walkers and whose spawn counts stay below 20 (so that every
-// class and tree split is small too); false, before anything is emitted, for
-// an entry that is not such (the caller hands it to the general routine).
+// both parts' walkers and whose spawn counts stay below limit (at most 20, so
+// that every class and tree split is small too); false, before anything is
+// emitted, for an entry that is not such (the caller hands it to the general
+// routine).
 // A part with two or more walkers may be handed to queue(el, par, rem),
 // which returns true when it takes it (field_part_job samples it later).
 template <bool SMALL, typename Emit, typename Queue>
 DQ_HD bool entry_events_field_impl(const SlotParams &P, double S, uint32_t step, uint32_t l,
                                    uint32_t m, int32_t R, int32_t I, int *err, Emit &&emit,
-                                   Queue &&queue) {
+                                   Queue &&queue, int64_t limit = 20) {
   const bool diag = (l == m);
   const int64_t nR = R < 0 ? -(int64_t)R : (int64_t)R;
   const int64_t nI = I < 0 ? -(int64_t)I : (int64_t)I;
@@ -852,7 +853,7 @@ DQ_HD bool entry_events_field_impl(const SlotParams &P, double S, uint32_t step,
       X7 = first == 7 ? x : X7;
       start = first + 1;
     }
-    if (X2 >= 20 || X3 >= 20 || X6 >= 20 || X7 >= 20) return false;
+    if (X2 >= limit || X3 >= limit || X6 >= limit || X7 >= limit) return false;
   } else {
     const double p8[8] = {p_r, p_i, P_re, P_im, p_r, p_i, P_re, P_im};
     const int64_t n8[8] = {nR, nR, nR, nR, nI, nI, nI, nI};
@@ -888,13 +889,14 @@ DQ_HD void entry_events_field(const SlotParams &P, double S, uint32_t step, uint
   entry_events_field(P, S, step, l, m, R, I, err, emit, [](int, int, int64_t) { return false; });
 }
 
-// entry_events_field for an entry whose draws are all small (see above);
-// false, with nothing emitted, for any other.  queue as above.
+// entry_events_field for an entry whose draws are all small and whose spawn
+// counts stay below limit (see above); false, with nothing emitted, for any
+// other.  queue as above.
 template <typename Emit, typename Queue>
 DQ_HD bool entry_events_field_small(const SlotParams &P, double S, uint32_t step, uint32_t l,
                                     uint32_t m, int32_t R, int32_t I, int *err, Emit &&emit,
-                                    Queue &&queue) {
-  return entry_events_field_impl<true>(P, S, step, l, m, R, I, err, emit, queue);
+                                    Queue &&queue, int64_t limit) {
+  return entry_events_field_impl<true>(P, S, step, l, m, R, I, err, emit, queue, limit);
 }
 
 // A part that entry_events_field_impl<SMALL> queued: rem walkers of parent

@@ -164,3 +164,26 @@ def test_field_heavy_entries_beside_the_rest(dq, orc, fork):
             assert _same_list(b.walkers(i), o.get_list()), i
             assert b.scalars(i) == o.scalars(), i
     b.close()
+
+
+@pytest.mark.parametrize("limit", [1, 2, 5])
+def test_field_entries_passed_on(dq, orc, limit):
+    """The call-free routine passes an entry with `limit` or more walkers
+    spawned along one element part by one part of its walkers to the general
+    routine (ddqmc_set_field_limit; 20 in production): at 1, every entry with
+    a spawn takes that way, at 2 and 5 many.  The oracle's lists either way,
+    the passed-on entries counted in the step counts."""
+    cfg = dict(workloads.d2(0.6), target_walkers=20000, n_equil=100, hx=0.1, hy=-0.07)
+    g = dq.Solve(dq.make_params(**cfg))
+    g.set_field_limit(limit)
+    o = orc.Oracle(**cfg)
+    for _ in range(2):
+        g.step(200)
+        o.step(200)
+        assert _same_list(g.walkers(), o.get_list())
+        assert g.scalars() == o.scalars()
+    assert g.step_counts()[:, 4].sum() > 0
+    for bad in (0, 21):
+        with pytest.raises(dq.DDQMCError):
+            g.set_field_limit(bad)
+    g.close()
