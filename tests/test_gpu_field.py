@@ -143,19 +143,23 @@ def test_pool_admits_a_field_solve(dq, orc):
     pool.close()
 
 
-@pytest.mark.parametrize("fork", [1, -1], ids=["beside", "after"])
-def test_field_heavy_entries_beside_the_rest(dq, orc, fork):
+@pytest.mark.parametrize("fork,graph_k", [(1, 0), (-1, 0), (1, 10)],
+                         ids=["beside", "after", "beside_in_graphs"])
+def test_field_heavy_entries_beside_the_rest(dq, orc, fork, graph_k):
     """Every solve with the field: the entries whose draws are not all small
     go to the scan's heavy list and the general routine, on the second stream
-    beside the call-free routine over the rest (fork 1) or after it (-1); the
-    call-free routine passes on entries with 20 or more spawns.  A batch of
-    two field solves with large populations against the oracle."""
+    beside the call-free routine over the rest (fork 1, also inside 10-step
+    HIP graphs) or after it (-1); the call-free routine passes on entries with
+    20 or more spawns.  A batch of two field solves with large populations
+    against the oracle."""
     cfgs = [dict(workloads.D1, solve_id=5, n_equil=100, hx=0.15, target_walkers=20000,
                  initial_walkers=20000),
             dict(workloads.d2(0.6), solve_id=6, target_walkers=50000, initial_walkers=50000,
                  n_equil=100, hy=0.1)]
     b = dq.Batch([dq.make_params(**c) for c in cfgs])
     b.set_heavy_fork(fork)
+    if graph_k:
+        b.set_graph_steps(graph_k)
     orcs = [orc.Oracle(**c) for c in cfgs]
     for _ in range(3):
         b.step(100)
