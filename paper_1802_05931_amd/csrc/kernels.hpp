@@ -1605,7 +1605,13 @@ __global__ __launch_bounds__(NT, sizeof(K) == 4 ? (MERGE_IT == 4 ? 8 : 5) : (MER
 }
 
 // Output offsets of the merge tiles, in place: cnt[t] <- survivors of tiles
-// < t; the new list size goes to ctrl->n_new.  One block of 1024 threads.
+// < t; the new list size goes to ctrl->n_new.  One block of 1024 threads, in
+// rounds of 1024 OFF_C tiles: wave w takes 64 OFF_C consecutive tiles,
+// loaded 64 at a time (coalesced), the waves' totals give each wave its
+// offset, then each group of 64 is scanned across the lanes.  (A thread per
+// run of consecutive tiles read its tiles 64 lanes apart: 74 us for the
+// 42,500 tiles of a 7.7e7-entry list.)
+constexpr int OFF_C = 16;
 __global__ __launch_bounds__(1024) void k_merge_offsets(Ctrl *ctrl, uint32_t *cnt,
                                                        uint32_t merge_tile) {
   if (ctrl->abort || (ctrl->flags & F_SPAWN_CAP)) return;
@@ -1613,23 +1619,38 @@ __global__ __launch_bounds__(1024) void k_merge_offsets(Ctrl *ctrl, uint32_t *cn
   const uint32_t total = ctrl->n_main + ctrl->n_spawn;
   const uint32_t n = (total + merge_tile - 1) / merge_tile;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const uint32_t per = (n + 1023) / 1024;
-  const uint32_t b0 = tid * per < n ? tid * per : n;
-  const uint32_t b1 = (b0 + per < n) ? b0 + per : n;
-  uint32_t local = 0;
-  for (uint32_t b = b0; b < b1; ++b) local += cnt[b];
-  const uint32_t inc = wave_incl_scan(local);
-  if (lane == 63) wsum[w] = inc;
-  __syncthreads();
-  uint32_t before = 0;
-  for (int i = 0; i < w; ++i) before += wsum[i];
-  uint32_t run = before + inc - local;
-  for (uint32_t b = b0; b < b1; ++b) {
-    const uint32_t c = cnt[b];
-    cnt[b] = run;
-    run += c;
+  uint32_t carry = 0;  // survivors of the earlier rounds (the same in every thread)
+  for (uint32_t r0 = 0; r0 < n; r0 += 1024u * OFF_C) {
+    const uint32_t wb = r0 + (uint32_t)w * 64u * OFF_C;
+    uint32_t v[OFF_C];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < OFF_C; ++k) {
+      const uint32_t b = wb + (uint32_t)k * 64u + (uint32_t)lane;
+      v[k] = b < n ? cnt[b] : 0u;
+      sum += v[k];
+    }
+    const uint32_t wt = wave_sum(sum);
+    if (lane == 0) wsum[w] = wt;
+    __syncthreads();
+    uint32_t off = carry, rt = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const uint32_t x = wsum[i];
+      off += i < w ? x : 0u;
+      rt += x;
+    }
+    __syncthreads();  // (wsum is written again in the next round)
+#pragma unroll
+    for (int k = 0; k < OFF_C; ++k) {
+      const uint32_t inc = wave_incl_scan(v[k]);
+      const uint32_t b = wb + (uint32_t)k * 64u + (uint32_t)lane;
+      if (b < n) cnt[b] = off + inc - v[k];
+      off += __shfl(inc, 63, 64);
+    }
+    carry += rt;
   }
-  if (tid == 1023) ctrl->n_new = before + inc;
+  if (tid == 0) ctrl->n_new = carry;
 }
 
 // ---- finalize (one block) ---------------------------------------------------
