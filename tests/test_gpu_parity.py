@@ -474,7 +474,9 @@ def test_full_size_4x4_window(dq, orc):
     (about 1.07e7 entries after some 14,500 steps, as the benchmark times it),
     at which size the list capacity is above 2^23 entries, so the large-entry
     kernel runs on the second stream beside the loud kernel, as in the timed
-    steps; then two steps from that snapshot are checked against the oracle."""
+    steps; then two steps from that snapshot are checked against the oracle,
+    and a third with merge tiles of 1024 positions (more than 8192 tiles: the
+    merge offsets' coalesced round scan)."""
     cfg = dict(workloads.D3)
     g = dq.Solve(dq.make_params(**cfg))
     g.step(15000)
@@ -496,6 +498,12 @@ def test_full_size_4x4_window(dq, orc):
         assert _same_list(g.walkers(), o.get_list())
         assert g.scalars() == o.scalars()
         print(f"  4x4 window step {i + 1} bit-identical", flush=True)
+    g.set_tiles(8, 4)
+    g.step(1)
+    o.step(1)
+    assert _same_list(g.walkers(), o.get_list())
+    assert g.scalars() == o.scalars()
+    assert sum(g.step_counts()[-1][:2]) > 8192 * 1024
     g.close()
 
 
