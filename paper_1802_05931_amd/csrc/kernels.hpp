@@ -131,6 +131,78 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Exclusive prefix of row[0, n) in place by a block of NTB threads (all of
+// them call it; wsum holds NTB / 64 words of LDS); returns the total, in every
+// thread.  Up to 8 NTB values each thread takes a run of at most eight
+// consecutive values (one wave scan).  Beyond, in rounds of 16 NTB values,
+// wave w takes 16 x 64 consecutive values, loaded 64 at a time (coalesced),
+// the waves' totals give each wave its offset, then each group of 64 is
+// scanned across the lanes: runs of consecutive values per thread would be
+// read 64 lanes apart (a 42,500-value prefix took 74 us that way).
+template <int NTB>
+__device__ uint32_t block_prefix_inplace(uint32_t *row, uint32_t n, uint32_t *wsum) {
+  constexpr int NW = NTB / 64;
+  constexpr int C = 16;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (n <= 8u * NTB) {
+    const uint32_t per = (n + NTB - 1) / NTB;
+    const uint32_t b0 = tid * per < n ? tid * per : n;
+    const uint32_t b1 = (b0 + per < n) ? b0 + per : n;
+    uint32_t local = 0;
+    for (uint32_t b = b0; b < b1; ++b) local += row[b];
+    const uint32_t inc = wave_incl_scan(local);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      const uint32_t x = wsum[i];
+      before += i < w ? x : 0u;
+      all += x;
+    }
+    uint32_t run = before + inc - local;
+    for (uint32_t b = b0; b < b1; ++b) {
+      const uint32_t c = row[b];
+      row[b] = run;
+      run += c;
+    }
+    __syncthreads();
+    return all;
+  }
+  uint32_t carry = 0;  // the earlier rounds' total (the same in every thread)
+  for (uint32_t r0 = 0; r0 < n; r0 += (uint32_t)NTB * C) {
+    const uint32_t wb = r0 + (uint32_t)w * 64u * C;
+    uint32_t v[C];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      const uint32_t b = wb + (uint32_t)k * 64u + (uint32_t)lane;
+      v[k] = b < n ? row[b] : 0u;
+      sum += v[k];
+    }
+    const uint32_t wt = wave_sum(sum);
+    if (lane == 0) wsum[w] = wt;
+    __syncthreads();
+    uint32_t off = carry, rt = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      const uint32_t x = wsum[i];
+      off += i < w ? x : 0u;
+      rt += x;
+    }
+    __syncthreads();  // (wsum is written again in the next round)
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      const uint32_t inc = wave_incl_scan(v[k]);
+      const uint32_t b = wb + (uint32_t)k * 64u + (uint32_t)lane;
+      if (b < n) row[b] = off + inc - v[k];
+      off += __shfl(inc, 63, 64);
+    }
+    carry += rt;
+  }
+  return carry;
+}
+
 template <typename K>
 __device__ __forceinline__ uint32_t lower_bound(const K *a, uint32_t n, K key) {
   uint32_t lo = 0, hi = n;
@@ -1151,18 +1223,7 @@ __global__ __launch_bounds__(NT) void k_sort_rowscan(Ctrl *ctrl, uint32_t *cnt, 
   }
   __shared__ uint32_t scan4[NT / 64];
   uint32_t *row = cnt + (size_t)blockIdx.x * ntiles;
-  const uint32_t per = (ntiles + NT - 1) / NT;
-  const uint32_t c0 = threadIdx.x * per < ntiles ? threadIdx.x * per : ntiles;
-  const uint32_t c1 = c0 + per < ntiles ? c0 + per : ntiles;
-  uint32_t local = 0;
-  for (uint32_t c = c0; c < c1; ++c) local += row[c];
-  uint32_t tot;
-  uint32_t run = block_excl_scan(local, scan4, &tot);
-  for (uint32_t c = c0; c < c1; ++c) {
-    const uint32_t v = row[c];
-    row[c] = run;
-    run += v;
-  }
+  const uint32_t tot = block_prefix_inplace<NT>(row, ntiles, scan4);
   if (threadIdx.x == 0) hist[pass * 256 + blockIdx.x] = tot;
 }
 
@@ -1605,75 +1666,15 @@ __global__ __launch_bounds__(NT, sizeof(K) == 4 ? (MERGE_IT == 4 ? 8 : 5) : (MER
 }
 
 // Output offsets of the merge tiles, in place: cnt[t] <- survivors of tiles
-// < t; the new list size goes to ctrl->n_new.  One block of 1024 threads.  Up
-// to OFF_SMALL tiles a thread takes a run of at most eight consecutive tiles
-// (one wave scan); beyond, in rounds of 1024 OFF_C tiles, wave w takes 64
-// OFF_C consecutive tiles, loaded 64 at a time (coalesced), the waves'
-// totals give each wave its offset, then each group of 64 is scanned across
-// the lanes.  (Runs of consecutive tiles per thread, read 64 lanes apart,
-// took 74 us for the 42,500 tiles of a 7.7e7-entry list; the rounds, 9
-// against 6 us for the 5,900 tiles of a 1.1e7-entry one.)
-constexpr int OFF_C = 16;
-constexpr uint32_t OFF_SMALL = 8 * 1024;
+// < t; the new list size goes to ctrl->n_new.  One block of 1024 threads.
 __global__ __launch_bounds__(1024) void k_merge_offsets(Ctrl *ctrl, uint32_t *cnt,
                                                        uint32_t merge_tile) {
   if (ctrl->abort || (ctrl->flags & F_SPAWN_CAP)) return;
   __shared__ uint32_t wsum[16];
   const uint32_t total = ctrl->n_main + ctrl->n_spawn;
   const uint32_t n = (total + merge_tile - 1) / merge_tile;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  if (n <= OFF_SMALL) {
-    const uint32_t per = (n + 1023) / 1024;
-    const uint32_t b0 = tid * per < n ? tid * per : n;
-    const uint32_t b1 = (b0 + per < n) ? b0 + per : n;
-    uint32_t local = 0;
-    for (uint32_t b = b0; b < b1; ++b) local += cnt[b];
-    const uint32_t inc = wave_incl_scan(local);
-    if (lane == 63) wsum[w] = inc;
-    __syncthreads();
-    uint32_t before = 0;
-    for (int i = 0; i < w; ++i) before += wsum[i];
-    uint32_t run = before + inc - local;
-    for (uint32_t b = b0; b < b1; ++b) {
-      const uint32_t c = cnt[b];
-      cnt[b] = run;
-      run += c;
-    }
-    if (tid == 1023) ctrl->n_new = before + inc;
-    return;
-  }
-  uint32_t carry = 0;  // survivors of the earlier rounds (the same in every thread)
-  for (uint32_t r0 = 0; r0 < n; r0 += 1024u * OFF_C) {
-    const uint32_t wb = r0 + (uint32_t)w * 64u * OFF_C;
-    uint32_t v[OFF_C];
-    uint32_t sum = 0;
-#pragma unroll
-    for (int k = 0; k < OFF_C; ++k) {
-      const uint32_t b = wb + (uint32_t)k * 64u + (uint32_t)lane;
-      v[k] = b < n ? cnt[b] : 0u;
-      sum += v[k];
-    }
-    const uint32_t wt = wave_sum(sum);
-    if (lane == 0) wsum[w] = wt;
-    __syncthreads();
-    uint32_t off = carry, rt = 0;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const uint32_t x = wsum[i];
-      off += i < w ? x : 0u;
-      rt += x;
-    }
-    __syncthreads();  // (wsum is written again in the next round)
-#pragma unroll
-    for (int k = 0; k < OFF_C; ++k) {
-      const uint32_t inc = wave_incl_scan(v[k]);
-      const uint32_t b = wb + (uint32_t)k * 64u + (uint32_t)lane;
-      if (b < n) cnt[b] = off + inc - v[k];
-      off += __shfl(inc, 63, 64);
-    }
-    carry += rt;
-  }
-  if (tid == 0) ctrl->n_new = carry;
+  const uint32_t all = block_prefix_inplace<1024>(cnt, n, wsum);
+  if (threadIdx.x == 0) ctrl->n_new = all;
 }
 
 // ---- finalize (one block) ---------------------------------------------------
