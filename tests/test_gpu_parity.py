@@ -72,7 +72,9 @@ def test_device_math_bit_exact(dq, orc):
     oute = dq.dev_math(xe)
     assert np.array_equal(oute[:, 1], np.array([orc.det_exp(v) for v in xe]))
     assert np.array_equal(out[:, 2], np.sqrt(x)), "device sqrt is not correctly rounded"
-    assert np.array_equal(out[:, 3], 1.0 / x), "device division is not correctly rounded"
+    with np.errstate(over="ignore"):  # 1 / 5e-324 overflows to inf on both sides
+        recip = 1.0 / x
+    assert np.array_equal(out[:, 3], recip), "device division is not correctly rounded"
 
 
 def test_device_quiet_test_matches_the_product(dq, orc):
