@@ -147,27 +147,107 @@ def valu_from_profile(kernel, workload, live=None):
     return None if d is None else d.get("valu_per_launch")
 
 
-def cpu_baseline(cfg, keys, re, im, sc, budget_s=15.0):
-    """The oracle as it stands, single-threaded, stepping the workload from the
-    GPU's state for about budget_s seconds."""
+def _oracle_steps(cfg, keys, re, im, sc, budget_s):
+    """Step the oracle from a list and its scalars for about budget_s seconds:
+    (walker-updates, entry-updates, steps, seconds)."""
     from oracle import orc
-    orc.build(force=False)
     o = orc.Oracle(**cfg)
     o.set_list(keys, re, im)
     o.set_scalars(sc["S"], sc["mode"], sc["step"], sc["nw_prev"])
     w_start = int(abs(re.astype("int64")).sum() + abs(im.astype("int64")).sum())
-    walker_updates = 0
-    steps = 0
+    n_start = len(keys)
+    walker_updates = entry_updates = steps = 0
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < budget_s:
         o.step(1)
         walker_updates += w_start
+        entry_updates += n_start
         w_start = o.last()["w_tot"]
+        n_start = o.size()
         steps += 1
     dt = time.perf_counter() - t0
-    return dict(value=walker_updates / dt, unit="walker-updates/s", cores=1, kind="oracle",
-                sample=f"{steps} oracle steps of the same workload from the GPU state at step "
-                       f"{sc['step']} ({len(keys)} entries), {dt:.1f} s on one host core")
+    o.close()
+    return walker_updates, entry_updates, steps, dt
+
+
+def host_cpus():
+    """The host's processor model, its logical CPU count and the CPUs this
+    process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return dict(model=model, nproc=os.cpu_count(), usable=sorted(os.sched_getaffinity(0)))
+
+
+def cpu_baseline(cfg, keys, re, im, sc, budget_s=15.0, workers=None):
+    """The oracle as it stands, single-threaded, stepping the workload from the
+    GPU's state for about budget_s seconds; then the same sample on `workers`
+    cores at once (default: every usable CPU, at most 16), one oracle process
+    per core with a seed of its own, as the all-cores aggregate."""
+    from oracle import orc
+    orc.build(force=False)
+    wu, eu, steps, dt = _oracle_steps(cfg, keys, re, im, sc, budget_s)
+    host = host_cpus()
+    out = dict(value=wu / dt, unit="walker-updates/s", cores=1, kind="oracle",
+               entry_updates_per_s=eu / dt,
+               sample=f"{steps} oracle steps of the same workload from the GPU state at step "
+                      f"{sc['step']} ({len(keys)} entries), {dt:.1f} s on one host core",
+               host=dict(model=host["model"], nproc=host["nproc"],
+                         usable_cpus=len(host["usable"])))
+    if workers is None:
+        workers = min(16, len(host["usable"]))
+    if workers > 1:
+        out["all_cores"] = cpu_aggregate(cfg, keys, re, im, sc, budget_s, host["usable"][:workers])
+    return out
+
+
+def cpu_aggregate(cfg, keys, re, im, sc, budget_s, cpus):
+    """The oracle sample in one process per CPU of `cpus`, all at once, each
+    pinned to its CPU and with its own seed: the sum of their rates."""
+    import subprocess
+    import tempfile
+    import numpy as np
+    with tempfile.TemporaryDirectory() as d:
+        np.savez(os.path.join(d, "list.npz"), keys=keys, re=re, im=im)
+        with open(os.path.join(d, "job.json"), "w") as f:
+            json.dump(dict(cfg=cfg, sc=sc, budget_s=budget_s), f)
+        procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", d,
+                                   "--cpu-seed", str(i + 1), "--cpu-core", str(c)],
+                                  stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+                 for i, c in enumerate(cpus)]
+        res = []
+        for p in procs:
+            o, e = p.communicate()
+            if p.returncode != 0:
+                raise RuntimeError(f"oracle worker failed ({p.returncode}): {e[-400:]}")
+            res.append(json.loads(o.strip().splitlines()[-1]))
+    steps = [r["steps"] for r in res]
+    return dict(value=sum(r["walker_updates"] / r["seconds"] for r in res),
+                unit="walker-updates/s", cores=len(cpus),
+                entry_updates_per_s=sum(r["entry_updates"] / r["seconds"] for r in res),
+                sample=f"{len(cpus)} oracle processes at once, each pinned to one host CPU, "
+                       f"seeds 1..{len(cpus)}, each stepping the same GPU state for about "
+                       f"{budget_s:g} s ({min(steps)}-{max(steps)} steps)")
+
+
+def cpu_worker(directory, seed, core):
+    """One process of the all-cores aggregate: prints its counts as JSON."""
+    import numpy as np
+    os.sched_setaffinity(0, {core})
+    with open(os.path.join(directory, "job.json")) as f:
+        job = json.load(f)
+    z = np.load(os.path.join(directory, "list.npz"))
+    cfg = dict(job["cfg"], seed=int(job["cfg"].get("seed", 0)) + seed)
+    wu, eu, steps, dt = _oracle_steps(cfg, z["keys"], z["re"], z["im"], job["sc"],
+                                      job["budget_s"])
+    print(json.dumps(dict(walker_updates=wu, entry_updates=eu, steps=steps, seconds=dt)),
+          flush=True)
 
 
 def trace_summary(directory, steps):
@@ -838,6 +918,12 @@ def main():
                          "one launch per kernel)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-cores", type=int, default=None,
+                    help="processes of the oracle's all-cores aggregate (default: every "
+                         "usable CPU, at most 16; 1 skips it)")
+    ap.add_argument("--cpu-worker", metavar="DIR", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-seed", type=int, default=1, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-core", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--trace-summary", metavar="DIR")
     ap.add_argument("--counter-summary", nargs="+", metavar="DIR",
                     help="FETCH_DIR WRITE_DIR [VALU_DIR [REQ_DIR]]: summarise rocprofv3 --pmc "
@@ -853,6 +939,9 @@ def main():
                     help="after the timed steps, copy a buffer of this many MiB three times "
                          "(a plain copy kernel of known size for scaling memory counters)")
     args = ap.parse_args()
+    if args.cpu_worker:
+        cpu_worker(args.cpu_worker, args.cpu_seed, args.cpu_core)
+        return
     if args.trace_summary:
         trace_summary(args.trace_summary, args.steps)
         return
@@ -914,7 +1003,8 @@ def main():
         out["served"] = bench_d4(args)
     # the oracle from the timed run's final (steady) list
     out["cpu_baseline"] = (None if args.no_cpu else
-                           cpu_baseline(cfg, keys, re, im, sc, args.cpu_seconds))
+                           cpu_baseline(cfg, keys, re, im, sc, args.cpu_seconds,
+                                        args.cpu_cores))
     print(json.dumps(out), flush=True)
 
 

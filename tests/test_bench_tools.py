@@ -180,3 +180,26 @@ def test_counter_summary_by_request_size(tmp_path, monkeypatch, capsys):
     assert abs(rec["bytes_per_launch"] - 2300 * 1024) < 1.0
     reads = 32 * 1000 + 64 * 4000 + 128 * 2000
     assert abs(rec["bytes_per_launch_by_request_size"] - (reads + 300 * 1024)) < 1.0
+
+
+def test_oracle_baseline_on_one_core_and_on_several():
+    """The oracle baseline from a list and its scalars: one core in-process,
+    then the aggregate of two pinned worker processes with seeds of their own."""
+    import workloads
+    from oracle import orc
+    orc.build(force=False)
+    cfg = dict(workloads.D1)
+    o = orc.Oracle(**cfg)
+    o.step(200)
+    keys, re, im = o.get_list()
+    sc = o.scalars()
+    o.close()
+    out = bench.cpu_baseline(cfg, keys, re, im, sc, budget_s=0.3, workers=2)
+    assert out["kind"] == "oracle" and out["cores"] == 1
+    assert out["value"] > 0 and out["entry_updates_per_s"] > 0
+    assert out["host"]["nproc"] >= 1 and out["host"]["usable_cpus"] >= 1
+    agg = out["all_cores"]
+    assert agg["cores"] == 2 and agg["value"] > 0 and agg["entry_updates_per_s"] > 0
+    assert "seeds 1..2" in agg["sample"]
+    assert "all_cores" not in bench.cpu_baseline(cfg, keys, re, im, sc, budget_s=0.1,
+                                                 workers=1)
