@@ -7,6 +7,9 @@ Cases span several sort and merge tiles with ragged tails, u32 and u64 keys,
 importance sampling, the initiator filter, buffer regrowth, batched and served
 solves, the error paths, and a window of the full-size 4x4 workload.
 """
+import os
+import time
+
 import numpy as np
 import pytest
 
@@ -476,9 +479,10 @@ def test_full_size_4x4_window(dq, orc):
     (about 1.07e7 entries after some 14,500 steps, as the benchmark times it),
     at which size the list capacity is above 2^23 entries, so the large-entry
     kernel runs on the second stream beside the loud kernel, as in the timed
-    steps; then two steps from that snapshot are checked against the oracle,
-    and a third with merge tiles of 1024 positions (more than 8192 tiles: the
-    merge offsets' coalesced round scan)."""
+    steps; then two steps from that snapshot are checked against the oracle
+    (DDQMC_D3_WINDOW steps, if set: 50 make the window that also times the
+    oracle on this workload), and one more with merge tiles of 1024 positions
+    (more than 8192 tiles: the merge offsets' coalesced round scan)."""
     cfg = dict(workloads.D3)
     g = dq.Solve(dq.make_params(**cfg))
     g.step(15000)
@@ -494,12 +498,15 @@ def test_full_size_4x4_window(dq, orc):
     o.set_scalars(sc["S"], sc["mode"], sc["step"], sc["nw_prev"])
     print(f"  4x4 snapshot at step {sc['step']}: {len(keys)} entries", flush=True)
     del keys, re, im
-    for i in range(2):
+    for i in range(int(os.environ.get("DDQMC_D3_WINDOW", "2"))):
         g.step(1)
+        t0 = time.perf_counter()
         o.step(1)
+        t_oracle = time.perf_counter() - t0
         assert _same_list(g.walkers(), o.get_list())
         assert g.scalars() == o.scalars()
-        print(f"  4x4 window step {i + 1} bit-identical", flush=True)
+        print(f"  4x4 window step {i + 1} bit-identical (oracle {t_oracle:.2f} s, "
+              f"{o.size()} entries)", flush=True)
     g.set_tiles(8, 4)
     g.step(1)
     o.step(1)
