@@ -1,11 +1,16 @@
 """Pins of the oracle's random-number and elementary-function pieces.
 
 * Philox4x32-10 against the published known-answer vectors of Salmon et al.
-  (SC'11, Random123 distribution).
+  (SC'11, Random123 distribution), and against rocRAND's own engine over
+  many keys and counters (the counter's carry across 32-bit words included).
 * The 53-bit uniform construction: values on the 2^-53 grid in [0, 1), moments.
 * det_log / det_exp (only +,-,*,/) against the C library's log / exp.
 """
+import ctypes
 import math
+import os
+import shutil
+import subprocess
 
 import numpy as np
 import pytest
@@ -22,6 +27,49 @@ KAT = [  # (counter, key, output) -- Random123 philox4x32_10 known answers
 @pytest.mark.parametrize("ctr,key,out", KAT)
 def test_philox_known_answers(orc, ctr, key, out):
     assert tuple(int(x) for x in orc.philox(ctr, key)) == out
+
+
+@pytest.fixture(scope="module")
+def rocrand_philox(tmp_path_factory):
+    """rocRAND's header-only Philox engine built for the host (tests/rocrand_philox.cpp)."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    if not shutil.which(hipcc) or not os.path.exists("/opt/rocm/include/rocrand"):
+        pytest.skip("hipcc or the rocRAND headers are missing")
+    src = os.path.join(os.path.dirname(__file__), "rocrand_philox.cpp")
+    so = str(tmp_path_factory.mktemp("rocrand") / "rocrand_philox.so")
+    subprocess.run([hipcc, "-x", "hip", "--offload-arch=gfx950", "-O2", "-fPIC", "-shared",
+                    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                    "-o", so, src], check=True, capture_output=True, timeout=300)
+    lib = ctypes.CDLL(so)
+    lib.rr_philox.argtypes = [ctypes.c_ulonglong] * 3 + [ctypes.c_uint32, ctypes.c_void_p]
+    lib.rr_philox.restype = None
+
+    def run(seed, subsequence, block, blocks):
+        out = np.zeros(4 * blocks, np.uint32)
+        lib.rr_philox(seed, subsequence, 4 * block, 4 * blocks, out.ctypes.data)
+        return out
+    return run
+
+
+def test_philox_equals_rocrand(orc, rocrand_philox):
+    """rocRAND's engine: key = the seed's two 32-bit halves; block b of
+    subsequence s has the counter (b low, b high, s low, s high), its four
+    outputs in order.  The oracle's Philox must give the same words for every
+    seed, subsequence and block, across the carry from the counter's first
+    word into its second."""
+    rng = np.random.default_rng(11)
+    cases = [(0, 0, 0), (0xffffffffffffffff, 0xffffffffffffffff, 0),
+             (0x0123456789abcdef, (7 << 32) | 5, (1 << 32) - 3)]
+    cases += [(int(rng.integers(0, 2 ** 63)) * 2 + 1, int(rng.integers(0, 2 ** 63)),
+               int(rng.integers(0, 2 ** 40))) for _ in range(20)]
+    for seed, sub, block in cases:
+        got = rocrand_philox(seed, sub, block, 6)
+        key = (seed & 0xffffffff, seed >> 32)
+        for j in range(6):
+            b = block + j
+            ctr = (b & 0xffffffff, (b >> 32) & 0xffffffff, sub & 0xffffffff, sub >> 32)
+            assert tuple(int(x) for x in orc.philox(ctr, key)) == \
+                tuple(int(x) for x in got[4 * j:4 * j + 4]), (seed, sub, b)
 
 
 def test_uniform_grid_and_moments(orc):
