@@ -222,11 +222,17 @@ def cpu_aggregate(cfg, keys, re, im, sc, budget_s, cpus):
                                   stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
                  for i, c in enumerate(cpus)]
         res = []
-        for p in procs:
-            o, e = p.communicate()
-            if p.returncode != 0:
-                raise RuntimeError(f"oracle worker failed ({p.returncode}): {e[-400:]}")
-            res.append(json.loads(o.strip().splitlines()[-1]))
+        try:
+            for p in procs:
+                o, e = p.communicate()
+                if p.returncode != 0:
+                    raise RuntimeError(f"oracle worker failed ({p.returncode}): {e[-400:]}")
+                res.append(json.loads(o.strip().splitlines()[-1]))
+        finally:  # no worker outlives a failed one
+            for p in procs:
+                if p.poll() is None:
+                    p.kill()
+                    p.wait()
     steps = [r["steps"] for r in res]
     return dict(value=sum(r["walker_updates"] / r["seconds"] for r in res),
                 unit="walker-updates/s", cores=len(cpus),
