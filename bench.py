@@ -632,7 +632,7 @@ def bench_d3(args, log=_log):
                         traffic=traffic_from_profile("k_merge_write", args.workload, live),
                         bytes_per_launch=round(m_bytes), mean_launch_us=round(m_dur * 1e6, 2))
     # The annihilation stages together (sort, merge count, merge write: the
-    # north-star's graded stage) on the method's algorithmic bytes B_alg: read
+    # HBM-bound part of the step) on the method's algorithmic bytes B_alg: read
     # and write the list, write the records and read them back,
     #   B_alg = 2 n_main (k_B + 8) + 2 n_sp (k_B + 9)  per step,
     # and, beside it, on the implementation's own bytes (radix passes and the
