@@ -962,8 +962,8 @@ def main():
                         d[2] if len(d) > 2 else None, state, d[3] if len(d) > 3 else None)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the "
-              "multi-GPU sharding of the step is a design, not an implementation.",
+        print(f"bench.py: the step runs on one GPU only (asked for {args.gpus}); its "
+              "sharding over several GPUs is a design, not an implementation.",
               file=sys.stderr)
         sys.exit(2)
 
