@@ -516,6 +516,33 @@ def test_full_size_4x4_window(dq, orc):
     g.close()
 
 
+def test_full_size_4x4_without_importance_sampling(dq, orc):
+    """The 4x4 workload without importance sampling (p = 0) at full size: its
+    steady list holds about 1.38e7 entries after some 8,500 steps (its two
+    list buffers, 330 MB, no longer fit the 256 MB last-level cache) and a
+    step emits about 1.9e6 records; two steps from that snapshot against the
+    oracle."""
+    cfg = dict(workloads.D3, is_p=0.0)
+    g = dq.Solve(dq.make_params(**cfg))
+    g.step(8500)
+    keys, re, im = g.walkers()
+    sc = g.scalars()
+    assert len(keys) > 13_000_000, len(keys)
+    assert g.step_counts()[-1][3] > 1_000_000  # loud entries at full size
+    o = orc.Oracle(**cfg)
+    o.set_list(keys, re, im)
+    o.set_scalars(sc["S"], sc["mode"], sc["step"], sc["nw_prev"])
+    print(f"  4x4 p = 0 snapshot at step {sc['step']}: {len(keys)} entries", flush=True)
+    del keys, re, im
+    for i in range(2):
+        g.step(1)
+        o.step(1)
+        assert _same_list(g.walkers(), o.get_list())
+        assert g.scalars() == o.scalars()
+        print(f"  4x4 p = 0 window step {i + 1} bit-identical", flush=True)
+    g.close()
+
+
 def test_d1_full_run(dq, orc):
     """D1 (2x2) for all of its 10^4 steps, the series and accumulators included."""
     cfg = dict(workloads.D1)
