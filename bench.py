@@ -71,10 +71,6 @@ WORKLOADS = {
     "d3": (dict(workloads.D3),
            "4x4 periodic dissipative XYZ, Jx 0.9 Jy 1 Jz 1 gamma 1, dt 0.002, n_a 3, "
            "IS p 1.5, 1e7 walkers"),
-    # same physics and population without importance sampling: the list holds
-    # about ten times as many configurations (the occupancy census: 1.06e7 at
-    # 1e6 walkers against 6.1e6 with p 1.5), over 1 GB, so it outgrows the
-    # 256 MB last-level cache
     # no initiator: the list grows without a steady size (past 2e8 entries
     # within ~750 steps at 1e6 walkers); timed as it passes 1e8 entries
     # (1.2 GB of list), far beyond the 256 MB last-level cache
@@ -82,10 +78,15 @@ WORKLOADS = {
               "4x4 periodic dissipative XYZ, Jx 0.9 Jy 1 Jz 1 gamma 1, dt 0.002, no initiator, "
               "IS p 1.5, 1e7 walkers, timed as its growing list passes 1e8 entries"),
     # the in-plane field along x (Sec. V.B): the parity rule no longer holds,
-    # and every spawn goes through the general sampling routine
+    # the list grows to about 7.7e7 entries, and the spawns go through the
+    # field's sampling routines
     "d3f": (dict(workloads.D3, hx=0.05),
             "4x4 periodic dissipative XYZ, Jx 0.9 Jy 1 Jz 1 gamma 1, dt 0.002, n_a 3, "
             "IS p 1.5, in-plane field hx 0.05, 1e7 walkers"),
+    # same physics and population without importance sampling: the list holds
+    # more configurations (the occupancy census at 1e6 walkers: 1.06e7 against
+    # 6.1e6 with p 1.5; here about 1.38e7), 165 MB per list buffer, so its two
+    # buffers outgrow the 256 MB last-level cache
     "d3l": (dict(workloads.D3, is_p=0.0),
             "4x4 periodic dissipative XYZ, Jx 0.9 Jy 1 Jz 1 gamma 1, dt 0.002, n_a 3, "
             "no IS, 1e7 walkers"),
