@@ -191,3 +191,34 @@ def test_field_entries_passed_on(dq, orc, limit):
         with pytest.raises(dq.DDQMCError):
             g.set_field_limit(bad)
     g.close()
+
+
+def test_full_size_field_step(dq, orc):
+    """The field workload at full size, as the benchmark times it (the 4x4
+    workload with hx 0.05): the GPU steps it to its steady list (about 7.65e7
+    entries after some 11,000 steps), where thousands of entries take the
+    heavy list on the second stream beside the call-free routine over
+    millions of others; then one step from that snapshot against the
+    oracle."""
+    cfg = dict(workloads.D3, hx=0.05)
+    g = dq.Solve(dq.make_params(**cfg))
+    g.step(11000)
+    keys, re, im = g.walkers()
+    sc = g.scalars()
+    _, cap = g.device_bytes()
+    assert len(keys) > 70_000_000, len(keys)
+    assert cap >= 1 << 23  # the fork's threshold (ddqmc_set_heavy_fork mode 0)
+    counts = g.step_counts()[-1]
+    assert counts[3] > 5_000_000 and counts[4] > 1000  # entries with events, heavy list
+    o = orc.Oracle(**cfg)
+    o.set_list(keys, re, im)
+    o.set_scalars(sc["S"], sc["mode"], sc["step"], sc["nw_prev"])
+    print(f"  field snapshot at step {sc['step']}: {len(keys)} entries, "
+          f"{counts[3]} with events, {counts[4]} heavy", flush=True)
+    del keys, re, im
+    g.step(1)
+    o.step(1)
+    assert _same_list(g.walkers(), o.get_list())
+    assert g.scalars() == o.scalars()
+    print(f"  field step bit-identical ({o.size()} entries)", flush=True)
+    g.close()
