@@ -1200,6 +1200,63 @@ static int cmp_contrib(const void *a, const void *b) {
   return (x > y) - (x < y);
 }
 
+/* Annihilation (Sec. III.C, the third rule): every contribution summed per
+ * configuration, the sums added to the step-start list (sorted unique keys,
+ * values already moved by their own clone/death), and every configuration whose
+ * total is zero dropped.  con is sorted and compacted in place; the new list,
+ * sorted, goes to nk/nre/nim, which must hold n + ncon entries; *nout is its
+ * length.  ORC_EOVERFLOW when a total leaves the int32 range. */
+static int annihilate(contrib_t *con, int64_t ncon, const uint64_t *keys, const int64_t *pr,
+                      const int64_t *pi, int64_t n, uint64_t *nk, int64_t *nre, int64_t *nim,
+                      int64_t *nout) {
+  int64_t i, a = 0, u = 0, nu = 0, j = 0;
+  qsort(con, (size_t)ncon, sizeof(contrib_t), cmp_contrib);
+  for (i = 0; i < ncon; i++) {
+    if (nu > 0 && con[nu - 1].key == con[i].key) {
+      con[nu - 1].re += con[i].re;
+      con[nu - 1].im += con[i].im;
+    } else {
+      con[nu++] = con[i];
+    }
+  }
+  while (a < n || u < nu) {
+    uint64_t key;
+    int64_t R, I;
+    if (u >= nu || (a < n && keys[a] < con[u].key)) {
+      key = keys[a]; R = pr[a]; I = pi[a]; a++;
+    } else if (a >= n || con[u].key < keys[a]) {
+      key = con[u].key; R = con[u].re; I = con[u].im; u++;
+    } else {
+      key = keys[a]; R = pr[a] + con[u].re; I = pi[a] + con[u].im; a++; u++;
+    }
+    if (R == 0 && I == 0) continue;
+    if (R > 2147483647LL || R < -2147483647LL || I > 2147483647LL || I < -2147483647LL)
+      return ORC_EOVERFLOW;
+    nk[j] = key; nre[j] = R; nim[j] = I; j++;
+  }
+  *nout = j;
+  return ORC_OK;
+}
+
+int orc_annihilate(const uint64_t *ckeys, const int64_t *cre, const int64_t *cim, int64_t ncon,
+                   const uint64_t *keys, const int64_t *pr, const int64_t *pi, int64_t n,
+                   uint64_t *nk, int64_t *nre, int64_t *nim, int64_t *nout) {
+  int64_t i;
+  int rc;
+  contrib_t *con;
+  if (ncon < 0 || n < 0 || !nout) return ORC_EINVAL;
+  con = (contrib_t *)malloc((size_t)(ncon ? ncon : 1) * sizeof(contrib_t));
+  if (!con) return ORC_ENOMEM;
+  for (i = 0; i < ncon; i++) {
+    con[i].key = ckeys[i];
+    con[i].re = cre[i];
+    con[i].im = cim[i];
+  }
+  rc = annihilate(con, ncon, keys, pr, pi, n, nk, nre, nim, nout);
+  free(con);
+  return rc;
+}
+
 static void estimator_sums(const orc_t *h, const uint64_t *keys, const int64_t *re,
                            const int64_t *im, int64_t n, int64_t out[ORC_NSUM]) {
   const model_t *md = &h->md;
@@ -1234,7 +1291,7 @@ static void estimator_sums(const orc_t *h, const uint64_t *keys, const int64_t *
 }
 
 static int one_step(orc_t *h) {
-  int64_t i, j, a, nn, u, nu;
+  int64_t i, j, nn;
   int err = ORC_OK;
   int64_t *pr = (int64_t *)malloc((size_t)(h->n ? h->n : 1) * sizeof(int64_t));
   int64_t *pi = (int64_t *)malloc((size_t)(h->n ? h->n : 1) * sizeof(int64_t));
@@ -1252,40 +1309,14 @@ static int one_step(orc_t *h) {
   }
   if (err != ORC_OK) { free(pr); free(pi); return err; }
 
-  /* annihilation: sum every contribution per configuration */
-  qsort(h->con, (size_t)h->ncon, sizeof(contrib_t), cmp_contrib);
-  nu = 0;
-  for (i = 0; i < h->ncon; i++) {
-    if (nu > 0 && h->con[nu - 1].key == h->con[i].key) {
-      h->con[nu - 1].re += h->con[i].re;
-      h->con[nu - 1].im += h->con[i].im;
-    } else {
-      h->con[nu++] = h->con[i];
-    }
-  }
-  nn = h->n + nu;
+  /* annihilation: sum every contribution per configuration, merge with the list */
+  nn = h->n + h->ncon;
   nk = (uint64_t *)malloc((size_t)(nn ? nn : 1) * sizeof(uint64_t));
   nre = (int64_t *)malloc((size_t)(nn ? nn : 1) * sizeof(int64_t));
   nim = (int64_t *)malloc((size_t)(nn ? nn : 1) * sizeof(int64_t));
   if (!nk || !nre || !nim) { err = ORC_ENOMEM; goto done; }
-  a = 0; j = 0; u = 0;
-  while (a < h->n || u < nu) {
-    uint64_t key;
-    int64_t R, I;
-    if (u >= nu || (a < h->n && h->keys[a] < h->con[u].key)) {
-      key = h->keys[a]; R = pr[a]; I = pi[a]; a++;
-    } else if (a >= h->n || h->con[u].key < h->keys[a]) {
-      key = h->con[u].key; R = h->con[u].re; I = h->con[u].im; u++;
-    } else {
-      key = h->keys[a]; R = pr[a] + h->con[u].re; I = pi[a] + h->con[u].im; a++; u++;
-    }
-    if (R == 0 && I == 0) continue;
-    if (R > 2147483647LL || R < -2147483647LL || I > 2147483647LL || I < -2147483647LL) {
-      err = ORC_EOVERFLOW;
-      goto done;
-    }
-    nk[j] = key; nre[j] = R; nim[j] = I; j++;
-  }
+  err = annihilate(h->con, h->ncon, h->keys, pr, pi, h->n, nk, nre, nim, &j);
+  if (err != ORC_OK) goto done;
   estimator_sums(h, nk, nre, nim, j, sums);
   if (j == 0) { err = ORC_EEXTINCT; goto done; }
 

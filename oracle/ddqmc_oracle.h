@@ -71,6 +71,14 @@ int64_t orc_series_len(const orc_t *h);
 int orc_get_series(const orc_t *h, int64_t *rows, int64_t cap_rows);
 
 /* ---- pieces exposed for the pin tests ---- */
+/* The step's annihilation: contributions (any order, repeated keys) summed per
+ * configuration and merged with a list of sorted unique keys whose values
+ * (int64) already carry their clone/death; zero totals dropped.  nk/nre/nim
+ * hold n + ncon entries; *nout receives the new list's length.  ORC_EOVERFLOW
+ * when a total leaves the int32 range. */
+int orc_annihilate(const uint64_t *ckeys, const int64_t *cre, const int64_t *cim, int64_t ncon,
+                   const uint64_t *keys, const int64_t *pr, const int64_t *pi, int64_t n,
+                   uint64_t *nk, int64_t *nre, int64_t *nim, int64_t *nout);
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 double orc_det_log(double x);
 double orc_det_exp(double x);

@@ -90,6 +90,8 @@ def lib():
         "orc_get_acc": (ctypes.c_int, [vp, i64p, i64p]),
         "orc_series_len": (ctypes.c_int64, [vp]),
         "orc_get_series": (ctypes.c_int, [vp, i64p, ctypes.c_int64]),
+        "orc_annihilate": (ctypes.c_int, [u64p, i64p, i64p, ctypes.c_int64, u64p, i64p, i64p,
+                                          ctypes.c_int64, u64p, i64p, i64p, i64p]),
         "orc_philox4x32_10": (None, [u32p, u32p, u32p]),
         "orc_det_log": (ctypes.c_double, [ctypes.c_double]),
         "orc_det_exp": (ctypes.c_double, [ctypes.c_double]),
@@ -202,6 +204,29 @@ class Oracle:
 
 
 # ---- pieces used by the pin tests -------------------------------------------
+
+def annihilate(ckeys, cre, cim, keys, pr, pi):
+    """The step's annihilation on given contributions and list values: the new
+    (keys, re, im), int64 values."""
+    ck = np.ascontiguousarray(ckeys, np.uint64)
+    cr = np.ascontiguousarray(cre, np.int64)
+    ci = np.ascontiguousarray(cim, np.int64)
+    k = np.ascontiguousarray(keys, np.uint64)
+    r = np.ascontiguousarray(pr, np.int64)
+    i = np.ascontiguousarray(pi, np.int64)
+    cap = max(1, len(k) + len(ck))
+    nk = np.empty(cap, np.uint64)
+    nr = np.empty(cap, np.int64)
+    ni = np.empty(cap, np.int64)
+    nout = ctypes.c_int64(0)
+    _check(lib().orc_annihilate(_ptr(ck, ctypes.c_uint64), _ptr(cr, ctypes.c_int64),
+                                _ptr(ci, ctypes.c_int64), len(ck), _ptr(k, ctypes.c_uint64),
+                                _ptr(r, ctypes.c_int64), _ptr(i, ctypes.c_int64), len(k),
+                                _ptr(nk, ctypes.c_uint64), _ptr(nr, ctypes.c_int64),
+                                _ptr(ni, ctypes.c_int64), ctypes.byref(nout)), "annihilate")
+    n = nout.value
+    return nk[:n].copy(), nr[:n].copy(), ni[:n].copy()
+
 
 def philox(ctr, key):
     c = np.asarray(ctr, np.uint32).copy()
