@@ -350,7 +350,7 @@ def counter_summary(fetch_dir, write_dir, probe_mb, workload, valu_dir=None, sta
             pr = max(req[k] for k in pk)
             out[0] += (f"; by request sizes the probe read {pr / 2 ** 20:.1f} MiB "
                        f"(of {probe_mb} MiB)")
-        out[2] = out[2].rstrip("|") + " read MB by request size | HBM MB (request sizes) |"
+        out[2] = out[2] + " read MB by request size | HBM MB (request sizes) |"
         out[3] = out[3] + "---:|---:|"
     rec, rec_req = {}, {}
     for name in sorted(fetch):
